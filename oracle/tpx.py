@@ -1,0 +1,292 @@
+"""Oracle, part 3: Toeplitz-like-plus-Cross levels (TEST INFRASTRUCTURE ONLY).
+
+Sec. 3.2.2 of arXiv 2202.11288 (eq. (split01)): a level of n = 2^k - 1
+v-unknowns and n + 1 w-unknowns, w = [w_o; w_bar], is
+
+    A_k = [A 0 B_bar; 0' 0 0'; C_bar 0 D_bar] + [0 p 0; q o zeta; 0 xi 0]
+
+with four n x n Toeplitz blocks (entries T[i, j] = t_{j-i}, the convention of
+Lemma 3.1) and the Cross vectors p (column w_o, v rows), q (row w_o, v
+columns), xi (column w_o, w_bar rows), zeta (row w_o, w_bar columns) and the
+scalar o.  Generators are stored as arrays g[d + n - 1], d = -(n-1)..n-1.
+
+* ``coarsen`` is Lemma 3.1 written in the paper's notation, with N_k read as
+  the number of intervals of level k (= n + 1); under that reading the
+  formulas equal the dense Galerkin product (pinned in the tests).
+* ``matvec`` uses, for each of the four Toeplitz blocks separately, the
+  circulant embedding of eq. (ccs3.4) of size L = 2(n+1) and
+  C x = ifft(fft(c) .* fft(x)) (Sec. 3.2), plus the O(n) Cross terms.
+* ``vcycle``/``solve`` are the same Algorithm 2 / outer loop as in
+  ``oracle.dense`` on this representation (FP64, scipy.fft).
+"""
+from __future__ import annotations
+
+import dataclasses
+import os
+
+import numpy as np
+import scipy.fft
+import scipy.linalg
+
+from . import discretize as disc
+from .dense import Options
+
+WORKERS = os.cpu_count() or 1
+
+
+@dataclasses.dataclass
+class TpX:
+    n: int
+    a: np.ndarray
+    b: np.ndarray
+    c: np.ndarray
+    d: np.ndarray
+    p: np.ndarray
+    q: np.ndarray
+    xi: np.ndarray
+    zeta: np.ndarray
+    o: float
+
+    @property
+    def size(self):
+        return 2 * self.n + 1
+
+    def diag(self):
+        n = self.n
+        return np.concatenate([np.full(n, self.a[n - 1]), [self.o], np.full(n, self.d[n - 1])])
+
+    def dense(self):
+        n = self.n
+        M = np.zeros((2 * n + 1, 2 * n + 1))
+        M[:n, :n] = toeplitz_dense(self.a, n)
+        M[:n, n + 1:] = toeplitz_dense(self.b, n)
+        M[n + 1:, :n] = toeplitz_dense(self.c, n)
+        M[n + 1:, n + 1:] = toeplitz_dense(self.d, n)
+        M[:n, n] = self.p
+        M[n, :n] = self.q
+        M[n, n] = self.o
+        M[n, n + 1:] = self.zeta
+        M[n + 1:, n] = self.xi
+        return M
+
+
+def toeplitz_dense(g, n):
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    return np.asarray(g)[j - i + n - 1]
+
+
+def from_dense(M):
+    """Split a dense level matrix as in eq. (split01) (Toeplitz-ness is not
+    checked here; the tests do)."""
+    m = M.shape[0]
+    n = (m - 1) // 2
+
+    def gen(T):
+        return np.concatenate([T[::-1, 0][:-1], T[0, :]])  # offsets -(n-1)..n-1
+
+    return TpX(n, gen(M[:n, :n]), gen(M[:n, n + 1:]), gen(M[n + 1:, :n]),
+               gen(M[n + 1:, n + 1:]), M[:n, n].copy(), M[n, :n].copy(),
+               M[n + 1:, n].copy(), M[n, n + 1:].copy(), float(M[n, n]))
+
+
+def from_stencil(kernel: disc.Kernel, N: int):
+    """Finest level from the row stencil W(s2) (half-grid offsets).
+
+    v_i sits at x = (i+1) h, w_o at h/2, w_bar_j at (j + 3/2) h (0-based), so
+    A, D_bar take W at even offsets 2d; B_bar at 2d+1; C_bar at 2d-1; the Cross
+    vectors at the offsets between w_o and each point.
+    """
+    W, S = disc.stencil(kernel, N)
+    n = N - 1
+
+    def Wat(s2):
+        s2 = np.asarray(s2)
+        out = np.zeros(s2.shape)
+        ok = np.abs(s2) <= S
+        out[ok] = W[s2[ok] + S]
+        return out
+
+    d = np.arange(-(n - 1), n)
+    i = np.arange(n)
+    return TpX(n, Wat(2 * d), Wat(2 * d + 1), Wat(2 * d - 1), Wat(2 * d),
+               Wat(-2 * i - 1), Wat(2 * i + 1), Wat(-2 * i - 2), Wat(2 * i + 2),
+               float(Wat(np.array(0))))
+
+
+def from_blocks(gA, gB, gC, gD, N: int):
+    """Finest level from generators of A, B, C, D (layout as in
+    ``discretize.assemble_dense_from_blocks``)."""
+    n = N - 1
+    gA, gB, gC, gD = (np.asarray(g, dtype=np.float64) for g in (gA, gB, gC, gD))
+    # B: offsets -(n-1)..n ; p = B[:,0] -> p_i = beta_{-i}; B_bar offset d -> beta_{d+1}
+    bB = lambda off: gB[off + n - 1]
+    # C: offsets -n..n-1 ; q_i = C[0,i] = gamma_i; C_bar offset d -> gamma_{d-1}
+    cC = lambda off: gC[off + n]
+    dD = lambda off: gD[off + n]
+    d = np.arange(-(n - 1), n)
+    i = np.arange(n)
+    return TpX(n, gA.copy(), bB(d + 1), cC(d - 1), dD(d), bB(-i), cC(i),
+               dD(-i - 1), dD(i + 1), float(dD(0)))
+
+
+def coarsen(T: TpX) -> TpX:
+    """Lemma 3.1: the Galerkin coarse level, O(n) work.
+
+    Toeplitz generators: 8 g'_i = g_{2i-2} + 4 g_{2i-1} + 6 g_{2i} + 4 g_{2i+1} + g_{2i+2}.
+    Cross vectors (1-based i, N_k = n + 1):
+      8 p'_i  = (a_{Nk-2i} + 2a_{Nk-2i-1} + a_{Nk-2i-2}) + 2(p_{2i-1} + 2p_{2i} + p_{2i+1})
+                + (b_{-2i+2} + 2b_{-2i+1} + b_{-2i})
+      8 q'_i  = (a_{-Nk+2i} + 2a_{-Nk+2i+1} + a_{-Nk+2i+2}) + 2(q_{2i-1} + 2q_{2i} + q_{2i+1})
+                + (c_{2i-2} + 2c_{2i-1} + c_{2i})
+      8 o'    = (a_0 + 2p_{Nk-1} + b_{-Nk+2}) + 2(q_{Nk-1} + 2o + zeta_1)
+                + (c_{Nk-2} + 2xi_1 + d_0)
+      8 xi'_i = (c_{Nk-2i} + 2c_{Nk-2i-1} + c_{Nk-2i-2}) + 2(xi_{2i-1} + 2xi_{2i} + xi_{2i+1})
+                + (d_{-2i+2} + 2d_{-2i+1} + d_{-2i})
+      8 zeta'_i = (b_{-Nk+2i} + 2b_{-Nk+2i+1} + b_{-Nk+2i+2}) + 2(zeta_{2i-1} + 2zeta_{2i} + zeta_{2i+1})
+                + (d_{2i-2} + 2d_{2i-1} + d_{2i})
+    """
+    n = T.n
+    Nk = n + 1
+    nc = (n - 1) // 2
+    g = lambda arr: (lambda off: arr[np.asarray(off) + n - 1])
+    a, b, c, d = g(T.a), g(T.b), g(T.c), g(T.d)
+    v1 = lambda arr: (lambda i: arr[np.asarray(i) - 1])  # 1-based vectors
+    p, q, xi, zeta = v1(T.p), v1(T.q), v1(T.xi), v1(T.zeta)
+
+    ic = np.arange(-(nc - 1), nc)
+
+    def toe(t):
+        return (t(2 * ic - 2) + 4 * t(2 * ic - 1) + 6 * t(2 * ic) + 4 * t(2 * ic + 1)
+                + t(2 * ic + 2)) / 8.0
+
+    i = np.arange(1, nc + 1)
+    pc = ((a(Nk - 2 * i) + 2 * a(Nk - 2 * i - 1) + a(Nk - 2 * i - 2))
+          + 2 * (p(2 * i - 1) + 2 * p(2 * i) + p(2 * i + 1))
+          + (b(-2 * i + 2) + 2 * b(-2 * i + 1) + b(-2 * i))) / 8.0
+    qc = ((a(-Nk + 2 * i) + 2 * a(-Nk + 2 * i + 1) + a(-Nk + 2 * i + 2))
+          + 2 * (q(2 * i - 1) + 2 * q(2 * i) + q(2 * i + 1))
+          + (c(2 * i - 2) + 2 * c(2 * i - 1) + c(2 * i))) / 8.0
+    oc = ((a(0) + 2 * p(Nk - 1) + b(-Nk + 2)) + 2 * (q(Nk - 1) + 2 * T.o + zeta(1))
+          + (c(Nk - 2) + 2 * xi(1) + d(0))) / 8.0
+    xic = ((c(Nk - 2 * i) + 2 * c(Nk - 2 * i - 1) + c(Nk - 2 * i - 2))
+           + 2 * (xi(2 * i - 1) + 2 * xi(2 * i) + xi(2 * i + 1))
+           + (d(-2 * i + 2) + 2 * d(-2 * i + 1) + d(-2 * i))) / 8.0
+    zc = ((b(-Nk + 2 * i) + 2 * b(-Nk + 2 * i + 1) + b(-Nk + 2 * i + 2))
+          + 2 * (zeta(2 * i - 1) + 2 * zeta(2 * i) + zeta(2 * i + 1))
+          + (d(2 * i - 2) + 2 * d(2 * i - 1) + d(2 * i))) / 8.0
+    return TpX(nc, toe(a), toe(b), toe(c), toe(d), pc, qc, xic, zc, float(oc))
+
+
+# --- FFT matvec -------------------------------------------------------------
+
+def circulant_spectrum(g, n):
+    """rfft of the first column of the L = 2(n+1) circulant that embeds
+    T[i, j] = t_{j-i} (eq. (ccs3.4)): c_m = t_{-m}, c_{L-m} = t_m."""
+    L = 2 * (n + 1)
+    col = np.zeros(L)
+    col[:n] = g[n - 1::-1]          # t_0, t_{-1}, ..., t_{-(n-1)}
+    if n > 1:
+        col[L - (n - 1):] = g[n:][::-1]      # t_{n-1}, ..., t_1
+    return scipy.fft.rfft(col, workers=WORKERS)
+
+
+def toeplitz_apply(spec, x, n):
+    """T x through the circulant embedding: ifft(fft(c) .* fft([x; 0]))[:n]."""
+    L = 2 * (n + 1)
+    X = scipy.fft.rfft(x, n=L, workers=WORKERS)
+    return scipy.fft.irfft(spec * X, n=L, workers=WORKERS)[:n]
+
+
+@dataclasses.dataclass
+class Level:
+    T: TpX
+    sA: np.ndarray
+    sB: np.ndarray
+    sC: np.ndarray
+    sD: np.ndarray
+    diag: np.ndarray
+
+    @classmethod
+    def build(cls, T: TpX):
+        n = T.n
+        return cls(T, circulant_spectrum(T.a, n), circulant_spectrum(T.b, n),
+                   circulant_spectrum(T.c, n), circulant_spectrum(T.d, n), T.diag())
+
+    def matvec(self, u):
+        """A_k u via the Cross splitting (Sec. 3.2.2)."""
+        T, n = self.T, self.T.n
+        v, wo, wb = u[:n], u[n], u[n + 1:]
+        yv = toeplitz_apply(self.sA, v, n) + toeplitz_apply(self.sB, wb, n) + T.p * wo
+        yo = T.q @ v + T.o * wo + T.zeta @ wb
+        yw = toeplitz_apply(self.sC, v, n) + toeplitz_apply(self.sD, wb, n) + T.xi * wo
+        return np.concatenate([yv, [yo], yw])
+
+
+def restrict(r):
+    """1/4 [1 2 1] stride 2 on the block-ordered vector (Sec. 3.1)."""
+    return 0.25 * (r[0:-2:2] + 2.0 * r[1:-1:2] + r[2::2])
+
+
+def prolong(e):
+    """2 R^T e (Sec. 3.1)."""
+    m = 2 * len(e) + 1
+    u = np.zeros(m)
+    u[0:-2:2] += 0.5 * e
+    u[1:-1:2] += e
+    u[2::2] += 0.5 * e
+    return u
+
+
+@dataclasses.dataclass
+class Hierarchy:
+    levels: list
+    lu: tuple
+
+    @classmethod
+    def build(cls, T_fine: TpX, coarsest_log2: int = 5):
+        Ts = [T_fine]
+        while Ts[-1].n > 2 ** coarsest_log2 - 1:
+            Ts.append(coarsen(Ts[-1]))
+        assert Ts[-1].n == 2 ** coarsest_log2 - 1, "N must be 2^K with K >= coarsest_log2"
+        levels = [Level.build(T) for T in Ts[:-1]]
+        coarsest = Ts[-1]
+        return cls(levels + [coarsest], scipy.linalg.lu_factor(coarsest.dense()))
+
+    @property
+    def finest(self):
+        return self.levels[0]
+
+    def matvec(self, u):
+        return self.levels[0].matvec(u)
+
+
+def vcycle(H: Hierarchy, b, opts: Options = Options(), level: int = 0):
+    """Algorithm 2 on Toeplitz-plus-Cross levels (same steps as oracle.dense.vcycle)."""
+    if level == len(H.levels) - 1:
+        return scipy.linalg.lu_solve(H.lu, b)
+    L = H.levels[level]
+    u = np.zeros_like(b)
+    for _ in range(opts.m1):
+        u = u + opts.omega_pre * (b - L.matvec(u)) / L.diag
+    e = vcycle(H, restrict(b - L.matvec(u)), opts, level + 1)
+    u = u + prolong(e)
+    for _ in range(opts.m2):
+        u = u + opts.omega_post * (b - L.matvec(u)) / L.diag
+    return u
+
+
+def solve(H: Hierarchy, b, tol=1e-10, max_iter=500, opts: Options = Options(), x0=None):
+    """Outer stationary iteration with Sec. 5's stopping rule; returns
+    (x, iterations, history)."""
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - H.matvec(x)
+    r0 = np.linalg.norm(r)
+    hist = [1.0]
+    it = 0
+    while hist[-1] >= tol and it < max_iter:
+        x = x + vcycle(H, r, opts)
+        r = b - H.matvec(x)
+        it += 1
+        hist.append(np.linalg.norm(r) / r0)
+    return x, it, np.array(hist)
