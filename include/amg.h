@@ -1,0 +1,183 @@
+/*
+ * amg.h -- C ABI of the MI355X (gfx950) fast block-structured algebraic
+ * multigrid for the Toeplitz-like-plus-Cross systems of
+ * M. Chen, R. Cao, S. Serra-Capizzano, "Fast algebraic multigrid for
+ * block-structured dense and Toeplitz-like-plus-Cross systems arising from
+ * nonlocal diffusion problems" (arXiv 2202.11288).
+ *
+ * Problem (Sec. 2.2): -L_delta u = f on (0,1), u = 0 on the interaction
+ * volume, L_delta u(x) = int_{|y-x|<=delta} gamma(y-x) (u(y) - u(x)) dy,
+ * discretised by shifted-symmetric piecewise-quadratic collocation
+ * (eq. (system1)) with N = 2^K intervals, h = 1/N.  The unknown vector has
+ * 2N-1 entries in the paper's block order
+ *     U_h = [u_1 .. u_{N-1} | u_{1/2} .. u_{N-1/2}]        (Sec. 2.2.1),
+ * i.e. v (N-1 node values) followed by w (N midpoint values).
+ *
+ * Solver: the block V-cycle of Algorithm 2 (damped Jacobi, eq. (7 Jacobi);
+ * simple restriction 1/4[1 2 1] and prolongation 2 R^T on the block-ordered
+ * vector, Sec. 3.1; Galerkin coarse levels, eq. (block Galerkin), kept as
+ * Toeplitz generators plus Cross vectors via Lemma 3.1, eq. (split01)); every
+ * level's matrix-vector product uses circulant-embedded FFTs (Sec. 3.2,
+ * eq. (ccs3.4)); the coarsest level is solved by LU.  The outer iteration is
+ * x <- x + B_K (b - A x), stopped when ||b - A x||_2 / ||b - A x_0||_2 < tol
+ * (Sec. 5).
+ *
+ * Conventions shared by every entry point:
+ *  - Vector arguments are DEVICE pointers (e.g. torch.Tensor.data_ptr() of a
+ *    cuda tensor), contiguous, 2N-1 entries in block order, owned by the
+ *    caller.  Host pointers are marked "host".
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    work is enqueued on it; functions that return values to the host
+ *    (amg_solve's iters/relres) synchronise that stream.
+ *  - Every function returns an amg_status; nothing throws across the ABI.
+ *    On error no output is written, except amg_solve, which leaves x at its
+ *    last iterate for AMG_NOT_CONVERGED / AMG_DIVERGED.
+ *  - A handle is not thread-safe: use one handle per concurrent stream.
+ */
+#ifndef AMG_H
+#define AMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amg_ctx* amg_t; /* opaque; owned by the library until amg_destroy */
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_NOT_CONVERGED = 1, /* max_iter reached; x holds the last iterate          */
+  AMG_DIVERGED = 2,      /* NaN/Inf or residual grew 1e3x over its minimum       */
+  AMG_EINVAL = -1,       /* bad argument (see each function)                     */
+  AMG_ENOMEM = -2,       /* device or host allocation failed                     */
+  AMG_EHIP = -3,         /* a HIP runtime call failed                            */
+  AMG_ENOTSUP = -4       /* valid request this build does not implement          */
+} amg_status;
+
+typedef enum {
+  /* gamma(s) = c on |s| <= delta, c = 3/(2 delta^3) (int gamma s^2 = 1).
+     Sec. 2.2 uses the constant kernel 3 delta^-3; the normalisation only
+     rescales A and f together.                                               */
+  AMG_K_CONST = 0,
+  /* gamma(s) = c*wl for s = y-x < 0, c*wr for s > 0, c as above
+     (non-symmetric operator; same shifted collocation rule).                 */
+  AMG_K_WEIGHTED = 1,
+  /* gamma(s) = c |s|^(-1-2 alpha), c = (1-alpha) delta^(2 alpha-2),
+     0 < alpha < 1/2 (the product-integration weights diverge beyond 1/2).    */
+  AMG_K_FRACTIONAL = 2,
+  /* Caller-supplied finest-level Toeplitz blocks of eq. (blocksystem):
+     gen (host) = [A | B | C | D] generators, each ordered from the lowest
+     offset to the highest, T[i,j] = t_{j-i}:
+       A (N-1)x(N-1): offsets -(N-2)..N-2   (2N-3 values)
+       B (N-1)xN    : offsets -(N-2)..N-1   (2N-2 values)
+       C Nx(N-1)    : offsets -(N-1)..N-2   (2N-2 values)
+       D NxN        : offsets -(N-1)..N-1   (2N-1 values)
+     8N-8 doubles in total; delta is ignored.                                */
+  AMG_K_GENERATORS = 3
+} amg_kernel_kind;
+
+typedef struct {
+  int kind;          /* amg_kernel_kind                                      */
+  double alpha;      /* AMG_K_FRACTIONAL only                                */
+  double wl, wr;     /* AMG_K_WEIGHTED only (the survey's variant: 1.2, 0.8) */
+  const double* gen; /* AMG_K_GENERATORS only (host, copied during setup)    */
+} amg_kernel_t;
+
+typedef enum { AMG_FP64 = 0, AMG_MIXED = 1 } amg_precision;
+
+typedef struct {
+  int m1, m2;                 /* pre/post Jacobi sweeps (Algorithm 2)        */
+  double omega_pre, omega_post; /* damping (eq. (7 Jacobi))                  */
+  int coarsest_log2;          /* coarsest level has 2^coarsest_log2 intervals */
+  int precision;              /* AMG_FP64: everything FP64.  AMG_MIXED: V-cycle
+                                 FFT matvecs/smoothing/transfers in FP32; outer
+                                 residual, refinement update and coarsest LU in
+                                 FP64 (iterative refinement).                 */
+  int max_iter;               /* outer iterations                            */
+  int flags;                  /* AMG_FLAG_* bits, 0 by default               */
+} amg_opts_t;
+
+/* amg_setup builds only the host-side hierarchy (generators, Lemma 3.1
+   levels, coarsest LU) and touches no GPU; amg_level_tpx, amg_num_levels and
+   amg_level_size work on such a handle, every device entry point returns
+   AMG_EINVAL.  Used to verify the host setup on machines without a GPU. */
+#define AMG_FLAG_HOST_ONLY 1
+
+/* Fill *o with m1 = m2 = 1, omega = 2/3, coarsest_log2 = 5, FP64,
+   max_iter = 200. */
+void amg_default_opts(amg_opts_t* o);
+
+/* Build the multigrid hierarchy (Sec. 3): finest generators by product
+ * integration of the kernel against the quadratic basis (eq. (ccs2.1); the
+ * partial last cell [r h, delta] is integrated exactly when delta/h is not an
+ * integer), Galerkin levels by Lemma 3.1 down to 2^coarsest_log2 intervals,
+ * per-level circulant spectra (eq. (ccs3.4)) on the device, LU of the
+ * coarsest level.  N must be a power of two with coarsest_log2 < log2 N <= 22
+ * and 2 <= coarsest_log2; 0 < delta < 1/2 (ignored for AMG_K_GENERATORS).
+ * *out receives the handle.  Errors: AMG_EINVAL (bad N, delta, alpha, weights,
+ * null pointer, options), AMG_ENOMEM, AMG_EHIP. */
+int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N,
+              const amg_opts_t* opts, void* stream, amg_t* out);
+
+/* y = A x on the finest level (FP64; x, y device, 2N-1 doubles, must not
+ * alias).  Errors: AMG_EINVAL (null), AMG_EHIP. */
+int amg_matvec(amg_t h, const double* x, double* y, void* stream);
+
+/* y = A_level x for level `level` (0 = finest, amg_num_levels()-1 =
+ * coarsest) in FP64; x, y device, amg_level_size(level) doubles.  Exposes
+ * every level's FFT matvec for verification.  Errors: AMG_EINVAL. */
+int amg_level_matvec(amg_t h, int level, const double* x, double* y, void* stream);
+
+/* e = B_K r: one V-cycle of Algorithm 2 from a zero initial guess.  With
+ * AMG_FP64, r and e are double*; with AMG_MIXED they are float* (the coarsest
+ * solve still runs in FP64).  2N-1 entries, device, must not alias. */
+int amg_vcycle(amg_t h, const void* r, void* e, void* stream);
+
+/* Solve A x = b by x <- x + B_K (b - A x) until the relative residual
+ * ||b - A x||_2 / ||b - A x_0||_2 < tol or max_iter (Sec. 5 stopping rule).
+ * b (device, 2N-1 doubles), x (device, in: initial guess, out: solution).
+ * iters/relres (host, may be NULL) receive the iteration count and the final
+ * relative residual (FP64, computed by the FFT matvec).  Returns AMG_OK,
+ * AMG_NOT_CONVERGED or AMG_DIVERGED, or an error code. */
+int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream,
+              int* iters, double* relres);
+
+/* Relative residual history of the last amg_solve: hist (host) receives
+ * min(cap, iters+1) values, hist[i] = ||b - A x_i|| / ||r_0||.  Returns the
+ * number written (>= 0) or an error code. */
+int amg_residual_history(amg_t h, double* hist, int cap);
+
+/* Number of levels (finest .. coarsest) and the unknown count 2 n_l + 1 of
+ * level l (n_l = 2^(K-l) - 1). */
+int amg_num_levels(amg_t h);
+int64_t amg_level_size(amg_t h, int level);
+
+/* Copy level `level`'s Toeplitz-plus-Cross data (eq. (split01)), as built on
+ * the host by Lemma 3.1, into host arrays (any may be NULL): the generators
+ * a, b, c, d of A, B_bar, C_bar, D_bar (2n-1 values each, offsets -(n-1)..n-1),
+ * the Cross vectors p, q, xi, zeta (n values each) and o (1 value). */
+int amg_level_tpx(amg_t h, int level, double* a, double* b, double* c, double* d,
+                  double* p, double* q, double* xi, double* zeta, double* o);
+
+/* Right-hand side f(x_c) = -L_delta u(x_c) for the manufactured solution
+ * u = x^2 (1-x)^2 (zero outside (0,1)) at the 2N-1 collocation points in
+ * block order; host output b_host (2N-1 doubles).  Same kernel/delta/N rules
+ * as amg_setup (AMG_K_GENERATORS is AMG_EINVAL). */
+int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, double* b_host);
+
+/* Device bytes amg_setup would allocate for this problem (spectra, Cross
+ * vectors, per-level work vectors, FFT scratch); < 0 on invalid input. */
+int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
+                            const amg_opts_t* opts);
+
+/* Release every device and host resource of the handle (NULL is a no-op). */
+int amg_destroy(amg_t h);
+
+/* Static description of a status code. */
+const char* amg_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG_H */

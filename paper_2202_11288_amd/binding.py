@@ -1,0 +1,214 @@
+"""Python binding of libamg.so (include/amg.h): argument marshalling only.
+
+Every function has the C ABI's name.  Device vectors are passed as torch
+tensors on the GPU (or raw device addresses as int); streams as
+``torch.cuda.Stream`` or raw ``hipStream_t`` ints (None = the current torch
+stream).  All computation happens in the HIP library; if ``libamg.so`` is
+missing, importing this module raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamg.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "amg.h")
+
+AMG_OK, AMG_NOT_CONVERGED, AMG_DIVERGED = 0, 1, 2
+AMG_EINVAL, AMG_ENOMEM, AMG_EHIP, AMG_ENOTSUP = -1, -2, -3, -4
+AMG_K_CONST, AMG_K_WEIGHTED, AMG_K_FRACTIONAL, AMG_K_GENERATORS = 0, 1, 2, 3
+AMG_FP64, AMG_MIXED = 0, 1
+AMG_FLAG_HOST_ONLY = 1
+
+
+class AmgError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} (status {status})")
+        self.status = status
+
+
+class amg_kernel_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("alpha", ctypes.c_double), ("wl", ctypes.c_double),
+                ("wr", ctypes.c_double), ("gen", ctypes.POINTER(ctypes.c_double))]
+
+
+class amg_opts_t(ctypes.Structure):
+    _fields_ = [("m1", ctypes.c_int), ("m2", ctypes.c_int), ("omega_pre", ctypes.c_double),
+                ("omega_post", ctypes.c_double), ("coarsest_log2", ctypes.c_int),
+                ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2202_11288_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, D, I, I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
+    DP = ctypes.POINTER(ctypes.c_double)
+    IP = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "amg_default_opts": (None, [ctypes.POINTER(amg_opts_t)]),
+        "amg_setup": (I, [ctypes.POINTER(amg_kernel_t), D, I64, ctypes.POINTER(amg_opts_t), P,
+                          ctypes.POINTER(P)]),
+        "amg_matvec": (I, [P, P, P, P]),
+        "amg_level_matvec": (I, [P, I, P, P, P]),
+        "amg_vcycle": (I, [P, P, P, P]),
+        "amg_solve": (I, [P, P, P, D, P, IP, DP]),
+        "amg_residual_history": (I, [P, DP, I]),
+        "amg_num_levels": (I, [P]),
+        "amg_level_size": (I64, [P, I]),
+        "amg_level_tpx": (I, [P, I, DP, DP, DP, DP, DP, DP, DP, DP, DP]),
+        "amg_manufactured_rhs": (I, [ctypes.POINTER(amg_kernel_t), D, I64, DP]),
+        "amg_footprint_bytes": (I64, [ctypes.POINTER(amg_kernel_t), D, I64,
+                                      ctypes.POINTER(amg_opts_t)]),
+        "amg_destroy": (I, [P]),
+        "amg_strerror": (ctypes.c_char_p, [I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def declared_symbols(header: str = HEADER):
+    """Function names declared in include/amg.h."""
+    txt = open(header).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(amg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def strerror(status: int) -> str:
+    return lib.amg_strerror(int(status)).decode()
+
+
+def _check(status: int, what: str, ok=(AMG_OK,)):
+    if status not in ok:
+        raise AmgError(status, what)
+    return status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def kernel(kind: int, alpha: float = 0.0, wl: float = 1.0, wr: float = 1.0, gen=None):
+    """amg_kernel_t; for AMG_K_GENERATORS `gen` is a float64 numpy array that
+    must stay alive until amg_setup returns."""
+    k = amg_kernel_t(kind, alpha, wl, wr, None)
+    if gen is not None:
+        k.gen = gen.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return k
+
+
+def amg_default_opts(**over) -> amg_opts_t:
+    o = amg_opts_t()
+    lib.amg_default_opts(ctypes.byref(o))
+    for k, v in over.items():
+        setattr(o, k, v)
+    return o
+
+
+def amg_setup(kern: amg_kernel_t, delta: float, N: int, opts: amg_opts_t | None = None,
+              stream=None):
+    h = ctypes.c_void_p()
+    host_only = opts is not None and (opts.flags & AMG_FLAG_HOST_ONLY)
+    st = lib.amg_setup(ctypes.byref(kern), float(delta), int(N),
+                       ctypes.byref(opts) if opts is not None else None,
+                       None if host_only else _stream(stream), ctypes.byref(h))
+    _check(st, "amg_setup")
+    return h
+
+
+def amg_destroy(h):
+    return _check(lib.amg_destroy(h), "amg_destroy")
+
+
+def amg_matvec(h, x, y, stream=None):
+    return _check(lib.amg_matvec(h, _ptr(x), _ptr(y), _stream(stream)), "amg_matvec")
+
+
+def amg_level_matvec(h, level: int, x, y, stream=None):
+    return _check(lib.amg_level_matvec(h, int(level), _ptr(x), _ptr(y), _stream(stream)),
+                  "amg_level_matvec")
+
+
+def amg_vcycle(h, r, e, stream=None):
+    return _check(lib.amg_vcycle(h, _ptr(r), _ptr(e), _stream(stream)), "amg_vcycle")
+
+
+def amg_solve(h, b, x, tol: float, stream=None, allow=(AMG_OK,)):
+    """Returns (status, iters, relres); raises unless status is in `allow`."""
+    it = ctypes.c_int()
+    rr = ctypes.c_double()
+    st = lib.amg_solve(h, _ptr(b), _ptr(x), float(tol), _stream(stream), ctypes.byref(it),
+                       ctypes.byref(rr))
+    _check(st, "amg_solve", ok=allow)
+    return st, it.value, rr.value
+
+
+def amg_residual_history(h, cap: int = 100001):
+    import numpy as np
+    buf = np.zeros(cap)
+    k = lib.amg_residual_history(h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap)
+    if k < 0:
+        raise AmgError(k, "amg_residual_history")
+    return buf[:k].copy()
+
+
+def amg_num_levels(h) -> int:
+    return lib.amg_num_levels(h)
+
+
+def amg_level_size(h, level: int) -> int:
+    return lib.amg_level_size(h, int(level))
+
+
+def amg_level_tpx(h, level: int):
+    """dict with the level's generators a, b, c, d, Cross vectors p, q, xi,
+    zeta and o (host copies)."""
+    import numpy as np
+    m = amg_level_size(h, level)
+    if m < 0:
+        raise AmgError(int(m), "amg_level_tpx")
+    n = (m - 1) // 2
+    arr = {k: np.zeros(2 * n - 1) for k in "abcd"}
+    arr.update({k: np.zeros(n) for k in ("p", "q", "xi", "zeta")})
+    o = ctypes.c_double()
+    DP = ctypes.POINTER(ctypes.c_double)
+    args = [arr[k].ctypes.data_as(DP) for k in ("a", "b", "c", "d", "p", "q", "xi", "zeta")]
+    _check(lib.amg_level_tpx(h, int(level), *args, ctypes.byref(o)), "amg_level_tpx")
+    arr["o"] = o.value
+    arr["n"] = n
+    return arr
+
+
+def amg_manufactured_rhs(kern: amg_kernel_t, delta: float, N: int):
+    import numpy as np
+    b = np.zeros(2 * N - 1)
+    _check(lib.amg_manufactured_rhs(ctypes.byref(kern), float(delta), int(N),
+                                    b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "amg_manufactured_rhs")
+    return b
+
+
+def amg_footprint_bytes(kern: amg_kernel_t, delta: float, N: int, opts: amg_opts_t | None = None):
+    return lib.amg_footprint_bytes(ctypes.byref(kern), float(delta), int(N),
+                                   ctypes.byref(opts) if opts is not None else None)

@@ -1,0 +1,749 @@
+// C ABI of the library (include/amg.h): hierarchy setup, level matvecs, the
+// block V-cycle of Algorithm 2 and the outer iteration of Sec. 5 on one
+// MI355X.  All device work is enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/amg.h"
+#include "amg_device.hpp"
+#include "amg_host.hpp"
+#include "fft_lds.hpp"
+
+using namespace amg;
+
+namespace {
+
+constexpr int kTailMaxLog = 13;  // levels with L <= 2^13 run in the one-workgroup tail kernel
+
+struct Plan {
+  int logL, logL1, logL2, tcols;
+  bool tail;
+};
+
+Plan plan_level(int64_t n) {
+  Plan p{};
+  int logL = 0;
+  while ((int64_t(1) << logL) < 2 * (n + 1)) ++logL;
+  p.logL = logL;
+  p.tail = logL <= kTailMaxLog;
+  if (p.tail) {
+    p.logL1 = logL;
+    p.logL2 = 0;
+    p.tcols = 1;
+    return p;
+  }
+  // rows of L1 <= 2048 complex (two rows per workgroup in 64 KB of LDS for
+  // FP64), columns of L2 in tiles of T columns with T*L2 <= 4096
+  p.logL1 = std::min(11, (logL + 1) / 2);
+  p.logL2 = logL - p.logL1;
+  int t = std::max(1, std::min(16, 4096 >> p.logL2));
+  while (t > 4 && ((1 << p.logL1) / t) < 256) t >>= 1;
+  p.tcols = t;
+  return p;
+}
+
+struct LevelRes {
+  int64_t n = 0;
+  Plan plan{};
+  bool sym = false;
+  double o = 0, dv = 0, dw = 0;
+  double *g1d = nullptr, *g2d = nullptr;
+  float *g1f = nullptr, *g2f = nullptr;
+  double *pd = nullptr, *qd = nullptr, *xid = nullptr, *zetad = nullptr;
+  float *pf = nullptr, *qf = nullptr, *xif = nullptr, *zetaf = nullptr;
+  double *bd = nullptr, *ud = nullptr, *rd = nullptr, *scald = nullptr;
+  float *bf = nullptr, *uf = nullptr, *rf = nullptr, *scalf = nullptr;
+
+  template <typename T>
+  LevelDev<T> dev() const;
+};
+
+template <>
+LevelDev<double> LevelRes::dev<double>() const {
+  LevelDev<double> v{};
+  v.n = (int)n;
+  v.logL = plan.logL;
+  v.logL1 = plan.logL1;
+  v.logL2 = plan.logL2;
+  v.tcols = plan.tcols;
+  v.sym = sym;
+  v.g1 = g1d;
+  v.g2 = g2d;
+  v.p = pd;
+  v.q = qd;
+  v.xi = xid;
+  v.zeta = zetad;
+  v.o = o;
+  v.dv = dv;
+  v.dw = dw;
+  v.b = bd;
+  v.u = ud;
+  v.r = rd;
+  v.scal = scald;
+  return v;
+}
+
+template <>
+LevelDev<float> LevelRes::dev<float>() const {
+  LevelDev<float> v{};
+  v.n = (int)n;
+  v.logL = plan.logL;
+  v.logL1 = plan.logL1;
+  v.logL2 = plan.logL2;
+  v.tcols = plan.tcols;
+  v.sym = sym;
+  v.g1 = g1f;
+  v.g2 = g2f;
+  v.p = pf;
+  v.q = qf;
+  v.xi = xif;
+  v.zeta = zetaf;
+  v.o = (float)o;
+  v.dv = (float)dv;
+  v.dw = (float)dw;
+  v.b = bf;
+  v.u = uf;
+  v.r = rf;
+  v.scal = scalf;
+  return v;
+}
+
+}  // namespace
+
+struct amg_ctx {
+  int device = 0;
+  int64_t N = 0;
+  amg_opts_t opts{};
+  bool host_only = false;
+  bool mixed = false;
+  std::vector<TpxLevel> host;
+  std::vector<LevelRes> lv;
+  int first_tail = 0;
+  int maxL_tail = 0;
+  CoarseLU lu{};
+  Twiddles<double> tw64{};
+  Twiddles<float> tw32{};
+  cplx<double>* buf64 = nullptr;
+  cplx<float>* buf32 = nullptr;
+  double* dpart64 = nullptr;  // per-block dot partials (FP64 levels)
+  float* dpart32 = nullptr;   // per-block dot partials (FP32 levels)
+  double* npart = nullptr;    // per-block residual-norm partials
+  LevelDev<double>* lvdev64 = nullptr;
+  LevelDev<float>* lvdev32 = nullptr;
+  SolveState* st_dev = nullptr;
+  SolveState* st_host = nullptr;  // pinned
+  double* hist_dev = nullptr;
+  double* rout = nullptr;  // FP64 outer residual (mixed precision)
+  std::vector<double> hist;
+  int last_iters = 0;
+  std::vector<void*> dev_allocs;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return AMG_EHIP;    \
+  } while (0)
+
+template <typename T>
+int dalloc(amg_ctx* c, T** p, size_t count) {
+  void* ptr = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&ptr, count * sizeof(T)) != hipSuccess) return AMG_ENOMEM;
+  c->dev_allocs.push_back(ptr);
+  *p = static_cast<T*>(ptr);
+  return AMG_OK;
+}
+
+#define AMG_TRY(expr)               \
+  do {                              \
+    int _r = (expr);                \
+    if (_r != AMG_OK) return _r;    \
+  } while (0)
+
+template <typename T>
+int upload(amg_ctx* c, T** dst, const std::vector<T>& src, hipStream_t s) {
+  AMG_TRY(dalloc(c, dst, src.size()));
+  HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return AMG_OK;
+}
+
+// Frees every allocation made after `mark` (setup temporaries); the caller
+// has synchronised the stream.
+void free_since(amg_ctx* c, size_t mark) {
+  while (c->dev_allocs.size() > mark) {
+    (void)hipFree(c->dev_allocs.back());
+    c->dev_allocs.pop_back();
+  }
+}
+
+std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+KernelSpec spec_of(const amg_kernel_t* k, double delta) {
+  KernelSpec s;
+  s.kind = k->kind;
+  s.delta = delta;
+  s.alpha = k->alpha;
+  s.wl = k->wl;
+  s.wr = k->wr;
+  s.gen = k->gen;
+  return s;
+}
+
+int check_opts(const amg_opts_t* o) {
+  if (o->m1 < 1 || o->m2 < 1 || o->m1 > 16 || o->m2 > 16) return AMG_ENOTSUP;
+  if (!(o->omega_pre > 0 && o->omega_pre < 2) || !(o->omega_post > 0 && o->omega_post < 2))
+    return AMG_EINVAL;
+  if (o->coarsest_log2 < 2 || o->coarsest_log2 > 7) return AMG_EINVAL;
+  if (o->precision != AMG_FP64 && o->precision != AMG_MIXED) return AMG_EINVAL;
+  if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
+  if (o->flags & ~AMG_FLAG_HOST_ONLY) return AMG_EINVAL;
+  return AMG_OK;
+}
+
+int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess) {
+  // device bytes: spectra (FP64 + FP32 if mixed), Cross vectors, vectors,
+  // FFT scratch, LU, tables
+  const bool mixed = o->precision == AMG_MIXED;
+  int64_t bytes = 0;
+  int64_t n = N - 1;
+  int64_t L0 = 2 * N;
+  while (n >= (int64_t(1) << o->coarsest_log2) - 1) {
+    const int64_t L = 2 * (n + 1);
+    const int64_t spec = (sym_guess ? 2 : 4) * L;  // reals per spectrum pair
+    bytes += spec * 8 + (mixed ? spec * 4 : 0);
+    bytes += 4 * n * (8 + (mixed ? 4 : 0));
+    bytes += 3 * (2 * n + 1) * (mixed ? 12 : 8);
+    if (n == (int64_t(1) << o->coarsest_log2) - 1) break;
+    n = (n - 1) / 2;
+  }
+  bytes += L0 * 16 * 2 + (mixed ? L0 * 8 : 0);           // FFT scratch (setup uses two)
+  bytes += (mixed ? (2 * N - 1) * 8 : 0);                // outer residual
+  const int64_t mc = (int64_t(2) << o->coarsest_log2) - 1;
+  bytes += 2 * mc * mc * 8;
+  bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
+  return bytes;
+}
+
+template <typename T>
+const Twiddles<T>& tw_of(const amg_ctx* c);
+template <>
+const Twiddles<double>& tw_of<double>(const amg_ctx* c) { return c->tw64; }
+template <>
+const Twiddles<float>& tw_of<float>(const amg_ctx* c) { return c->tw32; }
+template <typename T>
+cplx<T>* buf_of(const amg_ctx* c);
+template <>
+cplx<double>* buf_of<double>(const amg_ctx* c) { return c->buf64; }
+template <>
+cplx<float>* buf_of<float>(const amg_ctx* c) { return c->buf32; }
+template <typename T>
+T* dpart_of(const amg_ctx* c);
+template <>
+double* dpart_of<double>(const amg_ctx* c) { return c->dpart64; }
+template <>
+float* dpart_of<float>(const amg_ctx* c) { return c->dpart32; }
+template <typename T>
+const LevelDev<T>* lvdev_of(const amg_ctx* c);
+template <>
+const LevelDev<double>* lvdev_of<double>(const amg_ctx* c) { return c->lvdev64; }
+template <>
+const LevelDev<float>* lvdev_of<float>(const amg_ctx* c) { return c->lvdev32; }
+
+// One four-step matvec of level l with the given prologue and epilogue.
+template <typename T>
+int fourstep(amg_ctx* c, int l, int cmode, const ColIn<T>& in, int emode, const EpiOut<T>& out,
+             hipStream_t s) {
+  const LevelDev<T> d = c->lv[l].template dev<T>();
+  cplx<T>* buf = buf_of<T>(c);
+  T* dp = dpart_of<T>(c);
+  const Twiddles<T>& tw = tw_of<T>(c);
+  HIP_TRY(launch_col_fwd<T>(cmode, d, in, buf, tw, dp, s));
+  HIP_TRY(launch_row<T>(1, d, buf, tw, dp, col_blocks(d.logL1, d.tcols), out.xin, s));
+  HIP_TRY(launch_col_inv<T>(emode, d, out, buf, tw, c->npart, s));
+  return AMG_OK;
+}
+
+template <typename T>
+int vcycle_dev(amg_ctx* c, hipStream_t s) {
+  // input: level 0's b; output: level 0's u (precision T)
+  const amg_opts_t& o = c->opts;
+  const int nl = (int)c->lv.size();
+  const int ft = c->first_tail;
+  const T wpre = (T)o.omega_pre, wpost = (T)o.omega_post;
+  for (int l = 0; l < ft; ++l) {
+    const LevelDev<T> d = c->lv[l].template dev<T>();
+    ColIn<T> in{};
+    in.omega = wpre;
+    int cmode = COL_PRE;
+    if (l > 0) {
+      cmode = COL_PRE_RESTRICT;
+      in.x = c->lv[l - 1].template dev<T>().r;
+    }
+    EpiOut<T> out{};
+    out.xin = d.u;
+    out.omega = wpre;
+    for (int sweep = 1; sweep <= o.m1; ++sweep) {
+      const int em = (sweep == o.m1) ? EPI_RESID : EPI_SMOOTH;
+      AMG_TRY(fourstep<T>(c, l, cmode, in, em, out, s));
+      cmode = COL_MV;
+      in = ColIn<T>{};
+      in.x = d.u;
+    }
+  }
+  {
+    const T* rf = (ft > 0) ? c->lv[ft - 1].template dev<T>().r : nullptr;
+    HIP_TRY(launch_tail_vcycle<T>(lvdev_of<T>(c), ft, nl - 1, rf, o.m1, o.m2, wpre, wpost, c->lu,
+                                  tw_of<T>(c), c->maxL_tail, s));
+  }
+  for (int l = ft - 1; l >= 0; --l) {
+    const LevelDev<T> d = c->lv[l].template dev<T>();
+    ColIn<T> in{};
+    in.x = c->lv[l + 1].template dev<T>().u;
+    int cmode = COL_PROLONG;
+    EpiOut<T> out{};
+    out.xin = d.u;
+    out.omega = wpost;
+    for (int sweep = 0; sweep < o.m2; ++sweep) {
+      AMG_TRY(fourstep<T>(c, l, cmode, in, EPI_SMOOTH, out, s));
+      cmode = COL_MV;
+      in = ColIn<T>{};
+      in.x = d.u;
+    }
+  }
+  return AMG_OK;
+}
+
+// r = b - A x on the finest level (FP64), optionally with x += e fused in
+// front; writes the residual-norm partials and runs the stopping test.
+int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double tol,
+                   hipStream_t s) {
+  const LevelRes& L0 = c->lv[0];
+  const LevelDev<double> d = L0.dev<double>();
+  ColIn<double> in{};
+  EpiOut<double> out{};
+  out.xin = x;
+  out.bo = b;
+  out.ro = c->mixed ? c->rout : L0.bd;
+  out.r32 = c->mixed ? L0.bf : nullptr;
+  int cmode = COL_MV;
+  if (e) {
+    cmode = COL_OUTER_UPDATE;
+    in.xo = x;
+    in.e = e;
+    in.e_is_float = c->mixed ? 1 : 0;
+  } else {
+    in.x = x;
+  }
+  int npart = 1;
+  if (L0.plan.tail) {
+    HIP_TRY(launch_tail_matvec<double>(cmode, EPI_OUTER, d, in, out, c->tw64, c->npart, s));
+  } else {
+    AMG_TRY(fourstep<double>(c, 0, cmode, in, EPI_OUTER, out, s));
+    npart = col_blocks(d.logL1, d.tcols);
+  }
+  HIP_TRY(launch_finish(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s));
+  return AMG_OK;
+}
+
+int level_matvec64(amg_ctx* c, int l, const double* x, double* y, hipStream_t s) {
+  const LevelRes& R = c->lv[l];
+  const LevelDev<double> d = R.dev<double>();
+  ColIn<double> in{};
+  in.x = x;
+  EpiOut<double> out{};
+  out.xin = x;
+  out.y = y;
+  if (R.plan.tail) {
+    HIP_TRY(launch_tail_matvec<double>(COL_MV, EPI_MV, d, in, out, c->tw64, c->npart, s));
+    return AMG_OK;
+  }
+  return fourstep<double>(c, l, COL_MV, in, EPI_MV, out, s);
+}
+
+int setup_device(amg_ctx* c, hipStream_t s) {
+  const bool mixed = c->mixed;
+  const int nl = (int)c->host.size();
+  // twiddle tables (long double, rounded once)
+  {
+    const std::vector<double> base = twiddles(kTwM, kTwM);
+    const std::vector<double> lo = twiddles(int64_t(1) << kTw4Log, kTw4Lo);
+    const std::vector<double> hi = twiddles(int64_t(1) << kTw4Log, kTw4Hi, kTw4Lo);
+    double *b, *l, *h;
+    float *bf, *lf, *hf;
+    AMG_TRY(upload(c, &b, base, s));
+    AMG_TRY(upload(c, &l, lo, s));
+    AMG_TRY(upload(c, &h, hi, s));
+    AMG_TRY(upload(c, &bf, to_float(base), s));
+    AMG_TRY(upload(c, &lf, to_float(lo), s));
+    AMG_TRY(upload(c, &hf, to_float(hi), s));
+    c->tw64 = {reinterpret_cast<cplx<double>*>(b), reinterpret_cast<cplx<double>*>(l),
+               reinterpret_cast<cplx<double>*>(h)};
+    c->tw32 = {reinterpret_cast<cplx<float>*>(bf), reinterpret_cast<cplx<float>*>(lf),
+               reinterpret_cast<cplx<float>*>(hf)};
+  }
+  const int64_t L0 = 2 * c->N;
+  AMG_TRY(dalloc(c, &c->buf64, (size_t)L0));
+  if (mixed) AMG_TRY(dalloc(c, &c->buf32, (size_t)L0));
+  cplx<double>* zscratch = nullptr;  // second setup transform
+  AMG_TRY(dalloc(c, &zscratch, (size_t)L0));
+  int maxblocks = 1;
+  c->lv.resize(nl);
+  c->first_tail = nl - 1;
+  c->maxL_tail = 0;
+  for (int l = 0; l < nl; ++l) {
+    const TpxLevel& H = c->host[l];
+    LevelRes& R = c->lv[l];
+    R.n = H.n;
+    R.plan = plan_level(H.n);
+    if (l == nl - 1) R.plan.tail = true;  // the coarsest level always lives in the tail kernel
+    if (R.plan.tail) {
+      c->first_tail = std::min(c->first_tail, l);
+      c->maxL_tail = std::max(c->maxL_tail, 1 << R.plan.logL);
+      R.plan.logL1 = R.plan.logL;
+      R.plan.logL2 = 0;
+      R.plan.tcols = 1;
+    } else {
+      maxblocks = std::max(maxblocks, col_blocks(R.plan.logL1, R.plan.tcols));
+      maxblocks = std::max(maxblocks, (1 << R.plan.logL2) / 2);
+    }
+    R.sym = H.symmetric();
+    R.o = H.o;
+    R.dv = H.a[H.n - 1];
+    R.dw = H.d[H.n - 1];
+    const int64_t n = H.n, m = 2 * n + 1, L = int64_t(1) << R.plan.logL;
+    AMG_TRY(upload(c, &R.pd, H.p, s));
+    AMG_TRY(upload(c, &R.qd, H.q, s));
+    AMG_TRY(upload(c, &R.xid, H.xi, s));
+    AMG_TRY(upload(c, &R.zetad, H.zeta, s));
+    AMG_TRY(dalloc(c, &R.bd, m));
+    AMG_TRY(dalloc(c, &R.ud, m));
+    AMG_TRY(dalloc(c, &R.rd, m));
+    AMG_TRY(dalloc(c, &R.scald, 4));
+    HIP_TRY(hipMemsetAsync(R.bd, 0, m * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(R.ud, 0, m * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(R.rd, 0, m * sizeof(double), s));
+    if (mixed) {
+      AMG_TRY(upload(c, &R.pf, to_float(H.p), s));
+      AMG_TRY(upload(c, &R.qf, to_float(H.q), s));
+      AMG_TRY(upload(c, &R.xif, to_float(H.xi), s));
+      AMG_TRY(upload(c, &R.zetaf, to_float(H.zeta), s));
+      AMG_TRY(dalloc(c, &R.bf, m));
+      AMG_TRY(dalloc(c, &R.uf, m));
+      AMG_TRY(dalloc(c, &R.rf, m));
+      AMG_TRY(dalloc(c, &R.scalf, 4));
+      HIP_TRY(hipMemsetAsync(R.bf, 0, m * sizeof(float), s));
+      HIP_TRY(hipMemsetAsync(R.uf, 0, m * sizeof(float), s));
+      HIP_TRY(hipMemsetAsync(R.rf, 0, m * sizeof(float), s));
+    }
+    // spectra
+    const size_t nspec = (size_t)(R.sym ? L : 2 * L);
+    AMG_TRY(dalloc(c, &R.g1d, nspec));
+    AMG_TRY(dalloc(c, &R.g2d, nspec));
+    if (mixed) {
+      AMG_TRY(dalloc(c, &R.g1f, nspec));
+      AMG_TRY(dalloc(c, &R.g2f, nspec));
+    }
+    const size_t mark = c->dev_allocs.size();  // generators: setup temporaries
+    double *ga, *gb, *gc, *gd;
+    AMG_TRY(upload(c, &ga, H.a, s));
+    AMG_TRY(upload(c, &gb, H.b, s));
+    AMG_TRY(upload(c, &gc, H.c, s));
+    AMG_TRY(upload(c, &gd, H.d, s));
+    const LevelDev<double> d = R.dev<double>();
+    if (R.plan.tail) {
+      HIP_TRY(launch_tail_fft_setup(d, ga, gb, c->buf64, c->tw64, s));
+      HIP_TRY(launch_tail_fft_setup(d, gc, gd, zscratch, c->tw64, s));
+    } else {
+      ColIn<double> in{};
+      double* dummy = nullptr;
+      AMG_TRY(dalloc(c, &dummy, (size_t)col_blocks(d.logL1, d.tcols)));
+      in.gx = ga;
+      in.gy = gb;
+      HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, c->buf64, c->tw64, dummy, s));
+      HIP_TRY(launch_row<double>(0, d, c->buf64, c->tw64, dummy, 0, nullptr, s));
+      in.gx = gc;
+      in.gy = gd;
+      HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, zscratch, c->tw64, dummy, s));
+      HIP_TRY(launch_row<double>(0, d, zscratch, c->tw64, dummy, 0, nullptr, s));
+    }
+    HIP_TRY(launch_combine(R.plan.logL, R.plan.logL1, R.plan.logL2, c->buf64, zscratch, R.sym,
+                           R.g1d, R.g2d, R.g1f, R.g2f, s));
+    // generators are only needed for the spectra
+    HIP_TRY(hipStreamSynchronize(s));
+    free_since(c, mark);
+  }
+  // coarsest LU (host, FP64), stored column-major for coalesced columns
+  {
+    const TpxLevel& Hc = c->host.back();
+    const int m = (int)(2 * Hc.n + 1);
+    std::vector<double> A = densify(Hc);
+    std::vector<int> piv;
+    if (!lu_factor(A, m, piv)) return AMG_EINVAL;
+    std::vector<double> lcm((size_t)m * m, 0.0), ucm((size_t)m * m, 0.0), dinv(m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        if (i > j) lcm[(size_t)j * m + i] = A[(size_t)i * m + j];
+        else ucm[(size_t)j * m + i] = A[(size_t)i * m + j];
+      }
+    for (int k = 0; k < m; ++k) dinv[k] = 1.0 / A[(size_t)k * m + k];
+    std::vector<int> perm(m);
+    for (int i = 0; i < m; ++i) perm[i] = i;
+    for (int k = 0; k < m; ++k) std::swap(perm[k], perm[piv[k]]);
+    double *l, *u, *di;
+    int* pm;
+    AMG_TRY(upload(c, &l, lcm, s));
+    AMG_TRY(upload(c, &u, ucm, s));
+    AMG_TRY(upload(c, &di, dinv, s));
+    AMG_TRY(upload(c, &pm, perm, s));
+    c->lu = {m, l, u, di, pm};
+  }
+  AMG_TRY(dalloc(c, &c->dpart64, (size_t)maxblocks));
+  AMG_TRY(dalloc(c, &c->dpart32, (size_t)maxblocks));
+  AMG_TRY(dalloc(c, &c->npart, (size_t)maxblocks));
+  {
+    std::vector<LevelDev<double>> v64(nl);
+    for (int l = 0; l < nl; ++l) v64[l] = c->lv[l].dev<double>();
+    AMG_TRY(dalloc(c, &c->lvdev64, nl));
+    HIP_TRY(hipMemcpyAsync(c->lvdev64, v64.data(), nl * sizeof(LevelDev<double>),
+                           hipMemcpyHostToDevice, s));
+    if (mixed) {
+      std::vector<LevelDev<float>> v32(nl);
+      for (int l = 0; l < nl; ++l) v32[l] = c->lv[l].dev<float>();
+      AMG_TRY(dalloc(c, &c->lvdev32, nl));
+      HIP_TRY(hipMemcpyAsync(c->lvdev32, v32.data(), nl * sizeof(LevelDev<float>),
+                             hipMemcpyHostToDevice, s));
+    }
+  }
+  AMG_TRY(dalloc(c, &c->st_dev, 1));
+  AMG_TRY(dalloc(c, &c->hist_dev, (size_t)c->opts.max_iter + 2));
+  if (mixed) AMG_TRY(dalloc(c, &c->rout, (size_t)(2 * c->N - 1)));
+  void* ph = nullptr;
+  HIP_TRY(hipHostMalloc(&ph, sizeof(SolveState), hipHostMallocDefault));
+  c->st_host = static_cast<SolveState*>(ph);
+  HIP_TRY(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
+void release(amg_ctx* c) {
+  if (!c) return;
+  for (void* p : c->dev_allocs) (void)hipFree(p);
+  c->dev_allocs.clear();
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  c->st_host = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+void amg_default_opts(amg_opts_t* o) {
+  if (!o) return;
+  o->m1 = 1;
+  o->m2 = 1;
+  o->omega_pre = 2.0 / 3.0;
+  o->omega_post = 2.0 / 3.0;
+  o->coarsest_log2 = 5;
+  o->precision = AMG_FP64;
+  o->max_iter = 200;
+  o->flags = 0;
+}
+
+const char* amg_strerror(int st) {
+  switch (st) {
+    case AMG_OK: return "ok";
+    case AMG_NOT_CONVERGED: return "not converged within max_iter";
+    case AMG_DIVERGED: return "diverged (NaN/Inf or residual growth)";
+    case AMG_EINVAL: return "invalid argument";
+    case AMG_ENOMEM: return "out of memory";
+    case AMG_EHIP: return "HIP runtime error";
+    case AMG_ENOTSUP: return "not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opts_t* opts,
+              void* stream, amg_t* out) {
+  if (!kernel || !out) return AMG_EINVAL;
+  *out = nullptr;
+  amg_opts_t o;
+  if (opts) o = *opts;
+  else amg_default_opts(&o);
+  int st = check_opts(&o);
+  if (st != AMG_OK) return st;
+  const KernelSpec ks = spec_of(kernel, kernel->kind == AMG_K_GENERATORS ? 0.25 : delta);
+  if (!validate(ks, N, o.coarsest_log2).empty()) return AMG_EINVAL;
+  if (kernel->kind != AMG_K_GENERATORS && !(std::isfinite(delta))) return AMG_EINVAL;
+  amg_ctx* c = new (std::nothrow) amg_ctx();
+  if (!c) return AMG_ENOMEM;
+  c->N = N;
+  c->opts = o;
+  c->host_only = (o.flags & AMG_FLAG_HOST_ONLY) != 0;
+  c->mixed = o.precision == AMG_MIXED;
+  try {
+    c->host.push_back(finest_level(ks, N));
+    const int64_t nc = (int64_t(1) << o.coarsest_log2) - 1;
+    while (c->host.back().n > nc) c->host.push_back(coarsen(c->host.back()));
+  } catch (const std::bad_alloc&) {
+    delete c;
+    return AMG_ENOMEM;
+  }
+  for (const TpxLevel& t : c->host) {
+    for (const auto* v : {&t.a, &t.b, &t.c, &t.d, &t.p, &t.q, &t.xi, &t.zeta})
+      for (double x : *v)
+        if (!std::isfinite(x)) {
+          delete c;
+          return AMG_EINVAL;
+        }
+    if (!(t.a[t.n - 1] != 0.0 && t.d[t.n - 1] != 0.0 && t.o != 0.0)) {
+      delete c;
+      return AMG_EINVAL;  // Jacobi needs a nonzero diagonal
+    }
+  }
+  if (!c->host_only) {
+    if (hipGetDevice(&c->device) != hipSuccess) {
+      delete c;
+      return AMG_EHIP;
+    }
+    st = setup_device(c, (hipStream_t)stream);
+    if (st != AMG_OK) {
+      release(c);
+      delete c;
+      return st;
+    }
+  }
+  *out = c;
+  return AMG_OK;
+}
+
+int amg_destroy(amg_t h) {
+  if (!h) return AMG_OK;
+  if (!h->host_only) (void)hipSetDevice(h->device);
+  release(h);
+  delete h;
+  return AMG_OK;
+}
+
+int amg_num_levels(amg_t h) { return h ? (int)h->host.size() : AMG_EINVAL; }
+
+int64_t amg_level_size(amg_t h, int level) {
+  if (!h || level < 0 || level >= (int)h->host.size()) return AMG_EINVAL;
+  return 2 * h->host[level].n + 1;
+}
+
+int amg_level_tpx(amg_t h, int level, double* a, double* b, double* c, double* d, double* p,
+                  double* q, double* xi, double* zeta, double* o) {
+  if (!h || level < 0 || level >= (int)h->host.size()) return AMG_EINVAL;
+  const TpxLevel& t = h->host[level];
+  auto cp = [](double* dst, const std::vector<double>& v) {
+    if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+  };
+  cp(a, t.a);
+  cp(b, t.b);
+  cp(c, t.c);
+  cp(d, t.d);
+  cp(p, t.p);
+  cp(q, t.q);
+  cp(xi, t.xi);
+  cp(zeta, t.zeta);
+  if (o) *o = t.o;
+  return AMG_OK;
+}
+
+int amg_matvec(amg_t h, const double* x, double* y, void* stream) {
+  return amg_level_matvec(h, 0, x, y, stream);
+}
+
+int amg_level_matvec(amg_t h, int level, const double* x, double* y, void* stream) {
+  if (!h || !x || !y || h->host_only || level < 0 || level >= (int)h->lv.size()) return AMG_EINVAL;
+  if (x == y) return AMG_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  return level_matvec64(h, level, x, y, (hipStream_t)stream);
+}
+
+int amg_vcycle(amg_t h, const void* r, void* e, void* stream) {
+  if (!h || !r || !e || h->host_only || r == e) return AMG_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  const LevelRes& L0 = h->lv[0];
+  const size_t m = (size_t)(2 * L0.n + 1);
+  if (h->mixed) {
+    HIP_TRY(hipMemcpyAsync(L0.bf, r, m * sizeof(float), hipMemcpyDeviceToDevice, s));
+    AMG_TRY(vcycle_dev<float>(h, s));
+    HIP_TRY(hipMemcpyAsync(e, L0.uf, m * sizeof(float), hipMemcpyDeviceToDevice, s));
+  } else {
+    HIP_TRY(hipMemcpyAsync(L0.bd, r, m * sizeof(double), hipMemcpyDeviceToDevice, s));
+    AMG_TRY(vcycle_dev<double>(h, s));
+    HIP_TRY(hipMemcpyAsync(e, L0.ud, m * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return AMG_OK;
+}
+
+int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int* iters,
+              double* relres) {
+  if (!h || !b || !x || h->host_only || b == x) return AMG_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return AMG_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  SolveState init{};
+  *h->st_host = init;
+  HIP_TRY(hipMemcpyAsync(h->st_dev, h->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
+  AMG_TRY(outer_residual(h, b, x, nullptr, tol, s));
+  const void* e = h->mixed ? (const void*)h->lv[0].uf : (const void*)h->lv[0].ud;
+  for (;;) {
+    HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h->st_host->done) break;
+    if (h->mixed) AMG_TRY(vcycle_dev<float>(h, s));
+    else AMG_TRY(vcycle_dev<double>(h, s));
+    AMG_TRY(outer_residual(h, b, x, e, tol, s));
+  }
+  const SolveState st = *h->st_host;
+  h->last_iters = st.iter;
+  h->hist.assign((size_t)st.iter + 1, 0.0);
+  HIP_TRY(hipMemcpy(h->hist.data(), h->hist_dev, h->hist.size() * sizeof(double),
+                    hipMemcpyDeviceToHost));
+  if (iters) *iters = st.iter;
+  if (relres) *relres = st.relres;
+  return st.status;
+}
+
+int amg_residual_history(amg_t h, double* hist, int cap) {
+  if (!h || (!hist && cap > 0) || cap < 0) return AMG_EINVAL;
+  const int k = std::min<int>(cap, (int)h->hist.size());
+  for (int i = 0; i < k; ++i) hist[i] = h->hist[i];
+  return k;
+}
+
+int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, double* b_host) {
+  if (!kernel || !b_host || kernel->kind == AMG_K_GENERATORS) return AMG_EINVAL;
+  const KernelSpec ks = spec_of(kernel, delta);
+  if (!validate(ks, N, 2).empty() || !std::isfinite(delta)) return AMG_EINVAL;
+  manufactured_rhs(ks, N, b_host);
+  return AMG_OK;
+}
+
+int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
+                            const amg_opts_t* opts) {
+  if (!kernel) return AMG_EINVAL;
+  amg_opts_t o;
+  if (opts) o = *opts;
+  else amg_default_opts(&o);
+  if (check_opts(&o) != AMG_OK) return AMG_EINVAL;
+  const KernelSpec ks = spec_of(kernel, kernel->kind == AMG_K_GENERATORS ? 0.25 : delta);
+  if (!validate(ks, N, o.coarsest_log2).empty()) return AMG_EINVAL;
+  return footprint(N, &o, kernel->kind == AMG_K_CONST || kernel->kind == AMG_K_FRACTIONAL);
+}
+
+}  // extern "C"

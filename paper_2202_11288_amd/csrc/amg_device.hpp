@@ -1,0 +1,130 @@
+// Device-side data views and kernel launchers shared by the HIP kernels
+// (amg_kernels.hip) and the C-ABI orchestration (amg_api.cpp).  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace amg {
+
+template <typename T>
+struct cplx;
+
+// Constants of the FFT machinery.
+constexpr int kTwM = 16384;        // base twiddle table: e^{-2 pi i m / kTwM}
+constexpr int kTw4Log = 23;        // four-step twiddles resolved on 2^23 points
+constexpr int kTw4Lo = 4096;       // low table: e^{-2 pi i m / 2^23}, m < 4096
+constexpr int kTw4Hi = 2048;       // high table: e^{-2 pi i m 4096 / 2^23}, m < 2048
+constexpr int kNT4 = 256;          // threads of a four-step pass workgroup
+constexpr int kNTT = 1024;         // threads of the single-workgroup tail kernels
+
+template <typename T>
+struct Twiddles {
+  const cplx<T>* base;  // kTwM entries
+  const cplx<T>* lo;    // kTw4Lo entries
+  const cplx<T>* hi;    // kTw4Hi entries
+};
+
+// One Toeplitz-plus-Cross level (eq. (split01)) as the kernels see it.
+// n = v-size; the packed FFT signal z = v + i w_bar has L = 2(n+1) points.
+// Four-step levels: L = L1 * L2 (L1 = row length), column tiles of T columns.
+// Tail levels (whole FFT in one workgroup's LDS): logL2 = 0.
+// Spectra: G1, G2 with Y[f] = G1[f] Z[f] + G2[f] conj(Z[-f]), already divided
+// by L; stored at the position the row pass holds bin f (k1 + L1 k2 for
+// f = k2 + L2 k1; natural order for tail levels).  sym: G1 real, G2 = i*g2
+// (one real array each); otherwise interleaved complex arrays.
+template <typename T>
+struct LevelDev {
+  int n;
+  int logL, logL1, logL2, tcols;
+  int sym;
+  const T* g1;
+  const T* g2;
+  const T* p;
+  const T* q;
+  const T* xi;
+  const T* zeta;
+  T o, dv, dw;  // diagonal: a_0 (v rows), o (w_o row), d_0 (w_bar rows)
+  T* b;         // level right-hand side (2n+1)
+  T* u;         // level iterate (2n+1)
+  T* r;         // level residual (2n+1)
+  T* scal;      // scal[0]: y_o of the matvec in flight
+};
+
+// Prologue of the forward column pass: how the FFT input vector is formed.
+enum ColMode { COL_MV = 0, COL_PRE = 1, COL_PRE_RESTRICT = 2, COL_PROLONG = 3,
+               COL_OUTER_UPDATE = 4, COL_SETUP = 5 };
+// Epilogue of the inverse column pass.
+enum EpiMode { EPI_MV = 0, EPI_RESID = 1, EPI_SMOOTH = 2, EPI_OUTER = 3 };
+
+template <typename T>
+struct ColIn {
+  const T* x;          // COL_MV: input; COL_PRE_RESTRICT: fine residual; COL_PROLONG: coarse iterate
+  T omega;             // COL_PRE / COL_PRE_RESTRICT
+  double* xo;          // COL_OUTER_UPDATE: solution (updated in place)
+  const void* e;       // COL_OUTER_UPDATE: correction (float or double)
+  int e_is_float;
+  const double* gx;    // COL_SETUP: generator of the real part's block
+  const double* gy;    // COL_SETUP: generator of the imaginary part's block
+};
+
+template <typename T>
+struct EpiOut {
+  const T* xin;        // matvec input (its w_o feeds the Cross terms)
+  T* y;                // EPI_MV output
+  T omega;             // EPI_SMOOTH
+  const double* bo;    // EPI_OUTER: right-hand side
+  double* ro;          // EPI_OUTER: residual (FP64)
+  float* r32;          // EPI_OUTER: FP32 copy of the residual (may be null)
+};
+
+struct CoarseLU {
+  int m;
+  const double* lcm;   // unit-lower multipliers, column-major m x m
+  const double* ucm;   // upper factor, column-major m x m
+  const double* dinv;  // 1 / U[k][k]
+  const int* perm;     // (P b)[i] = b[perm[i]]
+};
+
+struct SolveState {
+  double r0;
+  double relres;
+  double best;
+  int iter;
+  int status;
+  int done;
+  int pad;
+};
+
+// ---- launchers (all asynchronous on `s`) ------------------------------------
+template <typename T>
+hipError_t launch_col_fwd(int mode, const LevelDev<T>& lv, const ColIn<T>& in, cplx<T>* buf,
+                          const Twiddles<T>& tw, T* part, hipStream_t s);
+template <typename T>
+hipError_t launch_row(int spectral, const LevelDev<T>& lv, cplx<T>* buf, const Twiddles<T>& tw,
+                      const T* part, int npart, const T* xin, hipStream_t s);
+template <typename T>
+hipError_t launch_col_inv(int mode, const LevelDev<T>& lv, const EpiOut<T>& out,
+                          const cplx<T>* buf, const Twiddles<T>& tw, double* part, hipStream_t s);
+template <typename T>
+hipError_t launch_tail_matvec(int colmode, int epimode, const LevelDev<T>& lv, const ColIn<T>& in,
+                              const EpiOut<T>& out, const Twiddles<T>& tw, double* part,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
+                              int m1, int m2, T wpre, T wpost, const CoarseLU& lu,
+                              const Twiddles<T>& tw, int maxL, hipStream_t s);
+hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, const double* gy,
+                                 cplx<double>* out, const Twiddles<double>& tw, hipStream_t s);
+hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1,
+                          const cplx<double>* z2, int sym, double* g1, double* g2, float* g1f,
+                          float* g2f, hipStream_t s);
+hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
+                         double* hist, hipStream_t s);
+hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s);
+
+// Column tiles / grid sizes used by the launchers (host helpers).
+inline int col_blocks(int logL1, int tcols) { return (1 << logL1) / tcols; }
+
+}  // namespace amg

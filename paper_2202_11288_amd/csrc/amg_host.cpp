@@ -1,0 +1,346 @@
+// Host numerics: product-integration generators (Sec. 2.2, eq. (ccs2.1),
+// shifted-symmetric rule of eq. (system1)), Galerkin coarsening (Lemma 3.1),
+// coarsest LU (Algorithm 2, B_1 = A_1^{-1}), twiddle tables.
+#include "amg_host.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+namespace amg {
+
+namespace {
+
+double kernel_c(const KernelSpec& k) {
+  if (k.kind == K_FRACTIONAL) return (1.0 - k.alpha) * std::pow(k.delta, 2.0 * k.alpha - 2.0);
+  return 3.0 / (2.0 * k.delta * k.delta * k.delta);
+}
+
+// Gauss-Legendre nodes/weights on [0,1] (Newton iteration on P_n, long double).
+struct GaussLegendre {
+  std::vector<double> x, w;
+  explicit GaussLegendre(int n) : x(n), w(n) {
+    const long double pi = acosl(-1.0L);
+    for (int i = 0; i < n; ++i) {
+      long double z = cosl(pi * (i + 0.75L) / (n + 0.5L)), dp = 0;
+      for (int it = 0; it < 100; ++it) {
+        long double p0 = 1, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+          long double p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1);
+        long double dz = p1 / dp;
+        z -= dz;
+        if (fabsl(dz) < 1e-19L) break;
+      }
+      x[i] = (double)((1 - z) / 2);
+      w[i] = (double)(1 / ((1 - z * z) * dp * dp));  // = 2/((1-z^2)P'^2) / 2
+    }
+  }
+};
+
+// int_0^theta (k + t)^beta t^j dt for j = 0,1,2 (dimensionless).  k = 0:
+// closed form (j >= 1; j = 0 diverges and is never requested).  k >= 1: the
+// integrand is analytic on a neighbourhood of [0, theta] whose nearest
+// singularity is at t = -k, so 32-point Gauss-Legendre is exact to rounding.
+void frac_cell(int64_t k, double theta, double beta, double J[3]) {
+  if (k == 0) {
+    J[0] = NAN;
+    J[1] = std::pow(theta, beta + 2) / (beta + 2);
+    J[2] = std::pow(theta, beta + 3) / (beta + 3);
+    return;
+  }
+  // nearest singularity at distance k from the cell: 12 points suffice for
+  // k >= 4 (Bernstein-ellipse factor > 17), 32 points below.
+  static const GaussLegendre gl32(32), gl12(12);
+  const GaussLegendre& gl = (k >= 4) ? gl12 : gl32;
+  long double s0 = 0, s1 = 0, s2 = 0;
+  for (size_t i = 0; i < gl.x.size(); ++i) {
+    const double t = theta * gl.x[i];
+    const long double f = (long double)gl.w[i] * std::pow((double)k + t, beta);
+    s0 += f;
+    s1 += f * t;
+    s2 += f * t * t;
+  }
+  J[0] = (double)(s0 * theta);
+  J[1] = (double)(s1 * theta);
+  J[2] = (double)(s2 * theta);
+}
+
+}  // namespace
+
+bool TpxLevel::symmetric() const {
+  const int64_t m = 2 * n - 1;
+  for (int64_t i = 0; i < m; ++i) {
+    if (a[i] != a[m - 1 - i] || d[i] != a[i] || c[i] != b[m - 1 - i]) return false;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (p[i] != q[i] || xi[i] != zeta[i]) return false;
+  return true;
+}
+
+std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2) {
+  std::ostringstream e;
+  if (N <= 0 || (N & (N - 1)) != 0) e << "N must be a power of two; ";
+  int K = 0;
+  while (N > 0 && (int64_t(1) << K) < N) ++K;
+  if (coarsest_log2 < 2) e << "coarsest_log2 must be >= 2; ";
+  if (K <= coarsest_log2) e << "need log2(N) > coarsest_log2; ";
+  if (K > 22) e << "log2(N) <= 22 in this build; ";
+  if (k.kind < 0 || k.kind > 3) e << "unknown kernel kind; ";
+  if (k.kind != K_GENERATORS) {
+    if (!(k.delta > 0.0 && k.delta < 0.5)) e << "need 0 < delta < 1/2; ";
+  } else if (k.gen == nullptr) {
+    e << "AMG_K_GENERATORS needs gen; ";
+  }
+  if (k.kind == K_FRACTIONAL && !(k.alpha > 0.0 && k.alpha < 0.5))
+    e << "fractional kernel needs 0 < alpha < 1/2; ";
+  if (k.kind == K_WEIGHTED && !(std::isfinite(k.wl) && std::isfinite(k.wr) && k.wl > 0 && k.wr > 0))
+    e << "weights must be positive; ";
+  return e.str();
+}
+
+std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
+  const double h = 1.0 / (double)N;
+  const double R = k.delta * (double)N;  // exact: N is a power of two
+  const int64_t r = (int64_t)std::floor(R);
+  const double th_last = R - (double)r;
+  const int64_t ncell = r + (th_last > 0.0 ? 1 : 0);
+  const int64_t S = 2 * ncell;
+  std::vector<double> W(2 * S + 1, 0.0);
+  const double c = kernel_c(k);
+  const bool frac = k.kind == K_FRACTIONAL;
+  const double beta = frac ? -1.0 - 2.0 * k.alpha : 0.0;
+  const double scale = frac ? c * std::pow(h, beta + 1.0) : c * h;
+  const double wr = (k.kind == K_WEIGHTED) ? k.wr : 1.0;
+  const double wl = (k.kind == K_WEIGHTED) ? k.wl : 1.0;
+  // cell k: t in [k h, (k+theta) h]; quadratic through local tau = 0, 1/2, 1:
+  //   l_a = 1 - 3 tau + 2 tau^2,  l_b = 4 tau - 4 tau^2,  l_c = 2 tau^2 - tau.
+  for (int64_t kc = 0; kc < ncell; ++kc) {
+    const double th = (kc < r) ? 1.0 : th_last;
+    double J[3];
+    if (frac) {
+      frac_cell(kc, th, beta, J);
+    } else {
+      J[0] = th;
+      J[1] = th * th / 2.0;
+      J[2] = th * th * th / 3.0;
+    }
+    for (double& v : J) v *= scale;
+    const double Ib = 4 * J[1] - 4 * J[2];
+    const double Ic = 2 * J[2] - J[1];
+    const double own = (kc == 0) ? (3 * J[1] - 2 * J[2]) : J[0];  // int gamma (1 - l_0)
+    W[S] += (wr + wl) * own;
+    if (kc > 0) {
+      const double Ia = J[0] - 3 * J[1] + 2 * J[2];
+      W[S + 2 * kc] -= wr * Ia;
+      W[S - 2 * kc] -= wl * Ia;
+    }
+    W[S + 2 * kc + 1] -= wr * Ib;
+    W[S - 2 * kc - 1] -= wl * Ib;
+    W[S + 2 * kc + 2] -= wr * Ic;
+    W[S - 2 * kc - 2] -= wl * Ic;
+  }
+  *Sout = S;
+  return W;
+}
+
+TpxLevel finest_level(const KernelSpec& k, int64_t N) {
+  TpxLevel t;
+  const int64_t n = N - 1;
+  t.n = n;
+  t.a.resize(2 * n - 1);
+  t.b.resize(2 * n - 1);
+  t.c.resize(2 * n - 1);
+  t.d.resize(2 * n - 1);
+  t.p.resize(n);
+  t.q.resize(n);
+  t.xi.resize(n);
+  t.zeta.resize(n);
+  if (k.kind == K_GENERATORS) {
+    // [A | B | C | D] with the layouts of the C ABI.
+    const double* gA = k.gen;
+    const double* gB = gA + (2 * n - 1);
+    const double* gC = gB + 2 * n;
+    const double* gD = gC + 2 * n;
+    auto B = [&](int64_t off) { return gB[off + n - 1]; };  // -(n-1)..n
+    auto C = [&](int64_t off) { return gC[off + n]; };      // -n..n-1
+    auto D = [&](int64_t off) { return gD[off + n]; };      // -n..n
+    for (int64_t dd = -(n - 1); dd <= n - 1; ++dd) {
+      t.a[dd + n - 1] = gA[dd + n - 1];
+      t.b[dd + n - 1] = B(dd + 1);   // B_bar = B[:, 1:]
+      t.c[dd + n - 1] = C(dd - 1);   // C_bar = C[1:, :]
+      t.d[dd + n - 1] = D(dd);       // D_bar = D[1:, 1:]
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      t.p[i] = B(-i);        // B[:, 0]
+      t.q[i] = C(i);         // C[0, :]
+      t.xi[i] = D(-i - 1);   // D[1:, 0]
+      t.zeta[i] = D(i + 1);  // D[0, 1:]
+    }
+    t.o = D(0);
+    return t;
+  }
+  int64_t S = 0;
+  const std::vector<double> W = row_stencil(k, N, &S);
+  auto Wat = [&](int64_t s2) { return (s2 < -S || s2 > S) ? 0.0 : W[s2 + S]; };
+  // Interleaved positions: v_i at 2(i+1), w_o at 1, w_bar_j at 2j+3 (units h/2).
+  for (int64_t dd = -(n - 1); dd <= n - 1; ++dd) {
+    t.a[dd + n - 1] = Wat(2 * dd);
+    t.b[dd + n - 1] = Wat(2 * dd + 1);
+    t.c[dd + n - 1] = Wat(2 * dd - 1);
+    t.d[dd + n - 1] = Wat(2 * dd);
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    t.p[i] = Wat(-2 * i - 1);
+    t.q[i] = Wat(2 * i + 1);
+    t.xi[i] = Wat(-2 * i - 2);
+    t.zeta[i] = Wat(2 * i + 2);
+  }
+  t.o = Wat(0);
+  return t;
+}
+
+TpxLevel coarsen(const TpxLevel& f) {
+  // Galerkin R A P with R = 1/4[1 2 1] (stride 2) on [v; w_o; w_bar] and
+  // P = 2 R^T.  The v/w_bar blocks only see the fine Toeplitz blocks, giving
+  // t'_i = (t_{2i-2} + 4t_{2i-1} + 6t_{2i} + 4t_{2i+1} + t_{2i+2}) / 8.
+  // The coarse w_o column is R (A z) with z = P e_{w_o} = 1/2 e_{v,n-1} +
+  // e_{w_o} + 1/2 e_{w_bar,0}; the coarse w_o row is (rho^T A) P with
+  // rho = 1/4 e_{v,n-1} + 1/2 e_{w_o} + 1/4 e_{w_bar,0} (Lemma 3.1).
+  const int64_t n = f.n, nc = (n - 1) / 2;
+  auto g = [n](const std::vector<double>& t, int64_t off) { return t[off + n - 1]; };
+  TpxLevel c;
+  c.n = nc;
+  for (auto* v : {&c.a, &c.b, &c.c, &c.d}) v->assign(2 * nc - 1, 0.0);
+  const std::vector<double>* fine[4] = {&f.a, &f.b, &f.c, &f.d};
+  std::vector<double>* coarse[4] = {&c.a, &c.b, &c.c, &c.d};
+  for (int blk = 0; blk < 4; ++blk) {
+    const auto& t = *fine[blk];
+    for (int64_t i = -(nc - 1); i <= nc - 1; ++i) {
+      (*coarse[blk])[i + nc - 1] = (g(t, 2 * i - 2) + 4 * g(t, 2 * i - 1) + 6 * g(t, 2 * i) +
+                                    4 * g(t, 2 * i + 1) + g(t, 2 * i + 2)) / 8.0;
+    }
+  }
+  std::vector<double> colv(n), colw(n), rowv(n), roww(n);
+  for (int64_t i = 0; i < n; ++i) {
+    colv[i] = 0.5 * g(f.a, n - 1 - i) + f.p[i] + 0.5 * g(f.b, -i);
+    colw[i] = 0.5 * g(f.c, n - 1 - i) + f.xi[i] + 0.5 * g(f.d, -i);
+    rowv[i] = 0.25 * g(f.a, i - n + 1) + 0.5 * f.q[i] + 0.25 * g(f.c, i);
+    roww[i] = 0.25 * g(f.b, i - n + 1) + 0.5 * f.zeta[i] + 0.25 * g(f.d, i);
+  }
+  const double colo = 0.5 * f.q[n - 1] + f.o + 0.5 * f.zeta[0];
+  auto R = [](const std::vector<double>& x, int64_t i) {
+    return 0.25 * (x[2 * i] + 2 * x[2 * i + 1] + x[2 * i + 2]);
+  };
+  c.p.resize(nc);
+  c.xi.resize(nc);
+  c.q.resize(nc);
+  c.zeta.resize(nc);
+  for (int64_t i = 0; i < nc; ++i) {
+    c.p[i] = R(colv, i);
+    c.xi[i] = R(colw, i);
+    c.q[i] = 2.0 * R(rowv, i);
+    c.zeta[i] = 2.0 * R(roww, i);
+  }
+  c.o = 0.25 * colv[n - 1] + 0.5 * colo + 0.25 * colw[0];
+  return c;
+}
+
+std::vector<double> densify(const TpxLevel& t) {
+  const int64_t n = t.n, m = 2 * n + 1;
+  std::vector<double> M(m * m, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t off = j - i + n - 1;
+      M[i * m + j] = t.a[off];
+      M[i * m + (n + 1 + j)] = t.b[off];
+      M[(n + 1 + i) * m + j] = t.c[off];
+      M[(n + 1 + i) * m + (n + 1 + j)] = t.d[off];
+    }
+    M[i * m + n] = t.p[i];
+    M[n * m + i] = t.q[i];
+    M[(n + 1 + i) * m + n] = t.xi[i];
+    M[n * m + (n + 1 + i)] = t.zeta[i];
+  }
+  M[n * m + n] = t.o;
+  return M;
+}
+
+bool lu_factor(std::vector<double>& A, int m, std::vector<int>& piv) {
+  piv.assign(m, 0);
+  for (int k = 0; k < m; ++k) {
+    int pr = k;
+    double best = std::fabs(A[k * m + k]);
+    for (int i = k + 1; i < m; ++i)
+      if (std::fabs(A[i * m + k]) > best) best = std::fabs(A[i * m + k]), pr = i;
+    piv[k] = pr;
+    if (best == 0.0) return false;
+    if (pr != k)
+      for (int j = 0; j < m; ++j) std::swap(A[k * m + j], A[pr * m + j]);
+    const double inv = 1.0 / A[k * m + k];
+    for (int i = k + 1; i < m; ++i) {
+      const double l = A[i * m + k] * inv;
+      A[i * m + k] = l;
+      for (int j = k + 1; j < m; ++j) A[i * m + j] -= l * A[k * m + j];
+    }
+  }
+  return true;
+}
+
+void manufactured_rhs(const KernelSpec& k, int64_t N, double* out) {
+  // f(x) = int_{|t|<=delta} gamma(t) (u(x) - u~(x+t)) dt, u = x^2 (1-x)^2 on
+  // (0,1), u~ = 0 outside.  Constant/weighted kernels: antiderivative
+  // U(y) = y^3/3 - y^4/2 + y^5/5.  Fractional kernel: Taylor expansion of u
+  // about x (exact, degree 4) where x + t stays in (0,1), u(x) times the
+  // kernel mass where it leaves.
+  const double d = k.delta, c = kernel_c(k);
+  const double wl = (k.kind == K_WEIGHTED) ? k.wl : 1.0;
+  const double wr = (k.kind == K_WEIGHTED) ? k.wr : 1.0;
+  auto u = [](double x) { return x * x * (1 - x) * (1 - x); };
+  auto U = [](double y) { return y * y * y * (1.0 / 3 - y / 2 + y * y / 5); };
+  const int64_t m = 2 * N - 1;
+  for (int64_t idx = 0; idx < m; ++idx) {
+    const double x = (idx < N - 1) ? (double)(idx + 1) / (double)N
+                                   : ((double)(idx - (N - 1)) + 0.5) / (double)N;
+    const double ux = u(x);
+    double f;
+    if (k.kind != K_FRACTIONAL) {
+      const double right = ux * d - (U(std::fmin(x + d, 1.0)) - U(x));
+      const double left = ux * d - (U(x) - U(std::fmax(x - d, 0.0)));
+      f = c * (wr * right + wl * left);
+    } else {
+      const double be = -1.0 - 2.0 * k.alpha;
+      const double tr = std::fmin(d, 1.0 - x), tl = std::fmin(d, x);
+      const double du[4] = {2 * x - 6 * x * x + 4 * x * x * x, 2 - 12 * x + 12 * x * x,
+                            -12 + 24 * x, 24.0};
+      const double fact[4] = {1, 2, 6, 24};
+      f = 0.0;
+      for (int p = 1; p <= 4; ++p) {
+        const double e = be + p + 1;
+        const double sgn = (p % 2) ? -1.0 : 1.0;
+        f -= du[p - 1] / fact[p - 1] * (std::pow(tr, e) + sgn * std::pow(tl, e)) / e;
+      }
+      for (double a : {1.0 - x, x})
+        if (a < d) f += ux * (std::pow(d, be + 1) - std::pow(a, be + 1)) / (be + 1);
+      f *= c;
+    }
+    out[idx] = f;
+  }
+}
+
+std::vector<double> twiddles(int64_t M, int64_t count, int64_t stride) {
+  std::vector<double> t(2 * count);
+  const long double two_pi = 2.0L * acosl(-1.0L);
+  for (int64_t m = 0; m < count; ++m) {
+    const int64_t e = (m * stride) % M;
+    const long double ang = two_pi * (long double)e / (long double)M;
+    t[2 * m] = (double)cosl(ang);
+    t[2 * m + 1] = (double)(-sinl(ang));
+  }
+  return t;
+}
+
+}  // namespace amg

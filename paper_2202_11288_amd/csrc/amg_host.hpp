@@ -1,0 +1,62 @@
+// Host-side (CPU, FP64) numerics of the library: finest-level generators by
+// product integration, Galerkin coarsening of Toeplitz-plus-Cross levels,
+// coarsest LU, twiddle tables.  Internal header (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace amg {
+
+enum KernelKind { K_CONST = 0, K_WEIGHTED = 1, K_FRACTIONAL = 2, K_GENERATORS = 3 };
+
+struct KernelSpec {
+  int kind = K_CONST;
+  double delta = 0.25;
+  double alpha = 0.0;
+  double wl = 1.0, wr = 1.0;
+  const double* gen = nullptr;
+};
+
+// One level in the Toeplitz-like-plus-Cross form (eq. (split01)):
+// n x n Toeplitz blocks A, B_bar, C_bar, D_bar with T[i][j] = t[j-i+n-1],
+// Cross vectors p, q, xi, zeta (length n) and the scalar o.
+struct TpxLevel {
+  int64_t n = 0;
+  std::vector<double> a, b, c, d;
+  std::vector<double> p, q, xi, zeta;
+  double o = 0.0;
+  // true when A = D_bar symmetric and C_bar = B_bar^T exactly: the packed
+  // spectra are then real / imaginary and stored compactly.
+  bool symmetric() const;
+};
+
+// Validation of the public arguments; returns an empty string when valid.
+std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2);
+
+// Row stencil W[s2 + S], s2 in [-S, S], in half-grid offsets (shifted-symmetric
+// collocation: every row has this stencil).
+std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* S);
+
+// Finest level from the kernel stencil or from caller generators.
+TpxLevel finest_level(const KernelSpec& k, int64_t N);
+
+// Galerkin coarse level R A P (Lemma 3.1), O(n).
+TpxLevel coarsen(const TpxLevel& f);
+
+// Dense (2n+1)^2 matrix of a level, row-major.
+std::vector<double> densify(const TpxLevel& t);
+
+// LU with partial pivoting, in place (row-major m x m); piv[i] = row swapped
+// with i at step i.  Returns false if a zero pivot is met.
+bool lu_factor(std::vector<double>& A, int m, std::vector<int>& piv);
+
+// Manufactured right-hand side f(x_c) for u = x^2 (1-x)^2, block order.
+void manufactured_rhs(const KernelSpec& k, int64_t N, double* b);
+
+// Twiddle e^{-2 pi i m / M} for m = 0..count-1 (interleaved re, im), computed
+// in long double and rounded once.
+std::vector<double> twiddles(int64_t M, int64_t count, int64_t stride = 1);
+
+}  // namespace amg

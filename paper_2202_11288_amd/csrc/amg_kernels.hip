@@ -1,0 +1,802 @@
+// HIP kernels of the block-structured V-cycle (Algorithm 2) with FFT-based
+// Toeplitz-plus-Cross matrix-vector products (Sec. 3.2, eq. (ccs3.4),
+// eq. (split01)) for gfx950.
+//
+// Each level's matvec works on the packed complex signal z = v + i w_bar
+// (zero-padded to L = 2(n+1)); one complex FFT replaces the two real ones,
+// and the 2x2 block product becomes, bin by bin,
+//     Y[f] = G1[f] Z[f] + G2[f] conj(Z[-f]),
+//     G1 = (A^ + D^ + i(C^ - B^))/2,  G2 = (A^ - D^ + i(C^ + B^))/2,
+// with A^..D^ the spectra of the four circulant embeddings.  The inverse FFT
+// of Y gives A v + B_bar w_bar in its real part and C_bar v + D_bar w_bar in
+// its imaginary part.  Large levels run the FFT as a four-step transform in
+// three HBM passes (column FFTs, row FFT + spectral product + inverse row FFT,
+// inverse column FFTs) with the vector formation (smoothing, restriction,
+// prolongation, refinement update) fused into the first pass and the residual
+// / Jacobi epilogue fused into the last.  Small levels run the whole V-cycle
+// below them in one workgroup with the FFT in LDS.
+#include <mutex>
+#include <unordered_map>
+
+#include "amg_device.hpp"
+#include "fft_lds.hpp"
+
+namespace amg {
+
+template <typename T>
+struct Cfg;
+template <>
+struct Cfg<double> {
+  static constexpr int E4 = 16;  // elements per thread, four-step passes (4096 / WG)
+  static constexpr int ET = 8;   // elements per thread, tail kernels (8192 / WG)
+};
+template <>
+struct Cfg<float> {
+  static constexpr int E4 = 32;  // 8192 / WG
+  static constexpr int ET = 16;  // 16384 / WG
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> tw4(const Twiddles<T>& tw, int logL, int64_t e) {
+  // e^{-2 pi i e / L}, e < L <= 2^23, from two table lookups
+  const int64_t idx = e << (kTw4Log - logL);
+  return cmul(tw.hi[idx >> 12], tw.lo[idx & (kTw4Lo - 1)]);
+}
+
+// Deterministic block sum (fixed tree order); every thread gets the result.
+template <typename T, int NT>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const T r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Prolongation 2 R^T at fine index m of a fine vector of length 2*mc + 1
+// (mc = coarse length): odd m = 2i+1 -> e[i]; even m = 2i -> (e[i-1] + e[i])/2.
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* e, int64_t mc, int64_t m) {
+  if (m & 1) return e[m >> 1];
+  const int64_t i = m >> 1;
+  T s = 0;
+  if (i >= 1) s += e[i - 1];
+  if (i < mc) s += e[i];
+  return T(0.5) * s;
+}
+
+// Restriction 1/4 [1 2 1] at coarse index i (Sec. 3.1).
+template <typename T>
+__device__ __forceinline__ T restrict_at(const T* r, int64_t i) {
+  return T(0.25) * (r[2 * i] + T(2) * r[2 * i + 1] + r[2 * i + 2]);
+}
+
+// Circulant first column of the embedding of T[i][j] = t_{j-i} (eq. (ccs3.4)):
+// c_m = t_{-m} (m < n), c_m = t_{L-m} (m > L-n), 0 otherwise.
+__device__ __forceinline__ double circ_col(const double* g, int64_t n, int64_t L, int64_t m) {
+  if (m < n) return g[n - 1 - m];
+  if (m > L - n) return g[n - 1 + (L - m)];
+  return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: forward column FFTs (length L2, stride L1) of a tile of T columns,
+// four-step twiddle, with the level's vector formation fused in front.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(kNT4) void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf,
+                                                  Twiddles<T> tw, T* part) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  __shared__ T red[kNT4];
+  const int64_t n = lv.n;
+  const int64_t L = int64_t(1) << lv.logL;
+  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2, TC = lv.tcols;
+  const int c0 = blockIdx.x * TC;
+  const int cnt = L2 * TC;
+  T dot = 0;
+  for (int idx = threadIdx.x; idx < cnt; idx += kNT4) {
+    const int i = idx / TC, t = idx - i * TC;
+    const int64_t j = (int64_t)(c0 + t) + (int64_t)L1 * i;
+    cplx<T> z = {T(0), T(0)};
+    if constexpr (MODE == COL_SETUP) {
+      z.x = (T)circ_col(in.gx, n, L, j);
+      z.y = (T)circ_col(in.gy, n, L, j);
+    } else if (j < n) {
+      const int64_t jw = n + 1 + j;
+      T v, w;
+      if constexpr (MODE == COL_MV) {
+        v = in.x[j];
+        w = in.x[jw];
+      } else if constexpr (MODE == COL_PRE || MODE == COL_PRE_RESTRICT) {
+        T bv, bw;
+        if constexpr (MODE == COL_PRE_RESTRICT) {
+          bv = restrict_at(in.x, j);
+          bw = restrict_at(in.x, jw);
+          lv.b[j] = bv;
+          lv.b[jw] = bw;
+        } else {
+          bv = lv.b[j];
+          bw = lv.b[jw];
+        }
+        v = in.omega * bv / lv.dv;
+        w = in.omega * bw / lv.dw;
+        lv.u[j] = v;
+        lv.u[jw] = w;
+      } else if constexpr (MODE == COL_PROLONG) {
+        // coarse vector length = n (2 n_c + 1 = n)
+        v = lv.u[j] + prolong_at(in.x, n, j);
+        w = lv.u[jw] + prolong_at(in.x, n, jw);
+        lv.u[j] = v;
+        lv.u[jw] = w;
+      } else {  // COL_OUTER_UPDATE (T = double)
+        const double ev = in.e_is_float ? (double)((const float*)in.e)[j] : ((const double*)in.e)[j];
+        const double ew = in.e_is_float ? (double)((const float*)in.e)[jw] : ((const double*)in.e)[jw];
+        const double xv = in.xo[j] + ev, xw = in.xo[jw] + ew;
+        in.xo[j] = xv;
+        in.xo[jw] = xw;
+        v = (T)xv;
+        w = (T)xw;
+      }
+      z.x = v;
+      z.y = w;
+      dot += lv.q[j] * v + lv.zeta[j] * w;
+    }
+    lds[idx] = z;
+  }
+  if constexpr (MODE != COL_SETUP && MODE != COL_MV) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the w_o entry
+      if constexpr (MODE == COL_PRE) {
+        lv.u[n] = in.omega * lv.b[n] / lv.o;
+      } else if constexpr (MODE == COL_PRE_RESTRICT) {
+        const T bo = restrict_at(in.x, n);
+        lv.b[n] = bo;
+        lv.u[n] = in.omega * bo / lv.o;
+      } else if constexpr (MODE == COL_PROLONG) {
+        lv.u[n] += prolong_at(in.x, n, n);
+      } else if constexpr (MODE == COL_OUTER_UPDATE) {
+        const double e = in.e_is_float ? (double)((const float*)in.e)[n] : ((const double*)in.e)[n];
+        in.xo[n] += e;
+      }
+    }
+  }
+  if constexpr (MODE != COL_SETUP) {
+    const T s = block_sum<T, kNT4>(dot, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  } else {
+    __syncthreads();
+  }
+  lds_fft<T, Cfg<T>::E4, kNT4, false>(lds, L2, TC, 1, TC, true, tw.base, kTwM);
+  for (int idx = threadIdx.x; idx < cnt; idx += kNT4) {
+    const int k2 = idx / TC, t = idx - k2 * TC;
+    const int j1 = c0 + t;
+    buf[(int64_t)j1 + (int64_t)L1 * k2] = cmul(lds[idx], tw4(tw, lv.logL, (int64_t)j1 * k2));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: for the row pair (k2, L2-k2) (or {0, L2/2}): forward row FFTs,
+// spectral 2x2 product (bins f and -f live in the paired rows), inverse row
+// FFTs, inverse four-step twiddle.  Block 0 also finishes the w_o row
+// y_o = q.v + o w_o + zeta.w_bar from pass 1's partial sums.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void spec_pair(const LevelDev<T>& lv, cplx<T>* lds, int la, int lb,
+                                          int64_t ga, int64_t gb) {
+  const cplx<T> za = lds[la], zb = lds[lb];
+  cplx<T> ya, yb;
+  if (lv.sym) {
+    const T g1a = lv.g1[ga], g2a = lv.g2[ga], g1b = lv.g1[gb], g2b = lv.g2[gb];
+    // G1 z + (i g2) conj(z')
+    ya = {g1a * za.x + g2a * zb.y, g1a * za.y + g2a * zb.x};
+    yb = {g1b * zb.x + g2b * za.y, g1b * zb.y + g2b * za.x};
+  } else {
+    const cplx<T>* G1 = reinterpret_cast<const cplx<T>*>(lv.g1);
+    const cplx<T>* G2 = reinterpret_cast<const cplx<T>*>(lv.g2);
+    ya = cmul(G1[ga], za) + cmul(G2[ga], conj(zb));
+    yb = cmul(G1[gb], zb) + cmul(G2[gb], conj(za));
+  }
+  lds[la] = ya;
+  if (la != lb) lds[lb] = yb;
+}
+
+template <typename T, bool SPECTRAL>
+__global__ __launch_bounds__(kNT4) void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw,
+                                              const T* part, int npart, const T* xin) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2;
+  const int item = blockIdx.x;
+  const int ka = item == 0 ? 0 : item;
+  const int kb = item == 0 ? L2 / 2 : L2 - item;
+  for (int t = threadIdx.x; t < L1; t += kNT4) {
+    lds[t] = buf[(int64_t)ka * L1 + t];
+    lds[L1 + t] = buf[(int64_t)kb * L1 + t];
+  }
+  __syncthreads();
+  lds_fft<T, Cfg<T>::E4, kNT4, false>(lds, L1, 2, L1, 1, false, tw.base, kTwM);
+  if constexpr (!SPECTRAL) {
+    for (int t = threadIdx.x; t < L1; t += kNT4) {
+      buf[(int64_t)ka * L1 + t] = lds[t];
+      buf[(int64_t)kb * L1 + t] = lds[L1 + t];
+    }
+    return;
+  } else {
+    const int64_t ra = (int64_t)ka * L1, rb = (int64_t)kb * L1;
+    if (item != 0) {
+      // (ka, k1) pairs with (kb, L1-1-k1)
+      for (int t = threadIdx.x; t < L1; t += kNT4)
+        spec_pair(lv, lds, t, L1 + (L1 - 1 - t), ra + t, rb + (L1 - 1 - t));
+    } else {
+      // row 0: k1 pairs with (L1-k1) mod L1; row L2/2: k1 pairs with L1-1-k1
+      const int npair0 = L1 / 2 + 1;
+      for (int t = threadIdx.x; t < npair0 + L1 / 2; t += kNT4) {
+        if (t < npair0) {
+          const int tb = (L1 - t) & (L1 - 1);
+          spec_pair(lv, lds, t, tb, ra + t, ra + tb);
+        } else {
+          const int k1 = t - npair0;
+          spec_pair(lv, lds, L1 + k1, L1 + (L1 - 1 - k1), rb + k1, rb + (L1 - 1 - k1));
+        }
+      }
+    }
+    __syncthreads();
+    lds_fft<T, Cfg<T>::E4, kNT4, true>(lds, L1, 2, L1, 1, false, tw.base, kTwM);
+    for (int t = threadIdx.x; t < L1; t += kNT4) {
+      buf[ra + t] = cmul(lds[t], conj(tw4(tw, lv.logL, (int64_t)t * ka)));
+      buf[rb + t] = cmul(lds[L1 + t], conj(tw4(tw, lv.logL, (int64_t)t * kb)));
+    }
+    if (item == 0 && threadIdx.x == 0) {
+      T s = 0;
+      for (int i = 0; i < npart; ++i) s += part[i];
+      lv.scal[0] = s + lv.o * xin[lv.n];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: inverse column FFTs; keeps the first n outputs and applies the
+// Cross terms and the residual / Jacobi / output epilogue.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(kNT4) void k_col_inv(LevelDev<T> lv, EpiOut<T> out,
+                                                  const cplx<T>* buf, Twiddles<T> tw,
+                                                  double* part) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  __shared__ double red[kNT4];
+  const int64_t n = lv.n;
+  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2, TC = lv.tcols;
+  const int c0 = blockIdx.x * TC;
+  const int cnt = L2 * TC;
+  for (int idx = threadIdx.x; idx < cnt; idx += kNT4) {
+    const int i = idx / TC, t = idx - i * TC;
+    lds[idx] = buf[(int64_t)(c0 + t) + (int64_t)L1 * i];
+  }
+  __syncthreads();
+  lds_fft<T, Cfg<T>::E4, kNT4, true>(lds, L2, TC, 1, TC, true, tw.base, kTwM);
+  const T wo = out.xin[n];
+  double ss = 0.0;
+  const int half = (L2 / 2) * TC;  // outputs j2 < L2/2 cover j < n
+  for (int idx = threadIdx.x; idx < half; idx += kNT4) {
+    const int i = idx / TC, t = idx - i * TC;
+    const int64_t j = (int64_t)(c0 + t) + (int64_t)L1 * i;
+    if (j >= n) continue;
+    const int64_t jw = n + 1 + j;
+    const cplx<T> y = lds[idx];
+    const T yv = y.x + lv.p[j] * wo;
+    const T yw = y.y + lv.xi[j] * wo;
+    if constexpr (MODE == EPI_MV) {
+      out.y[j] = yv;
+      out.y[jw] = yw;
+    } else if constexpr (MODE == EPI_RESID) {
+      lv.r[j] = lv.b[j] - yv;
+      lv.r[jw] = lv.b[jw] - yw;
+    } else if constexpr (MODE == EPI_SMOOTH) {
+      lv.u[j] += out.omega * (lv.b[j] - yv) / lv.dv;
+      lv.u[jw] += out.omega * (lv.b[jw] - yw) / lv.dw;
+    } else {  // EPI_OUTER
+      const double rv = out.bo[j] - (double)yv, rw = out.bo[jw] - (double)yw;
+      out.ro[j] = rv;
+      out.ro[jw] = rw;
+      if (out.r32) {
+        out.r32[j] = (float)rv;
+        out.r32[jw] = (float)rw;
+      }
+      ss += rv * rv + rw * rw;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const T yo = lv.scal[0];
+    if constexpr (MODE == EPI_MV) {
+      out.y[n] = yo;
+    } else if constexpr (MODE == EPI_RESID) {
+      lv.r[n] = lv.b[n] - yo;
+    } else if constexpr (MODE == EPI_SMOOTH) {
+      lv.u[n] += out.omega * (lv.b[n] - yo) / lv.o;
+    } else {
+      const double ro = out.bo[n] - (double)yo;
+      out.ro[n] = ro;
+      if (out.r32) out.r32[n] = (float)ro;
+      ss += ro * ro;
+    }
+  }
+  if constexpr (MODE == EPI_OUTER) {
+    const double s = block_sum<double, kNT4>(ss, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tail levels: the whole FFT of length L <= E*1024 in one workgroup's LDS.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ T tail_matvec_core(const LevelDev<T>& lv, const T* x, cplx<T>* z, T* red,
+                              const Twiddles<T>& tw) {
+  // leaves y_v + i y_w_bar (without the Cross terms) in z[0..n) and returns
+  // y_o = q.v + o w_o + zeta.w_bar
+  const int n = lv.n, L = 1 << lv.logL;
+  T dot = 0;
+  for (int j = threadIdx.x; j < L; j += kNTT) {
+    cplx<T> v = {T(0), T(0)};
+    if (j < n) {
+      v.x = x[j];
+      v.y = x[n + 1 + j];
+      dot += lv.q[j] * v.x + lv.zeta[j] * v.y;
+    }
+    z[j] = v;
+  }
+  const T s = block_sum<T, kNTT>(dot, red);
+  lds_fft<T, Cfg<T>::ET, kNTT, false>(z, L, 1, 0, 1, false, tw.base, kTwM);
+  for (int f = threadIdx.x; f <= L / 2; f += kNTT) {
+    const int fb = (L - f) & (L - 1);
+    spec_pair(lv, z, f, fb, f, fb);
+  }
+  __syncthreads();
+  lds_fft<T, Cfg<T>::ET, kNTT, true>(z, L, 1, 0, 1, false, tw.base, kTwM);
+  return s + lv.o * x[n];
+}
+
+template <typename T>
+__device__ void coarse_lu_solve(const CoarseLU& lu, const T* b, T* u) {
+  // wave 0 only; lane l holds x[l + 64 s], s < 4 (m <= 256)
+  const int lane = threadIdx.x;
+  const int m = lu.m;
+  double x[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int i = lane + 64 * s;
+    x[s] = (i < m) ? (double)b[lu.perm[i]] : 0.0;
+  }
+  for (int k = 0; k < m - 1; ++k) {  // L y = P b (unit lower)
+    const int sk = k >> 6;
+    double xs = x[0];
+#pragma unroll
+    for (int s = 1; s < 4; ++s)
+      if (sk == s) xs = x[s];
+    const double xk = __shfl(xs, k & 63, 64);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = lane + 64 * s;
+      if (i > k && i < m) x[s] -= lu.lcm[(int64_t)k * m + i] * xk;
+    }
+  }
+  for (int k = m - 1; k >= 0; --k) {  // U x = y
+    const int sk = k >> 6;
+    double xs = x[0];
+#pragma unroll
+    for (int s = 1; s < 4; ++s)
+      if (sk == s) xs = x[s];
+    const double xk = __shfl(xs, k & 63, 64) * lu.dinv[k];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = lane + 64 * s;
+      if (i == k) x[s] = xk;
+      else if (i < k) x[s] -= lu.ucm[(int64_t)k * m + i] * xk;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int i = lane + 64 * s;
+    if (i < m) u[i] = (T)x[s];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels, int first,
+                                                      int last, const T* rf, int m1, int m2,
+                                                      T wpre, T wpost, CoarseLU lu,
+                                                      Twiddles<T> tw, int maxL) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* z = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* red = reinterpret_cast<T*>(z + maxL);
+  // ---- descend: pre-smooth, residual, restrict
+  for (int l = first; l <= last; ++l) {
+    const LevelDev<T> lv = levels[l];
+    const int n = lv.n, m = 2 * n + 1;
+    const T* src = (l == first) ? rf : levels[l - 1].r;
+    if (src) {
+      for (int i = threadIdx.x; i < m; i += kNTT) lv.b[i] = restrict_at(src, i);
+    }
+    __syncthreads();
+    if (l == last) {
+      if (threadIdx.x < 64) coarse_lu_solve<T>(lu, lv.b, lv.u);
+      __syncthreads();
+      break;
+    }
+    for (int i = threadIdx.x; i < m; i += kNTT) {
+      const T d = (i < n) ? lv.dv : (i == n ? lv.o : lv.dw);
+      lv.u[i] = wpre * lv.b[i] / d;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < m1; ++sweep) {
+      const T yo = tail_matvec_core(lv, lv.u, z, red, tw);
+      const T wo = lv.u[n];
+      const bool last_sweep = sweep == m1 - 1;
+      __syncthreads();  // every thread has read u[n] before it changes
+      for (int j = threadIdx.x; j < n; j += kNTT) {
+        const T yv = z[j].x + lv.p[j] * wo, yw = z[j].y + lv.xi[j] * wo;
+        if (last_sweep) {
+          lv.r[j] = lv.b[j] - yv;
+          lv.r[n + 1 + j] = lv.b[n + 1 + j] - yw;
+        } else {
+          lv.u[j] += wpre * (lv.b[j] - yv) / lv.dv;
+          lv.u[n + 1 + j] += wpre * (lv.b[n + 1 + j] - yw) / lv.dw;
+        }
+      }
+      if (threadIdx.x == 0) {
+        if (last_sweep) lv.r[n] = lv.b[n] - yo;
+        else lv.u[n] += wpre * (lv.b[n] - yo) / lv.o;
+      }
+      __syncthreads();
+    }
+  }
+  // ---- ascend: prolongate, post-smooth
+  for (int l = last - 1; l >= first; --l) {
+    const LevelDev<T> lv = levels[l];
+    const int n = lv.n, m = 2 * n + 1;
+    const T* ec = levels[l + 1].u;
+    for (int i = threadIdx.x; i < m; i += kNTT) lv.u[i] += prolong_at(ec, n, i);
+    __syncthreads();
+    for (int sweep = 0; sweep < m2; ++sweep) {
+      const T yo = tail_matvec_core(lv, lv.u, z, red, tw);
+      const T wo = lv.u[n];
+      __syncthreads();
+      for (int j = threadIdx.x; j < n; j += kNTT) {
+        const T yv = z[j].x + lv.p[j] * wo, yw = z[j].y + lv.xi[j] * wo;
+        lv.u[j] += wpost * (lv.b[j] - yv) / lv.dv;
+        lv.u[n + 1 + j] += wpost * (lv.b[n + 1 + j] - yw) / lv.dw;
+      }
+      if (threadIdx.x == 0) lv.u[n] += wpost * (lv.b[n] - yo) / lv.o;
+      __syncthreads();
+    }
+  }
+}
+
+// One tail-level matvec: y = A x (EPI_MV) or the outer residual with the
+// refinement update fused in front (COL_OUTER_UPDATE + EPI_OUTER).
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> in, EpiOut<T> out,
+                                                      Twiddles<T> tw, double* part) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n = lv.n, L = 1 << lv.logL;
+  cplx<T>* z = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* red = reinterpret_cast<T*>(z + L);
+  __shared__ double redd[kNTT];
+  const T* x = out.xin;
+  if constexpr (CM == COL_OUTER_UPDATE) {
+    for (int i = threadIdx.x; i < 2 * n + 1; i += kNTT) {
+      const double e = in.e_is_float ? (double)((const float*)in.e)[i] : ((const double*)in.e)[i];
+      in.xo[i] += e;
+    }
+    __syncthreads();
+  }
+  const T yo = tail_matvec_core(lv, x, z, red, tw);
+  const T wo = x[n];
+  double ss = 0.0;
+  for (int j = threadIdx.x; j < n; j += kNTT) {
+    const T yv = z[j].x + lv.p[j] * wo, yw = z[j].y + lv.xi[j] * wo;
+    if constexpr (EM == EPI_MV) {
+      out.y[j] = yv;
+      out.y[n + 1 + j] = yw;
+    } else {
+      const double rv = out.bo[j] - (double)yv, rw = out.bo[n + 1 + j] - (double)yw;
+      out.ro[j] = rv;
+      out.ro[n + 1 + j] = rw;
+      if (out.r32) {
+        out.r32[j] = (float)rv;
+        out.r32[n + 1 + j] = (float)rw;
+      }
+      ss += rv * rv + rw * rw;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if constexpr (EM == EPI_MV) {
+      out.y[n] = yo;
+    } else {
+      const double ro = out.bo[n] - (double)yo;
+      out.ro[n] = ro;
+      if (out.r32) out.r32[n] = (float)ro;
+      ss += ro * ro;
+    }
+  }
+  if constexpr (EM == EPI_OUTER) {
+    const double s = block_sum<double, kNTT>(ss, redd);
+    if (threadIdx.x == 0) part[0] = s;
+  }
+}
+
+// Setup: FFT (natural order) of c_x + i c_y for a tail level.
+__global__ __launch_bounds__(kNTT) void k_tail_fft_setup(LevelDev<double> lv, const double* gx,
+                                                         const double* gy, cplx<double>* out,
+                                                         Twiddles<double> tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<double>* z = reinterpret_cast<cplx<double>*>(smem_raw);
+  const int64_t n = lv.n, L = int64_t(1) << lv.logL;
+  for (int j = threadIdx.x; j < L; j += kNTT) z[j] = {circ_col(gx, n, L, j), circ_col(gy, n, L, j)};
+  __syncthreads();
+  lds_fft<double, Cfg<double>::ET, kNTT, false>(z, (int)L, 1, 0, 1, false, tw.base, kTwM);
+  for (int j = threadIdx.x; j < L; j += kNTT) out[j] = z[j];
+}
+
+// Setup: spectra of the four blocks from two packed transforms
+// Z1 = F(c_A + i c_B), Z2 = F(c_C + i c_D); A^ = (Z1 + conj Z1(-f))/2,
+// B^ = (Z1 - conj Z1(-f))/(2i), etc.; G1, G2 as above, divided by L.
+__global__ void k_combine(int logL, int logL1, int logL2, const cplx<double>* z1,
+                          const cplx<double>* z2, int sym, double* g1, double* g2, float* g1f,
+                          float* g2f) {
+  const int64_t L = int64_t(1) << logL;
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= L) return;
+  int64_t pp;
+  if (logL2 == 0) {
+    pp = (L - pos) & (L - 1);
+  } else {
+    const int64_t L1 = int64_t(1) << logL1, L2 = int64_t(1) << logL2;
+    const int64_t k2 = pos >> logL1, k1 = pos & (L1 - 1);
+    const int64_t f = k2 + L2 * k1;
+    const int64_t fn = (L - f) & (L - 1);
+    pp = (fn & (L2 - 1)) * L1 + (fn >> logL2);
+  }
+  const cplx<double> a1 = z1[pos], b1 = conj(z1[pp]), a2 = z2[pos], b2 = conj(z2[pp]);
+  const cplx<double> Ah = scale(a1 + b1, 0.5), Ch = scale(a2 + b2, 0.5);
+  const cplx<double> Bh = scale(rot<double, false>(a1 - b1), 0.5);  // (z - conj)/(2i) = -i(z - conj)/2
+  const cplx<double> Dh = scale(rot<double, false>(a2 - b2), 0.5);
+  const double s = 0.5 / (double)L;
+  const cplx<double> G1 = scale((Ah + Dh) + rot<double, true>(Ch - Bh), s);
+  const cplx<double> G2 = scale((Ah - Dh) + rot<double, true>(Ch + Bh), s);
+  if (sym) {
+    g1[pos] = G1.x;
+    g2[pos] = G2.y;
+    if (g1f) {
+      g1f[pos] = (float)G1.x;
+      g2f[pos] = (float)G2.y;
+    }
+  } else {
+    g1[2 * pos] = G1.x;
+    g1[2 * pos + 1] = G1.y;
+    g2[2 * pos] = G2.x;
+    g2[2 * pos + 1] = G2.y;
+    if (g1f) {
+      g1f[2 * pos] = (float)G1.x;
+      g1f[2 * pos + 1] = (float)G1.y;
+      g2f[2 * pos] = (float)G2.x;
+      g2f[2 * pos + 1] = (float)G2.y;
+    }
+  }
+}
+
+// Stopping test of the outer iteration (Sec. 5): ||r_i|| / ||r_0|| < tol.
+__global__ void k_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
+                         double* hist) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (st->done) return;
+  double s = 0.0;
+  for (int i = 0; i < npart; ++i) s += part[i];
+  const double nrm = sqrt(s);
+  if (st->iter == 0) {
+    st->r0 = nrm;
+    st->best = 1.0;
+  }
+  const double rel = (st->r0 > 0.0) ? nrm / st->r0 : 0.0;
+  st->relres = rel;
+  hist[st->iter] = rel;
+  if (!(rel == rel) || isinf(rel)) {
+    st->status = 2;
+    st->done = 1;
+  } else if (rel < tol) {
+    st->status = 0;
+    st->done = 1;
+  } else if (rel > 1e3 * st->best) {
+    st->status = 2;
+    st->done = 1;
+  } else if (st->iter >= max_iter) {
+    st->status = 1;
+    st->done = 1;
+  }
+  if (rel < st->best) st->best = rel;
+  if (!st->done) st->iter += 1;
+}
+
+__global__ void k_copy_d2f(const double* a, float* b, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) b[i] = (float)a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+namespace {
+// Raise a kernel's dynamic-LDS limit once to the largest size it is launched
+// with (gfx950 has 160 KB of LDS per workgroup).
+template <typename K>
+hipError_t set_lds(K kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> done;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = done.find(key);
+  if (it != done.end() && it->second >= bytes) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done[key] = bytes;
+  return e;
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_col_fwd(int mode, const LevelDev<T>& lv, const ColIn<T>& in, cplx<T>* buf,
+                          const Twiddles<T>& tw, T* part, hipStream_t s) {
+  const int grid = col_blocks(lv.logL1, lv.tcols);
+  const size_t lds = sizeof(cplx<T>) * (size_t)lv.tcols << lv.logL2;
+  hipError_t e = hipSuccess;
+  switch (mode) {
+    case COL_MV: e = set_lds(k_col_fwd<T, COL_MV>, lds); break;
+    case COL_PRE: e = set_lds(k_col_fwd<T, COL_PRE>, lds); break;
+    case COL_PRE_RESTRICT: e = set_lds(k_col_fwd<T, COL_PRE_RESTRICT>, lds); break;
+    case COL_PROLONG: e = set_lds(k_col_fwd<T, COL_PROLONG>, lds); break;
+    case COL_OUTER_UPDATE: e = set_lds(k_col_fwd<T, COL_OUTER_UPDATE>, lds); break;
+    case COL_SETUP: e = set_lds(k_col_fwd<T, COL_SETUP>, lds); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  switch (mode) {
+    case COL_MV: hipLaunchKernelGGL((k_col_fwd<T, COL_MV>), grid, kNT4, lds, s, lv, in, buf, tw, part); break;
+    case COL_PRE: hipLaunchKernelGGL((k_col_fwd<T, COL_PRE>), grid, kNT4, lds, s, lv, in, buf, tw, part); break;
+    case COL_PRE_RESTRICT: hipLaunchKernelGGL((k_col_fwd<T, COL_PRE_RESTRICT>), grid, kNT4, lds, s, lv, in, buf, tw, part); break;
+    case COL_PROLONG: hipLaunchKernelGGL((k_col_fwd<T, COL_PROLONG>), grid, kNT4, lds, s, lv, in, buf, tw, part); break;
+    case COL_OUTER_UPDATE: hipLaunchKernelGGL((k_col_fwd<T, COL_OUTER_UPDATE>), grid, kNT4, lds, s, lv, in, buf, tw, part); break;
+    case COL_SETUP: hipLaunchKernelGGL((k_col_fwd<T, COL_SETUP>), grid, kNT4, lds, s, lv, in, buf, tw, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_row(int spectral, const LevelDev<T>& lv, cplx<T>* buf, const Twiddles<T>& tw,
+                      const T* part, int npart, const T* xin, hipStream_t s) {
+  const int grid = (1 << lv.logL2) / 2;
+  const size_t lds = sizeof(cplx<T>) * 2 << lv.logL1;
+  hipError_t e = spectral ? set_lds(k_row<T, true>, lds) : set_lds(k_row<T, false>, lds);
+  if (e != hipSuccess) return e;
+  if (spectral)
+    hipLaunchKernelGGL((k_row<T, true>), grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+  else
+    hipLaunchKernelGGL((k_row<T, false>), grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_col_inv(int mode, const LevelDev<T>& lv, const EpiOut<T>& out,
+                          const cplx<T>* buf, const Twiddles<T>& tw, double* part, hipStream_t s) {
+  const int grid = col_blocks(lv.logL1, lv.tcols);
+  const size_t lds = sizeof(cplx<T>) * (size_t)lv.tcols << lv.logL2;
+  hipError_t e = hipSuccess;
+  switch (mode) {
+    case EPI_MV: e = set_lds(k_col_inv<T, EPI_MV>, lds); break;
+    case EPI_RESID: e = set_lds(k_col_inv<T, EPI_RESID>, lds); break;
+    case EPI_SMOOTH: e = set_lds(k_col_inv<T, EPI_SMOOTH>, lds); break;
+    case EPI_OUTER: e = set_lds(k_col_inv<T, EPI_OUTER>, lds); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  switch (mode) {
+    case EPI_MV: hipLaunchKernelGGL((k_col_inv<T, EPI_MV>), grid, kNT4, lds, s, lv, out, buf, tw, part); break;
+    case EPI_RESID: hipLaunchKernelGGL((k_col_inv<T, EPI_RESID>), grid, kNT4, lds, s, lv, out, buf, tw, part); break;
+    case EPI_SMOOTH: hipLaunchKernelGGL((k_col_inv<T, EPI_SMOOTH>), grid, kNT4, lds, s, lv, out, buf, tw, part); break;
+    case EPI_OUTER: hipLaunchKernelGGL((k_col_inv<T, EPI_OUTER>), grid, kNT4, lds, s, lv, out, buf, tw, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tail_matvec(int colmode, int epimode, const LevelDev<T>& lv, const ColIn<T>& in,
+                              const EpiOut<T>& out, const Twiddles<T>& tw, double* part,
+                              hipStream_t s) {
+  const size_t L = size_t(1) << lv.logL;
+  const size_t lds = sizeof(cplx<T>) * L + sizeof(T) * kNTT;
+  hipError_t e;
+  if (colmode == COL_MV && epimode == EPI_MV) {
+    auto k = k_tail_matvec<T, COL_MV, EPI_MV>;
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, 1, kNTT, lds, s, lv, in, out, tw, part);
+  } else if (colmode == COL_MV && epimode == EPI_OUTER) {
+    auto k = k_tail_matvec<T, COL_MV, EPI_OUTER>;
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, 1, kNTT, lds, s, lv, in, out, tw, part);
+  } else if (colmode == COL_OUTER_UPDATE && epimode == EPI_OUTER) {
+    auto k = k_tail_matvec<T, COL_OUTER_UPDATE, EPI_OUTER>;
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, 1, kNTT, lds, s, lv, in, out, tw, part);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
+                              int m1, int m2, T wpre, T wpost, const CoarseLU& lu,
+                              const Twiddles<T>& tw, int maxL, hipStream_t s) {
+  const size_t lds = sizeof(cplx<T>) * (size_t)maxL + sizeof(T) * kNTT;
+  auto k = k_tail_vcycle<T>;
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, 1, kNTT, lds, s, levels_dev, first, last, rf, m1, m2, wpre, wpost, lu, tw,
+                     maxL);
+  return hipGetLastError();
+}
+
+hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, const double* gy,
+                                 cplx<double>* out, const Twiddles<double>& tw, hipStream_t s) {
+  const size_t lds = sizeof(cplx<double>) << lv.logL;
+  hipError_t e = set_lds(k_tail_fft_setup, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tail_fft_setup, 1, kNTT, lds, s, lv, gx, gy, out, tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1,
+                          const cplx<double>* z2, int sym, double* g1, double* g2, float* g1f,
+                          float* g2f, hipStream_t s) {
+  const int64_t L = int64_t(1) << logL;
+  const int grid = (int)((L + 255) / 256);
+  hipLaunchKernelGGL(k_combine, grid, 256, 0, s, logL, logL1, logL2, z1, z2, sym, g1, g2, g1f, g2f);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
+                         double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, 1, 64, 0, s, st, part, npart, tol, max_iter, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s) {
+  const int grid = (int)((m + 255) / 256);
+  hipLaunchKernelGGL(k_copy_d2f, grid, 256, 0, s, a, b, m);
+  return hipGetLastError();
+}
+
+#define AMG_INSTANTIATE(T)                                                                      \
+  template hipError_t launch_col_fwd<T>(int, const LevelDev<T>&, const ColIn<T>&, cplx<T>*,    \
+                                        const Twiddles<T>&, T*, hipStream_t);                  \
+  template hipError_t launch_row<T>(int, const LevelDev<T>&, cplx<T>*, const Twiddles<T>&,     \
+                                    const T*, int, const T*, hipStream_t);                     \
+  template hipError_t launch_col_inv<T>(int, const LevelDev<T>&, const EpiOut<T>&,             \
+                                        const cplx<T>*, const Twiddles<T>&, double*,           \
+                                        hipStream_t);                                          \
+  template hipError_t launch_tail_matvec<T>(int, int, const LevelDev<T>&, const ColIn<T>&,     \
+                                            const EpiOut<T>&, const Twiddles<T>&, double*,     \
+                                            hipStream_t);                                      \
+  template hipError_t launch_tail_vcycle<T>(const LevelDev<T>*, int, int, const T*, int, int,  \
+                                            T, T, const CoarseLU&, const Twiddles<T>&, int,    \
+                                            hipStream_t);
+AMG_INSTANTIATE(double)
+AMG_INSTANTIATE(float)
+
+}  // namespace amg

@@ -1,0 +1,144 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/amg.h declares, validates arguments, and its host-side setup
+(product-integration generators, Lemma 3.1 levels, manufactured RHS) agrees
+with the oracle (no device compute is called here)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import discretize as D
+from oracle import tpx
+from paper_2202_11288_amd import binding as B
+
+KERNELS = [
+    (B.kernel(B.AMG_K_CONST), D.Kernel(D.CONST, 0.25), 0.25),
+    (B.kernel(B.AMG_K_CONST), D.Kernel(D.CONST, 0.05), 0.05),
+    (B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8), D.Kernel(D.WEIGHTED, 0.05, wl=1.2, wr=0.8), 0.05),
+    (B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4), D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), 0.1),
+    (B.kernel(B.AMG_K_FRACTIONAL, alpha=0.2), D.Kernel(D.FRACTIONAL, 0.013, alpha=0.2), 0.013),
+]
+IDS = ["const-0.25", "const-0.05", "weighted-0.05", "frac-0.4", "frac-0.2-small-delta"]
+
+
+def test_exports_every_declared_symbol():
+    names = B.declared_symbols()
+    assert len(names) >= 14
+    missing = [s for s in names if not hasattr(B.lib, s)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("kp", KERNELS, ids=IDS)
+@pytest.mark.parametrize("N", [64, 512, 4096])
+def test_manufactured_rhs_matches_oracle(kp, N):
+    kern, okern, delta = kp
+    b = B.amg_manufactured_rhs(kern, delta, N)
+    ref = D.rhs_manufactured(okern, N)
+    # both evaluate f = c * (u(x) delta - (U(x+delta) - U(x))) (or its fractional
+    # analogue) in closed form; the difference cancels terms of size
+    # c * (delta + int u) with rounding ~eps each, so that is the scale
+    scale = okern.c * (delta ** (okern.beta + 1) if okern.kind == D.FRACTIONAL else delta + 1 / 30)
+    assert np.abs(b - ref).max() <= 64 * np.finfo(float).eps * scale
+
+
+def _compare_levels(h, T_levels):
+    assert B.amg_num_levels(h) == len(T_levels)
+    for l, To in enumerate(T_levels):
+        T = B.amg_level_tpx(h, l)
+        assert T["n"] == To.n
+        scale = np.abs(To.a).max()
+        for key in ("a", "b", "c", "d", "p", "q", "xi", "zeta"):
+            np.testing.assert_allclose(T[key], getattr(To, key), rtol=0, atol=1e-14 * scale,
+                                       err_msg=f"level {l} {key}")
+        assert abs(T["o"] - To.o) <= 1e-14 * scale
+
+
+def _oracle_levels(T0, coarsest_log2):
+    Ts = [T0]
+    while Ts[-1].n > 2 ** coarsest_log2 - 1:
+        Ts.append(tpx.coarsen(Ts[-1]))
+    return Ts
+
+
+@pytest.mark.parametrize("kp", KERNELS, ids=IDS)
+@pytest.mark.parametrize("N,cl", [(64, 5), (1024, 5), (2048, 6), (128, 6)])
+def test_host_setup_matches_oracle(kp, N, cl):
+    """C++ generators (Gauss-Legendre / closed form) and C++ Galerkin
+    recurrences equal the oracle's (binomial series / Lemma 3.1 as printed)."""
+    kern, okern, delta = kp
+    h = B.amg_setup(kern, delta, N, B.amg_default_opts(flags=B.AMG_FLAG_HOST_ONLY, coarsest_log2=cl))
+    try:
+        _compare_levels(h, _oracle_levels(tpx.from_stencil(okern, N), cl))
+    finally:
+        B.amg_destroy(h)
+
+
+def test_host_setup_generators_kind():
+    N = 256
+    gA, gB, gC, gD = synthetic.random_tpx_arrays(N - 1, seed=11)
+    gen = np.ascontiguousarray(np.concatenate([gA, gB, gC, gD]))
+    assert gen.size == 8 * N - 8
+    h = B.amg_setup(B.kernel(B.AMG_K_GENERATORS, gen=gen), 0.0, N,
+                    B.amg_default_opts(flags=B.AMG_FLAG_HOST_ONLY))
+    try:
+        _compare_levels(h, _oracle_levels(tpx.from_blocks(gA, gB, gC, gD, N), 5))
+    finally:
+        B.amg_destroy(h)
+
+
+def _setup_status(kern, delta, N, **opts):
+    flags = B.AMG_FLAG_HOST_ONLY | opts.pop("flags", 0)
+    o = B.amg_default_opts(flags=flags, **opts)
+    h = ctypes.c_void_p()
+    st = B.lib.amg_setup(ctypes.byref(kern), float(delta), int(N), ctypes.byref(o), None,
+                         ctypes.byref(h))
+    if st == B.AMG_OK:
+        B.lib.amg_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("case", [
+    dict(N=100), dict(N=0), dict(N=-64), dict(N=32), dict(N=16), dict(N=2 ** 23),
+    dict(delta=0.0), dict(delta=-0.1), dict(delta=0.5), dict(delta=float("nan")),
+    dict(kind=B.AMG_K_FRACTIONAL, alpha=0.5), dict(kind=B.AMG_K_FRACTIONAL, alpha=0.0),
+    dict(kind=B.AMG_K_WEIGHTED, wl=-1.0), dict(kind=7), dict(kind=B.AMG_K_GENERATORS),
+    dict(opts=dict(coarsest_log2=1)), dict(opts=dict(coarsest_log2=8)),
+    dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=8)),
+])
+def test_invalid_arguments_rejected(case):
+    kind = case.get("kind", B.AMG_K_CONST)
+    kern = B.kernel(kind, alpha=case.get("alpha", 0.3), wl=case.get("wl", 1.0), wr=1.0)
+    st = _setup_status(kern, case.get("delta", 0.1), case.get("N", 256), **case.get("opts", {}))
+    assert st == B.AMG_EINVAL
+
+
+def test_unsupported_sweep_counts():
+    assert _setup_status(B.kernel(B.AMG_K_CONST), 0.1, 256, m1=0) == B.AMG_ENOTSUP
+
+
+def test_null_pointers_and_host_only_handle():
+    assert B.lib.amg_setup(None, 0.1, 256, None, None, None) == B.AMG_EINVAL
+    h = B.amg_setup(B.kernel(B.AMG_K_CONST), 0.1, 256, B.amg_default_opts(flags=B.AMG_FLAG_HOST_ONLY))
+    try:
+        # device entry points refuse a host-only handle without touching a GPU
+        assert B.lib.amg_matvec(h, ctypes.c_void_p(8), ctypes.c_void_p(16), None) == B.AMG_EINVAL
+        assert B.lib.amg_vcycle(h, ctypes.c_void_p(8), ctypes.c_void_p(16), None) == B.AMG_EINVAL
+        assert B.lib.amg_level_matvec(h, 99, ctypes.c_void_p(8), ctypes.c_void_p(16), None) == B.AMG_EINVAL
+        assert B.amg_level_size(h, 0) == 511 and B.amg_level_size(h, 3) == 63
+        assert B.amg_level_size(h, 4) == B.AMG_EINVAL
+    finally:
+        B.amg_destroy(h)
+    assert B.lib.amg_destroy(None) == B.AMG_OK
+    assert B.lib.amg_manufactured_rhs(None, 0.1, 64, None) == B.AMG_EINVAL
+
+
+def test_footprint_and_strerror():
+    k = B.kernel(B.AMG_K_CONST)
+    f = [B.amg_footprint_bytes(k, 0.1, 2 ** K) for K in (10, 14, 20)]
+    assert all(x > 0 for x in f) and f[0] < f[1] < f[2]
+    assert B.amg_footprint_bytes(k, 0.1, 1000) == B.AMG_EINVAL
+    fm = B.amg_footprint_bytes(k, 0.1, 2 ** 20, B.amg_default_opts(precision=B.AMG_MIXED))
+    assert fm > f[2]
+    for st in (0, 1, 2, -1, -2, -3, -4):
+        assert B.strerror(st) and B.strerror(st) != "unknown status"

@@ -1,0 +1,329 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Every test prints the case it runs (flushed) before touching the GPU."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import dense
+from oracle import discretize as D
+from oracle import tpx
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only machines
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_2202_11288_amd import binding as B  # noqa: E402
+
+CONST25 = ("const-0.25", B.kernel(B.AMG_K_CONST), D.Kernel(D.CONST, 0.25), 0.25)
+CONST05 = ("const-0.05", B.kernel(B.AMG_K_CONST), D.Kernel(D.CONST, 0.05), 0.05)
+WEIGHT05 = ("weighted-0.05", B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8),
+            D.Kernel(D.WEIGHTED, 0.05, wl=1.2, wr=0.8), 0.05)
+FRAC04 = ("frac-0.4", B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4),
+          D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), 0.1)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+_oracle_cache = {}
+
+
+def oracle_hier(case, N, coarsest=5):
+    key = (case[0], N, coarsest)
+    if key not in _oracle_cache:
+        _oracle_cache.clear()
+        _oracle_cache[key] = tpx.Hierarchy.build(tpx.from_stencil(case[2], N), coarsest)
+    return _oracle_cache[key]
+
+
+def kappa_tol(H):
+    """Tolerance for comparing V-cycle outputs and solutions computed from two
+    equally valid hierarchies: their coarsest matrices (C++ recurrences vs the
+    oracle's Lemma 3.1) differ by rounding, and the exact coarsest solve
+    amplifies that by the condition number of the coarsest matrix, which for
+    the Galerkin levels tracks that of the finest one.  64 eps kappa."""
+    return 64 * np.finfo(float).eps * np.linalg.cond(H.levels[-1].dense())
+
+
+def oracle_level_matvec(H, l, x):
+    if l < len(H.levels) - 1:
+        return H.levels[l].matvec(x)
+    return H.levels[-1].dense() @ x
+
+
+@pytest.mark.parametrize("case,N", [
+    (CONST25, 64), (CONST25, 1024), (CONST25, 8192), (CONST25, 16384), (CONST25, 65536),
+    (CONST05, 32768), (WEIGHT05, 256), (WEIGHT05, 16384), (FRAC04, 1024), (FRAC04, 32768),
+])
+def test_level_matvec_every_level(case, N):
+    """y = A_l x on every level (tail levels: one-workgroup FFT in LDS;
+    larger ones: three-pass four-step FFT) against the oracle's FFT matvec
+    (itself pinned to dense products).  FFT rounding ~ eps log2 L."""
+    say("level_matvec", case[0], N)
+    h = B.amg_setup(case[1], case[3], N)
+    try:
+        H = oracle_hier(case, N)
+        for l in range(B.amg_num_levels(h)):
+            m = B.amg_level_size(h, l)
+            x = synthetic.random_vector(m, seed=1000 + l)
+            y = torch.empty(m, device="cuda", dtype=torch.float64)
+            B.amg_level_matvec(h, l, dev(x), y)
+            yr = oracle_level_matvec(H, l, x)
+            err = np.abs(host(y) - yr).max() / np.abs(yr).max()
+            assert err < 1e-13, (l, m, err)
+    finally:
+        B.amg_destroy(h)
+
+
+@pytest.mark.parametrize("N", [512, 16384])
+def test_matvec_general_blocks(N):
+    """Caller-supplied non-symmetric blocks (AMG_K_GENERATORS): the general
+    two-complex-spectra path against dense (small N) / oracle FFT (large N)."""
+    say("general_blocks", N)
+    gA, gB, gC, gD = synthetic.random_tpx_arrays(N - 1, seed=N, decay=0.001)
+    gen = np.ascontiguousarray(np.concatenate([gA, gB, gC, gD]))
+    h = B.amg_setup(B.kernel(B.AMG_K_GENERATORS, gen=gen), 0.0, N)
+    try:
+        T0 = tpx.from_blocks(gA, gB, gC, gD, N)
+        x = synthetic.random_vector(2 * N - 1, seed=5)
+        y = torch.empty(2 * N - 1, device="cuda", dtype=torch.float64)
+        B.amg_matvec(h, dev(x), y)
+        yr = (D.assemble_dense_from_blocks(gA, gB, gC, gD, N) @ x if N <= 1024
+              else tpx.Level.build(T0).matvec(x))
+        err = np.abs(host(y) - yr).max() / np.abs(yr).max()
+        assert err < 1e-13, err
+        # coarse levels of the general path
+        Ts = [T0]
+        for l in range(1, B.amg_num_levels(h)):
+            Ts.append(tpx.coarsen(Ts[-1]))
+            m = B.amg_level_size(h, l)
+            x = synthetic.random_vector(m, seed=l)
+            y = torch.empty(m, device="cuda", dtype=torch.float64)
+            B.amg_level_matvec(h, l, dev(x), y)
+            yr = Ts[-1].dense() @ x if m < 2000 else tpx.Level.build(Ts[-1]).matvec(x)
+            err = np.abs(host(y) - yr).max() / np.abs(yr).max()
+            assert err < 1e-13, (l, err)
+    finally:
+        B.amg_destroy(h)
+
+
+@pytest.mark.parametrize("case,N", [(CONST25, 1024), (CONST25, 16384), (WEIGHT05, 32768),
+                                    (FRAC04, 16384), (CONST05, 128)])
+def test_vcycle_matches_oracle(case, N):
+    """One V-cycle (Algorithm 2) from zero: same algorithm, so outputs agree
+    to rounding amplified by the conditioning (see kappa_tol)."""
+    say("vcycle", case[0], N)
+    h = B.amg_setup(case[1], case[3], N)
+    try:
+        H = oracle_hier(case, N)
+        r = synthetic.random_vector(2 * N - 1, seed=N + 7)
+        e = torch.empty(2 * N - 1, device="cuda", dtype=torch.float64)
+        B.amg_vcycle(h, dev(r), e)
+        er = tpx.vcycle(H, r)
+        err = np.abs(host(e) - er).max() / np.abs(er).max()
+        tol = max(1e-13, kappa_tol(H))
+        say("vcycle err", err, "tol", tol)
+        assert err < tol, (err, tol)
+    finally:
+        B.amg_destroy(h)
+
+
+@pytest.mark.parametrize("case,N,coarsest", [
+    (CONST25, 128, 6),      # two-grid, 2^7 intervals
+    (CONST25, 16384, 5), (CONST05, 16384, 5), (WEIGHT05, 32768, 5), (FRAC04, 4096, 5),
+])
+def test_solve_matches_oracle(case, N, coarsest):
+    """Outer iteration (Sec. 5 stopping rule, tol 1e-10, manufactured RHS):
+    same iteration count and residual history as the oracle; the oracle's
+    residual of the GPU solution is below tol."""
+    say("solve", case[0], N, coarsest)
+    tol = 1e-10
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(coarsest_log2=coarsest, max_iter=400))
+    try:
+        b = B.amg_manufactured_rhs(case[1], case[3], N)
+        x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        st, it, rel = B.amg_solve(h, dev(b), x, tol)
+        hist = B.amg_residual_history(h)
+        H = oracle_hier(case, N, coarsest)
+        xo, ito, histo = tpx.solve(H, b, tol=tol, max_iter=400)
+        assert abs(it - ito) <= 1, (it, ito)
+        k = min(len(hist), len(histo))
+        # each history entry is formed to ~eps kappa |r_0| (see kappa_tol)
+        np.testing.assert_allclose(hist[:k], histo[:k], rtol=1e-5, atol=max(1e-12, kappa_tol(H) / 16))
+        xg = host(x)
+        relo = np.linalg.norm(b - H.matvec(xg)) / np.linalg.norm(b)
+        # forming b - A x loses ~eps |A| |x| / |b| <= eps kappa
+        assert relo < 1.01 * tol + kappa_tol(H), relo
+        assert abs(rel - relo) < 1e-12 + kappa_tol(H)
+        # two solutions with relative residual < tol differ by <= 2 kappa tol
+        kap = np.linalg.cond(H.levels[-1].dense())
+        assert np.abs(xg - xo).max() <= max(1e-12, 4 * kap * tol) * np.abs(xo).max()
+    finally:
+        B.amg_destroy(h)
+
+
+@pytest.mark.parametrize("case,N", [(CONST25, 16384), (WEIGHT05, 32768), (CONST05, 4096)])
+def test_mixed_precision_refinement(case, N):
+    """FP32 V-cycle inside FP64 refinement reaches the same FP64 tolerance; the
+    solution agrees with the FP64 oracle's to ~cond * tol."""
+    say("mixed", case[0], N)
+    tol = 1e-10
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(precision=B.AMG_MIXED))
+    try:
+        b = B.amg_manufactured_rhs(case[1], case[3], N)
+        x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        st, it, rel = B.amg_solve(h, dev(b), x, tol)
+        H = oracle_hier(case, N)
+        xg = host(x)
+        relo = np.linalg.norm(b - H.matvec(xg)) / np.linalg.norm(b)
+        assert relo < 1.01 * tol
+        xo, ito, _ = tpx.solve(H, b, tol=1e-12, max_iter=400)
+        kap = np.linalg.cond(H.levels[-1].dense())
+        err = np.abs(xg - xo).max() / np.abs(xo).max()
+        say("mixed iters", it, "fp64 oracle iters", ito, "error vs FP64 oracle", err)
+        assert err <= 4 * kap * tol
+        assert it <= 2 * ito + 5
+    finally:
+        B.amg_destroy(h)
+
+
+def test_mixed_vcycle_close_to_fp64():
+    """The FP32 V-cycle approximates the FP64 one to FP32 accuracy."""
+    case, N = CONST25, 16384
+    say("mixed_vcycle", N)
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(precision=B.AMG_MIXED))
+    try:
+        r = synthetic.random_vector(2 * N - 1, seed=3)
+        e = torch.empty(2 * N - 1, device="cuda", dtype=torch.float32)
+        B.amg_vcycle(h, dev(r, torch.float32), e)
+        er = tpx.vcycle(oracle_hier(case, N), r)
+        err = np.abs(host(e) - er).max() / np.abs(er).max()
+        assert err < 5e-5, err
+    finally:
+        B.amg_destroy(h)
+
+
+def test_large_n_2_20():
+    """N = 2^20 (the benchmark size): finest matvec against the oracle's FFT
+    matvec, one V-cycle against the oracle's, and a full FP64 and mixed solve
+    whose residual the oracle evaluates."""
+    case, N = CONST25, 2 ** 20
+    say("large", N)
+    H = oracle_hier(case, N)
+    for prec in (B.AMG_FP64, B.AMG_MIXED):
+        h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(precision=prec))
+        try:
+            if prec == B.AMG_FP64:
+                x = synthetic.random_vector(2 * N - 1, seed=9)
+                y = torch.empty(2 * N - 1, device="cuda", dtype=torch.float64)
+                B.amg_matvec(h, dev(x), y)
+                yr = H.matvec(x)
+                assert np.abs(host(y) - yr).max() / np.abs(yr).max() < 1e-13
+                e = torch.empty_like(y)
+                B.amg_vcycle(h, dev(x), e)
+                er = tpx.vcycle(H, x)
+                assert np.abs(host(e) - er).max() / np.abs(er).max() < max(1e-13, kappa_tol(H))
+            b = B.amg_manufactured_rhs(case[1], case[3], N)
+            xs = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+            st, it, rel = B.amg_solve(h, dev(b), xs, 1e-10)
+            relo = np.linalg.norm(b - H.matvec(host(xs))) / np.linalg.norm(b)
+            say("large solve", prec, it, rel, relo)
+            assert relo < 1.01e-10
+        finally:
+            B.amg_destroy(h)
+
+
+def test_not_converged_keeps_last_iterate():
+    case, N = CONST25, 1024
+    say("not_converged", N)
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(max_iter=2))
+    try:
+        b = B.amg_manufactured_rhs(case[1], case[3], N)
+        x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        st, it, rel = B.amg_solve(h, dev(b), x, 1e-10, allow=(B.AMG_NOT_CONVERGED,))
+        assert st == B.AMG_NOT_CONVERGED and it == 2
+        xo, ito, _ = tpx.solve(oracle_hier(case, N), b, tol=1e-10, max_iter=2)
+        assert ito == 2
+        assert np.abs(host(x) - xo).max() <= 1e-11 * np.abs(xo).max()
+    finally:
+        B.amg_destroy(h)
+
+
+def test_divergence_detected():
+    """omega = 1 with the fractional kernel diverges (lambda_max(D^-1 A) > 2,
+    checked by the oracle on the CPU); the solver must stop with
+    AMG_DIVERGED instead of spinning."""
+    case, N = FRAC04, 1024
+    say("diverged", N)
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(omega_pre=1.0, omega_post=1.0))
+    try:
+        b = B.amg_manufactured_rhs(case[1], case[3], N)
+        x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        st, it, rel = B.amg_solve(h, dev(b), x, 1e-10, allow=(B.AMG_DIVERGED,))
+        assert st == B.AMG_DIVERGED and it < 10
+    finally:
+        B.amg_destroy(h)
+
+
+def test_zero_rhs_and_exact_initial_guess():
+    case, N = CONST25, 256
+    say("zero_rhs", N)
+    h = B.amg_setup(case[1], case[3], N)
+    try:
+        b = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        x = torch.zeros_like(b)
+        st, it, rel = B.amg_solve(h, b, x, 1e-10)
+        assert st == B.AMG_OK and it == 0 and rel == 0.0
+        assert float(torch.abs(x).max()) == 0.0
+    finally:
+        B.amg_destroy(h)
+
+
+def test_solve_is_deterministic():
+    case, N = WEIGHT05, 16384
+    say("deterministic", N)
+    h = B.amg_setup(case[1], case[3], N)
+    try:
+        b = dev(B.amg_manufactured_rhs(case[1], case[3], N))
+        x1 = torch.zeros_like(b)
+        x2 = torch.zeros_like(b)
+        B.amg_solve(h, b, x1, 1e-10)
+        B.amg_solve(h, b, x2, 1e-10)
+        assert torch.equal(x1, x2)
+    finally:
+        B.amg_destroy(h)
+
+
+def test_device_argument_errors():
+    case, N = CONST25, 256
+    h = B.amg_setup(case[1], case[3], N)
+    try:
+        x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        s = torch.cuda.current_stream().cuda_stream
+        import ctypes
+        assert B.lib.amg_matvec(h, None, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(s)) == B.AMG_EINVAL
+        assert B.lib.amg_matvec(h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                ctypes.c_void_p(s)) == B.AMG_EINVAL
+        assert B.lib.amg_level_matvec(h, 17, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(8),
+                                      ctypes.c_void_p(s)) == B.AMG_EINVAL
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        assert B.lib.amg_solve(h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(8), -1.0,
+                               ctypes.c_void_p(s), ctypes.byref(it), ctypes.byref(rr)) == B.AMG_EINVAL
+    finally:
+        B.amg_destroy(h)

@@ -124,9 +124,11 @@ def test_tpx_vcycle_equals_dense_vcycle(kern):
     b = D.rhs_manufactured(kern, N)
     e1 = dense.vcycle(H, b)
     e2 = tpx.vcycle(Ht, b)
-    # dense and FFT products round differently (~1e-16 of |A||u| per product);
-    # the fractional operator's spread of scales amplifies that to ~1e-12
-    assert np.abs(e1 - e2).max() <= 1e-11 * np.abs(e1).max()
+    # the two coarsest matrices (dense R A P vs Lemma 3.1) differ by rounding;
+    # the exact coarsest solve amplifies that by its condition number, which
+    # for the fractional kernel is ~2e4 here (it tracks the finest level's)
+    kap = np.linalg.cond(H.A[-1])
+    assert np.abs(e1 - e2).max() <= max(1e-13, 64 * np.finfo(float).eps * kap) * np.abs(e1).max()
     x1, i1, h1 = dense.solve(H, b, tol=1e-10, max_iter=200)
     x2, i2, h2 = tpx.solve(Ht, b, tol=1e-10, max_iter=200)
     assert i1 == i2
