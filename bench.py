@@ -1,0 +1,232 @@
+#!/usr/bin/env python
+"""Throughput of the fast block AMG on one MI355X: solves/s and unknowns/s at
+N = 2^20 intervals for the FP32 V-cycle + FP64 refinement form and the plain
+FP64 form, with p50/p99 latency, the roofline of the finest-level FFT matvec
+sweep, and the CPU FP64 oracle timed on the host beside it.
+
+A step is one complete solve (outer residual, V-cycles over every level --
+FFT matvecs, Jacobi, transfers, coarsest LU -- until ||r||/||r_0|| < tol) of
+the synthetic manufactured problem u = x^2 (1-x)^2, constant kernel
+3/(2 delta^3), delta = 0.25, zero volume constraint, with b resident in HBM.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed solves per form")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed solves per form")
+    ap.add_argument("--logN", type=int, default=20)
+    ap.add_argument("--delta", type=float, default=0.25)
+    ap.add_argument("--kernel", default="const", choices=["const", "weighted", "fractional"])
+    ap.add_argument("--alpha", type=float, default=0.4)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not record HIP events around the finest-level passes")
+    ap.add_argument("--rocprof-summary", metavar="KERNEL_TRACE_CSV",
+                    help="summarise a rocprofv3 --kernel-trace CSV (per kernel and grid size) "
+                         "and exit; no GPU needed")
+    return ap.parse_args()
+
+
+def rocprof_summary(path):
+    """Per (kernel, grid size) call count and average duration from a
+    rocprofv3 kernel-trace CSV; grid size identifies the level."""
+    import collections
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("amg::", "")
+        key = (name, int(r["Grid_Size_X"]))
+        agg[key][0] += 1
+        agg[key][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    tot = sum(v[1] for v in agg.values())
+    print(f"{'kernel':34s} {'grid':>9s} {'calls':>6s} {'avg_us':>9s} {'share%':>7s}")
+    for (name, grid), (calls, us) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        if us / tot < 0.002:
+            continue
+        print(f"{name:34s} {grid:9d} {calls:6d} {us / calls:9.2f} {100 * us / tot:7.2f}")
+    st = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    print(f"total kernel time {tot / 1e3:.2f} ms over {len(rows)} dispatches")
+
+
+def kernel_of(B, args):
+    if args.kernel == "const":
+        return B.kernel(B.AMG_K_CONST)
+    if args.kernel == "weighted":
+        return B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8)
+    return B.kernel(B.AMG_K_FRACTIONAL, alpha=args.alpha)
+
+
+def run_form(B, torch, args, precision, b_dev):
+    N = 2 ** args.logN
+    flags = 0 if args.no_profile else B.AMG_FLAG_PROFILE
+    opts = B.amg_default_opts(precision=precision, flags=flags, max_iter=500)
+    t0 = time.perf_counter()
+    h = B.amg_setup(kernel_of(B, args), args.delta, N, opts)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    x = torch.zeros_like(b_dev)
+    try:
+        for _ in range(args.warmup):
+            x.zero_()
+            B.amg_solve(h, b_dev, x, args.tol)
+        B.amg_profile_stats(h, reset=True)
+        lat, iters = [], []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            x.zero_()  # each solve starts from x_0 = 0
+            t1 = time.perf_counter()
+            st, it, rel = B.amg_solve(h, b_dev, x, args.tol)
+            lat.append(time.perf_counter() - t1)
+            iters.append(it)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        prof = B.amg_profile_stats(h)
+        return dict(handle=None, x=x.clone(), setup_s=setup_s, wall_s=wall, lat=np.array(lat),
+                    iters=iters, relres=rel, prof=prof)
+    finally:
+        B.amg_destroy(h)
+
+
+def sweep_roofline(prof, n, prefix, p_bytes, sym):
+    """Finest-level FFT matvec sweep: 3 passes timed from the event before
+    pass 1 to the event after pass 3.  Algorithmic bytes per sweep (one read
+    and one write of each vector, one read of each spectrum and Cross
+    vector): SPD 11 n p, general 16 n p."""
+    launches, ms = prof.get(f"{prefix}_finest_sweep", (0, 0.0))
+    if launches == 0:
+        return None
+    avg_s = ms / launches * 1e-3
+    alg = (11 if sym else 16) * n * p_bytes
+    ach = alg / avg_s / 1e9
+    passes = {}
+    for k in ("col_fwd", "row", "col_inv"):
+        ln, t = prof.get(f"{prefix}_finest_{k}", (0, 0.0))
+        passes[k] = {"launches": ln, "avg_us": round(t / max(ln, 1) * 1e3, 2)}
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"{prefix} finest-level FFT matvec sweep (3 passes)",
+            "alg_bytes_per_launch": alg, "avg_us": round(avg_s * 1e6, 2), "passes": passes}
+
+
+def summary(res, N):
+    lat = res["lat"]
+    steps = len(lat)
+    sps = steps / res["wall_s"]
+    return {"solves_per_s": round(sps, 3), "unknowns_per_s": round(sps * (2 * N - 1), 1),
+            "ms_per_solve": round(1e3 * res["wall_s"] / steps, 3),
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+            "iters": int(np.median(res["iters"])), "final_relres": res["relres"],
+            "setup_s": round(res["setup_s"], 3)}
+
+
+def cpu_baseline(args, b, x_fp64, x_mixed):
+    """The oracle (CPU FP64, scipy FFT) on the same workload: one full solve,
+    hierarchy setup excluded, on the host's cores; also evaluates the GPU
+    solutions' residuals and their error against the oracle's solution."""
+    from oracle import discretize as D
+    from oracle import tpx
+    N = 2 ** args.logN
+    ok = {"const": D.Kernel(D.CONST, args.delta),
+          "weighted": D.Kernel(D.WEIGHTED, args.delta, wl=1.2, wr=0.8),
+          "fractional": D.Kernel(D.FRACTIONAL, args.delta, alpha=args.alpha)}[args.kernel]
+    t0 = time.perf_counter()
+    H = tpx.Hierarchy.build(tpx.from_stencil(ok, N), 5)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xo, it, hist = tpx.solve(H, b, tol=args.tol, max_iter=500)
+    dt = time.perf_counter() - t0
+    nb = np.linalg.norm(b)
+    out = {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": tpx.WORKERS,
+           "kind": "oracle",
+           "sample": f"1 full FP64 solve at N=2^{args.logN} ({it} V-cycles, {dt:.1f} s; "
+                     f"hierarchy setup {setup:.1f} s excluded), same workload",
+           "unknowns_per_s": round((2 * N - 1) / dt, 1), "iters": it}
+    errs = {}
+    for name, x in (("fp64", x_fp64), ("mixed", x_mixed)):
+        errs[name] = {"relres_oracle": float(np.linalg.norm(b - H.matvec(x)) / nb),
+                      "err_vs_oracle": float(np.abs(x - xo).max() / np.abs(xo).max())}
+    return out, errs
+
+
+def main():
+    args = parse()
+    if args.rocprof_summary:
+        rocprof_summary(args.rocprof_summary)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
+              "part of it (each solve is independent -- shard instances across GPUs instead)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2202_11288_amd import binding as B
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    N = 2 ** args.logN
+    b = B.amg_manufactured_rhs(kernel_of(B, args), args.delta, N)
+    b_dev = torch.from_numpy(b).cuda()
+    print(f"# bench: N=2^{args.logN} kernel={args.kernel} delta={args.delta} "
+          f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    r64 = run_form(B, torch, args, B.AMG_FP64, b_dev)
+    print(f"# fp64 done: {summary(r64, N)}", file=sys.stderr, flush=True)
+    rmx = run_form(B, torch, args, B.AMG_MIXED, b_dev)
+    print(f"# mixed done: {summary(rmx, N)}", file=sys.stderr, flush=True)
+    s64, smx = summary(r64, N), summary(rmx, N)
+    sym = args.kernel != "weighted"
+    n = N - 1
+    roof64 = sweep_roofline(r64["prof"], n, "fp64", 8, sym)
+    roof32 = sweep_roofline(rmx["prof"], n, "fp32", 4, sym)
+    # dominant kernel of the headline (mixed) run
+    t32 = rmx["prof"].get("fp32_finest_sweep", (0, 0.0))[1]
+    t64 = rmx["prof"].get("fp64_finest_sweep", (0, 0.0))[1]
+    roof = roof32 if t32 >= t64 else sweep_roofline(rmx["prof"], n, "fp64", 8, sym)
+    cpu, errs = (None, None)
+    if not args.no_cpu_baseline:
+        cpu, errs = cpu_baseline(args, b, r64["x"].cpu().numpy(), rmx["x"].cpu().numpy())
+    out = {
+        "metric": "solves/s & unknowns/s at N=2^20, FP32+refine vs plain FP64; p50/p99 latency",
+        "value": smx["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": smx["ms_per_solve"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 V-cycle + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"manufactured u=x^2(1-x)^2, {args.kernel} kernel, delta={args.delta}, "
+                               f"N=2^{args.logN} intervals ({2 * N - 1} unknowns), tol={args.tol}, "
+                               "V-cycle to 2^5, omega=2/3, m1=m2=1",
+                   "N": N, "unknowns": 2 * N - 1, "delta": args.delta, "kernel": args.kernel,
+                   "tol": args.tol},
+        "unknowns_per_s": smx["unknowns_per_s"],
+        "mixed": smx, "fp64": s64,
+        "speedup_mixed_vs_fp64": round(smx["solves_per_s"] / s64["solves_per_s"], 3),
+        "roofline": roof, "roofline_fp64_form": roof64, "roofline_fp32_sweep": roof32,
+        "profile_events": not args.no_profile,
+        "cpu_baseline": cpu, "oracle_check": errs,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

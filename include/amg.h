@@ -103,6 +103,17 @@ typedef struct {
    amg_level_size work on such a handle, every device entry point returns
    AMG_EINVAL.  Used to verify the host setup on machines without a GPU. */
 #define AMG_FLAG_HOST_ONLY 1
+/* Record HIP events on the caller's stream around the finest level's three
+   FFT passes, the small-level V-cycle kernel, each V-cycle and each outer
+   residual during amg_solve; read the totals with amg_profile_stats. */
+#define AMG_FLAG_PROFILE 2
+
+/* Per-kernel timing accumulated while AMG_FLAG_PROFILE is set. */
+typedef struct {
+  char name[48];      /* e.g. "finest_col_fwd", "finest_row", "finest_col_inv" */
+  int64_t launches;   /* launches timed since the last reset                  */
+  double total_ms;    /* summed event-to-event time (ms)                      */
+} amg_stat_t;
 
 /* Fill *o with m1 = m2 = 1, omega = 2/3, coarsest_log2 = 5, FP64,
    max_iter = 200. */
@@ -159,6 +170,11 @@ int64_t amg_level_size(amg_t h, int level);
  * the Cross vectors p, q, xi, zeta (n values each) and o (1 value). */
 int amg_level_tpx(amg_t h, int level, double* a, double* b, double* c, double* d,
                   double* p, double* q, double* xi, double* zeta, double* o);
+
+/* Copy up to `cap` timing records (host array) accumulated by amg_solve
+ * under AMG_FLAG_PROFILE; returns the number of records (>= 0) or an error
+ * code.  reset != 0 clears the totals after copying. */
+int amg_profile_stats(amg_t h, amg_stat_t* out, int cap, int reset);
 
 /* Right-hand side f(x_c) = -L_delta u(x_c) for the manufactured solution
  * u = x^2 (1-x)^2 (zero outside (0,1)) at the 2N-1 collocation points in

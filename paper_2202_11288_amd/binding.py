@@ -21,6 +21,7 @@ AMG_EINVAL, AMG_ENOMEM, AMG_EHIP, AMG_ENOTSUP = -1, -2, -3, -4
 AMG_K_CONST, AMG_K_WEIGHTED, AMG_K_FRACTIONAL, AMG_K_GENERATORS = 0, 1, 2, 3
 AMG_FP64, AMG_MIXED = 0, 1
 AMG_FLAG_HOST_ONLY = 1
+AMG_FLAG_PROFILE = 2
 
 
 class AmgError(RuntimeError):
@@ -40,6 +41,11 @@ class amg_opts_t(ctypes.Structure):
                 ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("flags", ctypes.c_int)]
 
 
+class amg_stat_t(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2202_11288_amd.build`")
@@ -56,6 +62,7 @@ def _load():
         "amg_vcycle": (I, [P, P, P, P]),
         "amg_solve": (I, [P, P, P, D, P, IP, DP]),
         "amg_residual_history": (I, [P, DP, I]),
+        "amg_profile_stats": (I, [P, ctypes.POINTER(amg_stat_t), I, I]),
         "amg_num_levels": (I, [P]),
         "amg_level_size": (I64, [P, I]),
         "amg_level_tpx": (I, [P, I, DP, DP, DP, DP, DP, DP, DP, DP, DP]),
@@ -171,6 +178,15 @@ def amg_residual_history(h, cap: int = 100001):
     if k < 0:
         raise AmgError(k, "amg_residual_history")
     return buf[:k].copy()
+
+
+def amg_profile_stats(h, reset: bool = False):
+    """{name: (launches, total_ms)} recorded under AMG_FLAG_PROFILE."""
+    arr = (amg_stat_t * 16)()
+    k = lib.amg_profile_stats(h, arr, 16, int(bool(reset)))
+    if k < 0:
+        raise AmgError(k, "amg_profile_stats")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(k)}
 
 
 def amg_num_levels(h) -> int:

@@ -119,7 +119,58 @@ LevelDev<float> LevelRes::dev<float>() const {
 
 }  // namespace
 
+// Event-based timing of selected launches (AMG_FLAG_PROFILE).
+// Finest-level passes are kept apart by precision (FP32 kinds = FP64 kind + 4).
+enum ProfKind {
+  PK_COL_FWD = 0, PK_ROW, PK_COL_INV, PK_SWEEP,
+  PK_COL_FWD32, PK_ROW32, PK_COL_INV32, PK_SWEEP32,
+  PK_TAIL, PK_VCYCLE, PK_OUTER, PK_COUNT
+};
+static const char* const kProfNames[PK_COUNT] = {
+    "fp64_finest_col_fwd", "fp64_finest_row", "fp64_finest_col_inv", "fp64_finest_sweep",
+    "fp32_finest_col_fwd", "fp32_finest_row", "fp32_finest_col_inv", "fp32_finest_sweep",
+    "tail_vcycle", "vcycle", "outer_residual"};
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<std::pair<int, std::pair<size_t, size_t>>> pending;
+  int64_t launches[PK_COUNT] = {};
+  double total_ms[PK_COUNT] = {};
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  // returns the index of a recorded event, or SIZE_MAX if profiling is off
+  size_t mark(hipStream_t s) {
+    if (!on) return SIZE_MAX;
+    if (next == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return SIZE_MAX;
+      pool.push_back(e);
+    }
+    if (hipEventRecord(pool[next], s) != hipSuccess) return SIZE_MAX;
+    return next++;
+  }
+  void span(int kind, size_t a, size_t b) {
+    if (a != SIZE_MAX && b != SIZE_MAX) pending.push_back({kind, {a, b}});
+  }
+  // after the stream has been synchronised
+  void collect() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pool[p.second.first], pool[p.second.second]) == hipSuccess) {
+        launches[p.first] += 1;
+        total_ms[p.first] += ms;
+      }
+    }
+    pending.clear();
+    next = 0;
+  }
+};
+
 struct amg_ctx {
+  Profiler prof;
   int device = 0;
   int64_t N = 0;
   amg_opts_t opts{};
@@ -208,7 +259,7 @@ int check_opts(const amg_opts_t* o) {
   if (o->coarsest_log2 < 2 || o->coarsest_log2 > 7) return AMG_EINVAL;
   if (o->precision != AMG_FP64 && o->precision != AMG_MIXED) return AMG_EINVAL;
   if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
-  if (o->flags & ~AMG_FLAG_HOST_ONLY) return AMG_EINVAL;
+  if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE)) return AMG_EINVAL;
   return AMG_OK;
 }
 
@@ -269,9 +320,22 @@ int fourstep(amg_ctx* c, int l, int cmode, const ColIn<T>& in, int emode, const 
   cplx<T>* buf = buf_of<T>(c);
   T* dp = dpart_of<T>(c);
   const Twiddles<T>& tw = tw_of<T>(c);
+  Profiler& P = c->prof;
+  const bool prof = P.on && l == 0;
+  const size_t e0 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_col_fwd<T>(cmode, d, in, buf, tw, dp, s));
+  const size_t e1 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_row<T>(1, d, buf, tw, dp, col_blocks(d.logL1, d.tcols), out.xin, s));
+  const size_t e2 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_col_inv<T>(emode, d, out, buf, tw, c->npart, s));
+  if (prof) {
+    const size_t e3 = P.mark(s);
+    const int off = sizeof(T) == 4 ? PK_COL_FWD32 : PK_COL_FWD;
+    P.span(off + 0, e0, e1);
+    P.span(off + 1, e1, e2);
+    P.span(off + 2, e2, e3);
+    P.span(off + 3, e0, e3);
+  }
   return AMG_OK;
 }
 
@@ -304,8 +368,10 @@ int vcycle_dev(amg_ctx* c, hipStream_t s) {
   }
   {
     const T* rf = (ft > 0) ? c->lv[ft - 1].template dev<T>().r : nullptr;
+    const size_t t0 = c->prof.mark(s);
     HIP_TRY(launch_tail_vcycle<T>(lvdev_of<T>(c), ft, nl - 1, rf, o.m1, o.m2, wpre, wpost, c->lu,
                                   tw_of<T>(c), c->maxL_tail, s));
+    c->prof.span(PK_TAIL, t0, c->prof.mark(s));
   }
   for (int l = ft - 1; l >= 0; --l) {
     const LevelDev<T> d = c->lv[l].template dev<T>();
@@ -590,6 +656,7 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
   c->N = N;
   c->opts = o;
   c->host_only = (o.flags & AMG_FLAG_HOST_ONLY) != 0;
+  c->prof.on = (o.flags & AMG_FLAG_PROFILE) != 0 && !c->host_only;
   c->mixed = o.precision == AMG_MIXED;
   try {
     c->host.push_back(finest_level(ks, N));
@@ -705,10 +772,16 @@ int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int
     HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h->st_host->done) break;
+    const size_t v0 = h->prof.mark(s);
     if (h->mixed) AMG_TRY(vcycle_dev<float>(h, s));
     else AMG_TRY(vcycle_dev<double>(h, s));
+    const size_t v1 = h->prof.mark(s);
     AMG_TRY(outer_residual(h, b, x, e, tol, s));
+    const size_t v2 = h->prof.mark(s);
+    h->prof.span(PK_VCYCLE, v0, v1);
+    h->prof.span(PK_OUTER, v1, v2);
   }
+  h->prof.collect();
   const SolveState st = *h->st_host;
   h->last_iters = st.iter;
   h->hist.assign((size_t)st.iter + 1, 0.0);
@@ -717,6 +790,24 @@ int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int
   if (iters) *iters = st.iter;
   if (relres) *relres = st.relres;
   return st.status;
+}
+
+int amg_profile_stats(amg_t h, amg_stat_t* out, int cap, int reset) {
+  if (!h || cap < 0 || (!out && cap > 0)) return AMG_EINVAL;
+  const int k = std::min<int>(cap, PK_COUNT);
+  for (int i = 0; i < k; ++i) {
+    std::memset(&out[i], 0, sizeof(amg_stat_t));
+    std::snprintf(out[i].name, sizeof(out[i].name), "%s", kProfNames[i]);
+    out[i].launches = h->prof.launches[i];
+    out[i].total_ms = h->prof.total_ms[i];
+  }
+  if (reset) {
+    for (int i = 0; i < PK_COUNT; ++i) {
+      h->prof.launches[i] = 0;
+      h->prof.total_ms[i] = 0.0;
+    }
+  }
+  return k;
 }
 
 int amg_residual_history(amg_t h, double* hist, int cap) {
