@@ -22,7 +22,7 @@ using namespace amg;
 
 namespace {
 
-constexpr int kTailMaxLog = 13;  // levels with L <= 2^13 run in the one-workgroup tail kernel
+// levels with L <= 2^kTailLog run in the one-workgroup tail kernels (amg_device.hpp)
 
 struct Plan {
   int logL, logL1, logL2, tcols;
@@ -34,7 +34,7 @@ Plan plan_level(int64_t n) {
   int logL = 0;
   while ((int64_t(1) << logL) < 2 * (n + 1)) ++logL;
   p.logL = logL;
-  p.tail = logL <= kTailMaxLog;
+  p.tail = logL <= kTailLog;
   if (p.tail) {
     p.logL1 = logL;
     p.logL2 = 0;

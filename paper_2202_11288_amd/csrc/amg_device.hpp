@@ -12,12 +12,14 @@ template <typename T>
 struct cplx;
 
 // Constants of the FFT machinery.
-constexpr int kTwM = 16384;        // base twiddle table: e^{-2 pi i m / kTwM}
+constexpr int kTwLog = 14;
+constexpr int kTwM = 1 << kTwLog;  // base twiddle table: e^{-2 pi i m / kTwM}
 constexpr int kTw4Log = 23;        // four-step twiddles resolved on 2^23 points
 constexpr int kTw4Lo = 4096;       // low table: e^{-2 pi i m / 2^23}, m < 4096
 constexpr int kTw4Hi = 2048;       // high table: e^{-2 pi i m 4096 / 2^23}, m < 2048
 constexpr int kNT4 = 256;          // threads of a four-step pass workgroup
-constexpr int kNTT = 1024;         // threads of the single-workgroup tail kernels
+constexpr int kNTT = 512;          // threads of the single-workgroup tail kernels
+constexpr int kTailLog = 12;       // levels with L <= 2^12 run in the tail kernels
 
 template <typename T>
 struct Twiddles {

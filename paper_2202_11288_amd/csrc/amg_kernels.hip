@@ -14,7 +14,7 @@
 // inverse column FFTs) with the vector formation (smoothing, restriction,
 // prolongation, refinement update) fused into the first pass and the residual
 // / Jacobi epilogue fused into the last.  Small levels run the whole V-cycle
-// below them in one workgroup with the FFT in LDS.
+// below them in one workgroup with the FFT and its twiddles in LDS.
 #include <mutex>
 #include <unordered_map>
 
@@ -28,42 +28,29 @@ struct Cfg;
 template <>
 struct Cfg<double> {
   static constexpr int E4 = 16;  // elements per thread, four-step passes (4096 / WG)
-  static constexpr int ET = 8;   // elements per thread, tail kernels (8192 / WG)
+  static constexpr int ET = 8;   // elements per thread, tail kernels (4096 / WG)
 };
 template <>
 struct Cfg<float> {
   static constexpr int E4 = 32;  // 8192 / WG
-  static constexpr int ET = 16;  // 16384 / WG
+  static constexpr int ET = 8;
 };
 
-template <typename T>
-__device__ __forceinline__ cplx<T> tw4(const Twiddles<T>& tw, int logL, int64_t e) {
-  // e^{-2 pi i e / L}, e < L <= 2^23, from two table lookups
-  const int64_t idx = e << (kTw4Log - logL);
-  return cmul(tw.hi[idx >> 12], tw.lo[idx & (kTw4Lo - 1)]);
-}
+__device__ __forceinline__ int ilog2(int x) { return 31 - __clz(x); }
 
-// Deterministic block sum (fixed tree order); every thread gets the result.
-template <typename T, int NT>
-__device__ __forceinline__ T block_sum(T v, T* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const T r = red[0];
-  __syncthreads();
-  return r;
+template <typename T>
+__device__ __forceinline__ cplx<T> tw4(const Twiddles<T>& tw, int logL, int e) {
+  // e^{-2 pi i e / L}, e < L <= 2^23, from two table lookups
+  const int idx = e << (kTw4Log - logL);
+  return cmul(tw.hi[idx >> 12], tw.lo[idx & (kTw4Lo - 1)]);
 }
 
 // Prolongation 2 R^T at fine index m of a fine vector of length 2*mc + 1
 // (mc = coarse length): odd m = 2i+1 -> e[i]; even m = 2i -> (e[i-1] + e[i])/2.
 template <typename T>
-__device__ __forceinline__ T prolong_at(const T* e, int64_t mc, int64_t m) {
+__device__ __forceinline__ T prolong_at(const T* e, int mc, int m) {
   if (m & 1) return e[m >> 1];
-  const int64_t i = m >> 1;
+  const int i = m >> 1;
   T s = 0;
   if (i >= 1) s += e[i - 1];
   if (i < mc) s += e[i];
@@ -72,16 +59,22 @@ __device__ __forceinline__ T prolong_at(const T* e, int64_t mc, int64_t m) {
 
 // Restriction 1/4 [1 2 1] at coarse index i (Sec. 3.1).
 template <typename T>
-__device__ __forceinline__ T restrict_at(const T* r, int64_t i) {
+__device__ __forceinline__ T restrict_at(const T* r, int i) {
   return T(0.25) * (r[2 * i] + T(2) * r[2 * i + 1] + r[2 * i + 2]);
 }
 
 // Circulant first column of the embedding of T[i][j] = t_{j-i} (eq. (ccs3.4)):
 // c_m = t_{-m} (m < n), c_m = t_{L-m} (m > L-n), 0 otherwise.
-__device__ __forceinline__ double circ_col(const double* g, int64_t n, int64_t L, int64_t m) {
+__device__ __forceinline__ double circ_col(const double* g, int n, int L, int m) {
   if (m < n) return g[n - 1 - m];
   if (m > L - n) return g[n - 1 + (L - m)];
   return 0.0;
+}
+
+// Column tiles: consecutive tiles go to the same XCD (blocks are dealt to the
+// 8 XCDs round robin), so neighbouring row segments share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  return (G % 8 == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
 }
 
 // ---------------------------------------------------------------------------
@@ -92,23 +85,24 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kNT4) void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf,
                                                   Twiddles<T> tw, T* part) {
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  __shared__ T red[kNT4];
-  const int64_t n = lv.n;
-  const int64_t L = int64_t(1) << lv.logL;
-  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2, TC = lv.tcols;
-  const int c0 = blockIdx.x * TC;
-  const int cnt = L2 * TC;
+  const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
+  __shared__ T red[kNT4 / 64];
+  const int n = lv.n;
+  const int L = 1 << lv.logL;
+  const int TC = lv.tcols, logTC = ilog2(TC);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int c0 = tile * TC;
+  const int cnt = TC << lv.logL2;
   T dot = 0;
   for (int idx = threadIdx.x; idx < cnt; idx += kNT4) {
-    const int i = idx / TC, t = idx - i * TC;
-    const int64_t j = (int64_t)(c0 + t) + (int64_t)L1 * i;
+    const int i = idx >> logTC, t = idx & (TC - 1);
+    const int j = c0 + t + (i << lv.logL1);
     cplx<T> z = {T(0), T(0)};
     if constexpr (MODE == COL_SETUP) {
       z.x = (T)circ_col(in.gx, n, L, j);
       z.y = (T)circ_col(in.gy, n, L, j);
     } else if (j < n) {
-      const int64_t jw = n + 1 + j;
+      const int jw = n + 1 + j;
       T v, w;
       if constexpr (MODE == COL_MV) {
         v = in.x[j];
@@ -150,7 +144,7 @@ __global__ __launch_bounds__(kNT4) void k_col_fwd(LevelDev<T> lv, ColIn<T> in, c
     lds[idx] = z;
   }
   if constexpr (MODE != COL_SETUP && MODE != COL_MV) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the w_o entry
+    if (tile == 0 && threadIdx.x == 0) {  // the w_o entry
       if constexpr (MODE == COL_PRE) {
         lv.u[n] = in.omega * lv.b[n] / lv.o;
       } else if constexpr (MODE == COL_PRE_RESTRICT) {
@@ -167,15 +161,16 @@ __global__ __launch_bounds__(kNT4) void k_col_fwd(LevelDev<T> lv, ColIn<T> in, c
   }
   if constexpr (MODE != COL_SETUP) {
     const T s = block_sum<T, kNT4>(dot, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[tile] = s;
   } else {
     __syncthreads();
   }
-  lds_fft<T, Cfg<T>::E4, kNT4, false>(lds, L2, TC, 1, TC, true, tw.base, kTwM);
+  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  lds_fft<T, Cfg<T>::E4, kNT4, false>(lds, g, tw.base);
   for (int idx = threadIdx.x; idx < cnt; idx += kNT4) {
-    const int k2 = idx / TC, t = idx - k2 * TC;
+    const int k2 = idx >> logTC, t = idx & (TC - 1);
     const int j1 = c0 + t;
-    buf[(int64_t)j1 + (int64_t)L1 * k2] = cmul(lds[idx], tw4(tw, lv.logL, (int64_t)j1 * k2));
+    buf[j1 + (k2 << lv.logL1)] = cmul(lds[idx], tw4(tw, lv.logL, j1 * k2));
   }
 }
 
@@ -186,8 +181,8 @@ __global__ __launch_bounds__(kNT4) void k_col_fwd(LevelDev<T> lv, ColIn<T> in, c
 // y_o = q.v + o w_o + zeta.w_bar from pass 1's partial sums.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void spec_pair(const LevelDev<T>& lv, cplx<T>* lds, int la, int lb,
-                                          int64_t ga, int64_t gb) {
+__device__ __forceinline__ void spec_pair(const LevelDev<T>& lv, Lds<T> lds, int la, int lb,
+                                          int ga, int gb) {
   const cplx<T> za = lds[la], zb = lds[lb];
   cplx<T> ya, yb;
   if (lv.sym) {
@@ -209,25 +204,26 @@ template <typename T, bool SPECTRAL>
 __global__ __launch_bounds__(kNT4) void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw,
                                               const T* part, int npart, const T* xin) {
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2;
   const int item = blockIdx.x;
   const int ka = item == 0 ? 0 : item;
   const int kb = item == 0 ? L2 / 2 : L2 - item;
+  const int ra = ka << lv.logL1, rb = kb << lv.logL1;
   for (int t = threadIdx.x; t < L1; t += kNT4) {
-    lds[t] = buf[(int64_t)ka * L1 + t];
-    lds[L1 + t] = buf[(int64_t)kb * L1 + t];
+    lds[t] = buf[ra + t];
+    lds[L1 + t] = buf[rb + t];
   }
   __syncthreads();
-  lds_fft<T, Cfg<T>::E4, kNT4, false>(lds, L1, 2, L1, 1, false, tw.base, kTwM);
+  const FftGeom g{lv.logL1, 1, lv.logL1, 0, kTwLog, false};
+  lds_fft<T, Cfg<T>::E4, kNT4, false>(lds, g, tw.base);
   if constexpr (!SPECTRAL) {
     for (int t = threadIdx.x; t < L1; t += kNT4) {
-      buf[(int64_t)ka * L1 + t] = lds[t];
-      buf[(int64_t)kb * L1 + t] = lds[L1 + t];
+      buf[ra + t] = lds[t];
+      buf[rb + t] = lds[L1 + t];
     }
     return;
   } else {
-    const int64_t ra = (int64_t)ka * L1, rb = (int64_t)kb * L1;
     if (item != 0) {
       // (ka, k1) pairs with (kb, L1-1-k1)
       for (int t = threadIdx.x; t < L1; t += kNT4)
@@ -246,10 +242,10 @@ __global__ __launch_bounds__(kNT4) void k_row(LevelDev<T> lv, cplx<T>* buf, Twid
       }
     }
     __syncthreads();
-    lds_fft<T, Cfg<T>::E4, kNT4, true>(lds, L1, 2, L1, 1, false, tw.base, kTwM);
+    lds_fft<T, Cfg<T>::E4, kNT4, true>(lds, g, tw.base);
     for (int t = threadIdx.x; t < L1; t += kNT4) {
-      buf[ra + t] = cmul(lds[t], conj(tw4(tw, lv.logL, (int64_t)t * ka)));
-      buf[rb + t] = cmul(lds[L1 + t], conj(tw4(tw, lv.logL, (int64_t)t * kb)));
+      buf[ra + t] = cmul(lds[t], conj(tw4(tw, lv.logL, t * ka)));
+      buf[rb + t] = cmul(lds[L1 + t], conj(tw4(tw, lv.logL, t * kb)));
     }
     if (item == 0 && threadIdx.x == 0) {
       T s = 0;
@@ -268,26 +264,28 @@ __global__ __launch_bounds__(kNT4) void k_col_inv(LevelDev<T> lv, EpiOut<T> out,
                                                   const cplx<T>* buf, Twiddles<T> tw,
                                                   double* part) {
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  __shared__ double red[kNT4];
-  const int64_t n = lv.n;
-  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2, TC = lv.tcols;
-  const int c0 = blockIdx.x * TC;
-  const int cnt = L2 * TC;
+  const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
+  __shared__ double red[kNT4 / 64];
+  const int n = lv.n;
+  const int TC = lv.tcols, logTC = ilog2(TC);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int c0 = tile * TC;
+  const int cnt = TC << lv.logL2;
   for (int idx = threadIdx.x; idx < cnt; idx += kNT4) {
-    const int i = idx / TC, t = idx - i * TC;
-    lds[idx] = buf[(int64_t)(c0 + t) + (int64_t)L1 * i];
+    const int i = idx >> logTC, t = idx & (TC - 1);
+    lds[idx] = buf[c0 + t + (i << lv.logL1)];
   }
   __syncthreads();
-  lds_fft<T, Cfg<T>::E4, kNT4, true>(lds, L2, TC, 1, TC, true, tw.base, kTwM);
+  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  lds_fft<T, Cfg<T>::E4, kNT4, true>(lds, g, tw.base);
   const T wo = out.xin[n];
   double ss = 0.0;
-  const int half = (L2 / 2) * TC;  // outputs j2 < L2/2 cover j < n
+  const int half = cnt >> 1;  // outputs j2 < L2/2 cover j < n
   for (int idx = threadIdx.x; idx < half; idx += kNT4) {
-    const int i = idx / TC, t = idx - i * TC;
-    const int64_t j = (int64_t)(c0 + t) + (int64_t)L1 * i;
+    const int i = idx >> logTC, t = idx & (TC - 1);
+    const int j = c0 + t + (i << lv.logL1);
     if (j >= n) continue;
-    const int64_t jw = n + 1 + j;
+    const int jw = n + 1 + j;
     const cplx<T> y = lds[idx];
     const T yv = y.x + lv.p[j] * wo;
     const T yw = y.y + lv.xi[j] * wo;
@@ -311,7 +309,7 @@ __global__ __launch_bounds__(kNT4) void k_col_inv(LevelDev<T> lv, EpiOut<T> out,
       ss += rv * rv + rw * rw;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (tile == 0 && threadIdx.x == 0) {
     const T yo = lv.scal[0];
     if constexpr (MODE == EPI_MV) {
       out.y[n] = yo;
@@ -328,38 +326,132 @@ __global__ __launch_bounds__(kNT4) void k_col_inv(LevelDev<T> lv, EpiOut<T> out,
   }
   if constexpr (MODE == EPI_OUTER) {
     const double s = block_sum<double, kNT4>(ss, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[tile] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Tail levels: the whole FFT of length L <= E*1024 in one workgroup's LDS.
+// Tail levels: L <= 2^12, one workgroup of 512 threads, FFT and twiddles in LDS.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ T tail_matvec_core(const LevelDev<T>& lv, const T* x, cplx<T>* z, T* red,
-                              const Twiddles<T>& tw) {
-  // leaves y_v + i y_w_bar (without the Cross terms) in z[0..n) and returns
-  // y_o = q.v + o w_o + zeta.w_bar
-  const int n = lv.n, L = 1 << lv.logL;
-  T dot = 0;
-  for (int j = threadIdx.x; j < L; j += kNTT) {
-    cplx<T> v = {T(0), T(0)};
-    if (j < n) {
-      v.x = x[j];
-      v.y = x[n + 1 + j];
-      dot += lv.q[j] * v.x + lv.zeta[j] * v.y;
-    }
-    z[j] = v;
-  }
-  const T s = block_sum<T, kNTT>(dot, red);
-  lds_fft<T, Cfg<T>::ET, kNTT, false>(z, L, 1, 0, 1, false, tw.base, kTwM);
+struct TailLds {
+  Lds<T> z;     // lds_slots(2^kTailLog) complex
+  cplx<T>* tw;  // 2^kTailLog twiddles e^{-2 pi i m / 2^kTailLog}
+  T* red;       // kNTT/64 wave partials + 2 broadcast slots
+};
+
+template <typename T>
+__device__ TailLds<T> tail_lds(unsigned char* smem, const cplx<T>* tw_base) {
+  TailLds<T> s;
+  s.z.p = reinterpret_cast<cplx<T>*>(smem);
+  s.tw = s.z.p + lds_slots(1 << kTailLog);
+  s.red = reinterpret_cast<T*>(s.tw + (1 << kTailLog));
+  for (int m = threadIdx.x; m < (1 << kTailLog); m += kNTT)
+    s.tw[m] = tw_base[m << (kTwLog - kTailLog)];
+  __syncthreads();
+  return s;
+}
+constexpr size_t tail_lds_bytes(size_t elem) {
+  return 2 * elem * ((size_t)lds_slots(1 << kTailLog) + (1 << kTailLog)) + elem * (kNTT / 64 + 2);
+}
+
+// z holds the packed input (zero-padded); leaves y_v + i y_w_bar (without the
+// Cross terms) in z[0..n).
+template <typename T>
+__device__ void tail_fft_spectral(const LevelDev<T>& lv, const TailLds<T>& s) {
+  const int L = 1 << lv.logL;
+  const FftGeom g{lv.logL, 0, 0, 0, kTailLog, false};
+  lds_fft<T, Cfg<T>::ET, kNTT, false>(s.z, g, s.tw);
   for (int f = threadIdx.x; f <= L / 2; f += kNTT) {
     const int fb = (L - f) & (L - 1);
-    spec_pair(lv, z, f, fb, f, fb);
+    spec_pair(lv, s.z, f, fb, f, fb);
   }
   __syncthreads();
-  lds_fft<T, Cfg<T>::ET, kNTT, true>(z, L, 1, 0, 1, false, tw.base, kTwM);
-  return s + lv.o * x[n];
+  lds_fft<T, Cfg<T>::ET, kNTT, true>(s.z, g, s.tw);
+}
+
+enum TailPro { TP_PRE_B = 0, TP_PRE_RESTRICT, TP_USE_U, TP_PROLONG };
+enum TailEpi { TE_RESID = 0, TE_SMOOTH };
+constexpr int kTailJ = (1 << (kTailLog - 1)) / kNTT;  // v/w slots per thread (n < L/2)
+
+// One matvec step of a tail level: form u (prologue), y = A u, then the
+// residual or Jacobi epilogue; b and u stay in registers between the two.
+template <typename T>
+__device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int epi, const T* src,
+                                          T wpro, T wepi, const TailLds<T>& s) {
+  const int n = lv.n, L = 1 << lv.logL;
+  T bv[kTailJ], bw[kTailJ], uv[kTailJ], uw[kTailJ];
+  T dot = 0;
+#pragma unroll
+  for (int k = 0; k < kTailJ; ++k) {
+    const int j = threadIdx.x + k * kNTT;
+    bv[k] = bw[k] = uv[k] = uw[k] = T(0);
+    if (j < n) {
+      const int jw = n + 1 + j;
+      if (pro == TP_PRE_RESTRICT) {
+        bv[k] = restrict_at(src, j);
+        bw[k] = restrict_at(src, jw);
+        lv.b[j] = bv[k];
+        lv.b[jw] = bw[k];
+      } else {
+        bv[k] = lv.b[j];
+        bw[k] = lv.b[jw];
+      }
+      if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) {
+        uv[k] = wpro * bv[k] / lv.dv;
+        uw[k] = wpro * bw[k] / lv.dw;
+        lv.u[j] = uv[k];
+        lv.u[jw] = uw[k];
+      } else if (pro == TP_PROLONG) {
+        uv[k] = lv.u[j] + prolong_at(src, n, j);
+        uw[k] = lv.u[jw] + prolong_at(src, n, jw);
+        lv.u[j] = uv[k];
+        lv.u[jw] = uw[k];
+      } else {
+        uv[k] = lv.u[j];
+        uw[k] = lv.u[jw];
+      }
+      s.z[j] = {uv[k], uw[k]};
+      dot += lv.q[j] * uv[k] + lv.zeta[j] * uw[k];
+    }
+  }
+  for (int j = n + threadIdx.x; j < L; j += kNTT) s.z[j] = {T(0), T(0)};
+  if (threadIdx.x == 0) {  // the w_o entry
+    const T bo = (pro == TP_PRE_RESTRICT) ? restrict_at(src, n) : lv.b[n];
+    if (pro == TP_PRE_RESTRICT) lv.b[n] = bo;
+    T uo;
+    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) uo = wpro * bo / lv.o;
+    else if (pro == TP_PROLONG) uo = lv.u[n] + prolong_at(src, n, n);
+    else uo = lv.u[n];
+    if (pro != TP_USE_U) lv.u[n] = uo;
+    s.red[kNTT / 64] = uo;
+    s.red[kNTT / 64 + 1] = bo;
+  }
+  const T qdot = block_sum<T, kNTT>(dot, s.red);  // also publishes z and the w_o slots
+  const T uo = s.red[kNTT / 64], bo = s.red[kNTT / 64 + 1];
+  tail_fft_spectral(lv, s);
+#pragma unroll
+  for (int k = 0; k < kTailJ; ++k) {
+    const int j = threadIdx.x + k * kNTT;
+    if (j < n) {
+      const int jw = n + 1 + j;
+      const cplx<T> y = s.z[j];
+      const T yv = y.x + lv.p[j] * uo, yw = y.y + lv.xi[j] * uo;
+      if (epi == TE_RESID) {
+        lv.r[j] = bv[k] - yv;
+        lv.r[jw] = bw[k] - yw;
+      } else {
+        lv.u[j] = uv[k] + wepi * (bv[k] - yv) / lv.dv;
+        lv.u[jw] = uw[k] + wepi * (bw[k] - yw) / lv.dw;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    const T yo = qdot + lv.o * uo;
+    if (epi == TE_RESID) lv.r[n] = bo - yo;
+    else lv.u[n] = uo + wepi * (bo - yo) / lv.o;
+  }
+  __syncthreads();  // global writes visible to the next step; z and red reusable
 }
 
 template <typename T>
@@ -383,7 +475,7 @@ __device__ void coarse_lu_solve(const CoarseLU& lu, const T* b, T* u) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = lane + 64 * s;
-      if (i > k && i < m) x[s] -= lu.lcm[(int64_t)k * m + i] * xk;
+      if (i > k && i < m) x[s] -= lu.lcm[k * m + i] * xk;
     }
   }
   for (int k = m - 1; k >= 0; --k) {  // U x = y
@@ -397,7 +489,7 @@ __device__ void coarse_lu_solve(const CoarseLU& lu, const T* b, T* u) {
     for (int s = 0; s < 4; ++s) {
       const int i = lane + 64 * s;
       if (i == k) x[s] = xk;
-      else if (i < k) x[s] -= lu.ucm[(int64_t)k * m + i] * xk;
+      else if (i < k) x[s] -= lu.ucm[k * m + i] * xk;
     }
   }
 #pragma unroll
@@ -411,70 +503,47 @@ template <typename T>
 __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels, int first,
                                                       int last, const T* rf, int m1, int m2,
                                                       T wpre, T wpost, CoarseLU lu,
-                                                      Twiddles<T> tw, int maxL) {
+                                                      Twiddles<T> tw) {
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* z = reinterpret_cast<cplx<T>*>(smem_raw);
-  T* red = reinterpret_cast<T*>(z + maxL);
-  // ---- descend: pre-smooth, residual, restrict
-  for (int l = first; l <= last; ++l) {
-    const LevelDev<T> lv = levels[l];
-    const int n = lv.n, m = 2 * n + 1;
-    const T* src = (l == first) ? rf : levels[l - 1].r;
-    if (src) {
-      for (int i = threadIdx.x; i < m; i += kNTT) lv.b[i] = restrict_at(src, i);
-    }
-    __syncthreads();
-    if (l == last) {
-      if (threadIdx.x < 64) coarse_lu_solve<T>(lu, lv.b, lv.u);
+  const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);
+  // One loop over the V-cycle's matvec steps (a single inlined tail_step):
+  // descend (level first..last-1, m1 sweeps each, residual on the last one),
+  // the coarsest solve, then ascend (prolongation + m2 post-sweeps).
+  const int nlev = last - first;
+  const int ndesc = nlev * m1;
+  const int nsteps = ndesc + 1 + nlev * m2;
+  for (int step = 0; step < nsteps; ++step) {
+    if (step == ndesc) {  // coarsest level: b = R r_fine, exact solve by LU
+      const LevelDev<T> lc = levels[last];
+      const T* src = (last == first) ? rf : levels[last - 1].r;
+      if (src)
+        for (int i = threadIdx.x; i < 2 * lc.n + 1; i += kNTT) lc.b[i] = restrict_at(src, i);
       __syncthreads();
-      break;
-    }
-    for (int i = threadIdx.x; i < m; i += kNTT) {
-      const T d = (i < n) ? lv.dv : (i == n ? lv.o : lv.dw);
-      lv.u[i] = wpre * lv.b[i] / d;
-    }
-    __syncthreads();
-    for (int sweep = 0; sweep < m1; ++sweep) {
-      const T yo = tail_matvec_core(lv, lv.u, z, red, tw);
-      const T wo = lv.u[n];
-      const bool last_sweep = sweep == m1 - 1;
-      __syncthreads();  // every thread has read u[n] before it changes
-      for (int j = threadIdx.x; j < n; j += kNTT) {
-        const T yv = z[j].x + lv.p[j] * wo, yw = z[j].y + lv.xi[j] * wo;
-        if (last_sweep) {
-          lv.r[j] = lv.b[j] - yv;
-          lv.r[n + 1 + j] = lv.b[n + 1 + j] - yw;
-        } else {
-          lv.u[j] += wpre * (lv.b[j] - yv) / lv.dv;
-          lv.u[n + 1 + j] += wpre * (lv.b[n + 1 + j] - yw) / lv.dw;
-        }
-      }
-      if (threadIdx.x == 0) {
-        if (last_sweep) lv.r[n] = lv.b[n] - yo;
-        else lv.u[n] += wpre * (lv.b[n] - yo) / lv.o;
-      }
+      if (threadIdx.x < 64) coarse_lu_solve<T>(lu, lc.b, lc.u);
       __syncthreads();
+      continue;
     }
-  }
-  // ---- ascend: prolongate, post-smooth
-  for (int l = last - 1; l >= first; --l) {
-    const LevelDev<T> lv = levels[l];
-    const int n = lv.n, m = 2 * n + 1;
-    const T* ec = levels[l + 1].u;
-    for (int i = threadIdx.x; i < m; i += kNTT) lv.u[i] += prolong_at(ec, n, i);
-    __syncthreads();
-    for (int sweep = 0; sweep < m2; ++sweep) {
-      const T yo = tail_matvec_core(lv, lv.u, z, red, tw);
-      const T wo = lv.u[n];
-      __syncthreads();
-      for (int j = threadIdx.x; j < n; j += kNTT) {
-        const T yv = z[j].x + lv.p[j] * wo, yw = z[j].y + lv.xi[j] * wo;
-        lv.u[j] += wpost * (lv.b[j] - yv) / lv.dv;
-        lv.u[n + 1 + j] += wpost * (lv.b[n + 1 + j] - yw) / lv.dw;
-      }
-      if (threadIdx.x == 0) lv.u[n] += wpost * (lv.b[n] - yo) / lv.o;
-      __syncthreads();
+    int l, pro, epi;
+    const T* src;
+    T wpro, wepi;
+    if (step < ndesc) {
+      l = first + step / m1;
+      const int sweep = step - (l - first) * m1;  // 0-based
+      const T* fine = (l == first) ? rf : levels[l - 1].r;
+      pro = sweep > 0 ? TP_USE_U : (fine ? TP_PRE_RESTRICT : TP_PRE_B);
+      epi = sweep == m1 - 1 ? TE_RESID : TE_SMOOTH;
+      src = fine;
+      wpro = wepi = wpre;
+    } else {
+      const int a = step - ndesc - 1;
+      l = last - 1 - a / m2;
+      const int sweep = a - (last - 1 - l) * m2;
+      pro = sweep == 0 ? TP_PROLONG : TP_USE_U;
+      epi = TE_SMOOTH;
+      src = levels[l + 1].u;
+      wpro = wepi = wpost;
     }
+    tail_step(levels[l], pro, epi, src, wpro, wepi, s);
   }
 }
 
@@ -484,10 +553,9 @@ template <typename T, int CM, int EM>
 __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> in, EpiOut<T> out,
                                                       Twiddles<T> tw, double* part) {
   extern __shared__ unsigned char smem_raw[];
+  const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);
+  __shared__ double redd[kNTT / 64];
   const int n = lv.n, L = 1 << lv.logL;
-  cplx<T>* z = reinterpret_cast<cplx<T>*>(smem_raw);
-  T* red = reinterpret_cast<T*>(z + L);
-  __shared__ double redd[kNTT];
   const T* x = out.xin;
   if constexpr (CM == COL_OUTER_UPDATE) {
     for (int i = threadIdx.x; i < 2 * n + 1; i += kNTT) {
@@ -496,11 +564,22 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
     }
     __syncthreads();
   }
-  const T yo = tail_matvec_core(lv, x, z, red, tw);
+  T dot = 0;
+  for (int j = threadIdx.x; j < L; j += kNTT) {
+    cplx<T> v = {T(0), T(0)};
+    if (j < n) {
+      v = {x[j], x[n + 1 + j]};
+      dot += lv.q[j] * v.x + lv.zeta[j] * v.y;
+    }
+    s.z[j] = v;
+  }
+  const T yo = block_sum<T, kNTT>(dot, s.red) + lv.o * x[n];
+  tail_fft_spectral(lv, s);
   const T wo = x[n];
   double ss = 0.0;
   for (int j = threadIdx.x; j < n; j += kNTT) {
-    const T yv = z[j].x + lv.p[j] * wo, yw = z[j].y + lv.xi[j] * wo;
+    const cplx<T> z = s.z[j];
+    const T yv = z.x + lv.p[j] * wo, yw = z.y + lv.xi[j] * wo;
     if constexpr (EM == EPI_MV) {
       out.y[j] = yv;
       out.y[n + 1 + j] = yw;
@@ -526,8 +605,8 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
     }
   }
   if constexpr (EM == EPI_OUTER) {
-    const double s = block_sum<double, kNTT>(ss, redd);
-    if (threadIdx.x == 0) part[0] = s;
+    const double sum = block_sum<double, kNTT>(ss, redd);
+    if (threadIdx.x == 0) part[0] = sum;
   }
 }
 
@@ -536,12 +615,13 @@ __global__ __launch_bounds__(kNTT) void k_tail_fft_setup(LevelDev<double> lv, co
                                                          const double* gy, cplx<double>* out,
                                                          Twiddles<double> tw) {
   extern __shared__ unsigned char smem_raw[];
-  cplx<double>* z = reinterpret_cast<cplx<double>*>(smem_raw);
-  const int64_t n = lv.n, L = int64_t(1) << lv.logL;
-  for (int j = threadIdx.x; j < L; j += kNTT) z[j] = {circ_col(gx, n, L, j), circ_col(gy, n, L, j)};
+  const TailLds<double> s = tail_lds<double>(smem_raw, tw.base);
+  const int n = lv.n, L = 1 << lv.logL;
+  for (int j = threadIdx.x; j < L; j += kNTT) s.z[j] = {circ_col(gx, n, L, j), circ_col(gy, n, L, j)};
   __syncthreads();
-  lds_fft<double, Cfg<double>::ET, kNTT, false>(z, (int)L, 1, 0, 1, false, tw.base, kTwM);
-  for (int j = threadIdx.x; j < L; j += kNTT) out[j] = z[j];
+  const FftGeom g{lv.logL, 0, 0, 0, kTailLog, false};
+  lds_fft<double, Cfg<double>::ET, kNTT, false>(s.z, g, s.tw);
+  for (int j = threadIdx.x; j < L; j += kNTT) out[j] = s.z[j];
 }
 
 // Setup: spectra of the four blocks from two packed transforms
@@ -550,26 +630,26 @@ __global__ __launch_bounds__(kNTT) void k_tail_fft_setup(LevelDev<double> lv, co
 __global__ void k_combine(int logL, int logL1, int logL2, const cplx<double>* z1,
                           const cplx<double>* z2, int sym, double* g1, double* g2, float* g1f,
                           float* g2f) {
-  const int64_t L = int64_t(1) << logL;
-  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int L = 1 << logL;
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
   if (pos >= L) return;
-  int64_t pp;
+  int pp;
   if (logL2 == 0) {
     pp = (L - pos) & (L - 1);
   } else {
-    const int64_t L1 = int64_t(1) << logL1, L2 = int64_t(1) << logL2;
-    const int64_t k2 = pos >> logL1, k1 = pos & (L1 - 1);
-    const int64_t f = k2 + L2 * k1;
-    const int64_t fn = (L - f) & (L - 1);
+    const int L1 = 1 << logL1, L2 = 1 << logL2;
+    const int k2 = pos >> logL1, k1 = pos & (L1 - 1);
+    const int f = k2 + L2 * k1;
+    const int fn = (L - f) & (L - 1);
     pp = (fn & (L2 - 1)) * L1 + (fn >> logL2);
   }
   const cplx<double> a1 = z1[pos], b1 = conj(z1[pp]), a2 = z2[pos], b2 = conj(z2[pp]);
   const cplx<double> Ah = scale(a1 + b1, 0.5), Ch = scale(a2 + b2, 0.5);
-  const cplx<double> Bh = scale(rot<double, false>(a1 - b1), 0.5);  // (z - conj)/(2i) = -i(z - conj)/2
+  const cplx<double> Bh = scale(rot<double, false>(a1 - b1), 0.5);  // (z - conj)/(2i)
   const cplx<double> Dh = scale(rot<double, false>(a2 - b2), 0.5);
-  const double s = 0.5 / (double)L;
-  const cplx<double> G1 = scale((Ah + Dh) + rot<double, true>(Ch - Bh), s);
-  const cplx<double> G2 = scale((Ah - Dh) + rot<double, true>(Ch + Bh), s);
+  const double sc = 0.5 / (double)L;
+  const cplx<double> G1 = scale((Ah + Dh) + rot<double, true>(Ch - Bh), sc);
+  const cplx<double> G2 = scale((Ah - Dh) + rot<double, true>(Ch + Bh), sc);
   if (sym) {
     g1[pos] = G1.x;
     g2[pos] = G2.y;
@@ -592,12 +672,14 @@ __global__ void k_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 }
 
 // Stopping test of the outer iteration (Sec. 5): ||r_i|| / ||r_0|| < tol.
-__global__ void k_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
-                         double* hist) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* part, int npart,
+                                                double tol, int max_iter, double* hist) {
+  __shared__ double red[256 / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < npart; i += 256) v += part[i];
+  const double s = block_sum<double, 256>(v, red);
+  if (threadIdx.x != 0) return;
   if (st->done) return;
-  double s = 0.0;
-  for (int i = 0; i < npart; ++i) s += part[i];
   const double nrm = sqrt(s);
   if (st->iter == 0) {
     st->r0 = nrm;
@@ -652,7 +734,7 @@ template <typename T>
 hipError_t launch_col_fwd(int mode, const LevelDev<T>& lv, const ColIn<T>& in, cplx<T>* buf,
                           const Twiddles<T>& tw, T* part, hipStream_t s) {
   const int grid = col_blocks(lv.logL1, lv.tcols);
-  const size_t lds = sizeof(cplx<T>) * (size_t)lv.tcols << lv.logL2;
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(lv.tcols << lv.logL2);
   hipError_t e = hipSuccess;
   switch (mode) {
     case COL_MV: e = set_lds(k_col_fwd<T, COL_MV>, lds); break;
@@ -680,7 +762,7 @@ template <typename T>
 hipError_t launch_row(int spectral, const LevelDev<T>& lv, cplx<T>* buf, const Twiddles<T>& tw,
                       const T* part, int npart, const T* xin, hipStream_t s) {
   const int grid = (1 << lv.logL2) / 2;
-  const size_t lds = sizeof(cplx<T>) * 2 << lv.logL1;
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(2 << lv.logL1);
   hipError_t e = spectral ? set_lds(k_row<T, true>, lds) : set_lds(k_row<T, false>, lds);
   if (e != hipSuccess) return e;
   if (spectral)
@@ -694,7 +776,7 @@ template <typename T>
 hipError_t launch_col_inv(int mode, const LevelDev<T>& lv, const EpiOut<T>& out,
                           const cplx<T>* buf, const Twiddles<T>& tw, double* part, hipStream_t s) {
   const int grid = col_blocks(lv.logL1, lv.tcols);
-  const size_t lds = sizeof(cplx<T>) * (size_t)lv.tcols << lv.logL2;
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(lv.tcols << lv.logL2);
   hipError_t e = hipSuccess;
   switch (mode) {
     case EPI_MV: e = set_lds(k_col_inv<T, EPI_MV>, lds); break;
@@ -718,8 +800,8 @@ template <typename T>
 hipError_t launch_tail_matvec(int colmode, int epimode, const LevelDev<T>& lv, const ColIn<T>& in,
                               const EpiOut<T>& out, const Twiddles<T>& tw, double* part,
                               hipStream_t s) {
-  const size_t L = size_t(1) << lv.logL;
-  const size_t lds = sizeof(cplx<T>) * L + sizeof(T) * kNTT;
+  if (lv.logL > kTailLog) return hipErrorInvalidValue;
+  const size_t lds = tail_lds_bytes(sizeof(T));
   hipError_t e;
   if (colmode == COL_MV && epimode == EPI_MV) {
     auto k = k_tail_matvec<T, COL_MV, EPI_MV>;
@@ -743,18 +825,19 @@ template <typename T>
 hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
                               int m1, int m2, T wpre, T wpost, const CoarseLU& lu,
                               const Twiddles<T>& tw, int maxL, hipStream_t s) {
-  const size_t lds = sizeof(cplx<T>) * (size_t)maxL + sizeof(T) * kNTT;
+  if (maxL > (1 << kTailLog) || lu.m > 256) return hipErrorInvalidValue;
+  const size_t lds = tail_lds_bytes(sizeof(T));
   auto k = k_tail_vcycle<T>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, 1, kNTT, lds, s, levels_dev, first, last, rf, m1, m2, wpre, wpost, lu, tw,
-                     maxL);
+  hipLaunchKernelGGL(k, 1, kNTT, lds, s, levels_dev, first, last, rf, m1, m2, wpre, wpost, lu, tw);
   return hipGetLastError();
 }
 
 hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, const double* gy,
                                  cplx<double>* out, const Twiddles<double>& tw, hipStream_t s) {
-  const size_t lds = sizeof(cplx<double>) << lv.logL;
+  if (lv.logL > kTailLog) return hipErrorInvalidValue;
+  const size_t lds = tail_lds_bytes(sizeof(double));
   hipError_t e = set_lds(k_tail_fft_setup, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tail_fft_setup, 1, kNTT, lds, s, lv, gx, gy, out, tw);
@@ -772,7 +855,7 @@ hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 
 hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
                          double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, 1, 64, 0, s, st, part, npart, tol, max_iter, hist);
+  hipLaunchKernelGGL(k_finish, 1, 256, 0, s, st, part, npart, tol, max_iter, hist);
   return hipGetLastError();
 }
 

@@ -13,8 +13,6 @@ struct alignas(2 * sizeof(T)) cplx {
 };
 
 template <typename T>
-__device__ __forceinline__ cplx<T> mk(T a, T b) { return cplx<T>{a, b}; }
-template <typename T>
 __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
 __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
@@ -50,6 +48,18 @@ __device__ __forceinline__ void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx
   a3 = t1 - t3;
 }
 
+// (1 -+ i)/sqrt2 * a and (-1 -+ i)/sqrt2 * a without a general complex product
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> w8_1(cplx<T> a) {
+  const T s = T(0.70710678118654752440);
+  return INV ? cplx<T>{s * (a.x - a.y), s * (a.x + a.y)} : cplx<T>{s * (a.x + a.y), s * (a.y - a.x)};
+}
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> w8_3(cplx<T> a) {
+  const T s = T(0.70710678118654752440);
+  return INV ? cplx<T>{-s * (a.x + a.y), s * (a.x - a.y)} : cplx<T>{s * (a.y - a.x), -s * (a.x + a.y)};
+}
+
 template <typename T, bool INV>
 __device__ __forceinline__ void dft8(cplx<T>* a) {
   // radix-2 decimation in time: even/odd DFT4s, twiddles e^{-+2 pi i k/8}
@@ -57,13 +67,9 @@ __device__ __forceinline__ void dft8(cplx<T>* a) {
   cplx<T> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
   dft4<T, INV>(e0, e1, e2, e3);
   dft4<T, INV>(o0, o1, o2, o3);
-  const T s = T(0.70710678118654752440);
-  // w1 = (1 -+ i)/sqrt2, w2 = -+i, w3 = (-1 -+ i)/sqrt2
-  const cplx<T> w1 = INV ? cplx<T>{s, s} : cplx<T>{s, -s};
-  const cplx<T> w3 = INV ? cplx<T>{-s, s} : cplx<T>{-s, -s};
-  o1 = cmul(o1, w1);
+  o1 = w8_1<T, INV>(o1);
   o2 = rot<T, INV>(o2);
-  o3 = cmul(o3, w3);
+  o3 = w8_3<T, INV>(o3);
   a[0] = e0 + o0; a[4] = e0 - o0;
   a[1] = e1 + o1; a[5] = e1 - o1;
   a[2] = e2 + o2; a[6] = e2 - o2;
@@ -80,19 +86,23 @@ __device__ __forceinline__ void dft16(cplx<T>* a) {
   }
   dft8<T, INV>(e);
   dft8<T, INV>(o);
-  // cos/sin(k pi / 8), k = 0..7
-  const T c[8] = {T(1.0), T(0.92387953251128675613), T(0.70710678118654752440),
-                  T(0.38268343236508977173), T(0.0), T(-0.38268343236508977173),
-                  T(-0.70710678118654752440), T(-0.92387953251128675613)};
-  const T s[8] = {T(0.0), T(0.38268343236508977173), T(0.70710678118654752440),
-                  T(0.92387953251128675613), T(1.0), T(0.92387953251128675613),
-                  T(0.70710678118654752440), T(0.38268343236508977173)};
+  // e^{-+2 pi i k/16}: k = 2, 4, 6 reuse the eighth roots; 1, 3, 5, 7 need a product
+  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+  const cplx<T> w1 = INV ? cplx<T>{c1, s1} : cplx<T>{c1, -s1};
+  const cplx<T> w3 = INV ? cplx<T>{s1, c1} : cplx<T>{s1, -c1};
+  const cplx<T> w5 = INV ? cplx<T>{-s1, c1} : cplx<T>{-s1, -c1};
+  const cplx<T> w7 = INV ? cplx<T>{-c1, s1} : cplx<T>{-c1, -s1};
+  o[1] = cmul(o[1], w1);
+  o[2] = w8_1<T, INV>(o[2]);
+  o[3] = cmul(o[3], w3);
+  o[4] = rot<T, INV>(o[4]);
+  o[5] = cmul(o[5], w5);
+  o[6] = w8_3<T, INV>(o[6]);
+  o[7] = cmul(o[7], w7);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const cplx<T> w = INV ? cplx<T>{c[k], s[k]} : cplx<T>{c[k], -s[k]};
-    const cplx<T> t = (k == 0) ? o[k] : cmul(o[k], w);
-    a[k] = e[k] + t;
-    a[k + 8] = e[k] - t;
+    a[k] = e[k] + o[k];
+    a[k + 8] = e[k] - o[k];
   }
 }
 
@@ -104,48 +114,77 @@ __device__ __forceinline__ void dft(cplx<T>* a) {
   else dft16<T, INV>(a);
 }
 
+// ---- LDS view with a one-in-sixteen skew -------------------------------------
+// Element i lives at slot i + i/16: the power-of-two strides of the Stockham
+// stores (R*16 B, R*T*16 B) then fall on distinct 16-byte bank groups.
+template <typename T>
+struct Lds {
+  cplx<T>* p;
+  __device__ __forceinline__ cplx<T>& operator[](int i) const { return p[i + (i >> 4)]; }
+};
+__host__ __device__ constexpr int lds_slots(int count) { return count + (count >> 4) + 1; }
+
+// Twiddles w_r = e^{-2 pi i r step / 2^logtw} for r = 1..R-1 from at most four
+// table loads (w1, w2, w4, w8) and products of two or three of them.
+template <typename T, int R>
+__device__ __forceinline__ void twiddle_set(const cplx<T>* __restrict__ tw, int step, cplx<T>* w) {
+  w[1] = tw[step];
+  if constexpr (R >= 4) {
+    w[2] = tw[2 * step];
+    w[3] = cmul(w[1], w[2]);
+  }
+  if constexpr (R >= 8) {
+    w[4] = tw[4 * step];
+    w[5] = cmul(w[1], w[4]);
+    w[6] = cmul(w[2], w[4]);
+    w[7] = cmul(w[3], w[4]);
+  }
+  if constexpr (R >= 16) {
+    w[8] = tw[8 * step];
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+  }
+}
+
 // ---- Stockham FFT over signals in LDS ---------------------------------------
 //
-// S signals of length M (power of two); element i of signal s lives at
-// lds[s*ss + i*es].  NT threads each own E elements per pass (S*M <= E*NT).
-// Twiddles come from a base table tw[m] = e^{-2 pi i m / TWM} (conjugated for
-// the inverse transform); M must divide TWM.  Output is in natural order, in
-// place.  sigfast: consecutive threads take consecutive signals (use when
-// ss == 1, i.e. signals interleaved), otherwise consecutive butterflies.
+// S = 2^logS signals of length M = 2^logM; element i of signal s lives at
+// lds[(s << logss) + (i << loges)].  NT threads each own E elements per pass
+// (S*M <= E*NT).  Twiddles come from a base table tw[m] = e^{-2 pi i m/2^logtw}
+// (conjugated for the inverse transform), M <= 2^logtw.  Output is in natural
+// order, in place.  sigfast: consecutive threads take consecutive signals (use
+// when signals are interleaved), otherwise consecutive butterflies.
+struct FftGeom {
+  int logM, logS, logss, loges, logtw;
+  bool sigfast;
+};
 
 template <typename T, int R, int E, int NT, bool INV>
-__device__ __forceinline__ void stockham_pass(cplx<T>* lds, int M, int S, int ss, int es,
-                                              int Ns, bool sigfast, const cplx<T>* __restrict__ tw,
-                                              int twM) {
+__device__ __forceinline__ void stockham_pass(Lds<T> lds, const FftGeom& g, int logNs,
+                                              const cplx<T>* __restrict__ tw) {
   constexpr int NB = E / R;
+  constexpr int LR = R == 16 ? 4 : (R == 8 ? 3 : (R == 4 ? 2 : 1));
   static_assert(NB >= 1 && NB * R == E, "radix must divide E");
-  const int nbs = M / R;  // butterflies per signal
-  const int total = nbs * S;
+  const int lognbs = g.logM - LR;  // butterflies per signal = M / R
+  const int total = 1 << (lognbs + g.logS);
+  const int Ns = 1 << logNs;
   cplx<T> a[E];
 #pragma unroll
   for (int e = 0; e < NB; ++e) {
     const int bf = threadIdx.x + e * NT;
     if (bf < total) {
-      int s, j;
-      if (sigfast) {
-        s = bf % S;
-        j = bf / S;
-      } else {
-        s = bf / nbs;
-        j = bf - s * nbs;
-      }
+      const int s = g.sigfast ? (bf & ((1 << g.logS) - 1)) : (bf >> lognbs);
+      const int j = g.sigfast ? (bf >> g.logS) : (bf & ((1 << lognbs) - 1));
+      const int base = s << g.logss;
 #pragma unroll
-      for (int r = 0; r < R; ++r) a[e * R + r] = lds[s * ss + (j + r * nbs) * es];
-      // twiddle e^{-+2 pi i r k / (Ns R)}, k = j mod Ns
-      const int k = j & (Ns - 1);
-      if (Ns > 1) {
-        const int step = twM / (Ns * R) * k;
+      for (int r = 0; r < R; ++r) a[e * R + r] = lds[base + ((j + (r << lognbs)) << g.loges)];
+      if (logNs > 0) {
+        // e^{-+2 pi i r k / (Ns R)}, k = j mod Ns
+        const int k = j & (Ns - 1);
+        cplx<T> w[R];
+        twiddle_set<T, R>(tw, k << (g.logtw - logNs - LR), w);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          cplx<T> w = tw[r * step];
-          if (INV) w.y = -w.y;
-          a[e * R + r] = cmul(a[e * R + r], w);
-        }
+        for (int r = 1; r < R; ++r) a[e * R + r] = cmul(a[e * R + r], INV ? conj(w[r]) : w[r]);
       }
       dft<T, R, INV>(a + e * R);
     }
@@ -155,47 +194,61 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* lds, int M, int S, int ss
   for (int e = 0; e < NB; ++e) {
     const int bf = threadIdx.x + e * NT;
     if (bf < total) {
-      int s, j;
-      if (sigfast) {
-        s = bf % S;
-        j = bf / S;
-      } else {
-        s = bf / nbs;
-        j = bf - s * nbs;
-      }
+      const int s = g.sigfast ? (bf & ((1 << g.logS) - 1)) : (bf >> lognbs);
+      const int j = g.sigfast ? (bf >> g.logS) : (bf & ((1 << lognbs) - 1));
       const int k = j & (Ns - 1);
-      const int base = (j - k) * R + k;
+      const int out = ((j - k) << LR) + k;
+      const int base = s << g.logss;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[s * ss + (base + r * Ns) * es] = a[e * R + r];
+      for (int r = 0; r < R; ++r) lds[base + ((out + (r << logNs)) << g.loges)] = a[e * R + r];
     }
   }
   __syncthreads();
 }
 
-// Full FFT (forward if !INV) of S signals of length M in LDS, natural order in
-// and out.  A single radix-2/4/8 pass first (no twiddles), then radix RMAX.
+// Full FFT (forward if !INV) of the signals in LDS, natural order in and out.
+// A single radix-2/4/8 pass first (no twiddles), then radix RMAX passes.
 template <typename T, int E, int NT, bool INV>
-__device__ void lds_fft(cplx<T>* lds, int M, int S, int ss, int es, bool sigfast,
-                        const cplx<T>* __restrict__ tw, int twM) {
+__device__ void lds_fft(Lds<T> lds, const FftGeom& g, const cplx<T>* __restrict__ tw) {
   constexpr int RMAX = E >= 16 ? 16 : E;
   constexpr int LR = RMAX == 16 ? 4 : (RMAX == 8 ? 3 : (RMAX == 4 ? 2 : 1));
-  const int logM = 31 - __builtin_clz(M);
-  int rem = logM % LR;
-  int Ns = 1;
+  const int rem = g.logM % LR;
+  int logNs = 0;
   if (rem == 1) {
-    stockham_pass<T, 2, E, NT, INV>(lds, M, S, ss, es, Ns, sigfast, tw, twM);
-    Ns = 2;
+    stockham_pass<T, 2, E, NT, INV>(lds, g, 0, tw);
+    logNs = 1;
   } else if (rem == 2) {
-    stockham_pass<T, 4, E, NT, INV>(lds, M, S, ss, es, Ns, sigfast, tw, twM);
-    Ns = 4;
+    stockham_pass<T, 4, E, NT, INV>(lds, g, 0, tw);
+    logNs = 2;
   } else if (rem == 3) {
-    stockham_pass<T, 8, E, NT, INV>(lds, M, S, ss, es, Ns, sigfast, tw, twM);
-    Ns = 8;
+    stockham_pass<T, 8, E, NT, INV>(lds, g, 0, tw);
+    logNs = 3;
   }
-  while (Ns < M) {
-    stockham_pass<T, RMAX, E, NT, INV>(lds, M, S, ss, es, Ns, sigfast, tw, twM);
-    Ns *= RMAX;
+  while (logNs < g.logM) {
+    stockham_pass<T, RMAX, E, NT, INV>(lds, g, logNs, tw);
+    logNs += LR;
   }
+}
+
+// Deterministic reduction of one value per thread over a workgroup of NT
+// threads: butterfly within each wave (lane 0's fixed order), then the wave
+// partials in index order.  Every thread returns the same value.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <typename T, int NT>
+__device__ __forceinline__ T block_sum(T v, T* red /* >= NT/64 entries */) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T s = red[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
 }
 
 }  // namespace amg
