@@ -154,6 +154,20 @@ int amg_vcycle(amg_t h, const void* r, void* e, void* stream);
 int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream,
               int* iters, double* relres);
 
+/* Solve `count` independent problems: for each i, the same iteration as
+ * amg_solve(hs[i], b[i], x[i], tol[i]) (host arrays of device pointers and
+ * tolerances).  The instances run concurrently on internal streams of the
+ * library, forked from and joined back into `stream` (so the work is ordered
+ * after earlier work on `stream`, and later work on it sees the results);
+ * their iterations advance in rounds with one host synchronisation per round.
+ * Handles must be distinct and live on one device; N, kernel and precision
+ * may differ.  Each instance's arithmetic is identical to its solo solve.
+ * iters/relres (host arrays, may be NULL) receive per-instance results.
+ * Returns AMG_OK if every instance converged, else the largest positive
+ * status (AMG_NOT_CONVERGED, AMG_DIVERGED), or an error code. */
+int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const* x,
+                    const double* tol, void* stream, int* iters, double* relres);
+
 /* Relative residual history of the last amg_solve: hist (host) receives
  * min(cap, iters+1) values, hist[i] = ||b - A x_i|| / ||r_0||.  Returns the
  * number written (>= 0) or an error code. */

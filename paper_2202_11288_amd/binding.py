@@ -62,6 +62,8 @@ def _load():
         "amg_vcycle": (I, [P, P, P, P]),
         "amg_solve": (I, [P, P, P, D, P, IP, DP]),
         "amg_residual_history": (I, [P, DP, I]),
+        "amg_solve_batch": (I, [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                DP, P, IP, DP]),
         "amg_profile_stats": (I, [P, ctypes.POINTER(amg_stat_t), I, I]),
         "amg_num_levels": (I, [P]),
         "amg_level_size": (I64, [P, I]),
@@ -169,6 +171,20 @@ def amg_solve(h, b, x, tol: float, stream=None, allow=(AMG_OK,)):
                        ctypes.byref(rr))
     _check(st, "amg_solve", ok=allow)
     return st, it.value, rr.value
+
+
+def amg_solve_batch(hs, bs, xs, tols, stream=None, allow=(AMG_OK,)):
+    """Solve independent instances; returns (status, iters list, relres list)."""
+    k = len(hs)
+    H = (ctypes.c_void_p * k)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in hs])
+    Bp = (ctypes.c_void_p * k)(*[_ptr(b).value for b in bs])
+    Xp = (ctypes.c_void_p * k)(*[_ptr(x).value for x in xs])
+    T = (ctypes.c_double * k)(*[float(t) for t in tols])
+    it = (ctypes.c_int * k)()
+    rr = (ctypes.c_double * k)()
+    st = lib.amg_solve_batch(k, H, Bp, Xp, T, _stream(stream), it, rr)
+    _check(st, "amg_solve_batch", ok=allow)
+    return st, list(it), list(rr)
 
 
 def amg_residual_history(h, cap: int = 100001):

@@ -757,39 +757,144 @@ int amg_vcycle(amg_t h, const void* r, void* e, void* stream) {
   return AMG_OK;
 }
 
+namespace {
+
+// One solve is: begin (reset the stop state, r_0 = b - A x_0, stop test), then
+// rounds of (V-cycle, x += e fused into r = b - A x, stop test) until the
+// device-side state says done; every enqueue ends with an asynchronous copy of
+// the 40-byte state to pinned host memory.
+int solve_begin(amg_t h, const double* b, double* x, double tol, hipStream_t s) {
+  SolveState init{};
+  *h->st_host = init;
+  HIP_TRY(hipMemcpyAsync(h->st_dev, h->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
+  AMG_TRY(outer_residual(h, b, x, nullptr, tol, s));
+  HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  return AMG_OK;
+}
+
+int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s) {
+  const void* e = h->mixed ? (const void*)h->lv[0].uf : (const void*)h->lv[0].ud;
+  const size_t v0 = h->prof.mark(s);
+  if (h->mixed) AMG_TRY(vcycle_dev<float>(h, s));
+  else AMG_TRY(vcycle_dev<double>(h, s));
+  const size_t v1 = h->prof.mark(s);
+  AMG_TRY(outer_residual(h, b, x, e, tol, s));
+  const size_t v2 = h->prof.mark(s);
+  h->prof.span(PK_VCYCLE, v0, v1);
+  h->prof.span(PK_OUTER, v1, v2);
+  HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  return AMG_OK;
+}
+
+// After the stream has been synchronised: residual history and results.
+int solve_end(amg_t h, hipStream_t s, int* iters, double* relres) {
+  h->prof.collect();
+  const SolveState st = *h->st_host;
+  h->last_iters = st.iter;
+  h->hist.assign((size_t)st.iter + 1, 0.0);
+  HIP_TRY(hipMemcpyAsync(h->hist.data(), h->hist_dev, h->hist.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters) *iters = st.iter;
+  if (relres) *relres = st.relres;
+  return st.status;
+}
+
+// Internal streams (default priority) for amg_solve_batch, one pool per device.
+struct StreamPool {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;  // one per stream (join) + one (fork)
+};
+std::mutex g_pool_mu;
+std::unordered_map<int, StreamPool> g_pools;
+constexpr int kBatchStreams = 8;
+
+int get_pool(int device, StreamPool** out) {
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  StreamPool& p = g_pools[device];
+  if (p.streams.empty()) {
+    for (int i = 0; i < kBatchStreams; ++i) {
+      hipStream_t st;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      p.streams.push_back(st);
+    }
+    for (int i = 0; i <= kBatchStreams; ++i) {
+      hipEvent_t ev;
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      p.events.push_back(ev);
+    }
+  }
+  *out = &p;
+  return AMG_OK;
+}
+
+}  // namespace
+
 int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int* iters,
               double* relres) {
   if (!h || !b || !x || h->host_only || b == x) return AMG_EINVAL;
   if (!(tol > 0.0) || !std::isfinite(tol)) return AMG_EINVAL;
   HIP_TRY(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
-  SolveState init{};
-  *h->st_host = init;
-  HIP_TRY(hipMemcpyAsync(h->st_dev, h->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
-  AMG_TRY(outer_residual(h, b, x, nullptr, tol, s));
-  const void* e = h->mixed ? (const void*)h->lv[0].uf : (const void*)h->lv[0].ud;
+  AMG_TRY(solve_begin(h, b, x, tol, s));
   for (;;) {
-    HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h->st_host->done) break;
-    const size_t v0 = h->prof.mark(s);
-    if (h->mixed) AMG_TRY(vcycle_dev<float>(h, s));
-    else AMG_TRY(vcycle_dev<double>(h, s));
-    const size_t v1 = h->prof.mark(s);
-    AMG_TRY(outer_residual(h, b, x, e, tol, s));
-    const size_t v2 = h->prof.mark(s);
-    h->prof.span(PK_VCYCLE, v0, v1);
-    h->prof.span(PK_OUTER, v1, v2);
+    AMG_TRY(solve_round(h, b, x, tol, s));
   }
-  h->prof.collect();
-  const SolveState st = *h->st_host;
-  h->last_iters = st.iter;
-  h->hist.assign((size_t)st.iter + 1, 0.0);
-  HIP_TRY(hipMemcpy(h->hist.data(), h->hist_dev, h->hist.size() * sizeof(double),
-                    hipMemcpyDeviceToHost));
-  if (iters) *iters = st.iter;
-  if (relres) *relres = st.relres;
-  return st.status;
+  return solve_end(h, s, iters, relres);
+}
+
+int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const* x,
+                    const double* tol, void* stream, int* iters, double* relres) {
+  if (count < 0 || (count > 0 && (!hs || !b || !x || !tol))) return AMG_EINVAL;
+  if (count == 0) return AMG_OK;
+  const int dev = hs[0] ? hs[0]->device : -1;
+  for (int i = 0; i < count; ++i) {
+    amg_t h = hs[i];
+    if (!h || h->host_only || h->device != dev || !b[i] || !x[i] || b[i] == x[i]) return AMG_EINVAL;
+    if (!(tol[i] > 0.0) || !std::isfinite(tol[i])) return AMG_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == h) return AMG_EINVAL;  // a handle's buffers serve one solve at a time
+  }
+  HIP_TRY(hipSetDevice(dev));
+  hipStream_t s = (hipStream_t)stream;
+  StreamPool* pool = nullptr;
+  AMG_TRY(get_pool(dev, &pool));
+  const int S = std::min(count, kBatchStreams);
+  // fork: the internal streams start after the caller's stream
+  HIP_TRY(hipEventRecord(pool->events[kBatchStreams], s));
+  for (int k = 0; k < S; ++k) HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->events[kBatchStreams], 0));
+  for (int i = 0; i < count; ++i)
+    AMG_TRY(solve_begin(hs[i], b[i], x[i], tol[i], pool->streams[i % S]));
+  std::vector<char> done(count, 0);
+  for (;;) {
+    for (int k = 0; k < S; ++k) HIP_TRY(hipStreamSynchronize(pool->streams[k]));
+    int active = 0;
+    for (int i = 0; i < count; ++i) {
+      if (done[i]) continue;
+      if (hs[i]->st_host->done) {
+        done[i] = 1;
+        continue;
+      }
+      ++active;
+      AMG_TRY(solve_round(hs[i], b[i], x[i], tol[i], pool->streams[i % S]));
+    }
+    if (!active) break;
+  }
+  int worst = AMG_OK;
+  for (int i = 0; i < count; ++i) {
+    const int st = solve_end(hs[i], pool->streams[i % S], iters ? &iters[i] : nullptr,
+                             relres ? &relres[i] : nullptr);
+    if (st < 0) return st;
+    worst = std::max(worst, st);
+  }
+  // join: the caller's stream continues after every internal stream
+  for (int k = 0; k < S; ++k) {
+    HIP_TRY(hipEventRecord(pool->events[k], pool->streams[k]));
+    HIP_TRY(hipStreamWaitEvent(s, pool->events[k], 0));
+  }
+  return worst;
 }
 
 int amg_profile_stats(amg_t h, amg_stat_t* out, int cap, int reset) {

@@ -250,7 +250,11 @@ __global__ __launch_bounds__(kNT4) void k_row(LevelDev<T> lv, cplx<T>* buf, Twid
     if (item == 0 && threadIdx.x == 0) {
       T s = 0;
       for (int i = 0; i < npart; ++i) s += part[i];
-      lv.scal[0] = s + lv.o * xin[lv.n];
+      const T wo = xin[lv.n];
+      lv.scal[0] = s + lv.o * wo;
+      // snapshot of the input's w_o: pass 3 may update u[n] in place (Jacobi)
+      // while its other blocks still need the value the product used
+      lv.scal[1] = wo;
     }
   }
 }
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(kNT4) void k_col_inv(LevelDev<T> lv, EpiOut<T> out,
   __syncthreads();
   const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
   lds_fft<T, Cfg<T>::E4, kNT4, true>(lds, g, tw.base);
-  const T wo = out.xin[n];
+  const T wo = lv.scal[1];  // the matvec input's w_o (see k_row)
   double ss = 0.0;
   const int half = cnt >> 1;  // outputs j2 < L2/2 cover j < n
   for (int idx = threadIdx.x; idx < half; idx += kNT4) {

@@ -142,3 +142,20 @@ def test_footprint_and_strerror():
     assert fm > f[2]
     for st in (0, 1, 2, -1, -2, -3, -4):
         assert B.strerror(st) and B.strerror(st) != "unknown status"
+
+
+def test_solve_batch_argument_checks():
+    DP = ctypes.POINTER(ctypes.c_void_p)
+    assert B.lib.amg_solve_batch(0, None, None, None, None, None, None, None) == B.AMG_OK
+    assert B.lib.amg_solve_batch(-1, None, None, None, None, None, None, None) == B.AMG_EINVAL
+    assert B.lib.amg_solve_batch(2, None, None, None, None, None, None, None) == B.AMG_EINVAL
+    h = B.amg_setup(B.kernel(B.AMG_K_CONST), 0.1, 256, B.amg_default_opts(flags=B.AMG_FLAG_HOST_ONLY))
+    try:
+        hs = (ctypes.c_void_p * 1)(h.value)
+        ptrs = (ctypes.c_void_p * 1)(16)
+        ptrs2 = (ctypes.c_void_p * 1)(32)
+        tol = (ctypes.c_double * 1)(1e-10)
+        # host-only handles are refused before any device work
+        assert B.lib.amg_solve_batch(1, hs, ptrs, ptrs2, tol, None, None, None) == B.AMG_EINVAL
+    finally:
+        B.amg_destroy(h)

@@ -294,17 +294,22 @@ def test_zero_rhs_and_exact_initial_guess():
         B.amg_destroy(h)
 
 
-def test_solve_is_deterministic():
+@pytest.mark.parametrize("prec", [B.AMG_FP64, B.AMG_MIXED])
+def test_solve_is_deterministic(prec):
+    """Five solves of one problem are bitwise identical (fixed-order
+    reductions; no block reads a value another block of the same launch
+    writes)."""
     case, N = WEIGHT05, 16384
-    say("deterministic", N)
-    h = B.amg_setup(case[1], case[3], N)
+    say("deterministic", N, prec)
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(precision=prec))
     try:
         b = dev(B.amg_manufactured_rhs(case[1], case[3], N))
-        x1 = torch.zeros_like(b)
-        x2 = torch.zeros_like(b)
-        B.amg_solve(h, b, x1, 1e-10)
-        B.amg_solve(h, b, x2, 1e-10)
-        assert torch.equal(x1, x2)
+        xs = []
+        for _ in range(5):
+            x = torch.zeros_like(b)
+            B.amg_solve(h, b, x, 1e-10)
+            xs.append(x)
+        assert all(torch.equal(xs[0], x) for x in xs[1:])
     finally:
         B.amg_destroy(h)
 
@@ -327,3 +332,37 @@ def test_device_argument_errors():
                                ctypes.c_void_p(s), ctypes.byref(it), ctypes.byref(rr)) == B.AMG_EINVAL
     finally:
         B.amg_destroy(h)
+
+
+def test_solve_batch_matches_solo_solves():
+    """amg_solve_batch: instances of different N, kernel and precision run
+    concurrently; each result is bitwise the solo solve's (same kernels, same
+    order of operations per instance) and passes the oracle's residual check."""
+    say("solve_batch")
+    cases = [(CONST25, 4096, B.AMG_FP64), (WEIGHT05, 16384, B.AMG_MIXED),
+             (CONST05, 1024, B.AMG_FP64), (FRAC04, 2048, B.AMG_MIXED),
+             (CONST25, 32768, B.AMG_MIXED)]
+    hs, bs, xs, solo = [], [], [], []
+    try:
+        for case, N, prec in cases:
+            h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(precision=prec, max_iter=400))
+            hs.append(h)
+            b = dev(B.amg_manufactured_rhs(case[1], case[3], N))
+            bs.append(b)
+            x1 = torch.zeros_like(b)
+            B.amg_solve(h, b, x1, 1e-10)
+            solo.append((x1, B.amg_residual_history(h)))
+            xs.append(torch.zeros_like(b))
+        st, its, rels = B.amg_solve_batch(hs, bs, xs, [1e-10] * len(hs))
+        assert st == B.AMG_OK
+        for (case, N, prec), x, (x1, h1), it, h in zip(cases, xs, solo, its, hs):
+            assert torch.equal(x, x1), (case[0], N)
+            assert it == len(h1) - 1
+            np.testing.assert_array_equal(B.amg_residual_history(h), h1)
+            H = oracle_hier(case, N)
+            bh = host(bs[cases.index((case, N, prec))])
+            relo = np.linalg.norm(bh - H.matvec(host(x))) / np.linalg.norm(bh)
+            assert relo < 1.01e-10 + kappa_tol(H)
+    finally:
+        for h in hs:
+            B.amg_destroy(h)
