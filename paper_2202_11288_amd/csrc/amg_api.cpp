@@ -550,30 +550,19 @@ int setup_device(amg_ctx* c, hipStream_t s) {
     HIP_TRY(hipStreamSynchronize(s));
     free_since(c, mark);
   }
-  // coarsest LU (host, FP64), stored column-major for coalesced columns
+  // coarsest level: LU with partial pivoting (host, FP64), then A_c^{-1} by
+  // solving against the identity with those factors; stored column-major
   {
     const TpxLevel& Hc = c->host.back();
     const int m = (int)(2 * Hc.n + 1);
     std::vector<double> A = densify(Hc);
     std::vector<int> piv;
     if (!lu_factor(A, m, piv)) return AMG_EINVAL;
-    std::vector<double> lcm((size_t)m * m, 0.0), ucm((size_t)m * m, 0.0), dinv(m);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        if (i > j) lcm[(size_t)j * m + i] = A[(size_t)i * m + j];
-        else ucm[(size_t)j * m + i] = A[(size_t)i * m + j];
-      }
-    for (int k = 0; k < m; ++k) dinv[k] = 1.0 / A[(size_t)k * m + k];
-    std::vector<int> perm(m);
-    for (int i = 0; i < m; ++i) perm[i] = i;
-    for (int k = 0; k < m; ++k) std::swap(perm[k], perm[piv[k]]);
-    double *l, *u, *di;
-    int* pm;
-    AMG_TRY(upload(c, &l, lcm, s));
-    AMG_TRY(upload(c, &u, ucm, s));
-    AMG_TRY(upload(c, &di, dinv, s));
-    AMG_TRY(upload(c, &pm, perm, s));
-    c->lu = {m, l, u, di, pm};
+    std::vector<double> inv;
+    lu_inverse(A, m, piv, inv);
+    double* ai;
+    AMG_TRY(upload(c, &ai, inv, s));
+    c->lu = {m, ai};
   }
   AMG_TRY(dalloc(c, &c->dpart64, (size_t)maxblocks));
   AMG_TRY(dalloc(c, &c->dpart32, (size_t)maxblocks));

@@ -81,12 +81,11 @@ struct EpiOut {
   float* r32;          // EPI_OUTER: FP32 copy of the residual (may be null)
 };
 
+// Coarsest level: A_c^{-1} (column-major m x m), formed at setup from the
+// LU factors with partial pivoting.
 struct CoarseLU {
   int m;
-  const double* lcm;   // unit-lower multipliers, column-major m x m
-  const double* ucm;   // upper factor, column-major m x m
-  const double* dinv;  // 1 / U[k][k]
-  const int* perm;     // (P b)[i] = b[perm[i]]
+  const double* ainv;
 };
 
 struct SolveState {

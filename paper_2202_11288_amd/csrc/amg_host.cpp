@@ -290,6 +290,24 @@ bool lu_factor(std::vector<double>& A, int m, std::vector<int>& piv) {
   return true;
 }
 
+void lu_inverse(const std::vector<double>& LU, int m, const std::vector<int>& piv,
+                std::vector<double>& inv) {
+  inv.assign((size_t)m * m, 0.0);
+  std::vector<double> x(m);
+  for (int col = 0; col < m; ++col) {
+    std::fill(x.begin(), x.end(), 0.0);
+    x[col] = 1.0;
+    for (int k = 0; k < m; ++k) std::swap(x[k], x[piv[k]]);  // P e_col
+    for (int i = 0; i < m; ++i)                               // L y = P e
+      for (int k = 0; k < i; ++k) x[i] -= LU[(size_t)i * m + k] * x[k];
+    for (int i = m - 1; i >= 0; --i) {                        // U x = y
+      for (int k = i + 1; k < m; ++k) x[i] -= LU[(size_t)i * m + k] * x[k];
+      x[i] /= LU[(size_t)i * m + i];
+    }
+    for (int i = 0; i < m; ++i) inv[(size_t)col * m + i] = x[i];
+  }
+}
+
 void manufactured_rhs(const KernelSpec& k, int64_t N, double* out) {
   // f(x) = int_{|t|<=delta} gamma(t) (u(x) - u~(x+t)) dt, u = x^2 (1-x)^2 on
   // (0,1), u~ = 0 outside.  Constant/weighted kernels: antiderivative

@@ -52,6 +52,11 @@ std::vector<double> densify(const TpxLevel& t);
 // with i at step i.  Returns false if a zero pivot is met.
 bool lu_factor(std::vector<double>& A, int m, std::vector<int>& piv);
 
+// Inverse from the factors of lu_factor: inv (column-major m x m) solves
+// A inv = I column by column (P, unit-lower L, upper U).
+void lu_inverse(const std::vector<double>& LU, int m, const std::vector<int>& piv,
+                std::vector<double>& inv);
+
 // Manufactured right-hand side f(x_c) for u = x^2 (1-x)^2, block order.
 void manufactured_rhs(const KernelSpec& k, int64_t N, double* b);
 

@@ -359,16 +359,58 @@ constexpr size_t tail_lds_bytes(size_t elem) {
   return 2 * elem * ((size_t)lds_slots(1 << kTailLog) + (1 << kTailLog)) + elem * (kNTT / 64 + 2);
 }
 
+constexpr int kTailP = (1 << (kTailLog - 1)) / kNTT + 1;  // spectral pairs per thread (f <= L/2)
+
+// Spectra of the pairs (f, L-f), f = threadIdx.x + k*kNTT, loaded into
+// registers before the forward FFT so their latency overlaps it.
+template <typename T>
+struct TailSpec {
+  cplx<T> a1[kTailP], a2[kTailP], b1[kTailP], b2[kTailP];  // G1[f], G2[f], G1[-f], G2[-f]
+};
+
+template <typename T>
+__device__ __forceinline__ void tail_spec_load(const LevelDev<T>& lv, TailSpec<T>& sp) {
+  const int L = 1 << lv.logL;
+#pragma unroll
+  for (int k = 0; k < kTailP; ++k) {
+    const int f = threadIdx.x + k * kNTT;
+    if (f <= L / 2) {
+      const int fb = (L - f) & (L - 1);
+      if (lv.sym) {
+        sp.a1[k] = {lv.g1[f], T(0)};
+        sp.a2[k] = {T(0), lv.g2[f]};
+        sp.b1[k] = {lv.g1[fb], T(0)};
+        sp.b2[k] = {T(0), lv.g2[fb]};
+      } else {
+        const cplx<T>* G1 = reinterpret_cast<const cplx<T>*>(lv.g1);
+        const cplx<T>* G2 = reinterpret_cast<const cplx<T>*>(lv.g2);
+        sp.a1[k] = G1[f];
+        sp.a2[k] = G2[f];
+        sp.b1[k] = G1[fb];
+        sp.b2[k] = G2[fb];
+      }
+    }
+  }
+}
+
 // z holds the packed input (zero-padded); leaves y_v + i y_w_bar (without the
 // Cross terms) in z[0..n).
 template <typename T>
-__device__ void tail_fft_spectral(const LevelDev<T>& lv, const TailLds<T>& s) {
+__device__ void tail_fft_spectral(const LevelDev<T>& lv, const TailLds<T>& s, const TailSpec<T>& sp) {
   const int L = 1 << lv.logL;
   const FftGeom g{lv.logL, 0, 0, 0, kTailLog, false};
   lds_fft<T, Cfg<T>::ET, kNTT, false>(s.z, g, s.tw);
-  for (int f = threadIdx.x; f <= L / 2; f += kNTT) {
-    const int fb = (L - f) & (L - 1);
-    spec_pair(lv, s.z, f, fb, f, fb);
+#pragma unroll
+  for (int k = 0; k < kTailP; ++k) {
+    const int f = threadIdx.x + k * kNTT;
+    if (f <= L / 2) {
+      const int fb = (L - f) & (L - 1);
+      const cplx<T> za = s.z[f], zb = s.z[fb];
+      const cplx<T> ya = cmul(sp.a1[k], za) + cmul(sp.a2[k], conj(zb));
+      const cplx<T> yb = cmul(sp.b1[k], zb) + cmul(sp.b2[k], conj(za));
+      s.z[f] = ya;
+      if (fb != f) s.z[fb] = yb;
+    }
   }
   __syncthreads();
   lds_fft<T, Cfg<T>::ET, kNTT, true>(s.z, g, s.tw);
@@ -384,12 +426,18 @@ template <typename T>
 __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int epi, const T* src,
                                           T wpro, T wepi, const TailLds<T>& s) {
   const int n = lv.n, L = 1 << lv.logL;
-  T bv[kTailJ], bw[kTailJ], uv[kTailJ], uw[kTailJ];
+  TailSpec<T> sp;
+  tail_spec_load(lv, sp);
+  T bv[kTailJ], bw[kTailJ], uv[kTailJ], uw[kTailJ], pj[kTailJ], xj[kTailJ];
   T dot = 0;
 #pragma unroll
   for (int k = 0; k < kTailJ; ++k) {
     const int j = threadIdx.x + k * kNTT;
-    bv[k] = bw[k] = uv[k] = uw[k] = T(0);
+    bv[k] = bw[k] = uv[k] = uw[k] = pj[k] = xj[k] = T(0);
+    if (j < n) {
+      pj[k] = lv.p[j];
+      xj[k] = lv.xi[j];
+    }
     if (j < n) {
       const int jw = n + 1 + j;
       if (pro == TP_PRE_RESTRICT) {
@@ -433,14 +481,14 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
   }
   const T qdot = block_sum<T, kNTT>(dot, s.red);  // also publishes z and the w_o slots
   const T uo = s.red[kNTT / 64], bo = s.red[kNTT / 64 + 1];
-  tail_fft_spectral(lv, s);
+  tail_fft_spectral(lv, s, sp);
 #pragma unroll
   for (int k = 0; k < kTailJ; ++k) {
     const int j = threadIdx.x + k * kNTT;
     if (j < n) {
       const int jw = n + 1 + j;
       const cplx<T> y = s.z[j];
-      const T yv = y.x + lv.p[j] * uo, yw = y.y + lv.xi[j] * uo;
+      const T yv = y.x + pj[k] * uo, yw = y.y + xj[k] * uo;
       if (epi == TE_RESID) {
         lv.r[j] = bv[k] - yv;
         lv.r[jw] = bw[k] - yw;
@@ -458,49 +506,21 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
   __syncthreads();  // global writes visible to the next step; z and red reusable
 }
 
+// Coarsest level: u = A_c^{-1} b with the inverse formed at setup from the
+// LU factors (partial pivoting).  b is staged in LDS as FP64; thread i < m
+// forms row i from the column-major inverse (loads coalesced across threads,
+// all independent).
 template <typename T>
-__device__ void coarse_lu_solve(const CoarseLU& lu, const T* b, T* u) {
-  // wave 0 only; lane l holds x[l + 64 s], s < 4 (m <= 256)
-  const int lane = threadIdx.x;
+__device__ void coarse_solve(const CoarseLU& lu, const T* b, T* u, double* bs) {
   const int m = lu.m;
-  double x[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int i = lane + 64 * s;
-    x[s] = (i < m) ? (double)b[lu.perm[i]] : 0.0;
+  for (int i = threadIdx.x; i < m; i += kNTT) bs[i] = (double)b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += kNTT) {
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += lu.ainv[j * m + i] * bs[j];
+    u[i] = (T)acc;
   }
-  for (int k = 0; k < m - 1; ++k) {  // L y = P b (unit lower)
-    const int sk = k >> 6;
-    double xs = x[0];
-#pragma unroll
-    for (int s = 1; s < 4; ++s)
-      if (sk == s) xs = x[s];
-    const double xk = __shfl(xs, k & 63, 64);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int i = lane + 64 * s;
-      if (i > k && i < m) x[s] -= lu.lcm[k * m + i] * xk;
-    }
-  }
-  for (int k = m - 1; k >= 0; --k) {  // U x = y
-    const int sk = k >> 6;
-    double xs = x[0];
-#pragma unroll
-    for (int s = 1; s < 4; ++s)
-      if (sk == s) xs = x[s];
-    const double xk = __shfl(xs, k & 63, 64) * lu.dinv[k];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int i = lane + 64 * s;
-      if (i == k) x[s] = xk;
-      else if (i < k) x[s] -= lu.ucm[k * m + i] * xk;
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int i = lane + 64 * s;
-    if (i < m) u[i] = (T)x[s];
-  }
+  __syncthreads();
 }
 
 template <typename T>
@@ -523,8 +543,7 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
       if (src)
         for (int i = threadIdx.x; i < 2 * lc.n + 1; i += kNTT) lc.b[i] = restrict_at(src, i);
       __syncthreads();
-      if (threadIdx.x < 64) coarse_lu_solve<T>(lu, lc.b, lc.u);
-      __syncthreads();
+      coarse_solve<T>(lu, lc.b, lc.u, reinterpret_cast<double*>(s.z.p));
       continue;
     }
     int l, pro, epi;
@@ -547,7 +566,8 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
       src = levels[l + 1].u;
       wpro = wepi = wpost;
     }
-    tail_step(levels[l], pro, epi, src, wpro, wepi, s);
+    const LevelDev<T> lv = levels[l];
+    tail_step(lv, pro, epi, src, wpro, wepi, s);
   }
 }
 
@@ -577,8 +597,10 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
     }
     s.z[j] = v;
   }
+  TailSpec<T> sp;
+  tail_spec_load(lv, sp);
   const T yo = block_sum<T, kNTT>(dot, s.red) + lv.o * x[n];
-  tail_fft_spectral(lv, s);
+  tail_fft_spectral(lv, s, sp);
   const T wo = x[n];
   double ss = 0.0;
   for (int j = threadIdx.x; j < n; j += kNTT) {
@@ -829,7 +851,7 @@ template <typename T>
 hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
                               int m1, int m2, T wpre, T wpost, const CoarseLU& lu,
                               const Twiddles<T>& tw, int maxL, hipStream_t s) {
-  if (maxL > (1 << kTailLog) || lu.m > 256) return hipErrorInvalidValue;
+  if (maxL > (1 << kTailLog) || lu.m > 4 * (1 << kTailLog)) return hipErrorInvalidValue;
   const size_t lds = tail_lds_bytes(sizeof(T));
   auto k = k_tail_vcycle<T>;
   hipError_t e = set_lds(k, lds);
