@@ -49,6 +49,14 @@ class amg_stat_t(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2202_11288_amd.build`")
+    # One HIP runtime per process: torch ships its own libamdhip64, and a
+    # library loaded before torch would bind a second copy from the ROCm
+    # install, which then finds no device once torch's copy holds it.
+    # Importing torch first lets libamg.so resolve to the copy torch loaded.
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - torch is a dependency of the binding
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, D, I, I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
     DP = ctypes.POINTER(ctypes.c_double)

@@ -41,11 +41,11 @@ Plan plan_level(int64_t n) {
     p.tcols = 1;
     return p;
   }
-  // rows of L1 <= 2048 complex (two rows per workgroup in 64 KB of LDS for
-  // FP64), columns of L2 in tiles of T columns with T*L2 <= 4096
+  // rows of L1 <= kCap4/2 complex (two rows per workgroup: 64 KB of LDS for
+  // FP64), columns of L2 in tiles of T columns with T*L2 <= kCap4
   p.logL1 = std::min(11, (logL + 1) / 2);
   p.logL2 = logL - p.logL1;
-  int t = std::max(1, std::min(16, 4096 >> p.logL2));
+  int t = std::max(1, std::min(16, kCap4 >> p.logL2));
   while (t > 4 && ((1 << p.logL1) / t) < 256) t >>= 1;
   p.tcols = t;
   return p;
@@ -201,10 +201,18 @@ struct amg_ctx {
 
 namespace {
 
-#define HIP_TRY(expr)                         \
-  do {                                        \
-    hipError_t _e = (expr);                   \
-    if (_e != hipSuccess) return AMG_EHIP;    \
+// A failing HIP call returns AMG_EHIP; with AMG_DEBUG set in the environment
+// the call, its line and the HIP error name also go to stderr.
+int hip_fail(hipError_t e, const char* expr, int line) {
+  static const bool dbg = std::getenv("AMG_DEBUG") != nullptr;
+  if (dbg) std::fprintf(stderr, "amg: %s failed at line %d: %s\n", expr, line, hipGetErrorName(e));
+  return AMG_EHIP;
+}
+
+#define HIP_TRY(expr)                                             \
+  do {                                                            \
+    hipError_t _e = (expr);                                       \
+    if (_e != hipSuccess) return hip_fail(_e, #expr, __LINE__);   \
   } while (0)
 
 template <typename T>
@@ -668,9 +676,10 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
     }
   }
   if (!c->host_only) {
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    const hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
       delete c;
-      return AMG_EHIP;
+      return hip_fail(e, "hipGetDevice", __LINE__);
     }
     st = setup_device(c, (hipStream_t)stream);
     if (st != AMG_OK) {

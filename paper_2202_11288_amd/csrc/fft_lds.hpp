@@ -24,6 +24,20 @@ template <typename T>
 __device__ __forceinline__ cplx<T> conj(cplx<T> a) { return {a.x, -a.y}; }
 template <typename T>
 __device__ __forceinline__ cplx<T> scale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+// Global loads / stores of one complex value as a single 2-wide vector access
+// (keeps register staging arrays of complex values in registers).
+template <typename T>
+__device__ __forceinline__ cplx<T> ldg(const cplx<T>* p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = *reinterpret_cast<const V*>(p);
+  return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void stg(cplx<T>* p, cplx<T> a) {
+  using V = T __attribute__((ext_vector_type(2)));
+  *reinterpret_cast<V*>(p) = V{a.x, a.y};
+}
+
 // multiply by -i (forward) or +i (inverse)
 template <typename T, bool INV>
 __device__ __forceinline__ cplx<T> rot(cplx<T> a) {
@@ -146,6 +160,37 @@ __device__ __forceinline__ void twiddle_set(const cplx<T>* __restrict__ tw, int 
   }
 }
 
+// a[r] *= w_r (conjugated for the inverse), r = 1..15, with the same products
+// as twiddle_set formed just before use (conj(x) conj(y) = conj(xy) exactly),
+// so that at most eight twiddles are live at a time.
+template <typename T, bool INV>
+__device__ __forceinline__ void twiddle16_apply(cplx<T> (&a)[16], const cplx<T>* __restrict__ tw,
+                                                int step) {
+  cplx<T> w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step], w8 = tw[8 * step];
+  if (INV) {
+    w1 = conj(w1);
+    w2 = conj(w2);
+    w4 = conj(w4);
+    w8 = conj(w8);
+  }
+  const cplx<T> w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+  a[1] = cmul(a[1], w1);
+  a[2] = cmul(a[2], w2);
+  a[3] = cmul(a[3], w3);
+  a[4] = cmul(a[4], w4);
+  a[5] = cmul(a[5], w5);
+  a[6] = cmul(a[6], w6);
+  a[7] = cmul(a[7], w7);
+  a[8] = cmul(a[8], w8);
+  a[9] = cmul(a[9], cmul(w1, w8));
+  a[10] = cmul(a[10], cmul(w2, w8));
+  a[11] = cmul(a[11], cmul(w3, w8));
+  a[12] = cmul(a[12], cmul(w4, w8));
+  a[13] = cmul(a[13], cmul(w5, w8));
+  a[14] = cmul(a[14], cmul(w6, w8));
+  a[15] = cmul(a[15], cmul(w7, w8));
+}
+
 // ---- Stockham FFT over signals in LDS ---------------------------------------
 //
 // S = 2^logS signals of length M = 2^logM; element i of signal s lives at
@@ -209,7 +254,7 @@ __device__ __forceinline__ void stockham_pass(Lds<T> lds, const FftGeom& g, int 
 // Full FFT (forward if !INV) of the signals in LDS, natural order in and out.
 // A single radix-2/4/8 pass first (no twiddles), then radix RMAX passes.
 template <typename T, int E, int NT, bool INV>
-__device__ void lds_fft(Lds<T> lds, const FftGeom& g, const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft(Lds<T> lds, const FftGeom& g, const cplx<T>* __restrict__ tw) {
   constexpr int RMAX = E >= 16 ? 16 : E;
   constexpr int LR = RMAX == 16 ? 4 : (RMAX == 8 ? 3 : (RMAX == 4 ? 2 : 1));
   const int rem = g.logM % LR;
@@ -228,6 +273,50 @@ __device__ void lds_fft(Lds<T> lds, const FftGeom& g, const cplx<T>* __restrict_
     stockham_pass<T, RMAX, E, NT, INV>(lds, g, logNs, tw);
     logNs += LR;
   }
+}
+
+// FFT of the signals in LDS with the first and last passes on registers.
+// Each thread owns one radix-16 butterfly of the last pass: signal s, index
+// j0 < M/16 (M = 2^logM >= 32).  On entry a[e] = x_s[j0 + e M/16] (natural
+// order), on exit a[e] = X_s[j0 + e M/16]; the NT threads of the workgroup
+// must cover every (s, j0) pair exactly once.  The first pass (radix
+// 2^(logM mod 4), or 16) works on the registers and writes LDS, the middle
+// radix-16 passes stay in LDS, the last one reads LDS back into registers.
+// No barrier at the end: synchronise before the LDS region is written again.
+template <typename T, int R0, bool INV>
+__device__ __forceinline__ void first_pass_regs(cplx<T> (&a)[16], Lds<T> lds, const FftGeom& g,
+                                                int base, int j0, int q) {
+  constexpr int NB = 16 / R0;
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    cplx<T> b[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) b[r] = a[e + r * NB];  // x[j + r M/R0], j = j0 + e M/16
+    dft<T, R0, INV>(b);
+    const int j = j0 + (e << q);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) lds[base + ((j * R0 + r) << g.loges)] = b[r];
+  }
+}
+
+template <typename T, int NT, bool INV>
+__device__ __forceinline__ void fft_reg16(cplx<T> (&a)[16], Lds<T> lds, const FftGeom& g, int s,
+                                          int j0, const cplx<T>* __restrict__ tw) {
+  const int q = g.logM - 4;  // log2(M/16)
+  const int base = s << g.logss;
+  const int rem = g.logM & 3;
+  if (rem == 1) first_pass_regs<T, 2, INV>(a, lds, g, base, j0, q);
+  else if (rem == 2) first_pass_regs<T, 4, INV>(a, lds, g, base, j0, q);
+  else if (rem == 3) first_pass_regs<T, 8, INV>(a, lds, g, base, j0, q);
+  else first_pass_regs<T, 16, INV>(a, lds, g, base, j0, q);
+  __syncthreads();
+  for (int logNs = rem == 0 ? 4 : rem; logNs < q; logNs += 4)
+    stockham_pass<T, 16, 16, NT, INV>(lds, g, logNs, tw);
+  // last pass, Ns = M/16: butterfly j0 (k = j0), outputs j0 + r M/16
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a[r] = lds[base + ((j0 + (r << q)) << g.loges)];
+  twiddle16_apply<T, INV>(a, tw, j0 << (g.logtw - g.logM));
+  dft<T, 16, INV>(a);
 }
 
 // Deterministic reduction of one value per thread over a workgroup of NT

@@ -1,0 +1,719 @@
+// Four-step FFT passes of a large level's Toeplitz-plus-Cross matvec (Sec. 3.2,
+// eq. (ccs3.4), eq. (split01)): L = L1 * L2 points, three HBM passes.
+//   pass 1 (k_col_fwd): vector formation fused in front (smoothing start,
+//            restriction, prolongation, refinement update), column FFTs of
+//            length L2, four-step twiddle;
+//   pass 2 (k_row):     for a row pair (k2, L2-k2): row FFTs, the 2x2 spectral
+//            product (bins f and -f sit in the paired rows), inverse row FFTs,
+//            inverse twiddle;
+//   pass 3 (k_col_inv): inverse column FFTs, Cross terms, residual / Jacobi /
+//            output epilogue.
+// A workgroup holds at most kCap4 complex values (a tile of T columns or a
+// row pair).  The per-thread element counts are template parameters (EPT
+// column elements, KR row elements per row) so that every global load of a
+// pass is issued in compile-time batches into registers, with clamped
+// addresses and masked values, before any of them is used.  Internal header.
+#pragma once
+
+#include "kernel_common.hpp"
+
+namespace amg {
+
+// Elements per thread of the LDS FFTs (a full tile or row pair).
+constexpr int kE4 = kCap4 / kNT4;
+
+// ---------------------------------------------------------------------------
+// Pass 1.  Thread tid owns column j1 = c0 + (tid mod T) at rows i0 + e*di.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, int EPT>
+__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* part) {
+  extern __shared__ unsigned char smem_raw[];
+  const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
+  __shared__ T red[kNT4 / 64];
+  const int n = lv.n;
+  const int L = 1 << lv.logL;
+  const int logTC = ilog2(lv.tcols);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
+  const int i0 = threadIdx.x >> logTC, di = kNT4 >> logTC;
+  constexpr int CH = EPT < 8 ? EPT : 8;  // elements per load batch
+  // the w_o entry (tile 0, thread 0): its operands are fetched first
+  constexpr bool kWo = MODE != COL_SETUP && MODE != COL_MV;
+  const bool wo_thread = kWo && tile == 0 && threadIdx.x == 0;
+  T wo0 = 0, wo1 = 0, wo2 = 0;
+  if (wo_thread) {
+    if constexpr (MODE == COL_PRE) {
+      wo0 = lv.b[n];
+    } else if constexpr (MODE == COL_PRE_RESTRICT) {
+      wo0 = in.x[2 * n];
+      wo1 = in.x[2 * n + 1];
+      wo2 = in.x[2 * n + 2];
+    } else if constexpr (MODE == COL_PROLONG) {
+      wo0 = lv.u[n];
+      wo1 = prolong_at(in.x, n, n);
+    } else if constexpr (MODE == COL_OUTER_UPDATE) {
+      wo0 = (T)in.xo[n];
+      wo1 = in.e_is_float ? (T)((const float*)in.e)[n] : (T)((const double*)in.e)[n];
+    }
+  }
+  T dot = 0;
+  cplx<T> a[EPT];  // formed vector at rows i0 + e*di of column j1
+#pragma unroll
+  for (int e0 = 0; e0 < EPT; e0 += CH) {
+    int jj[CH];
+    bool ok[CH];
+    T r0[CH], r1[CH], r2[CH], r3[CH], r4[CH], r5[CH], qq[CH], zz[CH];
+    // (a) loads only
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int j = j1 + ((i0 + (e0 + c) * di) << lv.logL1);
+      jj[c] = j;
+      if constexpr (MODE == COL_SETUP) {
+        ok[c] = true;
+        r0[c] = (T)circ_col(in.gx, n, L, j);
+        r1[c] = (T)circ_col(in.gy, n, L, j);
+      } else {
+        ok[c] = j < n;
+        const int js = ok[c] ? j : 0, jw = n + 1 + js;
+        qq[c] = lv.q[js];
+        zz[c] = lv.zeta[js];
+        if constexpr (MODE == COL_MV) {
+          r0[c] = in.x[js];
+          r1[c] = in.x[jw];
+        } else if constexpr (MODE == COL_PRE) {
+          r0[c] = lv.b[js];
+          r1[c] = lv.b[jw];
+        } else if constexpr (MODE == COL_PRE_RESTRICT) {
+          r0[c] = in.x[2 * js];
+          r1[c] = in.x[2 * js + 1];
+          r2[c] = in.x[2 * js + 2];
+          r3[c] = in.x[2 * jw];
+          r4[c] = in.x[2 * jw + 1];
+          r5[c] = in.x[2 * jw + 2];
+        } else if constexpr (MODE == COL_PROLONG) {
+          // coarse vector length = n (2 n_c + 1 = n)
+          int lo, hi;
+          bool ml, mh;
+          r0[c] = lv.u[js];
+          r1[c] = lv.u[jw];
+          prolong_idx(js, n, lo, hi, ml, mh);
+          r2[c] = in.x[lo];
+          r3[c] = in.x[hi];
+          r2[c] = ml ? r2[c] : T(0);
+          r3[c] = mh ? r3[c] : T(0);
+          prolong_idx(jw, n, lo, hi, ml, mh);
+          r4[c] = in.x[lo];
+          r5[c] = in.x[hi];
+          r4[c] = ml ? r4[c] : T(0);
+          r5[c] = mh ? r5[c] : T(0);
+        } else {  // COL_OUTER_UPDATE (T = double)
+          r0[c] = (T)in.xo[js];
+          r1[c] = (T)in.xo[jw];
+        }
+      }
+    }
+    if constexpr (MODE == COL_OUTER_UPDATE) {
+      if (in.e_is_float) {
+        const float* ef = static_cast<const float*>(in.e);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int js = ok[c] ? jj[c] : 0;
+          r2[c] = (T)ef[js];
+          r3[c] = (T)ef[n + 1 + js];
+        }
+      } else {
+        const double* ed = static_cast<const double*>(in.e);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int js = ok[c] ? jj[c] : 0;
+          r2[c] = (T)ed[js];
+          r3[c] = (T)ed[n + 1 + js];
+        }
+      }
+    }
+    // (b) vector formation, stores, Cross dot product, LDS
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int j = jj[c], jw = n + 1 + j;
+      T v = r0[c], w = r1[c];
+      if constexpr (MODE == COL_PRE || MODE == COL_PRE_RESTRICT) {
+        if constexpr (MODE == COL_PRE_RESTRICT) {
+          const T bv = T(0.25) * (r0[c] + T(2) * r1[c] + r2[c]);
+          const T bw = T(0.25) * (r3[c] + T(2) * r4[c] + r5[c]);
+          if (ok[c]) {
+            lv.b[j] = bv;
+            lv.b[jw] = bw;
+          }
+          v = bv;
+          w = bw;
+        }
+        v = in.omega * v / lv.dv;
+        w = in.omega * w / lv.dw;
+        if (ok[c]) {
+          lv.u[j] = v;
+          lv.u[jw] = w;
+        }
+      } else if constexpr (MODE == COL_PROLONG) {
+        v = r0[c] + T(0.5) * (r2[c] + r3[c]);
+        w = r1[c] + T(0.5) * (r4[c] + r5[c]);
+        if (ok[c]) {
+          lv.u[j] = v;
+          lv.u[jw] = w;
+        }
+      } else if constexpr (MODE == COL_OUTER_UPDATE) {
+        v = r0[c] + r2[c];
+        w = r1[c] + r3[c];
+        if (ok[c]) {
+          in.xo[j] = v;
+          in.xo[jw] = w;
+        }
+      }
+      if (!ok[c]) v = w = T(0);
+      if constexpr (MODE != COL_SETUP) dot += qq[c] * v + zz[c] * w;
+      a[e0 + c] = cplx<T>{v, w};
+    }
+  }
+  if (wo_thread) {
+    if constexpr (MODE == COL_PRE) {
+      lv.u[n] = in.omega * wo0 / lv.o;
+    } else if constexpr (MODE == COL_PRE_RESTRICT) {
+      const T bo = T(0.25) * (wo0 + T(2) * wo1 + wo2);
+      lv.b[n] = bo;
+      lv.u[n] = in.omega * bo / lv.o;
+    } else if constexpr (MODE == COL_PROLONG) {
+      lv.u[n] = wo0 + wo1;
+    } else if constexpr (MODE == COL_OUTER_UPDATE) {
+      in.xo[n] = (double)wo0 + (double)wo1;
+    }
+  }
+  if constexpr (MODE != COL_SETUP) {
+    const T s = block_sum<T, kNT4>(dot, red);
+    if (threadIdx.x == 0) part[tile] = s;
+  }
+  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  if constexpr (EPT == 16) {
+    // the thread's rows i0 + e*di are the positions j0 + e*L2/16 of its
+    // last-pass butterfly (j0 = i0): first and last passes on registers
+    fft_reg16<T, kNT4, false>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * kNT4] = a[e];
+    __syncthreads();
+    lds_fft<T, kE4, kNT4, false>(lds, g, tw.base);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) a[e] = lds[(int)threadIdx.x + e * kNT4];
+  }
+  twiddle_run_mul<T, EPT, false>(tw, lv.logL, j1 * i0, j1 * di, a);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) stg(buf + j1 + ((i0 + e * di) << lv.logL1), a[e]);
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2.  Row pair (ka, kb) = (item, L2-item), or (0, L2/2) for item 0; the
+// thread owns elements t = tid + e*kNT4 of both rows (KR of each; KR = 1 also
+// covers L1 < kNT4).  Block 0 also finishes the w_o row
+// y_o = q.v + o w_o + zeta.w_bar from pass 1's partial sums.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void spec_pair(const LevelDev<T>& lv, Lds<T> lds, int la, int lb,
+                                          int ga, int gb) {
+  const cplx<T> za = lds[la], zb = lds[lb];
+  cplx<T> ya, yb;
+  if (lv.sym) {
+    const T g1a = lv.g1[ga], g2a = lv.g2[ga], g1b = lv.g1[gb], g2b = lv.g2[gb];
+    // G1 z + (i g2) conj(z')
+    ya = {g1a * za.x + g2a * zb.y, g1a * za.y + g2a * zb.x};
+    yb = {g1b * zb.x + g2b * za.y, g1b * zb.y + g2b * za.x};
+  } else {
+    const cplx<T>* G1 = reinterpret_cast<const cplx<T>*>(lv.g1);
+    const cplx<T>* G2 = reinterpret_cast<const cplx<T>*>(lv.g2);
+    ya = cmul(G1[ga], za) + cmul(G2[ga], conj(zb));
+    yb = cmul(G1[gb], zb) + cmul(G2[gb], conj(za));
+  }
+  lds[la] = ya;
+  if (la != lb) lds[lb] = yb;
+}
+
+// The y_o row of the product, in block 0: pass 1's partial sums of
+// q.v + zeta.w_bar (fetched by all threads at the start, reduced in a fixed
+// order at the end) plus o w_o, and a snapshot of the input's w_o (pass 3 may
+// update u[n] in place (Jacobi) while its other blocks still need the value
+// the product used).
+template <typename T>
+__device__ __forceinline__ T wo_partial(const T* part, int npart) {
+  T v = 0;
+  for (int i = threadIdx.x; i < npart; i += kNT4) v += part[i];
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ void finish_wo(const LevelDev<T>& lv, T v, T* red, const T* xin) {
+  const T s = block_sum<T, kNT4>(v, red);
+  if (threadIdx.x == 0) {
+    const T wo = xin[lv.n];
+    lv.scal[0] = s + lv.o * wo;
+    lv.scal[1] = wo;
+  }
+}
+
+// Row pair with L1 = 16 kNT4 / 2 (each thread owns one radix-16 butterfly of
+// the last pass: row s = tid / (L1/16), j0 = tid mod (L1/16), positions
+// p = j0 + e L1/16).  Loads feed the first FFT pass directly; the spectral
+// product exchanges the partner bins through LDS once; the last inverse pass
+// feeds the twiddle and the stores.
+template <typename T, bool SPECTRAL, bool SYM>
+__device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds, cplx<T>* buf,
+                                              const Twiddles<T>& tw, int item) {
+  constexpr int Q = 16 * kNT4 / 2 / 16;  // L1/16 butterflies per row
+  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2;
+  const int tid = threadIdx.x;
+  const int s = tid / Q, j0 = tid % Q;
+  const int k2 = item == 0 ? (s == 0 ? 0 : L2 / 2) : (s == 0 ? item : L2 - item);
+  const int row = k2 << lv.logL1;
+  cplx<T> a[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) a[e] = ldg(buf + row + j0 + e * Q);
+  // SPD spectra at the thread's positions: FP32 fetches them under the
+  // forward FFT; FP64 right after it (holding them across the FFT would spill)
+  constexpr bool kEarly = sizeof(T) == 4;
+  T g1[16], g2[16];
+  auto load_spec = [&]() {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      g1[e] = lv.g1[row + j0 + e * Q];
+      g2[e] = lv.g2[row + j0 + e * Q];
+    }
+  };
+  if (kEarly && SPECTRAL && SYM) load_spec();
+  const FftGeom g{lv.logL1, 1, lv.logL1, 0, kTwLog, false};
+  fft_reg16<T, kNT4, false>(a, lds, g, s, j0, tw.base);
+  if (!kEarly && SPECTRAL && SYM) load_spec();
+  if constexpr (!SPECTRAL) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) stg(buf + row + j0 + e * Q, a[e]);
+  } else {
+    // bin f = k2 + L2 k1 pairs with -f: (kb, L1-1-k1) for item != 0; within
+    // row 0 with (L1-k1) mod L1 and within row L2/2 with L1-1-k1 for item 0
+    __syncthreads();  // last-pass LDS reads done before the exchange writes
+#pragma unroll
+    for (int e = 0; e < 16; ++e) lds[(s << lv.logL1) + j0 + e * Q] = a[e];
+    __syncthreads();
+    auto partner = [&](int e) {
+      const int p = j0 + e * Q;
+      int slot;
+      if (item != 0) slot = s == 0 ? L1 + (L1 - 1 - p) : (L1 - 1 - p);
+      else slot = s == 0 ? ((L1 - p) & (L1 - 1)) : L1 + (L1 - 1 - p);
+      return lds[slot];
+    };
+    if constexpr (SYM) {
+      // G1 real, G2 = i g2: Y = g1 z + i g2 conj(z')
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const cplx<T> zp = partner(e);
+        a[e] = {g1[e] * a[e].x + g2[e] * zp.y, g1[e] * a[e].y + g2[e] * zp.x};
+      }
+    } else {
+      const cplx<T>* G1 = reinterpret_cast<const cplx<T>*>(lv.g1);
+      const cplx<T>* G2 = reinterpret_cast<const cplx<T>*>(lv.g2);
+#pragma unroll
+      for (int e0 = 0; e0 < 16; e0 += 4) {
+        cplx<T> h1[4], h2[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          h1[c] = ldg(G1 + row + j0 + (e0 + c) * Q);
+          h2[c] = ldg(G2 + row + j0 + (e0 + c) * Q);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          a[e0 + c] = cmul(h1[c], a[e0 + c]) + cmul(h2[c], conj(partner(e0 + c)));
+      }
+    }
+    __syncthreads();  // partner reads done before the inverse FFT writes LDS
+    fft_reg16<T, kNT4, true>(a, lds, g, s, j0, tw.base);
+    twiddle_run_mul<T, 16, true>(tw, lv.logL, j0 * k2, Q * k2, a);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) stg(buf + row + j0 + e * Q, a[e]);
+  }
+}
+
+template <typename T, bool SPECTRAL, bool SYM, int KR>
+__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
+  extern __shared__ unsigned char smem_raw[];
+  const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
+  __shared__ T red[kNT4 / 64];
+  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2;
+  const int item = blockIdx.x;
+  const int tid = threadIdx.x;
+  const T wpart = (SPECTRAL && item == 0) ? wo_partial(part, npart) : T(0);
+  if constexpr (KR == 8) {
+    row_pair_regs<T, SPECTRAL, SYM>(lv, lds, buf, tw, item);
+    if (SPECTRAL && item == 0) finish_wo(lv, wpart, red, xin);
+    return;
+  }
+  const int ka = item == 0 ? 0 : item;
+  const int kb = item == 0 ? L2 / 2 : L2 - item;
+  const int ra = ka << lv.logL1, rb = kb << lv.logL1;
+  const bool act = KR > 1 || tid < L1;  // KR == 1: rows shorter than the workgroup
+  const int t0 = act ? tid : 0;
+  {
+    cplx<T> za[KR], zb[KR];
+#pragma unroll
+    for (int e = 0; e < KR; ++e) {
+      za[e] = ldg(buf + ra + t0 + e * kNT4);
+      zb[e] = ldg(buf + rb + t0 + e * kNT4);
+    }
+    if (act) {
+#pragma unroll
+      for (int e = 0; e < KR; ++e) {
+        lds[t0 + e * kNT4] = za[e];
+        lds[L1 + t0 + e * kNT4] = zb[e];
+      }
+    }
+  }
+  // SPD spectra of this thread's pairs (t, L1-1-t), fetched under the FFT
+  T g1a[KR], g2a[KR], g1b[KR], g2b[KR];
+  const bool pre = SPECTRAL && SYM && item != 0;
+  if (pre) {
+#pragma unroll
+    for (int e = 0; e < KR; ++e) {
+      const int t = t0 + e * kNT4;
+      g1a[e] = lv.g1[ra + t];
+      g2a[e] = lv.g2[ra + t];
+      g1b[e] = lv.g1[rb + (L1 - 1 - t)];
+      g2b[e] = lv.g2[rb + (L1 - 1 - t)];
+    }
+  }
+  __syncthreads();
+  const FftGeom g{lv.logL1, 1, lv.logL1, 0, kTwLog, false};
+  lds_fft<T, kE4, kNT4, false>(lds, g, tw.base);
+  if constexpr (!SPECTRAL) {
+    if (act) {
+#pragma unroll
+      for (int e = 0; e < KR; ++e) {
+        buf[ra + t0 + e * kNT4] = lds[t0 + e * kNT4];
+        buf[rb + t0 + e * kNT4] = lds[L1 + t0 + e * kNT4];
+      }
+    }
+    return;
+  } else {
+    if (pre) {
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < KR; ++e) {
+          const int la = t0 + e * kNT4, lb = L1 + (L1 - 1 - la);
+          const cplx<T> za = lds[la], zb = lds[lb];
+          lds[la] = {g1a[e] * za.x + g2a[e] * zb.y, g1a[e] * za.y + g2a[e] * zb.x};
+          lds[lb] = {g1b[e] * zb.x + g2b[e] * za.y, g1b[e] * zb.y + g2b[e] * za.x};
+        }
+      }
+    } else if (!SYM && item != 0) {
+      // general spectra: (ka, k1) pairs with (kb, L1-1-k1); batches of 4 pairs
+      const cplx<T>* G1 = reinterpret_cast<const cplx<T>*>(lv.g1);
+      const cplx<T>* G2 = reinterpret_cast<const cplx<T>*>(lv.g2);
+      constexpr int CB = KR < 4 ? KR : 4;
+#pragma unroll
+      for (int e0 = 0; e0 < KR; e0 += CB) {
+        cplx<T> a1[CB], a2[CB], b1[CB], b2[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const int t = t0 + (e0 + c) * kNT4;
+          a1[c] = ldg(G1 + ra + t);
+          a2[c] = ldg(G2 + ra + t);
+          b1[c] = ldg(G1 + rb + (L1 - 1 - t));
+          b2[c] = ldg(G2 + rb + (L1 - 1 - t));
+        }
+        if (act) {
+#pragma unroll
+          for (int c = 0; c < CB; ++c) {
+            const int la = t0 + (e0 + c) * kNT4, lb = L1 + (L1 - 1 - la);
+            const cplx<T> za = lds[la], zb = lds[lb];
+            lds[la] = cmul(a1[c], za) + cmul(a2[c], conj(zb));
+            lds[lb] = cmul(b1[c], zb) + cmul(b2[c], conj(za));
+          }
+        }
+      }
+    } else {
+      // row 0: k1 pairs with (L1-k1) mod L1; row L2/2: k1 pairs with L1-1-k1
+      const int npair0 = L1 / 2 + 1;
+      for (int t = tid; t < npair0 + L1 / 2; t += kNT4) {
+        if (t < npair0) {
+          const int tb = (L1 - t) & (L1 - 1);
+          spec_pair(lv, lds, t, tb, ra + t, ra + tb);
+        } else {
+          const int k1 = t - npair0;
+          spec_pair(lv, lds, L1 + k1, L1 + (L1 - 1 - k1), rb + k1, rb + (L1 - 1 - k1));
+        }
+      }
+    }
+    __syncthreads();
+    lds_fft<T, kE4, kNT4, true>(lds, g, tw.base);
+    cplx<T> wa[KR], wb[KR];
+    twiddle_run<T, KR>(tw, lv.logL, t0 * ka, kNT4 * ka, wa);
+    twiddle_run<T, KR>(tw, lv.logL, t0 * kb, kNT4 * kb, wb);
+    if (act) {
+#pragma unroll
+      for (int e = 0; e < KR; ++e) {
+        const int t = t0 + e * kNT4;
+        buf[ra + t] = cmul(lds[t], conj(wa[e]));
+        buf[rb + t] = cmul(lds[L1 + t], conj(wb[e]));
+      }
+    }
+    if (item == 0) finish_wo(lv, wpart, red, xin);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3.  Same ownership as pass 1; the outputs j < n are the rows
+// j2 < L2/2, i.e. e < EPT/2 (EPT = 1: threads tid < kNT4/2).  The epilogue's
+// operands are fetched before the FFT so their latency overlaps it.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, int EPT>
+__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw, double* part) {
+  extern __shared__ unsigned char smem_raw[];
+  const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
+  __shared__ double red[kNT4 / 64];
+  constexpr int KH = EPT > 1 ? EPT / 2 : 1;
+  const int n = lv.n;
+  const int logTC = ilog2(lv.tcols);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
+  const int i0 = threadIdx.x >> logTC, di = kNT4 >> logTC;
+  cplx<T> a[EPT];  // rows i0 + e*di of column j1
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) a[e] = ldg(buf + j1 + ((i0 + e * di) << lv.logL1));
+  // the w_o row (tile 0, thread 0): its operands are fetched first
+  const bool wo_thread = tile == 0 && threadIdx.x == 0;
+  T yo = 0, wb = 0, wu = 0;
+  double wbo = 0.0;
+  if (wo_thread) {
+    yo = lv.scal[0];
+    if constexpr (MODE == EPI_RESID || MODE == EPI_SMOOTH) wb = lv.b[n];
+    if constexpr (MODE == EPI_SMOOTH) wu = lv.u[n];
+    if constexpr (MODE == EPI_OUTER) wbo = out.bo[n];
+  }
+  bool ok[KH];
+  int jj[KH];
+  T pp[KH], xx[KH], b0[KH], b1[KH], u0[KH], u1[KH];
+  double o0[KH], o1[KH];
+#pragma unroll
+  for (int e = 0; e < KH; ++e) {
+    const int j = j1 + ((i0 + e * di) << lv.logL1);
+    ok[e] = (EPT > 1 || (int)threadIdx.x < kNT4 / 2) && j < n;
+    jj[e] = j;
+    const int js = ok[e] ? j : 0, jw = n + 1 + js;
+    pp[e] = lv.p[js];
+    xx[e] = lv.xi[js];
+    if constexpr (MODE == EPI_RESID || MODE == EPI_SMOOTH) {
+      b0[e] = lv.b[js];
+      b1[e] = lv.b[jw];
+    }
+    if constexpr (MODE == EPI_SMOOTH && (sizeof(T) == 4 || EPT < 16)) {
+      u0[e] = lv.u[js];
+      u1[e] = lv.u[jw];
+    }
+    if constexpr (MODE == EPI_OUTER) {
+      o0[e] = out.bo[js];
+      o1[e] = out.bo[jw];
+    }
+  }
+  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  if constexpr (EPT == 16) {
+    fft_reg16<T, kNT4, true>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * kNT4] = a[e];
+    __syncthreads();
+    lds_fft<T, kE4, kNT4, true>(lds, g, tw.base);
+#pragma unroll
+    for (int e = 0; e < KH; ++e) a[e] = lds[(int)threadIdx.x + e * kNT4];
+  }
+  if constexpr (MODE == EPI_SMOOTH && sizeof(T) == 8 && EPT == 16) {
+    // FP64 full tiles: the iterate is fetched after the FFT (register budget)
+#pragma unroll
+    for (int e = 0; e < KH; ++e) {
+      const int js = ok[e] ? jj[e] : 0;
+      u0[e] = lv.u[js];
+      u1[e] = lv.u[n + 1 + js];
+    }
+  }
+  const T wo = lv.scal[1];  // the matvec input's w_o (see k_row)
+  double ss = 0.0;
+#pragma unroll
+  for (int e = 0; e < KH; ++e) {
+    if (!ok[e]) continue;
+    const int j = jj[e], jw = n + 1 + j;
+    const cplx<T> y = a[e];
+    const T yv = y.x + pp[e] * wo;
+    const T yw = y.y + xx[e] * wo;
+    if constexpr (MODE == EPI_MV) {
+      out.y[j] = yv;
+      out.y[jw] = yw;
+    } else if constexpr (MODE == EPI_RESID) {
+      lv.r[j] = b0[e] - yv;
+      lv.r[jw] = b1[e] - yw;
+    } else if constexpr (MODE == EPI_SMOOTH) {
+      lv.u[j] = u0[e] + out.omega * (b0[e] - yv) / lv.dv;
+      lv.u[jw] = u1[e] + out.omega * (b1[e] - yw) / lv.dw;
+    } else {  // EPI_OUTER
+      const double rv = o0[e] - (double)yv, rw = o1[e] - (double)yw;
+      out.ro[j] = rv;
+      out.ro[jw] = rw;
+      if (out.r32) {
+        out.r32[j] = (float)rv;
+        out.r32[jw] = (float)rw;
+      }
+      ss += rv * rv + rw * rw;
+    }
+  }
+  if (wo_thread) {
+    if constexpr (MODE == EPI_MV) {
+      out.y[n] = yo;
+    } else if constexpr (MODE == EPI_RESID) {
+      lv.r[n] = wb - yo;
+    } else if constexpr (MODE == EPI_SMOOTH) {
+      lv.u[n] = wu + out.omega * (wb - yo) / lv.o;
+    } else {
+      const double ro = wbo - (double)yo;
+      out.ro[n] = ro;
+      if (out.r32) out.r32[n] = (float)ro;
+      ss += ro * ro;
+    }
+  }
+  if constexpr (MODE == EPI_OUTER) {
+    const double s = block_sum<double, kNT4>(ss, red);
+    if (threadIdx.x == 0) part[tile] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers: the level geometry picks the instance (EPT = T L2 / kNT4,
+// KR = max(1, L1 / kNT4)); checked against the kernels' assumptions here.
+// ---------------------------------------------------------------------------
+inline bool col_geom_ok(int logL1, int logL2, int tcols, int* ept) {
+  const int cnt = tcols << logL2;
+  if (tcols < 1 || (tcols & (tcols - 1)) || tcols > kNT4 || (1 << logL1) % tcols) return false;
+  if (cnt % kNT4 || cnt > kCap4) return false;
+  *ept = cnt / kNT4;
+  return true;
+}
+
+template <typename T, int MODE>
+hipError_t col_fwd_ept(int ept, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
+                       const ColIn<T>& in, cplx<T>* buf, const Twiddles<T>& tw, T* part) {
+  switch (ept) {
+    case 1: return launch_lds(k_col_fwd<T, MODE, 1>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 2: return launch_lds(k_col_fwd<T, MODE, 2>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 4: return launch_lds(k_col_fwd<T, MODE, 4>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 8: return launch_lds(k_col_fwd<T, MODE, 8>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 16: return launch_lds(k_col_fwd<T, MODE, 16>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int MODE>
+hipError_t col_inv_ept(int ept, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
+                       const EpiOut<T>& out, const cplx<T>* buf, const Twiddles<T>& tw,
+                       double* part) {
+  switch (ept) {
+    case 1: return launch_lds(k_col_inv<T, MODE, 1>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 2: return launch_lds(k_col_inv<T, MODE, 2>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 4: return launch_lds(k_col_inv<T, MODE, 4>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 8: return launch_lds(k_col_inv<T, MODE, 8>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 16: return launch_lds(k_col_inv<T, MODE, 16>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, bool SPECTRAL, bool SYM>
+hipError_t row_kr(int kr, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
+                  cplx<T>* buf, const Twiddles<T>& tw, const T* part, int npart, const T* xin) {
+  switch (kr) {
+    case 1: return launch_lds(k_row<T, SPECTRAL, SYM, 1>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    case 2: return launch_lds(k_row<T, SPECTRAL, SYM, 2>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    case 4: return launch_lds(k_row<T, SPECTRAL, SYM, 4>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    case 8: return launch_lds(k_row<T, SPECTRAL, SYM, 8>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Modes built for FP32 (the V-cycle) and FP64 (everything).
+template <typename T>
+constexpr bool col_mode_built(int mode) {
+  return sizeof(T) == 8 || mode == COL_MV || mode == COL_PRE || mode == COL_PRE_RESTRICT ||
+         mode == COL_PROLONG;
+}
+template <typename T>
+constexpr bool epi_mode_built(int mode) {
+  return sizeof(T) == 8 || mode == EPI_RESID || mode == EPI_SMOOTH;
+}
+
+template <typename T>
+hipError_t launch_col_fwd(int mode, const LevelDev<T>& lv, const ColIn<T>& in, cplx<T>* buf,
+                               const Twiddles<T>& tw, T* part, hipStream_t s) {
+  int ept;
+  if (!col_geom_ok(lv.logL1, lv.logL2, lv.tcols, &ept) || !col_mode_built<T>(mode))
+    return hipErrorInvalidValue;
+  const int grid = col_blocks(lv.logL1, lv.tcols);
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(ept * kNT4);
+  switch (mode) {
+    case COL_MV: return col_fwd_ept<T, COL_MV>(ept, grid, lds, s, lv, in, buf, tw, part);
+    case COL_PRE: return col_fwd_ept<T, COL_PRE>(ept, grid, lds, s, lv, in, buf, tw, part);
+    case COL_PRE_RESTRICT:
+      return col_fwd_ept<T, COL_PRE_RESTRICT>(ept, grid, lds, s, lv, in, buf, tw, part);
+    case COL_PROLONG: return col_fwd_ept<T, COL_PROLONG>(ept, grid, lds, s, lv, in, buf, tw, part);
+    default: break;
+  }
+  if constexpr (sizeof(T) == 8) {
+    switch (mode) {
+      case COL_OUTER_UPDATE:
+        return col_fwd_ept<T, COL_OUTER_UPDATE>(ept, grid, lds, s, lv, in, buf, tw, part);
+      case COL_SETUP: return col_fwd_ept<T, COL_SETUP>(ept, grid, lds, s, lv, in, buf, tw, part);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_row(int spectral, const LevelDev<T>& lv, cplx<T>* buf,
+                           const Twiddles<T>& tw, const T* part, int npart, const T* xin,
+                           hipStream_t s) {
+  const int L1 = 1 << lv.logL1;
+  if (2 * L1 > kCap4 || lv.logL2 < 1) return hipErrorInvalidValue;
+  const int kr = L1 >= kNT4 ? L1 / kNT4 : 1;
+  const int grid = (1 << lv.logL2) / 2;
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(2 * L1);
+  if (spectral && lv.sym) return row_kr<T, true, true>(kr, grid, lds, s, lv, buf, tw, part, npart, xin);
+  if (spectral) return row_kr<T, true, false>(kr, grid, lds, s, lv, buf, tw, part, npart, xin);
+  if constexpr (sizeof(T) == 8)
+    return row_kr<T, false, false>(kr, grid, lds, s, lv, buf, tw, part, npart, xin);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_col_inv(int mode, const LevelDev<T>& lv, const EpiOut<T>& out,
+                               const cplx<T>* buf, const Twiddles<T>& tw, double* part,
+                               hipStream_t s) {
+  int ept;
+  if (!col_geom_ok(lv.logL1, lv.logL2, lv.tcols, &ept) || !epi_mode_built<T>(mode))
+    return hipErrorInvalidValue;
+  const int grid = col_blocks(lv.logL1, lv.tcols);
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(ept * kNT4);
+  switch (mode) {
+    case EPI_RESID: return col_inv_ept<T, EPI_RESID>(ept, grid, lds, s, lv, out, buf, tw, part);
+    case EPI_SMOOTH: return col_inv_ept<T, EPI_SMOOTH>(ept, grid, lds, s, lv, out, buf, tw, part);
+    default: break;
+  }
+  if constexpr (sizeof(T) == 8) {
+    switch (mode) {
+      case EPI_MV: return col_inv_ept<T, EPI_MV>(ept, grid, lds, s, lv, out, buf, tw, part);
+      case EPI_OUTER: return col_inv_ept<T, EPI_OUTER>(ept, grid, lds, s, lv, out, buf, tw, part);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace amg
