@@ -22,6 +22,7 @@ AMG_K_CONST, AMG_K_WEIGHTED, AMG_K_FRACTIONAL, AMG_K_GENERATORS = 0, 1, 2, 3
 AMG_FP64, AMG_MIXED = 0, 1
 AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2
+AMG_FLAG_EAGER = 4
 
 
 class AmgError(RuntimeError):

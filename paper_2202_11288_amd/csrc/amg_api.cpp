@@ -197,6 +197,12 @@ struct amg_ctx {
   std::vector<double> hist;
   int last_iters = 0;
   std::vector<void*> dev_allocs;
+  // V-cycle replay (see AMG_FLAG_EAGER): captured on an internal stream at
+  // the handle's second V-cycle; every argument of its kernels is a
+  // handle-owned buffer, so the graph stays valid for the handle's lifetime.
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t vgraph = nullptr;
+  int vcycles_eager = 0;
 };
 
 namespace {
@@ -267,7 +273,7 @@ int check_opts(const amg_opts_t* o) {
   if (o->coarsest_log2 < 2 || o->coarsest_log2 > 7) return AMG_EINVAL;
   if (o->precision != AMG_FP64 && o->precision != AMG_MIXED) return AMG_EINVAL;
   if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
-  if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE)) return AMG_EINVAL;
+  if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE | AMG_FLAG_EAGER)) return AMG_EINVAL;
   return AMG_OK;
 }
 
@@ -397,6 +403,38 @@ int vcycle_dev(amg_ctx* c, hipStream_t s) {
     }
   }
   return AMG_OK;
+}
+
+// One V-cycle in the handle's precision (level 0's b in, level 0's u out):
+// the first runs eagerly (it also raises the kernels' LDS limits), the second
+// is captured into a graph, and from then on the graph is replayed on s.
+int vcycle_run(amg_ctx* c, hipStream_t s) {
+  auto eager = [c](hipStream_t st) {
+    return c->mixed ? vcycle_dev<float>(c, st) : vcycle_dev<double>(c, st);
+  };
+  if (c->prof.on || (c->opts.flags & AMG_FLAG_EAGER)) return eager(s);
+  if (!c->vgraph && c->vcycles_eager >= 1) {
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int st = eager(c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != AMG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    HIP_TRY(ec);
+    const hipError_t ei = hipGraphInstantiate(&c->vgraph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) c->vgraph = nullptr;
+    HIP_TRY(ei);
+  }
+  if (c->vgraph) {
+    HIP_TRY(hipGraphLaunch(c->vgraph, s));
+    return AMG_OK;
+  }
+  ++c->vcycles_eager;
+  return eager(s);
 }
 
 // r = b - A x on the finest level (FP64), optionally with x += e fused in
@@ -601,6 +639,10 @@ int setup_device(amg_ctx* c, hipStream_t s) {
 
 void release(amg_ctx* c) {
   if (!c) return;
+  if (c->vgraph) (void)hipGraphExecDestroy(c->vgraph);
+  c->vgraph = nullptr;
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
   for (void* p : c->dev_allocs) (void)hipFree(p);
   c->dev_allocs.clear();
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -745,11 +787,11 @@ int amg_vcycle(amg_t h, const void* r, void* e, void* stream) {
   const size_t m = (size_t)(2 * L0.n + 1);
   if (h->mixed) {
     HIP_TRY(hipMemcpyAsync(L0.bf, r, m * sizeof(float), hipMemcpyDeviceToDevice, s));
-    AMG_TRY(vcycle_dev<float>(h, s));
+    AMG_TRY(vcycle_run(h, s));
     HIP_TRY(hipMemcpyAsync(e, L0.uf, m * sizeof(float), hipMemcpyDeviceToDevice, s));
   } else {
     HIP_TRY(hipMemcpyAsync(L0.bd, r, m * sizeof(double), hipMemcpyDeviceToDevice, s));
-    AMG_TRY(vcycle_dev<double>(h, s));
+    AMG_TRY(vcycle_run(h, s));
     HIP_TRY(hipMemcpyAsync(e, L0.ud, m * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   return AMG_OK;
@@ -773,8 +815,7 @@ int solve_begin(amg_t h, const double* b, double* x, double tol, hipStream_t s) 
 int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s) {
   const void* e = h->mixed ? (const void*)h->lv[0].uf : (const void*)h->lv[0].ud;
   const size_t v0 = h->prof.mark(s);
-  if (h->mixed) AMG_TRY(vcycle_dev<float>(h, s));
-  else AMG_TRY(vcycle_dev<double>(h, s));
+  AMG_TRY(vcycle_run(h, s));
   const size_t v1 = h->prof.mark(s);
   AMG_TRY(outer_residual(h, b, x, e, tol, s));
   const size_t v2 = h->prof.mark(s);
