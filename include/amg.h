@@ -107,9 +107,10 @@ typedef struct {
    FFT passes, the small-level V-cycle kernel, each V-cycle and each outer
    residual during amg_solve; read the totals with amg_profile_stats. */
 #define AMG_FLAG_PROFILE 2
-/* Launch every V-cycle kernel directly.  By default a handle's second
-   V-cycle is captured into a HIP graph on an internal stream and every later
-   V-cycle replays that graph on the caller's stream (same kernels, same
+/* Launch every V-cycle kernel directly.  By default, when the hierarchy has
+   at least two levels above the small-level kernel (N >= 2^13), a handle's
+   second V-cycle is captured into a HIP graph on an internal stream and every
+   later V-cycle replays that graph on the caller's stream (same kernels, same
    arguments, fewer launch gaps).  Set this flag when the caller captures the
    solve into a graph of its own.  Profiled handles always launch directly. */
 #define AMG_FLAG_EAGER 4

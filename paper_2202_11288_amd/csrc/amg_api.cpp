@@ -405,6 +405,8 @@ int vcycle_dev(amg_ctx* c, hipStream_t s) {
   return AMG_OK;
 }
 
+constexpr int kGraphMinLevels = 2;
+
 // One V-cycle in the handle's precision (level 0's b in, level 0's u out):
 // the first runs eagerly (it also raises the kernels' LDS limits), the second
 // is captured into a graph, and from then on the graph is replayed on s.
@@ -412,7 +414,10 @@ int vcycle_run(amg_ctx* c, hipStream_t s) {
   auto eager = [c](hipStream_t st) {
     return c->mixed ? vcycle_dev<float>(c, st) : vcycle_dev<double>(c, st);
   };
-  if (c->prof.on || (c->opts.flags & AMG_FLAG_EAGER)) return eager(s);
+  // a graph pays off only over many launches: at least two four-step levels
+  // (a V-cycle of only the small-level kernel launches it directly)
+  if (c->prof.on || (c->opts.flags & AMG_FLAG_EAGER) || c->first_tail < kGraphMinLevels)
+    return eager(s);
   if (!c->vgraph && c->vcycles_eager >= 1) {
     if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -109,59 +109,127 @@ constexpr int kTailJ = (1 << (kTailLog - 1)) / kNTT;  // v/w slots per thread (n
 
 // One matvec step of a tail level: form u (prologue), y = A u, then the
 // residual or Jacobi epilogue; b and u stay in registers between the two.
+// The prologue issues every global load of the step (spectra, Cross vectors,
+// b / u / the neighbouring level's vector, and thread 0's w_o operands) as
+// one batch with clamped addresses before any of them is used.
 template <typename T>
 __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int epi, const T* src,
                                           T wpro, T wepi, const TailLds<T>& s) {
+  constexpr int J = kTailJ;
   const int n = lv.n, L = 1 << lv.logL;
   TailSpec<T> sp;
   tail_spec_load(lv, sp);
-  T bv[kTailJ], bw[kTailJ], uv[kTailJ], uw[kTailJ], pj[kTailJ], xj[kTailJ];
+  int jj[J];
+  bool ok[J];
+  T pj[J], xj[J], qq[J], zz[J], r0[J], r1[J], r2[J], r3[J], r4[J], r5[J];
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    const int j = threadIdx.x + k * kNTT;
+    ok[k] = j < n;
+    jj[k] = ok[k] ? j : 0;
+    pj[k] = lv.p[jj[k]];
+    xj[k] = lv.xi[jj[k]];
+    qq[k] = lv.q[jj[k]];
+    zz[k] = lv.zeta[jj[k]];
+  }
+  if (pro == TP_PRE_RESTRICT) {
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+      const int js = jj[k], jw = n + 1 + js;
+      r0[k] = src[2 * js];
+      r1[k] = src[2 * js + 1];
+      r2[k] = src[2 * js + 2];
+      r3[k] = src[2 * jw];
+      r4[k] = src[2 * jw + 1];
+      r5[k] = src[2 * jw + 2];
+    }
+  } else if (pro == TP_PROLONG) {
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+      const int js = jj[k], jw = n + 1 + js;
+      int lo, hi;
+      bool ml, mh;
+      r0[k] = lv.b[js];
+      r1[k] = lv.b[jw];
+      r2[k] = lv.u[js];
+      r3[k] = lv.u[jw];
+      prolong_idx(js, n, lo, hi, ml, mh);
+      const T a0 = src[lo], a1 = src[hi];
+      prolong_idx(jw, n, lo, hi, ml, mh);
+      const T c0 = src[lo], c1 = src[hi];
+      prolong_idx(js, n, lo, hi, ml, mh);
+      r4[k] = T(0.5) * ((ml ? a0 : T(0)) + (mh ? a1 : T(0)));
+      prolong_idx(jw, n, lo, hi, ml, mh);
+      r5[k] = T(0.5) * ((ml ? c0 : T(0)) + (mh ? c1 : T(0)));
+    }
+  } else {  // TP_PRE_B, TP_USE_U
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+      const int js = jj[k], jw = n + 1 + js;
+      r0[k] = lv.b[js];
+      r1[k] = lv.b[jw];
+      r2[k] = lv.u[js];
+      r3[k] = lv.u[jw];
+    }
+  }
+  // thread 0: the w_o entry's operands, in the same batch
+  T wo_b = 0, wo_u = 0, wo_x = 0;
+  if (threadIdx.x == 0) {
+    if (pro == TP_PRE_RESTRICT) {
+      wo_b = T(0.25) * (src[2 * n] + T(2) * src[2 * n + 1] + src[2 * n + 2]);
+    } else {
+      wo_b = lv.b[n];
+      wo_u = lv.u[n];
+      if (pro == TP_PROLONG) wo_x = prolong_at(src, n, n);
+    }
+  }
+  T bv[J], bw[J], uv[J], uw[J];
   T dot = 0;
 #pragma unroll
-  for (int k = 0; k < kTailJ; ++k) {
-    const int j = threadIdx.x + k * kNTT;
-    bv[k] = bw[k] = uv[k] = uw[k] = pj[k] = xj[k] = T(0);
-    if (j < n) {
-      pj[k] = lv.p[j];
-      xj[k] = lv.xi[j];
+  for (int k = 0; k < J; ++k) {
+    if (pro == TP_PRE_RESTRICT) {
+      bv[k] = T(0.25) * (r0[k] + T(2) * r1[k] + r2[k]);
+      bw[k] = T(0.25) * (r3[k] + T(2) * r4[k] + r5[k]);
+    } else {
+      bv[k] = r0[k];
+      bw[k] = r1[k];
     }
-    if (j < n) {
-      const int jw = n + 1 + j;
+    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) {
+      uv[k] = wpro * bv[k] / lv.dv;
+      uw[k] = wpro * bw[k] / lv.dw;
+    } else if (pro == TP_PROLONG) {
+      uv[k] = r2[k] + r4[k];
+      uw[k] = r3[k] + r5[k];
+    } else {
+      uv[k] = r2[k];
+      uw[k] = r3[k];
+    }
+    if (!ok[k]) bv[k] = bw[k] = uv[k] = uw[k] = T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    if (ok[k]) {
+      const int j = jj[k], jw = n + 1 + j;
       if (pro == TP_PRE_RESTRICT) {
-        bv[k] = restrict_at(src, j);
-        bw[k] = restrict_at(src, jw);
         lv.b[j] = bv[k];
         lv.b[jw] = bw[k];
-      } else {
-        bv[k] = lv.b[j];
-        bw[k] = lv.b[jw];
       }
-      if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) {
-        uv[k] = wpro * bv[k] / lv.dv;
-        uw[k] = wpro * bw[k] / lv.dw;
+      if (pro != TP_USE_U) {
         lv.u[j] = uv[k];
         lv.u[jw] = uw[k];
-      } else if (pro == TP_PROLONG) {
-        uv[k] = lv.u[j] + prolong_at(src, n, j);
-        uw[k] = lv.u[jw] + prolong_at(src, n, jw);
-        lv.u[j] = uv[k];
-        lv.u[jw] = uw[k];
-      } else {
-        uv[k] = lv.u[j];
-        uw[k] = lv.u[jw];
       }
       s.z[j] = {uv[k], uw[k]};
-      dot += lv.q[j] * uv[k] + lv.zeta[j] * uw[k];
+      dot += qq[k] * uv[k] + zz[k] * uw[k];
     }
   }
   for (int j = n + threadIdx.x; j < L; j += kNTT) s.z[j] = {T(0), T(0)};
   if (threadIdx.x == 0) {  // the w_o entry
-    const T bo = (pro == TP_PRE_RESTRICT) ? restrict_at(src, n) : lv.b[n];
+    const T bo = wo_b;
     if (pro == TP_PRE_RESTRICT) lv.b[n] = bo;
     T uo;
     if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) uo = wpro * bo / lv.o;
-    else if (pro == TP_PROLONG) uo = lv.u[n] + prolong_at(src, n, n);
-    else uo = lv.u[n];
+    else if (pro == TP_PROLONG) uo = wo_u + wo_x;
+    else uo = wo_u;
     if (pro != TP_USE_U) lv.u[n] = uo;
     s.red[kNTT / 64] = uo;
     s.red[kNTT / 64 + 1] = bo;
