@@ -96,7 +96,23 @@ typedef struct {
                                  FP64 (iterative refinement).                 */
   int max_iter;               /* outer iterations                            */
   int flags;                  /* AMG_FLAG_* bits, 0 by default               */
+  int inner;                  /* AMG_INNER_VCYCLE (default) or AMG_INNER_PCG */
 } amg_opts_t;
+
+/* Outer iteration of amg_solve.
+   AMG_INNER_VCYCLE: the stationary iteration x <- x + B_K (b - A x) of the
+   paper (Algorithm 2 as the iteration operator, Sec. 5 stopping rule).
+   AMG_INNER_PCG: conjugate gradients preconditioned by one V-cycle B_K per
+   iteration (the Krylov acceleration of the same V-cycle), for symmetric
+   positive definite operators only (constant and fractional kernels, or
+   symmetric generators); Polak-Ribiere direction update, so a V-cycle run in
+   FP32 (AMG_MIXED) stays a valid preconditioner.  CG's theory wants a
+   symmetric V-cycle: m1 = m2 and omega_pre = omega_post (the defaults).  The
+   residual is the recurrence's r <- r - alpha A p in FP64; the stopping rule
+   is the same.  A non-positive <r, B r> or <p, A p> ends the solve with
+   AMG_DIVERGED. */
+#define AMG_INNER_VCYCLE 0
+#define AMG_INNER_PCG 1
 
 /* amg_setup builds only the host-side hierarchy (generators, Lemma 3.1
    levels, coarsest LU) and touches no GPU; amg_level_tpx, amg_num_levels and
@@ -123,7 +139,7 @@ typedef struct {
 } amg_stat_t;
 
 /* Fill *o with m1 = m2 = 1, omega = 2/3, coarsest_log2 = 5, FP64,
-   max_iter = 200. */
+   max_iter = 200, flags = 0, inner = AMG_INNER_VCYCLE. */
 void amg_default_opts(amg_opts_t* o);
 
 /* Build the multigrid hierarchy (Sec. 3): finest generators by product
@@ -134,7 +150,8 @@ void amg_default_opts(amg_opts_t* o);
  * coarsest level.  N must be a power of two with coarsest_log2 < log2 N <= 22
  * and 2 <= coarsest_log2; 0 < delta < 1/2 (ignored for AMG_K_GENERATORS).
  * *out receives the handle.  Errors: AMG_EINVAL (bad N, delta, alpha, weights,
- * null pointer, options), AMG_ENOMEM, AMG_EHIP. */
+ * null pointer, options; inner = AMG_INNER_PCG with a non-symmetric operator),
+ * AMG_ENOMEM, AMG_EHIP. */
 int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N,
               const amg_opts_t* opts, void* stream, amg_t* out);
 
@@ -152,7 +169,8 @@ int amg_level_matvec(amg_t h, int level, const double* x, double* y, void* strea
  * solve still runs in FP64).  2N-1 entries, device, must not alias. */
 int amg_vcycle(amg_t h, const void* r, void* e, void* stream);
 
-/* Solve A x = b by x <- x + B_K (b - A x) until the relative residual
+/* Solve A x = b by x <- x + B_K (b - A x) (or, with inner = AMG_INNER_PCG,
+ * by V-cycle-preconditioned conjugate gradients) until the relative residual
  * ||b - A x||_2 / ||b - A x_0||_2 < tol or max_iter (Sec. 5 stopping rule).
  * b (device, 2N-1 doubles), x (device, in: initial guess, out: solution).
  * iters/relres (host, may be NULL) receive the iteration count and the final

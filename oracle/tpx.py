@@ -18,6 +18,11 @@ scalar o.  Generators are stored as arrays g[d + n - 1], d = -(n-1)..n-1.
   C x = ifft(fft(c) .* fft(x)) (Sec. 3.2), plus the O(n) Cross terms.
 * ``vcycle``/``solve`` are the same Algorithm 2 / outer loop as in
   ``oracle.dense`` on this representation (FP64, scipy.fft).
+* ``pcg`` is conjugate gradients preconditioned by one V-cycle, the Krylov
+  acceleration of the outer iteration for the SPD case.  The paper runs the
+  stationary iteration only; ``pcg`` is pinned by properties of CG itself
+  (finite termination, monotone energy-norm error, the LU solution), not by
+  numbers of the paper.
 """
 from __future__ import annotations
 
@@ -289,4 +294,48 @@ def solve(H: Hierarchy, b, tol=1e-10, max_iter=500, opts: Options = Options(), x
         r = b - H.matvec(x)
         it += 1
         hist.append(np.linalg.norm(r) / r0)
+    return x, it, np.array(hist)
+
+
+def pcg(H: Hierarchy, b, tol=1e-10, max_iter=500, opts: Options = Options(), x0=None,
+        precond=None, callback=None):
+    """Conjugate gradients for the SPD case, preconditioned by one V-cycle
+    (the Krylov acceleration of the V-cycle iteration; the paper's method is
+    the stationary iteration of `solve`).  Steps, in this order, per
+    iteration: q = A p, alpha = <r, z> / <p, q>, x += alpha p, r -= alpha q,
+    stop test on ||r|| / ||r_0||, z = B r, beta in the Polak-Ribiere form
+    <z_new, r_new - r_old> / <z_old, r_old> (equal to the Fletcher-Reeves
+    ratio for an exactly symmetric preconditioner, and robust when the
+    preconditioner is applied in lower precision), p = z + beta p.
+    `precond` replaces the V-cycle (used by the pins with the identity);
+    `callback(x)` sees every iterate.  Returns (x, iterations, history); the
+    residual is the recurrence's."""
+    B = precond if precond is not None else (lambda r: vcycle(H, r, opts))
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - H.matvec(x)
+    r0 = np.linalg.norm(r)
+    hist = [1.0]
+    if r0 == 0.0:
+        return x, 0, np.array(hist)
+    z = B(r)
+    p = z.copy()
+    rz = float(r @ z)
+    it = 0
+    while it < max_iter:
+        q = H.matvec(p)
+        alpha = rz / float(p @ q)
+        x = x + alpha * p
+        if callback is not None:
+            callback(x)
+        r_old = r
+        r = r - alpha * q
+        it += 1
+        hist.append(np.linalg.norm(r) / r0)
+        if hist[-1] < tol:
+            break
+        z = B(r)
+        rz_new = float(r @ z)
+        beta = (rz_new - float(r_old @ z)) / rz
+        rz = rz_new
+        p = z + beta * p
     return x, it, np.array(hist)

@@ -23,6 +23,7 @@ AMG_FP64, AMG_MIXED = 0, 1
 AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2
 AMG_FLAG_EAGER = 4
+AMG_INNER_VCYCLE, AMG_INNER_PCG = 0, 1
 
 
 class AmgError(RuntimeError):
@@ -39,7 +40,8 @@ class amg_kernel_t(ctypes.Structure):
 class amg_opts_t(ctypes.Structure):
     _fields_ = [("m1", ctypes.c_int), ("m2", ctypes.c_int), ("omega_pre", ctypes.c_double),
                 ("omega_post", ctypes.c_double), ("coarsest_log2", ctypes.c_int),
-                ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("flags", ctypes.c_int),
+                ("inner", ctypes.c_int)]
 
 
 class amg_stat_t(ctypes.Structure):
@@ -139,7 +141,10 @@ def kernel(kind: int, alpha: float = 0.0, wl: float = 1.0, wr: float = 1.0, gen=
 def amg_default_opts(**over) -> amg_opts_t:
     o = amg_opts_t()
     lib.amg_default_opts(ctypes.byref(o))
+    fields = {name for name, _ in amg_opts_t._fields_}
     for k, v in over.items():
+        if k not in fields:
+            raise TypeError(f"amg_opts_t has no field {k!r}")
         setattr(o, k, v)
     return o
 

@@ -203,6 +203,12 @@ struct amg_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t vgraph = nullptr;
   int vcycles_eager = 0;
+  // conjugate gradients (inner = AMG_INNER_PCG): direction, A p, previous
+  // residual (FP64, 2N-1 each) and the dot-product block partials
+  double* cg_p = nullptr;
+  double* cg_q = nullptr;
+  double* cg_rold = nullptr;
+  double* cg_part = nullptr;
 };
 
 namespace {
@@ -274,6 +280,7 @@ int check_opts(const amg_opts_t* o) {
   if (o->precision != AMG_FP64 && o->precision != AMG_MIXED) return AMG_EINVAL;
   if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
   if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE | AMG_FLAG_EAGER)) return AMG_EINVAL;
+  if (o->inner != AMG_INNER_VCYCLE && o->inner != AMG_INNER_PCG) return AMG_EINVAL;
   return AMG_OK;
 }
 
@@ -295,6 +302,7 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess) {
   }
   bytes += L0 * 16 * 2 + (mixed ? L0 * 8 : 0);           // FFT scratch (setup uses two)
   bytes += (mixed ? (2 * N - 1) * 8 : 0);                // outer residual
+  if (o->inner == AMG_INNER_PCG) bytes += 3 * (2 * N - 1) * 8 + 2 * 1024 * 8;  // p, q, r_old
   const int64_t mc = (int64_t(2) << o->coarsest_log2) - 1;
   bytes += 2 * mc * mc * 8;
   bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
@@ -617,7 +625,10 @@ int setup_device(amg_ctx* c, hipStream_t s) {
   }
   AMG_TRY(dalloc(c, &c->dpart64, (size_t)maxblocks));
   AMG_TRY(dalloc(c, &c->dpart32, (size_t)maxblocks));
-  AMG_TRY(dalloc(c, &c->npart, (size_t)maxblocks));
+  // residual-norm partials: column blocks of the finest four-step level or
+  // the vector chunks of the conjugate-gradient update
+  AMG_TRY(dalloc(c, &c->npart,
+                 (size_t)std::max(maxblocks, vec_blocks((int64_t)(2 * c->N - 1)))));
   {
     std::vector<LevelDev<double>> v64(nl);
     for (int l = 0; l < nl; ++l) v64[l] = c->lv[l].dev<double>();
@@ -635,6 +646,13 @@ int setup_device(amg_ctx* c, hipStream_t s) {
   AMG_TRY(dalloc(c, &c->st_dev, 1));
   AMG_TRY(dalloc(c, &c->hist_dev, (size_t)c->opts.max_iter + 2));
   if (mixed) AMG_TRY(dalloc(c, &c->rout, (size_t)(2 * c->N - 1)));
+  if (c->opts.inner == AMG_INNER_PCG) {
+    const size_t m = (size_t)(2 * c->N - 1);
+    AMG_TRY(dalloc(c, &c->cg_p, m));
+    AMG_TRY(dalloc(c, &c->cg_q, m));
+    AMG_TRY(dalloc(c, &c->cg_rold, m));
+    AMG_TRY(dalloc(c, &c->cg_part, (size_t)(2 * vec_blocks((int64_t)m))));
+  }
   void* ph = nullptr;
   HIP_TRY(hipHostMalloc(&ph, sizeof(SolveState), hipHostMallocDefault));
   c->st_host = static_cast<SolveState*>(ph);
@@ -668,6 +686,7 @@ void amg_default_opts(amg_opts_t* o) {
   o->precision = AMG_FP64;
   o->max_iter = 200;
   o->flags = 0;
+  o->inner = AMG_INNER_VCYCLE;
 }
 
 const char* amg_strerror(int st) {
@@ -721,6 +740,10 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
       delete c;
       return AMG_EINVAL;  // Jacobi needs a nonzero diagonal
     }
+  }
+  if (o.inner == AMG_INNER_PCG && !c->host[0].symmetric()) {
+    delete c;
+    return AMG_EINVAL;  // conjugate gradients needs a symmetric operator
   }
   if (!c->host_only) {
     const hipError_t e = hipGetDevice(&c->device);
@@ -817,15 +840,63 @@ int solve_begin(amg_t h, const double* b, double* x, double tol, hipStream_t s) 
   return AMG_OK;
 }
 
-int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s) {
-  const void* e = h->mixed ? (const void*)h->lv[0].uf : (const void*)h->lv[0].ud;
+// Conjugate gradients preconditioned by the V-cycle.  The residual r lives
+// where the V-cycle reads its right-hand side (level 0's b; in the mixed form
+// r is FP64 in `rout` with its FP32 copy in level 0's b), z = B r is level 0's
+// u, and every scalar stays on the device.
+// z = B r, then the new direction (first: p = z; otherwise Polak-Ribiere).
+int pcg_precondition(amg_t h, int first, hipStream_t s) {
+  const LevelRes& L0 = h->lv[0];
+  const int64_t m = 2 * h->N - 1;
+  const int nb = vec_blocks(m);
   const size_t v0 = h->prof.mark(s);
   AMG_TRY(vcycle_run(h, s));
-  const size_t v1 = h->prof.mark(s);
-  AMG_TRY(outer_residual(h, b, x, e, tol, s));
-  const size_t v2 = h->prof.mark(s);
-  h->prof.span(PK_VCYCLE, v0, v1);
-  h->prof.span(PK_OUTER, v1, v2);
+  h->prof.span(PK_VCYCLE, v0, h->prof.mark(s));
+  const double* rold = first ? nullptr : h->cg_rold;
+  if (h->mixed)
+    HIP_TRY(launch_vdot<float>(h->rout, L0.uf, rold, m, h->cg_part, s));
+  else
+    HIP_TRY(launch_vdot<double>(L0.bd, L0.ud, rold, m, h->cg_part, s));
+  HIP_TRY(launch_cg_scalar(h->st_dev, h->cg_part, nb, first ? CG_INIT : CG_BETA, s));
+  if (h->mixed)
+    HIP_TRY(launch_cg_dir<float>(h->st_dev, h->cg_p, L0.uf, m, first, s));
+  else
+    HIP_TRY(launch_cg_dir<double>(h->st_dev, h->cg_p, L0.ud, m, first, s));
+  return AMG_OK;
+}
+
+// q = A p, alpha, x += alpha p, r -= alpha q (and its FP32 copy), stop test.
+int pcg_step(amg_t h, double* x, double tol, hipStream_t s) {
+  const LevelRes& L0 = h->lv[0];
+  const int64_t m = 2 * h->N - 1;
+  const size_t v0 = h->prof.mark(s);
+  AMG_TRY(level_matvec64(h, 0, h->cg_p, h->cg_q, s));
+  HIP_TRY(launch_vdot<double>(h->cg_p, h->cg_q, nullptr, m, h->cg_part, s));
+  HIP_TRY(launch_cg_scalar(h->st_dev, h->cg_part, vec_blocks(m), CG_ALPHA, s));
+  double* r = h->mixed ? h->rout : L0.bd;
+  HIP_TRY(launch_cg_update(h->st_dev, x, h->cg_p, r, h->cg_rold, h->cg_q, h->mixed ? L0.bf : nullptr,
+                           m, h->npart, s));
+  HIP_TRY(launch_finish(h->st_dev, h->npart, vec_blocks(m), tol, h->opts.max_iter, h->hist_dev, s));
+  h->prof.span(PK_OUTER, v0, h->prof.mark(s));
+  return AMG_OK;
+}
+
+// Enqueues the work up to the next stop test; round counts the calls since
+// solve_begin (whose residual and stop test come first).
+int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s, int round) {
+  if (h->opts.inner == AMG_INNER_PCG) {
+    AMG_TRY(pcg_precondition(h, round == 0, s));
+    AMG_TRY(pcg_step(h, x, tol, s));
+  } else {
+    const void* e = h->mixed ? (const void*)h->lv[0].uf : (const void*)h->lv[0].ud;
+    const size_t v0 = h->prof.mark(s);
+    AMG_TRY(vcycle_run(h, s));
+    const size_t v1 = h->prof.mark(s);
+    AMG_TRY(outer_residual(h, b, x, e, tol, s));
+    const size_t v2 = h->prof.mark(s);
+    h->prof.span(PK_VCYCLE, v0, v1);
+    h->prof.span(PK_OUTER, v1, v2);
+  }
   HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
   return AMG_OK;
 }
@@ -881,10 +952,10 @@ int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int
   HIP_TRY(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
   AMG_TRY(solve_begin(h, b, x, tol, s));
-  for (;;) {
+  for (int round = 0;; ++round) {
     HIP_TRY(hipStreamSynchronize(s));
     if (h->st_host->done) break;
-    AMG_TRY(solve_round(h, b, x, tol, s));
+    AMG_TRY(solve_round(h, b, x, tol, s, round));
   }
   return solve_end(h, s, iters, relres);
 }
@@ -912,7 +983,7 @@ int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const*
   for (int i = 0; i < count; ++i)
     AMG_TRY(solve_begin(hs[i], b[i], x[i], tol[i], pool->streams[i % S]));
   std::vector<char> done(count, 0);
-  for (;;) {
+  for (int round = 0;; ++round) {
     for (int k = 0; k < S; ++k) HIP_TRY(hipStreamSynchronize(pool->streams[k]));
     int active = 0;
     for (int i = 0; i < count; ++i) {
@@ -922,7 +993,7 @@ int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const*
         continue;
       }
       ++active;
-      AMG_TRY(solve_round(hs[i], b[i], x[i], tol[i], pool->streams[i % S]));
+      AMG_TRY(solve_round(hs[i], b[i], x[i], tol[i], pool->streams[i % S], round));
     }
     if (!active) break;
   }

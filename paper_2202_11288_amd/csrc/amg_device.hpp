@@ -97,7 +97,25 @@ struct SolveState {
   int status;
   int done;
   int pad;
+  // conjugate-gradient scalars (inner = AMG_INNER_PCG)
+  double rz;     // <r, z> of the current direction
+  double alpha;  // step length
+  double beta;   // direction update
 };
+
+// Stages of the conjugate-gradient scalar kernel.
+enum CgStage { CG_INIT = 0, CG_ALPHA = 1, CG_BETA = 2 };
+
+// Vector kernels: fixed contiguous chunks, one per block of kVecNT threads.
+constexpr int kVecNT = 256;
+inline int vec_blocks(int64_t m) {
+  const int64_t b = (m + 2047) / 2048;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+inline int64_t vec_chunk(int64_t m) {
+  const int nb = vec_blocks(m);
+  return (m + nb - 1) / nb;
+}
 
 // ---- launchers (all asynchronous on `s`) ------------------------------------
 template <typename T>
@@ -125,6 +143,19 @@ hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
                          double* hist, hipStream_t s);
 hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s);
+// part[2b] = a.z, part[2b+1] = c.z over chunk b (c may be null); z FP64 or FP32
+template <typename TZ>
+hipError_t launch_vdot(const double* a, const TZ* z, const double* c, int64_t m, double* part,
+                       hipStream_t s);
+hipError_t launch_cg_scalar(SolveState* st, const double* part, int nb, int stage, hipStream_t s);
+// x += alpha p; r_old = r; r -= alpha q; r32 = (float) r (if set); npart = ||r||^2 partials
+hipError_t launch_cg_update(const SolveState* st, double* x, const double* p, double* r,
+                            double* r_old, const double* q, float* r32, int64_t m, double* npart,
+                            hipStream_t s);
+// p = z (first) or p = z + beta p
+template <typename TZ>
+hipError_t launch_cg_dir(const SolveState* st, double* p, const TZ* z, int64_t m, int first,
+                         hipStream_t s);
 
 // Column tiles / grid sizes used by the launchers (host helpers).
 inline int col_blocks(int logL1, int tcols) { return (1 << logL1) / tcols; }

@@ -246,6 +246,26 @@ TpxLevel coarsen(const TpxLevel& f) {
     c.zeta[i] = 2.0 * R(roww, i);
   }
   c.o = 0.25 * colv[n - 1] + 0.5 * colo + 0.25 * colw[0];
+  if (f.symmetric()) {
+    // The Galerkin image of a symmetric level is symmetric, but the
+    // recurrences above give mirror entries that agree only up to rounding.
+    // Averaging them keeps every coarse level exactly symmetric, so it keeps
+    // the compact real spectra and the SPD kernels on the device.
+    const int64_t m = 2 * nc - 1;
+    std::vector<double> a(m), b(m);
+    for (int64_t i = 0; i < m; ++i) {
+      a[i] = 0.5 * (c.a[i] + c.a[m - 1 - i]);
+      b[i] = 0.5 * (c.b[i] + c.c[m - 1 - i]);
+    }
+    c.a = a;
+    c.d = a;
+    c.b = b;
+    for (int64_t i = 0; i < m; ++i) c.c[i] = b[m - 1 - i];
+    for (int64_t i = 0; i < nc; ++i) {
+      c.p[i] = c.q[i] = 0.5 * (c.p[i] + c.q[i]);
+      c.xi[i] = c.zeta[i] = 0.5 * (c.xi[i] + c.zeta[i]);
+    }
+  }
   return c;
 }
 

@@ -492,6 +492,92 @@ __global__ void k_copy_d2f(const double* a, float* b, int64_t m) {
 }
 
 // ---------------------------------------------------------------------------
+// Conjugate gradients preconditioned by the V-cycle (SPD case).  Dot products
+// and norms sum fixed contiguous chunks (one per block) and reduce the block
+// partials in index order, so every run gives the same bits.  The scalars
+// live in the solve state on the device; a finished solve (done) leaves them
+// and the vectors untouched.
+// ---------------------------------------------------------------------------
+template <typename TZ>
+__global__ __launch_bounds__(kVecNT) void k_vdot(const double* a, const TZ* z, const double* c,
+                                                 int64_t m, int64_t chunk, double* part) {
+  __shared__ double red[kVecNT / 64];
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = i0 + chunk < m ? i0 + chunk : m;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kVecNT) {
+    const double zi = (double)z[i];
+    s0 += a[i] * zi;
+    if (c) s1 += c[i] * zi;
+  }
+  s0 = block_sum<double, kVecNT>(s0, red);
+  s1 = block_sum<double, kVecNT>(s1, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0;
+    part[2 * blockIdx.x + 1] = s1;
+  }
+}
+
+__global__ __launch_bounds__(kVecNT) void k_cg_scalar(SolveState* st, const double* part, int nb,
+                                                      int stage) {
+  __shared__ double red[kVecNT / 64];
+  double v0 = 0.0, v1 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kVecNT) {
+    v0 += part[2 * i];
+    v1 += part[2 * i + 1];
+  }
+  v0 = block_sum<double, kVecNT>(v0, red);
+  v1 = block_sum<double, kVecNT>(v1, red);
+  if (threadIdx.x != 0 || st->done) return;
+  bool bad = !(v0 > 0.0) || isinf(v0);  // <r, z> and <p, A p> must be positive (SPD)
+  if (stage == CG_INIT) {
+    st->rz = v0;
+    st->beta = 0.0;
+  } else if (stage == CG_ALPHA) {
+    st->alpha = st->rz / v0;
+  } else {
+    // Polak-Ribiere: <z_new, r_new - r_old> / <z_old, r_old>
+    st->beta = (v0 - v1) / st->rz;
+    st->rz = v0;
+  }
+  if (bad) {
+    st->status = 2;  // AMG_DIVERGED: the operator or the preconditioner is not SPD
+    st->done = 1;
+  }
+}
+
+__global__ __launch_bounds__(kVecNT) void k_cg_update(const SolveState* st, double* x,
+                                                      const double* p, double* r, double* r_old,
+                                                      const double* q, float* r32, int64_t m,
+                                                      int64_t chunk, double* npart) {
+  __shared__ double red[kVecNT / 64];
+  if (st->done) return;  // uniform: every thread of every block returns
+  const double alpha = st->alpha;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = i0 + chunk < m ? i0 + chunk : m;
+  double ss = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kVecNT) {
+    x[i] += alpha * p[i];
+    const double ro = r[i], rn = ro - alpha * q[i];
+    r_old[i] = ro;
+    r[i] = rn;
+    if (r32) r32[i] = (float)rn;
+    ss += rn * rn;
+  }
+  ss = block_sum<double, kVecNT>(ss, red);
+  if (threadIdx.x == 0) npart[blockIdx.x] = ss;
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(kVecNT) void k_cg_dir(const SolveState* st, double* p, const TZ* z,
+                                                   int64_t m, int first) {
+  if (st->done) return;
+  const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
+  if (i >= m) return;
+  p[i] = first ? (double)z[i] : (double)z[i] + st->beta * p[i];
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -548,6 +634,42 @@ hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <typename TZ>
+hipError_t launch_vdot(const double* a, const TZ* z, const double* c, int64_t m, double* part,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_vdot<TZ>, vec_blocks(m), kVecNT, 0, s, a, z, c, m, vec_chunk(m), part);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_scalar(SolveState* st, const double* part, int nb, int stage, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_scalar, 1, kVecNT, 0, s, st, part, nb, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const SolveState* st, double* x, const double* p, double* r,
+                            double* r_old, const double* q, float* r32, int64_t m, double* npart,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, vec_blocks(m), kVecNT, 0, s, st, x, p, r, r_old, q, r32, m,
+                     vec_chunk(m), npart);
+  return hipGetLastError();
+}
+
+template <typename TZ>
+hipError_t launch_cg_dir(const SolveState* st, double* p, const TZ* z, int64_t m, int first,
+                         hipStream_t s) {
+  const int grid = (int)((m + kVecNT - 1) / kVecNT);
+  hipLaunchKernelGGL(k_cg_dir<TZ>, grid, kVecNT, 0, s, st, p, z, m, first);
+  return hipGetLastError();
+}
+
+template hipError_t launch_vdot<double>(const double*, const double*, const double*, int64_t,
+                                        double*, hipStream_t);
+template hipError_t launch_vdot<float>(const double*, const float*, const double*, int64_t,
+                                       double*, hipStream_t);
+template hipError_t launch_cg_dir<double>(const SolveState*, double*, const double*, int64_t, int,
+                                          hipStream_t);
+template hipError_t launch_cg_dir<float>(const SolveState*, double*, const float*, int64_t, int,
+                                         hipStream_t);
 #define AMG_INSTANTIATE(T)                                                                      \
   template hipError_t launch_tail_matvec<T>(int, int, const LevelDev<T>&, const ColIn<T>&,     \
                                             const EpiOut<T>&, const Twiddles<T>&, double*,     \

@@ -105,6 +105,8 @@ def _setup_status(kern, delta, N, **opts):
     dict(kind=B.AMG_K_WEIGHTED, wl=-1.0), dict(kind=7), dict(kind=B.AMG_K_GENERATORS),
     dict(opts=dict(coarsest_log2=1)), dict(opts=dict(coarsest_log2=8)),
     dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=8)),
+    dict(opts=dict(inner=2)), dict(opts=dict(inner=-1)),
+    dict(kind=B.AMG_K_WEIGHTED, wl=1.2, opts=dict(inner=B.AMG_INNER_PCG)),
 ])
 def test_invalid_arguments_rejected(case):
     kind = case.get("kind", B.AMG_K_CONST)
@@ -159,3 +161,21 @@ def test_solve_batch_argument_checks():
         assert B.lib.amg_solve_batch(1, hs, ptrs, ptrs2, tol, None, None, None) == B.AMG_EINVAL
     finally:
         B.amg_destroy(h)
+
+
+def test_conjugate_gradient_option():
+    """inner = AMG_INNER_PCG: accepted for the symmetric kernels (constant,
+    fractional), refused for the weighted (non-symmetric) one; the default is
+    the stationary iteration; the footprint counts CG's three vectors; unknown
+    option names are refused by the binding."""
+    assert B.amg_default_opts().inner == B.AMG_INNER_VCYCLE
+    for kern in (B.kernel(B.AMG_K_CONST), B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4)):
+        assert _setup_status(kern, 0.1, 1024, inner=B.AMG_INNER_PCG) == B.AMG_OK
+    assert _setup_status(B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8), 0.1, 1024,
+                         inner=B.AMG_INNER_PCG) == B.AMG_EINVAL
+    k = B.kernel(B.AMG_K_CONST)
+    f0 = B.amg_footprint_bytes(k, 0.1, 2 ** 16)
+    f1 = B.amg_footprint_bytes(k, 0.1, 2 ** 16, B.amg_default_opts(inner=B.AMG_INNER_PCG))
+    assert f1 - f0 >= 3 * (2 * 2 ** 16 - 1) * 8
+    with pytest.raises(TypeError):
+        B.amg_default_opts(innr=1)

@@ -400,3 +400,92 @@ def test_graph_replay_matches_eager(prec):
     finally:
         B.amg_destroy(he)
         B.amg_destroy(hg)
+
+
+@pytest.mark.parametrize("case,N", [(CONST25, 2 ** 14), (CONST05, 4096), (FRAC04, 4096)])
+def test_pcg_matches_oracle(case, N):
+    """V-cycle-preconditioned CG in FP64 against the oracle's pcg (same steps,
+    same Polak-Ribiere update): iteration counts within one, and the
+    solution's residual, evaluated by the oracle, below tol (plus the
+    hierarchy tolerance: the recurrence's residual and the true one differ by
+    rounding amplified by the condition number)."""
+    say("pcg", case[0], N)
+    H = oracle_hier(case, N)
+    b = synthetic.random_vector(2 * N - 1, seed=N + 5)
+    xo, ito, ho = tpx.pcg(H, b, tol=1e-10, max_iter=300)
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(inner=B.AMG_INNER_PCG, max_iter=300))
+    try:
+        x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        st, it, rel = B.amg_solve(h, dev(b), x, 1e-10)
+        say("pcg iterations gpu/oracle", it, ito, rel)
+        assert st == B.AMG_OK and rel < 1e-10
+        assert abs(it - ito) <= 1, (it, ito)
+        hist = B.amg_residual_history(h)
+        assert len(hist) == it + 1 and hist[0] == 1.0
+        relo = np.linalg.norm(b - H.matvec(host(x))) / np.linalg.norm(b)
+        assert relo < 1e-10 + kappa_tol(H), relo
+    finally:
+        B.amg_destroy(h)
+
+
+def test_pcg_mixed_and_fractional():
+    """PCG with the FP32 V-cycle as preconditioner (FP64 recurrence): the
+    fractional kernel (alpha = 0.4) at N = 2^14, where the stationary
+    iteration stalls, converges to 1e-10 (oracle-evaluated residual) within a
+    few iterations of the FP64 PCG; the constant kernel at N = 2^17 needs no
+    more iterations than the stationary mixed iteration."""
+    for case, N, stationary_too in ((FRAC04, 2 ** 14, False), (CONST25, 2 ** 17, True)):
+        say("pcg mixed", case[0], N)
+        H = oracle_hier(case, N)
+        b = synthetic.random_vector(2 * N - 1, seed=N + 7)
+        its = {}
+        for prec in (B.AMG_FP64, B.AMG_MIXED):
+            h = B.amg_setup(case[1], case[3], N,
+                            B.amg_default_opts(inner=B.AMG_INNER_PCG, precision=prec, max_iter=400))
+            try:
+                x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+                st, it, rel = B.amg_solve(h, dev(b), x, 1e-10)
+                assert st == B.AMG_OK, (prec, st)
+                relo = np.linalg.norm(b - H.matvec(host(x))) / np.linalg.norm(b)
+                assert relo < 1e-10 + kappa_tol(H), (prec, relo)
+                its[prec] = it
+            finally:
+                B.amg_destroy(h)
+        say("pcg iterations fp64/mixed", its)
+        assert its[B.AMG_MIXED] <= its[B.AMG_FP64] + 3
+        if stationary_too:
+            h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(precision=B.AMG_MIXED))
+            try:
+                x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+                _, it_stat, _ = B.amg_solve(h, dev(b), x, 1e-10)
+            finally:
+                B.amg_destroy(h)
+            assert its[B.AMG_MIXED] <= it_stat, (its, it_stat)
+
+
+def test_pcg_batch_matches_solo():
+    """amg_solve_batch with CG handles (and one stationary handle in the mix)
+    gives each solve's solo result bit for bit."""
+    say("pcg batch")
+    cases = [(CONST25, 8192, B.AMG_INNER_PCG, B.AMG_FP64), (FRAC04, 4096, B.AMG_INNER_PCG, B.AMG_MIXED),
+             (CONST05, 2048, B.AMG_INNER_VCYCLE, B.AMG_FP64), (CONST25, 2 ** 15, B.AMG_INNER_PCG, B.AMG_MIXED)]
+    hs, bs, xs, solo = [], [], [], []
+    try:
+        for case, N, inner, prec in cases:
+            h = B.amg_setup(case[1], case[3], N,
+                            B.amg_default_opts(inner=inner, precision=prec, max_iter=400))
+            hs.append(h)
+            b = dev(synthetic.random_vector(2 * N - 1, seed=N))
+            bs.append(b)
+            x1 = torch.zeros_like(b)
+            B.amg_solve(h, b, x1, 1e-10)
+            solo.append((x1, B.amg_residual_history(h)))
+            xs.append(torch.zeros_like(b))
+        st, its, rels = B.amg_solve_batch(hs, bs, xs, [1e-10] * len(hs))
+        assert st == B.AMG_OK
+        for (case, N, inner, prec), x, (x1, h1), h in zip(cases, xs, solo, hs):
+            assert torch.equal(x, x1), (case[0], N, inner)
+            np.testing.assert_array_equal(B.amg_residual_history(h), h1)
+    finally:
+        for h in hs:
+            B.amg_destroy(h)

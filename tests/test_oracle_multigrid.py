@@ -149,3 +149,46 @@ def test_two_grid_config_c1():
     x, it, hist = dense.solve(H, b, tol=1e-10)
     assert hist[-1] < 1e-10 and it <= 12
     assert np.abs(x - D.u_exact(D.points_block(N))).max() < 1e-9
+
+
+def test_pcg_identity_preconditioner_terminates():
+    """Plain CG (identity preconditioner) on a small SPD system terminates in
+    at most m = 2N - 1 steps in exact arithmetic; in FP64 the residual falls
+    below 1e-10 within m + 5 steps and the result is the LU solution.  A
+    wrong sign, index or beta formula breaks finite termination."""
+    N = 16
+    k = D.Kernel(D.CONST, 0.25)
+    A = D.assemble_dense(k, N)
+    H = tpx.Hierarchy.build(tpx.from_stencil(k, N), 2)
+    b = synthetic.random_vector(2 * N - 1, seed=3)
+    x, it, hist = tpx.pcg(H, b, tol=1e-10, max_iter=200, precond=lambda r: r.copy())
+    assert hist[-1] < 1e-10 and it <= (2 * N - 1) + 5, (it, hist[-1])
+    xs = scipy.linalg.solve(A, b)
+    assert np.abs(x - xs).max() <= 1e-8 * np.abs(xs).max()
+
+
+@pytest.mark.parametrize("kern", [D.Kernel(D.CONST, 0.05), D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4)],
+                         ids=lambda k: k.kind)
+def test_pcg_energy_error_decreases(kern):
+    """V-cycle-preconditioned CG (symmetric V-cycle: m1 = m2, equal damping,
+    P = 2 R^T) minimises the energy norm of the error over growing Krylov
+    spaces, so ||x_k - x*||_A never increases; it reaches the LU solution and
+    needs no more iterations than the stationary V-cycle iteration."""
+    N = 256
+    A = D.assemble_dense(kern, N)
+    H = tpx.Hierarchy.build(tpx.from_stencil(kern, N), 5)
+    b = D.rhs_manufactured(kern, N)
+    xs = scipy.linalg.solve(A, b)
+    errs = []
+
+    def energy(x):
+        e = x - xs
+        errs.append(float(np.sqrt(e @ (A @ e))))
+
+    x, it, hist = tpx.pcg(H, b, tol=1e-10, max_iter=100, callback=energy)
+    assert hist[-1] < 1e-10
+    e0 = float(np.sqrt(xs @ (A @ xs)))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-6) + 1e-12 * e0 for i in range(len(errs) - 1)), errs
+    assert np.abs(x - xs).max() <= 1e-7 * np.abs(xs).max()
+    _, it_stat, _ = tpx.solve(H, b, tol=1e-10, max_iter=500)
+    assert it <= it_stat, (it, it_stat)
