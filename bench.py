@@ -37,9 +37,18 @@ def parse():
     ap.add_argument("--alpha", type=float, default=0.4)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true",
+                    help="skip the V-cycle-preconditioned CG forms (reported beside the headline)")
     ap.add_argument("--prof-steps", type=int, default=3,
                     help="solves of the profiled pass (HIP events around the finest-level "
                          "passes, eager launches) that gives the roofline; 0 = skip")
+    ap.add_argument("--pmc-driver", action="store_true",
+                    help="the short program the --pmc counter runs profile: a plain copy of "
+                         "known size, then two mixed solves of the workload (eager launches)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="from the counter-collection CSVs of two rocprofv3 --pmc runs of "
+                         "--pmc-driver (FETCH_SIZE, then WRITE_SIZE), write the finest FP32 "
+                         "sweep's HBM traffic, scaled by the copy's, to profiles/; no GPU needed")
     ap.add_argument("--rocprof-summary", metavar="KERNEL_TRACE_CSV",
                     help="summarise a rocprofv3 --kernel-trace CSV (per kernel and grid size) "
                          "and exit; no GPU needed")
@@ -68,6 +77,116 @@ def rocprof_summary(path):
     print(f"total kernel time {tot / 1e3:.2f} ms over {len(rows)} dispatches")
 
 
+COPY_BYTES = 256 << 20  # the driver's plain copy: reads and writes this many bytes
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp32_finest_sweep_N2e20.json")
+KERNEL_SOURCES = ["fourstep.hpp", "fourstep_f32.hip", "fft_lds.hpp", "kernel_common.hpp",
+                  "amg_device.hpp"]
+
+
+def kernel_source_hash():
+    """Hash of the sources the finest-level FFT pass kernels are built from:
+    a traffic measurement is valid only for the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2202_11288_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_driver(args):
+    import torch
+
+    from paper_2202_11288_amd import binding as B
+    x = torch.ones(COPY_BYTES // 4, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    N = 2 ** args.logN
+    k = kernel_of(B, args)
+    b = torch.from_numpy(B.amg_manufactured_rhs(k, args.delta, N)).cuda()
+    h = B.amg_setup(k, args.delta, N,
+                    B.amg_default_opts(precision=B.AMG_MIXED, flags=B.AMG_FLAG_EAGER))
+    try:
+        for _ in range(2):
+            xs = torch.zeros_like(b)
+            B.amg_solve(h, b, xs, args.tol)
+        torch.cuda.synchronize()
+    finally:
+        B.amg_destroy(h)
+    print("pmc driver done", flush=True)
+
+
+def traffic_summary(fetch_csv, write_csv, logN):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the finest-level FP32
+    FFT pass kernels, each scaled by the factor that maps the same counter's
+    reading for the plain copy onto the copy's known bytes; per sweep = the
+    sum over the three passes' dispatches divided by the number of sweeps."""
+    import collections
+    import csv
+    import re
+
+    def load(path, counter):
+        per = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+            per[(name, int(r["Grid_Size"]))].append(float(r["Counter_Value"]) * 1024.0)
+        return per
+
+    out = {}
+    for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        per = load(path, counter)
+        copies = [v for (name, g), vals in per.items() if "copyBuffer" in name for v in vals]
+        big = max(copies)
+        scale = COPY_BYTES / big
+        fin = {k: v for k, v in per.items()
+               if k[0].startswith(("amg::k_col_fwd<float", "amg::k_row<float", "amg::k_col_inv<float"))}
+        # the finest level's kernels have the largest grids of their kind
+        sel = {}
+        for kind in ("k_col_fwd", "k_row", "k_col_inv"):
+            ks = {k: v for k, v in fin.items() if kind in k[0]}
+            g = max(gg for (_, gg) in ks)
+            sel[kind] = [x for (name, gg), vals in ks.items() if gg == g for x in vals]
+        sweeps = len(sel["k_row"])
+        total = sum(sum(v) for v in sel.values()) * scale / sweeps
+        out[label] = {"copy_counter_bytes": big, "copy_known_bytes": COPY_BYTES,
+                      "scale": round(scale, 4), "sweeps": sweeps,
+                      "bytes_per_sweep": round(total),
+                      "per_pass_bytes": {k: round(sum(v) * scale / sweeps) for k, v in sel.items()}}
+    res = {"kernel": f"fp32 finest-level FFT matvec sweep (3 passes), N=2^{logN}",
+           "source_hash": kernel_source_hash(),
+           "fetch": out["fetch"], "write": out["write"],
+           "traffic_bytes_per_sweep": out["fetch"]["bytes_per_sweep"] + out["write"]["bytes_per_sweep"],
+           "commands": [
+               "cd /tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+               "-d <repo>/gpurun_out/pmc_fetch -o run -- python3 <repo>/bench.py --pmc-driver",
+               "cd /tmp && timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv "
+               "-d <repo>/gpurun_out/pmc_write -o run -- python3 <repo>/bench.py --pmc-driver",
+               "python bench.py --traffic-summary gpurun_out/pmc_fetch/run_counter_collection.csv "
+               "gpurun_out/pmc_write/run_counter_collection.csv"]}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def measured_traffic():
+    """Bytes per finest FP32 sweep from the committed counter summary, or None
+    when it is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_sweep")
+
+
 def kernel_of(B, args):
     if args.kernel == "const":
         return B.kernel(B.AMG_K_CONST)
@@ -76,13 +195,15 @@ def kernel_of(B, args):
     return B.kernel(B.AMG_K_FRACTIONAL, alpha=args.alpha)
 
 
-def run_form(B, torch, args, precision, b_dev, profile=False):
+def run_form(B, torch, args, precision, b_dev, profile=False, inner=0):
     """Timed solves (graph-replayed V-cycles) or, with profile=True, the
     profiled pass: the same solves launched eagerly with HIP events around the
-    finest-level FFT passes on the solve stream."""
+    finest-level FFT passes on the solve stream.  inner selects the outer
+    iteration (0: the paper's stationary V-cycle iteration, 1: V-cycle-
+    preconditioned CG)."""
     N = 2 ** args.logN
     flags = B.AMG_FLAG_PROFILE if profile else 0
-    opts = B.amg_default_opts(precision=precision, flags=flags, max_iter=500)
+    opts = B.amg_default_opts(precision=precision, flags=flags, max_iter=500, inner=inner)
     steps = args.prof_steps if profile else args.steps
     warmup = 1 if profile else args.warmup
     t0 = time.perf_counter()
@@ -180,6 +301,12 @@ def main():
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary)
         return
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.logN)
+        return
+    if args.pmc_driver:
+        pmc_driver(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
@@ -203,6 +330,14 @@ def main():
     print(f"# mixed done: {summary(rmx, N)}", file=sys.stderr, flush=True)
     s64, smx = summary(r64, N), summary(rmx, N)
     sym = args.kernel != "weighted"
+    krylov = None
+    if sym and not args.no_pcg:
+        k64 = summary(run_form(B, torch, args, B.AMG_FP64, b_dev, inner=B.AMG_INNER_PCG), N)
+        kmx = summary(run_form(B, torch, args, B.AMG_MIXED, b_dev, inner=B.AMG_INNER_PCG), N)
+        print(f"# pcg done: fp64 {k64} mixed {kmx}", file=sys.stderr, flush=True)
+        krylov = {"note": "V-cycle-preconditioned CG (inner = AMG_INNER_PCG): same V-cycle, "
+                          "Krylov outer iteration; not the paper's stationary iteration",
+                  "mixed": kmx, "fp64": k64}
     n = N - 1
     roof = roof64 = roof32 = None
     if args.prof_steps > 0:
@@ -215,6 +350,12 @@ def main():
         t32 = pmx.get("fp32_finest_sweep", (0, 0.0))[1]
         t64 = pmx.get("fp64_finest_sweep", (0, 0.0))[1]
         roof = roof32 if t32 >= t64 else sweep_roofline(pmx, n, "fp64", 8, sym)
+        if roof is roof32 and roof32 is not None:
+            tb = measured_traffic()
+            roof32["traffic"] = tb
+            if tb:
+                roof32["traffic_note"] = ("HBM bytes per sweep from rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                          "scaled by a plain copy of known size (profiles/)")
     cpu, errs = (None, None)
     if not args.no_cpu_baseline:
         cpu, errs = cpu_baseline(args, b, r64["x"].cpu().numpy(), rmx["x"].cpu().numpy())
@@ -232,6 +373,7 @@ def main():
         "unknowns_per_s": smx["unknowns_per_s"],
         "mixed": smx, "fp64": s64,
         "speedup_mixed_vs_fp64": round(smx["solves_per_s"] / s64["solves_per_s"], 3),
+        "pcg": krylov,
         "roofline": roof, "roofline_fp64_form": roof64, "roofline_fp32_sweep": roof32,
         "roofline_source": (f"HIP events around the finest-level FFT passes on the solve stream, "
                             f"{args.prof_steps} profiled solves per form launched eagerly "
