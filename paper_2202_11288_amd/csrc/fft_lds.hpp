@@ -164,9 +164,8 @@ __device__ __forceinline__ void twiddle_set(const cplx<T>* __restrict__ tw, int 
 // as twiddle_set formed just before use (conj(x) conj(y) = conj(xy) exactly),
 // so that at most eight twiddles are live at a time.
 template <typename T, bool INV>
-__device__ __forceinline__ void twiddle16_apply(cplx<T> (&a)[16], const cplx<T>* __restrict__ tw,
-                                                int step) {
-  cplx<T> w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step], w8 = tw[8 * step];
+__device__ __forceinline__ void twiddle16_mul(cplx<T> (&a)[16], cplx<T> w1, cplx<T> w2, cplx<T> w4,
+                                              cplx<T> w8) {
   if (INV) {
     w1 = conj(w1);
     w2 = conj(w2);
@@ -189,6 +188,11 @@ __device__ __forceinline__ void twiddle16_apply(cplx<T> (&a)[16], const cplx<T>*
   a[13] = cmul(a[13], cmul(w5, w8));
   a[14] = cmul(a[14], cmul(w6, w8));
   a[15] = cmul(a[15], cmul(w7, w8));
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void twiddle16_apply(cplx<T> (&a)[16], const cplx<T>* __restrict__ tw,
+                                                int step) {
+  twiddle16_mul<T, INV>(a, tw[step], tw[2 * step], tw[4 * step], tw[8 * step]);
 }
 
 // ---- Stockham FFT over signals in LDS ---------------------------------------
@@ -317,6 +321,91 @@ __device__ __forceinline__ void fft_reg16(cplx<T> (&a)[16], Lds<T> lds, const Ff
   for (int r = 0; r < 16; ++r) a[r] = lds[base + ((j0 + (r << q)) << g.loges)];
   twiddle16_apply<T, INV>(a, tw, j0 << (g.logtw - g.logM));
   dft<T, 16, INV>(a);
+}
+
+// ---- LDS FFT with prefetched twiddles ----------------------------------------
+// The same pass sequence as lds_fft with E = 16 (a radix 2/4/8/16 first pass
+// without twiddles, then radix-16 passes, one butterfly per thread), for
+// signals of at most 4096 points in all (at most two radix-16 passes after the
+// first).  The twiddle bases w, w^2, w^4, w^8 of every radix-16 pass depend
+// only on the geometry and the thread, so they are fetched at kernel start,
+// under the signal's own loads, instead of inside each pass.
+template <typename T>
+struct FftTw {
+  cplx<T> w[2][4];
+};
+
+template <typename T>
+__device__ __forceinline__ void lds_fft_tw_prefetch(const FftGeom& g, const cplx<T>* __restrict__ tw,
+                                                    FftTw<T>& f) {
+  const int rem = g.logM & 3;
+  const int lognbs = g.logM - 4;
+  const int bf = threadIdx.x;
+  const int j = g.sigfast ? (bf >> g.logS) : (bf & ((1 << lognbs) - 1));
+  int logNs = rem == 0 ? 4 : rem;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    // threads past the last butterfly load in-range entries they never use
+    const int k = j & ((1 << logNs) - 1);
+    const int step = logNs < g.logM ? (k << (g.logtw - logNs - 4)) : 0;
+    f.w[p][0] = tw[step];
+    f.w[p][1] = tw[2 * step];
+    f.w[p][2] = tw[4 * step];
+    f.w[p][3] = tw[8 * step];
+    logNs += 4;
+  }
+}
+
+// One radix-16 pass (E = 16, NB = 1) with the thread's twiddle bases given.
+template <typename T, int NT, bool INV>
+__device__ __forceinline__ void stockham16_pre(Lds<T> lds, const FftGeom& g, int logNs,
+                                               const cplx<T> (&w)[4]) {
+  const int lognbs = g.logM - 4;
+  const int total = 1 << (lognbs + g.logS);
+  const int bf = threadIdx.x;
+  const bool act = bf < total;
+  const int s = g.sigfast ? (bf & ((1 << g.logS) - 1)) : (bf >> lognbs);
+  const int j = g.sigfast ? (bf >> g.logS) : (bf & ((1 << lognbs) - 1));
+  const int base = s << g.logss;
+  cplx<T> a[16];
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = lds[base + ((j + (r << lognbs)) << g.loges)];
+    twiddle16_mul<T, INV>(a, w[0], w[1], w[2], w[3]);
+    dft<T, 16, INV>(a);
+  }
+  __syncthreads();
+  if (act) {
+    const int k = j & ((1 << logNs) - 1);
+    const int out = ((j - k) << 4) + k;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[base + ((out + (r << logNs)) << g.loges)] = a[r];
+  }
+  __syncthreads();
+}
+
+template <typename T, int NT, bool INV>
+__device__ __forceinline__ void lds_fft_pf(Lds<T> lds, const FftGeom& g, const FftTw<T>& f) {
+  const int rem = g.logM & 3;
+  int logNs;
+  if (rem == 1) {
+    stockham_pass<T, 2, 16, NT, INV>(lds, g, 0, nullptr);
+    logNs = 1;
+  } else if (rem == 2) {
+    stockham_pass<T, 4, 16, NT, INV>(lds, g, 0, nullptr);
+    logNs = 2;
+  } else if (rem == 3) {
+    stockham_pass<T, 8, 16, NT, INV>(lds, g, 0, nullptr);
+    logNs = 3;
+  } else {
+    stockham_pass<T, 16, 16, NT, INV>(lds, g, 0, nullptr);
+    logNs = 4;
+  }
+  if (logNs < g.logM) {
+    stockham16_pre<T, NT, INV>(lds, g, logNs, f.w[0]);
+    logNs += 4;
+  }
+  if (logNs < g.logM) stockham16_pre<T, NT, INV>(lds, g, logNs, f.w[1]);
 }
 
 // Deterministic reduction of one value per thread over a workgroup of NT

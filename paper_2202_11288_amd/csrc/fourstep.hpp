@@ -38,6 +38,14 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
   const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
   const int i0 = threadIdx.x >> logTC, di = kNT4 >> logTC;
   constexpr int CH = EPT < 8 ? EPT : 8;  // elements per load batch
+  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  // partial tiles: every twiddle of the pass is fetched first, under the loads
+  FftTw<T> ft;
+  RunTw<T, EPT> rt;
+  if constexpr (EPT < 16) {
+    lds_fft_tw_prefetch(g, tw.base, ft);
+    run_tw_load<T, EPT>(tw, lv.logL, j1 * i0, j1 * di, rt);
+  }
   // the w_o entry (tile 0, thread 0): its operands are fetched first
   constexpr bool kWo = MODE != COL_SETUP && MODE != COL_MV;
   const bool wo_thread = kWo && tile == 0 && threadIdx.x == 0;
@@ -191,20 +199,20 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
     const T s = block_sum<T, kNT4>(dot, red);
     if (threadIdx.x == 0) part[tile] = s;
   }
-  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
   if constexpr (EPT == 16) {
     // the thread's rows i0 + e*di are the positions j0 + e*L2/16 of its
     // last-pass butterfly (j0 = i0): first and last passes on registers
     fft_reg16<T, kNT4, false>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
+    twiddle_run_mul<T, EPT, false>(tw, lv.logL, j1 * i0, j1 * di, a);
   } else {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * kNT4] = a[e];
     __syncthreads();
-    lds_fft<T, kE4, kNT4, false>(lds, g, tw.base);
+    lds_fft_pf<T, kNT4, false>(lds, g, ft);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) a[e] = lds[(int)threadIdx.x + e * kNT4];
+    twiddle_run_mul_pre<T, EPT, false>(rt, a);
   }
-  twiddle_run_mul<T, EPT, false>(tw, lv.logL, j1 * i0, j1 * di, a);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) stg(buf + j1 + ((i0 + e * di) << lv.logL1), a[e]);
 }
@@ -354,8 +362,17 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
   const int ka = item == 0 ? 0 : item;
   const int kb = item == 0 ? L2 / 2 : L2 - item;
   const int ra = ka << lv.logL1, rb = kb << lv.logL1;
+  // every twiddle of the pass is fetched first, under the loads
+  const FftGeom g{lv.logL1, 1, lv.logL1, 0, kTwLog, false};
+  FftTw<T> ft;
+  lds_fft_tw_prefetch(g, tw.base, ft);
   const bool act = KR > 1 || tid < L1;  // KR == 1: rows shorter than the workgroup
   const int t0 = act ? tid : 0;
+  RunTw<T, KR> rta, rtb;
+  if constexpr (SPECTRAL) {
+    run_tw_load<T, KR>(tw, lv.logL, t0 * ka, kNT4 * ka, rta);
+    run_tw_load<T, KR>(tw, lv.logL, t0 * kb, kNT4 * kb, rtb);
+  }
   {
     cplx<T> za[KR], zb[KR];
 #pragma unroll
@@ -385,8 +402,7 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
     }
   }
   __syncthreads();
-  const FftGeom g{lv.logL1, 1, lv.logL1, 0, kTwLog, false};
-  lds_fft<T, kE4, kNT4, false>(lds, g, tw.base);
+  lds_fft_pf<T, kNT4, false>(lds, g, ft);
   if constexpr (!SPECTRAL) {
     if (act) {
 #pragma unroll
@@ -447,16 +463,21 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
       }
     }
     __syncthreads();
-    lds_fft<T, kE4, kNT4, true>(lds, g, tw.base);
-    cplx<T> wa[KR], wb[KR];
-    twiddle_run<T, KR>(tw, lv.logL, t0 * ka, kNT4 * ka, wa);
-    twiddle_run<T, KR>(tw, lv.logL, t0 * kb, kNT4 * kb, wb);
+    lds_fft_pf<T, kNT4, true>(lds, g, ft);
+    cplx<T> ya[KR], yb[KR];
+#pragma unroll
+    for (int e = 0; e < KR; ++e) {
+      ya[e] = lds[t0 + e * kNT4];
+      yb[e] = lds[L1 + t0 + e * kNT4];
+    }
+    twiddle_run_mul_pre<T, KR, true>(rta, ya);
+    twiddle_run_mul_pre<T, KR, true>(rtb, yb);
     if (act) {
 #pragma unroll
       for (int e = 0; e < KR; ++e) {
         const int t = t0 + e * kNT4;
-        buf[ra + t] = cmul(lds[t], conj(wa[e]));
-        buf[rb + t] = cmul(lds[L1 + t], conj(wb[e]));
+        stg(buf + ra + t, ya[e]);
+        stg(buf + rb + t, yb[e]);
       }
     }
     if (item == 0) finish_wo(lv, wpart, red, xin);
@@ -480,6 +501,9 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
   const int i0 = threadIdx.x >> logTC, di = kNT4 >> logTC;
+  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  FftTw<T> ft;  // partial tiles: the FFT's twiddles are fetched first
+  if constexpr (EPT < 16) lds_fft_tw_prefetch(g, tw.base, ft);
   cplx<T> a[EPT];  // rows i0 + e*di of column j1
 #pragma unroll
   for (int e = 0; e < EPT; ++e) a[e] = ldg(buf + j1 + ((i0 + e * di) << lv.logL1));
@@ -518,14 +542,13 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
       o1[e] = out.bo[jw];
     }
   }
-  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
   if constexpr (EPT == 16) {
     fft_reg16<T, kNT4, true>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
   } else {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * kNT4] = a[e];
     __syncthreads();
-    lds_fft<T, kE4, kNT4, true>(lds, g, tw.base);
+    lds_fft_pf<T, kNT4, true>(lds, g, ft);
 #pragma unroll
     for (int e = 0; e < KH; ++e) a[e] = lds[(int)threadIdx.x + e * kNT4];
   }

@@ -51,41 +51,72 @@ __device__ __forceinline__ void twiddle_run(const Twiddles<T>& tw, int logL, int
   for (int k = 1; k < K; ++k) w[k] = cmul(p[0], p[k]);
 }
 
-// a[k] *= w[k] (CONJ: conj(w[k])) for the run of twiddle_run, with the same
-// products formed just before use so that few twiddles are live at a time.
+// The table entries behind the twiddle run e^{-2 pi i (m0 + k ds)/L}, k < K:
+// hi/lo pairs of the base and of ds, 2 ds, 4 ds, 8 ds (as many as K needs),
+// loaded ahead of their use.
+template <typename T, int K>
+struct RunTw {
+  static constexpr int P = K == 1 ? 1 : (K == 2 ? 2 : (K == 4 ? 3 : (K == 8 ? 4 : 5)));
+  cplx<T> hi[P], lo[P];
+};
+template <typename T, int K>
+__device__ __forceinline__ void run_tw_load(const Twiddles<T>& tw, int logL, int m0, int ds,
+                                            RunTw<T, K>& r) {
+  const int mask = (1 << logL) - 1;
+#pragma unroll
+  for (int i = 0; i < RunTw<T, K>::P; ++i) {
+    const int e = (i == 0 ? m0 : (ds << (i - 1))) & mask;
+    const int idx = e << (kTw4Log - logL);
+    r.hi[i] = tw.hi[idx >> 12];
+    r.lo[i] = tw.lo[idx & (kTw4Lo - 1)];
+  }
+}
+
+// a[k] *= w[k] (CONJ: conj(w[k])) for the run, with the same products as
+// twiddle_run formed just before use so that few twiddles are live at a time.
+template <typename T, int K, bool CONJ>
+__device__ __forceinline__ void twiddle_run_mul_pre(const RunTw<T, K>& r, cplx<T>* a) {
+  static_assert(K == 1 || K == 2 || K == 4 || K == 8 || K == 16, "run length");
+  auto cj = [](cplx<T> x) { return CONJ ? conj(x) : x; };
+  const cplx<T> p0 = cmul(r.hi[0], r.lo[0]);
+  a[0] = cmul(a[0], cj(p0));
+  if constexpr (K >= 2) {
+    const cplx<T> p1 = cmul(r.hi[1], r.lo[1]);
+    a[1] = cmul(a[1], cj(cmul(p0, p1)));
+    if constexpr (K >= 4) {
+      const cplx<T> p2 = cmul(r.hi[2], r.lo[2]);
+      const cplx<T> p3 = cmul(p1, p2);
+      a[2] = cmul(a[2], cj(cmul(p0, p2)));
+      a[3] = cmul(a[3], cj(cmul(p0, p3)));
+      if constexpr (K >= 8) {
+        const cplx<T> p4 = cmul(r.hi[3], r.lo[3]);
+        const cplx<T> p5 = cmul(p1, p4), p6 = cmul(p2, p4), p7 = cmul(p3, p4);
+        a[4] = cmul(a[4], cj(cmul(p0, p4)));
+        a[5] = cmul(a[5], cj(cmul(p0, p5)));
+        a[6] = cmul(a[6], cj(cmul(p0, p6)));
+        a[7] = cmul(a[7], cj(cmul(p0, p7)));
+        if constexpr (K >= 16) {
+          const cplx<T> p8 = cmul(r.hi[4], r.lo[4]);
+          a[8] = cmul(a[8], cj(cmul(p0, p8)));
+          a[9] = cmul(a[9], cj(cmul(p0, cmul(p1, p8))));
+          a[10] = cmul(a[10], cj(cmul(p0, cmul(p2, p8))));
+          a[11] = cmul(a[11], cj(cmul(p0, cmul(p3, p8))));
+          a[12] = cmul(a[12], cj(cmul(p0, cmul(p4, p8))));
+          a[13] = cmul(a[13], cj(cmul(p0, cmul(p5, p8))));
+          a[14] = cmul(a[14], cj(cmul(p0, cmul(p6, p8))));
+          a[15] = cmul(a[15], cj(cmul(p0, cmul(p7, p8))));
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int K, bool CONJ>
 __device__ __forceinline__ void twiddle_run_mul(const Twiddles<T>& tw, int logL, int m0, int ds,
                                                 cplx<T>* a) {
-  static_assert(K == 1 || K == 2 || K == 4 || K == 8 || K == 16, "run length");
-  const int mask = (1 << logL) - 1;
-  auto cj = [](cplx<T> x) { return CONJ ? conj(x) : x; };
-  const cplx<T> p0 = tw4(tw, logL, m0 & mask);
-  a[0] = cmul(a[0], cj(p0));
-  if constexpr (K == 1) return;
-  const cplx<T> p1 = tw4(tw, logL, ds & mask);
-  a[1] = cmul(a[1], cj(cmul(p0, p1)));
-  if constexpr (K == 2) return;
-  const cplx<T> p2 = tw4(tw, logL, (2 * ds) & mask);
-  const cplx<T> p3 = cmul(p1, p2);
-  a[2] = cmul(a[2], cj(cmul(p0, p2)));
-  a[3] = cmul(a[3], cj(cmul(p0, p3)));
-  if constexpr (K == 4) return;
-  const cplx<T> p4 = tw4(tw, logL, (4 * ds) & mask);
-  const cplx<T> p5 = cmul(p1, p4), p6 = cmul(p2, p4), p7 = cmul(p3, p4);
-  a[4] = cmul(a[4], cj(cmul(p0, p4)));
-  a[5] = cmul(a[5], cj(cmul(p0, p5)));
-  a[6] = cmul(a[6], cj(cmul(p0, p6)));
-  a[7] = cmul(a[7], cj(cmul(p0, p7)));
-  if constexpr (K == 8) return;
-  const cplx<T> p8 = tw4(tw, logL, (8 * ds) & mask);
-  a[8] = cmul(a[8], cj(cmul(p0, p8)));
-  a[9] = cmul(a[9], cj(cmul(p0, cmul(p1, p8))));
-  a[10] = cmul(a[10], cj(cmul(p0, cmul(p2, p8))));
-  a[11] = cmul(a[11], cj(cmul(p0, cmul(p3, p8))));
-  a[12] = cmul(a[12], cj(cmul(p0, cmul(p4, p8))));
-  a[13] = cmul(a[13], cj(cmul(p0, cmul(p5, p8))));
-  a[14] = cmul(a[14], cj(cmul(p0, cmul(p6, p8))));
-  a[15] = cmul(a[15], cj(cmul(p0, cmul(p7, p8))));
+  RunTw<T, K> r;
+  run_tw_load<T, K>(tw, logL, m0, ds, r);
+  twiddle_run_mul_pre<T, K, CONJ>(r, a);
 }
 
 // Prolongation 2 R^T at fine index m of a fine vector of length 2*mc + 1
