@@ -12,7 +12,13 @@ Follows Sec. 2.2 of Chen, Cao and Serra-Capizzano (arXiv 2202.11288):
   sees the quadratic pieces whose end points are midpoints, so every row has
   the same stencil and the block system is [A B; B^T A^] for the constant
   kernel;
-* unknowns ordered U_h = [u_1..u_{N-1}, u_{1/2}..u_{N-1/2}] (Sec. 2.2.1).
+* unknowns ordered U_h = [u_1..u_{N-1}, u_{1/2}..u_{N-1/2}] (Sec. 2.2.1);
+* the standard collocation of Sec. 2.2.1 (eq. (nonsym system)): midpoint rows
+  see the mesh cells around them, so C and D differ from B^T and A
+  (`midpoint_stencil_standard`, constant and weighted kernels), and non-zero
+  volume data g carried to the right-hand side through the coupling of the
+  interior rows to the exterior points (`assemble_with_exterior`, the content
+  of eqs. (rightside1), (rightside2)).
 
 Readings where the paper is silent (each also listed in the design doc):
 
@@ -23,7 +29,9 @@ Readings where the paper is silent (each also listed in the design doc):
 * when delta/h is not an integer, the last sub-interval I_{r+1} = [r h, delta]
   (Sec. 2.2) is integrated exactly, so the stencil reaches offset r+1;
   when delta < h the same rule integrates over [0, delta];
-* the manufactured solution is u = x^2 (1-x)^2 with zero volume data.
+* manufactured solutions: u = x^2 (1-x)^2 with zero volume data, and
+  u = (1+x)^6 with g = u on the interaction volume (the spatial profile of
+  the paper's test solution).
 
 All arithmetic is FP64 NumPy; the moment integrals are evaluated in closed
 form (constant kernels) or by closed form / binomial series (fractional
@@ -300,3 +308,122 @@ def rhs_manufactured(kernel: Kernel, N: int):
         out = a < d
         f += np.where(out, ux * (d ** (b + 1) - np.where(out, a, d) ** (b + 1)) / (b + 1), 0.0)
     return c * f
+
+
+# --- the standard (unshifted) collocation of Sec. 2.2.1 and volume data -------
+#
+# eq. (ccs2.6) / eq. (nonsym system): every row uses the quadratic pieces of
+# the mesh cells [x_m, x_{m+1}] (nodes at the ends, the midpoint inside).  For
+# a node row this is the rule of `stencil` above; a midpoint row x_c sees the
+# cells [(k - 1/2) h, (k + 1/2) h] around it, the central one holding x_c as
+# its midpoint, and the last one cut at the horizon.  The blocks C and D then
+# differ from B^T and A; the system is non-symmetric.  Constant and weighted
+# kernels.
+
+STANDARD, SHIFTED = "standard", "shifted"
+
+
+def midpoint_stencil_standard(kernel: Kernel, N: int):
+    """Midpoint-row stencil of the standard scheme, W(s2) in half-grid
+    offsets (odd s2: nodes, even s2: midpoints), returned as (W, S) with
+    W[s2 + S].  Right side t in [0, delta] (units of h, R = delta N): the
+    sub-interval [0, min(1/2, R)] of the central cell and the cells
+    [k - 1/2, min(k + 1/2, R)], k = 1, 2, ...; cell k's quadratic goes through
+    k - 1/2 (node, s2 = 2k - 1), k (midpoint, s2 = 2k), k + 1/2 (node,
+    s2 = 2k + 1) with Lagrange basis, in s = tau - k,
+      l_- = 2 s^2 - s,  l_0 = 1 - 4 s^2,  l_+ = 2 s^2 + s.
+    The left side is the mirror image (weight wl)."""
+    if kernel.kind not in (CONST, WEIGHTED):
+        raise ValueError("the standard scheme is set up for the constant and weighted kernels")
+    h = 1.0 / N
+    R = kernel.delta * N
+    subs = [(0.0, min(0.5, R), 0)]
+    k = 1
+    while k - 0.5 < R:
+        subs.append((k - 0.5, min(k + 0.5, R), k))
+        k += 1
+    S = 2 * subs[-1][2] + 1
+    W = np.zeros(2 * S + 1)
+    wl, wr = kernel.side_weights()
+    c = kernel.c * h
+
+    def mom(a, b, j):  # int_a^b s^j ds
+        return (b ** (j + 1) - a ** (j + 1)) / (j + 1)
+
+    for a, b, kk in subs:
+        sa, sb = a - kk, b - kk
+        J0, J1, J2 = (c * mom(sa, sb, j) for j in range(3))
+        Im = 2 * J2 - J1      # int gamma l_-
+        I0 = J0 - 4 * J2      # int gamma l_0
+        Ip = 2 * J2 + J1      # int gamma l_+
+        for sign, ws in ((+1, wr), (-1, wl)):
+            # mirror: on the left the cell's "-" end is at -(2k - 1), its "+" end at -(2k + 1)
+            W[S] += ws * J0
+            if kk == 0:
+                W[S] -= ws * I0
+            else:
+                W[S + sign * 2 * kk] -= ws * I0
+            W[S + sign * (2 * kk - 1)] -= ws * Im
+            W[S + sign * (2 * kk + 1)] -= ws * Ip
+    return W, S
+
+
+def row_stencils(kernel: Kernel, N: int, scheme: str = SHIFTED):
+    """(node-row stencil, midpoint-row stencil), each as (W, S)."""
+    Wn = stencil(kernel, N)
+    if scheme == SHIFTED:
+        return Wn, Wn
+    return Wn, midpoint_stencil_standard(kernel, N)
+
+
+def assemble_with_exterior(kernel: Kernel, N: int, scheme: str = SHIFTED):
+    """Dense collocation rows over interior AND exterior points.
+
+    Returns (A, E, q_ext): A is the (2N-1)^2 block-ordered matrix of the
+    interior unknowns; E (2N-1 x len(q_ext)) couples the interior rows to the
+    exterior half-grid positions q_ext (x = q h/2 <= 0 or >= 1, the points of
+    N_out the stencils reach), so that eq. (ccs2.6) with volume data g reads
+    A U = F - E g(x_ext), the right-hand side of eqs. (rightside1),
+    (rightside2).  Written out row by row; tiny N only."""
+    (Wn, Sn), (Wm, Sm) = row_stencils(kernel, N, scheme)
+    M = 2 * N - 1
+    S = max(Sn, Sm)
+    q_ext = np.concatenate([np.arange(-S, 1), np.arange(2 * N, 2 * N + S + 1)])
+    col_of_ext = {int(q): i for i, q in enumerate(q_ext)}
+    Aint = np.zeros((M + 1, M + 1))
+    E = np.zeros((M + 1, len(q_ext)))
+    for p in range(1, M + 1):
+        W, Sw = (Wn, Sn) if p % 2 == 0 else (Wm, Sm)
+        for s2 in range(-Sw, Sw + 1):
+            w = W[s2 + Sw]
+            if w == 0.0:
+                continue
+            q = p + s2
+            if 1 <= q <= M:
+                Aint[p, q] += w
+            else:
+                E[p, col_of_ext[q]] += w
+    perm = block_permutation(N)
+    return Aint[np.ix_(perm, perm)], E[perm, :], q_ext
+
+
+# --- manufactured solution with volume data: u = (1 + x)^6, g = u outside -----
+
+def u_poly6(x):
+    return (1.0 + np.asarray(x, dtype=np.float64)) ** 6
+
+
+def f_poly6(kernel: Kernel, x):
+    """f = -L_delta u for u = (1+x)^6 on all of R (so g = u on the interaction
+    volume), constant / weighted kernel, closed form through the
+    antiderivative U = (1+y)^7 / 7."""
+    if kernel.kind not in (CONST, WEIGHTED):
+        raise ValueError(kernel.kind)
+    x = np.asarray(x, dtype=np.float64)
+    d = kernel.delta
+    wl, wr = kernel.side_weights()
+    U = lambda y: (1.0 + y) ** 7 / 7.0
+    ux = u_poly6(x)
+    right = ux * d - (U(x + d) - U(x))
+    left = ux * d - (U(x) - U(x - d))
+    return kernel.c * (wr * right + wl * left)

@@ -95,28 +95,35 @@ def from_dense(M):
                M[n + 1:, n].copy(), M[n, n + 1:].copy(), float(M[n, n]))
 
 
-def from_stencil(kernel: disc.Kernel, N: int):
-    """Finest level from the row stencil W(s2) (half-grid offsets).
+def from_stencil(kernel: disc.Kernel, N: int, scheme: str = disc.SHIFTED):
+    """Finest level from the row stencils W(s2) (half-grid offsets).
 
-    v_i sits at x = (i+1) h, w_o at h/2, w_bar_j at (j + 3/2) h (0-based), so
-    A, D_bar take W at even offsets 2d; B_bar at 2d+1; C_bar at 2d-1; the Cross
-    vectors at the offsets between w_o and each point.
+    v_i sits at x = (i+1) h, w_o at h/2, w_bar_j at (j + 3/2) h (0-based).
+    Node rows (A, B_bar, p) take the node-row stencil: A at even offsets 2d,
+    B_bar at 2d+1, p at the offset to w_o.  Midpoint rows (C_bar, D_bar, q,
+    xi, zeta, o) take the midpoint-row stencil: C_bar at 2d-1, D_bar at 2d,
+    the w_o row and column at the offsets between w_o and each point.  Under
+    the shifted-symmetric rule both stencils are the same; under the standard
+    rule (eq. (ccs2.6)) the midpoint rows have their own.
     """
-    W, S = disc.stencil(kernel, N)
+    (Wn, Sn), (Wm, Sm) = disc.row_stencils(kernel, N, scheme)
     n = N - 1
 
-    def Wat(s2):
-        s2 = np.asarray(s2)
-        out = np.zeros(s2.shape)
-        ok = np.abs(s2) <= S
-        out[ok] = W[s2[ok] + S]
-        return out
+    def at(W, S):
+        def Wat(s2):
+            s2 = np.asarray(s2)
+            out = np.zeros(s2.shape)
+            ok = np.abs(s2) <= S
+            out[ok] = W[s2[ok] + S]
+            return out
+        return Wat
 
+    Wn_at, Wm_at = at(Wn, Sn), at(Wm, Sm)
     d = np.arange(-(n - 1), n)
     i = np.arange(n)
-    return TpX(n, Wat(2 * d), Wat(2 * d + 1), Wat(2 * d - 1), Wat(2 * d),
-               Wat(-2 * i - 1), Wat(2 * i + 1), Wat(-2 * i - 2), Wat(2 * i + 2),
-               float(Wat(np.array(0))))
+    return TpX(n, Wn_at(2 * d), Wn_at(2 * d + 1), Wm_at(2 * d - 1), Wm_at(2 * d),
+               Wn_at(-2 * i - 1), Wm_at(2 * i + 1), Wm_at(-2 * i - 2), Wm_at(2 * i + 2),
+               float(Wm_at(np.array(0))))
 
 
 def from_blocks(gA, gB, gC, gD, N: int):
