@@ -82,7 +82,20 @@ typedef struct {
   double alpha;      /* AMG_K_FRACTIONAL only                                */
   double wl, wr;     /* AMG_K_WEIGHTED only (the survey's variant: 1.2, 0.8) */
   const double* gen; /* AMG_K_GENERATORS only (host, copied during setup)    */
+  int scheme;        /* AMG_SCHEME_SHIFTED (default) or AMG_SCHEME_STANDARD  */
 } amg_kernel_t;
+
+/* Collocation rule (Sec. 2.2).
+   AMG_SCHEME_SHIFTED: the shifted-symmetric rule of eq. (system1): every row,
+   node or midpoint, uses the quadratic pieces whose end points are of its own
+   type, so all rows share one stencil (SPD for the constant kernel).
+   AMG_SCHEME_STANDARD: the standard collocation of eq. (ccs2.6) / eq.
+   (nonsym system): every row uses the mesh cells [x_m, x_{m+1}]; midpoint rows
+   get their own stencil (blocks C, D differ from B^T, A; non-symmetric).
+   Constant and weighted kernels (AMG_ENOTSUP for the fractional kernel);
+   ignored for AMG_K_GENERATORS. */
+#define AMG_SCHEME_SHIFTED 0
+#define AMG_SCHEME_STANDARD 1
 
 typedef enum { AMG_FP64 = 0, AMG_MIXED = 1 } amg_precision;
 
@@ -220,6 +233,22 @@ int amg_profile_stats(amg_t h, amg_stat_t* out, int cap, int reset);
  * block order; host output b_host (2N-1 doubles).  Same kernel/delta/N rules
  * as amg_setup (AMG_K_GENERATORS is AMG_EINVAL). */
 int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, double* b_host);
+
+/* Volume data (Sec. 2.2: u = g on the interaction volume).  The rows near
+ * x = 0 and x = 1 couple to the exterior collocation points x = -k h/2 and
+ * x = 1 + k h/2, k = 0..S.  Returns S (>= 0) for this kernel, delta, N and
+ * scheme, or an error status (< 0). */
+int64_t amg_volume_reach(const amg_kernel_t* kernel, double delta, int64_t N);
+
+/* b -= E g: carries known exterior values to the right-hand side (the
+ * boundary corrections of eqs. (rightside1), (rightside2), for either
+ * scheme).  g_left[k] = g(-k h/2), g_right[k] = g(1 + k h/2), k = 0..S (host,
+ * S + 1 doubles each, S from amg_volume_reach); b (host, 2N-1 doubles, block
+ * order) is updated in place.  Host only, FP64: direct sums for a short
+ * reach, FFT convolution (O(S log S)) beyond.  Errors: AMG_EINVAL (bad
+ * kernel, delta, N, null pointer), AMG_ENOTSUP, AMG_ENOMEM. */
+int amg_volume_rhs(const amg_kernel_t* kernel, double delta, int64_t N, const double* g_left,
+                   const double* g_right, double* b);
 
 /* Device bytes amg_setup would allocate for this problem (spectra, Cross
  * vectors, per-level work vectors, FFT scratch); < 0 on invalid input. */

@@ -427,3 +427,36 @@ def f_poly6(kernel: Kernel, x):
     right = ux * d - (U(x + d) - U(x))
     left = ux * d - (U(x) - U(x - d))
     return kernel.c * (wr * right + wl * left)
+
+
+def volume_correction(kernel: Kernel, N: int, g_left, g_right, scheme: str = SHIFTED):
+    """E g (block order) from the stencils, row by row over the rows that
+    reach the interaction volume only: g_left[k] = g(-k h/2),
+    g_right[k] = g(1 + k h/2), k = 0..S (S = the longer stencil's reach).
+    The same numbers as `assemble_with_exterior`'s E @ g without forming E."""
+    (Wn, Sn), (Wm, Sm) = row_stencils(kernel, N, scheme)
+    S = max(Sn, Sm)
+    g_left = np.asarray(g_left, dtype=np.float64)
+    g_right = np.asarray(g_right, dtype=np.float64)
+    M = 2 * N - 1
+    out = np.zeros(M + 1)  # interleaved positions 1..M
+    for p in range(1, M + 1):
+        W, Sw = (Wn, Sn) if p % 2 == 0 else (Wm, Sm)
+        acc = 0.0
+        # left exterior points q = -k, offset s2 = -k - p, in reach while s2 >= -Sw
+        kl = min(S, Sw - p)
+        if kl >= 0:
+            k = np.arange(kl + 1)
+            acc += W[-k - p + Sw] @ g_left[:kl + 1]
+        # right exterior points q = 2N + k, offset s2 = 2N + k - p, in reach while s2 <= Sw
+        kr = min(S, Sw - 2 * N + p)
+        if kr >= 0:
+            k = np.arange(kr + 1)
+            acc += W[2 * N + k - p + Sw] @ g_right[:kr + 1]
+        out[p] = acc
+    return out[block_permutation(N)]
+
+
+def volume_reach(kernel: Kernel, N: int, scheme: str = SHIFTED):
+    (Wn, Sn), (Wm, Sm) = row_stencils(kernel, N, scheme)
+    return max(Sn, Sm)

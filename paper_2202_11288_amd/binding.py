@@ -24,6 +24,7 @@ AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2
 AMG_FLAG_EAGER = 4
 AMG_INNER_VCYCLE, AMG_INNER_PCG = 0, 1
+AMG_SCHEME_SHIFTED, AMG_SCHEME_STANDARD = 0, 1
 
 
 class AmgError(RuntimeError):
@@ -34,7 +35,8 @@ class AmgError(RuntimeError):
 
 class amg_kernel_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("alpha", ctypes.c_double), ("wl", ctypes.c_double),
-                ("wr", ctypes.c_double), ("gen", ctypes.POINTER(ctypes.c_double))]
+                ("wr", ctypes.c_double), ("gen", ctypes.POINTER(ctypes.c_double)),
+                ("scheme", ctypes.c_int)]
 
 
 class amg_opts_t(ctypes.Structure):
@@ -80,6 +82,8 @@ def _load():
         "amg_level_size": (I64, [P, I]),
         "amg_level_tpx": (I, [P, I, DP, DP, DP, DP, DP, DP, DP, DP, DP]),
         "amg_manufactured_rhs": (I, [ctypes.POINTER(amg_kernel_t), D, I64, DP]),
+        "amg_volume_reach": (I64, [ctypes.POINTER(amg_kernel_t), D, I64]),
+        "amg_volume_rhs": (I, [ctypes.POINTER(amg_kernel_t), D, I64, DP, DP, DP]),
         "amg_footprint_bytes": (I64, [ctypes.POINTER(amg_kernel_t), D, I64,
                                       ctypes.POINTER(amg_opts_t)]),
         "amg_destroy": (I, [P]),
@@ -129,10 +133,11 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def kernel(kind: int, alpha: float = 0.0, wl: float = 1.0, wr: float = 1.0, gen=None):
+def kernel(kind: int, alpha: float = 0.0, wl: float = 1.0, wr: float = 1.0, gen=None,
+           scheme: int = AMG_SCHEME_SHIFTED):
     """amg_kernel_t; for AMG_K_GENERATORS `gen` is a float64 numpy array that
     must stay alive until amg_setup returns."""
-    k = amg_kernel_t(kind, alpha, wl, wr, None)
+    k = amg_kernel_t(kind, alpha, wl, wr, None, scheme)
     if gen is not None:
         k.gen = gen.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return k
@@ -252,6 +257,28 @@ def amg_manufactured_rhs(kern: amg_kernel_t, delta: float, N: int):
     _check(lib.amg_manufactured_rhs(ctypes.byref(kern), float(delta), int(N),
                                     b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
            "amg_manufactured_rhs")
+    return b
+
+
+def amg_volume_reach(kern: amg_kernel_t, delta: float, N: int) -> int:
+    S = lib.amg_volume_reach(ctypes.byref(kern), float(delta), int(N))
+    if S < 0:
+        raise AmgError(int(S), "amg_volume_reach")
+    return int(S)
+
+
+def amg_volume_rhs(kern: amg_kernel_t, delta: float, N: int, g_left, g_right, b):
+    """b -= E g in place; g_left, g_right, b are contiguous float64 numpy
+    arrays (S + 1, S + 1 and 2N - 1 values)."""
+    import numpy as np
+    S = amg_volume_reach(kern, delta, N)
+    DP = ctypes.POINTER(ctypes.c_double)
+    for name, a, m in (("g_left", g_left, S + 1), ("g_right", g_right, S + 1), ("b", b, 2 * N - 1)):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+                and a.shape == (m,)):
+            raise ValueError(f"{name} must be a contiguous float64 array of {m} values")
+    _check(lib.amg_volume_rhs(ctypes.byref(kern), float(delta), int(N), g_left.ctypes.data_as(DP),
+                              g_right.ctypes.data_as(DP), b.ctypes.data_as(DP)), "amg_volume_rhs")
     return b
 
 

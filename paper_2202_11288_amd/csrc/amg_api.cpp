@@ -269,6 +269,7 @@ KernelSpec spec_of(const amg_kernel_t* k, double delta) {
   s.wl = k->wl;
   s.wr = k->wr;
   s.gen = k->gen;
+  s.scheme = k->kind == AMG_K_GENERATORS ? SCHEME_SHIFTED : k->scheme;
   return s;
 }
 
@@ -714,6 +715,7 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
   const KernelSpec ks = spec_of(kernel, kernel->kind == AMG_K_GENERATORS ? 0.25 : delta);
   if (!validate(ks, N, o.coarsest_log2).empty()) return AMG_EINVAL;
   if (kernel->kind != AMG_K_GENERATORS && !(std::isfinite(delta))) return AMG_EINVAL;
+  if (!ks.supported()) return AMG_ENOTSUP;
   amg_ctx* c = new (std::nothrow) amg_ctx();
   if (!c) return AMG_ENOMEM;
   c->N = N;
@@ -1041,7 +1043,34 @@ int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, do
   if (!kernel || !b_host || kernel->kind == AMG_K_GENERATORS) return AMG_EINVAL;
   const KernelSpec ks = spec_of(kernel, delta);
   if (!validate(ks, N, 2).empty() || !std::isfinite(delta)) return AMG_EINVAL;
+  if (!ks.supported()) return AMG_ENOTSUP;
   manufactured_rhs(ks, N, b_host);
+  return AMG_OK;
+}
+
+int64_t amg_volume_reach(const amg_kernel_t* kernel, double delta, int64_t N) {
+  if (!kernel || kernel->kind == AMG_K_GENERATORS) return AMG_EINVAL;
+  const KernelSpec ks = spec_of(kernel, delta);
+  if (!validate(ks, N, 2).empty() || !std::isfinite(delta)) return AMG_EINVAL;
+  if (!ks.supported()) return AMG_ENOTSUP;
+  try {
+    return volume_reach(ks, N);
+  } catch (const std::bad_alloc&) {
+    return AMG_ENOMEM;
+  }
+}
+
+int amg_volume_rhs(const amg_kernel_t* kernel, double delta, int64_t N, const double* g_left,
+                   const double* g_right, double* b) {
+  if (!kernel || !g_left || !g_right || !b || kernel->kind == AMG_K_GENERATORS) return AMG_EINVAL;
+  const KernelSpec ks = spec_of(kernel, delta);
+  if (!validate(ks, N, 2).empty() || !std::isfinite(delta)) return AMG_EINVAL;
+  if (!ks.supported()) return AMG_ENOTSUP;
+  try {
+    volume_correction(ks, N, g_left, g_right, b);
+  } catch (const std::bad_alloc&) {
+    return AMG_ENOMEM;
+  }
   return AMG_OK;
 }
 
@@ -1054,7 +1083,9 @@ int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
   if (check_opts(&o) != AMG_OK) return AMG_EINVAL;
   const KernelSpec ks = spec_of(kernel, kernel->kind == AMG_K_GENERATORS ? 0.25 : delta);
   if (!validate(ks, N, o.coarsest_log2).empty()) return AMG_EINVAL;
-  return footprint(N, &o, kernel->kind == AMG_K_CONST || kernel->kind == AMG_K_FRACTIONAL);
+  if (!ks.supported()) return AMG_ENOTSUP;
+  return footprint(N, &o, (kernel->kind == AMG_K_CONST || kernel->kind == AMG_K_FRACTIONAL) &&
+                              ks.scheme == SCHEME_SHIFTED);
 }
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 #include "amg_host.hpp"
 
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <sstream>
 
@@ -99,6 +100,7 @@ std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2) {
     e << "fractional kernel needs 0 < alpha < 1/2; ";
   if (k.kind == K_WEIGHTED && !(std::isfinite(k.wl) && std::isfinite(k.wr) && k.wl > 0 && k.wr > 0))
     e << "weights must be positive; ";
+  if (k.scheme != SCHEME_SHIFTED && k.scheme != SCHEME_STANDARD) e << "unknown scheme; ";
   return e.str();
 }
 
@@ -147,6 +149,152 @@ std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
   return W;
 }
 
+std::vector<double> midpoint_stencil_standard(const KernelSpec& k, int64_t N, int64_t* Sout) {
+  const double h = 1.0 / (double)N;
+  const double R = k.delta * (double)N;  // exact: N is a power of two
+  const double c = kernel_c(k) * h;
+  const double wr = (k.kind == K_WEIGHTED) ? k.wr : 1.0;
+  const double wl = (k.kind == K_WEIGHTED) ? k.wl : 1.0;
+  // right side t in [0, delta] in units of h: [0, min(1/2, R)] from the
+  // central cell, then [kc - 1/2, min(kc + 1/2, R)], kc = 1, 2, ...
+  int64_t klast = 0;
+  while ((double)(klast + 1) - 0.5 < R) ++klast;
+  const int64_t S = 2 * klast + 1;
+  std::vector<double> W(2 * S + 1, 0.0);
+  for (int64_t kc = 0; kc <= klast; ++kc) {
+    const double a = kc == 0 ? 0.0 : (double)kc - 0.5;
+    const double b = std::min((double)kc + 0.5, R);
+    // moments in s = tau - kc; quadratic through s = -1/2 (node), 0 (midpoint),
+    // +1/2 (node): l_- = 2 s^2 - s, l_0 = 1 - 4 s^2, l_+ = 2 s^2 + s
+    const double sa = a - (double)kc, sb = b - (double)kc;
+    const double J0 = c * (sb - sa);
+    const double J1 = c * (sb * sb - sa * sa) / 2.0;
+    const double J2 = c * (sb * sb * sb - sa * sa * sa) / 3.0;
+    const double Im = 2 * J2 - J1, I0 = J0 - 4 * J2, Ip = 2 * J2 + J1;
+    W[S] += (wr + wl) * J0;
+    if (kc == 0) {
+      W[S] -= (wr + wl) * I0;
+    } else {
+      W[S + 2 * kc] -= wr * I0;
+      W[S - 2 * kc] -= wl * I0;
+    }
+    W[S + 2 * kc - 1] -= wr * Im;
+    W[S - 2 * kc + 1] -= wl * Im;
+    W[S + 2 * kc + 1] -= wr * Ip;
+    W[S - 2 * kc - 1] -= wl * Ip;
+  }
+  *Sout = S;
+  return W;
+}
+
+namespace {
+
+// node-row and midpoint-row stencils of the kernel's scheme
+void both_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
+                   std::vector<double>& Wm, int64_t& Sm) {
+  Wn = row_stencil(k, N, &Sn);
+  if (k.scheme == SCHEME_STANDARD) {
+    Wm = midpoint_stencil_standard(k, N, &Sm);
+  } else {
+    Wm = Wn;
+    Sm = Sn;
+  }
+}
+
+// In-place power-of-two complex FFT (iterative radix 2), twiddles evaluated
+// in long double; forward e^{-2 pi i jk/n}, inverse unnormalised.
+void fft_pow2(std::vector<std::complex<double>>& a, bool inv) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<std::complex<double>> w;
+  for (size_t len = 2; len <= n; len <<= 1) {
+    const size_t half = len / 2;
+    w.resize(half);
+    for (size_t k = 0; k < half; ++k) {
+      const long double ang = (inv ? 2.0L : -2.0L) * pi * (long double)k / (long double)len;
+      w[k] = {(double)std::cos(ang), (double)std::sin(ang)};
+    }
+    for (size_t i = 0; i < n; i += len)
+      for (size_t k = 0; k < half; ++k) {
+        const std::complex<double> u = a[i + k], v = a[i + k + half] * w[k];
+        a[i + k] = u + v;
+        a[i + k + half] = u - v;
+      }
+  }
+}
+
+// out[m] = sum_{k=0..S} V[m + k] g[k] for m = 0..S (V has S+1 entries,
+// zero beyond): a correlation, computed directly for a short reach and as a
+// convolution with the reversed g through one complex FFT pair otherwise.
+std::vector<double> correlate(const std::vector<double>& V, const double* g, int64_t S) {
+  std::vector<double> out((size_t)S + 1, 0.0);
+  if ((S + 1) * (S + 1) <= (int64_t(1) << 22)) {
+    for (int64_t m = 0; m <= S; ++m) {
+      double acc = 0.0;
+      for (int64_t k = 0; k <= S && m + k < (int64_t)V.size(); ++k) acc += V[m + k] * g[k];
+      out[m] = acc;
+    }
+    return out;
+  }
+  size_t n = 1;
+  while (n < V.size() + (size_t)S + 1) n <<= 1;
+  std::vector<std::complex<double>> x(n), y(n);
+  for (size_t i = 0; i < V.size(); ++i) x[i] = V[i];
+  for (int64_t i = 0; i <= S; ++i) y[(size_t)i] = g[S - i];  // reversed g
+  fft_pow2(x, false);
+  fft_pow2(y, false);
+  for (size_t i = 0; i < n; ++i) x[i] *= y[i];
+  fft_pow2(x, true);
+  const double inv_n = 1.0 / (double)n;
+  for (int64_t m = 0; m <= S; ++m) out[m] = x[(size_t)(m + S)].real() * inv_n;
+  return out;
+}
+
+}  // namespace
+
+int64_t volume_reach(const KernelSpec& k, int64_t N) {
+  std::vector<double> Wn, Wm;
+  int64_t Sn, Sm;
+  both_stencils(k, N, Wn, Sn, Wm, Sm);
+  return std::max(Sn, Sm);
+}
+
+void volume_correction(const KernelSpec& k, int64_t N, const double* gl, const double* gr,
+                       double* b) {
+  std::vector<double> Wn, Wm;
+  int64_t Sn, Sm;
+  both_stencils(k, N, Wn, Sn, Wm, Sm);
+  const int64_t S = std::max(Sn, Sm);
+  const int64_t M = 2 * N - 1;
+  // row at interleaved position p (1..M; even: node, odd: midpoint) couples
+  // to the left exterior point -k with W(-(p + k)) and to the right one
+  // 2N + k with W(2N + k - p); with m = p (left) or m = 2N - p (right) both
+  // are sums over k of V[m + k] g[k], V[j] = W(-j) or W(+j).
+  for (int side = 0; side < 2; ++side) {
+    const double* g = side == 0 ? gl : gr;
+    for (int type = 0; type < 2; ++type) {  // 0: node rows, 1: midpoint rows
+      const std::vector<double>& W = type == 0 ? Wn : Wm;
+      const int64_t Sw = type == 0 ? Sn : Sm;
+      std::vector<double> V((size_t)S + 1, 0.0);
+      for (int64_t j = 0; j <= Sw; ++j) V[(size_t)j] = W[(size_t)(Sw + (side == 0 ? -j : j))];
+      const std::vector<double> corr = correlate(V, g, S);
+      for (int64_t m = 1; m <= S; ++m) {
+        const int64_t p = side == 0 ? m : 2 * N - m;
+        if (p < 1 || p > M || (p % 2 == 0) != (type == 0)) continue;
+        // block order: node i at x = i h -> index i - 1; midpoint (j - 1/2) h -> N - 1 + j - 1
+        const int64_t idx = (p % 2 == 0) ? p / 2 - 1 : (N - 1) + (p + 1) / 2 - 1;
+        b[idx] -= corr[(size_t)m];
+      }
+    }
+  }
+}
+
 TpxLevel finest_level(const KernelSpec& k, int64_t N) {
   TpxLevel t;
   const int64_t n = N - 1;
@@ -183,23 +331,26 @@ TpxLevel finest_level(const KernelSpec& k, int64_t N) {
     t.o = D(0);
     return t;
   }
-  int64_t S = 0;
-  const std::vector<double> W = row_stencil(k, N, &S);
-  auto Wat = [&](int64_t s2) { return (s2 < -S || s2 > S) ? 0.0 : W[s2 + S]; };
+  std::vector<double> Wn, Wm;
+  int64_t Sn = 0, Sm = 0;
+  both_stencils(k, N, Wn, Sn, Wm, Sm);
+  auto node = [&](int64_t s2) { return (s2 < -Sn || s2 > Sn) ? 0.0 : Wn[s2 + Sn]; };
+  auto mid = [&](int64_t s2) { return (s2 < -Sm || s2 > Sm) ? 0.0 : Wm[s2 + Sm]; };
   // Interleaved positions: v_i at 2(i+1), w_o at 1, w_bar_j at 2j+3 (units h/2).
+  // Node rows: A, B_bar, p; midpoint rows: C_bar, D_bar, q, xi, zeta, o.
   for (int64_t dd = -(n - 1); dd <= n - 1; ++dd) {
-    t.a[dd + n - 1] = Wat(2 * dd);
-    t.b[dd + n - 1] = Wat(2 * dd + 1);
-    t.c[dd + n - 1] = Wat(2 * dd - 1);
-    t.d[dd + n - 1] = Wat(2 * dd);
+    t.a[dd + n - 1] = node(2 * dd);
+    t.b[dd + n - 1] = node(2 * dd + 1);
+    t.c[dd + n - 1] = mid(2 * dd - 1);
+    t.d[dd + n - 1] = mid(2 * dd);
   }
   for (int64_t i = 0; i < n; ++i) {
-    t.p[i] = Wat(-2 * i - 1);
-    t.q[i] = Wat(2 * i + 1);
-    t.xi[i] = Wat(-2 * i - 2);
-    t.zeta[i] = Wat(2 * i + 2);
+    t.p[i] = node(-2 * i - 1);
+    t.q[i] = mid(2 * i + 1);
+    t.xi[i] = mid(-2 * i - 2);
+    t.zeta[i] = mid(2 * i + 2);
   }
-  t.o = Wat(0);
+  t.o = mid(0);
   return t;
 }
 

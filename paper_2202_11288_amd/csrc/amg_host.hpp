@@ -11,12 +11,17 @@ namespace amg {
 
 enum KernelKind { K_CONST = 0, K_WEIGHTED = 1, K_FRACTIONAL = 2, K_GENERATORS = 3 };
 
+enum Scheme { SCHEME_SHIFTED = 0, SCHEME_STANDARD = 1 };
+
 struct KernelSpec {
   int kind = K_CONST;
   double delta = 0.25;
   double alpha = 0.0;
   double wl = 1.0, wr = 1.0;
   const double* gen = nullptr;
+  int scheme = SCHEME_SHIFTED;
+  // the standard rule is set up for the constant and weighted kernels
+  bool supported() const { return !(scheme == SCHEME_STANDARD && kind == K_FRACTIONAL); }
 };
 
 // One level in the Toeplitz-like-plus-Cross form (eq. (split01)):
@@ -38,6 +43,21 @@ std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2);
 // Row stencil W[s2 + S], s2 in [-S, S], in half-grid offsets (shifted-symmetric
 // collocation: every row has this stencil).
 std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* S);
+
+// Midpoint-row stencil of the standard collocation (eq. (ccs2.6)): the row at
+// a midpoint integrates over the mesh cells [(k-1/2)h, (k+1/2)h] around it,
+// the central one holding the point as its midpoint, the last one cut at the
+// horizon.  W[s2 + S], s2 in [-S, S] (odd s2: nodes, even: midpoints).
+std::vector<double> midpoint_stencil_standard(const KernelSpec& k, int64_t N, int64_t* S);
+
+// Reach S (half-grid steps) of the node- and midpoint-row stencils.
+int64_t volume_reach(const KernelSpec& k, int64_t N);
+
+// b -= E g for the volume data g_left[k] = g(-k h/2), g_right[k] = g(1 + k h/2),
+// k = 0..S (block-ordered b).  Direct sums for a short reach, FFT convolution
+// beyond.
+void volume_correction(const KernelSpec& k, int64_t N, const double* g_left,
+                       const double* g_right, double* b);
 
 // Finest level from the kernel stencil or from caller generators.
 TpxLevel finest_level(const KernelSpec& k, int64_t N);

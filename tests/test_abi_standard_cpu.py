@@ -1,0 +1,166 @@
+"""C-ABI host logic of the standard collocation (eq. (ccs2.6)) and of the
+volume data of Sec. 2.2, against the oracle (no GPU: host-only handles and
+the host-side right-hand-side routine)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import discretize as D
+from oracle import tpx
+from paper_2202_11288_amd import binding as B
+
+STD, SHF = B.AMG_SCHEME_STANDARD, B.AMG_SCHEME_SHIFTED
+OSCH = {STD: D.STANDARD, SHF: D.SHIFTED}
+
+KERNELS = [
+    (dict(kind=B.AMG_K_CONST), dict(kind=D.CONST), 0.25),
+    (dict(kind=B.AMG_K_CONST), dict(kind=D.CONST), 0.05),
+    (dict(kind=B.AMG_K_CONST), dict(kind=D.CONST), 0.0371),  # horizon off the mesh
+    (dict(kind=B.AMG_K_WEIGHTED, wl=1.2, wr=0.8), dict(kind=D.WEIGHTED, wl=1.2, wr=0.8), 0.05),
+]
+IDS = ["const-0.25", "const-0.05", "const-0.0371", "weighted-0.05"]
+
+
+def _kernels(kp, scheme):
+    kb, ko, delta = kp
+    return B.kernel(scheme=scheme, **kb), D.Kernel(ko["kind"], delta, wl=ko.get("wl", 1.0),
+                                                  wr=ko.get("wr", 1.0)), delta
+
+
+@pytest.mark.parametrize("kp", KERNELS, ids=IDS)
+@pytest.mark.parametrize("N,cl", [(64, 4), (1024, 5), (2048, 7)])
+def test_host_setup_standard_matches_oracle(kp, N, cl):
+    """Finest level from the node- and midpoint-row stencils and the Galerkin
+    hierarchy of Lemma 3.1 on it: library (C++) equals oracle."""
+    kern, okern, delta = _kernels(kp, STD)
+    h = B.amg_setup(kern, delta, N, B.amg_default_opts(flags=B.AMG_FLAG_HOST_ONLY, coarsest_log2=cl))
+    try:
+        Ts = [tpx.from_stencil(okern, N, D.STANDARD)]
+        while Ts[-1].n > 2 ** cl - 1:
+            Ts.append(tpx.coarsen(Ts[-1]))
+        assert B.amg_num_levels(h) == len(Ts)
+        for l, To in enumerate(Ts):
+            T = B.amg_level_tpx(h, l)
+            scale = np.abs(To.a).max()
+            for key in ("a", "b", "c", "d", "p", "q", "xi", "zeta"):
+                np.testing.assert_allclose(T[key], getattr(To, key), rtol=0,
+                                           atol=1e-14 * scale, err_msg=f"level {l} {key}")
+            assert abs(T["o"] - To.o) <= 1e-14 * scale
+        # the standard scheme is not symmetric: C_bar differs from B_bar^T
+        T0 = B.amg_level_tpx(h, 0)
+        assert np.abs(T0["c"] - T0["b"][::-1]).max() > 1e-8 * np.abs(T0["a"]).max()
+    finally:
+        B.amg_destroy(h)
+
+
+def _volume_case(kp, scheme, N, seed):
+    kern, okern, delta = _kernels(kp, scheme)
+    S = B.amg_volume_reach(kern, delta, N)
+    assert S == D.volume_reach(okern, N, OSCH[scheme])
+    rng = np.random.default_rng(seed)
+    gl, gr = rng.standard_normal(S + 1), rng.standard_normal(S + 1)
+    b0 = rng.standard_normal(2 * N - 1)
+    b = B.amg_volume_rhs(kern, delta, N, gl, gr, b0.copy())
+    ref = b0 - D.volume_correction(okern, N, gl, gr, OSCH[scheme])
+    W, Sw = D.stencil(okern, N)
+    # each entry sums at most S + 1 terms |W| |g| per side
+    tol = 8 * (S + 1) * np.finfo(float).eps * np.abs(W).max() * max(np.abs(gl).max(), np.abs(gr).max())
+    return b, ref, tol
+
+
+@pytest.mark.parametrize("scheme", [SHF, STD])
+@pytest.mark.parametrize("kp", KERNELS, ids=IDS)
+@pytest.mark.parametrize("N", [16, 64, 512])
+def test_volume_rhs_matches_oracle(kp, scheme, N):
+    """b - E g, direct sums (short reach)."""
+    b, ref, tol = _volume_case(kp, scheme, N, seed=N + 7 * scheme)
+    np.testing.assert_allclose(b, ref, rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("scheme", [SHF, STD])
+def test_volume_rhs_long_reach_fft(scheme):
+    """Reach beyond 2047 half-steps: the library switches to an FFT
+    correlation; same numbers as the oracle's row sums within the FFT's
+    rounding (relative ~log2(n) eps of the largest term sum)."""
+    kp = KERNELS[0]  # delta = 1/4
+    N = 8192
+    b, ref, tol = _volume_case(kp, scheme, N, seed=3)
+    assert B.amg_volume_reach(_kernels(kp, scheme)[0], 0.25, N) > 2047
+    np.testing.assert_allclose(b, ref, rtol=0, atol=16 * tol)
+
+
+def test_volume_rhs_fractional_shifted():
+    """The fractional kernel under the shifted rule also reaches the interaction
+    volume; same row sums."""
+    kern = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.3)
+    okern = D.Kernel(D.FRACTIONAL, 0.1, alpha=0.3)
+    N = 256
+    S = B.amg_volume_reach(kern, 0.1, N)
+    rng = np.random.default_rng(5)
+    gl, gr = rng.standard_normal(S + 1), rng.standard_normal(S + 1)
+    b = B.amg_volume_rhs(kern, 0.1, N, gl, gr, np.zeros(2 * N - 1))
+    ref = -D.volume_correction(okern, N, gl, gr)
+    np.testing.assert_allclose(b, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def _status(fn, kern, delta=0.1, N=256, **extra):
+    if fn == "setup":
+        o = B.amg_default_opts(flags=B.AMG_FLAG_HOST_ONLY)
+        h = ctypes.c_void_p()
+        st = B.lib.amg_setup(ctypes.byref(kern), delta, N, ctypes.byref(o), None, ctypes.byref(h))
+        if st == B.AMG_OK:
+            B.lib.amg_destroy(h)
+        return st
+    if fn == "reach":
+        return B.lib.amg_volume_reach(ctypes.byref(kern), delta, N)
+    if fn == "footprint":
+        return B.lib.amg_footprint_bytes(ctypes.byref(kern), delta, N, None)
+    buf = np.zeros(2 * N - 1)
+    DP = ctypes.POINTER(ctypes.c_double)
+    if fn == "rhs":
+        return B.lib.amg_manufactured_rhs(ctypes.byref(kern), delta, N, buf.ctypes.data_as(DP))
+    g = np.zeros(2 * N)
+    gp = None if extra.get("null_g") else g.ctypes.data_as(DP)
+    return B.lib.amg_volume_rhs(ctypes.byref(kern), delta, N, gp, g.ctypes.data_as(DP),
+                                buf.ctypes.data_as(DP))
+
+
+@pytest.mark.parametrize("fn", ["setup", "reach", "footprint", "rhs", "volume"])
+def test_scheme_argument_checks(fn):
+    """Standard + fractional is AMG_ENOTSUP; an unknown scheme is AMG_EINVAL;
+    the standard scheme is accepted for the constant and weighted kernels."""
+    frac = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.3, scheme=STD)
+    assert _status(fn, frac) == B.AMG_ENOTSUP
+    assert _status(fn, B.kernel(B.AMG_K_CONST, scheme=2)) == B.AMG_EINVAL
+    assert _status(fn, B.kernel(B.AMG_K_CONST, scheme=-1)) == B.AMG_EINVAL
+    for k in (B.kernel(B.AMG_K_CONST, scheme=STD), B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8,
+                                                              scheme=STD)):
+        assert _status(fn, k) >= 0
+
+
+def test_volume_argument_checks():
+    k = B.kernel(B.AMG_K_CONST)
+    assert _status("volume", k, null_g=True) == B.AMG_EINVAL
+    assert _status("volume", k, N=100) == B.AMG_EINVAL
+    assert _status("volume", k, delta=0.5) == B.AMG_EINVAL
+    assert _status("reach", B.kernel(B.AMG_K_GENERATORS)) == B.AMG_EINVAL
+    with pytest.raises(ValueError):
+        B.amg_volume_rhs(k, 0.1, 64, np.zeros(3), np.zeros(3), np.zeros(127))
+
+
+def test_generators_ignore_scheme():
+    """AMG_K_GENERATORS carries its own blocks: the scheme field is ignored."""
+    N = 64
+    gen = np.zeros(8 * N - 8)
+    gen[(2 * N - 3) // 2] = 4.0  # diagonal of A
+    gen[(2 * N - 3) + (2 * N - 2) + (2 * N - 2) + (2 * N - 1) // 2] = 4.0  # diagonal of D
+    assert _status("setup", B.kernel(B.AMG_K_GENERATORS, gen=gen, scheme=7), N=N) == B.AMG_OK
+
+
+def test_standard_footprint_counts_nonsymmetric_levels():
+    k_shf = B.kernel(B.AMG_K_CONST)
+    k_std = B.kernel(B.AMG_K_CONST, scheme=STD)
+    assert B.amg_footprint_bytes(k_std, 0.1, 2 ** 16) >= B.amg_footprint_bytes(k_shf, 0.1, 2 ** 16)

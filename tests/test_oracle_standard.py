@@ -84,3 +84,18 @@ def test_standard_tpx_level_and_vcycle():
     x, it, hist = tpx.solve(H, b, tol=1e-10, max_iter=100)
     assert hist[-1] < 1e-10 and it <= 15
     assert np.abs(x - np.linalg.solve(A, b)).max() <= 1e-8 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("scheme", [D.STANDARD, D.SHIFTED])
+def test_volume_correction_rows_equal_dense_exterior(scheme):
+    """The row-by-row volume correction equals the dense exterior block times
+    g (same stencils, two ways of summing)."""
+    kern = D.Kernel(D.WEIGHTED, 0.1, wl=1.2, wr=0.8)
+    N = 64
+    A, E, q = D.assemble_with_exterior(kern, N, scheme)
+    S = D.volume_reach(kern, N, scheme)
+    gl = D.u_poly6(-np.arange(S + 1) / (2.0 * N))
+    gr = D.u_poly6(1.0 + np.arange(S + 1) / (2.0 * N))
+    ge = D.u_poly6(q / (2.0 * N))
+    np.testing.assert_allclose(D.volume_correction(kern, N, gl, gr, scheme), E @ ge,
+                               rtol=1e-13, atol=1e-12 * np.abs(E).max())
