@@ -110,7 +110,20 @@ typedef struct {
   int max_iter;               /* outer iterations                            */
   int flags;                  /* AMG_FLAG_* bits, 0 by default               */
   int inner;                  /* AMG_INNER_VCYCLE (default) or AMG_INNER_PCG */
+  double shift, scale;        /* operator shift*I + scale*A (defaults 0, 1)  */
 } amg_opts_t;
+
+/* Shifted operators (Sec. 5, eq. (bdf4)).  With shift = sigma and scale = s
+   the handle solves (sigma I + s A) x = b, A the collocation matrix of the
+   kernel: the finest level's Toeplitz generators and Cross data are
+   multiplied by s and sigma is added to its diagonal (a_0, d_0, o); the
+   coarse levels are the Galerkin images of that level (Lemma 3.1), so one
+   hierarchy serves every time step of a fixed (sigma, s).  A BDF4 step at
+   time step tau has sigma = 25/12, s = tau (times the ratio of the caller's
+   kernel constant to this library's normalised one: 2 for the paper's
+   3 delta^-3).  scale must be finite and > 0, shift finite (AMG_EINVAL
+   otherwise).  The volume correction E g of amg_volume_rhs belongs to A:
+   scale it by s. */
 
 /* Outer iteration of amg_solve.
    AMG_INNER_VCYCLE: the stationary iteration x <- x + B_K (b - A x) of the
@@ -233,6 +246,19 @@ int amg_profile_stats(amg_t h, amg_stat_t* out, int cap, int reset);
  * block order; host output b_host (2N-1 doubles).  Same kernel/delta/N rules
  * as amg_setup (AMG_K_GENERATORS is AMG_EINVAL). */
 int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, double* b_host);
+
+/* One step of the fourth-order backward differentiation formula (Sec. 5,
+   eq. (bdf4)) on a handle with shift = 25/12 and scale = tau (see above):
+     b = 4 u1 - 3 u2 + (4/3) u3 - (1/4) u4 + src,   x <- u1,
+   then amg_solve(h, b, x, tol, ...) from that initial guess.  u1..u4 are
+   U^{k-1}..U^{k-4}, src = tau (F^k - E g^k) (NULL: zero), x receives U^k; all
+   device arrays of 2N-1 doubles in block order on the handle's device.  x may
+   be one of u1..u4 (b is formed before x is written); it must not be src.
+   b lives in a handle-owned buffer allocated by the first call (8 (2N-1)
+   bytes).  Same status, iters and relres as amg_solve. */
+int amg_bdf4_step(amg_t h, const double* u1, const double* u2, const double* u3,
+                  const double* u4, const double* src, double* x, double tol, void* stream,
+                  int* iters, double* relres);
 
 /* Volume data (Sec. 2.2: u = g on the interaction volume).  The rows near
  * x = 0 and x = 1 couple to the exterior collocation points x = -k h/2 and

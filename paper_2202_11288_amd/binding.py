@@ -43,7 +43,7 @@ class amg_opts_t(ctypes.Structure):
     _fields_ = [("m1", ctypes.c_int), ("m2", ctypes.c_int), ("omega_pre", ctypes.c_double),
                 ("omega_post", ctypes.c_double), ("coarsest_log2", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("flags", ctypes.c_int),
-                ("inner", ctypes.c_int)]
+                ("inner", ctypes.c_int), ("shift", ctypes.c_double), ("scale", ctypes.c_double)]
 
 
 class amg_stat_t(ctypes.Structure):
@@ -75,6 +75,7 @@ def _load():
         "amg_vcycle": (I, [P, P, P, P]),
         "amg_solve": (I, [P, P, P, D, P, IP, DP]),
         "amg_residual_history": (I, [P, DP, I]),
+        "amg_bdf4_step": (I, [P, P, P, P, P, P, P, D, P, IP, DP]),
         "amg_solve_batch": (I, [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                 DP, P, IP, DP]),
         "amg_profile_stats": (I, [P, ctypes.POINTER(amg_stat_t), I, I]),
@@ -189,6 +190,19 @@ def amg_solve(h, b, x, tol: float, stream=None, allow=(AMG_OK,)):
     st = lib.amg_solve(h, _ptr(b), _ptr(x), float(tol), _stream(stream), ctypes.byref(it),
                        ctypes.byref(rr))
     _check(st, "amg_solve", ok=allow)
+    return st, it.value, rr.value
+
+
+def amg_bdf4_step(h, hist, src, x, tol: float, stream=None, allow=(AMG_OK,)):
+    """hist = (U^{k-1}, U^{k-2}, U^{k-3}, U^{k-4}); src = tau (F^k - E g^k) or
+    None.  Returns (status, iters, relres)."""
+    if len(hist) != 4:
+        raise ValueError("BDF4 needs four previous time levels")
+    it = ctypes.c_int()
+    rr = ctypes.c_double()
+    st = lib.amg_bdf4_step(h, *[_ptr(u) for u in hist], _ptr(src), _ptr(x), float(tol),
+                           _stream(stream), ctypes.byref(it), ctypes.byref(rr))
+    _check(st, "amg_bdf4_step", ok=allow)
     return st, it.value, rr.value
 
 

@@ -209,6 +209,8 @@ struct amg_ctx {
   double* cg_q = nullptr;
   double* cg_rold = nullptr;
   double* cg_part = nullptr;
+  // right-hand side of amg_bdf4_step (allocated by its first call)
+  double* step_b = nullptr;
 };
 
 namespace {
@@ -282,6 +284,7 @@ int check_opts(const amg_opts_t* o) {
   if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
   if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE | AMG_FLAG_EAGER)) return AMG_EINVAL;
   if (o->inner != AMG_INNER_VCYCLE && o->inner != AMG_INNER_PCG) return AMG_EINVAL;
+  if (!(std::isfinite(o->scale) && o->scale > 0.0) || !std::isfinite(o->shift)) return AMG_EINVAL;
   return AMG_OK;
 }
 
@@ -688,6 +691,8 @@ void amg_default_opts(amg_opts_t* o) {
   o->max_iter = 200;
   o->flags = 0;
   o->inner = AMG_INNER_VCYCLE;
+  o->shift = 0.0;
+  o->scale = 1.0;
 }
 
 const char* amg_strerror(int st) {
@@ -725,6 +730,7 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
   c->mixed = o.precision == AMG_MIXED;
   try {
     c->host.push_back(finest_level(ks, N));
+    if (o.shift != 0.0 || o.scale != 1.0) shift_level(c->host[0], o.shift, o.scale);
     const int64_t nc = (int64_t(1) << o.coarsest_log2) - 1;
     while (c->host.back().n > nc) c->host.push_back(coarsen(c->host.back()));
   } catch (const std::bad_alloc&) {
@@ -960,6 +966,20 @@ int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int
     AMG_TRY(solve_round(h, b, x, tol, s, round));
   }
   return solve_end(h, s, iters, relres);
+}
+
+int amg_bdf4_step(amg_t h, const double* u1, const double* u2, const double* u3,
+                  const double* u4, const double* src, double* x, double tol, void* stream,
+                  int* iters, double* relres) {
+  if (!h || h->host_only || !u1 || !u2 || !u3 || !u4 || !x || x == src) return AMG_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return AMG_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t m = 2 * h->N - 1;
+  if (!h->step_b) AMG_TRY(dalloc(h, &h->step_b, (size_t)m));
+  HIP_TRY(launch_bdf4_rhs(u1, u2, u3, u4, src, h->step_b, m, s));
+  if (x != u1) HIP_TRY(hipMemcpyAsync(x, u1, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return amg_solve(h, h->step_b, x, tol, stream, iters, relres);
 }
 
 int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const* x,

@@ -157,6 +157,12 @@ template <typename TZ>
 hipError_t launch_cg_dir(const SolveState* st, double* p, const TZ* z, int64_t m, int first,
                          hipStream_t s);
 
+// b = 4 u1 - 3 u2 + (4/3) u3 - (1/4) u4 + src (src may be null): the BDF4
+// right-hand side
+hipError_t launch_bdf4_rhs(const double* u1, const double* u2, const double* u3,
+                           const double* u4, const double* src, double* b, int64_t m,
+                           hipStream_t s);
+
 // Column tiles / grid sizes used by the launchers (host helpers).
 inline int col_blocks(int logL1, int tcols) { return (1 << logL1) / tcols; }
 

@@ -295,6 +295,14 @@ void volume_correction(const KernelSpec& k, int64_t N, const double* gl, const d
   }
 }
 
+void shift_level(TpxLevel& t, double shift, double scale) {
+  for (auto* v : {&t.a, &t.b, &t.c, &t.d, &t.p, &t.q, &t.xi, &t.zeta})
+    for (double& x : *v) x *= scale;
+  t.o = t.o * scale + shift;
+  t.a[t.n - 1] += shift;
+  t.d[t.n - 1] += shift;
+}
+
 TpxLevel finest_level(const KernelSpec& k, int64_t N) {
   TpxLevel t;
   const int64_t n = N - 1;

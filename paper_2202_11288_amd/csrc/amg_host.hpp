@@ -59,6 +59,10 @@ int64_t volume_reach(const KernelSpec& k, int64_t N);
 void volume_correction(const KernelSpec& k, int64_t N, const double* g_left,
                        const double* g_right, double* b);
 
+// t <- shift*I + scale*t (generators and Cross data times scale, shift on
+// the diagonal entries a_0, d_0 and o).
+void shift_level(TpxLevel& t, double shift, double scale);
+
 // Finest level from the kernel stencil or from caller generators.
 TpxLevel finest_level(const KernelSpec& k, int64_t N);
 

@@ -568,6 +568,17 @@ __global__ __launch_bounds__(kVecNT) void k_cg_update(const SolveState* st, doub
   if (threadIdx.x == 0) npart[blockIdx.x] = ss;
 }
 
+// BDF4 history combination of eq. (bdf4), one element per thread
+__global__ __launch_bounds__(kVecNT) void k_bdf4_rhs(const double* u1, const double* u2,
+                                                     const double* u3, const double* u4,
+                                                     const double* src, double* b, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
+  if (i >= m) return;
+  double v = 4.0 * u1[i] - 3.0 * u2[i] + (4.0 / 3.0) * u3[i] - 0.25 * u4[i];
+  if (src) v += src[i];
+  b[i] = v;
+}
+
 template <typename TZ>
 __global__ __launch_bounds__(kVecNT) void k_cg_dir(const SolveState* st, double* p, const TZ* z,
                                                    int64_t m, int first) {
@@ -659,6 +670,14 @@ hipError_t launch_cg_dir(const SolveState* st, double* p, const TZ* z, int64_t m
                          hipStream_t s) {
   const int grid = (int)((m + kVecNT - 1) / kVecNT);
   hipLaunchKernelGGL(k_cg_dir<TZ>, grid, kVecNT, 0, s, st, p, z, m, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_bdf4_rhs(const double* u1, const double* u2, const double* u3,
+                           const double* u4, const double* src, double* b, int64_t m,
+                           hipStream_t s) {
+  const int grid = (int)((m + kVecNT - 1) / kVecNT);
+  hipLaunchKernelGGL(k_bdf4_rhs, grid, kVecNT, 0, s, u1, u2, u3, u4, src, b, m);
   return hipGetLastError();
 }
 
