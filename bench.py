@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--prof-steps", type=int, default=3,
                     help="solves of the profiled pass (HIP events around the finest-level "
                          "passes, eager launches) that gives the roofline; 0 = skip")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="instances of the uneven batch (seeded N, delta, kernel, random b) "
+                         "solved together by amg_solve_batch beside the headline; 0 = skip")
     ap.add_argument("--pmc-driver", action="store_true",
                     help="the short program the --pmc counter runs profile: a plain copy of "
                          "known size, then two mixed solves of the workload (eager launches)")
@@ -267,6 +270,75 @@ def summary(res, N):
             "setup_s": round(res["setup_s"], 3)}
 
 
+def batch_instances(count, seed=0):
+    """The uneven batch: N = 2^K with K uniform on 10..16, delta uniform on
+    [0.05, 0.3], constant or fractional kernel with even odds, b ~ N(0, 1) per
+    unknown.  alpha is uniform on [0.2, 0.45]: the product-integration weights
+    of the fractional kernel are finite only below 1/2, and the V-cycle-CG
+    iteration count grows without bound as alpha nears 1/2 (about 140 at
+    alpha = 0.45, N = 2^14; as many at alpha = 0.49 already at N = 2^10)."""
+    rng = np.random.default_rng(seed)
+    K = rng.integers(10, 17, size=count)
+    delta = rng.uniform(0.05, 0.3, size=count)
+    frac = rng.integers(0, 2, size=count)
+    alpha = rng.uniform(0.2, 0.45, size=count)
+    out = []
+    for i in range(count):
+        N = 2 ** int(K[i])
+        out.append(dict(N=N, delta=float(delta[i]), frac=bool(frac[i]), alpha=float(alpha[i]),
+                        b=rng.standard_normal(2 * N - 1)))
+    return out
+
+
+def run_batch(B, torch, args):
+    """All instances in one amg_solve_batch call (internal streams, graph-
+    replayed V-cycles), mixed precision, V-cycle-preconditioned CG (every
+    instance is symmetric positive definite), tol as the headline.  One
+    untimed batch first (it captures each handle's V-cycle graph), then the
+    timed one from x_0 = 0."""
+    inst = batch_instances(args.batch)
+    opts = B.amg_default_opts(precision=B.AMG_MIXED, inner=B.AMG_INNER_PCG, max_iter=500)
+    hs, bs, xs = [], [], []
+    t0 = time.perf_counter()
+    try:
+        for d in inst:
+            k = (B.kernel(B.AMG_K_FRACTIONAL, alpha=d["alpha"]) if d["frac"]
+                 else B.kernel(B.AMG_K_CONST))
+            hs.append(B.amg_setup(k, d["delta"], d["N"], opts))
+            bs.append(torch.from_numpy(d["b"]).cuda())
+            xs.append(torch.zeros_like(bs[-1]))
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        tols = [args.tol] * len(hs)
+        B.amg_solve_batch(hs, bs, xs, tols, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, its, rels = B.amg_solve_batch(hs, bs, xs, tols,
+                                          allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+    finally:
+        for h in hs:
+            B.amg_destroy(h)
+    unknowns = sum(2 * d["N"] - 1 for d in inst)
+    # algorithmic bytes per CG iteration (symmetric, FP32 V-cycle + FP64
+    # outer): V-cycle ~52 n p at p = 4, FP64 matvec 11 n * 8, CG vector work
+    # (x, p, r, r_old, q, z: ~10 reads/writes of 2n doubles) ~160 n
+    alg = sum(it * (52 * 4 + 88 + 160) * (d["N"] - 1) for it, d in zip(its, inst))
+    return {"instances": len(inst), "unknowns": unknowns, "wall_s": round(wall, 4),
+            "solves_per_s": round(len(inst) / wall, 2),
+            "unknowns_per_s": round(unknowns / wall, 1),
+            "iters_median": int(np.median(its)), "iters_max": int(max(its)),
+            "max_relres": float(max(rels)), "not_converged": int(sum(r >= args.tol for r in rels)),
+            "setup_s": round(setup_s, 2),
+            "est_alg_bytes": alg, "est_alg_frac_of_hbm_peak": round(alg / wall / 1e9 / HBM_PEAK_GBS, 4),
+            "workload": "N=2^K, K~U{10..16}; delta~U[0.05,0.3]; const or fractional 50/50, "
+                        "alpha~U[0.2,0.45]; b~N(0,1); seed 0; mixed, inner=PCG, "
+                        f"tol={args.tol}"}
+
+
 def cpu_baseline(args, b, x_fp64, x_mixed):
     """The oracle (CPU FP64, scipy FFT) on the same workload: one full solve,
     hierarchy setup excluded, on the host's cores; also evaluates the GPU
@@ -338,6 +410,10 @@ def main():
         krylov = {"note": "V-cycle-preconditioned CG (inner = AMG_INNER_PCG): same V-cycle, "
                           "Krylov outer iteration; not the paper's stationary iteration",
                   "mixed": kmx, "fp64": k64}
+    batch = None
+    if args.batch > 0:
+        batch = run_batch(B, torch, args)
+        print(f"# batch done: {batch}", file=sys.stderr, flush=True)
     n = N - 1
     roof = roof64 = roof32 = None
     if args.prof_steps > 0:
@@ -374,6 +450,7 @@ def main():
         "mixed": smx, "fp64": s64,
         "speedup_mixed_vs_fp64": round(smx["solves_per_s"] / s64["solves_per_s"], 3),
         "pcg": krylov,
+        "batch": batch,
         "roofline": roof, "roofline_fp64_form": roof64, "roofline_fp32_sweep": roof32,
         "roofline_source": (f"HIP events around the finest-level FFT passes on the solve stream, "
                             f"{args.prof_steps} profiled solves per form launched eagerly "
