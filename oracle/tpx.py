@@ -23,6 +23,10 @@ scalar o.  Generators are stored as arrays g[d + n - 1], d = -(n-1)..n-1.
   stationary iteration only; ``pcg`` is pinned by properties of CG itself
   (finite termination, monotone energy-norm error, the LU solution), not by
   numbers of the paper.
+* ``gmres`` is restarted flexible GMRES right-preconditioned by one V-cycle
+  per Arnoldi step, the Krylov acceleration for the non-symmetric operators;
+  pinned by the minimal-residual property over the Krylov space (brute-force
+  least squares on an explicit basis) and by finite termination.
 """
 from __future__ import annotations
 
@@ -345,4 +349,68 @@ def pcg(H: Hierarchy, b, tol=1e-10, max_iter=500, opts: Options = Options(), x0=
         beta = (rz_new - float(r_old @ z)) / rz
         rz = rz_new
         p = z + beta * p
+    return x, it, np.array(hist)
+
+
+def gmres(H: Hierarchy, b, tol=1e-10, max_iter=500, restart=30, opts: Options = Options(),
+          x0=None, precond=None):
+    """Restarted flexible GMRES, right-preconditioned (Saad's FGMRES): per
+    Arnoldi step j, z_j = B v_j (one V-cycle), w = A z_j, modified Gram-Schmidt
+    against v_0..v_j, v_{j+1} = w / h_{j+1,j}; Givens rotations keep the
+    Hessenberg matrix triangular and give the residual norm |g_{j+1}| of the
+    minimiser over span(z_0..z_j) without forming it.  A cycle ends when that
+    estimate is below tol * ||r_0||, after `restart` steps, at max_iter or on
+    breakdown (h_{j+1,j} = 0); then x += Z y with y from the triangular
+    system, the true residual b - A x is formed, and the solve stops if its
+    norm is below tol * ||r_0|| (else the next cycle starts from it).
+    Iterations count Arnoldi steps (V-cycles).  The history holds the
+    estimates, the last entry of each cycle replaced by the true value.
+    Returns (x, iterations, history)."""
+    B = precond if precond is not None else (lambda r: vcycle(H, r, opts))
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - H.matvec(x)
+    r0 = np.linalg.norm(r)
+    hist = [1.0]
+    if r0 == 0.0:
+        return x, 0, np.array(hist)
+    it = 0
+    while True:
+        beta = np.linalg.norm(r)
+        V = [r / beta]
+        Z = []
+        Hm = np.zeros((restart + 1, restart))
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        cs, sn = np.zeros(restart), np.zeros(restart)
+        k = 0
+        for j in range(restart):
+            z = B(V[j])
+            Z.append(z)
+            w = H.matvec(z)
+            for i in range(j + 1):
+                Hm[i, j] = float(w @ V[i])
+                w = w - Hm[i, j] * V[i]
+            hn = np.linalg.norm(w)
+            Hm[j + 1, j] = hn
+            for i in range(j):
+                a, c = Hm[i, j], Hm[i + 1, j]
+                Hm[i, j] = cs[i] * a + sn[i] * c
+                Hm[i + 1, j] = -sn[i] * a + cs[i] * c
+            d = np.hypot(Hm[j, j], Hm[j + 1, j])
+            cs[j], sn[j] = Hm[j, j] / d, Hm[j + 1, j] / d
+            Hm[j, j], Hm[j + 1, j] = d, 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            hist.append(abs(g[j + 1]) / r0)
+            if hn == 0.0 or hist[-1] < tol or it >= max_iter:
+                break
+            V.append(w / hn)
+        y = scipy.linalg.solve_triangular(Hm[:k, :k], g[:k])
+        x = x + np.column_stack(Z) @ y
+        r = b - H.matvec(x)
+        hist[-1] = np.linalg.norm(r) / r0
+        if hist[-1] < tol or it >= max_iter:
+            break
     return x, it, np.array(hist)
