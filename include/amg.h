@@ -111,6 +111,7 @@ typedef struct {
   int flags;                  /* AMG_FLAG_* bits, 0 by default               */
   int inner;                  /* AMG_INNER_VCYCLE (default) or AMG_INNER_PCG */
   double shift, scale;        /* operator shift*I + scale*A (defaults 0, 1)  */
+  int restart;                /* AMG_INNER_GMRES cycle length, 1..64 (30)    */
 } amg_opts_t;
 
 /* Shifted operators (Sec. 5, eq. (bdf4)).  With shift = sigma and scale = s
@@ -139,6 +140,16 @@ typedef struct {
    AMG_DIVERGED. */
 #define AMG_INNER_VCYCLE 0
 #define AMG_INNER_PCG 1
+/* AMG_INNER_GMRES: restarted flexible GMRES right-preconditioned by one
+   V-cycle per Arnoldi step, for any non-singular operator (the non-symmetric
+   weighted kernel and standard collocation included).  Classical
+   Gram-Schmidt applied twice; Givens rotations give the residual estimate
+   |g_{j+1}| that ends a cycle (below tol, after `restart` steps, or at
+   max_iter); then x += Z y, and the true residual b - A x (FP64) decides the
+   stop.  Iterations count V-cycles.  The history holds the estimates, the
+   last of each cycle replaced by the true value.  Device memory: 2 restart + 1
+   vectors of 2N-1 doubles (amg_footprint_bytes counts them). */
+#define AMG_INNER_GMRES 2
 
 /* amg_setup builds only the host-side hierarchy (generators, Lemma 3.1
    levels, coarsest LU) and touches no GPU; amg_level_tpx, amg_num_levels and

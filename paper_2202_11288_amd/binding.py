@@ -23,7 +23,7 @@ AMG_FP64, AMG_MIXED = 0, 1
 AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2
 AMG_FLAG_EAGER = 4
-AMG_INNER_VCYCLE, AMG_INNER_PCG = 0, 1
+AMG_INNER_VCYCLE, AMG_INNER_PCG, AMG_INNER_GMRES = 0, 1, 2
 AMG_SCHEME_SHIFTED, AMG_SCHEME_STANDARD = 0, 1
 
 
@@ -43,7 +43,8 @@ class amg_opts_t(ctypes.Structure):
     _fields_ = [("m1", ctypes.c_int), ("m2", ctypes.c_int), ("omega_pre", ctypes.c_double),
                 ("omega_post", ctypes.c_double), ("coarsest_log2", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("flags", ctypes.c_int),
-                ("inner", ctypes.c_int), ("shift", ctypes.c_double), ("scale", ctypes.c_double)]
+                ("inner", ctypes.c_int), ("shift", ctypes.c_double), ("scale", ctypes.c_double),
+                ("restart", ctypes.c_int)]
 
 
 class amg_stat_t(ctypes.Structure):

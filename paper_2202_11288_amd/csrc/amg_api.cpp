@@ -211,6 +211,16 @@ struct amg_ctx {
   double* cg_part = nullptr;
   // right-hand side of amg_bdf4_step (allocated by its first call)
   double* step_b = nullptr;
+  // restarted flexible GMRES (inner = AMG_INNER_GMRES): basis V ((restart+1)
+  // vectors), preconditioned vectors Z (restart vectors), Hessenberg matrix,
+  // rotations, rotated right-hand side, small scratch; gm_j = the next
+  // Arnoldi column (host-side, read after each round's synchronisation)
+  double* gm_V = nullptr;
+  double* gm_Z = nullptr;
+  double* gm_H = nullptr;
+  double* gm_small = nullptr;  // g | cs | sn | hcur | y | hn, kGmMax + 1 each
+  double* gm_part = nullptr;
+  int gm_j = 0;
 };
 
 namespace {
@@ -283,7 +293,9 @@ int check_opts(const amg_opts_t* o) {
   if (o->precision != AMG_FP64 && o->precision != AMG_MIXED) return AMG_EINVAL;
   if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
   if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE | AMG_FLAG_EAGER)) return AMG_EINVAL;
-  if (o->inner != AMG_INNER_VCYCLE && o->inner != AMG_INNER_PCG) return AMG_EINVAL;
+  if (o->inner != AMG_INNER_VCYCLE && o->inner != AMG_INNER_PCG && o->inner != AMG_INNER_GMRES)
+    return AMG_EINVAL;
+  if (o->restart < 1 || o->restart > kGmMax) return AMG_EINVAL;
   if (!(std::isfinite(o->scale) && o->scale > 0.0) || !std::isfinite(o->shift)) return AMG_EINVAL;
   return AMG_OK;
 }
@@ -307,6 +319,9 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess) {
   bytes += L0 * 16 * 2 + (mixed ? L0 * 8 : 0);           // FFT scratch (setup uses two)
   bytes += (mixed ? (2 * N - 1) * 8 : 0);                // outer residual
   if (o->inner == AMG_INNER_PCG) bytes += 3 * (2 * N - 1) * 8 + 2 * 1024 * 8;  // p, q, r_old
+  if (o->inner == AMG_INNER_GMRES)  // V, Z, H, small vectors, dot partials
+    bytes += (int64_t)(2 * o->restart + 1) * (2 * N - 1) * 8 +
+             (int64_t)(kGmMax + 1) * (kGmMax + 6 + 1024) * 8;
   const int64_t mc = (int64_t(2) << o->coarsest_log2) - 1;
   bytes += 2 * mc * mc * 8;
   bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
@@ -457,7 +472,7 @@ int vcycle_run(amg_ctx* c, hipStream_t s) {
 // r = b - A x on the finest level (FP64), optionally with x += e fused in
 // front; writes the residual-norm partials and runs the stopping test.
 int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double tol,
-                   hipStream_t s) {
+                   hipStream_t s, bool gm_check = false) {
   const LevelRes& L0 = c->lv[0];
   const LevelDev<double> d = L0.dev<double>();
   ColIn<double> in{};
@@ -482,7 +497,10 @@ int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double
     AMG_TRY(fourstep<double>(c, 0, cmode, in, EPI_OUTER, out, s));
     npart = col_blocks(d.logL1, d.tcols);
   }
-  HIP_TRY(launch_finish(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s));
+  if (gm_check)
+    HIP_TRY(launch_gm_check(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s));
+  else
+    HIP_TRY(launch_finish(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s));
   return AMG_OK;
 }
 
@@ -657,6 +675,15 @@ int setup_device(amg_ctx* c, hipStream_t s) {
     AMG_TRY(dalloc(c, &c->cg_rold, m));
     AMG_TRY(dalloc(c, &c->cg_part, (size_t)(2 * vec_blocks((int64_t)m))));
   }
+  if (c->opts.inner == AMG_INNER_GMRES) {
+    const size_t m = (size_t)(2 * c->N - 1);
+    const size_t R = (size_t)c->opts.restart;
+    AMG_TRY(dalloc(c, &c->gm_V, (R + 1) * m));
+    AMG_TRY(dalloc(c, &c->gm_Z, R * m));
+    AMG_TRY(dalloc(c, &c->gm_H, (size_t)(kGmMax + 1) * kGmMax));
+    AMG_TRY(dalloc(c, &c->gm_small, (size_t)(kGmMax + 1) * 6));
+    AMG_TRY(dalloc(c, &c->gm_part, (size_t)(kGmMax + 1) * vec_blocks((int64_t)m)));
+  }
   void* ph = nullptr;
   HIP_TRY(hipHostMalloc(&ph, sizeof(SolveState), hipHostMallocDefault));
   c->st_host = static_cast<SolveState*>(ph);
@@ -693,6 +720,7 @@ void amg_default_opts(amg_opts_t* o) {
   o->inner = AMG_INNER_VCYCLE;
   o->shift = 0.0;
   o->scale = 1.0;
+  o->restart = 30;
 }
 
 const char* amg_strerror(int st) {
@@ -845,6 +873,7 @@ int solve_begin(amg_t h, const double* b, double* x, double tol, hipStream_t s) 
   HIP_TRY(hipMemcpyAsync(h->st_dev, h->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
   AMG_TRY(outer_residual(h, b, x, nullptr, tol, s));
   HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  h->gm_j = 0;
   return AMG_OK;
 }
 
@@ -889,12 +918,68 @@ int pcg_step(amg_t h, double* x, double tol, hipStream_t s) {
   return AMG_OK;
 }
 
+// Restarted flexible GMRES, one Arnoldi step per round (one V-cycle):
+// z_j = B v_j, w = A z_j, two classical Gram-Schmidt passes against v_0..v_j,
+// Givens rotation and residual estimate; v_{j+1} = w / h_{j+1,j}.  The round
+// after a cycle ended (estimate below tol, restart length, max_iter) forms
+// x += Z y and the true residual b - A x with its stop test; the next round
+// starts a new cycle from that residual.  The residual r lives where the
+// V-cycle reads its right-hand side (level 0's b; mixed: `rout`).
+int gmres_round(amg_t h, const double* b, double* x, double tol, hipStream_t s) {
+  const LevelRes& L0 = h->lv[0];
+  const int64_t m = 2 * h->N - 1;
+  const int nb = vec_blocks(m);
+  double* g = h->gm_small;
+  double* cs = g + (kGmMax + 1);
+  double* sn = cs + (kGmMax + 1);
+  double* hcur = sn + (kGmMax + 1);
+  double* y = hcur + (kGmMax + 1);
+  double* hn = y + (kGmMax + 1);
+  double* vin64 = h->mixed ? nullptr : L0.bd;
+  float* vin32 = h->mixed ? L0.bf : nullptr;
+  const size_t v0 = h->prof.mark(s);
+  if (h->st_host->cycle_end) {
+    HIP_TRY(launch_gm_update(h->st_dev, h->gm_H, g, h->gm_j, y, x, h->gm_Z, m, s));
+    AMG_TRY(outer_residual(h, b, x, nullptr, tol, s, true));
+    h->gm_j = 0;
+    h->prof.span(PK_OUTER, v0, h->prof.mark(s));
+    return AMG_OK;
+  }
+  const int j = h->gm_j;
+  if (j == 0)
+    HIP_TRY(launch_gm_start(h->st_dev, h->mixed ? h->rout : L0.bd, h->gm_V, g, m, vin64, vin32, s));
+  AMG_TRY(vcycle_run(h, s));
+  const size_t v1 = h->prof.mark(s);
+  double* z = h->gm_Z + (int64_t)j * m;
+  if (h->mixed)
+    HIP_TRY(launch_copy_f2d(L0.uf, z, m, s));
+  else
+    HIP_TRY(hipMemcpyAsync(z, L0.ud, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double* w = h->gm_V + (int64_t)(j + 1) * m;
+  AMG_TRY(level_matvec64(h, 0, z, w, s));
+  double* Hj = h->gm_H + (int64_t)j * (kGmMax + 1);
+  for (int pass = 0; pass < 2; ++pass) {
+    HIP_TRY(launch_gm_dot(h->gm_V, j + 1, w, m, h->gm_part, s));
+    HIP_TRY(launch_gm_reduce(h->st_dev, h->gm_part, nb, j + 1, hcur, Hj, pass, s));
+    HIP_TRY(launch_gm_axpy(h->st_dev, w, h->gm_V, hcur, j + 1, m, pass ? h->npart : nullptr, s));
+  }
+  HIP_TRY(launch_gm_givens(h->st_dev, h->gm_H, j, cs, sn, g, hn, h->npart, nb, tol,
+                           h->opts.max_iter, h->opts.restart, h->hist_dev, s));
+  HIP_TRY(launch_gm_scale(h->st_dev, w, hn, m, vin64, vin32, s));
+  h->gm_j = j + 1;
+  h->prof.span(PK_VCYCLE, v0, v1);
+  h->prof.span(PK_OUTER, v1, h->prof.mark(s));
+  return AMG_OK;
+}
+
 // Enqueues the work up to the next stop test; round counts the calls since
 // solve_begin (whose residual and stop test come first).
 int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s, int round) {
   if (h->opts.inner == AMG_INNER_PCG) {
     AMG_TRY(pcg_precondition(h, round == 0, s));
     AMG_TRY(pcg_step(h, x, tol, s));
+  } else if (h->opts.inner == AMG_INNER_GMRES) {
+    AMG_TRY(gmres_round(h, b, x, tol, s));
   } else {
     const void* e = h->mixed ? (const void*)h->lv[0].uf : (const void*)h->lv[0].ud;
     const size_t v0 = h->prof.mark(s);

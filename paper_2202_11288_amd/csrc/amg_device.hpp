@@ -96,7 +96,7 @@ struct SolveState {
   int iter;
   int status;
   int done;
-  int pad;
+  int cycle_end;  // GMRES: the current Arnoldi cycle has ended (update x next)
   // conjugate-gradient scalars (inner = AMG_INNER_PCG)
   double rz;     // <r, z> of the current direction
   double alpha;  // step length
@@ -105,6 +105,11 @@ struct SolveState {
 
 // Stages of the conjugate-gradient scalar kernel.
 enum CgStage { CG_INIT = 0, CG_ALPHA = 1, CG_BETA = 2 };
+
+// Largest GMRES restart length (Krylov basis vectors per cycle).
+constexpr int kGmMax = 64;
+// Vectors per block row of the GMRES multi-dot kernel.
+constexpr int kGmGroup = 8;
 
 // Vector kernels: fixed contiguous chunks, one per block of kVecNT threads.
 constexpr int kVecNT = 256;
@@ -156,6 +161,38 @@ hipError_t launch_cg_update(const SolveState* st, double* x, const double* p, do
 template <typename TZ>
 hipError_t launch_cg_dir(const SolveState* st, double* p, const TZ* z, int64_t m, int first,
                          hipStream_t s);
+
+// ---- restarted flexible GMRES (inner = AMG_INNER_GMRES) ------------------
+// The basis V (ld = m) and the preconditioned vectors Z (ld = m) are FP64;
+// the Hessenberg matrix H is column-major with leading dimension kGmMax + 1;
+// g, cs, sn are the rotated right-hand side and the Givens rotations.
+// v0 = r / beta with beta = relres * r0 of the last residual; also written to
+// the V-cycle input (vin64 or vin32, either may be null); g[0] = beta.
+hipError_t launch_gm_start(const SolveState* st, const double* r, double* v0, double* g, int64_t m,
+                           double* vin64, float* vin32, hipStream_t s);
+// part[i * nb + blk] = <V[i], w> over chunk blk, i < cnt
+hipError_t launch_gm_dot(const double* V, int cnt, const double* w, int64_t m, double* part,
+                         hipStream_t s);
+// hcur[i] = sum_blk part[i * nb + blk]; hcol[i] = (accumulate ? hcol[i] : 0) + hcur[i]
+hipError_t launch_gm_reduce(const SolveState* st, const double* part, int nb, int cnt,
+                            double* hcur, double* hcol, int accumulate, hipStream_t s);
+// w -= sum_i hcur[i] V[i]; npart (if set) = ||w||^2 partials
+hipError_t launch_gm_axpy(const SolveState* st, double* w, const double* V, const double* hcur,
+                          int cnt, int64_t m, double* npart, hipStream_t s);
+// h_{j+1,j} = ||w|| (from npart), rotations, residual estimate, stop test
+hipError_t launch_gm_givens(SolveState* st, double* H, int j, double* cs, double* sn, double* g,
+                            double* hn, const double* npart, int nb, double tol, int max_iter,
+                            int restart, double* hist, hipStream_t s);
+// v_{j+1} = w / h_{j+1,j} in place, also into the V-cycle input (unless the cycle ended)
+hipError_t launch_gm_scale(const SolveState* st, double* w, const double* hn, int64_t m,
+                           double* vin64, float* vin32, hipStream_t s);
+// y = R^{-1} g (R = leading k x k block of the rotated H), x += Z y
+hipError_t launch_gm_update(const SolveState* st, const double* H, const double* g, int k,
+                            double* y, double* x, const double* Z, int64_t m, hipStream_t s);
+// true residual norm (npart) -> relres, stop test, next cycle
+hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double tol, int max_iter,
+                           double* hist, hipStream_t s);
+hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s);
 
 // b = 4 u1 - 3 u2 + (4/3) u3 - (1/4) u4 + src (src may be null): the BDF4
 // right-hand side

@@ -568,6 +568,200 @@ __global__ __launch_bounds__(kVecNT) void k_cg_update(const SolveState* st, doub
   if (threadIdx.x == 0) npart[blockIdx.x] = ss;
 }
 
+// ---------------------------------------------------------------------------
+// Restarted flexible GMRES (right preconditioner = one V-cycle per step).
+// Classical Gram-Schmidt applied twice: each pass is one multi-dot (all
+// <v_i, w> of the pass in one launch, fixed-order block partials) and one
+// update; the small dense work (Givens rotations, the triangular solve) runs
+// in one thread.  Every kernel returns at once when the solve is done.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kVecNT) void k_gm_start(const SolveState* st, const double* r,
+                                                     double* v0, double* g, int64_t m,
+                                                     double* vin64, float* vin32) {
+  if (st->done) return;
+  const double beta = st->relres * st->r0;
+  const double inv = 1.0 / beta;
+  const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
+  if (i == 0) g[0] = beta;
+  if (i >= m) return;
+  const double v = r[i] * inv;
+  v0[i] = v;
+  if (vin64) vin64[i] = v;
+  if (vin32) vin32[i] = (float)v;
+}
+
+__global__ __launch_bounds__(kVecNT) void k_gm_dot(const double* V, int cnt, const double* w,
+                                                   int64_t m, int64_t chunk, double* part) {
+  __shared__ double red[kVecNT / 64];
+  const int g0 = blockIdx.y * kGmGroup;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = i0 + chunk < m ? i0 + chunk : m;
+  double acc[kGmGroup];
+#pragma unroll
+  for (int k = 0; k < kGmGroup; ++k) acc[k] = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kVecNT) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < kGmGroup; ++k)
+      if (g0 + k < cnt) acc[k] += V[(int64_t)(g0 + k) * m + i] * wi;
+  }
+#pragma unroll
+  for (int k = 0; k < kGmGroup; ++k) {
+    const double t = block_sum<double, kVecNT>(acc[k], red);
+    if (threadIdx.x == 0 && g0 + k < cnt) part[(int64_t)(g0 + k) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kVecNT) void k_gm_reduce(const SolveState* st, const double* part,
+                                                      int nb, int cnt, double* hcur, double* hcol,
+                                                      int accumulate) {
+  __shared__ double red[kVecNT / 64];
+  if (st->done) return;
+  for (int k = 0; k < cnt; ++k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kVecNT) v += part[(int64_t)k * nb + b];
+    v = block_sum<double, kVecNT>(v, red);
+    if (threadIdx.x == 0) {
+      hcur[k] = v;
+      hcol[k] = accumulate ? hcol[k] + v : v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kVecNT) void k_gm_axpy(const SolveState* st, double* w,
+                                                    const double* V, const double* hcur, int cnt,
+                                                    int64_t m, int64_t chunk, double* npart) {
+  __shared__ double red[kVecNT / 64];
+  __shared__ double hs[kGmMax + 1];
+  if (st->done) return;
+  for (int k = threadIdx.x; k < cnt; k += kVecNT) hs[k] = hcur[k];
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = i0 + chunk < m ? i0 + chunk : m;
+  double ss = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kVecNT) {
+    double v = w[i];
+    for (int k = 0; k < cnt; ++k) v -= hs[k] * V[(int64_t)k * m + i];
+    w[i] = v;
+    ss += v * v;
+  }
+  if (npart) {
+    ss = block_sum<double, kVecNT>(ss, red);
+    if (threadIdx.x == 0) npart[blockIdx.x] = ss;
+  }
+}
+
+__global__ __launch_bounds__(kVecNT) void k_gm_givens(SolveState* st, double* H, int j,
+                                                      double* cs, double* sn, double* g,
+                                                      double* hn_out, const double* npart, int nb,
+                                                      double tol, int max_iter, int restart,
+                                                      double* hist) {
+  __shared__ double red[kVecNT / 64];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kVecNT) v += npart[b];
+  v = block_sum<double, kVecNT>(v, red);
+  if (threadIdx.x != 0 || st->done) return;
+  const double hn = sqrt(v);
+  *hn_out = hn;
+  double* Hj = H + (int64_t)j * (kGmMax + 1);
+  Hj[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = Hj[i], c = Hj[i + 1];
+    Hj[i] = cs[i] * a + sn[i] * c;
+    Hj[i + 1] = -sn[i] * a + cs[i] * c;
+  }
+  const double d = hypot(Hj[j], Hj[j + 1]);
+  if (!(d > 0.0) || isinf(d)) {  // singular or non-finite Hessenberg column
+    st->status = 2;
+    st->done = 1;
+    return;
+  }
+  cs[j] = Hj[j] / d;
+  sn[j] = Hj[j + 1] / d;
+  Hj[j] = d;
+  Hj[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  const double est = fabs(g[j + 1]) / st->r0;
+  st->relres = est;
+  hist[st->iter] = est;
+  if (!(est == est) || isinf(est)) {
+    st->status = 2;
+    st->done = 1;
+    return;
+  }
+  if (est < tol || j + 1 >= restart || st->iter >= max_iter || hn == 0.0)
+    st->cycle_end = 1;
+  else
+    st->iter += 1;
+}
+
+__global__ __launch_bounds__(kVecNT) void k_gm_scale(const SolveState* st, double* w,
+                                                     const double* hn, int64_t m, double* vin64,
+                                                     float* vin32) {
+  if (st->done || st->cycle_end) return;
+  const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
+  if (i >= m) return;
+  const double v = w[i] / *hn;
+  w[i] = v;
+  if (vin64) vin64[i] = v;
+  if (vin32) vin32[i] = (float)v;
+}
+
+__global__ void k_gm_solve(const SolveState* st, const double* H, const double* g, int k,
+                           double* y) {
+  if (threadIdx.x != 0 || st->done) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double v = g[i];
+    for (int l = i + 1; l < k; ++l) v -= H[(int64_t)l * (kGmMax + 1) + i] * y[l];
+    y[i] = v / H[(int64_t)i * (kGmMax + 1) + i];
+  }
+}
+
+__global__ __launch_bounds__(kVecNT) void k_gm_xupdate(const SolveState* st, double* x,
+                                                       const double* Z, const double* y, int k,
+                                                       int64_t m) {
+  __shared__ double ys[kGmMax];
+  if (st->done) return;
+  for (int l = threadIdx.x; l < k; l += kVecNT) ys[l] = y[l];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
+  if (i >= m) return;
+  double v = x[i];
+  for (int l = 0; l < k; ++l) v += ys[l] * Z[(int64_t)l * m + i];
+  x[i] = v;
+}
+
+__global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const double* npart, int nb,
+                                                     double tol, int max_iter, double* hist) {
+  __shared__ double red[kVecNT / 64];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kVecNT) v += npart[b];
+  v = block_sum<double, kVecNT>(v, red);
+  if (threadIdx.x != 0 || st->done) return;
+  const double rel = sqrt(v) / st->r0;
+  st->relres = rel;
+  hist[st->iter] = rel;
+  st->cycle_end = 0;
+  if (!(rel == rel) || isinf(rel)) {
+    st->status = 2;
+    st->done = 1;
+  } else if (rel < tol) {
+    st->status = 0;
+    st->done = 1;
+  } else if (st->iter >= max_iter) {
+    st->status = 1;
+    st->done = 1;
+  } else {
+    st->iter += 1;
+  }
+}
+
+__global__ void k_copy_f2d(const float* a, double* b, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) b[i] = (double)a[i];
+}
+
 // BDF4 history combination of eq. (bdf4), one element per thread
 __global__ __launch_bounds__(kVecNT) void k_bdf4_rhs(const double* u1, const double* u2,
                                                      const double* u3, const double* u4,
@@ -670,6 +864,68 @@ hipError_t launch_cg_dir(const SolveState* st, double* p, const TZ* z, int64_t m
                          hipStream_t s) {
   const int grid = (int)((m + kVecNT - 1) / kVecNT);
   hipLaunchKernelGGL(k_cg_dir<TZ>, grid, kVecNT, 0, s, st, p, z, m, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_start(const SolveState* st, const double* r, double* v0, double* g, int64_t m,
+                           double* vin64, float* vin32, hipStream_t s) {
+  const int grid = (int)((m + kVecNT - 1) / kVecNT);
+  hipLaunchKernelGGL(k_gm_start, grid, kVecNT, 0, s, st, r, v0, g, m, vin64, vin32);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_dot(const double* V, int cnt, const double* w, int64_t m, double* part,
+                         hipStream_t s) {
+  const dim3 grid(vec_blocks(m), (cnt + kGmGroup - 1) / kGmGroup);
+  hipLaunchKernelGGL(k_gm_dot, grid, kVecNT, 0, s, V, cnt, w, m, vec_chunk(m), part);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_reduce(const SolveState* st, const double* part, int nb, int cnt,
+                            double* hcur, double* hcol, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_reduce, 1, kVecNT, 0, s, st, part, nb, cnt, hcur, hcol, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_axpy(const SolveState* st, double* w, const double* V, const double* hcur,
+                          int cnt, int64_t m, double* npart, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_axpy, vec_blocks(m), kVecNT, 0, s, st, w, V, hcur, cnt, m, vec_chunk(m),
+                     npart);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_givens(SolveState* st, double* H, int j, double* cs, double* sn, double* g,
+                            double* hn, const double* npart, int nb, double tol, int max_iter,
+                            int restart, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_givens, 1, kVecNT, 0, s, st, H, j, cs, sn, g, hn, npart, nb, tol,
+                     max_iter, restart, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_scale(const SolveState* st, double* w, const double* hn, int64_t m,
+                           double* vin64, float* vin32, hipStream_t s) {
+  const int grid = (int)((m + kVecNT - 1) / kVecNT);
+  hipLaunchKernelGGL(k_gm_scale, grid, kVecNT, 0, s, st, w, hn, m, vin64, vin32);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_update(const SolveState* st, const double* H, const double* g, int k,
+                            double* y, double* x, const double* Z, int64_t m, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_solve, 1, 64, 0, s, st, H, g, k, y);
+  const int grid = (int)((m + kVecNT - 1) / kVecNT);
+  hipLaunchKernelGGL(k_gm_xupdate, grid, kVecNT, 0, s, st, x, Z, y, k, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double tol, int max_iter,
+                           double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_check, 1, kVecNT, 0, s, st, npart, nb, tol, max_iter, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s) {
+  const int grid = (int)((m + 255) / 256);
+  hipLaunchKernelGGL(k_copy_f2d, grid, 256, 0, s, a, b, m);
   return hipGetLastError();
 }
 

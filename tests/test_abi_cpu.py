@@ -105,7 +105,8 @@ def _setup_status(kern, delta, N, **opts):
     dict(kind=B.AMG_K_WEIGHTED, wl=-1.0), dict(kind=7), dict(kind=B.AMG_K_GENERATORS),
     dict(opts=dict(coarsest_log2=1)), dict(opts=dict(coarsest_log2=8)),
     dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=8)),
-    dict(opts=dict(inner=2)), dict(opts=dict(inner=-1)),
+    dict(opts=dict(inner=3)), dict(opts=dict(inner=-1)),
+    dict(opts=dict(inner=B.AMG_INNER_GMRES, restart=0)), dict(opts=dict(restart=65)),
     dict(kind=B.AMG_K_WEIGHTED, wl=1.2, opts=dict(inner=B.AMG_INNER_PCG)),
 ])
 def test_invalid_arguments_rejected(case):
@@ -179,3 +180,18 @@ def test_conjugate_gradient_option():
     assert f1 - f0 >= 3 * (2 * 2 ** 16 - 1) * 8
     with pytest.raises(TypeError):
         B.amg_default_opts(innr=1)
+
+
+def test_gmres_option():
+    """inner = AMG_INNER_GMRES: accepted for every kernel (non-symmetric ones
+    included); the footprint counts its 2 restart + 1 vectors."""
+    for kern in (B.kernel(B.AMG_K_CONST), B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8),
+                 B.kernel(B.AMG_K_CONST, scheme=B.AMG_SCHEME_STANDARD)):
+        assert _setup_status(kern, 0.1, 1024, inner=B.AMG_INNER_GMRES) == B.AMG_OK
+    assert B.amg_default_opts().restart == 30
+    k = B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8)
+    f0 = B.amg_footprint_bytes(k, 0.1, 2 ** 16)
+    for R in (1, 30, 64):
+        f1 = B.amg_footprint_bytes(k, 0.1, 2 ** 16, B.amg_default_opts(inner=B.AMG_INNER_GMRES,
+                                                                        restart=R))
+        assert f1 - f0 >= (2 * R + 1) * (2 * 2 ** 16 - 1) * 8
