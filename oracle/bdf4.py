@@ -110,14 +110,15 @@ def run_dense(kernel: disc.Kernel, N: int, scheme: str = disc.SHIFTED, scale: fl
 
 def shifted_tpx(T: tpx.TpX, shift: float, scale: float) -> tpx.TpX:
     """shift I + scale T on the Toeplitz-plus-Cross representation: every
-    generator and Cross entry times scale, shift on the diagonal entries
-    (offset 0 of A and D_bar, and o)."""
+    generator, Cross entry and band entry times scale, shift on the diagonal
+    entries (offset 0 of A and D_bar, and o)."""
     n = T.n
     a, d = scale * T.a, scale * T.d
     a[n - 1] += shift
     d[n - 1] += shift
+    band = None if T.band is None else tuple(scale * v for v in T.band)
     return tpx.TpX(n, a, scale * T.b, scale * T.c, d, scale * T.p, scale * T.q, scale * T.xi,
-                   scale * T.zeta, scale * T.o + shift)
+                   scale * T.zeta, scale * T.o + shift, band)
 
 
 def run_tpx(kernel: disc.Kernel, N: int, scheme: str = disc.SHIFTED, scale: float = None,

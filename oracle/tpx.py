@@ -55,6 +55,10 @@ class TpX:
     xi: np.ndarray
     zeta: np.ndarray
     o: float
+    # optional tridiagonal part on the block-ordered vector (sub, main, super;
+    # 2n+1 entries each, sub[0] = super[2n] = 0): the variable diagonal of the
+    # weakly singular model (eq. (3system)) and its Galerkin images
+    band: tuple = None
 
     @property
     def size(self):
@@ -62,7 +66,17 @@ class TpX:
 
     def diag(self):
         n = self.n
-        return np.concatenate([np.full(n, self.a[n - 1]), [self.o], np.full(n, self.d[n - 1])])
+        d = np.concatenate([np.full(n, self.a[n - 1]), [self.o], np.full(n, self.d[n - 1])])
+        return d if self.band is None else d + self.band[1]
+
+    def band_matvec(self, u):
+        if self.band is None:
+            return 0.0
+        s, m, p = self.band
+        y = m * u
+        y[1:] += s[1:] * u[:-1]
+        y[:-1] += p[:-1] * u[1:]
+        return y
 
     def dense(self):
         n = self.n
@@ -76,6 +90,12 @@ class TpX:
         M[n, n] = self.o
         M[n, n + 1:] = self.zeta
         M[n + 1:, n] = self.xi
+        if self.band is not None:
+            s, m, p = self.band
+            k = np.arange(2 * n + 1)
+            M[k, k] += m
+            M[k[1:], k[1:] - 1] += s[1:]
+            M[k[:-1], k[:-1] + 1] += p[:-1]
         return M
 
 
@@ -111,6 +131,11 @@ def from_stencil(kernel: disc.Kernel, N: int, scheme: str = disc.SHIFTED):
     rule (eq. (ccs2.6)) the midpoint rows have their own.
     """
     (Wn, Sn), (Wm, Sm) = disc.row_stencils(kernel, N, scheme)
+    return from_stencils(Wn, Sn, Wm, Sm, N)
+
+
+def from_stencils(Wn, Sn, Wm, Sm, N: int):
+    """`from_stencil` for given node-row and midpoint-row stencils."""
     n = N - 1
 
     def at(W, S):
@@ -191,7 +216,29 @@ def coarsen(T: TpX) -> TpX:
     zc = ((b(-Nk + 2 * i) + 2 * b(-Nk + 2 * i + 1) + b(-Nk + 2 * i + 2))
           + 2 * (zeta(2 * i - 1) + 2 * zeta(2 * i) + zeta(2 * i + 1))
           + (d(2 * i - 2) + 2 * d(2 * i - 1) + d(2 * i))) / 8.0
-    return TpX(nc, toe(a), toe(b), toe(c), toe(d), pc, qc, xic, zc, float(oc))
+    return TpX(nc, toe(a), toe(b), toe(c), toe(d), pc, qc, xic, zc, float(oc),
+               coarsen_band(T.band, n))
+
+
+def coarsen_band(band, n):
+    """Galerkin image R B P of a tridiagonal B (R = 1/4 [1 2 1] stride 2 on the
+    block-ordered vector, P = 2 R^T, Sec. 3.1): again tridiagonal, formed with
+    sparse products."""
+    if band is None:
+        return None
+    import scipy.sparse as sp
+    m = 2 * n + 1
+    mc = n
+    s, d, p = band
+    B = sp.diags([s[1:], d, p[:-1]], [-1, 0, 1], shape=(m, m), format="csr")
+    rows = np.repeat(np.arange(mc), 3)
+    cols = (2 * np.arange(mc)[:, None] + np.arange(3)[None, :]).ravel()
+    vals = np.tile([0.25, 0.5, 0.25], mc)
+    R = sp.csr_matrix((vals, (rows, cols)), shape=(mc, m))
+    C = (R @ B @ (2.0 * R.T)).tocsr()
+    sc = np.concatenate([[0.0], C.diagonal(-1)])
+    pc = np.concatenate([C.diagonal(1), [0.0]])
+    return (sc, C.diagonal(0).astype(np.float64), pc)
 
 
 # --- FFT matvec -------------------------------------------------------------
@@ -236,7 +283,7 @@ class Level:
         yv = toeplitz_apply(self.sA, v, n) + toeplitz_apply(self.sB, wb, n) + T.p * wo
         yo = T.q @ v + T.o * wo + T.zeta @ wb
         yw = toeplitz_apply(self.sC, v, n) + toeplitz_apply(self.sD, wb, n) + T.xi * wo
-        return np.concatenate([yv, [yo], yw])
+        return np.concatenate([yv, [yo], yw]) + T.band_matvec(u)
 
 
 def restrict(r):
