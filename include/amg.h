@@ -74,7 +74,17 @@ typedef enum {
        C Nx(N-1)    : offsets -(N-1)..N-2   (2N-2 values)
        D NxN        : offsets -(N-1)..N-1   (2N-1 values)
      8N-8 doubles in total; delta is ignored.                                */
-  AMG_K_GENERATORS = 3
+  AMG_K_GENERATORS = 3,
+  /* The weakly singular nonlocal model of Sec. 2.1 (eq. (3system)): the
+     operator int_0^1 (u(x) - u(y)) |x - y|^-gamma dy on (0, 1), 0 <= gamma
+     < 1, standard piecewise-quadratic collocation, Dirichlet data u(0),
+     u(1).  A = D - T: D the variable diagonal int_0^1 |x - y|^-gamma dy (a
+     tridiagonal band on every level: its Galerkin images), T the product-
+     integration weights (Toeplitz plus Cross).  This is eq. (3system)
+     divided by its factor eta_{h,gamma}.  delta and scheme are ignored; the
+     Dirichlet data enter through amg_volume_rhs (reach 0: g_left[0] = u(0),
+     g_right[0] = u(1)).  amg_manufactured_rhs is AMG_ENOTSUP.              */
+  AMG_K_WEAKLY_SINGULAR = 4
 } amg_kernel_kind;
 
 typedef struct {
@@ -83,6 +93,7 @@ typedef struct {
   double wl, wr;     /* AMG_K_WEIGHTED only (the survey's variant: 1.2, 0.8) */
   const double* gen; /* AMG_K_GENERATORS only (host, copied during setup)    */
   int scheme;        /* AMG_SCHEME_SHIFTED (default) or AMG_SCHEME_STANDARD  */
+  double gamma;      /* AMG_K_WEAKLY_SINGULAR only: exponent, 0 <= gamma < 1  */
 } amg_kernel_t;
 
 /* Collocation rule (Sec. 2.2).
@@ -246,6 +257,12 @@ int64_t amg_level_size(amg_t h, int level);
  * the Cross vectors p, q, xi, zeta (n values each) and o (1 value). */
 int amg_level_tpx(amg_t h, int level, double* a, double* b, double* c, double* d,
                   double* p, double* q, double* xi, double* zeta, double* o);
+
+/* Copy level `level`'s tridiagonal band (2n+1 values each, host arrays; any
+   may be NULL): sub[i] couples unknown i to i-1, main[i] to i, sup[i] to i+1.
+   Returns 1 if the level has a band (AMG_K_WEAKLY_SINGULAR), 0 if not (the
+   arrays are then left untouched), or AMG_EINVAL. */
+int amg_level_band(amg_t h, int level, double* sub, double* main, double* sup);
 
 /* Copy up to `cap` timing records (host array) accumulated by amg_solve
  * under AMG_FLAG_PROFILE; returns the number of records (>= 0) or an error

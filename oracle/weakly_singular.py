@@ -183,3 +183,26 @@ def bdf4_dense(gamma: float, N: int, steps: int = None):
         U.append(scipy.linalg.lu_solve(lu, history_rhs(U[-1], U[-2], U[-3], U[-4], src)))
         U = U[-4:]
     return U[-1], float(np.abs(U[-1] - exact(steps * tau, x)).max())
+
+
+def bdf4_tpx(gamma: float, N: int, steps: int, tol: float = 1e-10, coarsest_log2: int = 5,
+             max_iter: int = 200, opts: tpx.Options = tpx.Options()):
+    """The same steps solved by the V-cycle iteration on the hierarchy of
+    25/12 I + tau A (band included), from U^{k-1}; returns (U, iterations)."""
+    from .bdf4 import BDF4_LEAD, history_rhs, shifted_tpx
+    tau = 1.0 / N
+    H = tpx.Hierarchy.build(shifted_tpx(level(gamma, N), BDF4_LEAD, tau), coarsest_log2)
+    K0, K1 = boundary_coupling(gamma, N)
+    x = positions(N) / (2.0 * N)
+    U = [exact(k * tau, x) for k in range(4)]
+    its = []
+    for k in range(4, steps + 1):
+        t = k * tau
+        F = exact(t, x) + np.exp(t) * L_poly6(gamma, x)
+        src = tau * (F + K0 * exact(t, 0.0) + K1 * exact(t, 1.0))
+        Uk, it, _ = tpx.solve(H, history_rhs(U[-1], U[-2], U[-3], U[-4], src), tol=tol,
+                              max_iter=max_iter, opts=opts, x0=U[-1])
+        its.append(it)
+        U.append(Uk)
+        U = U[-4:]
+    return U[-1], its

@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "amg.h")
 AMG_OK, AMG_NOT_CONVERGED, AMG_DIVERGED = 0, 1, 2
 AMG_EINVAL, AMG_ENOMEM, AMG_EHIP, AMG_ENOTSUP = -1, -2, -3, -4
 AMG_K_CONST, AMG_K_WEIGHTED, AMG_K_FRACTIONAL, AMG_K_GENERATORS = 0, 1, 2, 3
+AMG_K_WEAKLY_SINGULAR = 4
 AMG_FP64, AMG_MIXED = 0, 1
 AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2
@@ -36,7 +37,7 @@ class AmgError(RuntimeError):
 class amg_kernel_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("alpha", ctypes.c_double), ("wl", ctypes.c_double),
                 ("wr", ctypes.c_double), ("gen", ctypes.POINTER(ctypes.c_double)),
-                ("scheme", ctypes.c_int)]
+                ("scheme", ctypes.c_int), ("gamma", ctypes.c_double)]
 
 
 class amg_opts_t(ctypes.Structure):
@@ -83,6 +84,7 @@ def _load():
         "amg_num_levels": (I, [P]),
         "amg_level_size": (I64, [P, I]),
         "amg_level_tpx": (I, [P, I, DP, DP, DP, DP, DP, DP, DP, DP, DP]),
+        "amg_level_band": (I, [P, I, DP, DP, DP]),
         "amg_manufactured_rhs": (I, [ctypes.POINTER(amg_kernel_t), D, I64, DP]),
         "amg_volume_reach": (I64, [ctypes.POINTER(amg_kernel_t), D, I64]),
         "amg_volume_rhs": (I, [ctypes.POINTER(amg_kernel_t), D, I64, DP, DP, DP]),
@@ -136,10 +138,10 @@ def _stream(stream):
 
 
 def kernel(kind: int, alpha: float = 0.0, wl: float = 1.0, wr: float = 1.0, gen=None,
-           scheme: int = AMG_SCHEME_SHIFTED):
+           scheme: int = AMG_SCHEME_SHIFTED, gamma: float = 0.0):
     """amg_kernel_t; for AMG_K_GENERATORS `gen` is a float64 numpy array that
     must stay alive until amg_setup returns."""
-    k = amg_kernel_t(kind, alpha, wl, wr, None, scheme)
+    k = amg_kernel_t(kind, alpha, wl, wr, None, scheme, gamma)
     if gen is not None:
         k.gen = gen.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return k
@@ -245,6 +247,20 @@ def amg_num_levels(h) -> int:
 
 def amg_level_size(h, level: int) -> int:
     return lib.amg_level_size(h, int(level))
+
+
+def amg_level_band(h, level: int):
+    """(sub, main, sup) of the level's tridiagonal band, or None."""
+    import numpy as np
+    m = amg_level_size(h, level)
+    if m < 0:
+        raise AmgError(int(m), "amg_level_band")
+    out = [np.zeros(m) for _ in range(3)]
+    DP = ctypes.POINTER(ctypes.c_double)
+    st = lib.amg_level_band(h, int(level), *[a.ctypes.data_as(DP) for a in out])
+    if st < 0:
+        raise AmgError(st, "amg_level_band")
+    return tuple(out) if st == 1 else None
 
 
 def amg_level_tpx(h, level: int):

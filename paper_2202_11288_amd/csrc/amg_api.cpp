@@ -62,6 +62,9 @@ struct LevelRes {
   float *pf = nullptr, *qf = nullptr, *xif = nullptr, *zetaf = nullptr;
   double *bd = nullptr, *ud = nullptr, *rd = nullptr, *scald = nullptr;
   float *bf = nullptr, *uf = nullptr, *rf = nullptr, *scalf = nullptr;
+  // band (weakly singular model): sub, main, super, 1 / diagonal, product
+  double *bsubd = nullptr, *bmaind = nullptr, *bsupd = nullptr, *dinvd = nullptr, *bcd = nullptr;
+  float *bsubf = nullptr, *bmainf = nullptr, *bsupf = nullptr, *dinvf = nullptr, *bcf = nullptr;
 
   template <typename T>
   LevelDev<T> dev() const;
@@ -89,6 +92,11 @@ LevelDev<double> LevelRes::dev<double>() const {
   v.u = ud;
   v.r = rd;
   v.scal = scald;
+  v.bsub = bsubd;
+  v.bmain = bmaind;
+  v.bsup = bsupd;
+  v.dinv = dinvd;
+  v.bc = bcd;
   return v;
 }
 
@@ -114,6 +122,11 @@ LevelDev<float> LevelRes::dev<float>() const {
   v.u = uf;
   v.r = rf;
   v.scal = scalf;
+  v.bsub = bsubf;
+  v.bmain = bmainf;
+  v.bsup = bsupf;
+  v.dinv = dinvf;
+  v.bc = bcf;
   return v;
 }
 
@@ -273,6 +286,10 @@ void free_since(amg_ctx* c, size_t mark) {
 
 std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
 
+bool ignores_delta(const amg_kernel_t* k) {
+  return k->kind == AMG_K_GENERATORS || k->kind == AMG_K_WEAKLY_SINGULAR;
+}
+
 KernelSpec spec_of(const amg_kernel_t* k, double delta) {
   KernelSpec s;
   s.kind = k->kind;
@@ -281,7 +298,9 @@ KernelSpec spec_of(const amg_kernel_t* k, double delta) {
   s.wl = k->wl;
   s.wr = k->wr;
   s.gen = k->gen;
-  s.scheme = k->kind == AMG_K_GENERATORS ? SCHEME_SHIFTED : k->scheme;
+  s.scheme = (k->kind == AMG_K_GENERATORS || k->kind == AMG_K_WEAKLY_SINGULAR) ? SCHEME_SHIFTED
+                                                                                : k->scheme;
+  s.gamma = k->gamma;
   return s;
 }
 
@@ -300,7 +319,7 @@ int check_opts(const amg_opts_t* o) {
   return AMG_OK;
 }
 
-int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess) {
+int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess, bool band) {
   // device bytes: spectra (FP64 + FP32 if mixed), Cross vectors, vectors,
   // FFT scratch, LU, tables
   const bool mixed = o->precision == AMG_MIXED;
@@ -313,6 +332,7 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess) {
     bytes += spec * 8 + (mixed ? spec * 4 : 0);
     bytes += 4 * n * (8 + (mixed ? 4 : 0));
     bytes += 3 * (2 * n + 1) * (mixed ? 12 : 8);
+    if (band) bytes += 5 * (2 * n + 1) * (mixed ? 12 : 8);  // band, 1/diagonal, product
     if (n == (int64_t(1) << o->coarsest_log2) - 1) break;
     n = (n - 1) / 2;
   }
@@ -365,6 +385,12 @@ int fourstep(amg_ctx* c, int l, int cmode, const ColIn<T>& in, int emode, const 
   const bool prof = P.on && l == 0;
   const size_t e0 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_col_fwd<T>(cmode, d, in, buf, tw, dp, s));
+  if (d.bmain) {
+    // the band's product with the matvec input (as formed by the first pass)
+    const T* xb = cmode == COL_MV ? in.x
+                : cmode == COL_OUTER_UPDATE ? reinterpret_cast<const T*>(in.xo) : d.u;
+    HIP_TRY(launch_band_mv<T>(d, xb, s));
+  }
   const size_t e1 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_row<T>(1, d, buf, tw, dp, col_blocks(d.logL1, d.tcols), out.xin, s));
   const size_t e2 = prof ? P.mark(s) : SIZE_MAX;
@@ -581,6 +607,25 @@ int setup_device(amg_ctx* c, hipStream_t s) {
     HIP_TRY(hipMemsetAsync(R.bd, 0, m * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(R.ud, 0, m * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(R.rd, 0, m * sizeof(double), s));
+    if (H.has_band()) {
+      std::vector<double> dinv((size_t)m);
+      for (int64_t i = 0; i < m; ++i) {
+        const double dt = i < n ? H.a[n - 1] : (i == n ? H.o : H.d[n - 1]);
+        dinv[(size_t)i] = 1.0 / (dt + H.bmain[(size_t)i]);
+      }
+      AMG_TRY(upload(c, &R.bsubd, H.bsub, s));
+      AMG_TRY(upload(c, &R.bmaind, H.bmain, s));
+      AMG_TRY(upload(c, &R.bsupd, H.bsup, s));
+      AMG_TRY(upload(c, &R.dinvd, dinv, s));
+      AMG_TRY(dalloc(c, &R.bcd, m));
+      if (mixed) {
+        AMG_TRY(upload(c, &R.bsubf, to_float(H.bsub), s));
+        AMG_TRY(upload(c, &R.bmainf, to_float(H.bmain), s));
+        AMG_TRY(upload(c, &R.bsupf, to_float(H.bsup), s));
+        AMG_TRY(upload(c, &R.dinvf, to_float(dinv), s));
+        AMG_TRY(dalloc(c, &R.bcf, m));
+      }
+    }
     if (mixed) {
       AMG_TRY(upload(c, &R.pf, to_float(H.p), s));
       AMG_TRY(upload(c, &R.qf, to_float(H.q), s));
@@ -745,9 +790,9 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
   else amg_default_opts(&o);
   int st = check_opts(&o);
   if (st != AMG_OK) return st;
-  const KernelSpec ks = spec_of(kernel, kernel->kind == AMG_K_GENERATORS ? 0.25 : delta);
+  const KernelSpec ks = spec_of(kernel, ignores_delta(kernel) ? 0.25 : delta);
   if (!validate(ks, N, o.coarsest_log2).empty()) return AMG_EINVAL;
-  if (kernel->kind != AMG_K_GENERATORS && !(std::isfinite(delta))) return AMG_EINVAL;
+  if (!ignores_delta(kernel) && !(std::isfinite(delta))) return AMG_EINVAL;
   if (!ks.supported()) return AMG_ENOTSUP;
   amg_ctx* c = new (std::nothrow) amg_ctx();
   if (!c) return AMG_ENOMEM;
@@ -811,6 +856,16 @@ int amg_num_levels(amg_t h) { return h ? (int)h->host.size() : AMG_EINVAL; }
 int64_t amg_level_size(amg_t h, int level) {
   if (!h || level < 0 || level >= (int)h->host.size()) return AMG_EINVAL;
   return 2 * h->host[level].n + 1;
+}
+
+int amg_level_band(amg_t h, int level, double* sub, double* main, double* sup) {
+  if (!h || level < 0 || level >= (int)h->host.size()) return AMG_EINVAL;
+  const TpxLevel& t = h->host[level];
+  if (!t.has_band()) return 0;
+  for (auto pr : {std::make_pair(sub, &t.bsub), std::make_pair(main, &t.bmain),
+                  std::make_pair(sup, &t.bsup)})
+    if (pr.first) std::memcpy(pr.first, pr.second->data(), pr.second->size() * sizeof(double));
+  return 1;
 }
 
 int amg_level_tpx(amg_t h, int level, double* a, double* b, double* c, double* d, double* p,
@@ -1146,6 +1201,7 @@ int amg_residual_history(amg_t h, double* hist, int cap) {
 
 int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, double* b_host) {
   if (!kernel || !b_host || kernel->kind == AMG_K_GENERATORS) return AMG_EINVAL;
+  if (kernel->kind == AMG_K_WEAKLY_SINGULAR) return AMG_ENOTSUP;
   const KernelSpec ks = spec_of(kernel, delta);
   if (!validate(ks, N, 2).empty() || !std::isfinite(delta)) return AMG_EINVAL;
   if (!ks.supported()) return AMG_ENOTSUP;
@@ -1155,8 +1211,8 @@ int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, do
 
 int64_t amg_volume_reach(const amg_kernel_t* kernel, double delta, int64_t N) {
   if (!kernel || kernel->kind == AMG_K_GENERATORS) return AMG_EINVAL;
-  const KernelSpec ks = spec_of(kernel, delta);
-  if (!validate(ks, N, 2).empty() || !std::isfinite(delta)) return AMG_EINVAL;
+  const KernelSpec ks = spec_of(kernel, ignores_delta(kernel) ? 0.25 : delta);
+  if (!validate(ks, N, 2).empty() || !std::isfinite(ks.delta)) return AMG_EINVAL;
   if (!ks.supported()) return AMG_ENOTSUP;
   try {
     return volume_reach(ks, N);
@@ -1168,8 +1224,8 @@ int64_t amg_volume_reach(const amg_kernel_t* kernel, double delta, int64_t N) {
 int amg_volume_rhs(const amg_kernel_t* kernel, double delta, int64_t N, const double* g_left,
                    const double* g_right, double* b) {
   if (!kernel || !g_left || !g_right || !b || kernel->kind == AMG_K_GENERATORS) return AMG_EINVAL;
-  const KernelSpec ks = spec_of(kernel, delta);
-  if (!validate(ks, N, 2).empty() || !std::isfinite(delta)) return AMG_EINVAL;
+  const KernelSpec ks = spec_of(kernel, ignores_delta(kernel) ? 0.25 : delta);
+  if (!validate(ks, N, 2).empty() || !std::isfinite(ks.delta)) return AMG_EINVAL;
   if (!ks.supported()) return AMG_ENOTSUP;
   try {
     volume_correction(ks, N, g_left, g_right, b);
@@ -1186,11 +1242,12 @@ int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
   if (opts) o = *opts;
   else amg_default_opts(&o);
   if (check_opts(&o) != AMG_OK) return AMG_EINVAL;
-  const KernelSpec ks = spec_of(kernel, kernel->kind == AMG_K_GENERATORS ? 0.25 : delta);
+  const KernelSpec ks = spec_of(kernel, ignores_delta(kernel) ? 0.25 : delta);
   if (!validate(ks, N, o.coarsest_log2).empty()) return AMG_EINVAL;
   if (!ks.supported()) return AMG_ENOTSUP;
   return footprint(N, &o, (kernel->kind == AMG_K_CONST || kernel->kind == AMG_K_FRACTIONAL) &&
-                              ks.scheme == SCHEME_SHIFTED);
+                              ks.scheme == SCHEME_SHIFTED,
+                   kernel->kind == AMG_K_WEAKLY_SINGULAR);
 }
 
 }  // extern "C"

@@ -53,6 +53,15 @@ struct LevelDev {
   T* u;         // level iterate (2n+1)
   T* r;         // level residual (2n+1)
   T* scal;      // scal[0]: y_o of the matvec in flight
+  // tridiagonal band (weakly singular model; all null otherwise): couplings
+  // of unknown i to i-1, i, i+1 on the block-ordered vector; dinv = 1 / the
+  // full diagonal (Toeplitz part + band); bc = band product B x of the matvec
+  // in flight (four-step levels)
+  const T* bsub;
+  const T* bmain;
+  const T* bsup;
+  const T* dinv;
+  T* bc;
 };
 
 // Prologue of the forward column pass: how the FFT input vector is formed.
@@ -193,6 +202,10 @@ hipError_t launch_gm_update(const SolveState* st, const double* H, const double*
 hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double tol, int max_iter,
                            double* hist, hipStream_t s);
 hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s);
+
+// bc = B x for the level's band (2n+1 entries)
+template <typename T>
+hipError_t launch_band_mv(const LevelDev<T>& lv, const T* x, hipStream_t s);
 
 // b = 4 u1 - 3 u2 + (4/3) u3 - (1/4) u4 + src (src may be null): the BDF4
 // right-hand side

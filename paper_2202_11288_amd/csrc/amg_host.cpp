@@ -73,6 +73,7 @@ void frac_cell(int64_t k, double theta, double beta, double J[3]) {
 }  // namespace
 
 bool TpxLevel::symmetric() const {
+  if (has_band()) return false;
   const int64_t m = 2 * n - 1;
   for (int64_t i = 0; i < m; ++i) {
     if (a[i] != a[m - 1 - i] || d[i] != a[i] || c[i] != b[m - 1 - i]) return false;
@@ -90,8 +91,10 @@ std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2) {
   if (coarsest_log2 < 2) e << "coarsest_log2 must be >= 2; ";
   if (K <= coarsest_log2) e << "need log2(N) > coarsest_log2; ";
   if (K > 22) e << "log2(N) <= 22 in this build; ";
-  if (k.kind < 0 || k.kind > 3) e << "unknown kernel kind; ";
-  if (k.kind != K_GENERATORS) {
+  if (k.kind < 0 || k.kind > 4) e << "unknown kernel kind; ";
+  if (k.kind == K_WEAKLY_SINGULAR) {
+    if (!(k.gamma >= 0.0 && k.gamma < 1.0)) e << "weakly singular kernel needs 0 <= gamma < 1; ";
+  } else if (k.kind != K_GENERATORS) {
     if (!(k.delta > 0.0 && k.delta < 0.5)) e << "need 0 < delta < 1/2; ";
   } else if (k.gen == nullptr) {
     e << "AMG_K_GENERATORS needs gen; ";
@@ -102,6 +105,96 @@ std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2) {
     e << "weights must be positive; ";
   if (k.scheme != SCHEME_SHIFTED && k.scheme != SCHEME_STANDARD) e << "unknown scheme; ";
   return e.str();
+}
+
+namespace {
+
+// int_0^1 |a - t|^-gamma t^j dt, j = 0, 1, 2, for a = a2 / 2 (the collocation
+// point's position in the cell's local coordinate t; a multiple of 1/2).
+// The point on the cell's end or at its midpoint: closed forms of the
+// end-point singularity; elsewhere the integrand is analytic on [0, 1] with
+// its singularity at distance >= 1/2, so Gauss-Legendre is exact to rounding
+// (32 points up to distance 4, 12 beyond).
+void ws_cell_moments(double gamma, int64_t a2, double J[3]) {
+  const double g = gamma;
+  if (a2 == 0) {
+    for (int j = 0; j < 3; ++j) J[j] = 1.0 / (j + 1 - g);
+    return;
+  }
+  if (a2 == 2) {  // substitute s = 1 - t
+    J[0] = 1.0 / (1 - g);
+    J[1] = 1.0 / (1 - g) - 1.0 / (2 - g);
+    J[2] = 1.0 / (1 - g) - 2.0 / (2 - g) + 1.0 / (3 - g);
+    return;
+  }
+  if (a2 == 1) {  // both halves from the midpoint: (1/2 -+ s)^j, s in [0, 1/2]
+    const double M0 = std::pow(0.5, 1 - g) / (1 - g), M2 = std::pow(0.5, 3 - g) / (3 - g);
+    J[0] = 2 * M0;
+    J[1] = M0;
+    J[2] = 0.5 * M0 + 2 * M2;
+    return;
+  }
+  static const GaussLegendre gl32(32), gl12(12);
+  const double a = 0.5 * (double)a2;
+  const double dist = a < 0 ? -a : a - 1;
+  const GaussLegendre& gl = (dist >= 4) ? gl12 : gl32;
+  long double s0 = 0, s1 = 0, s2 = 0;
+  for (size_t i = 0; i < gl.x.size(); ++i) {
+    const double t = gl.x[i];
+    const long double f = (long double)gl.w[i] * std::pow(std::fabs(a - t), -g);
+    s0 += f;
+    s1 += f * t;
+    s2 += f * t * t;
+  }
+  J[0] = (double)s0;
+  J[1] = (double)s1;
+  J[2] = (double)s2;
+}
+
+// Quadratic Lagrange basis on a cell, coefficients of t^0, t^1, t^2.
+constexpr double kLeft[3] = {1, -3, 2}, kMidB[3] = {0, 4, -4}, kRight[3] = {0, -1, 2};
+
+double ws_apply(const double J[3], const double* l) { return l[0] * J[0] + l[1] * J[1] + l[2] * J[2]; }
+
+}  // namespace
+
+void ws_stencils(double gamma, int64_t N, std::vector<double>& Wn, std::vector<double>& Wm,
+                 int64_t* Sout) {
+  // unknown at half-step offset s2 from the collocation point: a node's cells
+  // are [s2-2, s2] (it is their right end) and [s2, s2+2] (left end), local
+  // a2 = 2 - s2 and -s2; a midpoint's cell is [s2-1, s2+1], a2 = 1 - s2.
+  // Node rows see nodes at even s2, midpoint rows at odd s2.  Symmetric in s2.
+  const int64_t S = 2 * N;
+  const double sc = std::pow(1.0 / (double)N, 1.0 - gamma);
+  std::vector<double> J((size_t)(3 * (2 * S + 6)));
+  auto Jat = [&](int64_t a2) { return &J[(size_t)(3 * (a2 + S + 2))]; };
+  for (int64_t a2 = -S - 2; a2 <= S + 2; ++a2) ws_cell_moments(gamma, a2, Jat(a2));
+  Wn.assign((size_t)(2 * S + 1), 0.0);
+  Wm.assign((size_t)(2 * S + 1), 0.0);
+  for (int64_t s2 = 0; s2 <= S; ++s2) {
+    const double wnode = ws_apply(Jat(2 - s2), kRight) + ws_apply(Jat(-s2), kLeft);
+    const double wmid = ws_apply(Jat(1 - s2), kMidB);
+    const double en = -sc * ((s2 % 2 == 0) ? wnode : wmid);
+    const double em = -sc * ((s2 % 2 == 0) ? wmid : wnode);
+    Wn[S + s2] = Wn[S - s2] = en;
+    Wm[S + s2] = Wm[S - s2] = em;
+  }
+  *Sout = S;
+}
+
+void ws_boundary_coupling(double gamma, int64_t N, double* K0, double* K1) {
+  // boundary node x = 0: its right cell only (left end), a2 = c; x = 1: its
+  // left cell only (right end), a2 = c - (2N - 2); block order of the rows
+  const double sc = std::pow(1.0 / (double)N, 1.0 - gamma);
+  const int64_t m = 2 * N - 1;
+  for (int64_t idx = 0; idx < m; ++idx) {
+    const int64_t c = (idx < N - 1) ? 2 * (idx + 1) : 2 * (idx - (N - 1)) + 1;
+    double J[3];
+    ws_cell_moments(gamma, c, J);
+    K0[idx] = sc * ws_apply(J, kLeft);
+    ws_cell_moments(gamma, c - (2 * N - 2), J);
+    K1[idx] = sc * ws_apply(J, kRight);
+  }
 }
 
 std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
@@ -192,6 +285,11 @@ namespace {
 // node-row and midpoint-row stencils of the kernel's scheme
 void both_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
                    std::vector<double>& Wm, int64_t& Sm) {
+  if (k.kind == K_WEAKLY_SINGULAR) {
+    ws_stencils(k.gamma, N, Wn, Wm, &Sn);
+    Sm = Sn;
+    return;
+  }
   Wn = row_stencil(k, N, &Sn);
   if (k.scheme == SCHEME_STANDARD) {
     Wm = midpoint_stencil_standard(k, N, &Sm);
@@ -259,6 +357,7 @@ std::vector<double> correlate(const std::vector<double>& V, const double* g, int
 }  // namespace
 
 int64_t volume_reach(const KernelSpec& k, int64_t N) {
+  if (k.kind == K_WEAKLY_SINGULAR) return 0;  // the two boundary nodes only
   std::vector<double> Wn, Wm;
   int64_t Sn, Sm;
   both_stencils(k, N, Wn, Sn, Wm, Sm);
@@ -267,6 +366,13 @@ int64_t volume_reach(const KernelSpec& k, int64_t N) {
 
 void volume_correction(const KernelSpec& k, int64_t N, const double* gl, const double* gr,
                        double* b) {
+  if (k.kind == K_WEAKLY_SINGULAR) {
+    // Dirichlet data u(0) = gl[0], u(1) = gr[0]: b -= E g with E = -(K0 | K1)
+    std::vector<double> K0((size_t)(2 * N - 1)), K1((size_t)(2 * N - 1));
+    ws_boundary_coupling(k.gamma, N, K0.data(), K1.data());
+    for (int64_t i = 0; i < 2 * N - 1; ++i) b[i] += K0[(size_t)i] * gl[0] + K1[(size_t)i] * gr[0];
+    return;
+  }
   std::vector<double> Wn, Wm;
   int64_t Sn, Sm;
   both_stencils(k, N, Wn, Sn, Wm, Sm);
@@ -296,7 +402,7 @@ void volume_correction(const KernelSpec& k, int64_t N, const double* gl, const d
 }
 
 void shift_level(TpxLevel& t, double shift, double scale) {
-  for (auto* v : {&t.a, &t.b, &t.c, &t.d, &t.p, &t.q, &t.xi, &t.zeta})
+  for (auto* v : {&t.a, &t.b, &t.c, &t.d, &t.p, &t.q, &t.xi, &t.zeta, &t.bsub, &t.bmain, &t.bsup})
     for (double& x : *v) x *= scale;
   t.o = t.o * scale + shift;
   t.a[t.n - 1] += shift;
@@ -359,6 +465,19 @@ TpxLevel finest_level(const KernelSpec& k, int64_t N) {
     t.zeta[i] = mid(2 * i + 2);
   }
   t.o = mid(0);
+  if (k.kind == K_WEAKLY_SINGULAR) {
+    // variable diagonal int_0^1 |x - y|^-gamma dy at the collocation points
+    const int64_t m = 2 * n + 1;
+    t.bsub.assign((size_t)m, 0.0);
+    t.bsup.assign((size_t)m, 0.0);
+    t.bmain.resize((size_t)m);
+    for (int64_t idx = 0; idx < m; ++idx) {
+      const double x = (idx < n) ? (double)(idx + 1) / (double)N
+                                 : ((double)(idx - n) + 0.5) / (double)N;
+      t.bmain[(size_t)idx] =
+          (std::pow(x, 1 - k.gamma) + std::pow(1 - x, 1 - k.gamma)) / (1 - k.gamma);
+    }
+  }
   return t;
 }
 
@@ -405,6 +524,33 @@ TpxLevel coarsen(const TpxLevel& f) {
     c.zeta[i] = 2.0 * R(roww, i);
   }
   c.o = 0.25 * colv[n - 1] + 0.5 * colo + 0.25 * colw[0];
+  if (f.has_band()) {
+    // R B P of the tridiagonal part: c[i][j] = sum_{e,f} w_e B[2i+e][2j+f] 2 w_f,
+    // w = (1/4, 1/2, 1/4); tridiagonal again
+    const int64_t m = 2 * n + 1, mc = n;
+    const double w[3] = {0.25, 0.5, 0.25};
+    auto Bat = [&](int64_t i, int64_t j) {
+      if (j == i) return f.bmain[(size_t)i];
+      if (j == i - 1) return f.bsub[(size_t)i];
+      if (j == i + 1) return f.bsup[(size_t)i];
+      return 0.0;
+    };
+    c.bsub.assign((size_t)mc, 0.0);
+    c.bmain.assign((size_t)mc, 0.0);
+    c.bsup.assign((size_t)mc, 0.0);
+    for (int64_t i = 0; i < mc; ++i)
+      for (int64_t jd = -1; jd <= 1; ++jd) {
+        const int64_t j = i + jd;
+        if (j < 0 || j >= mc) continue;
+        double acc = 0.0;
+        for (int e = 0; e < 3; ++e)
+          for (int ff = 0; ff < 3; ++ff) {
+            const int64_t r = 2 * i + e, q = 2 * j + ff;
+            if (r < m && q < m) acc += w[e] * Bat(r, q) * 2.0 * w[ff];
+          }
+        (jd < 0 ? c.bsub : (jd == 0 ? c.bmain : c.bsup))[(size_t)i] = acc;
+      }
+  }
   if (f.symmetric()) {
     // The Galerkin image of a symmetric level is symmetric, but the
     // recurrences above give mirror entries that agree only up to rounding.
@@ -445,6 +591,12 @@ std::vector<double> densify(const TpxLevel& t) {
     M[n * m + (n + 1 + i)] = t.zeta[i];
   }
   M[n * m + n] = t.o;
+  if (t.has_band())
+    for (int64_t i = 0; i < m; ++i) {
+      M[i * m + i] += t.bmain[(size_t)i];
+      if (i > 0) M[i * m + i - 1] += t.bsub[(size_t)i];
+      if (i + 1 < m) M[i * m + i + 1] += t.bsup[(size_t)i];
+    }
   return M;
 }
 

@@ -9,7 +9,8 @@
 
 namespace amg {
 
-enum KernelKind { K_CONST = 0, K_WEIGHTED = 1, K_FRACTIONAL = 2, K_GENERATORS = 3 };
+enum KernelKind { K_CONST = 0, K_WEIGHTED = 1, K_FRACTIONAL = 2, K_GENERATORS = 3,
+                  K_WEAKLY_SINGULAR = 4 };
 
 enum Scheme { SCHEME_SHIFTED = 0, SCHEME_STANDARD = 1 };
 
@@ -20,6 +21,7 @@ struct KernelSpec {
   double wl = 1.0, wr = 1.0;
   const double* gen = nullptr;
   int scheme = SCHEME_SHIFTED;
+  double gamma = 0.0;  // K_WEAKLY_SINGULAR: |x - y|^-gamma on (0, 1)
   // the standard rule is set up for the constant and weighted kernels
   bool supported() const { return !(scheme == SCHEME_STANDARD && kind == K_FRACTIONAL); }
 };
@@ -32,8 +34,14 @@ struct TpxLevel {
   std::vector<double> a, b, c, d;
   std::vector<double> p, q, xi, zeta;
   double o = 0.0;
-  // true when A = D_bar symmetric and C_bar = B_bar^T exactly: the packed
-  // spectra are then real / imaginary and stored compactly.
+  // Optional tridiagonal part on the block-ordered vector (empty: none):
+  // bsub[i] couples i to i-1, bmain[i] to i, bsup[i] to i+1 (bsub[0] =
+  // bsup[2n] = 0).  The variable diagonal of the weakly singular model
+  // (eq. (3system)) at the finest level; its Galerkin images below.
+  std::vector<double> bsub, bmain, bsup;
+  bool has_band() const { return !bmain.empty(); }
+  // true when A = D_bar symmetric and C_bar = B_bar^T exactly (and no band):
+  // the packed spectra are then real / imaginary and stored compactly.
   bool symmetric() const;
 };
 
@@ -49,6 +57,14 @@ std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* S);
 // the central one holding the point as its midpoint, the last one cut at the
 // horizon.  W[s2 + S], s2 in [-S, S] (odd s2: nodes, even: midpoints).
 std::vector<double> midpoint_stencil_standard(const KernelSpec& k, int64_t N, int64_t* S);
+
+// Weakly singular model (eq. (3system), kernel |x - y|^-gamma on (0, 1)):
+// node- and midpoint-row stencils W[s2 + S] = -h^(1-gamma) * product-
+// integration weight of the unknown at half-step offset s2 (S = 2N); the
+// couplings K0, K1 (2N-1 each, block order) of the boundary nodes x = 0, 1.
+void ws_stencils(double gamma, int64_t N, std::vector<double>& Wn, std::vector<double>& Wm,
+                 int64_t* S);
+void ws_boundary_coupling(double gamma, int64_t N, double* K0, double* K1);
 
 // Reach S (half-grid steps) of the node- and midpoint-row stencils.
 int64_t volume_reach(const KernelSpec& k, int64_t N);

@@ -195,8 +195,13 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
       bw[k] = r1[k];
     }
     if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) {
-      uv[k] = wpro * bv[k] / lv.dv;
-      uw[k] = wpro * bw[k] / lv.dw;
+      if (lv.dinv) {
+        uv[k] = wpro * bv[k] * lv.dinv[jj[k]];
+        uw[k] = wpro * bw[k] * lv.dinv[n + 1 + jj[k]];
+      } else {
+        uv[k] = wpro * bv[k] / lv.dv;
+        uw[k] = wpro * bw[k] / lv.dw;
+      }
     } else if (pro == TP_PROLONG) {
       uv[k] = r2[k] + r4[k];
       uw[k] = r3[k] + r5[k];
@@ -227,7 +232,7 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
     const T bo = wo_b;
     if (pro == TP_PRE_RESTRICT) lv.b[n] = bo;
     T uo;
-    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) uo = wpro * bo / lv.o;
+    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) uo = wpro * bo * (lv.dinv ? lv.dinv[n] : T(1) / lv.o);
     else if (pro == TP_PROLONG) uo = wo_u + wo_x;
     else uo = wo_u;
     if (pro != TP_USE_U) lv.u[n] = uo;
@@ -236,6 +241,27 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
   }
   const T qdot = block_sum<T, kNTT>(dot, s.red);  // also publishes z and the w_o slots
   const T uo = s.red[kNTT / 64], bo = s.red[kNTT / 64 + 1];
+  // band product of u (weakly singular levels), read from z before the FFT
+  T cbv[J], cbw[J], cbo = T(0);
+  const bool band = lv.bmain != nullptr;
+  if (band) {
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+      cbv[k] = cbw[k] = T(0);
+      const int j = jj[k], jw = n + 1 + j;
+      if (ok[k]) {
+        const cplx<T> zc = s.z[j];
+        const T vlo = j > 0 ? s.z[j - 1].x : T(0);
+        const T vhi = j + 1 < n ? s.z[j + 1].x : uo;
+        const T wlo = j > 0 ? s.z[j - 1].y : uo;
+        const T whi = j + 1 < n ? s.z[j + 1].y : T(0);
+        cbv[k] = lv.bsub[j] * vlo + lv.bmain[j] * zc.x + lv.bsup[j] * vhi;
+        cbw[k] = lv.bsub[jw] * wlo + lv.bmain[jw] * zc.y + lv.bsup[jw] * whi;
+      }
+    }
+    if (threadIdx.x == 0) cbo = lv.bsub[n] * s.z[n - 1].x + lv.bmain[n] * uo + lv.bsup[n] * s.z[0].y;
+    __syncthreads();  // every read of z is done before the FFT overwrites it
+  }
   tail_fft_spectral(lv, s, sp);
 #pragma unroll
   for (int k = 0; k < kTailJ; ++k) {
@@ -243,10 +269,17 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
     if (j < n) {
       const int jw = n + 1 + j;
       const cplx<T> y = s.z[j];
-      const T yv = y.x + pj[k] * uo, yw = y.y + xj[k] * uo;
+      T yv = y.x + pj[k] * uo, yw = y.y + xj[k] * uo;
+      if (band) {
+        yv += cbv[k];
+        yw += cbw[k];
+      }
       if (epi == TE_RESID) {
         lv.r[j] = bv[k] - yv;
         lv.r[jw] = bw[k] - yw;
+      } else if (band) {
+        lv.u[j] = uv[k] + wepi * (bv[k] - yv) * lv.dinv[j];
+        lv.u[jw] = uw[k] + wepi * (bw[k] - yw) * lv.dinv[jw];
       } else {
         lv.u[j] = uv[k] + wepi * (bv[k] - yv) / lv.dv;
         lv.u[jw] = uw[k] + wepi * (bw[k] - yw) / lv.dw;
@@ -254,9 +287,9 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
     }
   }
   if (threadIdx.x == 0) {
-    const T yo = qdot + lv.o * uo;
+    const T yo = qdot + lv.o * uo + cbo;
     if (epi == TE_RESID) lv.r[n] = bo - yo;
-    else lv.u[n] = uo + wepi * (bo - yo) / lv.o;
+    else lv.u[n] = uo + wepi * (bo - yo) * (band ? lv.dinv[n] : T(1) / lv.o);
   }
   __syncthreads();  // global writes visible to the next step; z and red reusable
 }
@@ -354,13 +387,26 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
   }
   TailSpec<T> sp;
   tail_spec_load(lv, sp);
-  const T yo = block_sum<T, kNTT>(dot, s.red) + lv.o * x[n];
+  // band product of x (weakly singular levels) at index i of the block-ordered vector
+  auto bandx = [&](int i) {
+    const int m = 2 * n + 1;
+    T y = lv.bmain[i] * x[i];
+    if (i > 0) y += lv.bsub[i] * x[i - 1];
+    if (i + 1 < m) y += lv.bsup[i] * x[i + 1];
+    return y;
+  };
+  const bool band = lv.bmain != nullptr;
+  const T yo = block_sum<T, kNTT>(dot, s.red) + lv.o * x[n] + (band ? bandx(n) : T(0));
   tail_fft_spectral(lv, s, sp);
   const T wo = x[n];
   double ss = 0.0;
   for (int j = threadIdx.x; j < n; j += kNTT) {
     const cplx<T> z = s.z[j];
-    const T yv = z.x + lv.p[j] * wo, yw = z.y + lv.xi[j] * wo;
+    T yv = z.x + lv.p[j] * wo, yw = z.y + lv.xi[j] * wo;
+    if (band) {
+      yv += bandx(j);
+      yw += bandx(n + 1 + j);
+    }
     if constexpr (EM == EPI_MV) {
       out.y[j] = yv;
       out.y[n + 1 + j] = yw;
@@ -761,6 +807,27 @@ __global__ void k_copy_f2d(const float* a, double* b, int64_t m) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) b[i] = (double)a[i];
 }
+
+// Band product bc = B x of a level's tridiagonal part (block-ordered vector).
+template <typename T>
+__global__ __launch_bounds__(kVecNT) void k_band_mv(LevelDev<T> lv, const T* x) {
+  const int m = 2 * lv.n + 1;
+  const int i = blockIdx.x * kVecNT + threadIdx.x;
+  if (i >= m) return;
+  T y = lv.bmain[i] * x[i];
+  if (i > 0) y += lv.bsub[i] * x[i - 1];
+  if (i + 1 < m) y += lv.bsup[i] * x[i + 1];
+  lv.bc[i] = y;
+}
+
+template <typename T>
+hipError_t launch_band_mv(const LevelDev<T>& lv, const T* x, hipStream_t s) {
+  const int m = 2 * lv.n + 1;
+  hipLaunchKernelGGL(k_band_mv<T>, (m + kVecNT - 1) / kVecNT, kVecNT, 0, s, lv, x);
+  return hipGetLastError();
+}
+template hipError_t launch_band_mv<double>(const LevelDev<double>&, const double*, hipStream_t);
+template hipError_t launch_band_mv<float>(const LevelDev<float>&, const float*, hipStream_t);
 
 // BDF4 history combination of eq. (bdf4), one element per thread
 __global__ __launch_bounds__(kVecNT) void k_bdf4_rhs(const double* u1, const double* u2,

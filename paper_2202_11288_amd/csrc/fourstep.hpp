@@ -156,8 +156,14 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
           v = bv;
           w = bw;
         }
-        v = in.omega * v / lv.dv;
-        w = in.omega * w / lv.dw;
+        if (lv.dinv) {  // variable diagonal (weakly singular levels)
+          const int js = ok[c] ? j : 0;
+          v = in.omega * v * lv.dinv[js];
+          w = in.omega * w * lv.dinv[n + 1 + js];
+        } else {
+          v = in.omega * v / lv.dv;
+          w = in.omega * w / lv.dw;
+        }
         if (ok[c]) {
           lv.u[j] = v;
           lv.u[jw] = w;
@@ -184,11 +190,11 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
   }
   if (wo_thread) {
     if constexpr (MODE == COL_PRE) {
-      lv.u[n] = in.omega * wo0 / lv.o;
+      lv.u[n] = in.omega * wo0 * (lv.dinv ? lv.dinv[n] : T(1) / lv.o);
     } else if constexpr (MODE == COL_PRE_RESTRICT) {
       const T bo = T(0.25) * (wo0 + T(2) * wo1 + wo2);
       lv.b[n] = bo;
-      lv.u[n] = in.omega * bo / lv.o;
+      lv.u[n] = in.omega * bo * (lv.dinv ? lv.dinv[n] : T(1) / lv.o);
     } else if constexpr (MODE == COL_PROLONG) {
       lv.u[n] = wo0 + wo1;
     } else if constexpr (MODE == COL_OUTER_UPDATE) {
@@ -562,14 +568,19 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
     }
   }
   const T wo = lv.scal[1];  // the matvec input's w_o (see k_row)
+  const bool band = lv.bc != nullptr;  // weakly singular levels: + B x, variable diagonal
   double ss = 0.0;
 #pragma unroll
   for (int e = 0; e < KH; ++e) {
     if (!ok[e]) continue;
     const int j = jj[e], jw = n + 1 + j;
     const cplx<T> y = a[e];
-    const T yv = y.x + pp[e] * wo;
-    const T yw = y.y + xx[e] * wo;
+    T yv = y.x + pp[e] * wo;
+    T yw = y.y + xx[e] * wo;
+    if (band) {
+      yv += lv.bc[j];
+      yw += lv.bc[jw];
+    }
     if constexpr (MODE == EPI_MV) {
       out.y[j] = yv;
       out.y[jw] = yw;
@@ -577,8 +588,13 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
       lv.r[j] = b0[e] - yv;
       lv.r[jw] = b1[e] - yw;
     } else if constexpr (MODE == EPI_SMOOTH) {
-      lv.u[j] = u0[e] + out.omega * (b0[e] - yv) / lv.dv;
-      lv.u[jw] = u1[e] + out.omega * (b1[e] - yw) / lv.dw;
+      if (band) {
+        lv.u[j] = u0[e] + out.omega * (b0[e] - yv) * lv.dinv[j];
+        lv.u[jw] = u1[e] + out.omega * (b1[e] - yw) * lv.dinv[jw];
+      } else {
+        lv.u[j] = u0[e] + out.omega * (b0[e] - yv) / lv.dv;
+        lv.u[jw] = u1[e] + out.omega * (b1[e] - yw) / lv.dw;
+      }
     } else {  // EPI_OUTER
       const double rv = o0[e] - (double)yv, rw = o1[e] - (double)yw;
       out.ro[j] = rv;
@@ -591,12 +607,13 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
     }
   }
   if (wo_thread) {
+    if (band) yo += lv.bc[n];
     if constexpr (MODE == EPI_MV) {
       out.y[n] = yo;
     } else if constexpr (MODE == EPI_RESID) {
       lv.r[n] = wb - yo;
     } else if constexpr (MODE == EPI_SMOOTH) {
-      lv.u[n] = wu + out.omega * (wb - yo) / lv.o;
+      lv.u[n] = wu + out.omega * (wb - yo) * (band ? lv.dinv[n] : T(1) / lv.o);
     } else {
       const double ro = wbo - (double)yo;
       out.ro[n] = ro;
