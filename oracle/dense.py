@@ -79,6 +79,7 @@ class Options:
     m2: int = 1
     omega_pre: float = 2.0 / 3.0
     omega_post: float = 2.0 / 3.0
+    cycle: int = 1  # coarse-level visits per cycle: 1 = V, 2 = W (Toeplitz-plus-Cross path)
 
 
 def jacobi(A, u, b, omega):

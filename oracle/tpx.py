@@ -324,15 +324,25 @@ class Hierarchy:
         return self.levels[0].matvec(u)
 
 
-def vcycle(H: Hierarchy, b, opts: Options = Options(), level: int = 0):
-    """Algorithm 2 on Toeplitz-plus-Cross levels (same steps as oracle.dense.vcycle)."""
+def vcycle(H: Hierarchy, b, opts: Options = Options(), level: int = 0, x0=None):
+    """Algorithm 2 on Toeplitz-plus-Cross levels (same steps as oracle.dense.vcycle).
+
+    opts.cycle = 2 gives the W-cycle: the correction of every level above the
+    coarsest is computed by two cycles on the next level, the second starting
+    from the first's result (the same right-hand side); the level above the
+    coarsest visits the exact solve once.  x0 is the level's initial guess
+    (zero when None)."""
     if level == len(H.levels) - 1:
         return scipy.linalg.lu_solve(H.lu, b)
     L = H.levels[level]
-    u = np.zeros_like(b)
+    u = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     for _ in range(opts.m1):
         u = u + opts.omega_pre * (b - L.matvec(u)) / L.diag
-    e = vcycle(H, restrict(b - L.matvec(u)), opts, level + 1)
+    rc = restrict(b - L.matvec(u))
+    visits = 1 if level + 2 == len(H.levels) else opts.cycle
+    e = None
+    for _ in range(visits):
+        e = vcycle(H, rc, opts, level + 1, e)
     u = u + prolong(e)
     for _ in range(opts.m2):
         u = u + opts.omega_post * (b - L.matvec(u)) / L.diag

@@ -192,3 +192,36 @@ def test_pcg_energy_error_decreases(kern):
     assert np.abs(x - xs).max() <= 1e-7 * np.abs(xs).max()
     _, it_stat, _ = tpx.solve(H, b, tol=1e-10, max_iter=500)
     assert it <= it_stat, (it, it_stat)
+
+
+def test_w_cycle_pins():
+    """W-cycle (opts.cycle = 2): with two levels it is the V-cycle (the
+    coarsest is solved exactly once); it is a fixed linear map (B(r1 + r2) =
+    B r1 + B r2) whose error propagator I - B A contracts more than the
+    V-cycle's; for the fractional kernel (alpha = 0.4) the stationary
+    W-iteration count stays flat in N while the V-iteration's grows."""
+    k = D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4)
+    W = tpx.Options(cycle=2)
+    N = 64
+    H2 = tpx.Hierarchy.build(tpx.from_stencil(k, N), 5)
+    r = synthetic.random_vector(2 * N - 1, seed=1)
+    np.testing.assert_array_equal(tpx.vcycle(H2, r, W), tpx.vcycle(H2, r))
+    H = tpx.Hierarchy.build(tpx.from_stencil(k, N), 2)
+    r2 = synthetic.random_vector(2 * N - 1, seed=2)
+    lin = tpx.vcycle(H, r + r2, W) - tpx.vcycle(H, r, W) - tpx.vcycle(H, r2, W)
+    assert np.abs(lin).max() <= 1e-10 * np.abs(tpx.vcycle(H, r, W)).max()
+    A = H.levels[0].T.dense()
+    m = A.shape[0]
+    BW = np.column_stack([tpx.vcycle(H, e, W) for e in np.eye(m)])
+    BV = np.column_stack([tpx.vcycle(H, e) for e in np.eye(m)])
+    rho = lambda Bm: max(abs(np.linalg.eigvals(np.eye(m) - Bm @ A)))
+    assert rho(BW) < rho(BV) < 1
+    its = {}
+    for N in (256, 1024, 4096):
+        HN = tpx.Hierarchy.build(tpx.from_stencil(k, N), 5)
+        b = synthetic.random_vector(2 * N - 1, seed=N)
+        its[N] = (tpx.solve(HN, b, tol=1e-10, max_iter=600, opts=W)[1],
+                  tpx.solve(HN, b, tol=1e-10, max_iter=600)[1])
+    w = [v[0] for v in its.values()]
+    v = [v[1] for v in its.values()]
+    assert max(w) - min(w) <= 5 and v[-1] > 2 * v[0] and w[-1] < v[-1], its
