@@ -123,7 +123,17 @@ typedef struct {
   int inner;                  /* AMG_INNER_VCYCLE (default) or AMG_INNER_PCG */
   double shift, scale;        /* operator shift*I + scale*A (defaults 0, 1)  */
   int restart;                /* AMG_INNER_GMRES cycle length, 1..64 (30)    */
+  int cycle;                  /* coarse visits per level: 1 = V-cycle (the
+                                 paper's Algorithm 2, default), 2 = W-cycle */
 } amg_opts_t;
+
+/* W-cycle (cycle = 2): every level above the coarsest computes its coarse
+   correction with two cycles on the next level, the second starting from the
+   first's result with the same right-hand side (m1 smoothing sweeps from that
+   iterate, then the residual); the level above the coarsest solves exactly
+   once.  It keeps the stationary iteration count flat in N where the V-cycle's
+   grows (the fractional kernel), at the price of 2^l visits of level l: the
+   small levels, which are latency-bound, then dominate the cycle's time. */
 
 /* Shifted operators (Sec. 5, eq. (bdf4)).  With shift = sigma and scale = s
    the handle solves (sigma I + s A) x = b, A the collocation matrix of the

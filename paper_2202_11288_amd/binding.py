@@ -45,7 +45,7 @@ class amg_opts_t(ctypes.Structure):
                 ("omega_post", ctypes.c_double), ("coarsest_log2", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("flags", ctypes.c_int),
                 ("inner", ctypes.c_int), ("shift", ctypes.c_double), ("scale", ctypes.c_double),
-                ("restart", ctypes.c_int)]
+                ("restart", ctypes.c_int), ("cycle", ctypes.c_int)]
 
 
 class amg_stat_t(ctypes.Structure):

@@ -234,6 +234,10 @@ struct amg_ctx {
   double* gm_small = nullptr;  // g | cs | sn | hcur | y | hn, kGmMax + 1 each
   double* gm_part = nullptr;
   int gm_j = 0;
+  // W-cycles (cycle = 2): the small-level programs for the first and the
+  // later visits of the first small level
+  TailOp* tail_prog[2] = {nullptr, nullptr};
+  int tail_prog_n[2] = {0, 0};
 };
 
 namespace {
@@ -315,6 +319,7 @@ int check_opts(const amg_opts_t* o) {
   if (o->inner != AMG_INNER_VCYCLE && o->inner != AMG_INNER_PCG && o->inner != AMG_INNER_GMRES)
     return AMG_EINVAL;
   if (o->restart < 1 || o->restart > kGmMax) return AMG_EINVAL;
+  if (o->cycle != 1 && o->cycle != 2) return AMG_EINVAL;
   if (!(std::isfinite(o->scale) && o->scale > 0.0) || !std::isfinite(o->shift)) return AMG_EINVAL;
   return AMG_OK;
 }
@@ -407,8 +412,12 @@ int fourstep(amg_ctx* c, int l, int cmode, const ColIn<T>& in, int emode, const 
 }
 
 template <typename T>
+int wcycle_visit(amg_ctx* c, int l, bool first, hipStream_t s);
+
+template <typename T>
 int vcycle_dev(amg_ctx* c, hipStream_t s) {
   // input: level 0's b; output: level 0's u (precision T)
+  if (c->opts.cycle == 2) return wcycle_visit<T>(c, 0, true, s);
   const amg_opts_t& o = c->opts;
   const int nl = (int)c->lv.size();
   const int ft = c->first_tail;
@@ -454,6 +463,84 @@ int vcycle_dev(amg_ctx* c, hipStream_t s) {
       in = ColIn<T>{};
       in.x = d.u;
     }
+  }
+  return AMG_OK;
+}
+
+// The small-level part of a W-cycle visit of level l (first visit: smoothing
+// from zero as in the V-cycle; later visits: m1 sweeps from the current
+// iterate, then the residual); every level above the coarsest visits the
+// next level `gamma` times, the level above the coarsest visits it once.
+void tail_visit(std::vector<TailOp>& ops, int l, bool first, int ft, int last, int m1, int m2,
+                int gamma, bool has_rf) {
+  if (l == last) {
+    ops.push_back({last, 0, 0, TAILOP_COARSE});
+    return;
+  }
+  if (first) {
+    for (int sw = 0; sw < m1; ++sw) {
+      const int pro = sw > 0 ? TP_USE_U : ((l == ft && !has_rf) ? TP_PRE_B : TP_PRE_RESTRICT);
+      ops.push_back({l, pro, sw == m1 - 1 ? TE_RESID : TE_SMOOTH, 0});
+    }
+  } else {
+    for (int sw = 0; sw < m1; ++sw) ops.push_back({l, TP_USE_U, TE_SMOOTH, 0});
+    ops.push_back({l, TP_USE_U, TE_RESID, 0});
+  }
+  const int visits = (l + 1 == last) ? 1 : gamma;
+  for (int v = 0; v < visits; ++v) tail_visit(ops, l + 1, v == 0, ft, last, m1, m2, gamma, has_rf);
+  for (int sw = 0; sw < m2; ++sw)
+    ops.push_back({l, sw == 0 ? TP_PROLONG : TP_USE_U, TE_SMOOTH, TAILOP_UP});
+}
+
+// Level l of a W-cycle on the four-step levels (the small levels run as one
+// program per visit).
+template <typename T>
+int wcycle_visit(amg_ctx* c, int l, bool first, hipStream_t s) {
+  const amg_opts_t& o = c->opts;
+  const int nl = (int)c->lv.size();
+  const int ft = c->first_tail;
+  const T wpre = (T)o.omega_pre, wpost = (T)o.omega_post;
+  if (l == ft) {
+    const T* rf = (ft > 0) ? c->lv[ft - 1].template dev<T>().r : nullptr;
+    const int k = first ? 0 : 1;
+    HIP_TRY(launch_tail_program<T>(lvdev_of<T>(c), ft, nl - 1, rf, c->tail_prog[k],
+                                   c->tail_prog_n[k], wpre, wpost, c->lu, tw_of<T>(c),
+                                   c->maxL_tail, s));
+    return AMG_OK;
+  }
+  const LevelDev<T> d = c->lv[l].template dev<T>();
+  EpiOut<T> out{};
+  out.xin = d.u;
+  out.omega = wpre;
+  ColIn<T> mv{};
+  mv.x = d.u;
+  if (first) {
+    ColIn<T> in{};
+    in.omega = wpre;
+    int cmode = COL_PRE;
+    if (l > 0) {
+      cmode = COL_PRE_RESTRICT;
+      in.x = c->lv[l - 1].template dev<T>().r;
+    }
+    for (int sweep = 1; sweep <= o.m1; ++sweep) {
+      AMG_TRY(fourstep<T>(c, l, cmode, in, sweep == o.m1 ? EPI_RESID : EPI_SMOOTH, out, s));
+      cmode = COL_MV;
+      in = mv;
+    }
+  } else {
+    for (int sweep = 0; sweep < o.m1; ++sweep) AMG_TRY(fourstep<T>(c, l, COL_MV, mv, EPI_SMOOTH, out, s));
+    AMG_TRY(fourstep<T>(c, l, COL_MV, mv, EPI_RESID, out, s));
+  }
+  const int visits = (l + 1 == nl - 1) ? 1 : o.cycle;
+  for (int v = 0; v < visits; ++v) AMG_TRY(wcycle_visit<T>(c, l + 1, v == 0, s));
+  ColIn<T> in{};
+  in.x = c->lv[l + 1].template dev<T>().u;
+  int cmode = COL_PROLONG;
+  out.omega = wpost;
+  for (int sweep = 0; sweep < o.m2; ++sweep) {
+    AMG_TRY(fourstep<T>(c, l, cmode, in, EPI_SMOOTH, out, s));
+    cmode = COL_MV;
+    in = mv;
   }
   return AMG_OK;
 }
@@ -710,6 +797,19 @@ int setup_device(amg_ctx* c, hipStream_t s) {
                              hipMemcpyHostToDevice, s));
     }
   }
+  if (c->opts.cycle == 2) {
+    const int ft = c->first_tail, last = nl - 1;
+    for (int k = 0; k < 2; ++k) {
+      std::vector<TailOp> ops;
+      tail_visit(ops, ft, k == 0, ft, last, c->opts.m1, c->opts.m2, c->opts.cycle, ft > 0);
+      std::vector<int> raw(ops.size() * 4);
+      std::memcpy(raw.data(), ops.data(), raw.size() * sizeof(int));
+      int* dev = nullptr;
+      AMG_TRY(upload(c, &dev, raw, s));
+      c->tail_prog[k] = reinterpret_cast<TailOp*>(dev);
+      c->tail_prog_n[k] = (int)ops.size();
+    }
+  }
   AMG_TRY(dalloc(c, &c->st_dev, 1));
   AMG_TRY(dalloc(c, &c->hist_dev, (size_t)c->opts.max_iter + 2));
   if (mixed) AMG_TRY(dalloc(c, &c->rout, (size_t)(2 * c->N - 1)));
@@ -766,6 +866,7 @@ void amg_default_opts(amg_opts_t* o) {
   o->shift = 0.0;
   o->scale = 1.0;
   o->restart = 30;
+  o->cycle = 1;
 }
 
 const char* amg_strerror(int st) {

@@ -91,6 +91,17 @@ struct EpiOut {
   float* r32;          // EPI_OUTER: FP32 copy of the residual (may be null)
 };
 
+// Steps of the small-level kernel: how a step forms its iterate (prologue)
+// and what its epilogue writes.
+enum TailPro { TP_PRE_B = 0, TP_PRE_RESTRICT, TP_USE_U, TP_PROLONG };
+enum TailEpi { TE_RESID = 0, TE_SMOOTH };
+// One step of a small-level program (W-cycles): a matvec step of `level`
+// (pro, epi; post-smoothing damping when TAILOP_UP) or the coarsest solve.
+enum TailOpFlags { TAILOP_COARSE = 1, TAILOP_UP = 2 };
+struct TailOp {
+  int level, pro, epi, flags;
+};
+
 // Coarsest level: A_c^{-1} (column-major m x m), formed at setup from the
 // LU factors with partial pivoting.
 struct CoarseLU {
@@ -149,6 +160,10 @@ template <typename T>
 hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
                               int m1, int m2, T wpre, T wpost, const CoarseLU& lu,
                               const Twiddles<T>& tw, int maxL, hipStream_t s);
+template <typename T>
+hipError_t launch_tail_program(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
+                               const TailOp* ops, int nops, T wpre, T wpost, const CoarseLU& lu,
+                               const Twiddles<T>& tw, int maxL, hipStream_t s);
 hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, const double* gy,
                                  cplx<double>* out, const Twiddles<double>& tw, hipStream_t s);
 hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1,

@@ -103,8 +103,6 @@ __device__ void tail_fft_spectral(const LevelDev<T>& lv, const TailLds<T>& s, co
   lds_fft<T, kET, kNTT, true>(s.z, g, s.tw);
 }
 
-enum TailPro { TP_PRE_B = 0, TP_PRE_RESTRICT, TP_USE_U, TP_PROLONG };
-enum TailEpi { TE_RESID = 0, TE_SMOOTH };
 constexpr int kTailJ = (1 << (kTailLog - 1)) / kNTT;  // v/w slots per thread (n < L/2)
 
 // One matvec step of a tail level: form u (prologue), y = A u, then the
@@ -356,6 +354,36 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
     }
     const LevelDev<T> lv = levels[l];
     tail_step(lv, pro, epi, src, wpro, wepi, s);
+  }
+}
+
+// A cycle's small-level part as a program of steps built on the host (the
+// W-cycle: the second visit of a level smooths from its current iterate and
+// recomputes the residual; see TailOp).
+template <typename T>
+__global__ __launch_bounds__(kNTT) void k_tail_program(const LevelDev<T>* levels, int first,
+                                                       int last, const T* rf, const TailOp* ops,
+                                                       int nops, T wpre, T wpost, CoarseLU lu,
+                                                       Twiddles<T> tw) {
+  extern __shared__ unsigned char smem_raw[];
+  const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);
+  for (int k = 0; k < nops; ++k) {
+    const TailOp op = ops[k];
+    if (op.flags & TAILOP_COARSE) {  // coarsest level: b = R r_fine, exact solve
+      const LevelDev<T> lc = levels[last];
+      const T* src = (last == first) ? rf : levels[last - 1].r;
+      if (src)
+        for (int i = threadIdx.x; i < 2 * lc.n + 1; i += kNTT) lc.b[i] = restrict_at(src, i);
+      __syncthreads();
+      coarse_solve<T>(lu, lc.b, lc.u, reinterpret_cast<double*>(s.z.p));
+      continue;
+    }
+    const int l = op.level;
+    const T* src = nullptr;
+    if (op.pro == TP_PRE_RESTRICT) src = (l == first) ? rf : levels[l - 1].r;
+    if (op.pro == TP_PROLONG) src = levels[l + 1].u;
+    const T w = (op.flags & TAILOP_UP) ? wpost : wpre;
+    tail_step(levels[l], op.pro, op.epi, src, w, w, s);
   }
 }
 
@@ -878,6 +906,16 @@ hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last
                     wpost, lu, tw);
 }
 
+template <typename T>
+hipError_t launch_tail_program(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
+                               const TailOp* ops, int nops, T wpre, T wpost, const CoarseLU& lu,
+                               const Twiddles<T>& tw, int maxL, hipStream_t s) {
+  if (maxL > (1 << kTailLog) || lu.m > 4 * (1 << kTailLog)) return hipErrorInvalidValue;
+  const size_t lds = tail_lds_bytes(sizeof(T));
+  return launch_lds(k_tail_program<T>, 1, kNTT, lds, s, levels_dev, first, last, rf, ops, nops,
+                    wpre, wpost, lu, tw);
+}
+
 hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, const double* gy,
                                  cplx<double>* out, const Twiddles<double>& tw, hipStream_t s) {
   if (lv.logL > kTailLog) return hipErrorInvalidValue;
@@ -1018,7 +1056,10 @@ template hipError_t launch_cg_dir<float>(const SolveState*, double*, const float
                                             hipStream_t);                                      \
   template hipError_t launch_tail_vcycle<T>(const LevelDev<T>*, int, int, const T*, int, int,  \
                                             T, T, const CoarseLU&, const Twiddles<T>&, int,    \
-                                            hipStream_t);
+                                            hipStream_t);                                      \
+  template hipError_t launch_tail_program<T>(const LevelDev<T>*, int, int, const T*,           \
+                                             const TailOp*, int, T, T, const CoarseLU&,        \
+                                             const Twiddles<T>&, int, hipStream_t);
 AMG_INSTANTIATE(double)
 AMG_INSTANTIATE(float)
 

@@ -107,6 +107,7 @@ def _setup_status(kern, delta, N, **opts):
     dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=8)),
     dict(opts=dict(inner=3)), dict(opts=dict(inner=-1)),
     dict(opts=dict(inner=B.AMG_INNER_GMRES, restart=0)), dict(opts=dict(restart=65)),
+    dict(opts=dict(cycle=0)), dict(opts=dict(cycle=3)),
     dict(kind=B.AMG_K_WEIGHTED, wl=1.2, opts=dict(inner=B.AMG_INNER_PCG)),
 ])
 def test_invalid_arguments_rejected(case):
