@@ -110,7 +110,7 @@ constexpr int kTailJ = (1 << (kTailLog - 1)) / kNTT;  // v/w slots per thread (n
 // The prologue issues every global load of the step (spectra, Cross vectors,
 // b / u / the neighbouring level's vector, and thread 0's w_o operands) as
 // one batch with clamped addresses before any of them is used.
-template <typename T>
+template <typename T, bool BAND>
 __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int epi, const T* src,
                                           T wpro, T wepi, const TailLds<T>& s) {
   constexpr int J = kTailJ;
@@ -193,7 +193,7 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
       bw[k] = r1[k];
     }
     if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) {
-      if (lv.dinv) {
+      if constexpr (BAND) {
         uv[k] = wpro * bv[k] * lv.dinv[jj[k]];
         uw[k] = wpro * bw[k] * lv.dinv[n + 1 + jj[k]];
       } else {
@@ -230,7 +230,7 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
     const T bo = wo_b;
     if (pro == TP_PRE_RESTRICT) lv.b[n] = bo;
     T uo;
-    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) uo = wpro * bo * (lv.dinv ? lv.dinv[n] : T(1) / lv.o);
+    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) uo = wpro * bo * (BAND ? lv.dinv[n] : T(1) / lv.o);
     else if (pro == TP_PROLONG) uo = wo_u + wo_x;
     else uo = wo_u;
     if (pro != TP_USE_U) lv.u[n] = uo;
@@ -239,55 +239,70 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
   }
   const T qdot = block_sum<T, kNTT>(dot, s.red);  // also publishes z and the w_o slots
   const T uo = s.red[kNTT / 64], bo = s.red[kNTT / 64 + 1];
-  // band product of u (weakly singular levels), read from z before the FFT
-  T cbv[J], cbw[J], cbo = T(0);
-  const bool band = lv.bmain != nullptr;
-  if (band) {
-#pragma unroll
-    for (int k = 0; k < J; ++k) {
-      cbv[k] = cbw[k] = T(0);
-      const int j = jj[k], jw = n + 1 + j;
-      if (ok[k]) {
-        const cplx<T> zc = s.z[j];
-        const T vlo = j > 0 ? s.z[j - 1].x : T(0);
-        const T vhi = j + 1 < n ? s.z[j + 1].x : uo;
-        const T wlo = j > 0 ? s.z[j - 1].y : uo;
-        const T whi = j + 1 < n ? s.z[j + 1].y : T(0);
-        cbv[k] = lv.bsub[j] * vlo + lv.bmain[j] * zc.x + lv.bsup[j] * vhi;
-        cbw[k] = lv.bsub[jw] * wlo + lv.bmain[jw] * zc.y + lv.bsup[jw] * whi;
-      }
-    }
-    if (threadIdx.x == 0) cbo = lv.bsub[n] * s.z[n - 1].x + lv.bmain[n] * uo + lv.bsup[n] * s.z[0].y;
-    __syncthreads();  // every read of z is done before the FFT overwrites it
-  }
+  constexpr bool band = BAND;  // weakly singular levels (the band's pointers are set)
   tail_fft_spectral(lv, s, sp);
+  if constexpr (band) {
+    // weakly singular levels: + B u with u read back from the level's iterate
+    // (every thread stored or holds its part before the FFT's barriers); all
+    // new values are formed before any is stored, so no neighbour is
+    // overwritten while another thread still reads it
+    auto bandu = [&](int i) {
+      const int m = 2 * n + 1;
+      T y = lv.bmain[i] * lv.u[i];
+      if (i > 0) y += lv.bsub[i] * lv.u[i - 1];
+      if (i + 1 < m) y += lv.bsup[i] * lv.u[i + 1];
+      return y;
+    };
+    T nv[kTailJ], nw[kTailJ], no = T(0);
 #pragma unroll
-  for (int k = 0; k < kTailJ; ++k) {
-    const int j = threadIdx.x + k * kNTT;
-    if (j < n) {
-      const int jw = n + 1 + j;
-      const cplx<T> y = s.z[j];
-      T yv = y.x + pj[k] * uo, yw = y.y + xj[k] * uo;
-      if (band) {
-        yv += cbv[k];
-        yw += cbw[k];
-      }
-      if (epi == TE_RESID) {
-        lv.r[j] = bv[k] - yv;
-        lv.r[jw] = bw[k] - yw;
-      } else if (band) {
-        lv.u[j] = uv[k] + wepi * (bv[k] - yv) * lv.dinv[j];
-        lv.u[jw] = uw[k] + wepi * (bw[k] - yw) * lv.dinv[jw];
-      } else {
-        lv.u[j] = uv[k] + wepi * (bv[k] - yv) / lv.dv;
-        lv.u[jw] = uw[k] + wepi * (bw[k] - yw) / lv.dw;
+    for (int k = 0; k < kTailJ; ++k) {
+      const int j = threadIdx.x + k * kNTT;
+      nv[k] = nw[k] = T(0);
+      if (j < n) {
+        const int jw = n + 1 + j;
+        const cplx<T> y = s.z[j];
+        const T yv = y.x + pj[k] * uo + bandu(j), yw = y.y + xj[k] * uo + bandu(jw);
+        nv[k] = epi == TE_RESID ? bv[k] - yv : uv[k] + wepi * (bv[k] - yv) * lv.dinv[j];
+        nw[k] = epi == TE_RESID ? bw[k] - yw : uw[k] + wepi * (bw[k] - yw) * lv.dinv[jw];
       }
     }
-  }
-  if (threadIdx.x == 0) {
-    const T yo = qdot + lv.o * uo + cbo;
-    if (epi == TE_RESID) lv.r[n] = bo - yo;
-    else lv.u[n] = uo + wepi * (bo - yo) * (band ? lv.dinv[n] : T(1) / lv.o);
+    if (threadIdx.x == 0) {
+      const T yo = qdot + lv.o * uo + bandu(n);
+      no = epi == TE_RESID ? bo - yo : uo + wepi * (bo - yo) * lv.dinv[n];
+    }
+    __syncthreads();
+    T* dst = epi == TE_RESID ? lv.r : lv.u;
+#pragma unroll
+    for (int k = 0; k < kTailJ; ++k) {
+      const int j = threadIdx.x + k * kNTT;
+      if (j < n) {
+        dst[j] = nv[k];
+        dst[n + 1 + j] = nw[k];
+      }
+    }
+    if (threadIdx.x == 0) dst[n] = no;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kTailJ; ++k) {
+      const int j = threadIdx.x + k * kNTT;
+      if (j < n) {
+        const int jw = n + 1 + j;
+        const cplx<T> y = s.z[j];
+        const T yv = y.x + pj[k] * uo, yw = y.y + xj[k] * uo;
+        if (epi == TE_RESID) {
+          lv.r[j] = bv[k] - yv;
+          lv.r[jw] = bw[k] - yw;
+        } else {
+          lv.u[j] = uv[k] + wepi * (bv[k] - yv) / lv.dv;
+          lv.u[jw] = uw[k] + wepi * (bw[k] - yw) / lv.dw;
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      const T yo = qdot + lv.o * uo;
+      if (epi == TE_RESID) lv.r[n] = bo - yo;
+      else lv.u[n] = uo + wepi * (bo - yo) / lv.o;
+    }
   }
   __syncthreads();  // global writes visible to the next step; z and red reusable
 }
@@ -353,7 +368,10 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
       wpro = wepi = wpost;
     }
     const LevelDev<T> lv = levels[l];
-    tail_step(lv, pro, epi, src, wpro, wepi, s);
+    if (lv.bmain)
+      tail_step<T, true>(lv, pro, epi, src, wpro, wepi, s);
+    else
+      tail_step<T, false>(lv, pro, epi, src, wpro, wepi, s);
   }
 }
 
@@ -383,7 +401,10 @@ __global__ __launch_bounds__(kNTT) void k_tail_program(const LevelDev<T>* levels
     if (op.pro == TP_PRE_RESTRICT) src = (l == first) ? rf : levels[l - 1].r;
     if (op.pro == TP_PROLONG) src = levels[l + 1].u;
     const T w = (op.flags & TAILOP_UP) ? wpost : wpre;
-    tail_step(levels[l], op.pro, op.epi, src, w, w, s);
+    if (levels[l].bmain)
+      tail_step<T, true>(levels[l], op.pro, op.epi, src, w, w, s);
+    else
+      tail_step<T, false>(levels[l], op.pro, op.epi, src, w, w, s);
   }
 }
 
