@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=512,
                     help="instances of the uneven batch (seeded N, delta, kernel, random b) "
                          "solved together by amg_solve_batch beside the headline; 0 = skip")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the precision configuration (N = 2^22, fractional alpha = 0.4, "
+                         "delta = 0.1, FP32 V-cycle + FP64 residual, CG) beside the headline")
     ap.add_argument("--pmc-driver", action="store_true",
                     help="the short program the --pmc counter runs profile: a plain copy of "
                          "known size, then two mixed solves of the workload (eager launches)")
@@ -339,6 +342,49 @@ def run_batch(B, torch, args):
                         f"tol={args.tol}"}
 
 
+def run_c3(B, torch, args):
+    """N = 2^22 intervals (8,388,607 unknowns), delta = 0.1, fractional kernel
+    alpha = 0.4, manufactured right-hand side, tol 1e-10: the mixed form
+    (FP32 V-cycle, FP64 residual and update, FP64 coarsest solve) and the FP64
+    form, both with V-cycle-preconditioned CG (the stationary iteration needs
+    thousands of V-cycles here); the oracle evaluates the mixed solution's
+    residual and its error against the FP64 solution.  The recurrence passes
+    1e-10; the true residual, which decides, stops near 2e-9 (the FP64 floor
+    eps |A| |x| / |b| of this operator at this size): status "fp64 floor"."""
+    N = 2 ** 22
+    k = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4)
+    b = B.amg_manufactured_rhs(k, 0.1, N)
+    bd = torch.from_numpy(b).cuda()
+    out = {"workload": "N=2^22, delta=0.1, fractional alpha=0.4, manufactured u=x^2(1-x)^2, "
+                       "tol=1e-10, inner=PCG"}
+    xs = {}
+    for name, prec in (("mixed", B.AMG_MIXED), ("fp64", B.AMG_FP64)):
+        h = B.amg_setup(k, 0.1, N, B.amg_default_opts(precision=prec, inner=B.AMG_INNER_PCG,
+                                                     max_iter=1000))
+        try:
+            x = torch.zeros_like(bd)
+            B.amg_solve(h, bd, x, args.tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))  # warm-up
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it, rel = B.amg_solve(h, bd, x, args.tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            B.amg_destroy(h)
+        xs[name] = x.cpu().numpy()
+        out[name] = {"s_per_solve": round(dt, 4), "iters": it, "relres_true": rel,
+                     "status": {B.AMG_OK: "ok", B.AMG_NOT_CONVERGED: "fp64 floor"}[st],
+                     "unknowns_per_s": round((2 * N - 1) / dt, 1)}
+    out["err_mixed_vs_fp64"] = float(np.abs(xs["mixed"] - xs["fp64"]).max() / np.abs(xs["fp64"]).max())
+    if not args.no_cpu_baseline:
+        from oracle import discretize as D
+        from oracle import tpx
+        H = tpx.Hierarchy.build(tpx.from_stencil(D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), N), 5)
+        out["relres_mixed_oracle"] = float(np.linalg.norm(b - H.matvec(xs["mixed"])) / np.linalg.norm(b))
+    return out
+
+
 def cpu_baseline(args, b, x_fp64, x_mixed):
     """The oracle (CPU FP64, scipy FFT) on the same workload: one full solve,
     hierarchy setup excluded, on the host's cores; also evaluates the GPU
@@ -410,6 +456,10 @@ def main():
         krylov = {"note": "V-cycle-preconditioned CG (inner = AMG_INNER_PCG): same V-cycle, "
                           "Krylov outer iteration; not the paper's stationary iteration",
                   "mixed": kmx, "fp64": k64}
+    c3 = None
+    if not args.no_c3:
+        c3 = run_c3(B, torch, args)
+        print(f"# c3 done: {c3}", file=sys.stderr, flush=True)
     batch = None
     if args.batch > 0:
         batch = run_batch(B, torch, args)
@@ -451,6 +501,7 @@ def main():
         "speedup_mixed_vs_fp64": round(smx["solves_per_s"] / s64["solves_per_s"], 3),
         "pcg": krylov,
         "batch": batch,
+        "precision_config": c3,
         "roofline": roof, "roofline_fp64_form": roof64, "roofline_fp32_sweep": roof32,
         "roofline_source": (f"HIP events around the finest-level FFT passes on the solve stream, "
                             f"{args.prof_steps} profiled solves per form launched eagerly "

@@ -156,9 +156,14 @@ typedef struct {
    symmetric generators); Polak-Ribiere direction update, so a V-cycle run in
    FP32 (AMG_MIXED) stays a valid preconditioner.  CG's theory wants a
    symmetric V-cycle: m1 = m2 and omega_pre = omega_post (the defaults).  The
-   residual is the recurrence's r <- r - alpha A p in FP64; the stopping rule
-   is the same.  A non-positive <r, B r> or <p, A p> ends the solve with
-   AMG_DIVERGED. */
+   iteration runs on the recurrence's residual r <- r - alpha A p (FP64); when
+   it passes the stop test, the true residual b - A x is formed and decides
+   (the recurrence drifts from it on ill-conditioned problems): below tol the
+   solve ends, otherwise CG restarts from it; a true residual not below 0.9
+   times the previous one ends the solve with AMG_NOT_CONVERGED (it has
+   reached what FP64 resolves for this operator, about eps |A| |x| / |b|).
+   relres and the history's last entry are the true residual's.  A non-positive <r, B r> or <p, A p> ends
+   the solve with AMG_DIVERGED. */
 #define AMG_INNER_VCYCLE 0
 #define AMG_INNER_PCG 1
 /* AMG_INNER_GMRES: restarted flexible GMRES right-preconditioned by one

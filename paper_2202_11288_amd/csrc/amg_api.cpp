@@ -222,6 +222,7 @@ struct amg_ctx {
   double* cg_q = nullptr;
   double* cg_rold = nullptr;
   double* cg_part = nullptr;
+  bool cg_restart = false;  // the next CG step starts a new direction sequence
   // right-hand side of amg_bdf4_step (allocated by its first call)
   double* step_b = nullptr;
   // restarted flexible GMRES (inner = AMG_INNER_GMRES): basis V ((restart+1)
@@ -585,7 +586,7 @@ int vcycle_run(amg_ctx* c, hipStream_t s) {
 // r = b - A x on the finest level (FP64), optionally with x += e fused in
 // front; writes the residual-norm partials and runs the stopping test.
 int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double tol,
-                   hipStream_t s, bool gm_check = false) {
+                   hipStream_t s, bool gm_check = false, bool stall = false) {
   const LevelRes& L0 = c->lv[0];
   const LevelDev<double> d = L0.dev<double>();
   ColIn<double> in{};
@@ -611,7 +612,8 @@ int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double
     npart = col_blocks(d.logL1, d.tcols);
   }
   if (gm_check)
-    HIP_TRY(launch_gm_check(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s));
+    HIP_TRY(launch_gm_check(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s,
+                            stall ? 1 : 0));
   else
     HIP_TRY(launch_finish(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s));
   return AMG_OK;
@@ -1030,6 +1032,7 @@ int solve_begin(amg_t h, const double* b, double* x, double tol, hipStream_t s) 
   AMG_TRY(outer_residual(h, b, x, nullptr, tol, s));
   HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
   h->gm_j = 0;
+  h->cg_restart = false;
   return AMG_OK;
 }
 
@@ -1069,7 +1072,8 @@ int pcg_step(amg_t h, double* x, double tol, hipStream_t s) {
   double* r = h->mixed ? h->rout : L0.bd;
   HIP_TRY(launch_cg_update(h->st_dev, x, h->cg_p, r, h->cg_rold, h->cg_q, h->mixed ? L0.bf : nullptr,
                            m, h->npart, s));
-  HIP_TRY(launch_finish(h->st_dev, h->npart, vec_blocks(m), tol, h->opts.max_iter, h->hist_dev, s));
+  HIP_TRY(launch_finish(h->st_dev, h->npart, vec_blocks(m), tol, h->opts.max_iter, h->hist_dev, s,
+                        1));
   h->prof.span(PK_OUTER, v0, h->prof.mark(s));
   return AMG_OK;
 }
@@ -1132,8 +1136,18 @@ int gmres_round(amg_t h, const double* b, double* x, double tol, hipStream_t s) 
 // solve_begin (whose residual and stop test come first).
 int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s, int round) {
   if (h->opts.inner == AMG_INNER_PCG) {
-    AMG_TRY(pcg_precondition(h, round == 0, s));
-    AMG_TRY(pcg_step(h, x, tol, s));
+    if (h->st_host->cycle_end) {
+      // the recurrence's residual passed the test: b - A x decides; if it has
+      // not passed, CG restarts from it
+      const size_t v0 = h->prof.mark(s);
+      AMG_TRY(outer_residual(h, b, x, nullptr, tol, s, true, true));
+      h->prof.span(PK_OUTER, v0, h->prof.mark(s));
+      h->cg_restart = true;
+    } else {
+      AMG_TRY(pcg_precondition(h, round == 0 || h->cg_restart, s));
+      AMG_TRY(pcg_step(h, x, tol, s));
+      h->cg_restart = false;
+    }
   } else if (h->opts.inner == AMG_INNER_GMRES) {
     AMG_TRY(gmres_round(h, b, x, tol, s));
   } else {

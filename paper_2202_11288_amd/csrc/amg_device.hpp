@@ -121,6 +121,7 @@ struct SolveState {
   double rz;     // <r, z> of the current direction
   double alpha;  // step length
   double beta;   // direction update
+  double vtrue;  // last true residual formed to confirm a recurrence's (0: none yet)
 };
 
 // Stages of the conjugate-gradient scalar kernel.
@@ -169,8 +170,11 @@ hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, c
 hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1,
                           const cplx<double>* z2, int sym, double* g1, double* g2, float* g1f,
                           float* g2f, hipStream_t s);
+// Stop test on sqrt(sum part) / r0.  verify != 0 (a recurrence's residual):
+// passing the test sets cycle_end instead of done, and the true residual's
+// check (launch_gm_check) decides.
 hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
-                         double* hist, hipStream_t s);
+                         double* hist, hipStream_t s, int verify = 0);
 hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s);
 // part[2b] = a.z, part[2b+1] = c.z over chunk b (c may be null); z FP64 or FP32
 template <typename TZ>
@@ -213,9 +217,11 @@ hipError_t launch_gm_scale(const SolveState* st, double* w, const double* hn, in
 // y = R^{-1} g (R = leading k x k block of the rotated H), x += Z y
 hipError_t launch_gm_update(const SolveState* st, const double* H, const double* g, int k,
                             double* y, double* x, const double* Z, int64_t m, hipStream_t s);
-// true residual norm (npart) -> relres, stop test, next cycle
+// true residual norm (npart) -> relres, stop test, next cycle.  stall != 0:
+// a true residual that is not below 0.9 times the previous one ends the solve
+// (AMG_NOT_CONVERGED): the residual has reached what FP64 can resolve.
 hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double tol, int max_iter,
-                           double* hist, hipStream_t s);
+                           double* hist, hipStream_t s, int stall = 0);
 hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s);
 
 // bc = B x for the level's band (2n+1 entries)

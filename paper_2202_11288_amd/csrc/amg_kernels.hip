@@ -549,7 +549,8 @@ __global__ void k_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 
 // Stopping test of the outer iteration (Sec. 5): ||r_i|| / ||r_0|| < tol.
 __global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* part, int npart,
-                                                double tol, int max_iter, double* hist) {
+                                                double tol, int max_iter, double* hist,
+                                                int verify) {
   __shared__ double red[256 / 64];
   double v = 0.0;
   for (int i = threadIdx.x; i < npart; i += 256) v += part[i];
@@ -568,8 +569,12 @@ __global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* pa
     st->status = 2;
     st->done = 1;
   } else if (rel < tol) {
-    st->status = 0;
-    st->done = 1;
+    if (verify) {  // a recurrence's residual: b - A x decides (k_gm_check)
+      st->cycle_end = 1;
+    } else {
+      st->status = 0;
+      st->done = 1;
+    }
   } else if (rel > 1e3 * st->best) {
     st->status = 2;
     st->done = 1;
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* pa
     st->done = 1;
   }
   if (rel < st->best) st->best = rel;
-  if (!st->done) st->iter += 1;
+  if (!st->done && !st->cycle_end) st->iter += 1;
 }
 
 __global__ void k_copy_d2f(const double* a, float* b, int64_t m) {
@@ -828,7 +833,8 @@ __global__ __launch_bounds__(kVecNT) void k_gm_xupdate(const SolveState* st, dou
 }
 
 __global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const double* npart, int nb,
-                                                     double tol, int max_iter, double* hist) {
+                                                     double tol, int max_iter, double* hist,
+                                                     int stall) {
   __shared__ double red[kVecNT / 64];
   double v = 0.0;
   for (int b = threadIdx.x; b < nb; b += kVecNT) v += npart[b];
@@ -844,12 +850,13 @@ __global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const doubl
   } else if (rel < tol) {
     st->status = 0;
     st->done = 1;
-  } else if (st->iter >= max_iter) {
+  } else if (st->iter >= max_iter || (stall && st->vtrue > 0.0 && rel >= 0.9 * st->vtrue)) {
     st->status = 1;
     st->done = 1;
   } else {
     st->iter += 1;
   }
+  st->vtrue = rel;
 }
 
 __global__ void k_copy_f2d(const float* a, double* b, int64_t m) {
@@ -954,8 +961,8 @@ hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 }
 
 hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
-                         double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, 1, 256, 0, s, st, part, npart, tol, max_iter, hist);
+                         double* hist, hipStream_t s, int verify) {
+  hipLaunchKernelGGL(k_finish, 1, 256, 0, s, st, part, npart, tol, max_iter, hist, verify);
   return hipGetLastError();
 }
 
@@ -1044,8 +1051,8 @@ hipError_t launch_gm_update(const SolveState* st, const double* H, const double*
 }
 
 hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double tol, int max_iter,
-                           double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_check, 1, kVecNT, 0, s, st, npart, nb, tol, max_iter, hist);
+                           double* hist, hipStream_t s, int stall) {
+  hipLaunchKernelGGL(k_gm_check, 1, kVecNT, 0, s, st, npart, nb, tol, max_iter, hist, stall);
   return hipGetLastError();
 }
 

@@ -489,3 +489,48 @@ def test_pcg_batch_matches_solo():
     finally:
         for h in hs:
             B.amg_destroy(h)
+
+
+def test_fractional_2_22_mixed_pcg():
+    """The precision configuration at its full size: N = 2^22 intervals
+    (8,388,607 unknowns), delta = 0.1, fractional kernel alpha = 0.4, FP32
+    V-cycle with FP64 residual.  The finest FP64 matvec against the oracle's
+    FFT matvec (every output), and a V-cycle-preconditioned CG solve at tol
+    1e-10 whose final residual the oracle evaluates.  The CG recurrence passes
+    1e-10 after about 490 steps; the true residual b - A x, which decides,
+    stops near 2e-9 (about eps |A| |x| / |b| for this operator at this size),
+    so the solve ends as AMG_NOT_CONVERGED once restarts stop improving it."""
+    N = 2 ** 22
+    kern, okern, delta = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4), D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), 0.1
+    say("fractional 2^22")
+    H = tpx.Hierarchy.build(tpx.from_stencil(okern, N), 5)
+    # about 490 CG steps at this size (74 at 2^14, 294 at 2^20): the V-cycle's
+    # contraction for this kernel degrades with N
+    h = B.amg_setup(kern, delta, N, B.amg_default_opts(precision=B.AMG_MIXED,
+                                                      inner=B.AMG_INNER_PCG, max_iter=800))
+    try:
+        x = synthetic.random_vector(2 * N - 1, seed=22)
+        y = torch.empty(2 * N - 1, device="cuda", dtype=torch.float64)
+        B.amg_matvec(h, dev(x), y)
+        yr = H.matvec(x)
+        err = np.abs(host(y) - yr).max() / np.abs(yr).max()
+        say("matvec err", err)
+        assert err < 1e-13
+        b = B.amg_manufactured_rhs(kern, delta, N)
+        xs = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
+        st, it, rel = B.amg_solve(h, dev(b), xs, 1e-10, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+        xh = host(xs)
+        nb = np.linalg.norm(b)
+        yo = H.matvec(xh)
+        relo = np.linalg.norm(b - yo) / nb
+        # both evaluations of b - A x sit at their FP64 floor here: they differ
+        # by what the two FFT matvecs of this x differ by (|A| |x| >> |b|)
+        yg = torch.empty_like(xs)
+        B.amg_matvec(h, xs, yg)
+        d = np.linalg.norm(host(yg) - yo) / nb
+        say("pcg status", st, "iters", it, "rel", rel, "oracle rel", relo, "matvec gap", d)
+        assert rel < 1e-8
+        assert abs(rel - relo) <= 1.01 * d + 1e-12
+        assert 450 < it < 800
+    finally:
+        B.amg_destroy(h)
