@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=512,
                     help="instances of the uneven batch (seeded N, delta, kernel, random b) "
                          "solved together by amg_solve_batch beside the headline; 0 = skip")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the size/horizon/kernel sweep (N = 2^14, 2^17, 2^20; delta = 0.05, "
+                         "0.25; constant and weighted kernels) beside the headline")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the precision configuration (N = 2^22, fractional alpha = 0.4, "
                          "delta = 0.1, FP32 V-cycle + FP64 residual, CG) beside the headline")
@@ -342,6 +345,56 @@ def run_batch(B, torch, args):
                         f"tol={args.tol}"}
 
 
+def run_c2(B, torch, args):
+    """The plain-method configurations: N = 2^14, 2^17, 2^20 intervals, delta in
+    {0.05, 0.25}, the SPD constant kernel and the weighted 1.2/0.8 one,
+    manufactured right-hand side, V-cycle to 2^5, tol as the headline, one
+    solve at a time: FP64 and mixed solves/s (median of 5) and iterations; at
+    2^14 and 2^17 the oracle times its own FP64 solve and evaluates the GPU
+    solutions' residuals."""
+    rows = []
+    for logN in (14, 17, 20):
+        N = 2 ** logN
+        for delta in (0.05, 0.25):
+            for kname in ("const", "weighted"):
+                k = B.kernel(B.AMG_K_CONST) if kname == "const" else B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8)
+                b = B.amg_manufactured_rhs(k, delta, N)
+                bd = torch.from_numpy(b).cuda()
+                row = {"N": N, "delta": delta, "kernel": kname}
+                xs = {}
+                for name, prec in (("fp64", B.AMG_FP64), ("mixed", B.AMG_MIXED)):
+                    h = B.amg_setup(k, delta, N, B.amg_default_opts(precision=prec, max_iter=500))
+                    try:
+                        x = torch.zeros_like(bd)
+                        B.amg_solve(h, bd, x, args.tol)
+                        ts = []
+                        for _ in range(5):
+                            x.zero_()
+                            torch.cuda.synchronize()
+                            t0 = time.perf_counter()
+                            st, it, rel = B.amg_solve(h, bd, x, args.tol)
+                            ts.append(time.perf_counter() - t0)
+                    finally:
+                        B.amg_destroy(h)
+                    xs[name] = x.cpu().numpy()
+                    row[name] = {"solves_per_s": round(1.0 / float(np.median(ts)), 2), "iters": it,
+                                 "relres": rel}
+                if logN <= 17 and not args.no_cpu_baseline:
+                    from oracle import discretize as D
+                    from oracle import tpx
+                    ok = (D.Kernel(D.CONST, delta) if kname == "const"
+                          else D.Kernel(D.WEIGHTED, delta, wl=1.2, wr=0.8))
+                    H = tpx.Hierarchy.build(tpx.from_stencil(ok, N), 5)
+                    t0 = time.perf_counter()
+                    _, ito, _ = tpx.solve(H, b, tol=args.tol, max_iter=500)
+                    row["oracle"] = {"solves_per_s": round(1.0 / (time.perf_counter() - t0), 3),
+                                     "iters": ito, "cores": tpx.WORKERS,
+                                     "relres_of_gpu": {nm: float(np.linalg.norm(b - H.matvec(v)) / np.linalg.norm(b))
+                                                       for nm, v in xs.items()}}
+                rows.append(row)
+    return rows
+
+
 def run_c3(B, torch, args):
     """N = 2^22 intervals (8,388,607 unknowns), delta = 0.1, fractional kernel
     alpha = 0.4, manufactured right-hand side, tol 1e-10: the mixed form
@@ -456,6 +509,10 @@ def main():
         krylov = {"note": "V-cycle-preconditioned CG (inner = AMG_INNER_PCG): same V-cycle, "
                           "Krylov outer iteration; not the paper's stationary iteration",
                   "mixed": kmx, "fp64": k64}
+    c2 = None
+    if not args.no_c2:
+        c2 = run_c2(B, torch, args)
+        print(f"# c2 done: {c2}", file=sys.stderr, flush=True)
     c3 = None
     if not args.no_c3:
         c3 = run_c3(B, torch, args)
@@ -501,6 +558,7 @@ def main():
         "speedup_mixed_vs_fp64": round(smx["solves_per_s"] / s64["solves_per_s"], 3),
         "pcg": krylov,
         "batch": batch,
+        "plain_configs": c2,
         "precision_config": c3,
         "roofline": roof, "roofline_fp64_form": roof64, "roofline_fp32_sweep": roof32,
         "roofline_source": (f"HIP events around the finest-level FFT passes on the solve stream, "
