@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-c2", action="store_true",
                     help="skip the size/horizon/kernel sweep (N = 2^14, 2^17, 2^20; delta = 0.05, "
                          "0.25; constant and weighted kernels) beside the headline")
+    ap.add_argument("--no-ext", action="store_true",
+                    help="skip the extension forms (standard collocation with volume data, BDF4 "
+                         "steps, the weakly singular model, GMRES, W-cycles) beside the headline")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the precision configuration (N = 2^22, fractional alpha = 0.4, "
                          "delta = 0.1, FP32 V-cycle + FP64 residual, CG) beside the headline")
@@ -395,6 +398,123 @@ def run_c2(B, torch, args):
     return rows
 
 
+def timed_solves(B, torch, h, bd, tol, reps=5, x0=None):
+    """Median wall time of `reps` solves (after one untimed), iterations and
+    relres of the last."""
+    x = torch.zeros_like(bd) if x0 is None else x0.clone()
+    B.amg_solve(h, bd, x, tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+    ts = []
+    for _ in range(reps):
+        if x0 is None:
+            x.zero_()
+        else:
+            x.copy_(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, rel = B.amg_solve(h, bd, x, tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+        ts.append(time.perf_counter() - t0)
+    return {"ms_per_solve": round(1e3 * float(np.median(ts)), 3), "iters": it, "relres": rel,
+            "converged": st == B.AMG_OK}
+
+
+def run_extensions(B, torch, args):
+    """The forms beyond the paper's stationary V-cycle on the bench size
+    N = 2^20 (FP64 and mixed each): the standard (non-symmetric) collocation
+    with non-zero volume data; one BDF4 step (shift 25/12, scale tau = h) of
+    u = e^t x^2 (1-x)^2 from U^{k-1}; the weakly singular model (gamma = 0.5)
+    in its BDF4 step system with a seeded random right-hand side; GMRES for
+    the weighted kernel; and the stationary W-cycle iteration for the
+    fractional kernel (alpha = 0.4, delta = 0.1) at N = 2^14 beside the
+    V-cycle's."""
+    N = 2 ** 20
+    tol = args.tol
+    out = {}
+    rng = np.random.default_rng(7)
+    forms = (("fp64", B.AMG_FP64), ("mixed", B.AMG_MIXED))
+    # standard collocation, volume data g = (1+x)^6 on the interaction volume
+    k = B.kernel(B.AMG_K_CONST, scheme=B.AMG_SCHEME_STANDARD)
+    S = B.amg_volume_reach(k, 0.25, N)
+    kk = np.arange(S + 1) / (2.0 * N)
+    b = B.amg_manufactured_rhs(k, 0.25, N)
+    b = B.amg_volume_rhs(k, 0.25, N, (1.0 - kk) ** 6, (2.0 + kk) ** 6, b)
+    bd = torch.from_numpy(b).cuda()
+    out["standard_volume_data"] = {}
+    for name, prec in forms:
+        h = B.amg_setup(k, 0.25, N, B.amg_default_opts(precision=prec))
+        try:
+            out["standard_volume_data"][name] = timed_solves(B, torch, h, bd, tol)
+        finally:
+            B.amg_destroy(h)
+    # one BDF4 step of u = e^t x^2 (1-x)^2 (zero volume data), t_k = 4h
+    kc = B.kernel(B.AMG_K_CONST)
+    tau = 1.0 / N
+    f = B.amg_manufactured_rhs(kc, 0.25, N)
+    xs = np.concatenate([np.arange(1, N) / N, (np.arange(N) + 0.5) / N])
+    u = xs * xs * (1 - xs) ** 2
+    hist = [torch.from_numpy(np.exp(j * tau) * u).cuda() for j in (3, 2, 1, 0)]
+    t4 = 4 * tau
+    src = torch.from_numpy(tau * np.exp(t4) * (u + 2.0 * f)).cuda()  # kernel constant 3 delta^-3
+    out["bdf4_step"] = {}
+    for name, prec in forms:
+        h = B.amg_setup(kc, 0.25, N, B.amg_default_opts(precision=prec, shift=25.0 / 12.0,
+                                                       scale=2.0 * tau))
+        try:
+            # the step's initial residual b - M U^{k-1} is O(tau) of b: 1e-8 of it
+            # is ~1e-14 of b (1e-10 would sit below what FP64 resolves at 2^20)
+            tol_step = 1e-8
+            ok = (B.AMG_OK, B.AMG_NOT_CONVERGED)
+            xo = torch.empty_like(hist[0])
+            B.amg_bdf4_step(h, hist, src, xo, tol_step, allow=ok)
+            ts = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it, rel = B.amg_bdf4_step(h, hist, src, xo, tol_step, allow=ok)
+                ts.append(time.perf_counter() - t0)
+            err = float((xo.cpu().numpy() - np.exp(t4) * u).__abs__().max())
+            out["bdf4_step"][name] = {"ms_per_step": round(1e3 * float(np.median(ts)), 3),
+                                      "iters": it, "relres": rel, "tol": tol_step,
+                                      "converged": st == B.AMG_OK, "max_err_vs_u": err}
+        finally:
+            B.amg_destroy(h)
+    # the weakly singular model's BDF4 step system, random right-hand side
+    kw = B.kernel(B.AMG_K_WEAKLY_SINGULAR, gamma=0.5)
+    bw = torch.from_numpy(rng.standard_normal(2 * N - 1)).cuda()
+    out["weakly_singular_step"] = {}
+    for name, prec in forms:
+        t0 = time.perf_counter()
+        h = B.amg_setup(kw, 0.0, N, B.amg_default_opts(precision=prec, shift=25.0 / 12.0, scale=tau))
+        setup = time.perf_counter() - t0
+        try:
+            r = timed_solves(B, torch, h, bw, tol)
+            r["setup_s"] = round(setup, 2)
+            out["weakly_singular_step"][name] = r
+        finally:
+            B.amg_destroy(h)
+    # GMRES for the weighted kernel (manufactured right-hand side)
+    kwt = B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8)
+    bg = torch.from_numpy(B.amg_manufactured_rhs(kwt, 0.25, N)).cuda()
+    out["gmres_weighted"] = {}
+    for name, prec in forms:
+        h = B.amg_setup(kwt, 0.25, N, B.amg_default_opts(precision=prec, inner=B.AMG_INNER_GMRES))
+        try:
+            out["gmres_weighted"][name] = timed_solves(B, torch, h, bg, tol)
+        finally:
+            B.amg_destroy(h)
+    # W-cycle vs V-cycle, fractional kernel, N = 2^14 (FP64)
+    kf = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4)
+    Nf = 2 ** 14
+    bf = torch.from_numpy(B.amg_manufactured_rhs(kf, 0.1, Nf)).cuda()
+    out["wcycle_fractional_2e14"] = {}
+    for name, cyc in (("W", 2), ("V", 1)):
+        h = B.amg_setup(kf, 0.1, Nf, B.amg_default_opts(cycle=cyc, max_iter=2000))
+        try:
+            out["wcycle_fractional_2e14"][name] = timed_solves(B, torch, h, bf, tol, reps=2)
+        finally:
+            B.amg_destroy(h)
+    return out
+
+
 def run_c3(B, torch, args):
     """N = 2^22 intervals (8,388,607 unknowns), delta = 0.1, fractional kernel
     alpha = 0.4, manufactured right-hand side, tol 1e-10: the mixed form
@@ -513,6 +633,10 @@ def main():
     if not args.no_c2:
         c2 = run_c2(B, torch, args)
         print(f"# c2 done: {c2}", file=sys.stderr, flush=True)
+    ext = None
+    if not args.no_ext:
+        ext = run_extensions(B, torch, args)
+        print(f"# extensions done: {ext}", file=sys.stderr, flush=True)
     c3 = None
     if not args.no_c3:
         c3 = run_c3(B, torch, args)
@@ -559,6 +683,7 @@ def main():
         "pcg": krylov,
         "batch": batch,
         "plain_configs": c2,
+        "extensions": ext,
         "precision_config": c3,
         "roofline": roof, "roofline_fp64_form": roof64, "roofline_fp32_sweep": roof32,
         "roofline_source": (f"HIP events around the finest-level FFT passes on the solve stream, "
