@@ -128,6 +128,31 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+_PRECISION = {}  # handle address -> amg_precision of its setup (for amg_vcycle's dtype)
+
+
+def _vec(h, t, what: str, level: int = 0, f32: bool = False):
+    """A device vector argument: a raw address (int, passed as is) or a CUDA
+    tensor that must be contiguous, of the level's length 2n+1 and float64
+    (float32 where `f32`), so that the library never reads past it."""
+    if t is None or isinstance(t, int):
+        return _ptr(t)
+    import torch
+    m = lib.amg_level_size(h, int(level))
+    want = torch.float32 if f32 else torch.float64
+    if m < 0:
+        raise AmgError(int(m), what)
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == want and t.numel() == m):
+        raise ValueError(f"{what}: need a contiguous {want} CUDA tensor of {m} values, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}"
+                         f"{'' if t.is_contiguous() else ' (not contiguous)'}")
+    return _ptr(t)
+
+
+def _hkey(h):
+    return h.value if isinstance(h, ctypes.c_void_p) else h
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -166,32 +191,39 @@ def amg_setup(kern: amg_kernel_t, delta: float, N: int, opts: amg_opts_t | None 
                        ctypes.byref(opts) if opts is not None else None,
                        None if host_only else _stream(stream), ctypes.byref(h))
     _check(st, "amg_setup")
+    _PRECISION[h.value] = opts.precision if opts is not None else AMG_FP64
     return h
 
 
 def amg_destroy(h):
+    _PRECISION.pop(_hkey(h), None)
     return _check(lib.amg_destroy(h), "amg_destroy")
 
 
 def amg_matvec(h, x, y, stream=None):
-    return _check(lib.amg_matvec(h, _ptr(x), _ptr(y), _stream(stream)), "amg_matvec")
+    return _check(lib.amg_matvec(h, _vec(h, x, "amg_matvec x"), _vec(h, y, "amg_matvec y"),
+                                 _stream(stream)), "amg_matvec")
 
 
 def amg_level_matvec(h, level: int, x, y, stream=None):
-    return _check(lib.amg_level_matvec(h, int(level), _ptr(x), _ptr(y), _stream(stream)),
+    return _check(lib.amg_level_matvec(h, int(level), _vec(h, x, "amg_level_matvec x", level),
+                                       _vec(h, y, "amg_level_matvec y", level), _stream(stream)),
                   "amg_level_matvec")
 
 
 def amg_vcycle(h, r, e, stream=None):
-    return _check(lib.amg_vcycle(h, _ptr(r), _ptr(e), _stream(stream)), "amg_vcycle")
+    """r, e in the handle's V-cycle precision (float32 for AMG_MIXED)."""
+    f32 = _PRECISION.get(_hkey(h), AMG_FP64) == AMG_MIXED
+    return _check(lib.amg_vcycle(h, _vec(h, r, "amg_vcycle r", f32=f32),
+                                 _vec(h, e, "amg_vcycle e", f32=f32), _stream(stream)), "amg_vcycle")
 
 
 def amg_solve(h, b, x, tol: float, stream=None, allow=(AMG_OK,)):
     """Returns (status, iters, relres); raises unless status is in `allow`."""
     it = ctypes.c_int()
     rr = ctypes.c_double()
-    st = lib.amg_solve(h, _ptr(b), _ptr(x), float(tol), _stream(stream), ctypes.byref(it),
-                       ctypes.byref(rr))
+    st = lib.amg_solve(h, _vec(h, b, "amg_solve b"), _vec(h, x, "amg_solve x"), float(tol),
+                       _stream(stream), ctypes.byref(it), ctypes.byref(rr))
     _check(st, "amg_solve", ok=allow)
     return st, it.value, rr.value
 
@@ -203,8 +235,9 @@ def amg_bdf4_step(h, hist, src, x, tol: float, stream=None, allow=(AMG_OK,)):
         raise ValueError("BDF4 needs four previous time levels")
     it = ctypes.c_int()
     rr = ctypes.c_double()
-    st = lib.amg_bdf4_step(h, *[_ptr(u) for u in hist], _ptr(src), _ptr(x), float(tol),
-                           _stream(stream), ctypes.byref(it), ctypes.byref(rr))
+    st = lib.amg_bdf4_step(h, *[_vec(h, u, "amg_bdf4_step history") for u in hist],
+                           _vec(h, src, "amg_bdf4_step src"), _vec(h, x, "amg_bdf4_step x"),
+                           float(tol), _stream(stream), ctypes.byref(it), ctypes.byref(rr))
     _check(st, "amg_bdf4_step", ok=allow)
     return st, it.value, rr.value
 
@@ -213,8 +246,13 @@ def amg_solve_batch(hs, bs, xs, tols, stream=None, allow=(AMG_OK,)):
     """Solve independent instances; returns (status, iters list, relres list)."""
     k = len(hs)
     H = (ctypes.c_void_p * k)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in hs])
-    Bp = (ctypes.c_void_p * k)(*[_ptr(b).value for b in bs])
-    Xp = (ctypes.c_void_p * k)(*[_ptr(x).value for x in xs])
+    if not (len(bs) == k and len(xs) == k and len(tols) == k):
+        raise ValueError("amg_solve_batch: one b, x and tol per handle")
+    def addr(h, t, what):
+        v = _vec(h, t, what)
+        return None if v is None else v.value
+    Bp = (ctypes.c_void_p * k)(*[addr(h, b, "amg_solve_batch b") for h, b in zip(hs, bs)])
+    Xp = (ctypes.c_void_p * k)(*[addr(h, x, "amg_solve_batch x") for h, x in zip(hs, xs)])
     T = (ctypes.c_double * k)(*[float(t) for t in tols])
     it = (ctypes.c_int * k)()
     rr = (ctypes.c_double * k)()

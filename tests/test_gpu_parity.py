@@ -534,3 +534,33 @@ def test_fractional_2_22_mixed_pcg():
         assert 450 < it < 800
     finally:
         B.amg_destroy(h)
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding refuses tensors the library would read past or misread
+    (wrong dtype, length, layout or device) before any device work; the V-cycle
+    of a mixed handle takes float32."""
+    say("binding tensor checks")
+    N = 256
+    h = B.amg_setup(CONST25[1], CONST25[3], N)
+    hm = B.amg_setup(CONST25[1], CONST25[3], N, B.amg_default_opts(precision=B.AMG_MIXED))
+    try:
+        m = 2 * N - 1
+        good = torch.zeros(m, device="cuda", dtype=torch.float64)
+        bad = [torch.zeros(m, device="cuda", dtype=torch.float32),
+               torch.zeros(m - 1, device="cuda", dtype=torch.float64),
+               torch.zeros(2 * m, device="cuda", dtype=torch.float64)[::2],
+               torch.zeros(m, dtype=torch.float64)]
+        for t in bad:
+            with pytest.raises(ValueError):
+                B.amg_solve(h, t, good.clone(), 1e-10)
+            with pytest.raises(ValueError):
+                B.amg_matvec(h, good, t)
+        with pytest.raises(ValueError):
+            B.amg_vcycle(hm, good, good.clone())
+        r32 = torch.zeros(m, device="cuda", dtype=torch.float32)
+        B.amg_vcycle(hm, r32, torch.empty_like(r32))
+        torch.cuda.synchronize()
+    finally:
+        B.amg_destroy(h)
+        B.amg_destroy(hm)
