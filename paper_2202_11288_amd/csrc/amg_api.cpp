@@ -193,6 +193,7 @@ struct amg_ctx {
   std::vector<LevelRes> lv;
   int first_tail = 0;
   int maxL_tail = 0;
+  int tail_variant = 0;  // TAIL_BAND / TAIL_SYM of the tail levels (all alike)
   CoarseLU lu{};
   Twiddles<double> tw64{};
   Twiddles<float> tw32{};
@@ -447,7 +448,7 @@ int vcycle_dev(amg_ctx* c, hipStream_t s) {
     const T* rf = (ft > 0) ? c->lv[ft - 1].template dev<T>().r : nullptr;
     const size_t t0 = c->prof.mark(s);
     HIP_TRY(launch_tail_vcycle<T>(lvdev_of<T>(c), ft, nl - 1, rf, o.m1, o.m2, wpre, wpost, c->lu,
-                                  tw_of<T>(c), c->maxL_tail, s));
+                                  tw_of<T>(c), c->maxL_tail, c->tail_variant, s));
     c->prof.span(PK_TAIL, t0, c->prof.mark(s));
   }
   for (int l = ft - 1; l >= 0; --l) {
@@ -506,7 +507,7 @@ int wcycle_visit(amg_ctx* c, int l, bool first, hipStream_t s) {
     const int k = first ? 0 : 1;
     HIP_TRY(launch_tail_program<T>(lvdev_of<T>(c), ft, nl - 1, rf, c->tail_prog[k],
                                    c->tail_prog_n[k], wpre, wpost, c->lu, tw_of<T>(c),
-                                   c->maxL_tail, s));
+                                   c->maxL_tail, c->tail_variant, s));
     return AMG_OK;
   }
   const LevelDev<T> d = c->lv[l].template dev<T>();
@@ -778,6 +779,13 @@ int setup_device(amg_ctx* c, hipStream_t s) {
     double* ai;
     AMG_TRY(upload(c, &ai, inv, s));
     c->lu = {m, ai};
+  }
+  {
+    const int ft = c->first_tail;
+    const bool band = c->host[ft].has_band(), sym = c->lv[ft].sym;
+    for (int l = ft; l < nl; ++l)
+      if (c->host[l].has_band() != band || c->lv[l].sym != sym) return AMG_EINVAL;
+    c->tail_variant = (band ? TAIL_BAND : 0) | (sym ? TAIL_SYM : 0);
   }
   AMG_TRY(dalloc(c, &c->dpart64, (size_t)maxblocks));
   AMG_TRY(dalloc(c, &c->dpart32, (size_t)maxblocks));

@@ -21,6 +21,7 @@ constexpr int kNT4 = 256;          // threads of a four-step pass workgroup
 constexpr int kCap4 = 4096;        // complex values per four-step workgroup (tile or row pair)
 constexpr int kNTT = 512;          // threads of the single-workgroup tail kernels
 constexpr int kTailLog = 12;       // levels with L <= 2^12 run in the tail kernels
+constexpr int kTailMaxLev = 16;    // levels one tail kernel call may span (first..last)
 
 template <typename T>
 struct Twiddles {
@@ -157,14 +158,17 @@ template <typename T>
 hipError_t launch_tail_matvec(int colmode, int epimode, const LevelDev<T>& lv, const ColIn<T>& in,
                               const EpiOut<T>& out, const Twiddles<T>& tw, double* part,
                               hipStream_t s);
+// variant: TAIL_BAND if the levels carry a band, TAIL_SYM if their spectra
+// are of the symmetric form (every tail level alike).
+enum TailVariant { TAIL_BAND = 1, TAIL_SYM = 2 };
 template <typename T>
 hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
                               int m1, int m2, T wpre, T wpost, const CoarseLU& lu,
-                              const Twiddles<T>& tw, int maxL, hipStream_t s);
+                              const Twiddles<T>& tw, int maxL, int variant, hipStream_t s);
 template <typename T>
 hipError_t launch_tail_program(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
                                const TailOp* ops, int nops, T wpre, T wpost, const CoarseLU& lu,
-                               const Twiddles<T>& tw, int maxL, hipStream_t s);
+                               const Twiddles<T>& tw, int maxL, int variant, hipStream_t s);
 hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, const double* gy,
                                  cplx<double>* out, const Twiddles<double>& tw, hipStream_t s);
 hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1,

@@ -46,6 +46,70 @@ constexpr size_t tail_lds_bytes(size_t elem) {
   return 2 * elem * ((size_t)lds_slots(1 << kTailLog) + (1 << kTailLog)) + elem * (kNTT / 64 + 2);
 }
 
+// The level descriptors a tail call visits, copied to LDS once at kernel start
+// (one round trip instead of a dependent scalar load at every step), and read
+// back as wave-uniform values so that their pointers stay scalar.
+template <typename T>
+__device__ __forceinline__ void tail_levels_to_lds(const LevelDev<T>* levels, int first, int last,
+                                                   LevelDev<T>* lvs) {
+  static_assert(sizeof(LevelDev<T>) % 4 == 0, "descriptor copied as 32-bit words");
+  constexpr int W = sizeof(LevelDev<T>) / 4;
+  const int total = (last - first + 1) * W;
+  const unsigned* src = reinterpret_cast<const unsigned*>(levels + first);
+  unsigned* dst = reinterpret_cast<unsigned*>(lvs);
+  for (int i = threadIdx.x; i < total; i += kNTT) dst[i] = src[i];
+}
+// (Pointers are rebuilt through the global address space so that accesses
+// through them compile to global, not flat, memory instructions.)
+template <typename T>
+__device__ __forceinline__ T* ptr_uniform(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  using G = __attribute__((address_space(1))) T;
+  return (T*)(G*)(((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T val_uniform(T x) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+  } else {
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+template <typename T>
+__device__ __forceinline__ LevelDev<T> lv_uniform(const LevelDev<T>& x) {
+  LevelDev<T> o;
+  o.n = __builtin_amdgcn_readfirstlane(x.n);
+  o.logL = __builtin_amdgcn_readfirstlane(x.logL);
+  o.logL1 = __builtin_amdgcn_readfirstlane(x.logL1);
+  o.logL2 = __builtin_amdgcn_readfirstlane(x.logL2);
+  o.tcols = __builtin_amdgcn_readfirstlane(x.tcols);
+  o.sym = __builtin_amdgcn_readfirstlane(x.sym);
+  o.g1 = ptr_uniform(x.g1);
+  o.g2 = ptr_uniform(x.g2);
+  o.p = ptr_uniform(x.p);
+  o.q = ptr_uniform(x.q);
+  o.xi = ptr_uniform(x.xi);
+  o.zeta = ptr_uniform(x.zeta);
+  o.o = val_uniform(x.o);
+  o.dv = val_uniform(x.dv);
+  o.dw = val_uniform(x.dw);
+  o.b = ptr_uniform(x.b);
+  o.u = ptr_uniform(x.u);
+  o.r = ptr_uniform(x.r);
+  o.scal = ptr_uniform(x.scal);
+  o.bsub = ptr_uniform(x.bsub);
+  o.bmain = ptr_uniform(x.bmain);
+  o.bsup = ptr_uniform(x.bsup);
+  o.dinv = ptr_uniform(x.dinv);
+  o.bc = ptr_uniform(x.bc);
+  return o;
+}
+
 constexpr int kTailP = (1 << (kTailLog - 1)) / kNTT + 1;  // spectral pairs per thread (f <= L/2)
 
 // Spectra of the pairs (f, L-f), f = threadIdx.x + k*kNTT, loaded into
@@ -55,27 +119,32 @@ struct TailSpec {
   cplx<T> a1[kTailP], a2[kTailP], b1[kTailP], b2[kTailP];  // G1[f], G2[f], G1[-f], G2[-f]
 };
 
-template <typename T>
+// Waves whose pairs all lie past L/2 skip the loads (a wave-uniform branch:
+// on small levels most waves have nothing to load, and the cost of a load
+// instruction is paid per wave); within a loading wave the pairs past L/2
+// read bin 0 and are not used.
+template <typename T, bool SYM>
 __device__ __forceinline__ void tail_spec_load(const LevelDev<T>& lv, TailSpec<T>& sp) {
   const int L = 1 << lv.logL;
+  const int wave0 = threadIdx.x & ~63;
 #pragma unroll
   for (int k = 0; k < kTailP; ++k) {
-    const int f = threadIdx.x + k * kNTT;
-    if (f <= L / 2) {
-      const int fb = (L - f) & (L - 1);
-      if (lv.sym) {
-        sp.a1[k] = {lv.g1[f], T(0)};
-        sp.a2[k] = {T(0), lv.g2[f]};
-        sp.b1[k] = {lv.g1[fb], T(0)};
-        sp.b2[k] = {T(0), lv.g2[fb]};
-      } else {
-        const cplx<T>* G1 = reinterpret_cast<const cplx<T>*>(lv.g1);
-        const cplx<T>* G2 = reinterpret_cast<const cplx<T>*>(lv.g2);
-        sp.a1[k] = G1[f];
-        sp.a2[k] = G2[f];
-        sp.b1[k] = G1[fb];
-        sp.b2[k] = G2[fb];
-      }
+    if (wave0 + k * kNTT > L / 2) continue;
+    const int f0 = threadIdx.x + k * kNTT;
+    const int f = f0 <= L / 2 ? f0 : 0;
+    const int fb = (L - f) & (L - 1);
+    if constexpr (SYM) {
+      sp.a1[k] = {lv.g1[f], T(0)};
+      sp.a2[k] = {T(0), lv.g2[f]};
+      sp.b1[k] = {lv.g1[fb], T(0)};
+      sp.b2[k] = {T(0), lv.g2[fb]};
+    } else {
+      const cplx<T>* G1 = reinterpret_cast<const cplx<T>*>(lv.g1);
+      const cplx<T>* G2 = reinterpret_cast<const cplx<T>*>(lv.g2);
+      sp.a1[k] = G1[f];
+      sp.a2[k] = G2[f];
+      sp.b1[k] = G1[fb];
+      sp.b2[k] = G2[fb];
     }
   }
 }
@@ -107,102 +176,100 @@ constexpr int kTailJ = (1 << (kTailLog - 1)) / kNTT;  // v/w slots per thread (n
 
 // One matvec step of a tail level: form u (prologue), y = A u, then the
 // residual or Jacobi epilogue; b and u stay in registers between the two.
-// The prologue issues every global load of the step (spectra, Cross vectors,
-// b / u / the neighbouring level's vector, and thread 0's w_o operands) as
-// one batch with clamped addresses before any of them is used.
-template <typename T, bool BAND>
+// The prologue issues the global loads of the step (spectra, Cross vectors,
+// the prologue's operands, the w_o entry's) as one batch.  A load
+// instruction costs the same per wave however few of its lanes are in range,
+// so only waves holding elements j < n load (wave-uniform branches), and only
+// the operands the prologue kind needs.
+template <typename T, bool BAND, bool SYM>
 __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int epi, const T* src,
                                           T wpro, T wepi, const TailLds<T>& s) {
   constexpr int J = kTailJ;
   const int n = lv.n, L = 1 << lv.logL;
+  const bool restr = pro == TP_PRE_RESTRICT, prol = pro == TP_PROLONG;
   TailSpec<T> sp;
-  tail_spec_load(lv, sp);
+  tail_spec_load<T, SYM>(lv, sp);
+  const T* pa = restr ? src : lv.b;            // slots 0, 1
+  const T* pb = restr ? src : lv.u;            // slots 2, 3
+  const T* pc = (restr || prol) ? src : lv.b;  // slots 4..7
   int jj[J];
-  bool ok[J];
-  T pj[J], xj[J], qq[J], zz[J], r0[J], r1[J], r2[J], r3[J], r4[J], r5[J];
+  bool ok[J], ml0[J], mh0[J], ml1[J], mh1[J];
+  T pj[J], xj[J], qq[J], zz[J], r0[J], r1[J], r2[J], r3[J], r4[J], r5[J], r6[J], r7[J];
+  T dv0[J], dv1[J];
+  const int wave0 = threadIdx.x & ~63;
+  const bool six = restr || prol;  // operands 4 and 5
 #pragma unroll
   for (int k = 0; k < J; ++k) {
     const int j = threadIdx.x + k * kNTT;
     ok[k] = j < n;
-    jj[k] = ok[k] ? j : 0;
-    pj[k] = lv.p[jj[k]];
-    xj[k] = lv.xi[jj[k]];
-    qq[k] = lv.q[jj[k]];
-    zz[k] = lv.zeta[jj[k]];
-  }
-  if (pro == TP_PRE_RESTRICT) {
-#pragma unroll
-    for (int k = 0; k < J; ++k) {
-      const int js = jj[k], jw = n + 1 + js;
-      r0[k] = src[2 * js];
-      r1[k] = src[2 * js + 1];
-      r2[k] = src[2 * js + 2];
-      r3[k] = src[2 * jw];
-      r4[k] = src[2 * jw + 1];
-      r5[k] = src[2 * jw + 2];
+    const int js = ok[k] ? j : 0, jw = n + 1 + js;
+    jj[k] = js;
+    int lo0, hi0, lo1, hi1;
+    prolong_idx(js, n, lo0, hi0, ml0[k], mh0[k]);
+    prolong_idx(jw, n, lo1, hi1, ml1[k], mh1[k]);
+    pj[k] = xj[k] = qq[k] = zz[k] = T(0);
+    r0[k] = r1[k] = r2[k] = r3[k] = r4[k] = r5[k] = r6[k] = r7[k] = T(0);
+    dv0[k] = dv1[k] = T(0);
+    if (wave0 + k * kNTT >= n) continue;
+    pj[k] = lv.p[js];
+    xj[k] = lv.xi[js];
+    qq[k] = lv.q[js];
+    zz[k] = lv.zeta[js];
+    r0[k] = pa[restr ? 2 * js : js];
+    r1[k] = pa[restr ? 2 * js + 1 : jw];
+    r2[k] = pb[restr ? 2 * js + 2 : js];
+    r3[k] = pb[restr ? 2 * jw : jw];
+    if (six) {
+      r4[k] = pc[restr ? 2 * jw + 1 : lo0];
+      r5[k] = pc[restr ? 2 * jw + 2 : hi0];
     }
-  } else if (pro == TP_PROLONG) {
-#pragma unroll
-    for (int k = 0; k < J; ++k) {
-      const int js = jj[k], jw = n + 1 + js;
-      int lo, hi;
-      bool ml, mh;
-      r0[k] = lv.b[js];
-      r1[k] = lv.b[jw];
-      r2[k] = lv.u[js];
-      r3[k] = lv.u[jw];
-      prolong_idx(js, n, lo, hi, ml, mh);
-      const T a0 = src[lo], a1 = src[hi];
-      prolong_idx(jw, n, lo, hi, ml, mh);
-      const T c0 = src[lo], c1 = src[hi];
-      prolong_idx(js, n, lo, hi, ml, mh);
-      r4[k] = T(0.5) * ((ml ? a0 : T(0)) + (mh ? a1 : T(0)));
-      prolong_idx(jw, n, lo, hi, ml, mh);
-      r5[k] = T(0.5) * ((ml ? c0 : T(0)) + (mh ? c1 : T(0)));
+    if (prol) {
+      r6[k] = pc[lo1];
+      r7[k] = pc[hi1];
     }
-  } else {  // TP_PRE_B, TP_USE_U
-#pragma unroll
-    for (int k = 0; k < J; ++k) {
-      const int js = jj[k], jw = n + 1 + js;
-      r0[k] = lv.b[js];
-      r1[k] = lv.b[jw];
-      r2[k] = lv.u[js];
-      r3[k] = lv.u[jw];
+    if constexpr (BAND) {
+      dv0[k] = lv.dinv[js];
+      dv1[k] = lv.dinv[jw];
     }
   }
-  // thread 0: the w_o entry's operands, in the same batch
-  T wo_b = 0, wo_u = 0, wo_x = 0;
-  if (threadIdx.x == 0) {
-    if (pro == TP_PRE_RESTRICT) {
-      wo_b = T(0.25) * (src[2 * n] + T(2) * src[2 * n + 1] + src[2 * n + 2]);
-    } else {
-      wo_b = lv.b[n];
-      wo_u = lv.u[n];
-      if (pro == TP_PROLONG) wo_x = prolong_at(src, n, n);
-    }
+  // the w_o entry's operands (wave 0 loads them, one request each)
+  int wlo, whi;
+  bool wml, wmh;
+  prolong_idx(n, n, wlo, whi, wml, wmh);
+  T wo0 = T(0), wo1 = T(0), wo2 = T(0), wo3 = T(0), wdo = T(0);
+  if (wave0 == 0) {
+    wo0 = pa[restr ? 2 * n : n];
+    wo1 = pb[restr ? 2 * n + 1 : n];
+    wo2 = pc[restr ? 2 * n + 2 : (prol ? wlo : n)];
+    wo3 = pc[prol ? whi : n];
+    if constexpr (BAND) wdo = lv.dinv[n];
   }
+  const T wo_b = restr ? T(0.25) * (wo0 + T(2) * wo1 + wo2) : wo0;
+  const T wo_u = wo1;
+  const T wo_x = T(0.5) * ((wml ? wo2 : T(0)) + (wmh ? wo3 : T(0)));
   T bv[J], bw[J], uv[J], uw[J];
   T dot = 0;
+  const T wdv = wpro / lv.dv, wdw = wpro / lv.dw;
 #pragma unroll
   for (int k = 0; k < J; ++k) {
-    if (pro == TP_PRE_RESTRICT) {
+    if (restr) {
       bv[k] = T(0.25) * (r0[k] + T(2) * r1[k] + r2[k]);
       bw[k] = T(0.25) * (r3[k] + T(2) * r4[k] + r5[k]);
     } else {
       bv[k] = r0[k];
       bw[k] = r1[k];
     }
-    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) {
+    if (pro == TP_PRE_B || restr) {
       if constexpr (BAND) {
-        uv[k] = wpro * bv[k] * lv.dinv[jj[k]];
-        uw[k] = wpro * bw[k] * lv.dinv[n + 1 + jj[k]];
+        uv[k] = wpro * bv[k] * dv0[k];
+        uw[k] = wpro * bw[k] * dv1[k];
       } else {
-        uv[k] = wpro * bv[k] / lv.dv;
-        uw[k] = wpro * bw[k] / lv.dw;
+        uv[k] = wdv * bv[k];
+        uw[k] = wdw * bw[k];
       }
-    } else if (pro == TP_PROLONG) {
-      uv[k] = r2[k] + r4[k];
-      uw[k] = r3[k] + r5[k];
+    } else if (prol) {
+      uv[k] = r2[k] + T(0.5) * ((ml0[k] ? r4[k] : T(0)) + (mh0[k] ? r5[k] : T(0)));
+      uw[k] = r3[k] + T(0.5) * ((ml1[k] ? r6[k] : T(0)) + (mh1[k] ? r7[k] : T(0)));
     } else {
       uv[k] = r2[k];
       uw[k] = r3[k];
@@ -228,10 +295,10 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
   for (int j = n + threadIdx.x; j < L; j += kNTT) s.z[j] = {T(0), T(0)};
   if (threadIdx.x == 0) {  // the w_o entry
     const T bo = wo_b;
-    if (pro == TP_PRE_RESTRICT) lv.b[n] = bo;
+    if (restr) lv.b[n] = bo;
     T uo;
-    if (pro == TP_PRE_B || pro == TP_PRE_RESTRICT) uo = wpro * bo * (BAND ? lv.dinv[n] : T(1) / lv.o);
-    else if (pro == TP_PROLONG) uo = wo_u + wo_x;
+    if (pro == TP_PRE_B || restr) uo = wpro * bo * (BAND ? wdo : T(1) / lv.o);
+    else if (prol) uo = wo_u + wo_x;
     else uo = wo_u;
     if (pro != TP_USE_U) lv.u[n] = uo;
     s.red[kNTT / 64] = uo;
@@ -293,8 +360,8 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
           lv.r[j] = bv[k] - yv;
           lv.r[jw] = bw[k] - yw;
         } else {
-          lv.u[j] = uv[k] + wepi * (bv[k] - yv) / lv.dv;
-          lv.u[jw] = uw[k] + wepi * (bw[k] - yw) / lv.dw;
+          lv.u[j] = uv[k] + (wepi / lv.dv) * (bv[k] - yv);
+          lv.u[jw] = uw[k] + (wepi / lv.dw) * (bw[k] - yw);
         }
       }
     }
@@ -308,29 +375,60 @@ __device__ __forceinline__ void tail_step(const LevelDev<T>& lv, int pro, int ep
 }
 
 // Coarsest level: u = A_c^{-1} b with the inverse formed at setup from the
-// LU factors (partial pivoting).  b is staged in LDS as FP64; thread i < m
-// forms row i from the column-major inverse (loads coalesced across threads,
-// all independent).
+// LU factors (partial pivoting).  b is staged in LDS as FP64.  When m rows
+// leave threads idle, each row's dot product is split over P = kNTT / m
+// (rounded down to a power of two, at most 8) threads: thread (k, i) sums the
+// columns j = k mod P of row i, all its loads issued together (coalesced
+// across i), and the P partial sums are added in k order through LDS.
 template <typename T>
 __device__ void coarse_solve(const CoarseLU& lu, const T* b, T* u, double* bs) {
   const int m = lu.m;
   for (int i = threadIdx.x; i < m; i += kNTT) bs[i] = (double)b[i];
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += kNTT) {
-    double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += lu.ainv[j * m + i] * bs[j];
-    u[i] = (T)acc;
+  int P = 1;
+  while (P < 8 && 2 * P * m <= kNTT) P *= 2;
+  if (P == 1) {
+    for (int i = threadIdx.x; i < m; i += kNTT) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += lu.ainv[j * m + i] * bs[j];
+      u[i] = (T)acc;
+    }
+  } else {
+    double* part = bs + m;  // P * m partial sums
+    const int i = threadIdx.x % m, k = threadIdx.x / m;
+    if (k < P) {
+      double acc = 0.0;
+      int j = k;
+      for (; j + 3 * P < m; j += 4 * P) {
+        const double a0 = lu.ainv[j * m + i], a1 = lu.ainv[(j + P) * m + i];
+        const double a2 = lu.ainv[(j + 2 * P) * m + i], a3 = lu.ainv[(j + 3 * P) * m + i];
+        acc += a0 * bs[j];
+        acc += a1 * bs[j + P];
+        acc += a2 * bs[j + 2 * P];
+        acc += a3 * bs[j + 3 * P];
+      }
+      for (; j < m; j += P) acc += lu.ainv[j * m + i] * bs[j];
+      part[k * m + i] = acc;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < m; r += kNTT) {
+      double acc = part[r];
+      for (int q = 1; q < P; ++q) acc += part[q * m + r];
+      u[r] = (T)acc;
+    }
   }
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, bool BAND, bool SYM>
 __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels, int first,
                                                       int last, const T* rf, int m1, int m2,
                                                       T wpre, T wpost, CoarseLU lu,
                                                       Twiddles<T> tw) {
   extern __shared__ unsigned char smem_raw[];
-  const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);
+  __shared__ LevelDev<T> lvs[kTailMaxLev];
+  tail_levels_to_lds(levels, first, last, lvs);
+  const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);  // its barrier publishes lvs too
   // One loop over the V-cycle's matvec steps (a single inlined tail_step):
   // descend (level first..last-1, m1 sweeps each, residual on the last one),
   // the coarsest solve, then ascend (prolongation + m2 post-sweeps).
@@ -339,8 +437,8 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
   const int nsteps = ndesc + 1 + nlev * m2;
   for (int step = 0; step < nsteps; ++step) {
     if (step == ndesc) {  // coarsest level: b = R r_fine, exact solve by LU
-      const LevelDev<T> lc = levels[last];
-      const T* src = (last == first) ? rf : levels[last - 1].r;
+      const LevelDev<T> lc = lv_uniform(lvs[last - first]);
+      const T* src = (last == first) ? rf : ptr_uniform(lvs[last - 1 - first].r);
       if (src)
         for (int i = threadIdx.x; i < 2 * lc.n + 1; i += kNTT) lc.b[i] = restrict_at(src, i);
       __syncthreads();
@@ -353,7 +451,7 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
     if (step < ndesc) {
       l = first + step / m1;
       const int sweep = step - (l - first) * m1;  // 0-based
-      const T* fine = (l == first) ? rf : levels[l - 1].r;
+      const T* fine = (l == first) ? rf : ptr_uniform(lvs[l - 1 - first].r);
       pro = sweep > 0 ? TP_USE_U : (fine ? TP_PRE_RESTRICT : TP_PRE_B);
       epi = sweep == m1 - 1 ? TE_RESID : TE_SMOOTH;
       src = fine;
@@ -364,32 +462,30 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
       const int sweep = a - (last - 1 - l) * m2;
       pro = sweep == 0 ? TP_PROLONG : TP_USE_U;
       epi = TE_SMOOTH;
-      src = levels[l + 1].u;
+      src = ptr_uniform(lvs[l + 1 - first].u);
       wpro = wepi = wpost;
     }
-    const LevelDev<T> lv = levels[l];
-    if (lv.bmain)
-      tail_step<T, true>(lv, pro, epi, src, wpro, wepi, s);
-    else
-      tail_step<T, false>(lv, pro, epi, src, wpro, wepi, s);
+    tail_step<T, BAND, SYM>(lv_uniform(lvs[l - first]), pro, epi, src, wpro, wepi, s);
   }
 }
 
 // A cycle's small-level part as a program of steps built on the host (the
 // W-cycle: the second visit of a level smooths from its current iterate and
 // recomputes the residual; see TailOp).
-template <typename T>
+template <typename T, bool BAND, bool SYM>
 __global__ __launch_bounds__(kNTT) void k_tail_program(const LevelDev<T>* levels, int first,
                                                        int last, const T* rf, const TailOp* ops,
                                                        int nops, T wpre, T wpost, CoarseLU lu,
                                                        Twiddles<T> tw) {
   extern __shared__ unsigned char smem_raw[];
-  const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);
+  __shared__ LevelDev<T> lvs[kTailMaxLev];
+  tail_levels_to_lds(levels, first, last, lvs);
+  const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);  // its barrier publishes lvs too
   for (int k = 0; k < nops; ++k) {
     const TailOp op = ops[k];
     if (op.flags & TAILOP_COARSE) {  // coarsest level: b = R r_fine, exact solve
-      const LevelDev<T> lc = levels[last];
-      const T* src = (last == first) ? rf : levels[last - 1].r;
+      const LevelDev<T> lc = lv_uniform(lvs[last - first]);
+      const T* src = (last == first) ? rf : ptr_uniform(lvs[last - 1 - first].r);
       if (src)
         for (int i = threadIdx.x; i < 2 * lc.n + 1; i += kNTT) lc.b[i] = restrict_at(src, i);
       __syncthreads();
@@ -398,13 +494,10 @@ __global__ __launch_bounds__(kNTT) void k_tail_program(const LevelDev<T>* levels
     }
     const int l = op.level;
     const T* src = nullptr;
-    if (op.pro == TP_PRE_RESTRICT) src = (l == first) ? rf : levels[l - 1].r;
-    if (op.pro == TP_PROLONG) src = levels[l + 1].u;
+    if (op.pro == TP_PRE_RESTRICT) src = (l == first) ? rf : ptr_uniform(lvs[l - 1 - first].r);
+    if (op.pro == TP_PROLONG) src = ptr_uniform(lvs[l + 1 - first].u);
     const T w = (op.flags & TAILOP_UP) ? wpost : wpre;
-    if (levels[l].bmain)
-      tail_step<T, true>(levels[l], op.pro, op.epi, src, w, w, s);
-    else
-      tail_step<T, false>(levels[l], op.pro, op.epi, src, w, w, s);
+    tail_step<T, BAND, SYM>(lv_uniform(lvs[l - first]), op.pro, op.epi, src, w, w, s);
   }
 }
 
@@ -435,7 +528,10 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
     s.z[j] = v;
   }
   TailSpec<T> sp;
-  tail_spec_load(lv, sp);
+  if (lv.sym)
+    tail_spec_load<T, true>(lv, sp);
+  else
+    tail_spec_load<T, false>(lv, sp);
   // band product of x (weakly singular levels) at index i of the block-ordered vector
   auto bandx = [&](int i) {
     const int m = 2 * n + 1;
@@ -927,21 +1023,45 @@ hipError_t launch_tail_matvec(int colmode, int epimode, const LevelDev<T>& lv, c
 template <typename T>
 hipError_t launch_tail_vcycle(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
                               int m1, int m2, T wpre, T wpost, const CoarseLU& lu,
-                              const Twiddles<T>& tw, int maxL, hipStream_t s) {
-  if (maxL > (1 << kTailLog) || lu.m > 4 * (1 << kTailLog)) return hipErrorInvalidValue;
+                              const Twiddles<T>& tw, int maxL, int variant, hipStream_t s) {
+  if (maxL > (1 << kTailLog) || lu.m > 4 * (1 << kTailLog) || first < 0 ||
+      last - first + 1 > kTailMaxLev || last < first)
+    return hipErrorInvalidValue;
   const size_t lds = tail_lds_bytes(sizeof(T));
-  return launch_lds(k_tail_vcycle<T>, 1, kNTT, lds, s, levels_dev, first, last, rf, m1, m2, wpre,
-                    wpost, lu, tw);
+  switch (variant) {
+    case 0: return launch_lds(k_tail_vcycle<T, false, false>, 1, kNTT, lds, s, levels_dev, first,
+                              last, rf, m1, m2, wpre, wpost, lu, tw);
+    case TAIL_SYM: return launch_lds(k_tail_vcycle<T, false, true>, 1, kNTT, lds, s, levels_dev,
+                                     first, last, rf, m1, m2, wpre, wpost, lu, tw);
+    case TAIL_BAND: return launch_lds(k_tail_vcycle<T, true, false>, 1, kNTT, lds, s, levels_dev,
+                                      first, last, rf, m1, m2, wpre, wpost, lu, tw);
+    case TAIL_BAND | TAIL_SYM:
+      return launch_lds(k_tail_vcycle<T, true, true>, 1, kNTT, lds, s, levels_dev, first, last,
+                        rf, m1, m2, wpre, wpost, lu, tw);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
 hipError_t launch_tail_program(const LevelDev<T>* levels_dev, int first, int last, const T* rf,
                                const TailOp* ops, int nops, T wpre, T wpost, const CoarseLU& lu,
-                               const Twiddles<T>& tw, int maxL, hipStream_t s) {
-  if (maxL > (1 << kTailLog) || lu.m > 4 * (1 << kTailLog)) return hipErrorInvalidValue;
+                               const Twiddles<T>& tw, int maxL, int variant, hipStream_t s) {
+  if (maxL > (1 << kTailLog) || lu.m > 4 * (1 << kTailLog) || first < 0 ||
+      last - first + 1 > kTailMaxLev || last < first)
+    return hipErrorInvalidValue;
   const size_t lds = tail_lds_bytes(sizeof(T));
-  return launch_lds(k_tail_program<T>, 1, kNTT, lds, s, levels_dev, first, last, rf, ops, nops,
-                    wpre, wpost, lu, tw);
+  switch (variant) {
+    case 0: return launch_lds(k_tail_program<T, false, false>, 1, kNTT, lds, s, levels_dev, first,
+                              last, rf, ops, nops, wpre, wpost, lu, tw);
+    case TAIL_SYM: return launch_lds(k_tail_program<T, false, true>, 1, kNTT, lds, s, levels_dev,
+                                     first, last, rf, ops, nops, wpre, wpost, lu, tw);
+    case TAIL_BAND: return launch_lds(k_tail_program<T, true, false>, 1, kNTT, lds, s, levels_dev,
+                                      first, last, rf, ops, nops, wpre, wpost, lu, tw);
+    case TAIL_BAND | TAIL_SYM:
+      return launch_lds(k_tail_program<T, true, true>, 1, kNTT, lds, s, levels_dev, first, last,
+                        rf, ops, nops, wpre, wpost, lu, tw);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_tail_fft_setup(const LevelDev<double>& lv, const double* gx, const double* gy,
@@ -1084,10 +1204,10 @@ template hipError_t launch_cg_dir<float>(const SolveState*, double*, const float
                                             hipStream_t);                                      \
   template hipError_t launch_tail_vcycle<T>(const LevelDev<T>*, int, int, const T*, int, int,  \
                                             T, T, const CoarseLU&, const Twiddles<T>&, int,    \
-                                            hipStream_t);                                      \
+                                            int, hipStream_t);                                 \
   template hipError_t launch_tail_program<T>(const LevelDev<T>*, int, int, const T*,           \
                                              const TailOp*, int, T, T, const CoarseLU&,        \
-                                             const Twiddles<T>&, int, hipStream_t);
+                                             const Twiddles<T>&, int, int, hipStream_t);
 AMG_INSTANTIATE(double)
 AMG_INSTANTIATE(float)
 

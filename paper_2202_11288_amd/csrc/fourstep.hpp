@@ -37,7 +37,8 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
   const int i0 = threadIdx.x >> logTC, di = kNT4 >> logTC;
-  constexpr int CH = EPT < 8 ? EPT : 8;  // elements per load batch
+  // elements per load batch: FP32 issues the whole column's loads at once
+  constexpr int CH = (EPT < 8 || sizeof(T) == 4) ? EPT : 8;
   const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
   // partial tiles: every twiddle of the pass is fetched first, under the loads
   FftTw<T> ft;
@@ -65,6 +66,8 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
       wo1 = in.e_is_float ? (T)((const float*)in.e)[n] : (T)((const double*)in.e)[n];
     }
   }
+  // the damped inverse diagonal of the two blocks, one division per thread
+  const T wdv = in.omega / lv.dv, wdw = in.omega / lv.dw;
   T dot = 0;
   cplx<T> a[EPT];  // formed vector at rows i0 + e*di of column j1
 #pragma unroll
@@ -161,8 +164,8 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
           v = in.omega * v * lv.dinv[js];
           w = in.omega * w * lv.dinv[n + 1 + js];
         } else {
-          v = in.omega * v / lv.dv;
-          w = in.omega * w / lv.dw;
+          v = wdv * v;
+          w = wdw * w;
         }
         if (ok[c]) {
           lv.u[j] = v;
@@ -569,6 +572,7 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
   }
   const T wo = lv.scal[1];  // the matvec input's w_o (see k_row)
   const bool band = lv.bc != nullptr;  // weakly singular levels: + B x, variable diagonal
+  const T wdv = out.omega / lv.dv, wdw = out.omega / lv.dw;  // Jacobi factors, constant diagonal
   double ss = 0.0;
 #pragma unroll
   for (int e = 0; e < KH; ++e) {
@@ -592,8 +596,8 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
         lv.u[j] = u0[e] + out.omega * (b0[e] - yv) * lv.dinv[j];
         lv.u[jw] = u1[e] + out.omega * (b1[e] - yw) * lv.dinv[jw];
       } else {
-        lv.u[j] = u0[e] + out.omega * (b0[e] - yv) / lv.dv;
-        lv.u[jw] = u1[e] + out.omega * (b1[e] - yw) / lv.dw;
+        lv.u[j] = u0[e] + wdv * (b0[e] - yv);
+        lv.u[jw] = u1[e] + wdw * (b1[e] - yw);
       }
     } else {  // EPI_OUTER
       const double rv = o0[e] - (double)yv, rw = o1[e] - (double)yw;
