@@ -47,6 +47,9 @@ Plan plan_level(int64_t n) {
   p.logL2 = logL - p.logL1;
   int t = std::max(1, std::min(16, kCap4 >> p.logL2));
   while (t > 4 && ((1 << p.logL1) / t) < 256) t >>= 1;
+  // the largest levels: tiles of 2 kCap4 (twice the columns, so twice the
+  // bytes per row segment) while that still leaves a tile per CU
+  if ((t << p.logL2) == kCap4 && ((1 << p.logL1) / (2 * t)) >= 256) t *= 2;
   p.tcols = t;
   return p;
 }

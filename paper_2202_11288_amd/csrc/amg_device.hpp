@@ -19,6 +19,7 @@ constexpr int kTw4Lo = 4096;       // low table: e^{-2 pi i m / 2^23}, m < 4096
 constexpr int kTw4Hi = 2048;       // high table: e^{-2 pi i m 4096 / 2^23}, m < 2048
 constexpr int kNT4 = 256;          // threads of a four-step pass workgroup
 constexpr int kCap4 = 4096;        // complex values per four-step workgroup (tile or row pair)
+constexpr int kCapWide = 2 * kCap4;  // wide column tiles (2 kNT4 threads) of the largest levels
 constexpr int kNTT = 512;          // threads of the single-workgroup tail kernels
 constexpr int kTailLog = 12;       // levels with L <= 2^12 run in the tail kernels
 constexpr int kTailMaxLev = 16;    // levels one tail kernel call may span (first..last)

@@ -9,7 +9,10 @@
 //   pass 3 (k_col_inv): inverse column FFTs, Cross terms, residual / Jacobi /
 //            output epilogue.
 // A workgroup holds at most kCap4 complex values (a tile of T columns or a
-// row pair).  The per-thread element counts are template parameters (EPT
+// row pair); the largest levels use column tiles of 2 kCap4 on twice the
+// threads, so that each row segment of a real vector spans 32 bytes rather
+// than 16 (the column passes there are bound by the number of distinct
+// cache lines their loads touch).  The per-thread element counts are template parameters (EPT
 // column elements, KR row elements per row) so that every global load of a
 // pass is issued in compile-time batches into registers, with clamped
 // addresses and masked values, before any of them is used.  Internal header.
@@ -25,18 +28,18 @@ constexpr int kE4 = kCap4 / kNT4;
 // ---------------------------------------------------------------------------
 // Pass 1.  Thread tid owns column j1 = c0 + (tid mod T) at rows i0 + e*di.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int EPT>
-__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename T, int MODE, int EPT, int NT = kNT4>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* part) {
   extern __shared__ unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
-  __shared__ T red[kNT4 / 64];
+  __shared__ T red[NT / 64];
   const int n = lv.n;
   const int L = 1 << lv.logL;
   const int logTC = ilog2(lv.tcols);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
-  const int i0 = threadIdx.x >> logTC, di = kNT4 >> logTC;
+  const int i0 = threadIdx.x >> logTC, di = NT >> logTC;
   // elements per load batch: FP32 issues the whole column's loads at once
   constexpr int CH = (EPT < 8 || sizeof(T) == 4) ? EPT : 8;
   const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
@@ -205,21 +208,21 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
     }
   }
   if constexpr (MODE != COL_SETUP) {
-    const T s = block_sum<T, kNT4>(dot, red);
+    const T s = block_sum<T, NT>(dot, red);
     if (threadIdx.x == 0) part[tile] = s;
   }
   if constexpr (EPT == 16) {
     // the thread's rows i0 + e*di are the positions j0 + e*L2/16 of its
     // last-pass butterfly (j0 = i0): first and last passes on registers
-    fft_reg16<T, kNT4, false>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
+    fft_reg16<T, NT, false>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
     twiddle_run_mul<T, EPT, false>(tw, lv.logL, j1 * i0, j1 * di, a);
   } else {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * kNT4] = a[e];
+    for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * NT] = a[e];
     __syncthreads();
-    lds_fft_pf<T, kNT4, false>(lds, g, ft);
+    lds_fft_pf<T, NT, false>(lds, g, ft);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) a[e] = lds[(int)threadIdx.x + e * kNT4];
+    for (int e = 0; e < EPT; ++e) a[e] = lds[(int)threadIdx.x + e * NT];
     twiddle_run_mul_pre<T, EPT, false>(rt, a);
   }
 #pragma unroll
@@ -498,18 +501,18 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
 // j2 < L2/2, i.e. e < EPT/2 (EPT = 1: threads tid < kNT4/2).  The epilogue's
 // operands are fetched before the FFT so their latency overlaps it.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int EPT>
-__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename T, int MODE, int EPT, int NT = kNT4>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw, double* part) {
   extern __shared__ unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
-  __shared__ double red[kNT4 / 64];
+  __shared__ double red[NT / 64];
   constexpr int KH = EPT > 1 ? EPT / 2 : 1;
   const int n = lv.n;
   const int logTC = ilog2(lv.tcols);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
-  const int i0 = threadIdx.x >> logTC, di = kNT4 >> logTC;
+  const int i0 = threadIdx.x >> logTC, di = NT >> logTC;
   const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
   FftTw<T> ft;  // partial tiles: the FFT's twiddles are fetched first
   if constexpr (EPT < 16) lds_fft_tw_prefetch(g, tw.base, ft);
@@ -533,7 +536,7 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
 #pragma unroll
   for (int e = 0; e < KH; ++e) {
     const int j = j1 + ((i0 + e * di) << lv.logL1);
-    ok[e] = (EPT > 1 || (int)threadIdx.x < kNT4 / 2) && j < n;
+    ok[e] = (EPT > 1 || (int)threadIdx.x < NT / 2) && j < n;
     jj[e] = j;
     const int js = ok[e] ? j : 0, jw = n + 1 + js;
     pp[e] = lv.p[js];
@@ -552,14 +555,14 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
     }
   }
   if constexpr (EPT == 16) {
-    fft_reg16<T, kNT4, true>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
+    fft_reg16<T, NT, true>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
   } else {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * kNT4] = a[e];
+    for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * NT] = a[e];
     __syncthreads();
-    lds_fft_pf<T, kNT4, true>(lds, g, ft);
+    lds_fft_pf<T, NT, true>(lds, g, ft);
 #pragma unroll
-    for (int e = 0; e < KH; ++e) a[e] = lds[(int)threadIdx.x + e * kNT4];
+    for (int e = 0; e < KH; ++e) a[e] = lds[(int)threadIdx.x + e * NT];
   }
   if constexpr (MODE == EPI_SMOOTH && sizeof(T) == 8 && EPT == 16) {
     // FP64 full tiles: the iterate is fetched after the FFT (register budget)
@@ -626,7 +629,7 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
     }
   }
   if constexpr (MODE == EPI_OUTER) {
-    const double s = block_sum<double, kNT4>(ss, red);
+    const double s = block_sum<double, NT>(ss, red);
     if (threadIdx.x == 0) part[tile] = s;
   }
 }
@@ -635,10 +638,13 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
 // Launchers: the level geometry picks the instance (EPT = T L2 / kNT4,
 // KR = max(1, L1 / kNT4)); checked against the kernels' assumptions here.
 // ---------------------------------------------------------------------------
+// A column tile of cnt = tcols * L2 elements runs on kNT4 threads, cnt / kNT4
+// each (reported as ept), up to kCap4; a wide tile of 2 kCap4 elements runs on
+// 2 kNT4 threads with 16 each (reported as ept = 32).
 inline bool col_geom_ok(int logL1, int logL2, int tcols, int* ept) {
   const int cnt = tcols << logL2;
   if (tcols < 1 || (tcols & (tcols - 1)) || tcols > kNT4 || (1 << logL1) % tcols) return false;
-  if (cnt % kNT4 || cnt > kCap4) return false;
+  if (cnt % kNT4 || cnt > kCapWide) return false;
   *ept = cnt / kNT4;
   return true;
 }
@@ -652,6 +658,9 @@ hipError_t col_fwd_ept(int ept, int grid, size_t lds, hipStream_t s, const Level
     case 4: return launch_lds(k_col_fwd<T, MODE, 4>, grid, kNT4, lds, s, lv, in, buf, tw, part);
     case 8: return launch_lds(k_col_fwd<T, MODE, 8>, grid, kNT4, lds, s, lv, in, buf, tw, part);
     case 16: return launch_lds(k_col_fwd<T, MODE, 16>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 32:
+      return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4>, grid, 2 * kNT4, lds, s, lv, in, buf, tw,
+                        part);
     default: return hipErrorInvalidValue;
   }
 }
@@ -666,6 +675,9 @@ hipError_t col_inv_ept(int ept, int grid, size_t lds, hipStream_t s, const Level
     case 4: return launch_lds(k_col_inv<T, MODE, 4>, grid, kNT4, lds, s, lv, out, buf, tw, part);
     case 8: return launch_lds(k_col_inv<T, MODE, 8>, grid, kNT4, lds, s, lv, out, buf, tw, part);
     case 16: return launch_lds(k_col_inv<T, MODE, 16>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 32:
+      return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4>, grid, 2 * kNT4, lds, s, lv, out, buf, tw,
+                        part);
     default: return hipErrorInvalidValue;
   }
 }

@@ -90,11 +90,12 @@ def test_level_matvec_every_level(case, N):
         B.amg_destroy(h)
 
 
-@pytest.mark.parametrize("N", [512, 16384, 2 ** 20])
+@pytest.mark.parametrize("N", [512, 16384, 2 ** 20, 2 ** 21])
 def test_matvec_general_blocks(N):
     """Caller-supplied non-symmetric blocks (AMG_K_GENERATORS): the general
     two-complex-spectra path against dense (small N) / oracle FFT (large N;
-    2^20 runs the full-tile four-step kernels with register first/last passes)."""
+    2^20 runs the full-tile four-step kernels with register first/last passes,
+    2^20 and 2^21 the wide column tiles of the largest levels)."""
     say("general_blocks", N)
     gA, gB, gC, gD = synthetic.random_tpx_arrays(N - 1, seed=N, decay=0.001)
     gen = np.ascontiguousarray(np.concatenate([gA, gB, gC, gD]))
