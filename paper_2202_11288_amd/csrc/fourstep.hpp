@@ -28,7 +28,7 @@ constexpr int kE4 = kCap4 / kNT4;
 // ---------------------------------------------------------------------------
 // Pass 1.  Thread tid owns column j1 = c0 + (tid mod T) at rows i0 + e*di.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int EPT, int NT = kNT4>
+template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* part) {
   extern __shared__ unsigned char smem_raw[];
@@ -36,13 +36,16 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
   __shared__ T red[NT / 64];
   const int n = lv.n;
   const int L = 1 << lv.logL;
-  const int logTC = ilog2(lv.tcols);
+  // column length and tile width: compile-time constants when LOG2 != 0
+  const int logL2 = LOG2 ? LOG2 : lv.logL2;
+  const int logTC = LOG2 ? ilog2(EPT * NT) - LOG2 : ilog2(lv.tcols);
+  const int tcols = 1 << logTC;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
+  const int j1 = tile * tcols + (threadIdx.x & (tcols - 1));
   const int i0 = threadIdx.x >> logTC, di = NT >> logTC;
   // elements per load batch: FP32 issues the whole column's loads at once
   constexpr int CH = (EPT < 8 || sizeof(T) == 4) ? EPT : 8;
-  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  const FftGeom g{logL2, logTC, 0, logTC, kTwLog, true};
   // partial tiles: every twiddle of the pass is fetched first, under the loads
   FftTw<T> ft;
   RunTw<T, EPT> rt;
@@ -214,7 +217,7 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
   if constexpr (EPT == 16) {
     // the thread's rows i0 + e*di are the positions j0 + e*L2/16 of its
     // last-pass butterfly (j0 = i0): first and last passes on registers
-    fft_reg16<T, NT, false>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
+    fft_reg16<T, NT, false>(a, lds, g, threadIdx.x & (tcols - 1), i0, tw.base);
     twiddle_run_mul<T, EPT, false>(tw, lv.logL, j1 * i0, j1 * di, a);
   } else {
 #pragma unroll
@@ -285,11 +288,14 @@ template <typename T, bool SPECTRAL, bool SYM>
 __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds, cplx<T>* buf,
                                               const Twiddles<T>& tw, int item) {
   constexpr int Q = 16 * kNT4 / 2 / 16;  // L1/16 butterflies per row
-  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2;
+  constexpr int kLog1 = 11;               // log2 L1: the geometry is a compile-time constant
+  static_assert((1 << kLog1) == 16 * Q, "row length of the register row pass");
+  constexpr int L1 = 1 << kLog1;
+  const int L2 = 1 << lv.logL2;
   const int tid = threadIdx.x;
   const int s = tid / Q, j0 = tid % Q;
   const int k2 = item == 0 ? (s == 0 ? 0 : L2 / 2) : (s == 0 ? item : L2 - item);
-  const int row = k2 << lv.logL1;
+  const int row = k2 << kLog1;
   cplx<T> a[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) a[e] = ldg(buf + row + j0 + e * Q);
@@ -305,7 +311,7 @@ __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds,
     }
   };
   if (kEarly && SPECTRAL && SYM) load_spec();
-  const FftGeom g{lv.logL1, 1, lv.logL1, 0, kTwLog, false};
+  const FftGeom g{kLog1, 1, kLog1, 0, kTwLog, false};
   fft_reg16<T, kNT4, false>(a, lds, g, s, j0, tw.base);
   if (!kEarly && SPECTRAL && SYM) load_spec();
   if constexpr (!SPECTRAL) {
@@ -316,7 +322,7 @@ __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds,
     // row 0 with (L1-k1) mod L1 and within row L2/2 with L1-1-k1 for item 0
     __syncthreads();  // last-pass LDS reads done before the exchange writes
 #pragma unroll
-    for (int e = 0; e < 16; ++e) lds[(s << lv.logL1) + j0 + e * Q] = a[e];
+    for (int e = 0; e < 16; ++e) lds[(s << kLog1) + j0 + e * Q] = a[e];
     __syncthreads();
     auto partner = [&](int e) {
       const int p = j0 + e * Q;
@@ -501,7 +507,7 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
 // j2 < L2/2, i.e. e < EPT/2 (EPT = 1: threads tid < kNT4/2).  The epilogue's
 // operands are fetched before the FFT so their latency overlaps it.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int EPT, int NT = kNT4>
+template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw, double* part) {
   extern __shared__ unsigned char smem_raw[];
@@ -509,11 +515,14 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
   __shared__ double red[NT / 64];
   constexpr int KH = EPT > 1 ? EPT / 2 : 1;
   const int n = lv.n;
-  const int logTC = ilog2(lv.tcols);
+  // column length and tile width: compile-time constants when LOG2 != 0
+  const int logL2 = LOG2 ? LOG2 : lv.logL2;
+  const int logTC = LOG2 ? ilog2(EPT * NT) - LOG2 : ilog2(lv.tcols);
+  const int tcols = 1 << logTC;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int j1 = tile * lv.tcols + (threadIdx.x & (lv.tcols - 1));
+  const int j1 = tile * tcols + (threadIdx.x & (tcols - 1));
   const int i0 = threadIdx.x >> logTC, di = NT >> logTC;
-  const FftGeom g{lv.logL2, logTC, 0, logTC, kTwLog, true};
+  const FftGeom g{logL2, logTC, 0, logTC, kTwLog, true};
   FftTw<T> ft;  // partial tiles: the FFT's twiddles are fetched first
   if constexpr (EPT < 16) lds_fft_tw_prefetch(g, tw.base, ft);
   cplx<T> a[EPT];  // rows i0 + e*di of column j1
@@ -555,7 +564,7 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
     }
   }
   if constexpr (EPT == 16) {
-    fft_reg16<T, NT, true>(a, lds, g, threadIdx.x & (lv.tcols - 1), i0, tw.base);
+    fft_reg16<T, NT, true>(a, lds, g, threadIdx.x & (tcols - 1), i0, tw.base);
   } else {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) lds[(int)threadIdx.x + e * NT] = a[e];
@@ -657,10 +666,21 @@ hipError_t col_fwd_ept(int ept, int grid, size_t lds, hipStream_t s, const Level
     case 2: return launch_lds(k_col_fwd<T, MODE, 2>, grid, kNT4, lds, s, lv, in, buf, tw, part);
     case 4: return launch_lds(k_col_fwd<T, MODE, 4>, grid, kNT4, lds, s, lv, in, buf, tw, part);
     case 8: return launch_lds(k_col_fwd<T, MODE, 8>, grid, kNT4, lds, s, lv, in, buf, tw, part);
-    case 16: return launch_lds(k_col_fwd<T, MODE, 16>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 16:
+      if (lv.logL2 == 10)
+        return launch_lds(k_col_fwd<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, in, buf, tw,
+                          part);
+      return launch_lds(k_col_fwd<T, MODE, 16>, grid, kNT4, lds, s, lv, in, buf, tw, part);
     case 32:
-      return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4>, grid, 2 * kNT4, lds, s, lv, in, buf, tw,
-                        part);
+      switch (lv.logL2) {
+        case 10: return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4, 10>, grid, 2 * kNT4, lds, s, lv,
+                                   in, buf, tw, part);
+        case 11: return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4, 11>, grid, 2 * kNT4, lds, s, lv,
+                                   in, buf, tw, part);
+        case 12: return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4, 12>, grid, 2 * kNT4, lds, s, lv,
+                                   in, buf, tw, part);
+        default: return hipErrorInvalidValue;
+      }
     default: return hipErrorInvalidValue;
   }
 }
@@ -674,10 +694,21 @@ hipError_t col_inv_ept(int ept, int grid, size_t lds, hipStream_t s, const Level
     case 2: return launch_lds(k_col_inv<T, MODE, 2>, grid, kNT4, lds, s, lv, out, buf, tw, part);
     case 4: return launch_lds(k_col_inv<T, MODE, 4>, grid, kNT4, lds, s, lv, out, buf, tw, part);
     case 8: return launch_lds(k_col_inv<T, MODE, 8>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 16: return launch_lds(k_col_inv<T, MODE, 16>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 16:
+      if (lv.logL2 == 10)
+        return launch_lds(k_col_inv<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, out, buf, tw,
+                          part);
+      return launch_lds(k_col_inv<T, MODE, 16>, grid, kNT4, lds, s, lv, out, buf, tw, part);
     case 32:
-      return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4>, grid, 2 * kNT4, lds, s, lv, out, buf, tw,
-                        part);
+      switch (lv.logL2) {
+        case 10: return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4, 10>, grid, 2 * kNT4, lds, s, lv,
+                                   out, buf, tw, part);
+        case 11: return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4, 11>, grid, 2 * kNT4, lds, s, lv,
+                                   out, buf, tw, part);
+        case 12: return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4, 12>, grid, 2 * kNT4, lds, s, lv,
+                                   out, buf, tw, part);
+        default: return hipErrorInvalidValue;
+      }
     default: return hipErrorInvalidValue;
   }
 }
