@@ -362,13 +362,15 @@ __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds,
   }
 }
 
-template <typename T, bool SPECTRAL, bool SYM, int KR>
+template <typename T, bool SPECTRAL, bool SYM, int KR, int LOG1 = 0>
 __global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
 void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
   extern __shared__ unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   __shared__ T red[kNT4 / 64];
-  const int L1 = 1 << lv.logL1, L2 = 1 << lv.logL2;
+  // row length: a compile-time constant when LOG1 != 0
+  const int logL1 = LOG1 ? LOG1 : lv.logL1;
+  const int L1 = 1 << logL1, L2 = 1 << lv.logL2;
   const int item = blockIdx.x;
   const int tid = threadIdx.x;
   const T wpart = (SPECTRAL && item == 0) ? wo_partial(part, npart) : T(0);
@@ -379,9 +381,9 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
   }
   const int ka = item == 0 ? 0 : item;
   const int kb = item == 0 ? L2 / 2 : L2 - item;
-  const int ra = ka << lv.logL1, rb = kb << lv.logL1;
+  const int ra = ka << logL1, rb = kb << logL1;
   // every twiddle of the pass is fetched first, under the loads
-  const FftGeom g{lv.logL1, 1, lv.logL1, 0, kTwLog, false};
+  const FftGeom g{logL1, 1, logL1, 0, kTwLog, false};
   FftTw<T> ft;
   lds_fft_tw_prefetch(g, tw.base, ft);
   const bool act = KR > 1 || tid < L1;  // KR == 1: rows shorter than the workgroup
@@ -662,10 +664,26 @@ template <typename T, int MODE>
 hipError_t col_fwd_ept(int ept, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
                        const ColIn<T>& in, cplx<T>* buf, const Twiddles<T>& tw, T* part) {
   switch (ept) {
-    case 1: return launch_lds(k_col_fwd<T, MODE, 1>, grid, kNT4, lds, s, lv, in, buf, tw, part);
-    case 2: return launch_lds(k_col_fwd<T, MODE, 2>, grid, kNT4, lds, s, lv, in, buf, tw, part);
-    case 4: return launch_lds(k_col_fwd<T, MODE, 4>, grid, kNT4, lds, s, lv, in, buf, tw, part);
-    case 8: return launch_lds(k_col_fwd<T, MODE, 8>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 1:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_fwd<T, MODE, 1, kNT4, 6>, grid, kNT4, lds, s, lv, in, buf, tw,
+                          part);
+      return launch_lds(k_col_fwd<T, MODE, 1>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 2:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_fwd<T, MODE, 2, kNT4, 7>, grid, kNT4, lds, s, lv, in, buf, tw,
+                          part);
+      return launch_lds(k_col_fwd<T, MODE, 2>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 4:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_fwd<T, MODE, 4, kNT4, 8>, grid, kNT4, lds, s, lv, in, buf, tw,
+                          part);
+      return launch_lds(k_col_fwd<T, MODE, 4>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 8:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_fwd<T, MODE, 8, kNT4, 9>, grid, kNT4, lds, s, lv, in, buf, tw,
+                          part);
+      return launch_lds(k_col_fwd<T, MODE, 8>, grid, kNT4, lds, s, lv, in, buf, tw, part);
     case 16:
       if (lv.logL2 == 10)
         return launch_lds(k_col_fwd<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, in, buf, tw,
@@ -690,10 +708,26 @@ hipError_t col_inv_ept(int ept, int grid, size_t lds, hipStream_t s, const Level
                        const EpiOut<T>& out, const cplx<T>* buf, const Twiddles<T>& tw,
                        double* part) {
   switch (ept) {
-    case 1: return launch_lds(k_col_inv<T, MODE, 1>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 2: return launch_lds(k_col_inv<T, MODE, 2>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 4: return launch_lds(k_col_inv<T, MODE, 4>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 8: return launch_lds(k_col_inv<T, MODE, 8>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 1:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_inv<T, MODE, 1, kNT4, 6>, grid, kNT4, lds, s, lv, out, buf, tw,
+                          part);
+      return launch_lds(k_col_inv<T, MODE, 1>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 2:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_inv<T, MODE, 2, kNT4, 7>, grid, kNT4, lds, s, lv, out, buf, tw,
+                          part);
+      return launch_lds(k_col_inv<T, MODE, 2>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 4:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_inv<T, MODE, 4, kNT4, 8>, grid, kNT4, lds, s, lv, out, buf, tw,
+                          part);
+      return launch_lds(k_col_inv<T, MODE, 4>, grid, kNT4, lds, s, lv, out, buf, tw, part);
+    case 8:
+      if (lv.tcols == 4)
+        return launch_lds(k_col_inv<T, MODE, 8, kNT4, 9>, grid, kNT4, lds, s, lv, out, buf, tw,
+                          part);
+      return launch_lds(k_col_inv<T, MODE, 8>, grid, kNT4, lds, s, lv, out, buf, tw, part);
     case 16:
       if (lv.logL2 == 10)
         return launch_lds(k_col_inv<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, out, buf, tw,
@@ -717,9 +751,16 @@ template <typename T, bool SPECTRAL, bool SYM>
 hipError_t row_kr(int kr, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
                   cplx<T>* buf, const Twiddles<T>& tw, const T* part, int npart, const T* xin) {
   switch (kr) {
-    case 1: return launch_lds(k_row<T, SPECTRAL, SYM, 1>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
-    case 2: return launch_lds(k_row<T, SPECTRAL, SYM, 2>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
-    case 4: return launch_lds(k_row<T, SPECTRAL, SYM, 4>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    case 1:
+      if (lv.logL1 == 7)
+        return launch_lds(k_row<T, SPECTRAL, SYM, 1, 7>, grid, kNT4, lds, s, lv, buf, tw, part,
+                          npart, xin);
+      if (lv.logL1 == 8)
+        return launch_lds(k_row<T, SPECTRAL, SYM, 1, 8>, grid, kNT4, lds, s, lv, buf, tw, part,
+                          npart, xin);
+      return launch_lds(k_row<T, SPECTRAL, SYM, 1>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    case 2: return launch_lds(k_row<T, SPECTRAL, SYM, 2, 9>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    case 4: return launch_lds(k_row<T, SPECTRAL, SYM, 4, 10>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
     case 8: return launch_lds(k_row<T, SPECTRAL, SYM, 8>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
     default: return hipErrorInvalidValue;
   }
