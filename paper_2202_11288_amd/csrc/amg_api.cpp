@@ -1143,6 +1143,16 @@ int gmres_round(amg_t h, const double* b, double* x, double tol, hipStream_t s) 
   return AMG_OK;
 }
 
+// Waits for a round's stop test by polling the stream instead of a blocking
+// synchronise (whose wake-up latency is of the order of a small level's whole
+// V-cycle): the calling thread spins while the round runs.
+hipError_t round_wait(hipStream_t s) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) return e;
+  }
+}
+
 // Enqueues the work up to the next stop test; round counts the calls since
 // solve_begin (whose residual and stop test come first).
 int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s, int round) {
@@ -1171,7 +1181,7 @@ int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s, 
     h->prof.span(PK_VCYCLE, v0, v1);
     h->prof.span(PK_OUTER, v1, v2);
   }
-  HIP_TRY(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(launch_publish(h->st_dev, h->st_host, s));
   return AMG_OK;
 }
 
@@ -1227,7 +1237,7 @@ int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int
   hipStream_t s = (hipStream_t)stream;
   AMG_TRY(solve_begin(h, b, x, tol, s));
   for (int round = 0;; ++round) {
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(round_wait(s));
     if (h->st_host->done) break;
     AMG_TRY(solve_round(h, b, x, tol, s, round));
   }
@@ -1272,7 +1282,7 @@ int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const*
     AMG_TRY(solve_begin(hs[i], b[i], x[i], tol[i], pool->streams[i % S]));
   std::vector<char> done(count, 0);
   for (int round = 0;; ++round) {
-    for (int k = 0; k < S; ++k) HIP_TRY(hipStreamSynchronize(pool->streams[k]));
+    for (int k = 0; k < S; ++k) HIP_TRY(round_wait(pool->streams[k]));
     int active = 0;
     for (int i = 0; i < count; ++i) {
       if (done[i]) continue;

@@ -228,6 +228,7 @@ hipError_t launch_gm_update(const SolveState* st, const double* H, const double*
 hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double tol, int max_iter,
                            double* hist, hipStream_t s, int stall = 0);
 hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s);
+hipError_t launch_publish(const SolveState* st, SolveState* host, hipStream_t s);
 
 // bc = B x for the level's band (2n+1 entries)
 template <typename T>

@@ -955,6 +955,20 @@ __global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const doubl
   st->vtrue = rel;
 }
 
+// The solve state into pinned host memory (the host's view of the round):
+// written by the device directly instead of a copy command.
+__global__ void k_publish(const SolveState* st, SolveState* host) {
+  const int w = threadIdx.x;
+  constexpr int W = sizeof(SolveState) / 4;
+  if (w < W) reinterpret_cast<unsigned*>(host)[w] = reinterpret_cast<const unsigned*>(st)[w];
+  __threadfence_system();
+}
+hipError_t launch_publish(const SolveState* st, SolveState* host, hipStream_t s) {
+  static_assert(sizeof(SolveState) % 4 == 0 && sizeof(SolveState) / 4 <= 64, "state words");
+  hipLaunchKernelGGL(k_publish, 1, 64, 0, s, st, host);
+  return hipGetLastError();
+}
+
 __global__ void k_copy_f2d(const float* a, double* b, int64_t m) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) b[i] = (double)a[i];
