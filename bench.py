@@ -155,15 +155,19 @@ def traffic_summary(fetch_csv, write_csv, logN):
         copies = [v for (name, g), vals in per.items() if "copyBuffer" in name for v in vals]
         big = max(copies)
         scale = COPY_BYTES / big
-        fin = {k: v for k, v in per.items()
-               if k[0].startswith(("amg::k_col_fwd<float", "amg::k_row<float", "amg::k_col_inv<float"))}
-        # the finest level's kernels have the largest grids of their kind
-        sel = {}
-        for kind in ("k_col_fwd", "k_row", "k_col_inv"):
-            ks = {k: v for k, v in fin.items() if kind in k[0]}
-            g = max(gg for (_, gg) in ks)
-            sel[kind] = [x for (name, gg), vals in ks.items() if gg == g for x in vals]
+        # the finest level's FP32 passes: the wide (512-thread) column tiles and
+        # the row pass on rows of 2048 points (KR = 8); the level below shares
+        # the row pass's grid size, so the template arguments decide
+        finest = {"k_col_fwd": ("amg::k_col_fwd<float", ", 16, 512,"),
+                  "k_row": ("amg::k_row<float", ", 8, 0>"),
+                  "k_col_inv": ("amg::k_col_inv<float", ", 16, 512,")}
+        sel = {kind: [x for (name, _), vals in per.items()
+                      if name.startswith(pre) and tag in name for x in vals]
+               for kind, (pre, tag) in finest.items()}
         sweeps = len(sel["k_row"])
+        if not sweeps or any(len(v) != sweeps for v in sel.values()):
+            raise SystemExit(f"{counter}: finest-level dispatch counts differ: "
+                             f"{ {k: len(v) for k, v in sel.items()} }")
         total = sum(sum(v) for v in sel.values()) * scale / sweeps
         out[label] = {"copy_counter_bytes": big, "copy_known_bytes": COPY_BYTES,
                       "scale": round(scale, 4), "sweeps": sweeps,
