@@ -24,6 +24,10 @@ namespace {
 
 // levels with L <= 2^kTailLog run in the one-workgroup tail kernels (amg_device.hpp)
 
+// Levels above the coarsest with at most this many unknowns are folded into
+// one dense operator of the V-cycle below them (form_sub_vcycle).
+constexpr int kSubDenseMax = 255;
+
 struct Plan {
   int logL, logL1, logL2, tcols;
   bool tail;
@@ -198,6 +202,12 @@ struct amg_ctx {
   int maxL_tail = 0;
   int tail_variant = 0;  // TAIL_BAND / TAIL_SYM of the tail levels (all alike)
   CoarseLU lu{};
+  // The V-cycle's small-level kernel stops at level vc_last and applies lu_vc
+  // there: the coarsest level's inverse, or (when a level above the coarsest
+  // has at most kSubDenseMax unknowns) the dense matrix of the whole V-cycle
+  // below and including that level, which is linear in its right-hand side.
+  int vc_last = 0;
+  CoarseLU lu_vc{};
   Twiddles<double> tw64{};
   Twiddles<float> tw32{};
   cplx<double>* buf64 = nullptr;
@@ -354,6 +364,8 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess, bool band) {
              (int64_t)(kGmMax + 1) * (kGmMax + 6 + 1024) * 8;
   const int64_t mc = (int64_t(2) << o->coarsest_log2) - 1;
   bytes += 2 * mc * mc * 8;
+  if (o->cycle != 2 && mc < kSubDenseMax)  // the folded sub-cycle's operator
+    bytes += (int64_t)kSubDenseMax * kSubDenseMax * 8;
   bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
   return bytes;
 }
@@ -450,8 +462,8 @@ int vcycle_dev(amg_ctx* c, hipStream_t s) {
   {
     const T* rf = (ft > 0) ? c->lv[ft - 1].template dev<T>().r : nullptr;
     const size_t t0 = c->prof.mark(s);
-    HIP_TRY(launch_tail_vcycle<T>(lvdev_of<T>(c), ft, nl - 1, rf, o.m1, o.m2, wpre, wpost, c->lu,
-                                  tw_of<T>(c), c->maxL_tail, c->tail_variant, s));
+    HIP_TRY(launch_tail_vcycle<T>(lvdev_of<T>(c), ft, c->vc_last, rf, o.m1, o.m2, wpre, wpost,
+                                  c->lu_vc, tw_of<T>(c), c->maxL_tail, c->tail_variant, s));
     c->prof.span(PK_TAIL, t0, c->prof.mark(s));
   }
   for (int l = ft - 1; l >= 0; --l) {
@@ -638,6 +650,49 @@ int level_matvec64(amg_ctx* c, int l, const double* x, double* y, hipStream_t s)
   return fourstep<double>(c, l, COL_MV, in, EPI_MV, out, s);
 }
 
+// The V-cycle below and including level k (pre-smoothing from zero, the
+// recursion, post-smoothing) is a linear map of level k's right-hand side.
+// For the largest level k above the coarsest with at most kSubDenseMax
+// unknowns, its matrix is formed column by column by running the FP64
+// small-level kernel on the unit vectors; the V-cycle's small-level kernel
+// then stops at level k and applies it as it applies the coarsest inverse.
+// One dense product of m^2 entries replaces that level's and the levels
+// below's steps (a few microseconds of one workgroup each, whatever their
+// size) and the coarsest solve.
+int form_sub_vcycle(amg_ctx* c, hipStream_t s) {
+  const int nl = (int)c->lv.size();
+  const int ft = c->first_tail;
+  int k = -1;
+  for (int l = ft; l < nl - 1; ++l)
+    if (2 * c->lv[l].n + 1 <= kSubDenseMax) {
+      k = l;
+      break;
+    }
+  if (k < 0) return AMG_OK;
+  const amg_opts_t& o = c->opts;
+  const int m = (int)(2 * c->lv[k].n + 1);
+  double* M = nullptr;
+  AMG_TRY(dalloc(c, &M, (size_t)m * m));
+  double* bk = c->lv[k].bd;
+  const double* uk = c->lv[k].ud;
+  for (int j = 0; j < m; ++j) {
+    HIP_TRY(launch_basis(bk, m, j, s));
+    HIP_TRY(launch_tail_vcycle<double>(c->lvdev64, k, nl - 1, nullptr, o.m1, o.m2, o.omega_pre,
+                                       o.omega_post, c->lu, c->tw64, c->maxL_tail,
+                                       c->tail_variant, s));
+    HIP_TRY(hipMemcpyAsync(M + (size_t)j * m, uk, (size_t)m * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  }
+  float* M32 = nullptr;  // the FP32 V-cycle reads the operator's FP32 rounding
+  if (c->mixed) {
+    AMG_TRY(dalloc(c, &M32, (size_t)m * m));
+    HIP_TRY(launch_copy_d2f(M, M32, (int64_t)m * m, s));
+  }
+  c->vc_last = k;
+  c->lu_vc = {m, M, M32};
+  return AMG_OK;
+}
+
 int setup_device(amg_ctx* c, hipStream_t s) {
   const bool mixed = c->mixed;
   const int nl = (int)c->host.size();
@@ -781,7 +836,7 @@ int setup_device(amg_ctx* c, hipStream_t s) {
     lu_inverse(A, m, piv, inv);
     double* ai;
     AMG_TRY(upload(c, &ai, inv, s));
-    c->lu = {m, ai};
+    c->lu = {m, ai, nullptr};
   }
   {
     const int ft = c->first_tail;
@@ -810,6 +865,9 @@ int setup_device(amg_ctx* c, hipStream_t s) {
                              hipMemcpyHostToDevice, s));
     }
   }
+  c->vc_last = nl - 1;
+  c->lu_vc = c->lu;
+  if (c->opts.cycle != 2) AMG_TRY(form_sub_vcycle(c, s));
   if (c->opts.cycle == 2) {
     const int ft = c->first_tail, last = nl - 1;
     for (int k = 0; k < 2; ++k) {

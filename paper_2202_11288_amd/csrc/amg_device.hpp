@@ -105,10 +105,13 @@ struct TailOp {
 };
 
 // Coarsest level: A_c^{-1} (column-major m x m), formed at setup from the
-// LU factors with partial pivoting.
+// LU factors with partial pivoting; or the matrix of the V-cycle below a
+// level folded into one operator.  ainv32: its FP32 rounding for the FP32
+// V-cycle (null: the FP32 V-cycle reads ainv).
 struct CoarseLU {
   int m;
   const double* ainv;
+  const float* ainv32;
 };
 
 struct SolveState {
@@ -229,6 +232,7 @@ hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double t
                            double* hist, hipStream_t s, int stall = 0);
 hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s);
 hipError_t launch_publish(const SolveState* st, SolveState* host, hipStream_t s);
+hipError_t launch_basis(double* b, int m, int j, hipStream_t s);
 
 // bc = B x for the level's band (2n+1 entries)
 template <typename T>

@@ -31,7 +31,7 @@ constexpr int kE4 = kCap4 / kNT4;
 template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* part) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   __shared__ T red[NT / 64];
   const int n = lv.n;
@@ -365,7 +365,7 @@ __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds,
 template <typename T, bool SPECTRAL, bool SYM, int KR, int LOG1 = 0>
 __global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
 void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   __shared__ T red[kNT4 / 64];
   // row length: a compile-time constant when LOG1 != 0
@@ -512,7 +512,7 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
 template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw, double* part) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   __shared__ double red[NT / 64];
   constexpr int KH = EPT > 1 ? EPT / 2 : 1;
