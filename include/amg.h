@@ -116,8 +116,8 @@ typedef struct {
   int coarsest_log2;          /* coarsest level has 2^coarsest_log2 intervals */
   int precision;              /* AMG_FP64: everything FP64.  AMG_MIXED: V-cycle
                                  FFT matvecs/smoothing/transfers in FP32; outer
-                                 residual, refinement update and coarsest LU in
-                                 FP64 (iterative refinement).                 */
+                                 residual, refinement update and the coarsest
+                                 inverse in FP64 (iterative refinement).      */
   int max_iter;               /* outer iterations                            */
   int flags;                  /* AMG_FLAG_* bits, 0 by default               */
   int inner;                  /* AMG_INNER_VCYCLE (default) or AMG_INNER_PCG */
@@ -210,7 +210,11 @@ void amg_default_opts(amg_opts_t* o);
  * partial last cell [r h, delta] is integrated exactly when delta/h is not an
  * integer), Galerkin levels by Lemma 3.1 down to 2^coarsest_log2 intervals,
  * per-level circulant spectra (eq. (ccs3.4)) on the device, LU of the
- * coarsest level.  N must be a power of two with coarsest_log2 < log2 N <= 22
+ * coarsest level.  For V-cycles (cycle = 1), the cycle below and including
+ * the largest level above the coarsest with at most 255 unknowns is a linear
+ * map of that level's right-hand side: setup forms its matrix from the unit
+ * vectors (FP64, a few ms) and V-cycles apply it as one dense product (the
+ * same operator as the recursion, to rounding).  N must be a power of two with coarsest_log2 < log2 N <= 22
  * and 2 <= coarsest_log2; 0 < delta < 1/2 (ignored for AMG_K_GENERATORS).
  * *out receives the handle.  Errors: AMG_EINVAL (bad N, delta, alpha, weights,
  * null pointer, options; inner = AMG_INNER_PCG with a non-symmetric operator),
@@ -228,8 +232,10 @@ int amg_matvec(amg_t h, const double* x, double* y, void* stream);
 int amg_level_matvec(amg_t h, int level, const double* x, double* y, void* stream);
 
 /* e = B_K r: one V-cycle of Algorithm 2 from a zero initial guess.  With
- * AMG_FP64, r and e are double*; with AMG_MIXED they are float* (the coarsest
- * solve still runs in FP64).  2N-1 entries, device, must not alias. */
+ * AMG_FP64, r and e are double*; with AMG_MIXED they are float* (the
+ * coarsest inverse is applied from FP64 entries with FP64 sums, the folded
+ * bottom levels (amg_setup) from their FP32 rounding).  2N-1 entries,
+ * device, must not alias. */
 int amg_vcycle(amg_t h, const void* r, void* e, void* stream);
 
 /* Solve A x = b by x <- x + B_K (b - A x) (or, with inner = AMG_INNER_PCG,
