@@ -208,6 +208,11 @@ struct amg_ctx {
   // below and including that level, which is linear in its right-hand side.
   int vc_last = 0;
   CoarseLU lu_vc{};
+  // The same for W-cycles: the small-level programs stop at level w_last and
+  // apply lu_w there (the coarsest inverse, or the matrix of all the visits a
+  // level receives each time the level above descends).
+  int w_last = 0;
+  CoarseLU lu_w{};
   Twiddles<double> tw64{};
   Twiddles<float> tw32{};
   cplx<double>* buf64 = nullptr;
@@ -364,7 +369,7 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess, bool band) {
              (int64_t)(kGmMax + 1) * (kGmMax + 6 + 1024) * 8;
   const int64_t mc = (int64_t(2) << o->coarsest_log2) - 1;
   bytes += 2 * mc * mc * 8;
-  if (o->cycle != 2 && mc < kSubDenseMax)  // the folded sub-cycle's operator
+  if (mc < kSubDenseMax)  // the folded sub-cycle's operator
     bytes += (int64_t)kSubDenseMax * kSubDenseMax * 8;
   bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
   return bytes;
@@ -520,8 +525,8 @@ int wcycle_visit(amg_ctx* c, int l, bool first, hipStream_t s) {
   if (l == ft) {
     const T* rf = (ft > 0) ? c->lv[ft - 1].template dev<T>().r : nullptr;
     const int k = first ? 0 : 1;
-    HIP_TRY(launch_tail_program<T>(lvdev_of<T>(c), ft, nl - 1, rf, c->tail_prog[k],
-                                   c->tail_prog_n[k], wpre, wpost, c->lu, tw_of<T>(c),
+    HIP_TRY(launch_tail_program<T>(lvdev_of<T>(c), ft, c->w_last, rf, c->tail_prog[k],
+                                   c->tail_prog_n[k], wpre, wpost, c->lu_w, tw_of<T>(c),
                                    c->maxL_tail, c->tail_variant, s));
     return AMG_OK;
   }
@@ -690,6 +695,55 @@ int form_sub_vcycle(amg_ctx* c, hipStream_t s) {
   }
   c->vc_last = k;
   c->lu_vc = {m, M, M32};
+  return AMG_OK;
+}
+
+// W-cycles: each time a level descends, the level below receives gamma visits
+// (the first from zero, the others from the current iterate with the same
+// right-hand side), which together are a linear map of that right-hand
+// side.  For the largest level strictly below the small-level kernel's first
+// one with at most kSubDenseMax unknowns, setup forms the matrix of those
+// visits from the unit vectors (the FP64 step-program kernel on a program of
+// just those visits), and the small-level programs stop there and apply it:
+// 2^d visits of that level and everything below become 2^d dense products.
+int form_sub_wcycle(amg_ctx* c, hipStream_t s) {
+  const int nl = (int)c->lv.size();
+  const int ft = c->first_tail, last = nl - 1;
+  int k = -1;
+  for (int l = ft + 1; l < last; ++l)
+    if (2 * c->lv[l].n + 1 <= kSubDenseMax) {
+      k = l;
+      break;
+    }
+  if (k < 0) return AMG_OK;
+  const amg_opts_t& o = c->opts;
+  std::vector<TailOp> ops;
+  for (int v = 0; v < o.cycle; ++v) tail_visit(ops, k, v == 0, k, last, o.m1, o.m2, o.cycle, false);
+  std::vector<int> raw(ops.size() * 4);
+  std::memcpy(raw.data(), ops.data(), raw.size() * sizeof(int));
+  int* prog = nullptr;
+  AMG_TRY(upload(c, &prog, raw, s));
+  const int m = (int)(2 * c->lv[k].n + 1);
+  double* M = nullptr;
+  AMG_TRY(dalloc(c, &M, (size_t)m * m));
+  double* bk = c->lv[k].bd;
+  const double* uk = c->lv[k].ud;
+  for (int j = 0; j < m; ++j) {
+    HIP_TRY(launch_basis(bk, m, j, s));
+    HIP_TRY(launch_tail_program<double>(c->lvdev64, k, last, nullptr,
+                                        reinterpret_cast<const TailOp*>(prog), (int)ops.size(),
+                                        o.omega_pre, o.omega_post, c->lu, c->tw64, c->maxL_tail,
+                                        c->tail_variant, s));
+    HIP_TRY(hipMemcpyAsync(M + (size_t)j * m, uk, (size_t)m * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  }
+  float* M32 = nullptr;
+  if (c->mixed) {
+    AMG_TRY(dalloc(c, &M32, (size_t)m * m));
+    HIP_TRY(launch_copy_d2f(M, M32, (int64_t)m * m, s));
+  }
+  c->w_last = k;
+  c->lu_w = {m, M, M32};
   return AMG_OK;
 }
 
@@ -869,10 +923,13 @@ int setup_device(amg_ctx* c, hipStream_t s) {
   c->lu_vc = c->lu;
   if (c->opts.cycle != 2) AMG_TRY(form_sub_vcycle(c, s));
   if (c->opts.cycle == 2) {
-    const int ft = c->first_tail, last = nl - 1;
+    const int ft = c->first_tail;
+    c->w_last = nl - 1;
+    c->lu_w = c->lu;
+    AMG_TRY(form_sub_wcycle(c, s));
     for (int k = 0; k < 2; ++k) {
       std::vector<TailOp> ops;
-      tail_visit(ops, ft, k == 0, ft, last, c->opts.m1, c->opts.m2, c->opts.cycle, ft > 0);
+      tail_visit(ops, ft, k == 0, ft, c->w_last, c->opts.m1, c->opts.m2, c->opts.cycle, ft > 0);
       std::vector<int> raw(ops.size() * 4);
       std::memcpy(raw.data(), ops.data(), raw.size() * sizeof(int));
       int* dev = nullptr;

@@ -520,7 +520,9 @@ __global__ __launch_bounds__(kNTT) void k_tail_program(const LevelDev<T>* levels
                                                        Twiddles<T> tw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ LevelDev<T> lvs[kTailMaxLev];
+  __shared__ T warm_sink;
   tail_levels_to_lds(levels, first, last, lvs);
+  coarse_warm<T>(lu, &warm_sink);  // under the twiddle table's loads
   const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);  // its barrier publishes lvs too
   for (int k = 0; k < nops; ++k) {
     const TailOp op = ops[k];

@@ -571,21 +571,24 @@ def test_binding_rejects_bad_tensors():
                                                        (2, 1, 3, 1.0, 0.5), (1, 3, 4, 0.8, 0.6),
                                                        (1, 1, 7, 2 / 3, 2 / 3)])
 @pytest.mark.parametrize("case,N", [(CONST25, 4096), (WEIGHT05, 1024)])
-def test_vcycle_bottom_levels(case, N, m1, m2, coarsest, wpre, wpost):
-    """The V-cycle's levels of at most 255 unknowns (above the coarsest) run as
-    one dense product with the matrix of that sub-cycle, formed at setup from
-    the unit vectors: one V-cycle from zero against the oracle's recursive
-    V-cycle, with several sweep counts, damping factors and coarsest levels
-    (coarsest 2^7: no level qualifies, the plain recursion)."""
-    say("vcycle bottom levels", case[0], N, m1, m2, coarsest, wpre, wpost)
+@pytest.mark.parametrize("cycle", [1, 2])
+def test_vcycle_bottom_levels(case, N, m1, m2, coarsest, wpre, wpost, cycle):
+    """The cycle's levels of at most 255 unknowns (above the coarsest; for
+    W-cycles, below the small-level kernel's first level) run as one dense
+    product with the matrix of that sub-cycle (for W-cycles: of all the visits
+    the level receives per descent), formed at setup from the unit vectors:
+    one V- or W-cycle from zero against the oracle's recursive cycle, with
+    several sweep counts, damping factors and coarsest levels (coarsest 2^7:
+    no level qualifies, the plain recursion)."""
+    say("cycle bottom levels", case[0], N, m1, m2, coarsest, wpre, wpost, cycle)
     H = oracle_hier(case, N, coarsest)
-    opts = dense.Options(m1=m1, m2=m2, omega_pre=wpre, omega_post=wpost)
+    opts = dense.Options(m1=m1, m2=m2, omega_pre=wpre, omega_post=wpost, cycle=cycle)
     b = synthetic.random_vector(2 * N - 1, seed=N + m1 + 10 * m2)
     er = tpx.vcycle(H, b, opts)
     for prec in (B.AMG_FP64, B.AMG_MIXED):
         h = B.amg_setup(case[1], case[3], N,
                         B.amg_default_opts(precision=prec, m1=m1, m2=m2, coarsest_log2=coarsest,
-                                           omega_pre=wpre, omega_post=wpost))
+                                           omega_pre=wpre, omega_post=wpost, cycle=cycle))
         try:
             dt = torch.float64 if prec == B.AMG_FP64 else torch.float32
             e = torch.empty(2 * N - 1, device="cuda", dtype=dt)
