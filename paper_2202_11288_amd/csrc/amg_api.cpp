@@ -25,8 +25,12 @@ namespace {
 // levels with L <= 2^kTailLog run in the one-workgroup tail kernels (amg_device.hpp)
 
 // Levels above the coarsest with at most this many unknowns are folded into
-// one dense operator of the V-cycle below them (form_sub_vcycle).
+// one dense operator of the cycle below them (form_sub_vcycle,
+// form_sub_wcycle).  A W-cycle visits the bottom levels so often that a
+// product with a 511 x 511 matrix still beats the sub-cycles it replaces; a
+// V-cycle visits them once, and 255 is where the product stops paying.
 constexpr int kSubDenseMax = 255;
+constexpr int kSubDenseMaxW = 511;
 
 struct Plan {
   int logL, logL1, logL2, tcols;
@@ -369,8 +373,8 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess, bool band) {
              (int64_t)(kGmMax + 1) * (kGmMax + 6 + 1024) * 8;
   const int64_t mc = (int64_t(2) << o->coarsest_log2) - 1;
   bytes += 2 * mc * mc * 8;
-  if (mc < kSubDenseMax)  // the folded sub-cycle's operator
-    bytes += (int64_t)kSubDenseMax * kSubDenseMax * 8;
+  const int64_t md = o->cycle == 2 ? kSubDenseMaxW : kSubDenseMax;
+  if (mc < md) bytes += md * md * (mixed ? 12 : 8);  // the folded sub-cycle's operator
   bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
   return bytes;
 }
@@ -711,7 +715,7 @@ int form_sub_wcycle(amg_ctx* c, hipStream_t s) {
   const int ft = c->first_tail, last = nl - 1;
   int k = -1;
   for (int l = ft + 1; l < last; ++l)
-    if (2 * c->lv[l].n + 1 <= kSubDenseMax) {
+    if (2 * c->lv[l].n + 1 <= kSubDenseMaxW) {
       k = l;
       break;
     }

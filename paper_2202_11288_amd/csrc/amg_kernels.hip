@@ -435,9 +435,9 @@ __device__ void coarse_solve(const CoarseLU& lu, const T* b, T* u, double* bs) {
 
 // Pulls the matrix coarse_solve will read into this XCD's L2 at kernel start
 // (the large levels have evicted it since the previous cycle; a folded
-// sub-cycle's matrix is up to 520 KB): one word per 128-byte line, with
-// clamped addresses, folded into one value that is stored only if it equals
-// a constant, so that the loads stay live.
+// sub-cycle's matrix is up to 2 MB): one word per 128-byte line, in batches
+// of 8 lines per thread with clamped addresses, folded into one value that is
+// stored only if it equals a constant, so that the loads stay live.
 template <typename T>
 __device__ void coarse_warm(const CoarseLU& lu, T* sink) {
   const char* p = reinterpret_cast<const char*>(lu.ainv);
@@ -448,13 +448,16 @@ __device__ void coarse_warm(const CoarseLU& lu, T* sink) {
       bytes = (long)lu.m * lu.m * 4;
     }
   }
-  constexpr int K = 8;  // 8 * kNTT lines of 128 bytes: 512 KB
+  constexpr int K = 8;
+  constexpr long kBatch = (long)K * kNTT * 128;  // bytes covered per batch
   unsigned acc = 0;
+  for (long base = 0; base < bytes; base += kBatch) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    long off = ((long)threadIdx.x + (long)k * kNTT) * 128;
-    off = off < bytes ? off : bytes - 4;
-    acc ^= *reinterpret_cast<const unsigned*>(p + off);
+    for (int k = 0; k < K; ++k) {
+      long off = base + ((long)threadIdx.x + (long)k * kNTT) * 128;
+      off = off < bytes ? off : bytes - 4;
+      acc ^= *reinterpret_cast<const unsigned*>(p + off);
+    }
   }
   if (acc == 0x5bd1e995u) sink[0] = T(0);
 }
