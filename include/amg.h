@@ -210,11 +210,13 @@ void amg_default_opts(amg_opts_t* o);
  * partial last cell [r h, delta] is integrated exactly when delta/h is not an
  * integer), Galerkin levels by Lemma 3.1 down to 2^coarsest_log2 intervals,
  * per-level circulant spectra (eq. (ccs3.4)) on the device, LU of the
- * coarsest level.  For V-cycles (cycle = 1), the cycle below and including
- * the largest level above the coarsest with at most 255 unknowns is a linear
- * map of that level's right-hand side: setup forms its matrix from the unit
- * vectors (FP64, a few ms) and V-cycles apply it as one dense product (the
- * same operator as the recursion, to rounding).  N must be a power of two with coarsest_log2 < log2 N <= 22
+ * coarsest level.  The cycle below and including the largest level above the
+ * coarsest with at most 255 unknowns (V-cycles), or the visits a level with
+ * at most 511 unknowns receives per descent (W-cycles, below the small-level
+ * kernel's first level), is a linear map of that level's right-hand side:
+ * setup forms its matrix from the unit vectors (FP64, a few ms) and cycles
+ * apply it as one dense product (the same operator as the recursion, to
+ * rounding).  N must be a power of two with coarsest_log2 < log2 N <= 22
  * and 2 <= coarsest_log2; 0 < delta < 1/2 (ignored for AMG_K_GENERATORS).
  * *out receives the handle.  Errors: AMG_EINVAL (bad N, delta, alpha, weights,
  * null pointer, options; inner = AMG_INNER_PCG with a non-symmetric operator),
