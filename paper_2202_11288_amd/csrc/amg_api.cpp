@@ -610,8 +610,11 @@ int vcycle_run(amg_ctx* c, hipStream_t s) {
 
 // r = b - A x on the finest level (FP64), optionally with x += e fused in
 // front; writes the residual-norm partials and runs the stopping test.
+// publish != null: the stop test also writes the state to that pinned host
+// copy (the round ends there).
 int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double tol,
-                   hipStream_t s, bool gm_check = false, bool stall = false) {
+                   hipStream_t s, bool gm_check = false, bool stall = false,
+                   SolveState* publish = nullptr) {
   const LevelRes& L0 = c->lv[0];
   const LevelDev<double> d = L0.dev<double>();
   ColIn<double> in{};
@@ -640,7 +643,8 @@ int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double
     HIP_TRY(launch_gm_check(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s,
                             stall ? 1 : 0));
   else
-    HIP_TRY(launch_finish(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s));
+    HIP_TRY(launch_finish(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s, 0,
+                          publish));
   return AMG_OK;
 }
 
@@ -1272,6 +1276,23 @@ hipError_t round_wait(hipStream_t s) {
   }
 }
 
+// The stationary iteration's round ends with the stop test writing the state
+// to pinned host memory, so the host can watch that copy (the iteration count
+// advanced, or done) and queue the next round before the stream has reported
+// completion; the stream is still queried every so often, so that a failure
+// ends the wait.  Words are written whole, and iter advances only when done
+// stays 0, so either change is a consistent signal.
+hipError_t state_wait(const SolveState* host, int prev_iter, hipStream_t s) {
+  const volatile SolveState* hs = host;
+  for (unsigned k = 1;; ++k) {
+    if (hs->done || hs->iter != prev_iter) return hipSuccess;
+    if ((k & 255) == 0) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e != hipErrorNotReady) return e;
+    }
+  }
+}
+
 // Enqueues the work up to the next stop test; round counts the calls since
 // solve_begin (whose residual and stop test come first).
 int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s, int round) {
@@ -1295,10 +1316,11 @@ int solve_round(amg_t h, const double* b, double* x, double tol, hipStream_t s, 
     const size_t v0 = h->prof.mark(s);
     AMG_TRY(vcycle_run(h, s));
     const size_t v1 = h->prof.mark(s);
-    AMG_TRY(outer_residual(h, b, x, e, tol, s));
+    AMG_TRY(outer_residual(h, b, x, e, tol, s, false, false, h->st_host));
     const size_t v2 = h->prof.mark(s);
     h->prof.span(PK_VCYCLE, v0, v1);
     h->prof.span(PK_OUTER, v1, v2);
+    return AMG_OK;  // the stop test published the state
   }
   HIP_TRY(launch_publish(h->st_dev, h->st_host, s));
   return AMG_OK;
@@ -1355,11 +1377,18 @@ int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream, int
   HIP_TRY(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
   AMG_TRY(solve_begin(h, b, x, tol, s));
+  const bool watch = h->opts.inner == AMG_INNER_VCYCLE;  // its rounds publish their own state
+  int prev_iter = 0;
   for (int round = 0;; ++round) {
-    HIP_TRY(round_wait(s));
+    if (watch && round > 0)
+      HIP_TRY(state_wait(h->st_host, prev_iter, s));
+    else
+      HIP_TRY(round_wait(s));
     if (h->st_host->done) break;
+    prev_iter = h->st_host->iter;
     AMG_TRY(solve_round(h, b, x, tol, s, round));
   }
+  HIP_TRY(round_wait(s));  // the last round complete before its state is read
   return solve_end(h, s, iters, relres);
 }
 

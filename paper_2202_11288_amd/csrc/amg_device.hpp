@@ -182,7 +182,8 @@ hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 // passing the test sets cycle_end instead of done, and the true residual's
 // check (launch_gm_check) decides.
 hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
-                         double* hist, hipStream_t s, int verify = 0);
+                         double* hist, hipStream_t s, int verify = 0,
+                         SolveState* host = nullptr);
 hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s);
 // part[2b] = a.z, part[2b+1] = c.z over chunk b (c may be null); z FP64 or FP32
 template <typename TZ>

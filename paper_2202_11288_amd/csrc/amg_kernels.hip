@@ -690,14 +690,10 @@ __global__ void k_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 }
 
 // Stopping test of the outer iteration (Sec. 5): ||r_i|| / ||r_0|| < tol.
-__global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* part, int npart,
-                                                double tol, int max_iter, double* hist,
-                                                int verify) {
-  __shared__ double red[256 / 64];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < npart; i += 256) v += part[i];
-  const double s = block_sum<double, 256>(v, red);
-  if (threadIdx.x != 0) return;
+// host != null: the state is also written to pinned host memory at the end
+// (the round's last kernel publishes it itself; see k_publish).
+__device__ void finish_state(SolveState* st, double s, double tol, int max_iter, double* hist,
+                             int verify) {
   if (st->done) return;
   const double nrm = sqrt(s);
   if (st->iter == 0) {
@@ -726,6 +722,22 @@ __global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* pa
   }
   if (rel < st->best) st->best = rel;
   if (!st->done && !st->cycle_end) st->iter += 1;
+}
+__global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* part, int npart,
+                                                double tol, int max_iter, double* hist,
+                                                int verify, SolveState* host) {
+  __shared__ double red[256 / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < npart; i += 256) v += part[i];
+  const double s = block_sum<double, 256>(v, red);
+  if (threadIdx.x == 0) finish_state(st, s, tol, max_iter, hist, verify);
+  if (host) {
+    __syncthreads();  // thread 0's state writes before the copy
+    constexpr int W = sizeof(SolveState) / 4;
+    if (threadIdx.x < W)
+      reinterpret_cast<unsigned*>(host)[threadIdx.x] = reinterpret_cast<const unsigned*>(st)[threadIdx.x];
+    __threadfence_system();
+  }
 }
 
 __global__ void k_copy_d2f(const double* a, float* b, int64_t m) {
@@ -1151,8 +1163,9 @@ hipError_t launch_combine(int logL, int logL1, int logL2, const cplx<double>* z1
 }
 
 hipError_t launch_finish(SolveState* st, const double* part, int npart, double tol, int max_iter,
-                         double* hist, hipStream_t s, int verify) {
-  hipLaunchKernelGGL(k_finish, 1, 256, 0, s, st, part, npart, tol, max_iter, hist, verify);
+                         double* hist, hipStream_t s, int verify, SolveState* host) {
+  static_assert(sizeof(SolveState) % 4 == 0 && sizeof(SolveState) / 4 <= 256, "state words");
+  hipLaunchKernelGGL(k_finish, 1, 256, 0, s, st, part, npart, tol, max_iter, hist, verify, host);
   return hipGetLastError();
 }
 
