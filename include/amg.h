@@ -245,8 +245,11 @@ int amg_vcycle(amg_t h, const void* r, void* e, void* stream);
  * ||b - A x||_2 / ||b - A x_0||_2 < tol or max_iter (Sec. 5 stopping rule).
  * b (device, 2N-1 doubles), x (device, in: initial guess, out: solution).
  * iters/relres (host, may be NULL) receive the iteration count and the final
- * relative residual (FP64, computed by the FFT matvec).  Returns AMG_OK,
- * AMG_NOT_CONVERGED or AMG_DIVERGED, or an error code. */
+ * relative residual (FP64, computed by the FFT matvec).  The call returns when
+ * the solve is done (its work is queued on `stream`); between iterations the
+ * calling thread polls (pinned host memory the stop test writes, or the
+ * stream) rather than sleeping, so it keeps one CPU core busy meanwhile.
+ * Returns AMG_OK, AMG_NOT_CONVERGED or AMG_DIVERGED, or an error code. */
 int amg_solve(amg_t h, const double* b, double* x, double tol, void* stream,
               int* iters, double* relres);
 
