@@ -17,6 +17,8 @@
 // below them in one workgroup with the FFT and its twiddles in LDS.
 #include "kernel_common.hpp"
 
+#include <type_traits>
+
 namespace amg {
 
 constexpr int kET = (1 << kTailLog) / kNTT;  // elements per thread, tail kernels
@@ -159,7 +161,25 @@ template <typename T>
 __device__ void tail_fft_spectral(const LevelDev<T>& lv, const TailLds<T>& s, const TailSpec<T>& sp) {
   const int L = 1 << lv.logL;
   const FftGeom g{lv.logL, 0, 0, 0, kTailLog, false};
-  lds_fft<T, kET, kNTT, false>(s.z, g, s.tw);
+  // FP32: the two largest tail levels (most of the small-level kernel's FFT
+  // work) with the geometry as compile-time constants, so the Stockham index
+  // arithmetic folds; the others share one runtime-geometry copy (FP64 keeps
+  // the one copy: the specialised ones need more registers than it has left)
+  auto fft = [&](auto inv) {
+    constexpr bool INV = decltype(inv)::value;
+    if (sizeof(T) == 8) {
+      lds_fft<T, kET, kNTT, INV>(s.z, g, s.tw);
+    } else if (lv.logL == kTailLog) {
+      constexpr FftGeom gc{kTailLog, 0, 0, 0, kTailLog, false};
+      lds_fft<T, kET, kNTT, INV>(s.z, gc, s.tw);
+    } else if (lv.logL == kTailLog - 1) {
+      constexpr FftGeom gc{kTailLog - 1, 0, 0, 0, kTailLog, false};
+      lds_fft<T, kET, kNTT, INV>(s.z, gc, s.tw);
+    } else {
+      lds_fft<T, kET, kNTT, INV>(s.z, g, s.tw);
+    }
+  };
+  fft(std::false_type{});
 #pragma unroll
   for (int k = 0; k < kTailP; ++k) {
     const int f = threadIdx.x + k * kNTT;
@@ -173,7 +193,7 @@ __device__ void tail_fft_spectral(const LevelDev<T>& lv, const TailLds<T>& s, co
     }
   }
   __syncthreads();
-  lds_fft<T, kET, kNTT, true>(s.z, g, s.tw);
+  fft(std::true_type{});
 }
 
 constexpr int kTailJ = (1 << (kTailLog - 1)) / kNTT;  // v/w slots per thread (n < L/2)
