@@ -131,7 +131,13 @@ def pmc_driver(args):
     print("pmc driver done", flush=True)
 
 
-def traffic_summary(fetch_csv, write_csv, logN):
+def traffic_workload(args):
+    """The workload a traffic measurement belongs to (the --pmc-driver run)."""
+    return {"logN": args.logN, "kernel": args.kernel, "delta": args.delta,
+            "alpha": args.alpha if args.kernel == "fractional" else None}
+
+
+def traffic_summary(fetch_csv, write_csv, logN, workload):
     """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the finest-level FP32
     FFT pass kernels, each scaled by the factor that maps the same counter's
     reading for the plain copy onto the copy's known bytes; per sweep = the
@@ -174,6 +180,7 @@ def traffic_summary(fetch_csv, write_csv, logN):
                       "bytes_per_sweep": round(total),
                       "per_pass_bytes": {k: round(sum(v) * scale / sweeps) for k, v in sel.items()}}
     res = {"kernel": f"fp32 finest-level FFT matvec sweep (3 passes), N=2^{logN}",
+           "workload": workload,
            "source_hash": kernel_source_hash(),
            "fetch": out["fetch"], "write": out["write"],
            "traffic_bytes_per_sweep": out["fetch"]["bytes_per_sweep"] + out["write"]["bytes_per_sweep"],
@@ -190,15 +197,16 @@ def traffic_summary(fetch_csv, write_csv, logN):
     print(json.dumps(res, indent=1))
 
 
-def measured_traffic():
+def measured_traffic(args):
     """Bytes per finest FP32 sweep from the committed counter summary, or None
-    when it is missing or was taken on other kernel sources."""
+    when it is missing, was taken on other kernel sources or on another
+    workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != traffic_workload(args):
         return None
     return t.get("traffic_bytes_per_sweep")
 
@@ -597,7 +605,8 @@ def main():
         rocprof_summary(args.rocprof_summary)
         return
     if args.traffic_summary:
-        traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.logN)
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.logN,
+                        traffic_workload(args))
         return
     if args.pmc_driver:
         pmc_driver(args)
@@ -662,7 +671,7 @@ def main():
         t64 = pmx.get("fp64_finest_sweep", (0, 0.0))[1]
         roof = roof32 if t32 >= t64 else sweep_roofline(pmx, n, "fp64", 8, sym)
         if roof is roof32 and roof32 is not None:
-            tb = measured_traffic()
+            tb = measured_traffic(args)
             roof32["traffic"] = tb
             if tb:
                 roof32["traffic_note"] = ("HBM bytes per sweep from rocprofv3 FETCH_SIZE + WRITE_SIZE, "

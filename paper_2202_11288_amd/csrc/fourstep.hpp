@@ -12,10 +12,12 @@
 // row pair); the largest levels use column tiles of 2 kCap4 on twice the
 // threads, so that each row segment of a real vector spans 32 bytes rather
 // than 16 (the column passes there are bound by the number of distinct
-// cache lines their loads touch).  The per-thread element counts are template parameters (EPT
-// column elements, KR row elements per row) so that every global load of a
-// pass is issued in compile-time batches into registers, with clamped
-// addresses and masked values, before any of them is used.  Internal header.
+// cache lines their loads touch), and L = 2^23 also row pairs of 2 kCap4
+// (rows of 4096 points, so that its columns of 2048 still come in tiles of 4).
+// The per-thread element counts are template parameters (EPT column
+// elements, KR row elements per row) so that every global load of a pass is
+// issued in compile-time batches into registers, with clamped addresses and
+// masked values, before any of them is used.  Internal header.
 #pragma once
 
 #include "kernel_common.hpp"
@@ -263,15 +265,15 @@ __device__ __forceinline__ void spec_pair(const LevelDev<T>& lv, Lds<T> lds, int
 // order at the end) plus o w_o, and a snapshot of the input's w_o (pass 3 may
 // update u[n] in place (Jacobi) while its other blocks still need the value
 // the product used).
-template <typename T>
+template <typename T, int NT = kNT4>
 __device__ __forceinline__ T wo_partial(const T* part, int npart) {
   T v = 0;
-  for (int i = threadIdx.x; i < npart; i += kNT4) v += part[i];
+  for (int i = threadIdx.x; i < npart; i += NT) v += part[i];
   return v;
 }
-template <typename T>
+template <typename T, int NT = kNT4>
 __device__ __forceinline__ void finish_wo(const LevelDev<T>& lv, T v, T* red, const T* xin) {
-  const T s = block_sum<T, kNT4>(v, red);
+  const T s = block_sum<T, NT>(v, red);
   if (threadIdx.x == 0) {
     const T wo = xin[lv.n];
     lv.scal[0] = s + lv.o * wo;
@@ -279,16 +281,19 @@ __device__ __forceinline__ void finish_wo(const LevelDev<T>& lv, T v, T* red, co
   }
 }
 
-// Row pair with L1 = 16 kNT4 / 2 (each thread owns one radix-16 butterfly of
+// Row pair with L1 = 16 NT / 2 (each thread owns one radix-16 butterfly of
 // the last pass: row s = tid / (L1/16), j0 = tid mod (L1/16), positions
 // p = j0 + e L1/16).  Loads feed the first FFT pass directly; the spectral
 // product exchanges the partner bins through LDS once; the last inverse pass
-// feeds the twiddle and the stores.
-template <typename T, bool SPECTRAL, bool SYM>
+// feeds the twiddle and the stores.  NT = kNT4: rows of 2048 points;
+// NT = 2 kNT4: rows of 4096 (the largest level, whose columns then stay short
+// enough for tiles of 4 columns).
+template <typename T, bool SPECTRAL, bool SYM, int NT = kNT4>
 __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds, cplx<T>* buf,
                                               const Twiddles<T>& tw, int item) {
-  constexpr int Q = 16 * kNT4 / 2 / 16;  // L1/16 butterflies per row
-  constexpr int kLog1 = 11;               // log2 L1: the geometry is a compile-time constant
+  constexpr int Q = 16 * NT / 2 / 16;  // L1/16 butterflies per row
+  // log2 L1: the geometry is a compile-time constant
+  constexpr int kLog1 = NT == kNT4 ? 11 : 12;
   static_assert((1 << kLog1) == 16 * Q, "row length of the register row pass");
   constexpr int L1 = 1 << kLog1;
   const int L2 = 1 << lv.logL2;
@@ -312,7 +317,7 @@ __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds,
   };
   if (kEarly && SPECTRAL && SYM) load_spec();
   const FftGeom g{kLog1, 1, kLog1, 0, kTwLog, false};
-  fft_reg16<T, kNT4, false>(a, lds, g, s, j0, tw.base);
+  fft_reg16<T, NT, false>(a, lds, g, s, j0, tw.base);
   if (!kEarly && SPECTRAL && SYM) load_spec();
   if constexpr (!SPECTRAL) {
 #pragma unroll
@@ -355,7 +360,7 @@ __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds,
       }
     }
     __syncthreads();  // partner reads done before the inverse FFT writes LDS
-    fft_reg16<T, kNT4, true>(a, lds, g, s, j0, tw.base);
+    fft_reg16<T, NT, true>(a, lds, g, s, j0, tw.base);
     twiddle_run_mul<T, 16, true>(tw, lv.logL, j0 * k2, Q * k2, a);
 #pragma unroll
     for (int e = 0; e < 16; ++e) stg(buf + row + j0 + e * Q, a[e]);
@@ -502,6 +507,20 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
     }
     if (item == 0) finish_wo(lv, wpart, red, xin);
   }
+}
+
+// Pass 2 for rows of 4096 points: the register row pass on 2 kNT4 threads.
+template <typename T, bool SPECTRAL, bool SYM>
+__global__ __launch_bounds__(2 * kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+void k_row_w(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
+  constexpr int NT = 2 * kNT4;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
+  __shared__ T red[NT / 64];
+  const int item = blockIdx.x;
+  const T wpart = (SPECTRAL && item == 0) ? wo_partial<T, NT>(part, npart) : T(0);
+  row_pair_regs<T, SPECTRAL, SYM, NT>(lv, lds, buf, tw, item);
+  if (SPECTRAL && item == 0) finish_wo<T, NT>(lv, wpart, red, xin);
 }
 
 // ---------------------------------------------------------------------------
@@ -762,6 +781,9 @@ hipError_t row_kr(int kr, int grid, size_t lds, hipStream_t s, const LevelDev<T>
     case 2: return launch_lds(k_row<T, SPECTRAL, SYM, 2, 9>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
     case 4: return launch_lds(k_row<T, SPECTRAL, SYM, 4, 10>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
     case 8: return launch_lds(k_row<T, SPECTRAL, SYM, 8>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
+    case 16:
+      return launch_lds(k_row_w<T, SPECTRAL, SYM>, grid, 2 * kNT4, lds, s, lv, buf, tw, part, npart,
+                        xin);
     default: return hipErrorInvalidValue;
   }
 }
@@ -809,7 +831,7 @@ hipError_t launch_row(int spectral, const LevelDev<T>& lv, cplx<T>* buf,
                            const Twiddles<T>& tw, const T* part, int npart, const T* xin,
                            hipStream_t s) {
   const int L1 = 1 << lv.logL1;
-  if (2 * L1 > kCap4 || lv.logL2 < 1) return hipErrorInvalidValue;
+  if (2 * L1 > kCapWide || lv.logL2 < 1) return hipErrorInvalidValue;
   const int kr = L1 >= kNT4 ? L1 / kNT4 : 1;
   const int grid = (1 << lv.logL2) / 2;
   const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(2 * L1);

@@ -90,12 +90,13 @@ def test_level_matvec_every_level(case, N):
         B.amg_destroy(h)
 
 
-@pytest.mark.parametrize("N", [512, 16384, 2 ** 20, 2 ** 21])
+@pytest.mark.parametrize("N", [512, 16384, 2 ** 20, 2 ** 21, 2 ** 22])
 def test_matvec_general_blocks(N):
     """Caller-supplied non-symmetric blocks (AMG_K_GENERATORS): the general
     two-complex-spectra path against dense (small N) / oracle FFT (large N;
     2^20 runs the full-tile four-step kernels with register first/last passes,
-    2^20 and 2^21 the wide column tiles of the largest levels)."""
+    2^20 and 2^21 the wide column tiles of the largest levels, 2^22 rows of
+    4096 points)."""
     say("general_blocks", N)
     gA, gB, gC, gD = synthetic.random_tpx_arrays(N - 1, seed=N, decay=0.001)
     gen = np.ascontiguousarray(np.concatenate([gA, gB, gC, gD]))
@@ -490,6 +491,36 @@ def test_pcg_batch_matches_solo():
     finally:
         for h in hs:
             B.amg_destroy(h)
+
+
+@pytest.mark.parametrize("case", [CONST25, WEIGHT05], ids=lambda c: c[0])
+def test_rows_of_4096_at_2_22(case):
+    """N = 2^22: the finest level (L = 2^23) runs rows of 4096 points (the
+    register row pass on 512 threads) and column tiles of 4 x 2048.  The FP64
+    matvec against the oracle's FFT matvec (every output), and one FP32
+    V-cycle against the oracle's FP64 V-cycle (FP32 rounding through FFTs of
+    up to 2^23 points and the exact coarsest solve)."""
+    N = 2 ** 22
+    say("rows of 4096", case[0], N)
+    h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(precision=B.AMG_MIXED))
+    try:
+        H = oracle_hier(case, N)
+        x = synthetic.random_vector(2 * N - 1, seed=41)
+        y = torch.empty(2 * N - 1, device="cuda", dtype=torch.float64)
+        B.amg_matvec(h, dev(x), y)
+        yr = H.matvec(x)
+        err = np.abs(host(y) - yr).max() / np.abs(yr).max()
+        say("matvec err", err)
+        assert err < 1e-13, err
+        r = synthetic.random_vector(2 * N - 1, seed=43)
+        e = torch.empty(2 * N - 1, device="cuda", dtype=torch.float32)
+        B.amg_vcycle(h, dev(r, torch.float32), e)
+        er = tpx.vcycle(H, r)
+        err = np.abs(host(e) - er).max() / np.abs(er).max()
+        say("fp32 vcycle err", err)
+        assert err < 1e-4, err
+    finally:
+        B.amg_destroy(h)
 
 
 def test_fractional_2_22_mixed_pcg():
