@@ -89,7 +89,7 @@ def rocprof_summary(path):
     print(f"total kernel time {tot / 1e3:.2f} ms over {len(rows)} dispatches")
 
 
-COPY_BYTES = 256 << 20  # the driver's plain copy: reads and writes this many bytes
+COPY_BYTES = 256 << 20  # the PMC run's plain copy: reads and writes this many bytes
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp32_finest_sweep_N2e20.json")
 KERNEL_SOURCES = ["fourstep.hpp", "fourstep_f32.hip", "fft_lds.hpp", "kernel_common.hpp",
                   "amg_device.hpp"]
@@ -186,11 +186,11 @@ def traffic_summary(fetch_csv, write_csv, logN, workload):
            "traffic_bytes_per_sweep": out["fetch"]["bytes_per_sweep"] + out["write"]["bytes_per_sweep"],
            "commands": [
                "cd /tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv "
-               "-d <repo>/gpurun_out/pmc_fetch -o run -- python3 <repo>/bench.py --pmc-driver",
+               "-d <out>/pmc_fetch -o run -- python3 <repo>/bench.py --pmc-driver",
                "cd /tmp && timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv "
-               "-d <repo>/gpurun_out/pmc_write -o run -- python3 <repo>/bench.py --pmc-driver",
-               "python bench.py --traffic-summary gpurun_out/pmc_fetch/run_counter_collection.csv "
-               "gpurun_out/pmc_write/run_counter_collection.csv"]}
+               "-d <out>/pmc_write -o run -- python3 <repo>/bench.py --pmc-driver",
+               "python bench.py --traffic-summary <out>/pmc_fetch/run_counter_collection.csv "
+               "<out>/pmc_write/run_counter_collection.csv"]}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(res, f, indent=1)
@@ -613,8 +613,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
-              "part of it (each solve is independent -- shard instances across GPUs instead)",
+        print("bench.py measures one MI355X; runs on more than one GPU are not "
+              "supported (each solve is independent -- shard instances across GPUs instead)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -52,7 +52,7 @@ typedef enum {
   AMG_EINVAL = -1,       /* bad argument (see each function)                     */
   AMG_ENOMEM = -2,       /* device or host allocation failed                     */
   AMG_EHIP = -3,         /* a HIP runtime call failed                            */
-  AMG_ENOTSUP = -4       /* valid request this build does not implement          */
+  AMG_ENOTSUP = -4       /* valid request the library does not implement        */
 } amg_status;
 
 typedef enum {
@@ -90,7 +90,7 @@ typedef enum {
 typedef struct {
   int kind;          /* amg_kernel_kind                                      */
   double alpha;      /* AMG_K_FRACTIONAL only                                */
-  double wl, wr;     /* AMG_K_WEIGHTED only (the survey's variant: 1.2, 0.8) */
+  double wl, wr;     /* AMG_K_WEIGHTED only (e.g. 1.2, 0.8)                 */
   const double* gen; /* AMG_K_GENERATORS only (host, copied during setup)    */
   int scheme;        /* AMG_SCHEME_SHIFTED (default) or AMG_SCHEME_STANDARD  */
   double gamma;      /* AMG_K_WEAKLY_SINGULAR only: exponent, 0 <= gamma < 1  */

@@ -20,7 +20,7 @@ Follows Sec. 2.2 of Chen, Cao and Serra-Capizzano (arXiv 2202.11288):
   interior rows to the exterior points (`assemble_with_exterior`, the content
   of eqs. (rightside1), (rightside2)).
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
 
 * kernels are normalised so that int gamma(s) s^2 ds = 1: constant
   c = 3/(2 delta^3); "weighted" = c*wl for s < 0 and c*wr for s > 0;

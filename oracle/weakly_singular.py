@@ -27,7 +27,7 @@ from the closed-form moments of |s|^-gamma s^i, evaluated with mpmath at 50
 digits (the differences of large powers at far cells need it).  Times
 h^(1-gamma).
 
-Readings (the design doc lists them): the printed closed forms of m_k, q_k, n_k,
+Readings: the printed closed forms of m_k, q_k, n_k,
 n_0, m_0 and p_k (k >= 1) equal these weights times eta h^(1-gamma); the
 printed p_0 and eta_{i/2} (i >= 2, the vector K) do not (the pins show the
 product-integration values instead, which reproduce the paper's Table TT03b).

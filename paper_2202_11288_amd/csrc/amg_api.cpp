@@ -1016,7 +1016,7 @@ const char* amg_strerror(int st) {
     case AMG_EINVAL: return "invalid argument";
     case AMG_ENOMEM: return "out of memory";
     case AMG_EHIP: return "HIP runtime error";
-    case AMG_ENOTSUP: return "not supported by this build";
+    case AMG_ENOTSUP: return "not supported by this library";
     default: return "unknown status";
   }
 }

@@ -90,7 +90,7 @@ std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2) {
   while (N > 0 && (int64_t(1) << K) < N) ++K;
   if (coarsest_log2 < 2) e << "coarsest_log2 must be >= 2; ";
   if (K <= coarsest_log2) e << "need log2(N) > coarsest_log2; ";
-  if (K > 22) e << "log2(N) <= 22 in this build; ";
+  if (K > 22) e << "log2(N) <= 22 is supported; ";
   if (k.kind < 0 || k.kind > 4) e << "unknown kernel kind; ";
   if (k.kind == K_WEAKLY_SINGULAR) {
     if (!(k.gamma >= 0.0 && k.gamma < 1.0)) e << "weakly singular kernel needs 0 <= gamma < 1; ";
