@@ -50,11 +50,12 @@ Plan plan_level(int64_t n) {
     return p;
   }
   // rows of L1 <= kCap4/2 complex (two rows per workgroup: 64 KB of LDS for
-  // FP64), columns of L2 in tiles of T columns with T*L2 <= kCap4.  L = 2^23
-  // takes rows of 4096 (a row pair of 2 kCap4 on twice the threads): with
-  // rows of 2048 its columns of 4096 would come in tiles of 2, whose 8-byte
-  // row segments made the column passes line-bound
-  p.logL1 = std::min(12, (logL + 1) / 2);
+  // FP64), columns of L2 in tiles of T columns with T*L2 <= kCap4.  L >= 2^22
+  // take rows of 4096 (a row pair of 2 kCap4 on twice the threads): with rows
+  // of 2048 the columns of L = 2^23 would come in tiles of 2 (8-byte row
+  // segments, which made its column passes line-bound) and those of L = 2^22
+  // in tiles of 4 rather than 8
+  p.logL1 = logL >= 22 ? 12 : std::min(11, (logL + 1) / 2);
   p.logL2 = logL - p.logL1;
   int t = std::max(1, std::min(16, kCap4 >> p.logL2));
   while (t > 4 && ((1 << p.logL1) / t) < 256) t >>= 1;

@@ -12,8 +12,8 @@
 // row pair); the largest levels use column tiles of 2 kCap4 on twice the
 // threads, so that each row segment of a real vector spans 32 bytes rather
 // than 16 (the column passes there are bound by the number of distinct
-// cache lines their loads touch), and L = 2^23 also row pairs of 2 kCap4
-// (rows of 4096 points, so that its columns of 2048 still come in tiles of 4).
+// cache lines their loads touch), and L >= 2^22 also row pairs of 2 kCap4
+// (rows of 4096 points, so that their columns come in tiles of 8 or 4).
 // The per-thread element counts are template parameters (EPT column
 // elements, KR row elements per row) so that every global load of a pass is
 // issued in compile-time batches into registers, with clamped addresses and
@@ -286,8 +286,8 @@ __device__ __forceinline__ void finish_wo(const LevelDev<T>& lv, T v, T* red, co
 // p = j0 + e L1/16).  Loads feed the first FFT pass directly; the spectral
 // product exchanges the partner bins through LDS once; the last inverse pass
 // feeds the twiddle and the stores.  NT = kNT4: rows of 2048 points;
-// NT = 2 kNT4: rows of 4096 (the largest level, whose columns then stay short
-// enough for tiles of 4 columns).
+// NT = 2 kNT4: rows of 4096 (the levels with L >= 2^22, whose columns then
+// stay short enough for wide tiles of 8 or 4 columns).
 template <typename T, bool SPECTRAL, bool SYM, int NT = kNT4>
 __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds, cplx<T>* buf,
                                               const Twiddles<T>& tw, int item) {
