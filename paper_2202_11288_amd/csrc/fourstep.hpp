@@ -510,8 +510,10 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
 }
 
 // Pass 2 for rows of 4096 points: the register row pass on 2 kNT4 threads.
+// The FP32 symmetric form fits two workgroups per CU (70 KB of LDS each).
 template <typename T, bool SPECTRAL, bool SYM>
-__global__ __launch_bounds__(2 * kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(2 * kNT4)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && SYM ? 4 : 2)))
 void k_row_w(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
   constexpr int NT = 2 * kNT4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
