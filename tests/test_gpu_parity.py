@@ -496,8 +496,9 @@ def test_pcg_batch_matches_solo():
 @pytest.mark.parametrize("case", [CONST25, WEIGHT05], ids=lambda c: c[0])
 def test_rows_of_4096_at_2_22(case):
     """N = 2^22: the finest level (L = 2^23) runs rows of 4096 points (the
-    register row pass on 512 threads) and column tiles of 4 x 2048.  The FP64
-    matvec against the oracle's FFT matvec (every output), and one FP32
+    register row pass on 512 threads) and column tiles of 4 x 2048, level 1
+    (L = 2^22) rows of 4096 and column tiles of 8 x 1024.  The FP64 matvec of
+    both levels against the oracle's FFT matvec (every output), and one FP32
     V-cycle against the oracle's FP64 V-cycle (FP32 rounding through FFTs of
     up to 2^23 points and the exact coarsest solve)."""
     N = 2 ** 22
@@ -511,6 +512,14 @@ def test_rows_of_4096_at_2_22(case):
         yr = H.matvec(x)
         err = np.abs(host(y) - yr).max() / np.abs(yr).max()
         say("matvec err", err)
+        assert err < 1e-13, err
+        m1 = B.amg_level_size(h, 1)
+        x1 = synthetic.random_vector(m1, seed=42)
+        y1 = torch.empty(m1, device="cuda", dtype=torch.float64)
+        B.amg_level_matvec(h, 1, dev(x1), y1)
+        yr1 = H.levels[1].matvec(x1)
+        err = np.abs(host(y1) - yr1).max() / np.abs(yr1).max()
+        say("level-1 matvec err", err)
         assert err < 1e-13, err
         r = synthetic.random_vector(2 * N - 1, seed=43)
         e = torch.empty(2 * N - 1, device="cuda", dtype=torch.float32)
