@@ -162,14 +162,17 @@ def traffic_summary(fetch_csv, write_csv, logN, workload):
         big = max(copies)
         scale = COPY_BYTES / big
         # the finest level's FP32 passes: the wide (512-thread) column tiles and
-        # the row pass on rows of 2048 points (KR = 8); the level below shares
-        # the row pass's grid size, so the template arguments decide
+        # the row pass on rows of 2048 points (KR = 8); other levels may share
+        # the template arguments or the grid size, not both: the largest grid
+        # among the matching instances is the finest level's
         finest = {"k_col_fwd": ("amg::k_col_fwd<float", ", 16, 512,"),
                   "k_row": ("amg::k_row<float", ", 8, 0>"),
                   "k_col_inv": ("amg::k_col_inv<float", ", 16, 512,")}
-        sel = {kind: [x for (name, _), vals in per.items()
-                      if name.startswith(pre) and tag in name for x in vals]
-               for kind, (pre, tag) in finest.items()}
+        sel = {}
+        for kind, (pre, tag) in finest.items():
+            keys = [(name, g) for (name, g) in per if name.startswith(pre) and tag in name]
+            gmax = max((g for _, g in keys), default=0)
+            sel[kind] = [x for (name, g) in keys if g == gmax for x in per[(name, g)]]
         sweeps = len(sel["k_row"])
         if not sweeps or any(len(v) != sweeps for v in sel.values()):
             raise SystemExit(f"{counter}: finest-level dispatch counts differ: "

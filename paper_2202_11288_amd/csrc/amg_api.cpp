@@ -55,7 +55,7 @@ Plan plan_level(int64_t n) {
   // of 2048 the columns of L = 2^23 would come in tiles of 2 (8-byte row
   // segments, which made its column passes line-bound) and those of L = 2^22
   // in tiles of 4 rather than 8
-  p.logL1 = logL >= 22 ? 12 : std::min(11, (logL + 1) / 2);
+  p.logL1 = logL >= 22 ? 12 : (logL == 20 ? 11 : std::min(11, (logL + 1) / 2));
   p.logL2 = logL - p.logL1;
   int t = std::max(1, std::min(16, kCap4 >> p.logL2));
   while (t > 4 && ((1 << p.logL1) / t) < 256) t >>= 1;

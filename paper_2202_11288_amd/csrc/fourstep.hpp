@@ -709,6 +709,9 @@ hipError_t col_fwd_ept(int ept, int grid, size_t lds, hipStream_t s, const Level
       if (lv.logL2 == 10)
         return launch_lds(k_col_fwd<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, in, buf, tw,
                           part);
+      if (lv.logL2 == 9)
+        return launch_lds(k_col_fwd<T, MODE, 16, kNT4, 9>, grid, kNT4, lds, s, lv, in, buf, tw,
+                          part);
       return launch_lds(k_col_fwd<T, MODE, 16>, grid, kNT4, lds, s, lv, in, buf, tw, part);
     case 32:
       switch (lv.logL2) {
@@ -752,6 +755,9 @@ hipError_t col_inv_ept(int ept, int grid, size_t lds, hipStream_t s, const Level
     case 16:
       if (lv.logL2 == 10)
         return launch_lds(k_col_inv<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, out, buf, tw,
+                          part);
+      if (lv.logL2 == 9)
+        return launch_lds(k_col_inv<T, MODE, 16, kNT4, 9>, grid, kNT4, lds, s, lv, out, buf, tw,
                           part);
       return launch_lds(k_col_inv<T, MODE, 16>, grid, kNT4, lds, s, lv, out, buf, tw, part);
     case 32:
