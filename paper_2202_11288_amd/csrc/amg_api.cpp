@@ -54,7 +54,8 @@ Plan plan_level(int64_t n) {
   // take rows of 4096 (a row pair of 2 kCap4 on twice the threads): with rows
   // of 2048 the columns of L = 2^23 would come in tiles of 2 (8-byte row
   // segments, which made its column passes line-bound) and those of L = 2^22
-  // in tiles of 4 rather than 8
+  // in tiles of 4 rather than 8.  L = 2^20 takes rows of 2048 for the same
+  // reason: columns of 512 in tiles of 8 rather than columns of 1024 in 4
   p.logL1 = logL >= 22 ? 12 : (logL == 20 ? 11 : std::min(11, (logL + 1) / 2));
   p.logL2 = logL - p.logL1;
   int t = std::max(1, std::min(16, kCap4 >> p.logL2));
