@@ -193,6 +193,24 @@ typedef struct {
    arguments, fewer launch gaps).  Set this flag when the caller captures the
    solve into a graph of its own.  Profiled handles always launch directly. */
 #define AMG_FLAG_EAGER 4
+/* Form the outer FP64 residual b - A x (the stopping rule's measure, and the
+   refinement's right-hand side) in split form.  The finest matrix is, in the
+   interleaved order of the collocation points, the row stencil W of each
+   point cut to the interior columns (eq. (ccs2.6)); its entries within 64
+   half-steps are applied in difference form
+     sum_{0<|k|<=64} W(k) (x_{s+k} - x_s) + R_s x_s,
+   R_s = the row's near entries summed in long double at setup, and only the
+   entries beyond 64 half-steps go through the FFT (their own spectra).  A
+   plain FP64 FFT evaluation of b - A x carries an error of about
+   eps |A| |x|, which for kernels with large near-field weights (the
+   fractional kernel at large N) exceeds 1e-10 |b|; the split form's error is
+   that of the small far-field entries and of the differences of neighbouring
+   values (about 1e-12 |b| at N = 2^22, fractional alpha = 0.4).  Constant,
+   weighted and fractional kernels (AMG_ENOTSUP otherwise); no effect for
+   N < 2^11, whose finest level runs in the small-level kernels.  Costs one
+   near-field pass (129 terms per unknown) per outer residual and FP64
+   spectra of the far field. */
+#define AMG_FLAG_ACCURATE_RESIDUAL 8
 
 /* Per-kernel timing accumulated while AMG_FLAG_PROFILE is set. */
 typedef struct {
@@ -228,10 +246,32 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N,
  * alias).  Errors: AMG_EINVAL (null), AMG_EHIP. */
 int amg_matvec(amg_t h, const double* x, double* y, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): y = A x on the finest level, the
+ * same kernels and arithmetic as amg_matvec (bitwise the same result), with
+ * the FFT work buffer, the block partials and the w_o scalars taken from a
+ * static device array of the library (8 MiB + 32 KiB per device, held until
+ * the process ends) instead of the handle's work memory.  Calls no hipMalloc,
+ * hipFree or other allocating routine.  Limit: N <= 2^18 (AMG_EINVAL above;
+ * with AMG_DEBUG set the reason goes to stderr).  Every call on a device
+ * shares that device's array: calls that overlap on one device (different
+ * streams, threads or handles) race.  x, y device, 2N-1 doubles, must not
+ * alias.  Errors: AMG_EINVAL, AMG_EHIP. */
+int amg_matvec_noalloc(amg_t h, const double* x, double* y, void* stream);
+
 /* y = A_level x for level `level` (0 = finest, amg_num_levels()-1 =
  * coarsest) in FP64; x, y device, amg_level_size(level) doubles.  Exposes
  * every level's FFT matvec for verification.  Errors: AMG_EINVAL. */
 int amg_level_matvec(amg_t h, int level, const double* x, double* y, void* stream);
+
+/* y = A_level x in FP32, with the FP32 spectra, Cross vectors and FFTs the
+ * FP32 V-cycle of an AMG_MIXED handle uses (Sec. 3.2, eq. (ccs3.4)):
+ * the same kernels as amg_level_matvec, instantiated for float.  x, y
+ * device, amg_level_size(level) floats, must not alias.  Exposes the FP32
+ * FFT matvec of every level for verification (its error grows like
+ * eps_32 log2 L).  Errors: AMG_EINVAL (null, aliasing, bad level, or a
+ * handle not set up with AMG_MIXED), AMG_EHIP. */
+int amg_level_matvec_f32(amg_t h, int level, const float* x, float* y, void* stream);
 
 /* e = B_K r: one V-cycle of Algorithm 2 from a zero initial guess.  With
  * AMG_FP64, r and e are double*; with AMG_MIXED they are float* (the

@@ -286,6 +286,57 @@ class Level:
         return np.concatenate([yv, [yo], yw]) + T.band_matvec(u)
 
 
+def residual_extended(T: TpX, b, x):
+    """b - A x for the level T in extended precision (x86 80-bit long
+    double, unit roundoff 5.4e-20): the definition of the residual of the
+    operator whose FP64 generators and Cross data T holds, evaluated with the
+    same circulant embedding as `Level.matvec` (eq. (ccs3.4)) but with every
+    step, the spectra included, in long double.  b and x are FP64 (or long
+    double) vectors of T.size entries.  Returns the residual as a long
+    double array; its norm relative to ||b|| is the stopping rule's measure
+    (Sec. 5) free of FP64's evaluation floor eps |A| |x|.  Pinned against
+    50-digit exact dense products at tiny N and against the FP64 FFT matvec
+    within that matvec's own error at large N."""
+    ld = np.longdouble
+    n = T.n
+    L = 2 * (n + 1)
+
+    def spec(g):
+        g = np.asarray(g, dtype=ld)
+        col = np.zeros(L, dtype=ld)
+        col[:n] = g[n - 1::-1]
+        if n > 1:
+            col[L - (n - 1):] = g[n:][::-1]
+        return scipy.fft.rfft(col)
+
+    def apply(S, X):
+        return scipy.fft.irfft(S * X, n=L)[:n]
+
+    x = np.asarray(x, dtype=ld)
+    b = np.asarray(b, dtype=ld)
+    v, wo, wb = x[:n], x[n], x[n + 1:]
+    V = scipy.fft.rfft(v, n=L)
+    W = scipy.fft.rfft(wb, n=L)
+    p, q, xi, zeta = (np.asarray(a, dtype=ld) for a in (T.p, T.q, T.xi, T.zeta))
+    yv = apply(spec(T.a), V) + apply(spec(T.b), W) + p * wo
+    yw = apply(spec(T.c), V) + apply(spec(T.d), W) + xi * wo
+    yo = np.dot(q, v) + ld(T.o) * wo + np.dot(zeta, wb)
+    y = np.concatenate([yv, [yo], yw])
+    if T.band is not None:
+        s_, m_, p_ = (np.asarray(a, dtype=ld) for a in T.band)
+        y += m_ * x
+        y[1:] += s_[1:] * x[:-1]
+        y[:-1] += p_[:-1] * x[1:]
+    return b - y
+
+
+def relres_extended(T: TpX, b, x) -> float:
+    """||b - A x||_2 / ||b||_2 with the residual from `residual_extended`."""
+    r = residual_extended(T, b, x)
+    bl = np.asarray(b, dtype=np.longdouble)
+    return float(np.sqrt(np.dot(r, r)) / np.sqrt(np.dot(bl, bl)))
+
+
 def restrict(r):
     """1/4 [1 2 1] stride 2 on the block-ordered vector (Sec. 3.1)."""
     return 0.25 * (r[0:-2:2] + 2.0 * r[1:-1:2] + r[2::2])

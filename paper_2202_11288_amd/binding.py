@@ -24,6 +24,7 @@ AMG_FP64, AMG_MIXED = 0, 1
 AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2
 AMG_FLAG_EAGER = 4
+AMG_FLAG_ACCURATE_RESIDUAL = 8
 AMG_INNER_VCYCLE, AMG_INNER_PCG, AMG_INNER_GMRES = 0, 1, 2
 AMG_SCHEME_SHIFTED, AMG_SCHEME_STANDARD = 0, 1
 
@@ -73,7 +74,9 @@ def _load():
         "amg_setup": (I, [ctypes.POINTER(amg_kernel_t), D, I64, ctypes.POINTER(amg_opts_t), P,
                           ctypes.POINTER(P)]),
         "amg_matvec": (I, [P, P, P, P]),
+        "amg_matvec_noalloc": (I, [P, P, P, P]),
         "amg_level_matvec": (I, [P, I, P, P, P]),
+        "amg_level_matvec_f32": (I, [P, I, P, P, P]),
         "amg_vcycle": (I, [P, P, P, P]),
         "amg_solve": (I, [P, P, P, D, P, IP, DP]),
         "amg_residual_history": (I, [P, DP, I]),
@@ -205,10 +208,25 @@ def amg_matvec(h, x, y, stream=None):
                                  _stream(stream)), "amg_matvec")
 
 
+def amg_matvec_noalloc(h, x, y, stream=None):
+    """amg_matvec with the library's static work memory (N <= 2^18)."""
+    return _check(lib.amg_matvec_noalloc(h, _vec(h, x, "amg_matvec_noalloc x"),
+                                         _vec(h, y, "amg_matvec_noalloc y"), _stream(stream)),
+                  "amg_matvec_noalloc")
+
+
 def amg_level_matvec(h, level: int, x, y, stream=None):
     return _check(lib.amg_level_matvec(h, int(level), _vec(h, x, "amg_level_matvec x", level),
                                        _vec(h, y, "amg_level_matvec y", level), _stream(stream)),
                   "amg_level_matvec")
+
+
+def amg_level_matvec_f32(h, level: int, x, y, stream=None):
+    """FP32 level matvec of an AMG_MIXED handle; x, y float32."""
+    return _check(lib.amg_level_matvec_f32(
+        h, int(level), _vec(h, x, "amg_level_matvec_f32 x", level, f32=True),
+        _vec(h, y, "amg_level_matvec_f32 y", level, f32=True), _stream(stream)),
+        "amg_level_matvec_f32")
 
 
 def amg_vcycle(h, r, e, stream=None):

@@ -200,6 +200,7 @@ struct Profiler {
 
 struct amg_ctx {
   Profiler prof;
+  KernelSpec kspec{};
   int device = 0;
   int64_t N = 0;
   amg_opts_t opts{};
@@ -267,6 +268,16 @@ struct amg_ctx {
   // later visits of the first small level
   TailOp* tail_prog[2] = {nullptr, nullptr};
   int tail_prog_n[2] = {0, 0};
+  // split outer residual (AMG_FLAG_ACCURATE_RESIDUAL): the finest level's far
+  // field (spectra and Cross data of the stencil entries beyond kNearM
+  // half-steps, geometry and work vectors of level 0) and the near field
+  bool split = false;
+  LevelRes far0;
+  double* ynear = nullptr;
+  double* near_w = nullptr;
+  double* near_rl = nullptr;
+  double* near_rr = nullptr;
+  double near_rin[2] = {0.0, 0.0};
 };
 
 namespace {
@@ -344,7 +355,9 @@ int check_opts(const amg_opts_t* o) {
   if (o->coarsest_log2 < 2 || o->coarsest_log2 > 7) return AMG_EINVAL;
   if (o->precision != AMG_FP64 && o->precision != AMG_MIXED) return AMG_EINVAL;
   if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
-  if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE | AMG_FLAG_EAGER)) return AMG_EINVAL;
+  if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE | AMG_FLAG_EAGER |
+                   AMG_FLAG_ACCURATE_RESIDUAL))
+    return AMG_EINVAL;
   if (o->inner != AMG_INNER_VCYCLE && o->inner != AMG_INNER_PCG && o->inner != AMG_INNER_GMRES)
     return AMG_EINVAL;
   if (o->restart < 1 || o->restart > kGmMax) return AMG_EINVAL;
@@ -381,6 +394,9 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess, bool band) {
   const int64_t md = o->cycle == 2 ? kSubDenseMaxW : kSubDenseMax;
   if (mc < md) bytes += md * md * (mixed ? 12 : 8);  // the folded sub-cycle's operator
   bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
+  if (o->flags & AMG_FLAG_ACCURATE_RESIDUAL)  // far-field spectra + Cross, near-field output
+    bytes += (sym_guess ? 2 : 4) * L0 * 8 + 4 * (N - 1) * 8 + (2 * N - 1) * 8 +
+             (4 * kNearM + 2) * 8;
   return bytes;
 }
 
@@ -409,16 +425,27 @@ const LevelDev<double>* lvdev_of<double>(const amg_ctx* c) { return c->lvdev64; 
 template <>
 const LevelDev<float>* lvdev_of<float>(const amg_ctx* c) { return c->lvdev32; }
 
+// Work memory of a four-step matvec: the FFT buffer (L complex), the pass-1
+// block partials of the w_o row and the level's two w_o scalars.  Null
+// members: the handle's own.
+template <typename T>
+struct FourstepWork {
+  cplx<T>* buf = nullptr;
+  T* part = nullptr;
+  T* scal = nullptr;
+};
+
 // One four-step matvec of level l with the given prologue and epilogue.
 template <typename T>
 int fourstep(amg_ctx* c, int l, int cmode, const ColIn<T>& in, int emode, const EpiOut<T>& out,
-             hipStream_t s) {
-  const LevelDev<T> d = c->lv[l].template dev<T>();
-  cplx<T>* buf = buf_of<T>(c);
-  T* dp = dpart_of<T>(c);
+             hipStream_t s, const FourstepWork<T>& wk = FourstepWork<T>{}) {
+  LevelDev<T> d = c->lv[l].template dev<T>();
+  if (wk.scal) d.scal = wk.scal;
+  cplx<T>* buf = wk.buf ? wk.buf : buf_of<T>(c);
+  T* dp = wk.part ? wk.part : dpart_of<T>(c);
   const Twiddles<T>& tw = tw_of<T>(c);
   Profiler& P = c->prof;
-  const bool prof = P.on && l == 0;
+  const bool prof = P.on && l == 0 && !wk.buf;  // caller-provided work memory: no events
   const size_t e0 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_col_fwd<T>(cmode, d, in, buf, tw, dp, s));
   if (d.bmain) {
@@ -638,7 +665,19 @@ int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double
     in.x = x;
   }
   int npart = 1;
-  if (L0.plan.tail) {
+  if (c->split) {
+    // far field through the FFT passes (pass 1 also applies x += e), the near
+    // field in difference form from the updated x, added in the epilogue
+    const LevelDev<double> df = c->far0.dev<double>();
+    HIP_TRY(launch_col_fwd<double>(cmode, df, in, c->buf64, c->tw64, c->dpart64, s));
+    HIP_TRY(launch_near(x, c->ynear, c->N, c->near_w, c->near_rl, c->near_rr, c->near_rin[0],
+                        c->near_rin[1], s));
+    HIP_TRY(launch_row<double>(1, df, c->buf64, c->tw64, c->dpart64,
+                               col_blocks(df.logL1, df.tcols), x, s));
+    out.ynear = c->ynear;
+    HIP_TRY(launch_col_inv<double>(EPI_OUTER, df, out, c->buf64, c->tw64, c->npart, s));
+    npart = col_blocks(df.logL1, df.tcols);
+  } else if (L0.plan.tail) {
     HIP_TRY(launch_tail_matvec<double>(cmode, EPI_OUTER, d, in, out, c->tw64, c->npart, s));
   } else {
     AMG_TRY(fourstep<double>(c, 0, cmode, in, EPI_OUTER, out, s));
@@ -653,19 +692,26 @@ int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double
   return AMG_OK;
 }
 
-int level_matvec64(amg_ctx* c, int l, const double* x, double* y, hipStream_t s) {
+template <typename T>
+int level_matvec(amg_ctx* c, int l, const T* x, T* y, hipStream_t s,
+                 const FourstepWork<T>& wk = FourstepWork<T>{}) {
   const LevelRes& R = c->lv[l];
-  const LevelDev<double> d = R.dev<double>();
-  ColIn<double> in{};
+  const LevelDev<T> d = R.template dev<T>();
+  ColIn<T> in{};
   in.x = x;
-  EpiOut<double> out{};
+  EpiOut<T> out{};
   out.xin = x;
   out.y = y;
   if (R.plan.tail) {
-    HIP_TRY(launch_tail_matvec<double>(COL_MV, EPI_MV, d, in, out, c->tw64, c->npart, s));
+    // the tail kernel's work lives in LDS (no partials are written for EPI_MV)
+    HIP_TRY(launch_tail_matvec<T>(COL_MV, EPI_MV, d, in, out, tw_of<T>(c), nullptr, s));
     return AMG_OK;
   }
-  return fourstep<double>(c, l, COL_MV, in, EPI_MV, out, s);
+  return fourstep<T>(c, l, COL_MV, in, EPI_MV, out, s, wk);
+}
+
+int level_matvec64(amg_ctx* c, int l, const double* x, double* y, hipStream_t s) {
+  return level_matvec<double>(c, l, x, y, s);
 }
 
 // The V-cycle below and including level k (pre-smoothing from zero, the
@@ -757,6 +803,50 @@ int form_sub_wcycle(amg_ctx* c, hipStream_t s) {
   }
   c->w_last = k;
   c->lu_w = {m, M, M32};
+  return AMG_OK;
+}
+
+// Spectra G1, G2 of a level (eq. (ccs3.4)) in FP64 (and their FP32 rounding
+// when `f32`): the circulant columns of its four Toeplitz generators through
+// the level's forward FFT, combined into the packed product's form.
+int level_spectra(amg_ctx* c, const TpxLevel& H, LevelRes& R, bool f32, cplx<double>* zscratch,
+                  hipStream_t s) {
+  const int64_t L = int64_t(1) << R.plan.logL;
+  const size_t nspec = (size_t)(R.sym ? L : 2 * L);
+  AMG_TRY(dalloc(c, &R.g1d, nspec));
+  AMG_TRY(dalloc(c, &R.g2d, nspec));
+  if (f32) {
+    AMG_TRY(dalloc(c, &R.g1f, nspec));
+    AMG_TRY(dalloc(c, &R.g2f, nspec));
+  }
+  const size_t mark = c->dev_allocs.size();  // generators: setup temporaries
+  double *ga, *gb, *gc, *gd;
+  AMG_TRY(upload(c, &ga, H.a, s));
+  AMG_TRY(upload(c, &gb, H.b, s));
+  AMG_TRY(upload(c, &gc, H.c, s));
+  AMG_TRY(upload(c, &gd, H.d, s));
+  const LevelDev<double> d = R.dev<double>();
+  if (R.plan.tail) {
+    HIP_TRY(launch_tail_fft_setup(d, ga, gb, c->buf64, c->tw64, s));
+    HIP_TRY(launch_tail_fft_setup(d, gc, gd, zscratch, c->tw64, s));
+  } else {
+    ColIn<double> in{};
+    double* dummy = nullptr;
+    AMG_TRY(dalloc(c, &dummy, (size_t)col_blocks(d.logL1, d.tcols)));
+    in.gx = ga;
+    in.gy = gb;
+    HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, c->buf64, c->tw64, dummy, s));
+    HIP_TRY(launch_row<double>(0, d, c->buf64, c->tw64, dummy, 0, nullptr, s));
+    in.gx = gc;
+    in.gy = gd;
+    HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, zscratch, c->tw64, dummy, s));
+    HIP_TRY(launch_row<double>(0, d, zscratch, c->tw64, dummy, 0, nullptr, s));
+  }
+  HIP_TRY(launch_combine(R.plan.logL, R.plan.logL1, R.plan.logL2, c->buf64, zscratch, R.sym,
+                         R.g1d, R.g2d, f32 ? R.g1f : nullptr, f32 ? R.g2f : nullptr, s));
+  // generators are only needed for the spectra
+  HIP_TRY(hipStreamSynchronize(s));
+  free_since(c, mark);
   return AMG_OK;
 }
 
@@ -854,42 +944,35 @@ int setup_device(amg_ctx* c, hipStream_t s) {
       HIP_TRY(hipMemsetAsync(R.uf, 0, m * sizeof(float), s));
       HIP_TRY(hipMemsetAsync(R.rf, 0, m * sizeof(float), s));
     }
-    // spectra
-    const size_t nspec = (size_t)(R.sym ? L : 2 * L);
-    AMG_TRY(dalloc(c, &R.g1d, nspec));
-    AMG_TRY(dalloc(c, &R.g2d, nspec));
-    if (mixed) {
-      AMG_TRY(dalloc(c, &R.g1f, nspec));
-      AMG_TRY(dalloc(c, &R.g2f, nspec));
-    }
-    const size_t mark = c->dev_allocs.size();  // generators: setup temporaries
-    double *ga, *gb, *gc, *gd;
-    AMG_TRY(upload(c, &ga, H.a, s));
-    AMG_TRY(upload(c, &gb, H.b, s));
-    AMG_TRY(upload(c, &gc, H.c, s));
-    AMG_TRY(upload(c, &gd, H.d, s));
-    const LevelDev<double> d = R.dev<double>();
-    if (R.plan.tail) {
-      HIP_TRY(launch_tail_fft_setup(d, ga, gb, c->buf64, c->tw64, s));
-      HIP_TRY(launch_tail_fft_setup(d, gc, gd, zscratch, c->tw64, s));
-    } else {
-      ColIn<double> in{};
-      double* dummy = nullptr;
-      AMG_TRY(dalloc(c, &dummy, (size_t)col_blocks(d.logL1, d.tcols)));
-      in.gx = ga;
-      in.gy = gb;
-      HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, c->buf64, c->tw64, dummy, s));
-      HIP_TRY(launch_row<double>(0, d, c->buf64, c->tw64, dummy, 0, nullptr, s));
-      in.gx = gc;
-      in.gy = gd;
-      HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, zscratch, c->tw64, dummy, s));
-      HIP_TRY(launch_row<double>(0, d, zscratch, c->tw64, dummy, 0, nullptr, s));
-    }
-    HIP_TRY(launch_combine(R.plan.logL, R.plan.logL1, R.plan.logL2, c->buf64, zscratch, R.sym,
-                           R.g1d, R.g2d, R.g1f, R.g2f, s));
-    // generators are only needed for the spectra
-    HIP_TRY(hipStreamSynchronize(s));
-    free_since(c, mark);
+    AMG_TRY(level_spectra(c, H, R, mixed, zscratch, s));
+  }
+  if (c->split) {
+    // the far field of the finest level: same geometry and work vectors,
+    // its own spectra (FP64 only) and Cross data
+    const KernelSpec ks = c->kspec;
+    TpxLevel far = finest_level(ks, c->N, kNearM);
+    if (c->opts.scale != 1.0) shift_level(far, 0.0, c->opts.scale);
+    LevelRes& F = c->far0;
+    F = c->lv[0];
+    F.sym = far.symmetric() && c->lv[0].sym;
+    F.o = far.o;
+    F.g1f = F.g2f = nullptr;
+    F.pf = F.qf = F.xif = F.zetaf = nullptr;
+    AMG_TRY(upload(c, &F.pd, far.p, s));
+    AMG_TRY(upload(c, &F.qd, far.q, s));
+    AMG_TRY(upload(c, &F.xid, far.xi, s));
+    AMG_TRY(upload(c, &F.zetad, far.zeta, s));
+    AMG_TRY(level_spectra(c, far, F, false, zscratch, s));
+    NearField nf;
+    near_field(ks, c->N, kNearM, c->opts.shift, c->opts.scale, nf);
+    std::vector<double> w(nf.wn);
+    w.insert(w.end(), nf.wm.begin(), nf.wm.end());
+    AMG_TRY(upload(c, &c->near_w, w, s));
+    AMG_TRY(upload(c, &c->near_rl, nf.rsum_left, s));
+    AMG_TRY(upload(c, &c->near_rr, nf.rsum_right, s));
+    c->near_rin[0] = nf.rsum_in[0];
+    c->near_rin[1] = nf.rsum_in[1];
+    AMG_TRY(dalloc(c, &c->ynear, (size_t)(2 * c->N - 1)));
   }
   // coarsest level: LU with partial pivoting (host, FP64), then A_c^{-1} by
   // solving against the identity with those factors; stored column-major
@@ -989,6 +1072,36 @@ void release(amg_ctx* c) {
   c->st_host = nullptr;
 }
 
+// Static work memory of amg_matvec_noalloc: the FFT buffer of a finest level
+// of up to 2^18 intervals (2N complex doubles), its block partials and the
+// w_o scalars.  Each device holds its own copy for the life of the process;
+// host code must use the per-device address from hipGetSymbolAddress (the
+// array's name on the host is only a stand-in).
+constexpr size_t kScratchFftBytes = size_t(8) << 20;
+constexpr size_t kScratchPartBytes = size_t(32) << 10;
+constexpr size_t kScratchBytes = kScratchFftBytes + kScratchPartBytes + 256;
+constexpr int64_t kScratchMaxN = int64_t(1) << 18;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device `dev` (current), looked up once.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return AMG_EINVAL;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __LINE__);
+    if (!p) return AMG_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return AMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1043,6 +1156,16 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
   c->host_only = (o.flags & AMG_FLAG_HOST_ONLY) != 0;
   c->prof.on = (o.flags & AMG_FLAG_PROFILE) != 0 && !c->host_only;
   c->mixed = o.precision == AMG_MIXED;
+  c->kspec = ks;
+  if (o.flags & AMG_FLAG_ACCURATE_RESIDUAL) {
+    if (kernel->kind != AMG_K_CONST && kernel->kind != AMG_K_WEIGHTED &&
+        kernel->kind != AMG_K_FRACTIONAL) {
+      delete c;
+      return AMG_ENOTSUP;
+    }
+    // finest levels in the small-level kernels keep the plain residual
+    c->split = !plan_level(N - 1).tail;
+  }
   try {
     c->host.push_back(finest_level(ks, N));
     if (o.shift != 0.0 || o.scale != 1.0) shift_level(c->host[0], o.shift, o.scale);
@@ -1074,7 +1197,9 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
       delete c;
       return hip_fail(e, "hipGetDevice", __LINE__);
     }
-    st = setup_device(c, (hipStream_t)stream);
+    void* sp = nullptr;
+    st = scratch_address(c->device, &sp);
+    if (st == AMG_OK) st = setup_device(c, (hipStream_t)stream);
     if (st != AMG_OK) {
       release(c);
       delete c;
@@ -1138,6 +1263,33 @@ int amg_level_matvec(amg_t h, int level, const double* x, double* y, void* strea
   if (x == y) return AMG_EINVAL;
   HIP_TRY(hipSetDevice(h->device));
   return level_matvec64(h, level, x, y, (hipStream_t)stream);
+}
+
+int amg_matvec_noalloc(amg_t h, const double* x, double* y, void* stream) {
+  if (!h || !x || !y || h->host_only || x == y) return AMG_EINVAL;
+  if (h->N > kScratchMaxN) {
+    if (std::getenv("AMG_DEBUG"))
+      std::fprintf(stderr, "amg: amg_matvec_noalloc: N = %lld exceeds the static scratch (N <= %lld)\n",
+                   (long long)h->N, (long long)kScratchMaxN);
+    return AMG_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(h->device));
+  void* sp = nullptr;
+  AMG_TRY(scratch_address(h->device, &sp));
+  unsigned char* base = static_cast<unsigned char*>(sp);
+  FourstepWork<double> wk;
+  wk.buf = reinterpret_cast<cplx<double>*>(base);
+  wk.part = reinterpret_cast<double*>(base + kScratchFftBytes);
+  wk.scal = reinterpret_cast<double*>(base + kScratchFftBytes + kScratchPartBytes);
+  return level_matvec<double>(h, 0, x, y, (hipStream_t)stream, wk);
+}
+
+int amg_level_matvec_f32(amg_t h, int level, const float* x, float* y, void* stream) {
+  if (!h || !x || !y || h->host_only || !h->mixed || level < 0 || level >= (int)h->lv.size())
+    return AMG_EINVAL;
+  if ((const void*)x == (const void*)y) return AMG_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  return level_matvec<float>(h, level, x, y, (hipStream_t)stream);
 }
 
 int amg_vcycle(amg_t h, const void* r, void* e, void* stream) {

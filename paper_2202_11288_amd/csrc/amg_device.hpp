@@ -91,6 +91,8 @@ struct EpiOut {
   const double* bo;    // EPI_OUTER: right-hand side
   double* ro;          // EPI_OUTER: residual (FP64)
   float* r32;          // EPI_OUTER: FP32 copy of the residual (may be null)
+  const double* ynear; // EPI_OUTER: near-field part of A x added to the FFT's
+                       // far-field product (split residual; null: none)
 };
 
 // Steps of the small-level kernel: how a step forms its iterate (prologue)
@@ -244,6 +246,15 @@ hipError_t launch_band_mv(const LevelDev<T>& lv, const T* x, hipStream_t s);
 hipError_t launch_bdf4_rhs(const double* u1, const double* u2, const double* u3,
                            const double* u4, const double* src, double* b, int64_t m,
                            hipStream_t s);
+
+// Near field of the split residual (amg_host.hpp NearField): y (block order,
+// 2N-1 doubles) = sum_{0<|k|<=M} W(k) (x_{s+k} - x_s) + R_s x_s at every
+// collocation position s; w = [node-row W | midpoint-row W] (2 (2M+1)
+// doubles), rl / rr = R_s of the first / last M positions, rin_n / rin_m =
+// R_s of the other node / midpoint positions.
+constexpr int kNearM = 64;  // near offsets |k| <= kNearM half-steps
+hipError_t launch_near(const double* x, double* y, int64_t N, const double* w, const double* rl,
+                       const double* rr, double rin_n, double rin_m, hipStream_t s);
 
 // Column tiles / grid sizes used by the launchers (host helpers).
 inline int col_blocks(int logL1, int tcols) { return (1 << logL1) / tcols; }

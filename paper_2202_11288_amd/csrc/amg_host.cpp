@@ -409,7 +409,7 @@ void shift_level(TpxLevel& t, double shift, double scale) {
   t.d[t.n - 1] += shift;
 }
 
-TpxLevel finest_level(const KernelSpec& k, int64_t N) {
+TpxLevel finest_level(const KernelSpec& k, int64_t N, int64_t near_cut) {
   TpxLevel t;
   const int64_t n = N - 1;
   t.n = n;
@@ -448,8 +448,12 @@ TpxLevel finest_level(const KernelSpec& k, int64_t N) {
   std::vector<double> Wn, Wm;
   int64_t Sn = 0, Sm = 0;
   both_stencils(k, N, Wn, Sn, Wm, Sm);
-  auto node = [&](int64_t s2) { return (s2 < -Sn || s2 > Sn) ? 0.0 : Wn[s2 + Sn]; };
-  auto mid = [&](int64_t s2) { return (s2 < -Sm || s2 > Sm) ? 0.0 : Wm[s2 + Sm]; };
+  auto node = [&](int64_t s2) {
+    return (s2 < -Sn || s2 > Sn || (s2 >= -near_cut && s2 <= near_cut)) ? 0.0 : Wn[s2 + Sn];
+  };
+  auto mid = [&](int64_t s2) {
+    return (s2 < -Sm || s2 > Sm || (s2 >= -near_cut && s2 <= near_cut)) ? 0.0 : Wm[s2 + Sm];
+  };
   // Interleaved positions: v_i at 2(i+1), w_o at 1, w_bar_j at 2j+3 (units h/2).
   // Node rows: A, B_bar, p; midpoint rows: C_bar, D_bar, q, xi, zeta, o.
   for (int64_t dd = -(n - 1); dd <= n - 1; ++dd) {
@@ -479,6 +483,45 @@ TpxLevel finest_level(const KernelSpec& k, int64_t N) {
     }
   }
   return t;
+}
+
+void near_field(const KernelSpec& k, int64_t N, int M, double shift, double scale,
+                NearField& nf) {
+  std::vector<double> Wn, Wm;
+  int64_t Sn = 0, Sm = 0;
+  both_stencils(k, N, Wn, Sn, Wm, Sm);
+  auto at = [](const std::vector<double>& W, int64_t S, int64_t s2) {
+    return (s2 < -S || s2 > S) ? 0.0 : W[s2 + S];
+  };
+  nf.M = M;
+  nf.wn.assign(2 * M + 1, 0.0);
+  nf.wm.assign(2 * M + 1, 0.0);
+  for (int kk = -M; kk <= M; ++kk) {
+    nf.wn[kk + M] = scale * at(Wn, Sn, kk);
+    nf.wm[kk + M] = scale * at(Wm, Sm, kk);
+  }
+  const int64_t last = 2 * N - 1;
+  // R_s: the stencil of row s summed over its in-range near columns
+  auto rsum = [&](int64_t s) {
+    const std::vector<double>& W = (s % 2 == 0) ? Wn : Wm;
+    const int64_t S = (s % 2 == 0) ? Sn : Sm;
+    long double acc = 0.0L;
+    for (int kk = -M; kk <= M; ++kk)
+      if (s + kk >= 1 && s + kk <= last) acc += (long double)at(W, S, kk);
+    return (double)(acc * (long double)scale + (long double)shift);
+  };
+  nf.rsum_left.resize(M);
+  nf.rsum_right.resize(M);
+  for (int64_t s = 1; s <= M; ++s) nf.rsum_left[s - 1] = rsum(s);
+  for (int64_t s = last - M + 1; s <= last; ++s) nf.rsum_right[s - (last - M + 1)] = rsum(s);
+  // interior rows (every near column in range): one value per point type
+  for (int t = 0; t < 2; ++t) {
+    const std::vector<double>& W = t == 0 ? Wn : Wm;
+    const int64_t S = t == 0 ? Sn : Sm;
+    long double acc = 0.0L;
+    for (int kk = -M; kk <= M; ++kk) acc += (long double)at(W, S, kk);
+    nf.rsum_in[t] = (double)(acc * (long double)scale + (long double)shift);
+  }
 }
 
 TpxLevel coarsen(const TpxLevel& f) {

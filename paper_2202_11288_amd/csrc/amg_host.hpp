@@ -80,7 +80,31 @@ void volume_correction(const KernelSpec& k, int64_t N, const double* g_left,
 void shift_level(TpxLevel& t, double shift, double scale);
 
 // Finest level from the kernel stencil or from caller generators.
-TpxLevel finest_level(const KernelSpec& k, int64_t N);
+// near_cut >= 0 (stencil kernels only): the stencil entries at half-step
+// offsets |s2| <= near_cut are left out (the far field of the split residual
+// below).
+TpxLevel finest_level(const KernelSpec& k, int64_t N, int64_t near_cut = -1);
+
+// Near field of the finest level for the split evaluation of A x (stencil
+// kernels).  In the interleaved order of the collocation points (position s
+// = 1..2N-1 in units of h/2: nodes at even s, midpoints at odd s) row s of
+// the finest matrix is the row stencil of its point type, W(s' - s), cut to
+// the columns 1..2N-1 (eq. (ccs2.6); under the shifted rule both types share
+// one stencil).  With the near offsets |k| <= M applied in difference form,
+//   (A x)_s = sum_{0<|k|<=M} W(k) (x_{s+k} - x_s) + R_s x_s + far_s(x),
+//   R_s = sum_{|k|<=M, 1<=s+k<=2N-1} W(k)   (+ shift),
+// the products that cancel in a smooth x meet only differences of
+// neighbouring values, and the far field (all |k| > M) is a Toeplitz-plus-
+// Cross level of small entries.  w[k + M] = scale * W(k) per row type;
+// rsum_left[s-1] (s = 1..M), rsum_right[s-(2N-M)] (s = 2N-M..2N-1) and
+// rsum_in[type] (every other s) hold R_s, summed in long double.
+struct NearField {
+  int M = 0;
+  std::vector<double> wn, wm;            // node rows, midpoint rows (2M+1 each)
+  std::vector<double> rsum_left, rsum_right;
+  double rsum_in[2] = {0.0, 0.0};        // [0] node rows, [1] midpoint rows
+};
+void near_field(const KernelSpec& k, int64_t N, int M, double shift, double scale, NearField& nf);
 
 // Galerkin coarse level R A P (Lemma 3.1), O(n).
 TpxLevel coarsen(const TpxLevel& f);

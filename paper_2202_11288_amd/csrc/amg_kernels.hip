@@ -622,7 +622,8 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
       out.y[j] = yv;
       out.y[n + 1 + j] = yw;
     } else {
-      const double rv = out.bo[j] - (double)yv, rw = out.bo[n + 1 + j] - (double)yw;
+      const double qv = out.ynear ? out.ynear[j] : 0.0, qw = out.ynear ? out.ynear[n + 1 + j] : 0.0;
+      const double rv = out.bo[j] - ((double)yv + qv), rw = out.bo[n + 1 + j] - ((double)yw + qw);
       out.ro[j] = rv;
       out.ro[n + 1 + j] = rw;
       if (out.r32) {
@@ -636,7 +637,7 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
     if constexpr (EM == EPI_MV) {
       out.y[n] = yo;
     } else {
-      const double ro = out.bo[n] - (double)yo;
+      const double ro = out.bo[n] - ((double)yo + (out.ynear ? out.ynear[n] : 0.0));
       out.ro[n] = ro;
       if (out.r32) out.r32[n] = (float)ro;
       ss += ro * ro;
@@ -1101,6 +1102,76 @@ __global__ __launch_bounds__(kVecNT) void k_cg_dir(const SolveState* st, double*
   const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
   if (i >= m) return;
   p[i] = first ? (double)z[i] : (double)z[i] + st->beta * p[i];
+}
+
+// ---------------------------------------------------------------------------
+// Near field of the split residual.  A workgroup owns kNearTS consecutive
+// collocation positions s (units of h/2: nodes at even s, midpoints at odd
+// s) and stages x at s - M .. s + kNearTS - 1 + M, read from the block
+// order, in LDS; each output sums W(k) (x_{s+k} - x_s) over 0 < |k| <= M in
+// (k, -k) pairs in a fixed order and adds R_s x_s.  Only the first and last
+// workgroups hold positions whose stencil leaves 1..2N-1; they test every
+// column (out-of-range columns are not in the matrix).
+// ---------------------------------------------------------------------------
+constexpr int kNearTS = 1024;
+constexpr int kNearNT = 256;
+
+__device__ __forceinline__ int64_t near_block(int64_t s, int64_t n) {
+  // block-order index of position s: node s = 2(i+1) -> i; midpoint s = 2k+1 -> n + k
+  return (s & 1) ? n + (s >> 1) : (s >> 1) - 1;
+}
+
+__global__ __launch_bounds__(kNearNT) void k_near(const double* x, double* y, int64_t N,
+                                                 const double* w, const double* rl,
+                                                 const double* rr, double rin_n, double rin_m) {
+  constexpr int M = kNearM;
+  __shared__ double zs[kNearTS + 2 * M];
+  __shared__ double ws[2 * (2 * M + 1)];
+  const int64_t last = 2 * N - 1, n = N - 1;
+  const int64_t s0 = 1 + (int64_t)blockIdx.x * kNearTS;
+  // workgroups with a position within M of either end test every column
+  const bool edge = s0 <= M || s0 + kNearTS - 1 > last - M;
+  for (int i = threadIdx.x; i < kNearTS + 2 * M; i += kNearNT) {
+    const int64_t s = s0 - M + i;
+    zs[i] = (s >= 1 && s <= last) ? x[near_block(s, n)] : 0.0;
+  }
+  for (int i = threadIdx.x; i < 2 * (2 * M + 1); i += kNearNT) ws[i] = w[i];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kNearTS / kNearNT; ++e) {
+    const int t = threadIdx.x + e * kNearNT;
+    const int64_t s = s0 + t;
+    if (s > last) break;
+    const double* W = ws + ((s & 1) ? (2 * M + 1) : 0) + M;
+    const int c = t + M;
+    const double zc = zs[c];
+    double acc = 0.0;
+    double R = (s & 1) ? rin_m : rin_n;
+    if (!edge) {
+#pragma unroll 8
+      for (int k = 1; k <= M; ++k) acc += W[k] * (zs[c + k] - zc) + W[-k] * (zs[c - k] - zc);
+    } else {
+      for (int k = 1; k <= M; ++k) {
+        if (s + k <= last) acc += W[k] * (zs[c + k] - zc);
+        if (s - k >= 1) acc += W[-k] * (zs[c - k] - zc);
+      }
+      if (s <= M) R = rl[s - 1];
+      else if (s > last - M) R = rr[s - (last - M + 1)];
+    }
+    y[near_block(s, n)] = acc + R * zc;
+  }
+}
+
+hipError_t launch_near(const double* x, double* y, int64_t N, const double* w, const double* rl,
+                       const double* rr, double rin_n, double rin_m, hipStream_t s) {
+  const int64_t m = 2 * N - 1;
+  const int64_t grid = (m + kNearTS - 1) / kNearTS;
+  // the edge test of the kernel assumes a tile longer than the near reach
+  static_assert(kNearTS > kNearM, "near tile");
+  if (N <= kNearM || grid > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_near, dim3((unsigned)grid), dim3(kNearNT), 0, s, x, y, N, w, rl, rr, rin_n,
+                     rin_m);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

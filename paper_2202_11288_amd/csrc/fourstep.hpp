@@ -559,12 +559,12 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
     yo = lv.scal[0];
     if constexpr (MODE == EPI_RESID || MODE == EPI_SMOOTH) wb = lv.b[n];
     if constexpr (MODE == EPI_SMOOTH) wu = lv.u[n];
-    if constexpr (MODE == EPI_OUTER) wbo = out.bo[n];
+    if constexpr (MODE == EPI_OUTER) wbo = out.bo[n] - (out.ynear ? out.ynear[n] : 0.0);
   }
   bool ok[KH];
   int jj[KH];
   T pp[KH], xx[KH], b0[KH], b1[KH], u0[KH], u1[KH];
-  double o0[KH], o1[KH];
+  double o0[KH], o1[KH], q0[KH], q1[KH];
 #pragma unroll
   for (int e = 0; e < KH; ++e) {
     const int j = j1 + ((i0 + e * di) << lv.logL1);
@@ -584,6 +584,8 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
     if constexpr (MODE == EPI_OUTER) {
       o0[e] = out.bo[js];
       o1[e] = out.bo[jw];
+      q0[e] = out.ynear ? out.ynear[js] : 0.0;
+      q1[e] = out.ynear ? out.ynear[jw] : 0.0;
     }
   }
   if constexpr (EPT == 16) {
@@ -635,7 +637,7 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
         lv.u[jw] = u1[e] + wdw * (b1[e] - yw);
       }
     } else {  // EPI_OUTER
-      const double rv = o0[e] - (double)yv, rw = o1[e] - (double)yw;
+      const double rv = o0[e] - ((double)yv + q0[e]), rw = o1[e] - ((double)yw + q1[e]);
       out.ro[j] = rv;
       out.ro[jw] = rw;
       if (out.r32) {
@@ -804,7 +806,7 @@ constexpr bool col_mode_built(int mode) {
 }
 template <typename T>
 constexpr bool epi_mode_built(int mode) {
-  return sizeof(T) == 8 || mode == EPI_RESID || mode == EPI_SMOOTH;
+  return sizeof(T) == 8 || mode == EPI_MV || mode == EPI_RESID || mode == EPI_SMOOTH;
 }
 
 template <typename T>
@@ -860,13 +862,13 @@ hipError_t launch_col_inv(int mode, const LevelDev<T>& lv, const EpiOut<T>& out,
   const int grid = col_blocks(lv.logL1, lv.tcols);
   const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(ept * kNT4);
   switch (mode) {
+    case EPI_MV: return col_inv_ept<T, EPI_MV>(ept, grid, lds, s, lv, out, buf, tw, part);
     case EPI_RESID: return col_inv_ept<T, EPI_RESID>(ept, grid, lds, s, lv, out, buf, tw, part);
     case EPI_SMOOTH: return col_inv_ept<T, EPI_SMOOTH>(ept, grid, lds, s, lv, out, buf, tw, part);
     default: break;
   }
   if constexpr (sizeof(T) == 8) {
     switch (mode) {
-      case EPI_MV: return col_inv_ept<T, EPI_MV>(ept, grid, lds, s, lv, out, buf, tw, part);
       case EPI_OUTER: return col_inv_ept<T, EPI_OUTER>(ept, grid, lds, s, lv, out, buf, tw, part);
       default: break;
     }

@@ -104,7 +104,7 @@ def _setup_status(kern, delta, N, **opts):
     dict(kind=B.AMG_K_FRACTIONAL, alpha=0.5), dict(kind=B.AMG_K_FRACTIONAL, alpha=0.0),
     dict(kind=B.AMG_K_WEIGHTED, wl=-1.0), dict(kind=7), dict(kind=B.AMG_K_GENERATORS),
     dict(opts=dict(coarsest_log2=1)), dict(opts=dict(coarsest_log2=8)),
-    dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=8)),
+    dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=16)),
     dict(opts=dict(inner=3)), dict(opts=dict(inner=-1)),
     dict(opts=dict(inner=B.AMG_INNER_GMRES, restart=0)), dict(opts=dict(restart=65)),
     dict(opts=dict(cycle=0)), dict(opts=dict(cycle=3)),
@@ -115,6 +115,25 @@ def test_invalid_arguments_rejected(case):
     kern = B.kernel(kind, alpha=case.get("alpha", 0.3), wl=case.get("wl", 1.0), wr=1.0)
     st = _setup_status(kern, case.get("delta", 0.1), case.get("N", 256), **case.get("opts", {}))
     assert st == B.AMG_EINVAL
+
+
+def test_accurate_residual_flag():
+    """AMG_FLAG_ACCURATE_RESIDUAL is accepted for the stencil kernels and
+    refused (AMG_ENOTSUP) where the finest matrix is not a row stencil in the
+    points' order (caller generators, the weakly singular model's band);
+    its far-field spectra and near-field output count in the footprint."""
+    fl = B.AMG_FLAG_ACCURATE_RESIDUAL
+    for kind in (B.AMG_K_CONST, B.AMG_K_WEIGHTED, B.AMG_K_FRACTIONAL):
+        assert _setup_status(B.kernel(kind, alpha=0.3, wl=1.2, wr=0.8), 0.1, 4096, flags=fl) == B.AMG_OK
+    gen = np.zeros(8 * 256 - 8)
+    gen[255 - 1] = 1.0
+    assert _setup_status(B.kernel(B.AMG_K_GENERATORS, gen=gen), 0.0, 256, flags=fl) == B.AMG_ENOTSUP
+    assert _setup_status(B.kernel(B.AMG_K_WEAKLY_SINGULAR, gamma=0.5), 0.1, 256,
+                         flags=fl) == B.AMG_ENOTSUP
+    k = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4)
+    f0 = B.amg_footprint_bytes(k, 0.1, 2 ** 20)
+    f1 = B.amg_footprint_bytes(k, 0.1, 2 ** 20, B.amg_default_opts(flags=fl))
+    assert f1 - f0 >= 2 * 2 ** 21 * 8 + (2 ** 21 - 1) * 8
 
 
 def test_unsupported_sweep_counts():
