@@ -199,8 +199,14 @@ typedef struct {
    point cut to the interior columns (eq. (ccs2.6)); its entries within 64
    half-steps are applied in difference form
      sum_{0<|k|<=64} W(k) (x_{s+k} - x_s) + R_s x_s,
-   R_s = the row's near entries summed in long double at setup, and only the
-   entries beyond 64 half-steps go through the FFT (their own spectra).  A
+   R_s = the row's near entries summed, and only the entries beyond 64
+   half-steps go through the FFT (their own spectra).  The own-point weight
+   W(0) = int gamma (1 - l_0) equals -sum_{k != 0} W(k), the quadratic basis
+   being a partition of unity on every cell (so interior rows sum to zero);
+   R_s is formed from that identity in long double at setup, as minus the
+   stencil's weight beyond 64 half-steps and outside the interval, so the
+   operator measured is the collocation matrix with that diagonal, not its
+   FP64 rounding (whose last bit alone moves b - A x by eps |W(0)| |x|).  A
    plain FP64 FFT evaluation of b - A x carries an error of about
    eps |A| |x|, which for kernels with large near-field weights (the
    fractional kernel at large N) exceeds 1e-10 |b|; the split form's error is

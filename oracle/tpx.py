@@ -286,6 +286,42 @@ class Level:
         return np.concatenate([yv, [yo], yw]) + T.band_matvec(u)
 
 
+def from_stencil_rowsum(kernel: disc.Kernel, N: int, scheme: str = disc.SHIFTED):
+    """The finest level of `from_stencil` with every array in long double and
+    the own-point weight W(0) = int gamma (1 - l_0) of each row stencil taken
+    as -sum_{k != 0} W(k), summed in long double: the quadratic basis is a
+    partition of unity on every cell (sum_k l_k = 1), so the two are equal
+    and an interior row of the matrix sums to zero (Sec. 2.2).  The FP64
+    rounding of W(0) (a number of size c h^-2alpha for the fractional
+    kernel) alone moves b - A x by eps |W(0)| |x|; this form defines the
+    matrix without it, for `residual_extended`.  Pinned: its diagonal equals
+    the integral formula's to a few FP64 units of W(0)."""
+    ld = np.longdouble
+    (Wn, Sn), (Wm, Sm) = disc.row_stencils(kernel, N, scheme)
+    Wn = np.asarray(Wn, dtype=ld)
+    Wm = np.asarray(Wm, dtype=ld)
+    Wn[Sn] = -(Wn[:Sn].sum() + Wn[Sn + 1:].sum())
+    Wm[Sm] = -(Wm[:Sm].sum() + Wm[Sm + 1:].sum())
+    n = N - 1
+
+    def at(W, S):
+        def Wat(s2):
+            s2 = np.asarray(s2)
+            out = np.zeros(s2.shape, dtype=ld)
+            ok = np.abs(s2) <= S
+            out[ok] = W[s2[ok] + S]
+            return out
+        return Wat
+
+    Wn_at, Wm_at = at(Wn, Sn), at(Wm, Sm)
+    d = np.arange(-(n - 1), n)
+    i = np.arange(n)
+    T = TpX(n, Wn_at(2 * d), Wn_at(2 * d + 1), Wm_at(2 * d - 1), Wm_at(2 * d),
+            Wn_at(-2 * i - 1), Wm_at(2 * i + 1), Wm_at(-2 * i - 2), Wm_at(2 * i + 2), 0.0)
+    T.o = Wm_at(np.array(0))[()]
+    return T
+
+
 def residual_extended(T: TpX, b, x):
     """b - A x for the level T in extended precision (x86 80-bit long
     double, unit roundoff 5.4e-20): the definition of the residual of the
@@ -320,7 +356,7 @@ def residual_extended(T: TpX, b, x):
     p, q, xi, zeta = (np.asarray(a, dtype=ld) for a in (T.p, T.q, T.xi, T.zeta))
     yv = apply(spec(T.a), V) + apply(spec(T.b), W) + p * wo
     yw = apply(spec(T.c), V) + apply(spec(T.d), W) + xi * wo
-    yo = np.dot(q, v) + ld(T.o) * wo + np.dot(zeta, wb)
+    yo = np.dot(q, v) + np.longdouble(T.o) * wo + np.dot(zeta, wb)
     y = np.concatenate([yv, [yo], yw])
     if T.band is not None:
         s_, m_, p_ = (np.asarray(a, dtype=ld) for a in T.band)

@@ -497,31 +497,37 @@ void near_field(const KernelSpec& k, int64_t N, int M, double shift, double scal
   nf.wn.assign(2 * M + 1, 0.0);
   nf.wm.assign(2 * M + 1, 0.0);
   for (int kk = -M; kk <= M; ++kk) {
-    nf.wn[kk + M] = scale * at(Wn, Sn, kk);
-    nf.wm[kk + M] = scale * at(Wm, Sm, kk);
+    nf.wn[kk + M] = kk == 0 ? 0.0 : scale * at(Wn, Sn, kk);
+    nf.wm[kk + M] = kk == 0 ? 0.0 : scale * at(Wm, Sm, kk);
+  }
+  // The own-point weight int gamma (1 - l_0) equals -sum_{k != 0} W(k) (the
+  // quadratic basis is a partition of unity on every cell), so a row's near
+  // sum R_s = W(0) + sum_{0<|k|<=M, in range} W(k) is minus the stencil's
+  // weight beyond M half-steps and minus its near weight outside 1..2N-1:
+  // small numbers, summed in long double, free of the rounding of W(0).
+  long double far[2] = {0.0L, 0.0L};
+  for (int t = 0; t < 2; ++t) {
+    const std::vector<double>& W = t == 0 ? Wn : Wm;
+    const int64_t S = t == 0 ? Sn : Sm;
+    for (int64_t s2 = -S; s2 <= S; ++s2)
+      if (s2 < -M || s2 > M) far[t] += (long double)W[s2 + S];
   }
   const int64_t last = 2 * N - 1;
-  // R_s: the stencil of row s summed over its in-range near columns
   auto rsum = [&](int64_t s) {
-    const std::vector<double>& W = (s % 2 == 0) ? Wn : Wm;
-    const int64_t S = (s % 2 == 0) ? Sn : Sm;
-    long double acc = 0.0L;
+    const int t = (s % 2 == 0) ? 0 : 1;
+    const std::vector<double>& W = t == 0 ? Wn : Wm;
+    const int64_t S = t == 0 ? Sn : Sm;
+    long double acc = -far[t];
     for (int kk = -M; kk <= M; ++kk)
-      if (s + kk >= 1 && s + kk <= last) acc += (long double)at(W, S, kk);
+      if (kk != 0 && (s + kk < 1 || s + kk > last)) acc -= (long double)at(W, S, kk);
     return (double)(acc * (long double)scale + (long double)shift);
   };
   nf.rsum_left.resize(M);
   nf.rsum_right.resize(M);
   for (int64_t s = 1; s <= M; ++s) nf.rsum_left[s - 1] = rsum(s);
   for (int64_t s = last - M + 1; s <= last; ++s) nf.rsum_right[s - (last - M + 1)] = rsum(s);
-  // interior rows (every near column in range): one value per point type
-  for (int t = 0; t < 2; ++t) {
-    const std::vector<double>& W = t == 0 ? Wn : Wm;
-    const int64_t S = t == 0 ? Sn : Sm;
-    long double acc = 0.0L;
-    for (int kk = -M; kk <= M; ++kk) acc += (long double)at(W, S, kk);
-    nf.rsum_in[t] = (double)(acc * (long double)scale + (long double)shift);
-  }
+  for (int t = 0; t < 2; ++t)
+    nf.rsum_in[t] = (double)(-far[t] * (long double)scale + (long double)shift);
 }
 
 TpxLevel coarsen(const TpxLevel& f) {

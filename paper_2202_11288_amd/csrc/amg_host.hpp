@@ -95,9 +95,13 @@ TpxLevel finest_level(const KernelSpec& k, int64_t N, int64_t near_cut = -1);
 //   R_s = sum_{|k|<=M, 1<=s+k<=2N-1} W(k)   (+ shift),
 // the products that cancel in a smooth x meet only differences of
 // neighbouring values, and the far field (all |k| > M) is a Toeplitz-plus-
-// Cross level of small entries.  w[k + M] = scale * W(k) per row type;
-// rsum_left[s-1] (s = 1..M), rsum_right[s-(2N-M)] (s = 2N-M..2N-1) and
-// rsum_in[type] (every other s) hold R_s, summed in long double.
+// Cross level of small entries.  The own-point weight W(0) = int gamma
+// (1 - l_0) is taken as -sum_{k != 0} W(k) (the basis is a partition of
+// unity), so R_s = -(stencil weight beyond M) - (near weight outside
+// 1..2N-1), summed in long double without the rounding of W(0).
+// w[k + M] = scale * W(k) per row type (w[M] = 0); rsum_left[s-1] (s =
+// 1..M), rsum_right[s-(2N-M)] (s = 2N-M..2N-1) and rsum_in[type] (every
+// other s) hold scale * R_s + shift.
 struct NearField {
   int M = 0;
   std::vector<double> wn, wm;            // node rows, midpoint rows (2M+1 each)

@@ -139,7 +139,10 @@ def test_split_residual_matches_extended_oracle(case, N, prec):
     solve to the tolerance both reach."""
     say("split residual", case[0], N, prec)
     b = B.amg_manufactured_rhs(case[1], case[3], N)
-    T = tpx.from_stencil(case[2], N)
+    # the collocation matrix with W(0) from the partition of unity, as the
+    # split residual defines it (its FP64 rounding alone moves b - A x by
+    # eps |W(0)| |x|, 2e-10 of |b| at 2^16 for the fractional kernel)
+    T = tpx.from_stencil_rowsum(case[2], N)
     xs = {}
     for flags in (0, B.AMG_FLAG_ACCURATE_RESIDUAL):
         h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(
@@ -173,7 +176,7 @@ def test_split_residual_shifted_operator():
     say("split residual shifted", N)
     sigma, s = 25.0 / 12.0, 1.0 / N
     b = synthetic.random_vector(2 * N - 1, seed=5)
-    T = tpx.from_stencil(case[2], N)
+    T = tpx.from_stencil_rowsum(case[2], N)
     h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(
         shift=sigma, scale=s, flags=B.AMG_FLAG_ACCURATE_RESIDUAL))
     try:
@@ -196,14 +199,15 @@ def test_precision_config_2_22_reaches_1e10():
     (8,388,607 unknowns), delta = 0.1, fractional kernel alpha = 0.4, FP32
     V-cycle (V-cycle-preconditioned CG) with FP64 refinement and the split
     FP64 residual.  The solve ends AMG_OK with relative residual below 1e-10
-    as the oracle measures it in extended precision, and the GPU's own
-    measure agrees with the oracle's to 1e-11.  A plain FP64 FFT evaluation
-    of b - A x cannot confirm 1e-10 here: it differs from the extended one
-    by about eps |A| |x| / |b| = 2e-9."""
+    as the oracle measures it in extended precision (the collocation matrix
+    with W(0) from the partition of unity), and the GPU's own measure agrees
+    with the oracle's to 1e-11.  A plain FP64 FFT evaluation of b - A x
+    cannot confirm 1e-10 here: it differs from the extended one by about
+    eps |A| |x| / |b| = 2e-9."""
     N = 2 ** 22
     kern, okern, delta = FRAC04[1], FRAC04[2], FRAC04[3]
     say("precision config 2^22")
-    T = tpx.from_stencil(okern, N)
+    T = tpx.from_stencil_rowsum(okern, N)
     b = B.amg_manufactured_rhs(kern, delta, N)
     h = B.amg_setup(kern, delta, N, B.amg_default_opts(
         precision=B.AMG_MIXED, inner=B.AMG_INNER_PCG, max_iter=1500,
@@ -215,7 +219,7 @@ def test_precision_config_2_22_reaches_1e10():
         xh = host(xs)
         rext = tpx.relres_extended(T, b, xh)
         # the plain FP64 FFT evaluation of the same x, for the record
-        r64 = np.linalg.norm(b - tpx.Level.build(T).matvec(xh)) / np.linalg.norm(b)
+        r64 = np.linalg.norm(b - tpx.Level.build(tpx.from_stencil(okern, N)).matvec(xh)) / np.linalg.norm(b)
         say("extended relres", rext, "plain FP64 FFT evaluation", r64)
         assert st == B.AMG_OK
         assert rel < 1e-10 and rext < 1e-10

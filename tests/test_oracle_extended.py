@@ -100,3 +100,68 @@ def test_extended_residual_below_fp64_floor():
     lin = rex - (tpx.residual_extended(T, b, x1) + tpx.residual_extended(T, z, x2))
     d = float(np.sqrt(np.dot(lin, lin)))
     assert d < 1e-12 * nb and d < 1e-3 * gap64
+
+
+@pytest.mark.parametrize("kern", [D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), D.Kernel(D.CONST, 0.05),
+                                  D.Kernel(D.WEIGHTED, 0.05, wl=1.2, wr=0.8),
+                                  D.Kernel(D.FRACTIONAL, 0.013, alpha=0.2)], ids=lambda k: k.kind)
+def test_rowsum_diagonal_equals_integral_diagonal(kern):
+    """from_stencil_rowsum: the own-point weight -sum_{k != 0} W(k) (partition
+    of unity) equals the integral formula's int gamma (1 - l_0) to a few FP64
+    units of it, every other entry is the FP64 level's exactly, and interior
+    rows of the matrix sum to zero to long double accuracy."""
+    for N in (2 ** 8, 2 ** 12, 2 ** 15):
+        T = tpx.from_stencil(kern, N)
+        Tr = tpx.from_stencil_rowsum(kern, N)
+        n = N - 1
+        for g, gr in ((T.a, Tr.a), (T.d, Tr.d)):
+            assert abs(float(gr[n - 1]) - g[n - 1]) <= 16 * np.spacing(abs(g[n - 1]))
+            off = np.r_[0:n - 1, n:2 * n - 1]
+            np.testing.assert_array_equal(gr[off].astype(np.float64), g[off])
+        for g, gr in ((T.b, Tr.b), (T.c, Tr.c), (T.p, Tr.p), (T.xi, Tr.xi)):
+            np.testing.assert_array_equal(gr.astype(np.float64), g)
+        assert abs(float(Tr.o) - T.o) <= 16 * np.spacing(abs(T.o))
+        # a node row in the middle of the interval: its whole stencil is inside
+        M = np.zeros(2 * n + 1, dtype=np.longdouble)
+        i = n // 2
+        row = np.concatenate([Tr.a[n - 1 - i:2 * n - 1 - i], [Tr.p[i]], Tr.b[n - 1 - i:2 * n - 1 - i]])
+        tot = float(row.sum())
+        assert abs(tot) <= 64 * np.finfo(np.longdouble).eps * float(np.abs(row).sum()), tot
+
+
+def test_rowsum_level_exact_dense():
+    """The extended residual of the row-sum level equals the exact 50-digit
+    residual of that level's long double entries (tiny N)."""
+    n, N = 31, 32
+    Tr = tpx.from_stencil_rowsum(D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), N)
+    mpmath.mp.dps = 50
+    Md = tpx.TpX(n, *(np.asarray(getattr(Tr, f), dtype=np.float64) for f in
+                      ("a", "b", "c", "d", "p", "q", "xi", "zeta")), float(Tr.o)).dense()
+    x = synthetic.random_vector(2 * n + 1, seed=3)
+    b = Md @ x
+    r = tpx.residual_extended(Tr, b, x)
+    # exact residual of the long double matrix: entries as mpmath numbers
+    def ent(i, j):
+        if i < n and j < n:
+            return Tr.a[j - i + n - 1]
+        if i < n and j == n:
+            return Tr.p[i]
+        if i < n:
+            return Tr.b[(j - n - 1) - i + n - 1]
+        if i == n and j < n:
+            return Tr.q[j]
+        if i == n and j == n:
+            return Tr.o
+        if i == n:
+            return Tr.zeta[j - n - 1]
+        if j < n:
+            return Tr.c[j - (i - n - 1) + n - 1]
+        if j == n:
+            return Tr.xi[i - n - 1]
+        return Tr.d[(j - n - 1) - (i - n - 1) + n - 1]
+    scale = float(np.abs(Md).sum(axis=1).max() * np.abs(x).max())
+    for i in range(2 * n + 1):
+        acc = mpmath.mpf(b[i])
+        for j in range(2 * n + 1):
+            acc -= mpmath.mpf(str(ent(i, j))) * mpmath.mpf(x[j])
+        assert abs(float(mpmath.mpf(str(r[i])) - acc)) <= 1e-17 * scale, i
