@@ -197,6 +197,23 @@ void ws_boundary_coupling(double gamma, int64_t N, double* K0, double* K1) {
   }
 }
 
+namespace {
+
+// The own-point weight int gamma (1 - l_0) equals -sum_{k != 0} W(k): the
+// quadratic basis is a partition of unity on every cell, so a row whose
+// stencil lies inside the interval sums to zero.  Summed cell by cell in FP64
+// it drifts by many units in its last place at large N (tens at N = 2^22 for
+// the fractional kernel, 5e7 in size there), which alone moves A x by that
+// much times x; it is set from the identity, summed in long double.
+void own_weight_from_row_sum(std::vector<double>& W, int64_t S) {
+  long double acc = 0.0L;
+  for (int64_t i = 0; i < (int64_t)W.size(); ++i)
+    if (i != S) acc += (long double)W[(size_t)i];
+  W[(size_t)S] = (double)(-acc);
+}
+
+}  // namespace
+
 std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
   const double h = 1.0 / (double)N;
   const double R = k.delta * (double)N;  // exact: N is a power of two
@@ -238,6 +255,7 @@ std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
     W[S + 2 * kc + 2] -= wr * Ic;
     W[S - 2 * kc - 2] -= wl * Ic;
   }
+  own_weight_from_row_sum(W, S);
   *Sout = S;
   return W;
 }
@@ -276,6 +294,7 @@ std::vector<double> midpoint_stencil_standard(const KernelSpec& k, int64_t N, in
     W[S + 2 * kc + 1] -= wr * Ip;
     W[S - 2 * kc - 1] -= wl * Ip;
   }
+  own_weight_from_row_sum(W, S);
   *Sout = S;
   return W;
 }

@@ -1030,6 +1030,10 @@ __global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const doubl
     st->done = 1;
   } else {
     st->iter += 1;
+    // the next recurrence starts from this residual: the growth test of
+    // finish_state measures from here (a Krylov method's 2-norm residual is
+    // not monotone, and a restart can start above the recurrence's minimum)
+    st->best = rel;
   }
   st->vtrue = rel;
 }
