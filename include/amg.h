@@ -252,6 +252,13 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N,
  * alias).  Errors: AMG_EINVAL (null), AMG_EHIP. */
 int amg_matvec(amg_t h, const double* x, double* y, void* stream);
 
+/* r = b - A x on the finest level in FP64, evaluated exactly as the solve's
+ * outer residual (Sec. 5 stopping rule): the FFT matvec, or with
+ * AMG_FLAG_ACCURATE_RESIDUAL the split form (near field in difference form,
+ * far field through the FFT).  b, x, r device, 2N-1 doubles; r must alias
+ * neither.  Errors: AMG_EINVAL, AMG_EHIP. */
+int amg_residual(amg_t h, const double* b, const double* x, double* r, void* stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc): y = A x on the finest level, the
  * same kernels and arithmetic as amg_matvec (bitwise the same result), with

@@ -75,6 +75,7 @@ def _load():
                           ctypes.POINTER(P)]),
         "amg_matvec": (I, [P, P, P, P]),
         "amg_matvec_noalloc": (I, [P, P, P, P]),
+        "amg_residual": (I, [P, P, P, P, P]),
         "amg_level_matvec": (I, [P, I, P, P, P]),
         "amg_level_matvec_f32": (I, [P, I, P, P, P]),
         "amg_vcycle": (I, [P, P, P, P]),
@@ -206,6 +207,12 @@ def amg_destroy(h):
 def amg_matvec(h, x, y, stream=None):
     return _check(lib.amg_matvec(h, _vec(h, x, "amg_matvec x"), _vec(h, y, "amg_matvec y"),
                                  _stream(stream)), "amg_matvec")
+
+
+def amg_residual(h, b, x, r, stream=None):
+    """r = b - A x, evaluated as the solve's outer residual."""
+    return _check(lib.amg_residual(h, _vec(h, b, "amg_residual b"), _vec(h, x, "amg_residual x"),
+                                   _vec(h, r, "amg_residual r"), _stream(stream)), "amg_residual")
 
 
 def amg_matvec_noalloc(h, x, y, stream=None):

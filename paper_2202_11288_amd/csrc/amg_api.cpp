@@ -640,21 +640,20 @@ int vcycle_run(amg_ctx* c, hipStream_t s) {
   return eager(s);
 }
 
-// r = b - A x on the finest level (FP64), optionally with x += e fused in
-// front; writes the residual-norm partials and runs the stopping test.
-// publish != null: the stop test also writes the state to that pinned host
-// copy (the round ends there).
-int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double tol,
-                   hipStream_t s, bool gm_check = false, bool stall = false,
-                   SolveState* publish = nullptr) {
+// The passes of r = b - A x on the finest level (FP64; split form under
+// AMG_FLAG_ACCURATE_RESIDUAL), optionally with x += e fused in front, into
+// ro (and its FP32 copy r32, if set); the block partials of ||r||^2 go to
+// c->npart.  Returns the number of partials through *npart_out.
+int residual_passes(amg_ctx* c, const double* b, double* x, const void* e, double* ro,
+                    float* r32, hipStream_t s, int* npart_out) {
   const LevelRes& L0 = c->lv[0];
   const LevelDev<double> d = L0.dev<double>();
   ColIn<double> in{};
   EpiOut<double> out{};
   out.xin = x;
   out.bo = b;
-  out.ro = c->mixed ? c->rout : L0.bd;
-  out.r32 = c->mixed ? L0.bf : nullptr;
+  out.ro = ro;
+  out.r32 = r32;
   int cmode = COL_MV;
   if (e) {
     cmode = COL_OUTER_UPDATE;
@@ -683,6 +682,20 @@ int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double
     AMG_TRY(fourstep<double>(c, 0, cmode, in, EPI_OUTER, out, s));
     npart = col_blocks(d.logL1, d.tcols);
   }
+  *npart_out = npart;
+  return AMG_OK;
+}
+
+// r = b - A x (residual_passes into the solver's residual buffers), then the
+// stopping test; publish != null: the stop test also writes the state to
+// that pinned host copy (the round ends there).
+int outer_residual(amg_ctx* c, const double* b, double* x, const void* e, double tol,
+                   hipStream_t s, bool gm_check = false, bool stall = false,
+                   SolveState* publish = nullptr) {
+  const LevelRes& L0 = c->lv[0];
+  int npart = 1;
+  AMG_TRY(residual_passes(c, b, x, e, c->mixed ? c->rout : L0.bd, c->mixed ? L0.bf : nullptr, s,
+                          &npart));
   if (gm_check)
     HIP_TRY(launch_gm_check(c->st_dev, c->npart, npart, tol, c->opts.max_iter, c->hist_dev, s,
                             stall ? 1 : 0));
@@ -1263,6 +1276,15 @@ int amg_level_matvec(amg_t h, int level, const double* x, double* y, void* strea
   if (x == y) return AMG_EINVAL;
   HIP_TRY(hipSetDevice(h->device));
   return level_matvec64(h, level, x, y, (hipStream_t)stream);
+}
+
+int amg_residual(amg_t h, const double* b, const double* x, double* r, void* stream) {
+  if (!h || !b || !x || !r || h->host_only || r == b || r == x) return AMG_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  int npart = 1;
+  // COL_MV does not write x (x += e is not requested)
+  return residual_passes(h, b, const_cast<double*>(x), nullptr, r, nullptr, (hipStream_t)stream,
+                         &npart);
 }
 
 int amg_matvec_noalloc(amg_t h, const double* x, double* y, void* stream) {
