@@ -196,6 +196,37 @@ def test_split_residual_shifted_operator():
         B.amg_destroy(h)
 
 
+@pytest.mark.parametrize("N", [2 ** 12, 2 ** 16, 2 ** 22])
+def test_amg_residual_split_operator(N):
+    """amg_residual with AMG_FLAG_ACCURATE_RESIDUAL: A x in split form on
+    random, smooth and boundary-localised vectors and the w_o unit vector,
+    against the oracle's extended-precision product with the row-sum level.
+    Rough vectors agree to FP64 rounding (1e-15 of |A x|); smooth ones to
+    1e-11 of |A x| at 2^22, where the plain FFT evaluation is off by 2e-9."""
+    kern, okern = FRAC04[1], FRAC04[2]
+    say("amg_residual split", N)
+    T = tpx.from_stencil_rowsum(okern, N)
+    m = 2 * N - 1
+    pts = D.points_block(N)
+    vecs = {"random": synthetic.random_vector(m, seed=1), "smooth": np.sin(np.pi * pts),
+            "x2": pts ** 2 * (1 - pts) ** 2,
+            "left": np.where(pts < 40 / N, synthetic.random_vector(m, seed=2), 0.0),
+            "right": np.where(pts > 1 - 40 / N, synthetic.random_vector(m, seed=3), 0.0),
+            "wo": np.eye(1, m, N - 1).ravel()}
+    h = B.amg_setup(kern, FRAC04[3], N, B.amg_default_opts(flags=B.AMG_FLAG_ACCURATE_RESIDUAL))
+    try:
+        zero = torch.zeros(m, device="cuda", dtype=torch.float64)
+        for name, v in vecs.items():
+            ref = -(tpx.residual_extended(T, np.zeros(m), v)).astype(np.float64)
+            r = torch.empty_like(zero)
+            B.amg_residual(h, zero, dev(v), r)
+            err = np.linalg.norm(-host(r) - ref) / np.linalg.norm(ref)
+            say(name, "err", err)
+            assert err < (2e-11 if name in ("smooth", "x2") else 2e-15), (name, err)
+    finally:
+        B.amg_destroy(h)
+
+
 def representation_floor(T, b, x, seed=7):
     """||A dx|| / ||b|| for dx uniform in +-ulp(x_i)/2: the relative residual
     that rounding x to FP64 alone leaves (the rough rounding noise meets the
