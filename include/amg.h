@@ -331,7 +331,11 @@ int amg_num_levels(amg_t h);
 int64_t amg_level_size(amg_t h, int level);
 
 /* Copy level `level`'s Toeplitz-plus-Cross data (eq. (split01)), as built on
- * the host by Lemma 3.1, into host arrays (any may be NULL): the generators
+ * the host by Lemma 3.1, into host arrays (any may be NULL).  The hierarchy of
+ * a device handle with a constant, weighted or fractional kernel is formed
+ * on the device (the same recurrences; the host keeps only the coarsest
+ * level), and its other levels give AMG_ENOTSUP: set the handle up with
+ * AMG_FLAG_HOST_ONLY to inspect them.  The generators
  * a, b, c, d of A, B_bar, C_bar, D_bar (2n-1 values each, offsets -(n-1)..n-1),
  * the Cross vectors p, q, xi, zeta (n values each) and o (1 value). */
 int amg_level_tpx(amg_t h, int level, double* a, double* b, double* c, double* d,

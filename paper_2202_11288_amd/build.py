@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libamg.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = [("fourstep_f64.hip", True), ("fourstep_f32.hip", True), ("amg_kernels.hip", True),
-           ("amg_api.cpp", True), ("amg_host.cpp", False)]
+           ("amg_setup.hip", True), ("amg_api.cpp", True), ("amg_host.cpp", False)]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]

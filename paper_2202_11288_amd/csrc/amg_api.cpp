@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -239,6 +240,7 @@ struct amg_ctx {
   std::vector<double> hist;
   int last_iters = 0;
   std::vector<void*> dev_allocs;
+  std::vector<void*> setup_temps;
   // V-cycle replay (see AMG_FLAG_EAGER): captured on an internal stream at
   // the handle's second V-cycle; every argument of its kernels is a
   // handle-owned buffer, so the graph stays valid for the handle's lifetime.
@@ -271,6 +273,11 @@ struct amg_ctx {
   // split outer residual (AMG_FLAG_ACCURATE_RESIDUAL): the finest level's far
   // field (spectra and Cross data of the stencil entries beyond kNearM
   // half-steps, geometry and work vectors of level 0) and the near field
+  // hierarchy formed on the device (stencil kernels, not AMG_FLAG_HOST_ONLY):
+  // the host keeps only the level sizes, the diagonal scalars and the
+  // coarsest level; gpu_sym: the levels are symmetric (known from the kernel)
+  bool gpu_setup = false;
+  bool gpu_sym = false;
   bool split = false;
   LevelRes far0;
   double* ynear = nullptr;
@@ -317,6 +324,28 @@ int upload(amg_ctx* c, T** dst, const std::vector<T>& src, hipStream_t s) {
   AMG_TRY(dalloc(c, dst, src.size()));
   HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return AMG_OK;
+}
+
+// Setup temporaries that stay allocated until setup has synchronised its
+// stream once at the end (the generators behind the spectra).
+template <typename T>
+int dalloc_temp(amg_ctx* c, T** p, size_t count) {
+  void* ptr = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&ptr, count * sizeof(T)) != hipSuccess) return AMG_ENOMEM;
+  c->setup_temps.push_back(ptr);
+  *p = static_cast<T*>(ptr);
+  return AMG_OK;
+}
+template <typename T>
+int upload_temp(amg_ctx* c, T** dst, const std::vector<T>& src, hipStream_t s) {
+  AMG_TRY(dalloc_temp(c, dst, src.size()));
+  HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return AMG_OK;
+}
+void free_setup_temps(amg_ctx* c) {
+  for (void* p : c->setup_temps) (void)hipFree(p);
+  c->setup_temps.clear();
 }
 
 // Frees every allocation made after `mark` (setup temporaries); the caller
@@ -750,16 +779,57 @@ int form_sub_vcycle(amg_ctx* c, hipStream_t s) {
   const int m = (int)(2 * c->lv[k].n + 1);
   double* M = nullptr;
   AMG_TRY(dalloc(c, &M, (size_t)m * m));
-  double* bk = c->lv[k].bd;
-  const double* uk = c->lv[k].ud;
-  for (int j = 0; j < m; ++j) {
-    HIP_TRY(launch_basis(bk, m, j, s));
-    HIP_TRY(launch_tail_vcycle<double>(c->lvdev64, k, nl - 1, nullptr, o.m1, o.m2, o.omega_pre,
-                                       o.omega_post, c->lu, c->tw64, c->maxL_tail,
-                                       c->tail_variant, s));
-    HIP_TRY(hipMemcpyAsync(M + (size_t)j * m, uk, (size_t)m * sizeof(double),
-                           hipMemcpyDeviceToDevice, s));
+  // all m unit vectors at once: one small-level kernel block per column, each
+  // with its own copies of the level vectors (b, u, r, scal) of levels k..last
+  // in a setup scratch block and its own level table
+  const int last = nl - 1;
+  int64_t col = 0;  // doubles per column
+  std::vector<int64_t> off(nl, 0);
+  for (int l = k; l <= last; ++l) {
+    off[l] = col;
+    col += 3 * (2 * c->lv[l].n + 1) + 4;
   }
+  col = (col + 31) & ~int64_t(31);
+  const size_t mark = c->dev_allocs.size();  // setup temporaries
+  double* scr = nullptr;
+  AMG_TRY(dalloc(c, &scr, (size_t)(col * m)));
+  std::vector<LevelDev<double>> tables((size_t)m * nl);
+  for (int j = 0; j < m; ++j)
+    for (int l = k; l <= last; ++l) {
+      LevelDev<double> d = c->lv[l].dev<double>();
+      const int64_t sz = 2 * c->lv[l].n + 1;
+      double* base = scr + (int64_t)j * col + off[l];
+      d.b = base;
+      d.u = base + sz;
+      d.r = base + 2 * sz;
+      d.scal = base + 3 * sz;
+      tables[(size_t)j * nl + l] = d;
+    }
+  LevelDev<double>* tdev = nullptr;
+  AMG_TRY(upload(c, &tdev, tables, s));
+  std::vector<TailArgs<double>> args((size_t)m);
+  for (int j = 0; j < m; ++j) {
+    TailArgs<double>& a = args[(size_t)j];
+    a.levels = tdev + (size_t)j * nl;
+    a.first = k;
+    a.last = last;
+    a.rf = nullptr;
+    a.m1 = o.m1;
+    a.m2 = o.m2;
+    a.wpre = o.omega_pre;
+    a.wpost = o.omega_post;
+    a.lu = c->lu;
+    a.st = nullptr;
+    a.gate = GATE_ACTIVE;
+  }
+  TailArgs<double>* adev = nullptr;
+  AMG_TRY(upload(c, &adev, args, s));
+  HIP_TRY(hipMemsetAsync(scr, 0, (size_t)(col * m) * sizeof(double), s));
+  HIP_TRY(launch_basis_batch(scr + off[k], col, m, s));
+  HIP_TRY(launch_tail_vcycle_batch<double>(adev, m, c->tail_variant, c->tw64, s));
+  HIP_TRY(launch_gather_columns(M, scr + off[k] + (2 * c->lv[k].n + 1), col, m, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  free_since(c, mark);
   float* M32 = nullptr;  // the FP32 V-cycle reads the operator's FP32 rounding
   if (c->mixed) {
     AMG_TRY(dalloc(c, &M32, (size_t)m * m));
@@ -822,8 +892,24 @@ int form_sub_wcycle(amg_ctx* c, hipStream_t s) {
 // Spectra G1, G2 of a level (eq. (ccs3.4)) in FP64 (and their FP32 rounding
 // when `f32`): the circulant columns of its four Toeplitz generators through
 // the level's forward FFT, combined into the packed product's form.
+int level_spectra_dev(amg_ctx* c, const double* ga, const double* gb, const double* gc,
+                      const double* gd, LevelRes& R, bool f32, cplx<double>* zscratch,
+                      hipStream_t s);
+
 int level_spectra(amg_ctx* c, const TpxLevel& H, LevelRes& R, bool f32, cplx<double>* zscratch,
                   hipStream_t s) {
+  // generators: setup temporaries, freed when setup has synchronised
+  double *ga, *gb, *gc, *gd;
+  AMG_TRY(upload_temp(c, &ga, H.a, s));
+  AMG_TRY(upload_temp(c, &gb, H.b, s));
+  AMG_TRY(upload_temp(c, &gc, H.c, s));
+  AMG_TRY(upload_temp(c, &gd, H.d, s));
+  return level_spectra_dev(c, ga, gb, gc, gd, R, f32, zscratch, s);
+}
+
+int level_spectra_dev(amg_ctx* c, const double* ga, const double* gb, const double* gc,
+                      const double* gd, LevelRes& R, bool f32, cplx<double>* zscratch,
+                      hipStream_t s) {
   const int64_t L = int64_t(1) << R.plan.logL;
   const size_t nspec = (size_t)(R.sym ? L : 2 * L);
   AMG_TRY(dalloc(c, &R.g1d, nspec));
@@ -832,12 +918,6 @@ int level_spectra(amg_ctx* c, const TpxLevel& H, LevelRes& R, bool f32, cplx<dou
     AMG_TRY(dalloc(c, &R.g1f, nspec));
     AMG_TRY(dalloc(c, &R.g2f, nspec));
   }
-  const size_t mark = c->dev_allocs.size();  // generators: setup temporaries
-  double *ga, *gb, *gc, *gd;
-  AMG_TRY(upload(c, &ga, H.a, s));
-  AMG_TRY(upload(c, &gb, H.b, s));
-  AMG_TRY(upload(c, &gc, H.c, s));
-  AMG_TRY(upload(c, &gd, H.d, s));
   const LevelDev<double> d = R.dev<double>();
   if (R.plan.tail) {
     HIP_TRY(launch_tail_fft_setup(d, ga, gb, c->buf64, c->tw64, s));
@@ -845,45 +925,67 @@ int level_spectra(amg_ctx* c, const TpxLevel& H, LevelRes& R, bool f32, cplx<dou
   } else {
     ColIn<double> in{};
     double* dummy = nullptr;
-    AMG_TRY(dalloc(c, &dummy, (size_t)col_blocks(d.logL1, d.tcols)));
-    in.gx = ga;
-    in.gy = gb;
+    AMG_TRY(dalloc_temp(c, &dummy, (size_t)col_blocks(d.logL1, d.tcols)));
+    in.gx = const_cast<double*>(ga);
+    in.gy = const_cast<double*>(gb);
     HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, c->buf64, c->tw64, dummy, s));
     HIP_TRY(launch_row<double>(0, d, c->buf64, c->tw64, dummy, 0, nullptr, s));
-    in.gx = gc;
-    in.gy = gd;
+    in.gx = const_cast<double*>(gc);
+    in.gy = const_cast<double*>(gd);
     HIP_TRY(launch_col_fwd<double>(COL_SETUP, d, in, zscratch, c->tw64, dummy, s));
     HIP_TRY(launch_row<double>(0, d, zscratch, c->tw64, dummy, 0, nullptr, s));
   }
   HIP_TRY(launch_combine(R.plan.logL, R.plan.logL1, R.plan.logL2, c->buf64, zscratch, R.sym,
                          R.g1d, R.g2d, f32 ? R.g1f : nullptr, f32 ? R.g2f : nullptr, s));
-  // generators are only needed for the spectra
-  HIP_TRY(hipStreamSynchronize(s));
-  free_since(c, mark);
+  return AMG_OK;
+}
+
+struct DevTwiddles {
+  Twiddles<double> t64{};
+  Twiddles<float> t32{};
+  bool ready = false;
+};
+std::mutex g_tw_mu;
+std::unordered_map<int, DevTwiddles> g_tw;
+
+int device_twiddles(int dev, hipStream_t s, Twiddles<double>* t64, Twiddles<float>* t32) {
+  std::lock_guard<std::mutex> g(g_tw_mu);
+  DevTwiddles& D = g_tw[dev];
+  if (!D.ready) {
+    const std::vector<double> base = twiddles(kTwM, kTwM);
+    const std::vector<double> lo = twiddles(int64_t(1) << kTw4Log, kTw4Lo);
+    const std::vector<double> hi = twiddles(int64_t(1) << kTw4Log, kTw4Hi, kTw4Lo);
+    const std::vector<float> basef = to_float(base), lof = to_float(lo), hif = to_float(hi);
+    const std::vector<const void*> src = {base.data(), lo.data(), hi.data(),
+                                          basef.data(), lof.data(), hif.data()};
+    const size_t bytes[6] = {base.size() * 8, lo.size() * 8, hi.size() * 8,
+                             basef.size() * 4, lof.size() * 4, hif.size() * 4};
+    void* p[6] = {};
+    for (int i = 0; i < 6; ++i) {
+      if (hipMalloc(&p[i], bytes[i]) != hipSuccess) {
+        for (int k = 0; k < i; ++k) (void)hipFree(p[k]);
+        return AMG_ENOMEM;
+      }
+      HIP_TRY(hipMemcpyAsync(p[i], src[i], bytes[i], hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    D.t64 = {static_cast<cplx<double>*>(p[0]), static_cast<cplx<double>*>(p[1]),
+             static_cast<cplx<double>*>(p[2])};
+    D.t32 = {static_cast<cplx<float>*>(p[3]), static_cast<cplx<float>*>(p[4]),
+             static_cast<cplx<float>*>(p[5])};
+    D.ready = true;
+  }
+  *t64 = D.t64;
+  *t32 = D.t32;
   return AMG_OK;
 }
 
 int setup_device(amg_ctx* c, hipStream_t s) {
   const bool mixed = c->mixed;
   const int nl = (int)c->host.size();
-  // twiddle tables (long double, rounded once)
-  {
-    const std::vector<double> base = twiddles(kTwM, kTwM);
-    const std::vector<double> lo = twiddles(int64_t(1) << kTw4Log, kTw4Lo);
-    const std::vector<double> hi = twiddles(int64_t(1) << kTw4Log, kTw4Hi, kTw4Lo);
-    double *b, *l, *h;
-    float *bf, *lf, *hf;
-    AMG_TRY(upload(c, &b, base, s));
-    AMG_TRY(upload(c, &l, lo, s));
-    AMG_TRY(upload(c, &h, hi, s));
-    AMG_TRY(upload(c, &bf, to_float(base), s));
-    AMG_TRY(upload(c, &lf, to_float(lo), s));
-    AMG_TRY(upload(c, &hf, to_float(hi), s));
-    c->tw64 = {reinterpret_cast<cplx<double>*>(b), reinterpret_cast<cplx<double>*>(l),
-               reinterpret_cast<cplx<double>*>(h)};
-    c->tw32 = {reinterpret_cast<cplx<float>*>(bf), reinterpret_cast<cplx<float>*>(lf),
-               reinterpret_cast<cplx<float>*>(hf)};
-  }
+  // twiddle tables (long double, rounded once): one copy per device, shared
+  // by every handle on it and kept until the process ends
+  AMG_TRY(device_twiddles(c->device, s, &c->tw64, &c->tw32));
   const int64_t L0 = 2 * c->N;
   AMG_TRY(dalloc(c, &c->buf64, (size_t)L0));
   if (mixed) AMG_TRY(dalloc(c, &c->buf32, (size_t)L0));
@@ -893,6 +995,74 @@ int setup_device(amg_ctx* c, hipStream_t s) {
   c->lv.resize(nl);
   c->first_tail = nl - 1;
   c->maxL_tail = 0;
+  // device-built hierarchy (stencil kernels): every level's generators and
+  // Cross data formed on the device; the host receives the diagonal scalars
+  // and the coarsest level (for its LU)
+  std::vector<DevTpx> dt;
+  if (c->gpu_setup) {
+    dt.resize(nl);
+    std::vector<double> Wn, Wm;
+    int64_t Sn = 0, Sm = 0;
+    row_stencils(c->kspec, c->N, Wn, Sn, Wm, Sm);
+    double *wn, *wm, *scratch, *dscal;
+    int* bad;
+    AMG_TRY(upload_temp(c, &wn, Wn, s));
+    AMG_TRY(upload_temp(c, &wm, Wm, s));
+    AMG_TRY(dalloc_temp(c, &scratch, (size_t)(4 * c->host[0].n)));
+    AMG_TRY(dalloc_temp(c, &dscal, (size_t)(3 * nl)));
+    AMG_TRY(dalloc_temp(c, &bad, 1));
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), s));
+    for (int l = 0; l < nl; ++l) {
+      const int64_t n = c->host[l].n;
+      LevelRes& R = c->lv[l];
+      DevTpx& T = dt[l];
+      AMG_TRY(dalloc_temp(c, &T.a, (size_t)(2 * n - 1)));
+      AMG_TRY(dalloc_temp(c, &T.b, (size_t)(2 * n - 1)));
+      AMG_TRY(dalloc_temp(c, &T.c, (size_t)(2 * n - 1)));
+      AMG_TRY(dalloc_temp(c, &T.d, (size_t)(2 * n - 1)));
+      AMG_TRY(dalloc_temp(c, &T.o, 1));
+      AMG_TRY(dalloc(c, &R.pd, (size_t)n));
+      AMG_TRY(dalloc(c, &R.qd, (size_t)n));
+      AMG_TRY(dalloc(c, &R.xid, (size_t)n));
+      AMG_TRY(dalloc(c, &R.zetad, (size_t)n));
+      T.p = R.pd;
+      T.q = R.qd;
+      T.xi = R.xid;
+      T.zeta = R.zetad;
+      if (l == 0)
+        HIP_TRY(launch_finest_level(wn, Sn, wm, Sm, n, c->opts.scale, c->opts.shift, T, bad, s));
+      else
+        HIP_TRY(launch_coarsen(dt[l - 1], c->host[l - 1].n, T, scratch, c->gpu_sym, bad, s));
+      HIP_TRY(launch_level_scalars(T, n, dscal + 3 * l, s));
+    }
+    std::vector<double> sc((size_t)(3 * nl));
+    int hbad = 0;
+    HIP_TRY(hipMemcpyAsync(sc.data(), dscal, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    // the coarsest level on the host, for its LU
+    TpxLevel& Hc = c->host[nl - 1];
+    const int64_t nc = Hc.n;
+    for (auto* v : {&Hc.a, &Hc.b, &Hc.c, &Hc.d}) v->assign((size_t)(2 * nc - 1), 0.0);
+    for (auto* v : {&Hc.p, &Hc.q, &Hc.xi, &Hc.zeta}) v->assign((size_t)nc, 0.0);
+    const DevTpx& Tc = dt[nl - 1];
+    const std::pair<std::vector<double>*, const double*> cp[8] = {
+        {&Hc.a, Tc.a}, {&Hc.b, Tc.b}, {&Hc.c, Tc.c}, {&Hc.d, Tc.d},
+        {&Hc.p, Tc.p}, {&Hc.q, Tc.q}, {&Hc.xi, Tc.xi}, {&Hc.zeta, Tc.zeta}};
+    for (const auto& pr : cp)
+      HIP_TRY(hipMemcpyAsync(pr.first->data(), pr.second, pr.first->size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hbad) return AMG_EINVAL;
+    for (int l = 0; l < nl; ++l) {
+      c->host[l].o = sc[(size_t)(3 * l)];
+      c->lv[l].o = sc[(size_t)(3 * l)];
+      c->lv[l].dv = sc[(size_t)(3 * l + 1)];
+      c->lv[l].dw = sc[(size_t)(3 * l + 2)];
+      if (!(c->lv[l].dv != 0.0 && c->lv[l].dw != 0.0 && c->lv[l].o != 0.0))
+        return AMG_EINVAL;  // Jacobi needs a nonzero diagonal
+    }
+    Hc.o = sc[(size_t)(3 * (nl - 1))];
+  }
   for (int l = 0; l < nl; ++l) {
     const TpxLevel& H = c->host[l];
     LevelRes& R = c->lv[l];
@@ -909,15 +1079,20 @@ int setup_device(amg_ctx* c, hipStream_t s) {
       maxblocks = std::max(maxblocks, col_blocks(R.plan.logL1, R.plan.tcols));
       maxblocks = std::max(maxblocks, (1 << R.plan.logL2) / 2);
     }
-    R.sym = H.symmetric();
-    R.o = H.o;
-    R.dv = H.a[H.n - 1];
-    R.dw = H.d[H.n - 1];
     const int64_t n = H.n, m = 2 * n + 1, L = int64_t(1) << R.plan.logL;
-    AMG_TRY(upload(c, &R.pd, H.p, s));
-    AMG_TRY(upload(c, &R.qd, H.q, s));
-    AMG_TRY(upload(c, &R.xid, H.xi, s));
-    AMG_TRY(upload(c, &R.zetad, H.zeta, s));
+    if (c->gpu_setup) {
+      R.sym = c->gpu_sym;
+    } else {
+      R.sym = H.symmetric();
+      R.o = H.o;
+      R.dv = H.a[H.n - 1];
+      R.dw = H.d[H.n - 1];
+      AMG_TRY(upload(c, &R.pd, H.p, s));
+      AMG_TRY(upload(c, &R.qd, H.q, s));
+      AMG_TRY(upload(c, &R.xid, H.xi, s));
+      AMG_TRY(upload(c, &R.zetad, H.zeta, s));
+    }
+    (void)L;
     AMG_TRY(dalloc(c, &R.bd, m));
     AMG_TRY(dalloc(c, &R.ud, m));
     AMG_TRY(dalloc(c, &R.rd, m));
@@ -945,10 +1120,21 @@ int setup_device(amg_ctx* c, hipStream_t s) {
       }
     }
     if (mixed) {
-      AMG_TRY(upload(c, &R.pf, to_float(H.p), s));
-      AMG_TRY(upload(c, &R.qf, to_float(H.q), s));
-      AMG_TRY(upload(c, &R.xif, to_float(H.xi), s));
-      AMG_TRY(upload(c, &R.zetaf, to_float(H.zeta), s));
+      if (c->gpu_setup) {
+        AMG_TRY(dalloc(c, &R.pf, (size_t)n));
+        AMG_TRY(dalloc(c, &R.qf, (size_t)n));
+        AMG_TRY(dalloc(c, &R.xif, (size_t)n));
+        AMG_TRY(dalloc(c, &R.zetaf, (size_t)n));
+        HIP_TRY(launch_copy_d2f(R.pd, R.pf, n, s));
+        HIP_TRY(launch_copy_d2f(R.qd, R.qf, n, s));
+        HIP_TRY(launch_copy_d2f(R.xid, R.xif, n, s));
+        HIP_TRY(launch_copy_d2f(R.zetad, R.zetaf, n, s));
+      } else {
+        AMG_TRY(upload(c, &R.pf, to_float(H.p), s));
+        AMG_TRY(upload(c, &R.qf, to_float(H.q), s));
+        AMG_TRY(upload(c, &R.xif, to_float(H.xi), s));
+        AMG_TRY(upload(c, &R.zetaf, to_float(H.zeta), s));
+      }
       AMG_TRY(dalloc(c, &R.bf, m));
       AMG_TRY(dalloc(c, &R.uf, m));
       AMG_TRY(dalloc(c, &R.rf, m));
@@ -957,7 +1143,10 @@ int setup_device(amg_ctx* c, hipStream_t s) {
       HIP_TRY(hipMemsetAsync(R.uf, 0, m * sizeof(float), s));
       HIP_TRY(hipMemsetAsync(R.rf, 0, m * sizeof(float), s));
     }
-    AMG_TRY(level_spectra(c, H, R, mixed, zscratch, s));
+    if (c->gpu_setup)
+      AMG_TRY(level_spectra_dev(c, dt[l].a, dt[l].b, dt[l].c, dt[l].d, R, mixed, zscratch, s));
+    else
+      AMG_TRY(level_spectra(c, H, R, mixed, zscratch, s));
   }
   if (c->split) {
     // the far field of the finest level: same geometry and work vectors,
@@ -1070,6 +1259,7 @@ int setup_device(amg_ctx* c, hipStream_t s) {
   HIP_TRY(hipHostMalloc(&ph, sizeof(SolveState), hipHostMallocDefault));
   c->st_host = static_cast<SolveState*>(ph);
   HIP_TRY(hipStreamSynchronize(s));
+  free_setup_temps(c);
   return AMG_OK;
 }
 
@@ -1081,6 +1271,8 @@ void release(amg_ctx* c) {
   c->cap_stream = nullptr;
   for (void* p : c->dev_allocs) (void)hipFree(p);
   c->dev_allocs.clear();
+  for (void* p : c->setup_temps) (void)hipFree(p);
+  c->setup_temps.clear();
   if (c->st_host) (void)hipHostFree(c->st_host);
   c->st_host = nullptr;
 }
@@ -1179,28 +1371,49 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
     // finest levels in the small-level kernels keep the plain residual
     c->split = !plan_level(N - 1).tail;
   }
+  // Stencil kernels on a device handle form their hierarchy on the device
+  // (the same arithmetic, amg_setup.hip); the host keeps the level sizes
+  c->gpu_setup = !c->host_only && (kernel->kind == AMG_K_CONST ||
+                                    kernel->kind == AMG_K_WEIGHTED ||
+                                    kernel->kind == AMG_K_FRACTIONAL);
+  // symmetric levels: a symmetric kernel under the shifted rule (the stencil
+  // is then exactly symmetric, and Lemma 3.1 keeps it so)
+  c->gpu_sym = ks.scheme == SCHEME_SHIFTED &&
+               (kernel->kind != AMG_K_WEIGHTED || kernel->wl == kernel->wr);
   try {
-    c->host.push_back(finest_level(ks, N));
-    if (o.shift != 0.0 || o.scale != 1.0) shift_level(c->host[0], o.shift, o.scale);
-    const int64_t nc = (int64_t(1) << o.coarsest_log2) - 1;
-    while (c->host.back().n > nc) c->host.push_back(coarsen(c->host.back()));
+    if (c->gpu_setup) {
+      const int64_t nc = (int64_t(1) << o.coarsest_log2) - 1;
+      for (int64_t n = N - 1;; n = (n - 1) / 2) {
+        TpxLevel t;
+        t.n = n;
+        c->host.push_back(t);
+        if (n <= nc) break;
+      }
+    } else {
+      c->host.push_back(finest_level(ks, N));
+      if (o.shift != 0.0 || o.scale != 1.0) shift_level(c->host[0], o.shift, o.scale);
+      const int64_t nc = (int64_t(1) << o.coarsest_log2) - 1;
+      while (c->host.back().n > nc) c->host.push_back(coarsen(c->host.back()));
+    }
   } catch (const std::bad_alloc&) {
     delete c;
     return AMG_ENOMEM;
   }
-  for (const TpxLevel& t : c->host) {
-    for (const auto* v : {&t.a, &t.b, &t.c, &t.d, &t.p, &t.q, &t.xi, &t.zeta})
-      for (double x : *v)
-        if (!std::isfinite(x)) {
-          delete c;
-          return AMG_EINVAL;
-        }
-    if (!(t.a[t.n - 1] != 0.0 && t.d[t.n - 1] != 0.0 && t.o != 0.0)) {
-      delete c;
-      return AMG_EINVAL;  // Jacobi needs a nonzero diagonal
+  if (!c->gpu_setup) {
+    for (const TpxLevel& t : c->host) {
+      for (const auto* v : {&t.a, &t.b, &t.c, &t.d, &t.p, &t.q, &t.xi, &t.zeta})
+        for (double x : *v)
+          if (!std::isfinite(x)) {
+            delete c;
+            return AMG_EINVAL;
+          }
+      if (!(t.a[t.n - 1] != 0.0 && t.d[t.n - 1] != 0.0 && t.o != 0.0)) {
+        delete c;
+        return AMG_EINVAL;  // Jacobi needs a nonzero diagonal
+      }
     }
   }
-  if (o.inner == AMG_INNER_PCG && !c->host[0].symmetric()) {
+  if (o.inner == AMG_INNER_PCG && !(c->gpu_setup ? c->gpu_sym : c->host[0].symmetric())) {
     delete c;
     return AMG_EINVAL;  // conjugate gradients needs a symmetric operator
   }
@@ -1252,6 +1465,7 @@ int amg_level_tpx(amg_t h, int level, double* a, double* b, double* c, double* d
                   double* q, double* xi, double* zeta, double* o) {
   if (!h || level < 0 || level >= (int)h->host.size()) return AMG_EINVAL;
   const TpxLevel& t = h->host[level];
+  if (t.a.empty()) return AMG_ENOTSUP;  // formed on the device (see amg.h)
   auto cp = [](double* dst, const std::vector<double>& v) {
     if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
   };
@@ -1340,6 +1554,7 @@ namespace {
 // the 40-byte state to pinned host memory.
 int solve_begin(amg_t h, const double* b, double* x, double tol, hipStream_t s) {
   SolveState init{};
+  init.cg_first = 1;
   *h->st_host = init;
   HIP_TRY(hipMemcpyAsync(h->st_dev, h->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
   AMG_TRY(outer_residual(h, b, x, nullptr, tol, s));
@@ -1585,6 +1800,614 @@ int amg_bdf4_step(amg_t h, const double* u1, const double* u2, const double* u3,
   return amg_solve(h, h->step_b, x, tol, stream, iters, relres);
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batched rounds (amg_solve_batch): every launch covers all instances of one
+// (precision, level size, pass, mode) group, one block row per instance, with
+// that instance's own arguments and buffers; gates in the instances' solve
+// states decide who takes part (finished instances, and the CG step vs the
+// check of b - A x).  A round is: the CG checks, one V-cycle over every
+// instance (descending level sizes, the small levels of all instances in one
+// launch, ascending sizes), the stationary instances' x += e with b - A x and
+// stop test, and the CG instances' step (direction, A p, update, stop test).
+// Per instance it is the same sequence of kernels and arithmetic as its solo
+// solve, so results are bitwise those of amg_solve.
+// ---------------------------------------------------------------------------
+bool batchable(const amg_ctx* c) {
+  if (c->opts.cycle != 1 || c->split || c->prof.on) return false;
+  if (c->opts.inner != AMG_INNER_VCYCLE && c->opts.inner != AMG_INNER_PCG) return false;
+  for (const LevelRes& R : c->lv)
+    if (R.bmaind) return false;  // band levels (weakly singular model)
+  return true;
+}
+
+// A growing host-side list of argument records, uploaded as one block.
+struct ArgArena {
+  std::vector<unsigned char> host;
+  size_t put(const void* p, size_t bytes) {
+    const size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + bytes);
+    std::memcpy(host.data() + off, p, bytes);
+    return off;
+  }
+};
+
+using Launch = std::function<hipError_t(unsigned char* dev, hipStream_t)>;
+
+struct BatchPlan {
+  std::vector<Launch> round;   // launches of one round, in order
+  ArgArena arena;
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+};
+
+template <typename T>
+struct PrecTag {};
+
+template <typename T>
+void add_pass_group(BatchPlan& P, int pass, int mode, const LevelDev<T>& geom,
+                    const std::vector<PassArgs<T>>& args, const Twiddles<T>& tw) {
+  if (args.empty()) return;
+  const size_t off = P.arena.put(args.data(), args.size() * sizeof(PassArgs<T>));
+  const int count = (int)args.size();
+  const LevelDev<T> g = geom;
+  const Twiddles<T> t = tw;
+  P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+    const PassArgs<T>* a = reinterpret_cast<const PassArgs<T>*>(dev + off);
+    if (pass == 0) return launch_col_fwd_batch<T>(mode, g, a, count, t, s);
+    if (pass == 1) return launch_row_batch<T>(g, a, count, t, s);
+    return launch_col_inv_batch<T>(mode, g, a, count, t, s);
+  });
+}
+
+template <typename T>
+void add_tail_matvec_group(BatchPlan& P, int cmode, int emode, const std::vector<PassArgs<T>>& args,
+                           const Twiddles<T>& tw) {
+  if (args.empty()) return;
+  const size_t off = P.arena.put(args.data(), args.size() * sizeof(PassArgs<T>));
+  const int count = (int)args.size();
+  const Twiddles<T> t = tw;
+  P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+    return launch_tail_matvec_batch<T>(cmode, emode,
+                                       reinterpret_cast<const PassArgs<T>*>(dev + off), count, t, s);
+  });
+}
+
+template <typename T>
+PassArgs<T> pass_args(amg_ctx* c, int l, const ColIn<T>& in, const EpiOut<T>& out, int gate,
+                      bool fp64_outer) {
+  PassArgs<T> a{};
+  a.lv = c->lv[l].template dev<T>();
+  a.in = in;
+  a.out = out;
+  a.buf = buf_of<T>(c);
+  a.part = dpart_of<T>(c);
+  a.npart = col_blocks(a.lv.logL1, a.lv.tcols);
+  a.xin = out.xin;
+  a.npart_out = c->npart;
+  a.st = c->st_dev;
+  a.gate = gate;
+  (void)fp64_outer;
+  return a;
+}
+
+// Four-step matvec sweeps of one level size for a set of (instance, level)
+// pairs of one precision: groups by pass-1 mode and by symmetry (row pass).
+template <typename T>
+struct SweepItem {
+  amg_ctx* c;
+  int l;
+  int cmode, emode;
+  ColIn<T> in;
+  EpiOut<T> out;
+  int gate;
+};
+template <typename T>
+void add_sweep(BatchPlan& P, const std::vector<SweepItem<T>>& items) {
+  if (items.empty()) return;
+  const Twiddles<T>& tw = tw_of<T>(items[0].c);
+  // pass 1 by prologue mode
+  for (int cm : {COL_MV, COL_PRE, COL_PRE_RESTRICT, COL_PROLONG, COL_OUTER_UPDATE}) {
+    std::vector<PassArgs<T>> v;
+    LevelDev<T> geom{};
+    for (const auto& it : items)
+      if (it.cmode == cm) {
+        v.push_back(pass_args<T>(it.c, it.l, it.in, it.out, it.gate, false));
+        geom = v.back().lv;
+      }
+    add_pass_group<T>(P, 0, cm, geom, v, tw);
+  }
+  for (int sy : {0, 1}) {
+    std::vector<PassArgs<T>> v;
+    LevelDev<T> geom{};
+    for (const auto& it : items) {
+      PassArgs<T> a = pass_args<T>(it.c, it.l, it.in, it.out, it.gate, false);
+      if ((a.lv.sym != 0) == (sy != 0)) {
+        v.push_back(a);
+        geom = a.lv;
+      }
+    }
+    add_pass_group<T>(P, 1, 1, geom, v, tw);
+  }
+  for (int em : {EPI_MV, EPI_RESID, EPI_SMOOTH, EPI_OUTER}) {
+    std::vector<PassArgs<T>> v;
+    LevelDev<T> geom{};
+    for (const auto& it : items)
+      if (it.emode == em) {
+        v.push_back(pass_args<T>(it.c, it.l, it.in, it.out, it.gate, false));
+        geom = v.back().lv;
+      }
+    add_pass_group<T>(P, 2, em, geom, v, tw);
+  }
+}
+
+// One V-cycle (Algorithm 2, as vcycle_dev) of every instance of precision T.
+template <typename T>
+void plan_vcycle(BatchPlan& P, const std::vector<amg_ctx*>& cs, const std::vector<int>& gates) {
+  std::vector<int> idx;
+  for (size_t i = 0; i < cs.size(); ++i)
+    if ((sizeof(T) == 4) == cs[i]->mixed) idx.push_back((int)i);
+  if (idx.empty()) return;
+  int maxlog = 0;
+  for (int i : idx) maxlog = std::max(maxlog, cs[i]->lv[0].plan.logL);
+  const int m1 = cs[idx[0]]->opts.m1, m2 = cs[idx[0]]->opts.m2;
+  // descent: level sizes from the largest down to the four-step range's end
+  for (int lg = maxlog; lg > kTailLog; --lg) {
+    for (int sweep = 1; sweep <= m1; ++sweep) {
+      std::vector<SweepItem<T>> items;
+      for (int i : idx) {
+        amg_ctx* c = cs[i];
+        for (int l = 0; l < c->first_tail; ++l) {
+          if (c->lv[l].plan.logL != lg) continue;
+          const LevelDev<T> d = c->lv[l].template dev<T>();
+          SweepItem<T> it{};
+          it.c = c;
+          it.l = l;
+          it.gate = gates[i];
+          it.out.xin = d.u;
+          it.out.omega = (T)c->opts.omega_pre;
+          it.emode = sweep == m1 ? EPI_RESID : EPI_SMOOTH;
+          if (sweep == 1) {
+            it.in.omega = (T)c->opts.omega_pre;
+            it.cmode = l == 0 ? COL_PRE : COL_PRE_RESTRICT;
+            if (l > 0) it.in.x = c->lv[l - 1].template dev<T>().r;
+          } else {
+            it.cmode = COL_MV;
+            it.in.x = d.u;
+          }
+          items.push_back(it);
+        }
+      }
+      add_sweep<T>(P, items);
+    }
+  }
+  // the small levels and the coarsest solve, one block per instance
+  for (int variant = 0; variant < 4; ++variant) {
+    std::vector<TailArgs<T>> v;
+    for (int i : idx) {
+      amg_ctx* c = cs[i];
+      if (c->tail_variant != variant) continue;
+      TailArgs<T> a{};
+      a.levels = lvdev_of<T>(c);
+      a.first = c->first_tail;
+      a.last = c->vc_last;
+      a.rf = c->first_tail > 0 ? c->lv[c->first_tail - 1].template dev<T>().r : nullptr;
+      a.m1 = c->opts.m1;
+      a.m2 = c->opts.m2;
+      a.wpre = (T)c->opts.omega_pre;
+      a.wpost = (T)c->opts.omega_post;
+      a.lu = c->lu_vc;
+      a.st = c->st_dev;
+      a.gate = gates[i];
+      v.push_back(a);
+    }
+    if (v.empty()) continue;
+    const size_t off = P.arena.put(v.data(), v.size() * sizeof(TailArgs<T>));
+    const int count = (int)v.size();
+    const Twiddles<T> tw = tw_of<T>(cs[idx[0]]);
+    P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+      return launch_tail_vcycle_batch<T>(reinterpret_cast<const TailArgs<T>*>(dev + off), count,
+                                         variant, tw, s);
+    });
+  }
+  // ascent
+  for (int lg = kTailLog + 1; lg <= maxlog; ++lg) {
+    for (int sweep = 0; sweep < m2; ++sweep) {
+      std::vector<SweepItem<T>> items;
+      for (int i : idx) {
+        amg_ctx* c = cs[i];
+        for (int l = 0; l < c->first_tail; ++l) {
+          if (c->lv[l].plan.logL != lg) continue;
+          const LevelDev<T> d = c->lv[l].template dev<T>();
+          SweepItem<T> it{};
+          it.c = c;
+          it.l = l;
+          it.gate = gates[i];
+          it.out.xin = d.u;
+          it.out.omega = (T)c->opts.omega_post;
+          it.emode = EPI_SMOOTH;
+          if (sweep == 0) {
+            it.cmode = COL_PROLONG;
+            it.in.x = c->lv[l + 1].template dev<T>().u;
+          } else {
+            it.cmode = COL_MV;
+            it.in.x = d.u;
+          }
+          items.push_back(it);
+        }
+      }
+      add_sweep<T>(P, items);
+    }
+  }
+}
+
+// FP64 finest-level products of the instances in `sel`: four-step ones by
+// level size, tail-size ones in one launch.  mk(c, i) gives (cmode, emode,
+// in, out) of instance i.
+template <typename F>
+void plan_fp64_finest(BatchPlan& P, const std::vector<amg_ctx*>& cs, const std::vector<int>& sel,
+                      int gate, F&& mk) {
+  if (sel.empty()) return;
+  int maxlog = 0;
+  for (int i : sel) maxlog = std::max(maxlog, cs[i]->lv[0].plan.logL);
+  for (int lg = maxlog; lg > kTailLog; --lg) {
+    std::vector<SweepItem<double>> items;
+    for (int i : sel) {
+      amg_ctx* c = cs[i];
+      if (c->lv[0].plan.tail || c->lv[0].plan.logL != lg) continue;
+      SweepItem<double> it{};
+      it.c = c;
+      it.l = 0;
+      it.gate = gate;
+      mk(c, i, it.cmode, it.emode, it.in, it.out);
+      items.push_back(it);
+    }
+    add_sweep<double>(P, items);
+  }
+  for (int cm : {COL_MV, COL_OUTER_UPDATE})
+    for (int em : {EPI_MV, EPI_OUTER}) {
+      std::vector<PassArgs<double>> v;
+      for (int i : sel) {
+        amg_ctx* c = cs[i];
+        if (!c->lv[0].plan.tail) continue;
+        int cmode, emode;
+        ColIn<double> in{};
+        EpiOut<double> out{};
+        mk(c, i, cmode, emode, in, out);
+        if (cmode != cm || emode != em) continue;
+        PassArgs<double> a = pass_args<double>(c, 0, in, out, gate, true);
+        v.push_back(a);
+      }
+      if (!v.empty()) add_tail_matvec_group<double>(P, cm, em, v, cs[sel[0]]->tw64);
+    }
+}
+
+int build_batch_plan(BatchPlan& P, const std::vector<amg_ctx*>& cs,
+                     const std::vector<const double*>& bs, const std::vector<double*>& xs,
+                     const std::vector<double>& tols) {
+  P.round.clear();
+  P.arena.host.clear();
+  const int n = (int)cs.size();
+  std::vector<int> stat, cg;
+  for (int i = 0; i < n; ++i) (cs[i]->opts.inner == AMG_INNER_PCG ? cg : stat).push_back(i);
+  auto outer_in = [&](amg_ctx* c, int i, bool update, ColIn<double>& in, EpiOut<double>& out) {
+    const LevelRes& L0 = c->lv[0];
+    out.xin = xs[i];
+    out.bo = bs[i];
+    out.ro = c->mixed ? c->rout : L0.bd;
+    out.r32 = c->mixed ? L0.bf : nullptr;
+    if (update) {
+      in.xo = xs[i];
+      in.e = c->mixed ? (const void*)L0.uf : (const void*)L0.ud;
+      in.e_is_float = c->mixed ? 1 : 0;
+    } else {
+      in.x = xs[i];
+    }
+  };
+  // 1. CG: the check of b - A x where the recurrence passed
+  plan_fp64_finest(P, cs, cg, GATE_CG_CHECK,
+                   [&](amg_ctx* c, int i, int& cm, int& em, ColIn<double>& in, EpiOut<double>& out) {
+                     cm = COL_MV;
+                     em = EPI_OUTER;
+                     outer_in(c, i, false, in, out);
+                   });
+  {
+    std::vector<FinishArgs> v;
+    for (int i : cg) {
+      amg_ctx* c = cs[i];
+      FinishArgs a{};
+      a.st = c->st_dev;
+      a.gate = GATE_CG_CHECK;
+      a.part = c->npart;
+      a.npart = c->lv[0].plan.tail ? 1 : col_blocks(c->lv[0].plan.logL1, c->lv[0].plan.tcols);
+      a.tol = tols[i];
+      a.max_iter = c->opts.max_iter;
+      a.hist = c->hist_dev;
+      a.verify = 1;  // the stall rule
+      a.host = c->st_host;
+      v.push_back(a);
+    }
+    if (!v.empty()) {
+      const size_t off = P.arena.put(v.data(), v.size() * sizeof(FinishArgs));
+      const int count = (int)v.size();
+      P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+        return launch_gm_check_batch(reinterpret_cast<const FinishArgs*>(dev + off), count, s);
+      });
+    }
+  }
+  // 2. one V-cycle per instance (stationary: every round; CG: in its step)
+  std::vector<int> gates(n);
+  for (int i = 0; i < n; ++i) gates[i] = cs[i]->opts.inner == AMG_INNER_PCG ? GATE_CG_STEP : GATE_ACTIVE;
+  plan_vcycle<float>(P, cs, gates);
+  plan_vcycle<double>(P, cs, gates);
+  // 3. stationary: x += e, r = b - A x, stop test
+  plan_fp64_finest(P, cs, stat, GATE_ACTIVE,
+                   [&](amg_ctx* c, int i, int& cm, int& em, ColIn<double>& in, EpiOut<double>& out) {
+                     cm = COL_OUTER_UPDATE;
+                     em = EPI_OUTER;
+                     outer_in(c, i, true, in, out);
+                   });
+  auto add_finish = [&](const std::vector<int>& sel, int gate, int verify, bool vecparts) {
+    std::vector<FinishArgs> v;
+    for (int i : sel) {
+      amg_ctx* c = cs[i];
+      FinishArgs a{};
+      a.st = c->st_dev;
+      a.gate = gate;
+      a.part = c->npart;
+      a.npart = vecparts ? vec_blocks(2 * c->N - 1)
+                         : (c->lv[0].plan.tail ? 1
+                                               : col_blocks(c->lv[0].plan.logL1, c->lv[0].plan.tcols));
+      a.tol = tols[i];
+      a.max_iter = c->opts.max_iter;
+      a.hist = c->hist_dev;
+      a.verify = verify;
+      a.host = c->st_host;
+      v.push_back(a);
+    }
+    if (v.empty()) return;
+    const size_t off = P.arena.put(v.data(), v.size() * sizeof(FinishArgs));
+    const int count = (int)v.size();
+    P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+      return launch_finish_batch(reinterpret_cast<const FinishArgs*>(dev + off), count, s);
+    });
+  };
+  add_finish(stat, GATE_ACTIVE, 0, false);
+  // 4. CG step: z = B r was formed above; direction, A p, update, stop test
+  if (!cg.empty()) {
+    int64_t mmax = 0;
+    for (int i : cg) mmax = std::max<int64_t>(mmax, 2 * cs[i]->N - 1);
+    for (int prec = 0; prec < 2; ++prec) {  // 0: FP64 z, 1: FP32 z
+      std::vector<VdotArgs> vd;
+      std::vector<CgArgs> cga;
+      for (int i : cg) {
+        amg_ctx* c = cs[i];
+        if ((prec == 1) != c->mixed) continue;
+        const LevelRes& L0 = c->lv[0];
+        VdotArgs a{};
+        a.st = c->st_dev;
+        a.gate = GATE_CG_STEP;
+        a.a = c->mixed ? c->rout : L0.bd;
+        a.z = c->mixed ? (const void*)L0.uf : (const void*)L0.ud;
+        a.c = c->cg_rold;
+        a.m = 2 * c->N - 1;
+        a.part = c->cg_part;
+        vd.push_back(a);
+        CgArgs g{};
+        g.st = c->st_dev;
+        g.gate = GATE_CG_STEP;
+        g.part = c->cg_part;
+        g.nb = vec_blocks(a.m);
+        g.p = c->cg_p;
+        g.z = a.z;
+        g.m = a.m;
+        cga.push_back(g);
+      }
+      if (vd.empty()) continue;
+      const size_t ov = P.arena.put(vd.data(), vd.size() * sizeof(VdotArgs));
+      const size_t og = P.arena.put(cga.data(), cga.size() * sizeof(CgArgs));
+      const int count = (int)vd.size();
+      P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+        const VdotArgs* a = reinterpret_cast<const VdotArgs*>(dev + ov);
+        return prec ? launch_vdot_batch<float>(a, count, mmax, s)
+                    : launch_vdot_batch<double>(a, count, mmax, s);
+      });
+      P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+        return launch_cg_scalar_batch(reinterpret_cast<const CgArgs*>(dev + og), count, CG_AUTO, s);
+      });
+      P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+        const CgArgs* g = reinterpret_cast<const CgArgs*>(dev + og);
+        return prec ? launch_cg_dir_batch<float>(g, count, mmax, s)
+                    : launch_cg_dir_batch<double>(g, count, mmax, s);
+      });
+    }
+    // q = A p (FP64)
+    plan_fp64_finest(P, cs, cg, GATE_CG_STEP,
+                     [&](amg_ctx* c, int i, int& cm, int& em, ColIn<double>& in, EpiOut<double>& out) {
+                       (void)i;
+                       cm = COL_MV;
+                       em = EPI_MV;
+                       in.x = c->cg_p;
+                       out.xin = c->cg_p;
+                       out.y = c->cg_q;
+                     });
+    std::vector<VdotArgs> vd;
+    std::vector<CgArgs> cga;
+    for (int i : cg) {
+      amg_ctx* c = cs[i];
+      const LevelRes& L0 = c->lv[0];
+      VdotArgs a{};
+      a.st = c->st_dev;
+      a.gate = GATE_CG_STEP;
+      a.a = c->cg_p;
+      a.z = c->cg_q;
+      a.c = nullptr;
+      a.m = 2 * c->N - 1;
+      a.part = c->cg_part;
+      vd.push_back(a);
+      CgArgs g{};
+      g.st = c->st_dev;
+      g.gate = GATE_CG_STEP;
+      g.part = c->cg_part;
+      g.nb = vec_blocks(a.m);
+      g.x = xs[i];
+      g.p = c->cg_p;
+      g.r = c->mixed ? c->rout : L0.bd;
+      g.r_old = c->cg_rold;
+      g.q = c->cg_q;
+      g.r32 = c->mixed ? L0.bf : nullptr;
+      g.m = a.m;
+      g.npart = c->npart;
+      cga.push_back(g);
+    }
+    const size_t ov = P.arena.put(vd.data(), vd.size() * sizeof(VdotArgs));
+    const size_t og = P.arena.put(cga.data(), cga.size() * sizeof(CgArgs));
+    const int count = (int)vd.size();
+    P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+      return launch_vdot_batch<double>(reinterpret_cast<const VdotArgs*>(dev + ov), count, mmax, s);
+    });
+    P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+      return launch_cg_scalar_batch(reinterpret_cast<const CgArgs*>(dev + og), count, CG_ALPHA, s);
+    });
+    P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+      return launch_cg_update_batch(reinterpret_cast<const CgArgs*>(dev + og), count, mmax, s);
+    });
+    add_finish(cg, GATE_CG_STEP, 1, true);
+  }
+  return AMG_OK;
+}
+
+int run_batch_plan(BatchPlan& P, hipStream_t s) {
+  const size_t need = P.arena.host.size();
+  if (need > P.dev_bytes) {
+    if (P.dev) (void)hipFree(P.dev);
+    P.dev = nullptr;
+    P.dev_bytes = 0;
+    if (hipMalloc(&P.dev, need) != hipSuccess) return AMG_ENOMEM;
+    P.dev_bytes = need;
+  }
+  HIP_TRY(hipMemcpyAsync(P.dev, P.arena.host.data(), need, hipMemcpyHostToDevice, s));
+  // the tables must be in place before the round reads them; pageable source
+  // memory: the copy has been staged when the call returns
+  return AMG_OK;
+}
+
+// The round's launches captured into a graph on an internal stream (the
+// tables stay in place until the next rebuild); replayed on the caller's
+// stream.
+int capture_round(BatchPlan& P, hipGraphExec_t* out) {
+  *out = nullptr;
+  hipStream_t cap = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  int st = AMG_OK;
+  if (e == hipSuccess) {
+    for (const Launch& L : P.round) {
+      const hipError_t le = L(static_cast<unsigned char*>(P.dev), cap);
+      if (le != hipSuccess) {
+        st = hip_fail(le, "batched launch (capture)", __LINE__);
+        break;
+      }
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    if (st == AMG_OK && e == hipSuccess) {
+      e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) *out = nullptr;
+    }
+    if (g) (void)hipGraphDestroy(g);
+  }
+  (void)hipStreamDestroy(cap);
+  if (st != AMG_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "round capture", __LINE__);
+  return AMG_OK;
+}
+
+// Rounds queued per wait for the instances' states: finished instances sit
+// out by their gates, so the rounds after the last instance finishes are
+// near-empty launches.
+constexpr int kRoundsPerWait = 4;
+
+int batch_solve(const std::vector<amg_ctx*>& cs, const std::vector<const double*>& bs,
+                const std::vector<double*>& xs, const std::vector<double>& tols, hipStream_t s) {
+  const int n = (int)cs.size();
+  for (int i = 0; i < n; ++i) AMG_TRY(solve_begin(cs[i], bs[i], xs[i], tols[i], s));
+  HIP_TRY(round_wait(s));
+  BatchPlan P;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int> active;
+  for (int i = 0; i < n; ++i)
+    if (!cs[i]->st_host->done) active.push_back(i);
+  size_t built_for = 0;
+  bool eager = false;
+  int st = AMG_OK;
+  while (!active.empty()) {
+    if (built_for == 0 || active.size() * 4 <= built_for * 3) {
+      // (re)build the round over the active instances only
+      HIP_TRY(round_wait(s));  // the previous tables are no longer read
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+      std::vector<amg_ctx*> c2;
+      std::vector<const double*> b2;
+      std::vector<double*> x2;
+      std::vector<double> t2;
+      for (int i : active) {
+        c2.push_back(cs[i]);
+        b2.push_back(bs[i]);
+        x2.push_back(xs[i]);
+        t2.push_back(tols[i]);
+      }
+      st = build_batch_plan(P, c2, b2, x2, t2);
+      if (st == AMG_OK) st = run_batch_plan(P, s);
+      if (st != AMG_OK) break;
+      built_for = active.size();
+      eager = true;
+    }
+    if (eager) {
+      // the first round of a plan runs directly (it also raises the kernels'
+      // LDS limits); the next ones replay its captured graph
+      for (const Launch& L : P.round) {
+        const hipError_t e = L(static_cast<unsigned char*>(P.dev), s);
+        if (e != hipSuccess) {
+          st = hip_fail(e, "batched launch", __LINE__);
+          break;
+        }
+      }
+      if (st != AMG_OK) break;
+      eager = false;
+    } else {
+      if (!gexec) {
+        st = capture_round(P, &gexec);
+        if (st != AMG_OK) break;
+      }
+      for (int r = 0; r < kRoundsPerWait; ++r) {
+        const hipError_t e = hipGraphLaunch(gexec, s);
+        if (e != hipSuccess) {
+          st = hip_fail(e, "hipGraphLaunch", __LINE__);
+          break;
+        }
+      }
+      if (st != AMG_OK) break;
+    }
+    HIP_TRY(round_wait(s));
+    std::vector<int> still;
+    for (int i : active)
+      if (!cs[i]->st_host->done) still.push_back(i);
+    active.swap(still);
+  }
+  (void)round_wait(s);
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (P.dev) (void)hipFree(P.dev);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const* x,
                     const double* tol, void* stream, int* iters, double* relres) {
   if (count < 0 || (count > 0 && (!hs || !b || !x || !tol))) return AMG_EINVAL;
@@ -1599,6 +2422,36 @@ int amg_solve_batch(int count, amg_t* hs, const double* const* b, double* const*
   }
   HIP_TRY(hipSetDevice(dev));
   hipStream_t s = (hipStream_t)stream;
+  bool batched = true;
+  for (int i = 0; i < count; ++i)
+    if (!batchable(hs[i]) || hs[i]->opts.m1 != hs[0]->opts.m1 || hs[i]->opts.m2 != hs[0]->opts.m2)
+      batched = false;
+  if (batched) {
+    std::vector<amg_ctx*> cs(hs, hs + count);
+    std::vector<const double*> bs(b, b + count);
+    std::vector<double*> xs(x, x + count);
+    std::vector<double> ts(tol, tol + count);
+    AMG_TRY(batch_solve(cs, bs, xs, ts, s));
+    // results: every history copy queued, one wait
+    for (int i = 0; i < count; ++i) {
+      amg_t h = hs[i];
+      h->prof.collect();
+      const SolveState st = *h->st_host;
+      h->last_iters = st.iter;
+      h->hist.assign((size_t)st.iter + 1, 0.0);
+      HIP_TRY(hipMemcpyAsync(h->hist.data(), h->hist_dev, h->hist.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    int worst = AMG_OK;
+    for (int i = 0; i < count; ++i) {
+      const SolveState st = *hs[i]->st_host;
+      if (iters) iters[i] = st.iter;
+      if (relres) relres[i] = st.relres;
+      worst = std::max(worst, st.status);
+    }
+    return worst;
+  }
   StreamPool* pool = nullptr;
   AMG_TRY(get_pool(dev, &pool));
   const int S = std::min(count, kBatchStreams);

@@ -129,10 +129,107 @@ struct SolveState {
   double alpha;  // step length
   double beta;   // direction update
   double vtrue;  // last true residual formed to confirm a recurrence's (0: none yet)
+  int cg_first;  // the next CG step starts a new direction sequence (p = z)
+  int pad_;
 };
 
-// Stages of the conjugate-gradient scalar kernel.
-enum CgStage { CG_INIT = 0, CG_ALPHA = 1, CG_BETA = 2 };
+// Arguments of one instance of a batched pass (block row blockIdx.y of a
+// batched launch; the *_b kernels): the level, the prologue / epilogue
+// operands, the FFT buffer and the partial-sum buffers of that instance's
+// own launch, and its solve state with the gate that decides whether the
+// instance takes part in this round.
+enum PassGate { GATE_ACTIVE = 0, GATE_CG_STEP = 1, GATE_CG_CHECK = 2 };
+template <typename T>
+struct PassArgs {
+  LevelDev<T> lv;
+  ColIn<T> in;         // pass 1
+  EpiOut<T> out;       // pass 3
+  cplx<T>* buf;        // L complex
+  T* part;             // pass 1 writes the w_o row's block partials, pass 2 reads them
+  int npart;           // their count
+  const T* xin;        // pass 2: the matvec input (its w_o)
+  double* npart_out;   // pass 3 (EPI_OUTER): residual-norm block partials
+  const SolveState* st;
+  int gate;            // PassGate
+};
+// Whether an instance sits out a batched launch: solved, or (CG) in the other
+// half of its round (a step of the recurrence vs the check of b - A x).  Read
+// from state written by an earlier launch, so every thread of a block agrees.
+__device__ __forceinline__ bool gate_skip(const SolveState* st, int gate) {
+  if (!st) return false;
+  if (st->done) return true;
+  if (gate == GATE_CG_STEP) return st->cycle_end != 0;
+  if (gate == GATE_CG_CHECK) return st->cycle_end == 0;
+  return false;
+}
+
+// Stages of the conjugate-gradient scalar kernel (CG_AUTO: CG_INIT when the
+// state's cg_first is set, else CG_BETA).
+enum CgStage { CG_INIT = 0, CG_ALPHA = 1, CG_BETA = 2, CG_AUTO = 3 };
+
+// Per-instance arguments of the batched small-level V-cycle and of the
+// batched solver kernels (one block row per instance).
+template <typename T>
+struct TailArgs {
+  const LevelDev<T>* levels;  // the handle's device level table
+  int first, last;
+  const T* rf;
+  int m1, m2;
+  T wpre, wpost;
+  CoarseLU lu;
+  const SolveState* st;
+  int gate;
+};
+struct VdotArgs {           // part[2b] = a.z, part[2b+1] = c.z over chunk b
+  const SolveState* st;
+  int gate;
+  const double* a;
+  const void* z;            // float or double (one type per launch)
+  const double* c;
+  int64_t m;
+  double* part;
+};
+struct CgArgs {             // scalar stage, direction, update of one instance
+  SolveState* st;
+  int gate;
+  const double* part;       // cg_scalar: the vdot partials
+  int nb;
+  double* p;                // cg_dir, cg_update
+  const void* z;            // cg_dir
+  double* x;                // cg_update
+  double* r;
+  double* r_old;
+  const double* q;
+  float* r32;
+  int64_t m;
+  double* npart;            // cg_update: ||r||^2 partials
+};
+struct FinishArgs {         // stop test (k_finish / k_gm_check) of one instance
+  SolveState* st;
+  int gate;
+  const double* part;
+  int npart;
+  double tol;
+  int max_iter;
+  double* hist;
+  int verify;               // k_finish: recurrence residual; k_gm_check: stall rule
+  SolveState* host;         // pinned copy of the state (may be null)
+};
+
+template <typename T>
+hipError_t launch_tail_vcycle_batch(const TailArgs<T>* args, int count, int variant,
+                                    const Twiddles<T>& tw, hipStream_t s);
+template <typename T>
+hipError_t launch_tail_matvec_batch(int colmode, int epimode, const PassArgs<T>* args, int count,
+                                    const Twiddles<T>& tw, hipStream_t s);
+template <typename TZ>
+hipError_t launch_vdot_batch(const VdotArgs* args, int count, int64_t mmax, hipStream_t s);
+hipError_t launch_cg_scalar_batch(const CgArgs* args, int count, int stage, hipStream_t s);
+template <typename TZ>
+hipError_t launch_cg_dir_batch(const CgArgs* args, int count, int64_t mmax, hipStream_t s);
+hipError_t launch_cg_update_batch(const CgArgs* args, int count, int64_t mmax, hipStream_t s);
+hipError_t launch_finish_batch(const FinishArgs* args, int count, hipStream_t s);
+hipError_t launch_gm_check_batch(const FinishArgs* args, int count, hipStream_t s);
 
 // Largest GMRES restart length (Krylov basis vectors per cycle).
 constexpr int kGmMax = 64;
@@ -141,11 +238,11 @@ constexpr int kGmGroup = 8;
 
 // Vector kernels: fixed contiguous chunks, one per block of kVecNT threads.
 constexpr int kVecNT = 256;
-inline int vec_blocks(int64_t m) {
+__host__ __device__ inline int vec_blocks(int64_t m) {
   const int64_t b = (m + 2047) / 2048;
   return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
-inline int64_t vec_chunk(int64_t m) {
+__host__ __device__ inline int64_t vec_chunk(int64_t m) {
   const int nb = vec_blocks(m);
   return (m + nb - 1) / nb;
 }
@@ -160,6 +257,17 @@ hipError_t launch_row(int spectral, const LevelDev<T>& lv, cplx<T>* buf, const T
 template <typename T>
 hipError_t launch_col_inv(int mode, const LevelDev<T>& lv, const EpiOut<T>& out,
                           const cplx<T>* buf, const Twiddles<T>& tw, double* part, hipStream_t s);
+// Batched forms of the three passes: `count` instances of the geometry of
+// `geom`, per-instance arguments in the device table `args` (PassArgs).
+template <typename T>
+hipError_t launch_col_fwd_batch(int mode, const LevelDev<T>& geom, const PassArgs<T>* args,
+                                int count, const Twiddles<T>& tw, hipStream_t s);
+template <typename T>
+hipError_t launch_row_batch(const LevelDev<T>& geom, const PassArgs<T>* args, int count,
+                            const Twiddles<T>& tw, hipStream_t s);
+template <typename T>
+hipError_t launch_col_inv_batch(int mode, const LevelDev<T>& geom, const PassArgs<T>* args,
+                                int count, const Twiddles<T>& tw, hipStream_t s);
 template <typename T>
 hipError_t launch_tail_matvec(int colmode, int epimode, const LevelDev<T>& lv, const ColIn<T>& in,
                               const EpiOut<T>& out, const Twiddles<T>& tw, double* part,
@@ -236,6 +344,11 @@ hipError_t launch_gm_check(SolveState* st, const double* npart, int nb, double t
 hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s);
 hipError_t launch_publish(const SolveState* st, SolveState* host, hipStream_t s);
 hipError_t launch_basis(double* b, int m, int j, hipStream_t s);
+// b_j = e_j for j < m, b_j at base + j * stride
+hipError_t launch_basis_batch(double* base, int64_t stride, int m, hipStream_t s);
+// M[:, j] = u_j (column-major m x m), u_j at base + j * stride
+hipError_t launch_gather_columns(double* M, const double* base, int64_t stride, int m,
+                                 hipStream_t s);
 
 // bc = B x for the level's band (2n+1 entries)
 template <typename T>
@@ -255,6 +368,27 @@ hipError_t launch_bdf4_rhs(const double* u1, const double* u2, const double* u3,
 constexpr int kNearM = 64;  // near offsets |k| <= kNearM half-steps
 hipError_t launch_near(const double* x, double* y, int64_t N, const double* w, const double* rl,
                        const double* rr, double rin_n, double rin_m, hipStream_t s);
+
+// One Toeplitz-plus-Cross level in device memory (setup): generators a, b,
+// c, d (2n - 1 entries, offsets -(n-1)..n-1), Cross vectors p, q, xi, zeta
+// (n entries) and the scalar o (one entry).
+struct DevTpx {
+  double *a, *b, *c, *d;
+  double *p, *q, *xi, *zeta;
+  double* o;
+};
+// The finest level from the node- and midpoint-row stencils (Wn[s2 + Sn],
+// Wm[s2 + Sm]), scaled by `scale`, `shift` added to the diagonal entries.
+hipError_t launch_finest_level(const double* Wn, int64_t Sn, const double* Wm, int64_t Sm,
+                               int64_t n, double scale, double shift, const DevTpx& f, int* bad,
+                               hipStream_t s);
+// The Galerkin coarse level of f (v-size n) by Lemma 3.1 into c (v-size
+// (n-1)/2); scratch holds 4 n doubles; sym: average the mirror entries
+// (symmetric levels).  *bad becomes nonzero if an entry is not finite.
+hipError_t launch_coarsen(const DevTpx& f, int64_t n, const DevTpx& c, double* scratch, bool sym,
+                          int* bad, hipStream_t s);
+// out[0..2] = o, a_0, d_0 of the level
+hipError_t launch_level_scalars(const DevTpx& t, int64_t n, double* out, hipStream_t s);
 
 // Column tiles / grid sizes used by the launchers (host helpers).
 inline int col_blocks(int logL1, int tcols) { return (1 << logL1) / tcols; }

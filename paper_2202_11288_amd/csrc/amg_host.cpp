@@ -318,6 +318,15 @@ void both_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int6
   }
 }
 
+}  // namespace
+
+void row_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
+                  std::vector<double>& Wm, int64_t& Sm) {
+  both_stencils(k, N, Wn, Sn, Wm, Sm);
+}
+
+namespace {
+
 // In-place power-of-two complex FFT (iterative radix 2), twiddles evaluated
 // in long double; forward e^{-2 pi i jk/n}, inverse unnormalised.
 void fft_pow2(std::vector<std::complex<double>>& a, bool inv) {

@@ -66,6 +66,11 @@ void ws_stencils(double gamma, int64_t N, std::vector<double>& Wn, std::vector<d
                  int64_t* S);
 void ws_boundary_coupling(double gamma, int64_t N, double* K0, double* K1);
 
+// Node-row and midpoint-row stencils of the kernel's collocation scheme
+// (equal under the shifted-symmetric rule); W[s2 + S], s2 in [-S, S].
+void row_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
+                  std::vector<double>& Wm, int64_t& Sm);
+
 // Reach S (half-grid steps) of the node- and midpoint-row stencils.
 int64_t volume_reach(const KernelSpec& k, int64_t N);
 

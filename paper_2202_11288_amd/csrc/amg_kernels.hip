@@ -483,10 +483,9 @@ __device__ void coarse_warm(const CoarseLU& lu, T* sink) {
 }
 
 template <typename T, bool BAND, bool SYM>
-__global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels, int first,
-                                                      int last, const T* rf, int m1, int m2,
-                                                      T wpre, T wpost, CoarseLU lu,
-                                                      Twiddles<T> tw) {
+__device__ __forceinline__ void tail_vcycle_body(const LevelDev<T>* levels, int first, int last,
+                                                 const T* rf, int m1, int m2, T wpre, T wpost,
+                                                 const CoarseLU& lu, const Twiddles<T>& tw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ LevelDev<T> lvs[kTailMaxLev];
   __shared__ T warm_sink;
@@ -533,6 +532,24 @@ __global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels,
   }
 }
 
+template <typename T, bool BAND, bool SYM>
+__global__ __launch_bounds__(kNTT) void k_tail_vcycle(const LevelDev<T>* levels, int first,
+                                                      int last, const T* rf, int m1, int m2,
+                                                      T wpre, T wpost, CoarseLU lu,
+                                                      Twiddles<T> tw) {
+  tail_vcycle_body<T, BAND, SYM>(levels, first, last, rf, m1, m2, wpre, wpost, lu, tw);
+}
+// One block per instance: the small levels of a batch of handles in one launch.
+template <typename T, bool BAND, bool SYM>
+__global__ __launch_bounds__(kNTT) void k_tail_vcycle_b(const TailArgs<T>* __restrict__ args,
+                                                        Twiddles<T> tw) {
+  const TailArgs<T>* a = args + blockIdx.x;
+  if (gate_skip(a->st, a->gate)) return;
+  const CoarseLU lu = a->lu;
+  tail_vcycle_body<T, BAND, SYM>(a->levels, a->first, a->last, a->rf, a->m1, a->m2, a->wpre,
+                                 a->wpost, lu, tw);
+}
+
 // A cycle's small-level part as a program of steps built on the host (the
 // W-cycle: the second visit of a level smooths from its current iterate and
 // recomputes the residual; see TailOp).
@@ -570,8 +587,9 @@ __global__ __launch_bounds__(kNTT) void k_tail_program(const LevelDev<T>* levels
 // One tail-level matvec: y = A x (EPI_MV) or the outer residual with the
 // refinement update fused in front (COL_OUTER_UPDATE + EPI_OUTER).
 template <typename T, int CM, int EM>
-__global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> in, EpiOut<T> out,
-                                                      Twiddles<T> tw, double* part) {
+__device__ __forceinline__ void tail_matvec_body(const LevelDev<T>& lv, const ColIn<T>& in,
+                                                 const EpiOut<T>& out, const Twiddles<T>& tw,
+                                                 double* part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const TailLds<T> s = tail_lds<T>(smem_raw, tw.base);
   __shared__ double redd[kNTT / 64];
@@ -647,6 +665,22 @@ __global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> i
     const double sum = block_sum<double, kNTT>(ss, redd);
     if (threadIdx.x == 0) part[0] = sum;
   }
+}
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(kNTT) void k_tail_matvec(LevelDev<T> lv, ColIn<T> in, EpiOut<T> out,
+                                                      Twiddles<T> tw, double* part) {
+  tail_matvec_body<T, CM, EM>(lv, in, out, tw, part);
+}
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(kNTT) void k_tail_matvec_b(const PassArgs<T>* __restrict__ args,
+                                                        Twiddles<T> tw) {
+  const PassArgs<T>* a = args + blockIdx.x;
+  if (gate_skip(a->st, a->gate)) return;
+  const LevelDev<T> lv = a->lv;
+  const ColIn<T> in = a->in;
+  const EpiOut<T> out = a->out;
+  tail_matvec_body<T, CM, EM>(lv, in, out, tw, a->npart_out);
 }
 
 // Setup: FFT (natural order) of c_x + i c_y for a tail level.
@@ -761,6 +795,24 @@ __global__ __launch_bounds__(256) void k_finish(SolveState* st, const double* pa
   }
 }
 
+__global__ __launch_bounds__(256) void k_finish_b(const FinishArgs* __restrict__ args) {
+  __shared__ double red[256 / 64];
+  const FinishArgs* a = args + blockIdx.x;
+  if (gate_skip(a->st, a->gate)) return;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < a->npart; i += 256) v += a->part[i];
+  const double s = block_sum<double, 256>(v, red);
+  if (threadIdx.x == 0) finish_state(a->st, s, a->tol, a->max_iter, a->hist, a->verify);
+  if (a->host) {
+    __syncthreads();  // thread 0's state writes before the copy
+    constexpr int W = sizeof(SolveState) / 4;
+    if (threadIdx.x < W)
+      reinterpret_cast<unsigned*>(a->host)[threadIdx.x] =
+          reinterpret_cast<const unsigned*>(a->st)[threadIdx.x];
+    __threadfence_system();
+  }
+}
+
 __global__ void k_copy_d2f(const double* a, float* b, int64_t m) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) b[i] = (float)a[i];
@@ -774,8 +826,8 @@ __global__ void k_copy_d2f(const double* a, float* b, int64_t m) {
 // and the vectors untouched.
 // ---------------------------------------------------------------------------
 template <typename TZ>
-__global__ __launch_bounds__(kVecNT) void k_vdot(const double* a, const TZ* z, const double* c,
-                                                 int64_t m, int64_t chunk, double* part) {
+__device__ __forceinline__ void vdot_body(const double* a, const TZ* z, const double* c, int64_t m,
+                                          int64_t chunk, double* part) {
   __shared__ double red[kVecNT / 64];
   const int64_t i0 = (int64_t)blockIdx.x * chunk;
   const int64_t i1 = i0 + chunk < m ? i0 + chunk : m;
@@ -792,9 +844,23 @@ __global__ __launch_bounds__(kVecNT) void k_vdot(const double* a, const TZ* z, c
     part[2 * blockIdx.x + 1] = s1;
   }
 }
+template <typename TZ>
+__global__ __launch_bounds__(kVecNT) void k_vdot(const double* a, const TZ* z, const double* c,
+                                                 int64_t m, int64_t chunk, double* part) {
+  vdot_body<TZ>(a, z, c, m, chunk, part);
+}
+// Batched: block (x, y) is chunk x of instance y (the instance's own
+// partition: vec_blocks(m) chunks of vec_chunk(m)).
+template <typename TZ>
+__global__ __launch_bounds__(kVecNT) void k_vdot_b(const VdotArgs* __restrict__ args) {
+  const VdotArgs* g = args + blockIdx.y;
+  if (gate_skip(g->st, g->gate)) return;
+  if ((int)blockIdx.x >= vec_blocks(g->m)) return;
+  vdot_body<TZ>(g->a, static_cast<const TZ*>(g->z), g->c, g->m, vec_chunk(g->m), g->part);
+}
 
-__global__ __launch_bounds__(kVecNT) void k_cg_scalar(SolveState* st, const double* part, int nb,
-                                                      int stage) {
+__device__ __forceinline__ void cg_scalar_body(SolveState* st, const double* part, int nb,
+                                               int stage) {
   __shared__ double red[kVecNT / 64];
   double v0 = 0.0, v1 = 0.0;
   for (int i = threadIdx.x; i < nb; i += kVecNT) {
@@ -820,11 +886,22 @@ __global__ __launch_bounds__(kVecNT) void k_cg_scalar(SolveState* st, const doub
     st->done = 1;
   }
 }
+__global__ __launch_bounds__(kVecNT) void k_cg_scalar(SolveState* st, const double* part, int nb,
+                                                      int stage) {
+  cg_scalar_body(st, part, nb, stage);
+}
+__global__ __launch_bounds__(kVecNT) void k_cg_scalar_b(const CgArgs* __restrict__ args,
+                                                        int stage) {
+  const CgArgs* g = args + blockIdx.x;
+  if (gate_skip(g->st, g->gate)) return;
+  const int sg = stage == CG_AUTO ? (g->st->cg_first ? CG_INIT : CG_BETA) : stage;
+  cg_scalar_body(g->st, g->part, g->nb, sg);
+}
 
-__global__ __launch_bounds__(kVecNT) void k_cg_update(const SolveState* st, double* x,
-                                                      const double* p, double* r, double* r_old,
-                                                      const double* q, float* r32, int64_t m,
-                                                      int64_t chunk, double* npart) {
+__device__ __forceinline__ void cg_update_body(const SolveState* st, double* x, const double* p,
+                                               double* r, double* r_old, const double* q,
+                                               float* r32, int64_t m, int64_t chunk,
+                                               double* npart) {
   __shared__ double red[kVecNT / 64];
   if (st->done) return;  // uniform: every thread of every block returns
   const double alpha = st->alpha;
@@ -841,6 +918,21 @@ __global__ __launch_bounds__(kVecNT) void k_cg_update(const SolveState* st, doub
   }
   ss = block_sum<double, kVecNT>(ss, red);
   if (threadIdx.x == 0) npart[blockIdx.x] = ss;
+}
+__global__ __launch_bounds__(kVecNT) void k_cg_update(const SolveState* st, double* x,
+                                                      const double* p, double* r, double* r_old,
+                                                      const double* q, float* r32, int64_t m,
+                                                      int64_t chunk, double* npart) {
+  cg_update_body(st, x, p, r, r_old, q, r32, m, chunk, npart);
+}
+// Batched; block 0 also clears the instance's cg_first (the direction of
+// this step has been formed).
+__global__ __launch_bounds__(kVecNT) void k_cg_update_b(const CgArgs* __restrict__ args) {
+  const CgArgs* g = args + blockIdx.y;
+  if (gate_skip(g->st, g->gate)) return;
+  if ((int)blockIdx.x >= vec_blocks(g->m)) return;
+  cg_update_body(g->st, g->x, g->p, g->r, g->r_old, g->q, g->r32, g->m, vec_chunk(g->m), g->npart);
+  if (blockIdx.x == 0 && threadIdx.x == 0) g->st->cg_first = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,14 +1099,9 @@ __global__ __launch_bounds__(kVecNT) void k_gm_xupdate(const SolveState* st, dou
   x[i] = v;
 }
 
-__global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const double* npart, int nb,
-                                                     double tol, int max_iter, double* hist,
-                                                     int stall) {
-  __shared__ double red[kVecNT / 64];
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kVecNT) v += npart[b];
-  v = block_sum<double, kVecNT>(v, red);
-  if (threadIdx.x != 0 || st->done) return;
+__device__ __forceinline__ void gm_check_state(SolveState* st, double v, double tol, int max_iter,
+                                               double* hist, int stall) {
+  if (st->done) return;
   const double rel = sqrt(v) / st->r0;
   st->relres = rel;
   hist[st->iter] = rel;
@@ -1034,8 +1121,35 @@ __global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const doubl
     // finish_state measures from here (a Krylov method's 2-norm residual is
     // not monotone, and a restart can start above the recurrence's minimum)
     st->best = rel;
+    st->cg_first = 1;  // CG restarts from it
   }
   st->vtrue = rel;
+}
+__global__ __launch_bounds__(kVecNT) void k_gm_check(SolveState* st, const double* npart, int nb,
+                                                     double tol, int max_iter, double* hist,
+                                                     int stall) {
+  __shared__ double red[kVecNT / 64];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kVecNT) v += npart[b];
+  v = block_sum<double, kVecNT>(v, red);
+  if (threadIdx.x == 0) gm_check_state(st, v, tol, max_iter, hist, stall);
+}
+__global__ __launch_bounds__(kVecNT) void k_gm_check_b(const FinishArgs* __restrict__ args) {
+  __shared__ double red[kVecNT / 64];
+  const FinishArgs* a = args + blockIdx.x;
+  if (gate_skip(a->st, a->gate)) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < a->npart; b += kVecNT) v += a->part[b];
+  v = block_sum<double, kVecNT>(v, red);
+  if (threadIdx.x == 0) gm_check_state(a->st, v, a->tol, a->max_iter, a->hist, a->verify);
+  if (a->host) {
+    __syncthreads();
+    constexpr int W = sizeof(SolveState) / 4;
+    if (threadIdx.x < W)
+      reinterpret_cast<unsigned*>(a->host)[threadIdx.x] =
+          reinterpret_cast<const unsigned*>(a->st)[threadIdx.x];
+    __threadfence_system();
+  }
 }
 
 // The solve state into pinned host memory (the host's view of the round):
@@ -1057,6 +1171,33 @@ __global__ void k_basis(double* b, int m, int j) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) b[i] = i == j ? 1.0 : 0.0;
 }
+// Column j of a batch of unit-vector right-hand sides: b_j = e_j, where b_j
+// starts at base + j * stride (m entries each, m columns).
+__global__ void k_basis_batch(double* base, int64_t stride, int m) {
+  const int j = blockIdx.y;
+  double* b = base + (int64_t)j * stride;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    b[i] = i == j ? 1.0 : 0.0;
+}
+hipError_t launch_basis_batch(double* base, int64_t stride, int m, hipStream_t s) {
+  if (m < 1 || m > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_basis_batch, dim3((m + 255) / 256, m), 256, 0, s, base, stride, m);
+  return hipGetLastError();
+}
+// M[:, j] = u_j (column-major m x m), u_j at base + j * stride.
+__global__ void k_gather_columns(double* M, const double* base, int64_t stride, int m) {
+  const int j = blockIdx.y;
+  const double* u = base + (int64_t)j * stride;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    M[(int64_t)j * m + i] = u[i];
+}
+hipError_t launch_gather_columns(double* M, const double* base, int64_t stride, int m,
+                                 hipStream_t s) {
+  if (m < 1 || m > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_columns, dim3((m + 255) / 256, m), 256, 0, s, M, base, stride, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_basis(double* b, int m, int j, hipStream_t s) {
   hipLaunchKernelGGL(k_basis, (m + 255) / 256, 256, 0, s, b, m, j);
   return hipGetLastError();
@@ -1106,6 +1247,16 @@ __global__ __launch_bounds__(kVecNT) void k_cg_dir(const SolveState* st, double*
   const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
   if (i >= m) return;
   p[i] = first ? (double)z[i] : (double)z[i] + st->beta * p[i];
+}
+template <typename TZ>
+__global__ __launch_bounds__(kVecNT) void k_cg_dir_b(const CgArgs* __restrict__ args) {
+  const CgArgs* g = args + blockIdx.y;
+  if (gate_skip(g->st, g->gate)) return;
+  const int64_t i = (int64_t)blockIdx.x * kVecNT + threadIdx.x;
+  if (i >= g->m) return;
+  const TZ* z = static_cast<const TZ*>(g->z);
+  const SolveState* st = g->st;
+  g->p[i] = st->cg_first ? (double)z[i] : (double)z[i] + st->beta * g->p[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1368,6 +1519,75 @@ hipError_t launch_bdf4_rhs(const double* u1, const double* u2, const double* u3,
   return hipGetLastError();
 }
 
+// ---- batched launchers ------------------------------------------------------
+template <typename T>
+hipError_t launch_tail_vcycle_batch(const TailArgs<T>* args, int count, int variant,
+                                    const Twiddles<T>& tw, hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  const size_t lds = tail_lds_bytes(sizeof(T));
+  switch (variant) {
+    case 0: return launch_lds(k_tail_vcycle_b<T, false, false>, count, kNTT, lds, s, args, tw);
+    case TAIL_SYM: return launch_lds(k_tail_vcycle_b<T, false, true>, count, kNTT, lds, s, args, tw);
+    case TAIL_BAND: return launch_lds(k_tail_vcycle_b<T, true, false>, count, kNTT, lds, s, args, tw);
+    case TAIL_BAND | TAIL_SYM:
+      return launch_lds(k_tail_vcycle_b<T, true, true>, count, kNTT, lds, s, args, tw);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_tail_matvec_batch(int colmode, int epimode, const PassArgs<T>* args, int count,
+                                    const Twiddles<T>& tw, hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  const size_t lds = tail_lds_bytes(sizeof(T));
+  if (colmode == COL_MV && epimode == EPI_MV)
+    return launch_lds(k_tail_matvec_b<T, COL_MV, EPI_MV>, count, kNTT, lds, s, args, tw);
+  if (colmode == COL_MV && epimode == EPI_OUTER)
+    return launch_lds(k_tail_matvec_b<T, COL_MV, EPI_OUTER>, count, kNTT, lds, s, args, tw);
+  if (colmode == COL_OUTER_UPDATE && epimode == EPI_OUTER)
+    return launch_lds(k_tail_matvec_b<T, COL_OUTER_UPDATE, EPI_OUTER>, count, kNTT, lds, s, args,
+                      tw);
+  return hipErrorInvalidValue;
+}
+
+template <typename TZ>
+hipError_t launch_vdot_batch(const VdotArgs* args, int count, int64_t mmax, hipStream_t s) {
+  if (count < 1 || count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vdot_b<TZ>, dim3(vec_blocks(mmax), count), kVecNT, 0, s, args);
+  return hipGetLastError();
+}
+hipError_t launch_cg_scalar_batch(const CgArgs* args, int count, int stage, hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_scalar_b, count, kVecNT, 0, s, args, stage);
+  return hipGetLastError();
+}
+template <typename TZ>
+hipError_t launch_cg_dir_batch(const CgArgs* args, int count, int64_t mmax, hipStream_t s) {
+  if (count < 1 || count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_dir_b<TZ>, dim3((unsigned)((mmax + kVecNT - 1) / kVecNT), count), kVecNT,
+                     0, s, args);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update_batch(const CgArgs* args, int count, int64_t mmax, hipStream_t s) {
+  if (count < 1 || count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_update_b, dim3(vec_blocks(mmax), count), kVecNT, 0, s, args);
+  return hipGetLastError();
+}
+hipError_t launch_finish_batch(const FinishArgs* args, int count, hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finish_b, count, 256, 0, s, args);
+  return hipGetLastError();
+}
+hipError_t launch_gm_check_batch(const FinishArgs* args, int count, hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gm_check_b, count, kVecNT, 0, s, args);
+  return hipGetLastError();
+}
+template hipError_t launch_vdot_batch<double>(const VdotArgs*, int, int64_t, hipStream_t);
+template hipError_t launch_vdot_batch<float>(const VdotArgs*, int, int64_t, hipStream_t);
+template hipError_t launch_cg_dir_batch<double>(const CgArgs*, int, int64_t, hipStream_t);
+template hipError_t launch_cg_dir_batch<float>(const CgArgs*, int, int64_t, hipStream_t);
+
 template hipError_t launch_vdot<double>(const double*, const double*, const double*, int64_t,
                                         double*, hipStream_t);
 template hipError_t launch_vdot<float>(const double*, const float*, const double*, int64_t,
@@ -1388,5 +1608,13 @@ template hipError_t launch_cg_dir<float>(const SolveState*, double*, const float
                                              const Twiddles<T>&, int, int, hipStream_t);
 AMG_INSTANTIATE(double)
 AMG_INSTANTIATE(float)
+template hipError_t launch_tail_vcycle_batch<double>(const TailArgs<double>*, int, int,
+                                                     const Twiddles<double>&, hipStream_t);
+template hipError_t launch_tail_vcycle_batch<float>(const TailArgs<float>*, int, int,
+                                                    const Twiddles<float>&, hipStream_t);
+template hipError_t launch_tail_matvec_batch<double>(int, int, const PassArgs<double>*, int,
+                                                     const Twiddles<double>&, hipStream_t);
+template hipError_t launch_tail_matvec_batch<float>(int, int, const PassArgs<float>*, int,
+                                                    const Twiddles<float>&, hipStream_t);
 
 }  // namespace amg

@@ -20,6 +20,8 @@
 // masked values, before any of them is used.  Internal header.
 #pragma once
 
+#include <type_traits>
+
 #include "kernel_common.hpp"
 
 namespace amg {
@@ -31,8 +33,8 @@ constexpr int kE4 = kCap4 / kNT4;
 // Pass 1.  Thread tid owns column j1 = c0 + (tid mod T) at rows i0 + e*di.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
-void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* part) {
+__device__ __forceinline__ void col_fwd_body(const LevelDev<T>& lv, const ColIn<T>& in,
+                                             cplx<T>* buf, const Twiddles<T>& tw, T* part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   __shared__ T red[NT / 64];
@@ -234,6 +236,24 @@ void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* par
   for (int e = 0; e < EPT; ++e) stg(buf + j1 + ((i0 + e * di) << lv.logL1), a[e]);
 }
 
+template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_fwd(LevelDev<T> lv, ColIn<T> in, cplx<T>* buf, Twiddles<T> tw, T* part) {
+  col_fwd_body<T, MODE, EPT, NT, LOG2>(lv, in, buf, tw, part);
+}
+// The same pass for a batch of instances of one geometry: block (x, y) runs
+// tile x of instance y with that instance's arguments (gated by its solve
+// state), so each instance's arithmetic is that of its own launch.
+template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_fwd_b(const PassArgs<T>* __restrict__ args, Twiddles<T> tw) {
+  const PassArgs<T>* a = args + blockIdx.y;
+  if (gate_skip(a->st, a->gate)) return;
+  const LevelDev<T> lv = a->lv;
+  const ColIn<T> in = a->in;
+  col_fwd_body<T, MODE, EPT, NT, LOG2>(lv, in, a->buf, tw, a->part);
+}
+
 // ---------------------------------------------------------------------------
 // Pass 2.  Row pair (ka, kb) = (item, L2-item), or (0, L2/2) for item 0; the
 // thread owns elements t = tid + e*kNT4 of both rows (KR of each; KR = 1 also
@@ -368,8 +388,8 @@ __device__ __forceinline__ void row_pair_regs(const LevelDev<T>& lv, Lds<T> lds,
 }
 
 template <typename T, bool SPECTRAL, bool SYM, int KR, int LOG1 = 0>
-__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
-void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
+__device__ __forceinline__ void row_body(const LevelDev<T>& lv, cplx<T>* buf, const Twiddles<T>& tw,
+                                         const T* part, int npart, const T* xin) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   __shared__ T red[kNT4 / 64];
@@ -509,12 +529,26 @@ void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npar
   }
 }
 
+template <typename T, bool SPECTRAL, bool SYM, int KR, int LOG1 = 0>
+__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+void k_row(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
+  row_body<T, SPECTRAL, SYM, KR, LOG1>(lv, buf, tw, part, npart, xin);
+}
+template <typename T, bool SPECTRAL, bool SYM, int KR, int LOG1 = 0>
+__global__ __launch_bounds__(kNT4) __attribute__((amdgpu_waves_per_eu(2)))
+void k_row_b(const PassArgs<T>* __restrict__ args, Twiddles<T> tw) {
+  const PassArgs<T>* a = args + blockIdx.y;
+  if (gate_skip(a->st, a->gate)) return;
+  const LevelDev<T> lv = a->lv;
+  row_body<T, SPECTRAL, SYM, KR, LOG1>(lv, a->buf, tw, a->part, a->npart, a->xin);
+}
+
 // Pass 2 for rows of 4096 points: the register row pass on 2 kNT4 threads.
 // The FP32 symmetric form fits two workgroups per CU (70 KB of LDS each).
 template <typename T, bool SPECTRAL, bool SYM>
-__global__ __launch_bounds__(2 * kNT4)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && SYM ? 4 : 2)))
-void k_row_w(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
+__device__ __forceinline__ void row_w_body(const LevelDev<T>& lv, cplx<T>* buf,
+                                           const Twiddles<T>& tw, const T* part, int npart,
+                                           const T* xin) {
   constexpr int NT = 2 * kNT4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
@@ -525,14 +559,31 @@ void k_row_w(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int np
   if (SPECTRAL && item == 0) finish_wo<T, NT>(lv, wpart, red, xin);
 }
 
+template <typename T, bool SPECTRAL, bool SYM>
+__global__ __launch_bounds__(2 * kNT4)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && SYM ? 4 : 2)))
+void k_row_w(LevelDev<T> lv, cplx<T>* buf, Twiddles<T> tw, const T* part, int npart, const T* xin) {
+  row_w_body<T, SPECTRAL, SYM>(lv, buf, tw, part, npart, xin);
+}
+template <typename T, bool SPECTRAL, bool SYM>
+__global__ __launch_bounds__(2 * kNT4)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && SYM ? 4 : 2)))
+void k_row_w_b(const PassArgs<T>* __restrict__ args, Twiddles<T> tw) {
+  const PassArgs<T>* a = args + blockIdx.y;
+  if (gate_skip(a->st, a->gate)) return;
+  const LevelDev<T> lv = a->lv;
+  row_w_body<T, SPECTRAL, SYM>(lv, a->buf, tw, a->part, a->npart, a->xin);
+}
+
 // ---------------------------------------------------------------------------
 // Pass 3.  Same ownership as pass 1; the outputs j < n are the rows
 // j2 < L2/2, i.e. e < EPT/2 (EPT = 1: threads tid < kNT4/2).  The epilogue's
 // operands are fetched before the FFT so their latency overlaps it.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
-void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw, double* part) {
+__device__ __forceinline__ void col_inv_body(const LevelDev<T>& lv, const EpiOut<T>& out,
+                                             const cplx<T>* buf, const Twiddles<T>& tw,
+                                             double* part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Lds<T> lds{reinterpret_cast<cplx<T>*>(smem_raw)};
   __shared__ double red[NT / 64];
@@ -668,6 +719,21 @@ void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw
   }
 }
 
+template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_inv(LevelDev<T> lv, EpiOut<T> out, const cplx<T>* buf, Twiddles<T> tw, double* part) {
+  col_inv_body<T, MODE, EPT, NT, LOG2>(lv, out, buf, tw, part);
+}
+template <typename T, int MODE, int EPT, int NT = kNT4, int LOG2 = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_inv_b(const PassArgs<T>* __restrict__ args, Twiddles<T> tw) {
+  const PassArgs<T>* a = args + blockIdx.y;
+  if (gate_skip(a->st, a->gate)) return;
+  const LevelDev<T> lv = a->lv;
+  const EpiOut<T> out = a->out;
+  col_inv_body<T, MODE, EPT, NT, LOG2>(lv, out, a->buf, tw, a->npart_out);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers: the level geometry picks the instance (EPT = T L2 / kNT4,
 // KR = max(1, L1 / kNT4)); checked against the kernels' assumptions here.
@@ -683,119 +749,83 @@ inline bool col_geom_ok(int logL1, int logL2, int tcols, int* ept) {
   return true;
 }
 
-template <typename T, int MODE>
-hipError_t col_fwd_ept(int ept, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
-                       const ColIn<T>& in, cplx<T>* buf, const Twiddles<T>& tw, T* part) {
+// The compile-time geometry of a column pass, from the element count per
+// thread (ept; 32 = a wide tile of 2 kNT4 threads with 16 each), the tile
+// width and the column length: f(EPT, NT, LOG2) as integral constants.
+template <int V>
+using IC = std::integral_constant<int, V>;
+template <typename F>
+hipError_t col_pick(int ept, int tcols, int logL2, F&& f) {
   switch (ept) {
-    case 1:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_fwd<T, MODE, 1, kNT4, 6>, grid, kNT4, lds, s, lv, in, buf, tw,
-                          part);
-      return launch_lds(k_col_fwd<T, MODE, 1>, grid, kNT4, lds, s, lv, in, buf, tw, part);
-    case 2:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_fwd<T, MODE, 2, kNT4, 7>, grid, kNT4, lds, s, lv, in, buf, tw,
-                          part);
-      return launch_lds(k_col_fwd<T, MODE, 2>, grid, kNT4, lds, s, lv, in, buf, tw, part);
-    case 4:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_fwd<T, MODE, 4, kNT4, 8>, grid, kNT4, lds, s, lv, in, buf, tw,
-                          part);
-      return launch_lds(k_col_fwd<T, MODE, 4>, grid, kNT4, lds, s, lv, in, buf, tw, part);
-    case 8:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_fwd<T, MODE, 8, kNT4, 9>, grid, kNT4, lds, s, lv, in, buf, tw,
-                          part);
-      return launch_lds(k_col_fwd<T, MODE, 8>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+    case 1: return tcols == 4 ? f(IC<1>{}, IC<kNT4>{}, IC<6>{}) : f(IC<1>{}, IC<kNT4>{}, IC<0>{});
+    case 2: return tcols == 4 ? f(IC<2>{}, IC<kNT4>{}, IC<7>{}) : f(IC<2>{}, IC<kNT4>{}, IC<0>{});
+    case 4: return tcols == 4 ? f(IC<4>{}, IC<kNT4>{}, IC<8>{}) : f(IC<4>{}, IC<kNT4>{}, IC<0>{});
+    case 8: return tcols == 4 ? f(IC<8>{}, IC<kNT4>{}, IC<9>{}) : f(IC<8>{}, IC<kNT4>{}, IC<0>{});
     case 16:
-      if (lv.logL2 == 10)
-        return launch_lds(k_col_fwd<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, in, buf, tw,
-                          part);
-      if (lv.logL2 == 9)
-        return launch_lds(k_col_fwd<T, MODE, 16, kNT4, 9>, grid, kNT4, lds, s, lv, in, buf, tw,
-                          part);
-      return launch_lds(k_col_fwd<T, MODE, 16>, grid, kNT4, lds, s, lv, in, buf, tw, part);
+      if (logL2 == 10) return f(IC<16>{}, IC<kNT4>{}, IC<10>{});
+      if (logL2 == 9) return f(IC<16>{}, IC<kNT4>{}, IC<9>{});
+      return f(IC<16>{}, IC<kNT4>{}, IC<0>{});
     case 32:
-      switch (lv.logL2) {
-        case 10: return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4, 10>, grid, 2 * kNT4, lds, s, lv,
-                                   in, buf, tw, part);
-        case 11: return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4, 11>, grid, 2 * kNT4, lds, s, lv,
-                                   in, buf, tw, part);
-        case 12: return launch_lds(k_col_fwd<T, MODE, 16, 2 * kNT4, 12>, grid, 2 * kNT4, lds, s, lv,
-                                   in, buf, tw, part);
+      switch (logL2) {
+        case 10: return f(IC<16>{}, IC<2 * kNT4>{}, IC<10>{});
+        case 11: return f(IC<16>{}, IC<2 * kNT4>{}, IC<11>{});
+        case 12: return f(IC<16>{}, IC<2 * kNT4>{}, IC<12>{});
         default: return hipErrorInvalidValue;
       }
     default: return hipErrorInvalidValue;
   }
+}
+
+// The row pass's compile-time geometry: f(KR, LOG1) (KR = 16: rows of 4096
+// points, the wide register row pass).
+template <typename F>
+hipError_t row_pick(int kr, int logL1, F&& f) {
+  switch (kr) {
+    case 1:
+      if (logL1 == 7) return f(IC<1>{}, IC<7>{});
+      if (logL1 == 8) return f(IC<1>{}, IC<8>{});
+      return f(IC<1>{}, IC<0>{});
+    case 2: return f(IC<2>{}, IC<9>{});
+    case 4: return f(IC<4>{}, IC<10>{});
+    case 8: return f(IC<8>{}, IC<0>{});
+    case 16: return f(IC<16>{}, IC<0>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int MODE>
+hipError_t col_fwd_ept(int ept, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
+                       const ColIn<T>& in, cplx<T>* buf, const Twiddles<T>& tw, T* part) {
+  return col_pick(ept, lv.tcols, lv.logL2, [&](auto E, auto NTc, auto G) {
+    constexpr int NT = decltype(NTc)::value;
+    return launch_lds(k_col_fwd<T, MODE, decltype(E)::value, NT, decltype(G)::value>, grid, NT,
+                      lds, s, lv, in, buf, tw, part);
+  });
 }
 
 template <typename T, int MODE>
 hipError_t col_inv_ept(int ept, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
                        const EpiOut<T>& out, const cplx<T>* buf, const Twiddles<T>& tw,
                        double* part) {
-  switch (ept) {
-    case 1:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_inv<T, MODE, 1, kNT4, 6>, grid, kNT4, lds, s, lv, out, buf, tw,
-                          part);
-      return launch_lds(k_col_inv<T, MODE, 1>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 2:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_inv<T, MODE, 2, kNT4, 7>, grid, kNT4, lds, s, lv, out, buf, tw,
-                          part);
-      return launch_lds(k_col_inv<T, MODE, 2>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 4:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_inv<T, MODE, 4, kNT4, 8>, grid, kNT4, lds, s, lv, out, buf, tw,
-                          part);
-      return launch_lds(k_col_inv<T, MODE, 4>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 8:
-      if (lv.tcols == 4)
-        return launch_lds(k_col_inv<T, MODE, 8, kNT4, 9>, grid, kNT4, lds, s, lv, out, buf, tw,
-                          part);
-      return launch_lds(k_col_inv<T, MODE, 8>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 16:
-      if (lv.logL2 == 10)
-        return launch_lds(k_col_inv<T, MODE, 16, kNT4, 10>, grid, kNT4, lds, s, lv, out, buf, tw,
-                          part);
-      if (lv.logL2 == 9)
-        return launch_lds(k_col_inv<T, MODE, 16, kNT4, 9>, grid, kNT4, lds, s, lv, out, buf, tw,
-                          part);
-      return launch_lds(k_col_inv<T, MODE, 16>, grid, kNT4, lds, s, lv, out, buf, tw, part);
-    case 32:
-      switch (lv.logL2) {
-        case 10: return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4, 10>, grid, 2 * kNT4, lds, s, lv,
-                                   out, buf, tw, part);
-        case 11: return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4, 11>, grid, 2 * kNT4, lds, s, lv,
-                                   out, buf, tw, part);
-        case 12: return launch_lds(k_col_inv<T, MODE, 16, 2 * kNT4, 12>, grid, 2 * kNT4, lds, s, lv,
-                                   out, buf, tw, part);
-        default: return hipErrorInvalidValue;
-      }
-    default: return hipErrorInvalidValue;
-  }
+  return col_pick(ept, lv.tcols, lv.logL2, [&](auto E, auto NTc, auto G) {
+    constexpr int NT = decltype(NTc)::value;
+    return launch_lds(k_col_inv<T, MODE, decltype(E)::value, NT, decltype(G)::value>, grid, NT,
+                      lds, s, lv, out, buf, tw, part);
+  });
 }
 
 template <typename T, bool SPECTRAL, bool SYM>
 hipError_t row_kr(int kr, int grid, size_t lds, hipStream_t s, const LevelDev<T>& lv,
                   cplx<T>* buf, const Twiddles<T>& tw, const T* part, int npart, const T* xin) {
-  switch (kr) {
-    case 1:
-      if (lv.logL1 == 7)
-        return launch_lds(k_row<T, SPECTRAL, SYM, 1, 7>, grid, kNT4, lds, s, lv, buf, tw, part,
-                          npart, xin);
-      if (lv.logL1 == 8)
-        return launch_lds(k_row<T, SPECTRAL, SYM, 1, 8>, grid, kNT4, lds, s, lv, buf, tw, part,
-                          npart, xin);
-      return launch_lds(k_row<T, SPECTRAL, SYM, 1>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
-    case 2: return launch_lds(k_row<T, SPECTRAL, SYM, 2, 9>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
-    case 4: return launch_lds(k_row<T, SPECTRAL, SYM, 4, 10>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
-    case 8: return launch_lds(k_row<T, SPECTRAL, SYM, 8>, grid, kNT4, lds, s, lv, buf, tw, part, npart, xin);
-    case 16:
-      return launch_lds(k_row_w<T, SPECTRAL, SYM>, grid, 2 * kNT4, lds, s, lv, buf, tw, part, npart,
-                        xin);
-    default: return hipErrorInvalidValue;
-  }
+  return row_pick(kr, lv.logL1, [&](auto K, auto G) {
+    constexpr int KR = decltype(K)::value;
+    if constexpr (KR == 16)
+      return launch_lds(k_row_w<T, SPECTRAL, SYM>, grid, 2 * kNT4, lds, s, lv, buf, tw, part,
+                        npart, xin);
+    else
+      return launch_lds(k_row<T, SPECTRAL, SYM, KR, decltype(G)::value>, grid, kNT4, lds, s, lv,
+                        buf, tw, part, npart, xin);
+  });
 }
 
 // Modes built for FP32 (the V-cycle) and FP64 (everything).
@@ -872,6 +902,93 @@ hipError_t launch_col_inv(int mode, const LevelDev<T>& lv, const EpiOut<T>& out,
       case EPI_OUTER: return col_inv_ept<T, EPI_OUTER>(ept, grid, lds, s, lv, out, buf, tw, part);
       default: break;
     }
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: `count` instances of one level geometry (the geometry of
+// `geom`; each instance's own arguments in the device table `args`), block
+// row y = instance y.  Same kernels bodies, same per-instance arithmetic.
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_col_fwd_batch(int mode, const LevelDev<T>& geom, const PassArgs<T>* args,
+                                int count, const Twiddles<T>& tw, hipStream_t s) {
+  int ept;
+  if (count < 1 || count > 65535 || !col_geom_ok(geom.logL1, geom.logL2, geom.tcols, &ept) ||
+      !col_mode_built<T>(mode))
+    return hipErrorInvalidValue;
+  const dim3 grid(col_blocks(geom.logL1, geom.tcols), count);
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(ept * kNT4);
+  auto go = [&](auto M) {
+    constexpr int MODE = decltype(M)::value;
+    return col_pick(ept, geom.tcols, geom.logL2, [&](auto E, auto NTc, auto G) {
+      constexpr int NT = decltype(NTc)::value;
+      return launch_lds(k_col_fwd_b<T, MODE, decltype(E)::value, NT, decltype(G)::value>, grid,
+                        NT, lds, s, args, tw);
+    });
+  };
+  switch (mode) {
+    case COL_MV: return go(IC<COL_MV>{});
+    case COL_PRE: return go(IC<COL_PRE>{});
+    case COL_PRE_RESTRICT: return go(IC<COL_PRE_RESTRICT>{});
+    case COL_PROLONG: return go(IC<COL_PROLONG>{});
+    default: break;
+  }
+  if constexpr (sizeof(T) == 8) {
+    if (mode == COL_OUTER_UPDATE) return go(IC<COL_OUTER_UPDATE>{});
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_row_batch(const LevelDev<T>& geom, const PassArgs<T>* args, int count,
+                            const Twiddles<T>& tw, hipStream_t s) {
+  const int L1 = 1 << geom.logL1;
+  if (count < 1 || count > 65535 || 2 * L1 > kCapWide || geom.logL2 < 1)
+    return hipErrorInvalidValue;
+  const int kr = L1 >= kNT4 ? L1 / kNT4 : 1;
+  const dim3 grid((1 << geom.logL2) / 2, count);
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(2 * L1);
+  auto go = [&](auto SY) {
+    constexpr bool SYM = decltype(SY)::value != 0;
+    return row_pick(kr, geom.logL1, [&](auto K, auto G) {
+      constexpr int KR = decltype(K)::value;
+      if constexpr (KR == 16)
+        return launch_lds(k_row_w_b<T, true, SYM>, grid, 2 * kNT4, lds, s, args, tw);
+      else
+        return launch_lds(k_row_b<T, true, SYM, KR, decltype(G)::value>, grid, kNT4, lds, s, args,
+                          tw);
+    });
+  };
+  return geom.sym ? go(IC<1>{}) : go(IC<0>{});
+}
+
+template <typename T>
+hipError_t launch_col_inv_batch(int mode, const LevelDev<T>& geom, const PassArgs<T>* args,
+                                int count, const Twiddles<T>& tw, hipStream_t s) {
+  int ept;
+  if (count < 1 || count > 65535 || !col_geom_ok(geom.logL1, geom.logL2, geom.tcols, &ept) ||
+      !epi_mode_built<T>(mode))
+    return hipErrorInvalidValue;
+  const dim3 grid(col_blocks(geom.logL1, geom.tcols), count);
+  const size_t lds = sizeof(cplx<T>) * (size_t)lds_slots(ept * kNT4);
+  auto go = [&](auto M) {
+    constexpr int MODE = decltype(M)::value;
+    return col_pick(ept, geom.tcols, geom.logL2, [&](auto E, auto NTc, auto G) {
+      constexpr int NT = decltype(NTc)::value;
+      return launch_lds(k_col_inv_b<T, MODE, decltype(E)::value, NT, decltype(G)::value>, grid,
+                        NT, lds, s, args, tw);
+    });
+  };
+  switch (mode) {
+    case EPI_MV: return go(IC<EPI_MV>{});
+    case EPI_RESID: return go(IC<EPI_RESID>{});
+    case EPI_SMOOTH: return go(IC<EPI_SMOOTH>{});
+    default: break;
+  }
+  if constexpr (sizeof(T) == 8) {
+    if (mode == EPI_OUTER) return go(IC<EPI_OUTER>{});
   }
   return hipErrorInvalidValue;
 }

@@ -10,4 +10,11 @@ template hipError_t launch_row<float>(int, const LevelDev<float>&, cplx<float>*,
 template hipError_t launch_col_inv<float>(int, const LevelDev<float>&, const EpiOut<float>&,
                                        const cplx<float>*, const Twiddles<float>&, double*, hipStream_t);
 
+template hipError_t launch_col_fwd_batch<float>(int, const LevelDev<float>&, const PassArgs<float>*, int,
+                                                 const Twiddles<float>&, hipStream_t);
+template hipError_t launch_row_batch<float>(const LevelDev<float>&, const PassArgs<float>*, int,
+                                         const Twiddles<float>&, hipStream_t);
+template hipError_t launch_col_inv_batch<float>(int, const LevelDev<float>&, const PassArgs<float>*, int,
+                                             const Twiddles<float>&, hipStream_t);
+
 }  // namespace amg

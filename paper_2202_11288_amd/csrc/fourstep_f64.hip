@@ -10,4 +10,11 @@ template hipError_t launch_row<double>(int, const LevelDev<double>&, cplx<double
 template hipError_t launch_col_inv<double>(int, const LevelDev<double>&, const EpiOut<double>&,
                                        const cplx<double>*, const Twiddles<double>&, double*, hipStream_t);
 
+template hipError_t launch_col_fwd_batch<double>(int, const LevelDev<double>&, const PassArgs<double>*, int,
+                                                 const Twiddles<double>&, hipStream_t);
+template hipError_t launch_row_batch<double>(const LevelDev<double>&, const PassArgs<double>*, int,
+                                         const Twiddles<double>&, hipStream_t);
+template hipError_t launch_col_inv_batch<double>(int, const LevelDev<double>&, const PassArgs<double>*, int,
+                                             const Twiddles<double>&, hipStream_t);
+
 }  // namespace amg

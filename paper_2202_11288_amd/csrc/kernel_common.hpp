@@ -164,7 +164,7 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 // Raise a kernel's dynamic-LDS limit once to the largest size it is launched
 // with (gfx950 has 160 KB of LDS per workgroup), then launch it.
 template <typename... P, typename... A>
-hipError_t launch_lds(void (*kernel)(P...), int grid, int block, size_t lds, hipStream_t s,
+hipError_t launch_lds(void (*kernel)(P...), dim3 grid, int block, size_t lds, hipStream_t s,
                       A&&... args) {
   static std::mutex mu;
   static std::unordered_map<const void*, size_t> done;
@@ -179,7 +179,7 @@ hipError_t launch_lds(void (*kernel)(P...), int grid, int block, size_t lds, hip
       done[key] = lds;
     }
   }
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, s, std::forward<A>(args)...);
+  hipLaunchKernelGGL(kernel, grid, dim3(block), lds, s, std::forward<A>(args)...);
   return hipGetLastError();
 }
 
