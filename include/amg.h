@@ -395,6 +395,64 @@ int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
 /* Release every device and host resource of the handle (NULL is a no-op). */
 int amg_destroy(amg_t h);
 
+/* ---- Serving: a request loop with continuous batching ------------------
+ * A server solves independent requests (kernel, delta, N, options, b, x,
+ * tol), each the same iteration as amg_solve, while requests keep arriving.
+ *  - Admission: a submitted request waits until its device footprint
+ *    (amg_footprint_bytes) fits in the server's memory budget, counting the
+ *    requests in flight and the cached hierarchies (evicted oldest first).
+ *  - Setup: worker threads build hierarchies on their own streams; a cached
+ *    hierarchy of a finished request with the same problem key (kernel
+ *    parameters, delta, N, options: its generator spectra for every level)
+ *    is taken instead.
+ *  - Rounds: amg_server_step starts the requests whose hierarchy is ready
+ *    (x then holds their initial guess), runs `rounds` rounds in which every
+ *    request in flight does one iteration (batched launches over all of
+ *    them, as amg_solve_batch), and retires the finished ones.  A request's
+ *    arithmetic is that of its solo amg_solve, whatever else is in flight.
+ * Supported: constant, weighted and fractional kernels; V-cycle or CG inner
+ * iteration; V-cycles (cycle = 1); one (m1, m2) per server (AMG_ENOTSUP
+ * otherwise).  b and x are device arrays of 2N-1 doubles owned by the caller,
+ * valid until the request is reported by amg_server_poll.  Calls on one
+ * server from several threads must be serialised by the caller. */
+typedef struct amg_server* amg_server_t;
+typedef struct {
+  int64_t id;        /* the id amg_server_submit returned                    */
+  int status;        /* amg_solve's status, or the setup's error code        */
+  int iters;
+  double relres;
+  int cached;        /* 1: the request reused a cached hierarchy             */
+} amg_server_result_t;
+typedef struct {
+  int64_t submitted, finished, rounds;
+  int64_t cache_hits, cache_misses, evictions;
+  int64_t reserved_bytes, peak_reserved_bytes, cached_hierarchies;
+} amg_server_stats_t;
+
+/* Create a server on the current device: `workers` setup threads (1..64),
+ * device memory budget in bytes, rounds enqueued on `stream`.  Errors:
+ * AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
+int amg_server_create(int64_t mem_budget_bytes, int workers, void* stream, amg_server_t* out);
+/* Queue a request; *id (host, may be NULL) receives its id.  opts may be
+ * NULL (defaults).  Errors: AMG_EINVAL (bad arguments), AMG_ENOTSUP (see
+ * above, or a footprint larger than the budget). */
+int amg_server_submit(amg_server_t sv, const amg_kernel_t* kernel, double delta, int64_t N,
+                      const amg_opts_t* opts, const double* b, double* x, double tol,
+                      int64_t* id);
+/* Start ready requests, run `rounds` rounds over the requests in flight,
+ * retire the finished ones; returns when the rounds are done (the calling
+ * thread polls the stream).  With rounds > 0 and no request in the rounds,
+ * it first waits until a set-up in progress ends (returns at once if there
+ * is none).  *in_flight / *waiting (host, may be NULL): the requests started
+ * or being set up / waiting for memory. */
+int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting);
+/* Copy up to `cap` results of requests finished since the last poll (host
+ * array); returns their number. */
+int amg_server_poll(amg_server_t sv, amg_server_result_t* out, int cap);
+int amg_server_stats(amg_server_t sv, amg_server_stats_t* out);
+/* Stop the workers and release every hierarchy (NULL is a no-op). */
+int amg_server_destroy(amg_server_t sv);
+
 /* Static description of a status code. */
 const char* amg_strerror(int status);
 

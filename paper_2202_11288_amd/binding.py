@@ -49,6 +49,17 @@ class amg_opts_t(ctypes.Structure):
                 ("restart", ctypes.c_int), ("cycle", ctypes.c_int)]
 
 
+class amg_server_result_t(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("relres", ctypes.c_double), ("cached", ctypes.c_int)]
+
+
+class amg_server_stats_t(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("submitted", "finished", "rounds", "cache_hits", "cache_misses", "evictions",
+                 "reserved_bytes", "peak_reserved_bytes", "cached_hierarchies")]
+
+
 class amg_stat_t(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
@@ -95,6 +106,14 @@ def _load():
         "amg_footprint_bytes": (I64, [ctypes.POINTER(amg_kernel_t), D, I64,
                                       ctypes.POINTER(amg_opts_t)]),
         "amg_destroy": (I, [P]),
+        "amg_server_create": (I, [I64, I, P, ctypes.POINTER(P)]),
+        "amg_server_submit": (I, [P, ctypes.POINTER(amg_kernel_t), D, I64,
+                                  ctypes.POINTER(amg_opts_t), P, P, D,
+                                  ctypes.POINTER(ctypes.c_int64)]),
+        "amg_server_step": (I, [P, I, IP, IP]),
+        "amg_server_poll": (I, [P, ctypes.POINTER(amg_server_result_t), I]),
+        "amg_server_stats": (I, [P, ctypes.POINTER(amg_server_stats_t)]),
+        "amg_server_destroy": (I, [P]),
         "amg_strerror": (ctypes.c_char_p, [I]),
     }
     for name, (res, args) in sig.items():
@@ -379,3 +398,58 @@ def amg_volume_rhs(kern: amg_kernel_t, delta: float, N: int, g_left, g_right, b)
 def amg_footprint_bytes(kern: amg_kernel_t, delta: float, N: int, opts: amg_opts_t | None = None):
     return lib.amg_footprint_bytes(ctypes.byref(kern), float(delta), int(N),
                                    ctypes.byref(opts) if opts is not None else None)
+
+
+# ---- serving ---------------------------------------------------------------
+
+def amg_server_create(mem_budget_bytes: int, workers: int = 4, stream=None):
+    sv = ctypes.c_void_p()
+    _check(lib.amg_server_create(int(mem_budget_bytes), int(workers), _stream(stream),
+                                 ctypes.byref(sv)), "amg_server_create")
+    return sv
+
+
+def amg_server_submit(sv, kern: amg_kernel_t, delta: float, N: int, b, x, tol: float,
+                      opts: amg_opts_t | None = None) -> int:
+    """Queue a request; b, x are contiguous float64 CUDA tensors of 2N - 1
+    values that must stay alive until the request is polled."""
+    import torch
+    m = 2 * int(N) - 1
+    for name, t in (("b", b), ("x", x)):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and t.numel() == m):
+            raise ValueError(f"amg_server_submit {name}: need a contiguous float64 CUDA tensor "
+                             f"of {m} values")
+    rid = ctypes.c_int64()
+    _check(lib.amg_server_submit(sv, ctypes.byref(kern), float(delta), int(N),
+                                 ctypes.byref(opts) if opts is not None else None, _ptr(b), _ptr(x),
+                                 float(tol), ctypes.byref(rid)), "amg_server_submit")
+    return rid.value
+
+
+def amg_server_step(sv, rounds: int = 1):
+    """Returns (in_flight, waiting)."""
+    a, w = ctypes.c_int(), ctypes.c_int()
+    _check(lib.amg_server_step(sv, int(rounds), ctypes.byref(a), ctypes.byref(w)),
+           "amg_server_step")
+    return a.value, w.value
+
+
+def amg_server_poll(sv, cap: int = 4096):
+    """[(id, status, iters, relres, cached)] of the requests finished since the
+    last poll."""
+    arr = (amg_server_result_t * cap)()
+    k = lib.amg_server_poll(sv, arr, cap)
+    if k < 0:
+        raise AmgError(k, "amg_server_poll")
+    return [(arr[i].id, arr[i].status, arr[i].iters, arr[i].relres, arr[i].cached)
+            for i in range(k)]
+
+
+def amg_server_stats(sv) -> dict:
+    st = amg_server_stats_t()
+    _check(lib.amg_server_stats(sv, ctypes.byref(st)), "amg_server_stats")
+    return {name: getattr(st, name) for name, _ in amg_server_stats_t._fields_}
+
+
+def amg_server_destroy(sv):
+    return _check(lib.amg_server_destroy(sv), "amg_server_destroy")

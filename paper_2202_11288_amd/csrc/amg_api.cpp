@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
 #include <functional>
 #include <cmath>
 #include <cstdio>
@@ -2564,6 +2568,416 @@ int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
   return footprint(N, &o, (kernel->kind == AMG_K_CONST || kernel->kind == AMG_K_FRACTIONAL) &&
                               ks.scheme == SCHEME_SHIFTED,
                    kernel->kind == AMG_K_WEAKLY_SINGULAR);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: a request loop over the batched rounds (amg_server_*).  Requests
+// are admitted by device footprint, set up by worker threads on their own
+// streams (or taken from a cache of idle hierarchies with the same problem
+// key), started between rounds, and advanced together: every round runs one
+// iteration of every request in flight, whatever it arrived; finished ones
+// leave, new ones join (continuous batching at iteration granularity).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ServerKey {
+  int kind, scheme, precision, inner, m1, m2, coarsest, max_iter;
+  double alpha, wl, wr, delta, omega_pre, omega_post, shift, scale;
+  int64_t N;
+  bool operator<(const ServerKey& o) const {
+    return std::memcmp(this, &o, sizeof(ServerKey)) < 0;
+  }
+};
+
+ServerKey server_key(const amg_kernel_t& k, double delta, int64_t N, const amg_opts_t& o) {
+  ServerKey key;
+  std::memset(&key, 0, sizeof key);  // padding compares equal
+  key.kind = k.kind;
+  key.scheme = k.scheme;
+  key.precision = o.precision;
+  key.inner = o.inner;
+  key.m1 = o.m1;
+  key.m2 = o.m2;
+  key.coarsest = o.coarsest_log2;
+  key.max_iter = o.max_iter;
+  key.alpha = k.kind == AMG_K_FRACTIONAL ? k.alpha : 0.0;
+  key.wl = k.kind == AMG_K_WEIGHTED ? k.wl : 0.0;
+  key.wr = k.kind == AMG_K_WEIGHTED ? k.wr : 0.0;
+  key.delta = delta;
+  key.omega_pre = o.omega_pre;
+  key.omega_post = o.omega_post;
+  key.shift = o.shift;
+  key.scale = o.scale;
+  key.N = N;
+  return key;
+}
+
+struct ServerReq {
+  int64_t id = 0;
+  amg_kernel_t kernel{};
+  double delta = 0;
+  int64_t N = 0;
+  amg_opts_t opts{};
+  const double* b = nullptr;
+  double* x = nullptr;
+  double tol = 0;
+  int64_t bytes = 0;
+  ServerKey key{};
+  amg_t h = nullptr;
+  int setup_status = AMG_OK;
+  bool cached = false;
+};
+
+}  // namespace
+
+struct amg_server {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t budget = 0, reserved = 0, peak_reserved = 0;
+  int m1 = -1, m2 = -1;
+  int64_t next_id = 1;
+  std::mutex mu;
+  std::condition_variable cv;       // work for the set-up threads
+  std::condition_variable cv_done;  // a set-up finished
+  int setting_up = 0;               // set-ups a worker has taken
+  bool stop = false;
+  std::deque<ServerReq*> pending;   // submitted, not admitted
+  std::deque<ServerReq*> setup_q;   // admitted (memory reserved), for a worker
+  std::vector<ServerReq*> ready;    // hierarchy ready, starts at the next step
+  std::vector<ServerReq*> active;   // in the rounds (step thread only)
+  std::vector<ServerReq*> failed;   // setup failed, reported by the next poll
+  std::vector<amg_server_result_t> finished;
+  std::multimap<ServerKey, std::pair<amg_t, int64_t>> idle;  // cached hierarchies
+  std::deque<std::pair<ServerKey, amg_t>> idle_order;       // oldest first
+  std::vector<std::thread> workers;
+  BatchPlan plan;
+  bool dirty = true;
+  amg_server_stats_t stats{};
+};
+
+namespace {
+
+// Take a cached hierarchy for the key, if one is idle (caller holds mu).
+amg_t cache_take(amg_server* sv, const ServerKey& key, int64_t* bytes) {
+  auto it = sv->idle.find(key);
+  if (it == sv->idle.end()) return nullptr;
+  amg_t h = it->second.first;
+  *bytes = it->second.second;
+  sv->idle.erase(it);
+  for (auto o = sv->idle_order.begin(); o != sv->idle_order.end(); ++o)
+    if (o->second == h) {
+      sv->idle_order.erase(o);
+      break;
+    }
+  return h;
+}
+
+// Evict the oldest cached hierarchy (caller holds mu); false if none.
+bool cache_evict_one(amg_server* sv) {
+  if (sv->idle_order.empty()) return false;
+  const auto victim = sv->idle_order.front();
+  sv->idle_order.pop_front();
+  auto range = sv->idle.equal_range(victim.first);
+  for (auto it = range.first; it != range.second; ++it)
+    if (it->second.first == victim.second) {
+      sv->reserved -= it->second.second;
+      sv->idle.erase(it);
+      break;
+    }
+  (void)amg_destroy(victim.second);
+  sv->stats.evictions += 1;
+  return true;
+}
+
+// Admit pending requests in order while their footprint fits (caller holds
+// mu): a cached hierarchy with the same key is taken at once; otherwise the
+// memory is reserved (evicting idle hierarchies if needed) and a worker sets
+// the request up.
+void admit(amg_server* sv) {
+  while (!sv->pending.empty()) {
+    ServerReq* r = sv->pending.front();
+    int64_t cbytes = 0;
+    amg_t h = cache_take(sv, r->key, &cbytes);
+    if (h) {
+      r->h = h;
+      r->bytes = cbytes;
+      r->cached = true;
+      sv->stats.cache_hits += 1;
+      sv->pending.pop_front();
+      sv->ready.push_back(r);
+      continue;
+    }
+    while (sv->reserved + r->bytes > sv->budget && cache_evict_one(sv)) {
+    }
+    if (sv->reserved + r->bytes > sv->budget) break;  // waits for memory
+    sv->reserved += r->bytes;
+    sv->peak_reserved = std::max(sv->peak_reserved, sv->reserved);
+    sv->stats.cache_misses += 1;
+    sv->pending.pop_front();
+    sv->setup_q.push_back(r);
+    sv->cv.notify_one();
+  }
+}
+
+void server_worker(amg_server* sv) {
+  (void)hipSetDevice(sv->device);
+  hipStream_t ws = nullptr;
+  (void)hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
+  for (;;) {
+    ServerReq* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv.wait(lk, [&] { return sv->stop || !sv->setup_q.empty(); });
+      if (sv->stop && sv->setup_q.empty()) break;
+      r = sv->setup_q.front();
+      sv->setup_q.pop_front();
+      sv->setting_up += 1;
+    }
+    amg_t h = nullptr;
+    const int st = amg_setup(&r->kernel, r->delta, r->N, &r->opts, ws, &h);
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      r->setup_status = st;
+      r->h = h;
+      if (st == AMG_OK) {
+        sv->ready.push_back(r);
+      } else {
+        sv->reserved -= r->bytes;
+        sv->failed.push_back(r);
+        admit(sv);
+      }
+      sv->setting_up -= 1;
+    }
+    sv->cv_done.notify_all();
+  }
+  if (ws) (void)hipStreamDestroy(ws);
+}
+
+void retire(amg_server* sv, ServerReq* r, const SolveState& st) {
+  amg_server_result_t res{};
+  res.id = r->id;
+  res.status = st.status;
+  res.iters = st.iter;
+  res.relres = st.relres;
+  res.cached = r->cached ? 1 : 0;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->finished.push_back(res);
+  sv->stats.finished += 1;
+  // the hierarchy stays on the device for a later request with the same key
+  sv->idle.insert({r->key, {r->h, r->bytes}});
+  sv->idle_order.push_back({r->key, r->h});
+  delete r;
+  admit(sv);
+}
+
+}  // namespace
+
+extern "C" {
+
+int amg_server_create(int64_t mem_budget_bytes, int workers, void* stream, amg_server_t* out) {
+  if (!out || mem_budget_bytes <= 0 || workers < 1 || workers > 64) return AMG_EINVAL;
+  *out = nullptr;
+  amg_server* sv = new (std::nothrow) amg_server();
+  if (!sv) return AMG_ENOMEM;
+  const hipError_t e = hipGetDevice(&sv->device);
+  if (e != hipSuccess) {
+    delete sv;
+    return hip_fail(e, "hipGetDevice", __LINE__);
+  }
+  sv->budget = mem_budget_bytes;
+  sv->stream = (hipStream_t)stream;
+  try {
+    for (int i = 0; i < workers; ++i) sv->workers.emplace_back(server_worker, sv);
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stop = true;
+    }
+    sv->cv.notify_all();
+    for (auto& t : sv->workers) t.join();
+    delete sv;
+    return AMG_ENOMEM;
+  }
+  *out = sv;
+  return AMG_OK;
+}
+
+int amg_server_submit(amg_server_t sv, const amg_kernel_t* kernel, double delta, int64_t N,
+                      const amg_opts_t* opts, const double* b, double* x, double tol,
+                      int64_t* id) {
+  if (!sv || !kernel || !b || !x || b == x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_EINVAL;
+  if (kernel->kind != AMG_K_CONST && kernel->kind != AMG_K_WEIGHTED &&
+      kernel->kind != AMG_K_FRACTIONAL)
+    return AMG_ENOTSUP;
+  amg_opts_t o;
+  if (opts) o = *opts;
+  else amg_default_opts(&o);
+  if (o.cycle != 1 || (o.inner != AMG_INNER_VCYCLE && o.inner != AMG_INNER_PCG) ||
+      (o.flags & (AMG_FLAG_ACCURATE_RESIDUAL | AMG_FLAG_PROFILE | AMG_FLAG_HOST_ONLY)))
+    return AMG_ENOTSUP;
+  const int64_t bytes = amg_footprint_bytes(kernel, delta, N, &o);
+  if (bytes < 0) return (int)bytes;
+  ServerReq* r = new (std::nothrow) ServerReq();
+  if (!r) return AMG_ENOMEM;
+  r->kernel = *kernel;
+  r->kernel.gen = nullptr;
+  r->delta = delta;
+  r->N = N;
+  r->opts = o;
+  r->b = b;
+  r->x = x;
+  r->tol = tol;
+  r->bytes = bytes;
+  r->key = server_key(*kernel, delta, N, o);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->m1 < 0) {
+    sv->m1 = o.m1;
+    sv->m2 = o.m2;
+  }
+  if (o.m1 != sv->m1 || o.m2 != sv->m2 || bytes > sv->budget) {
+    delete r;
+    return AMG_ENOTSUP;  // one sweep count per server; larger than the budget
+  }
+  r->id = sv->next_id++;
+  if (id) *id = r->id;
+  sv->pending.push_back(r);
+  sv->stats.submitted += 1;
+  admit(sv);
+  return AMG_OK;
+}
+
+int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
+  if (!sv || rounds < 0) return AMG_EINVAL;
+  HIP_TRY(hipSetDevice(sv->device));
+  hipStream_t s = sv->stream;
+  std::vector<ServerReq*> start;
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    admit(sv);
+    // nothing to run yet: wait for the first set-up to end
+    if (sv->active.empty() && rounds > 0)
+      sv->cv_done.wait(lk, [&] {
+        return !sv->ready.empty() || !sv->failed.empty() ||
+               (sv->setup_q.empty() && sv->setting_up == 0);
+      });
+    start.swap(sv->ready);
+  }
+  for (ServerReq* r : start) {
+    AMG_TRY(solve_begin(r->h, r->b, r->x, r->tol, s));
+    sv->active.push_back(r);
+    sv->dirty = true;
+  }
+  if (!start.empty()) HIP_TRY(round_wait(s));  // the starting states are on the host
+  // requests solved by their initial guess leave at once
+  for (size_t i = 0; i < sv->active.size();) {
+    ServerReq* r = sv->active[i];
+    if (r->h->st_host->done) {
+      const SolveState st = *r->h->st_host;
+      sv->active.erase(sv->active.begin() + (long)i);
+      retire(sv, r, st);
+      sv->dirty = true;
+    } else {
+      ++i;
+    }
+  }
+  if (!sv->active.empty() && rounds > 0) {
+    if (sv->dirty) {
+      HIP_TRY(round_wait(s));
+      std::vector<amg_ctx*> cs;
+      std::vector<const double*> bs;
+      std::vector<double*> xs;
+      std::vector<double> ts;
+      for (ServerReq* r : sv->active) {
+        cs.push_back(r->h);
+        bs.push_back(r->b);
+        xs.push_back(r->x);
+        ts.push_back(r->tol);
+      }
+      AMG_TRY(build_batch_plan(sv->plan, cs, bs, xs, ts));
+      AMG_TRY(run_batch_plan(sv->plan, s));
+      sv->dirty = false;
+    }
+    for (int k = 0; k < rounds; ++k)
+      for (const Launch& L : sv->plan.round) {
+        const hipError_t e = L(static_cast<unsigned char*>(sv->plan.dev), s);
+        if (e != hipSuccess) return hip_fail(e, "server round", __LINE__);
+      }
+    sv->stats.rounds += rounds;
+    HIP_TRY(round_wait(s));
+    for (size_t i = 0; i < sv->active.size();) {
+      ServerReq* r = sv->active[i];
+      if (r->h->st_host->done) {
+        const SolveState st = *r->h->st_host;
+        sv->active.erase(sv->active.begin() + (long)i);
+        retire(sv, r, st);
+        sv->dirty = true;
+      } else {
+        ++i;
+      }
+    }
+  }
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (in_flight)
+    *in_flight = (int)(sv->active.size() + sv->ready.size() + sv->setup_q.size()) + sv->setting_up;
+  if (waiting) *waiting = (int)sv->pending.size();
+  return AMG_OK;
+}
+
+int amg_server_poll(amg_server_t sv, amg_server_result_t* out, int cap) {
+  if (!sv || cap < 0 || (!out && cap > 0)) return AMG_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  for (ServerReq* r : sv->failed) {
+    amg_server_result_t res{};
+    res.id = r->id;
+    res.status = r->setup_status;
+    sv->finished.push_back(res);
+    delete r;
+  }
+  sv->failed.clear();
+  const int k = std::min<int>(cap, (int)sv->finished.size());
+  for (int i = 0; i < k; ++i) out[i] = sv->finished[(size_t)i];
+  sv->finished.erase(sv->finished.begin(), sv->finished.begin() + k);
+  return k;
+}
+
+int amg_server_stats(amg_server_t sv, amg_server_stats_t* out) {
+  if (!sv || !out) return AMG_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  *out = sv->stats;
+  out->reserved_bytes = sv->reserved;
+  out->peak_reserved_bytes = sv->peak_reserved;
+  out->cached_hierarchies = (int64_t)sv->idle.size();
+  return AMG_OK;
+}
+
+int amg_server_destroy(amg_server_t sv) {
+  if (!sv) return AMG_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  for (auto& t : sv->workers) t.join();
+  (void)hipSetDevice(sv->device);
+  if (sv->stream) (void)round_wait(sv->stream);
+  for (ServerReq* r : sv->active) {
+    (void)amg_destroy(r->h);
+    delete r;
+  }
+  for (ServerReq* r : sv->ready) {
+    (void)amg_destroy(r->h);
+    delete r;
+  }
+  for (ServerReq* r : sv->pending) delete r;
+  for (ServerReq* r : sv->setup_q) delete r;
+  for (ServerReq* r : sv->failed) delete r;
+  for (auto& kv : sv->idle) (void)amg_destroy(kv.second.first);
+  if (sv->plan.dev) (void)hipFree(sv->plan.dev);
+  delete sv;
+  return AMG_OK;
 }
 
 }  // extern "C"
