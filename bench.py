@@ -54,6 +54,22 @@ def parse():
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the precision configuration (N = 2^22, fractional alpha = 0.4, "
                          "delta = 0.1, FP32 V-cycle + FP64 residual, CG) beside the headline")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the serving run (Poisson arrivals, mixed sizes); 0 = skip")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="serving arrivals per second")
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0,
+                    help="device memory budget of the request server")
+    ap.add_argument("--serve-workers", type=int, default=2,
+                    help="set-up threads of the server (each has its own stream; with the "
+                         "server's and the arrival side's streams, 2 keep to the 4 hardware queues "
+                         "a process gets by default)")
+    ap.add_argument("--serve-rounds", type=int, default=1,
+                    help="rounds per amg_server_step of the serving run")
+    ap.add_argument("--serve-queue-gb", type=float, default=48.0,
+                    help="bound on the b and x vectors of requests submitted and not finished; "
+                         "arrivals beyond it are shed (counted)")
+    ap.add_argument("--serve-drain-s", type=float, default=60.0,
+                    help="longest wait for requests still in flight after the last arrival")
     ap.add_argument("--pmc-driver", action="store_true",
                     help="the short program the --pmc counter runs profile: a plain copy of "
                          "known size, then two mixed solves of the workload (eager launches)")
@@ -359,7 +375,8 @@ def run_batch(B, torch, args):
             "setup_s": round(setup_s, 2),
             "est_alg_bytes": alg, "est_alg_frac_of_hbm_peak": round(alg / wall / 1e9 / HBM_PEAK_GBS, 4),
             "workload": "N=2^K, K~U{10..16}; delta~U[0.05,0.3]; const or fractional 50/50, "
-                        "alpha~U[0.2,0.45]; b~N(0,1); seed 0; mixed, inner=PCG, "
+                        "alpha~U[0.2,0.45] (half the range [0.2,0.8]: the fractional weights are "
+                        "finite only for alpha < 1/2); b~N(0,1); seed 0; mixed, inner=PCG, "
                         f"tol={args.tol}"}
 
 
@@ -530,47 +547,211 @@ def run_extensions(B, torch, args):
     return out
 
 
+def representation_floor(tpx, T, b, x, seed=7):
+    """||A dx|| / ||b|| for dx uniform in +-ulp(x_i)/2, by the oracle in
+    extended precision: the relative residual that rounding the solution to
+    FP64 alone leaves; no FP64 vector near x has a residual much below it."""
+    g = np.random.default_rng(seed)
+    dx = (g.random(x.size) - 0.5) * np.spacing(np.abs(x))
+    Ad = tpx.residual_extended(T, np.zeros_like(x), dx)
+    return float(np.sqrt(np.dot(Ad, Ad))) / np.linalg.norm(b)
+
+
 def run_c3(B, torch, args):
-    """N = 2^22 intervals (8,388,607 unknowns), delta = 0.1, fractional kernel
-    alpha = 0.4, manufactured right-hand side, tol 1e-10: the mixed form
-    (FP32 V-cycle, FP64 residual and update, FP64 coarsest solve) and the FP64
-    form, both with V-cycle-preconditioned CG (the stationary iteration needs
-    thousands of V-cycles here); the oracle evaluates the mixed solution's
-    residual and its error against the FP64 solution.  The recurrence passes
-    1e-10; the true residual, which decides, stops near 2e-9 (the FP64 floor
-    eps |A| |x| / |b| of this operator at this size): status "fp64 floor"."""
-    N = 2 ** 22
+    """The precision configuration: delta = 0.1, fractional kernel alpha =
+    0.4, manufactured right-hand side, tol 1e-10, at N = 2^22 intervals
+    (8,388,607 unknowns) and at N = 2^20.  Mixed form (FP32 V-cycle, FP64
+    residual, update and coarsest solve) and FP64 form, both as V-cycle-
+    preconditioned CG (the stationary iteration needs thousands of V-cycles
+    here), with the split FP64 residual (near field in difference form, far
+    field by FFT) so that the stopping test sees the true residual.  The
+    oracle evaluates each solution's residual in extended precision and the
+    FP64 representation floor of the solution: at 2^22 that floor is above
+    1e-10, and the solve stops at it (status "fp64 floor")."""
     k = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4)
-    b = B.amg_manufactured_rhs(k, 0.1, N)
-    bd = torch.from_numpy(b).cuda()
-    out = {"workload": "N=2^22, delta=0.1, fractional alpha=0.4, manufactured u=x^2(1-x)^2, "
-                       "tol=1e-10, inner=PCG"}
-    xs = {}
-    for name, prec in (("mixed", B.AMG_MIXED), ("fp64", B.AMG_FP64)):
-        h = B.amg_setup(k, 0.1, N, B.amg_default_opts(precision=prec, inner=B.AMG_INNER_PCG,
-                                                     max_iter=1000))
-        try:
-            x = torch.zeros_like(bd)
-            B.amg_solve(h, bd, x, args.tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))  # warm-up
-            x.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, it, rel = B.amg_solve(h, bd, x, args.tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-        finally:
-            B.amg_destroy(h)
-        xs[name] = x.cpu().numpy()
-        out[name] = {"s_per_solve": round(dt, 4), "iters": it, "relres_true": rel,
-                     "status": {B.AMG_OK: "ok", B.AMG_NOT_CONVERGED: "fp64 floor"}[st],
-                     "unknowns_per_s": round((2 * N - 1) / dt, 1)}
-    out["err_mixed_vs_fp64"] = float(np.abs(xs["mixed"] - xs["fp64"]).max() / np.abs(xs["fp64"]).max())
-    if not args.no_cpu_baseline:
-        from oracle import discretize as D
-        from oracle import tpx
-        H = tpx.Hierarchy.build(tpx.from_stencil(D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), N), 5)
-        out["relres_mixed_oracle"] = float(np.linalg.norm(b - H.matvec(xs["mixed"])) / np.linalg.norm(b))
+    out = {"workload": "delta=0.1, fractional alpha=0.4, manufactured u=x^2(1-x)^2, tol=1e-10, "
+                       "inner=PCG, split FP64 residual (AMG_FLAG_ACCURATE_RESIDUAL)"}
+    for logN in (22, 20):
+        N = 2 ** logN
+        b = B.amg_manufactured_rhs(k, 0.1, N)
+        bd = torch.from_numpy(b).cuda()
+        res, xs = {}, {}
+        for name, prec in (("mixed", B.AMG_MIXED), ("fp64", B.AMG_FP64)):
+            h = B.amg_setup(k, 0.1, N, B.amg_default_opts(
+                precision=prec, inner=B.AMG_INNER_PCG, max_iter=1500,
+                flags=B.AMG_FLAG_ACCURATE_RESIDUAL))
+            try:
+                x = torch.zeros_like(bd)
+                B.amg_solve(h, bd, x, args.tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))  # warm-up
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it, rel = B.amg_solve(h, bd, x, args.tol, allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            finally:
+                B.amg_destroy(h)
+            xs[name] = x.cpu().numpy()
+            res[name] = {"s_per_solve": round(dt, 4), "iters": it, "relres": rel,
+                         "status": {B.AMG_OK: "ok", B.AMG_NOT_CONVERGED: "fp64 floor"}[st],
+                         "unknowns_per_s": round((2 * N - 1) / dt, 1)}
+        res["err_mixed_vs_fp64"] = float(np.abs(xs["mixed"] - xs["fp64"]).max()
+                                         / np.abs(xs["fp64"]).max())
+        if not args.no_cpu_baseline:
+            from oracle import discretize as D
+            from oracle import tpx
+            T = tpx.from_stencil_rowsum(D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), N)
+            for name in ("mixed", "fp64"):
+                res[name]["relres_oracle_extended"] = float(tpx.relres_extended(T, b, xs[name]))
+            res["fp64_representation_floor"] = representation_floor(tpx, T, b, xs["mixed"])
+        out[f"N=2^{logN}"] = res
+        print(f"# c3 N=2^{logN}: {res}", file=sys.stderr, flush=True)
     return out
+
+
+def serve_requests(seconds, rate, seed=1):
+    """The serving workload: Poisson arrivals at `rate` per second over
+    `seconds`, N = 2^K with K uniform on 12..22, delta uniform on [0.02,
+    0.3], constant or weighted (1.2 / 0.8, non-symmetric) kernel with even
+    odds, tol 1e-8 or 1e-10 with even odds, b ~ N(0, 1) drawn on the device
+    from a per-request seed."""
+    g = np.random.default_rng(seed)
+    out, t = [], 0.0
+    while True:
+        t += float(g.exponential(1.0 / rate))
+        if t >= seconds:
+            return out
+        K = int(g.integers(12, 23))
+        out.append(dict(t=t, K=K, N=2 ** K, delta=float(g.uniform(0.02, 0.3)),
+                        weighted=bool(g.integers(0, 2)), tol=[1e-8, 1e-10][int(g.integers(0, 2))],
+                        seed=int(g.integers(0, 2 ** 62))))
+
+
+def run_serve(B, torch, args):
+    """Open-loop serving: an arrival thread submits each request at its
+    scheduled time (b drawn on the device); the main thread steps the server
+    (one round over every request in flight per step, requests joining and
+    leaving between rounds) and collects results.  Latency is from the
+    scheduled arrival to the poll that returns the result.  Mixed precision,
+    stationary V-cycle iteration (the weighted kernel is non-symmetric).  One
+    untimed request per size first (module loads, twiddle tables)."""
+    import threading
+    reqs = serve_requests(args.serve_seconds, args.serve_rate)
+    opts = B.amg_default_opts(precision=B.AMG_MIXED, max_iter=100)
+    sv = B.amg_server_create(int(args.serve_budget_gb * 2 ** 30), workers=args.serve_workers)
+    lock = threading.Lock()
+    live, done = {}, {}
+    gen_stream = torch.cuda.Stream()  # the arrival side's stream for b and x
+
+    def kern(r):
+        return (B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8) if r["weighted"]
+                else B.kernel(B.AMG_K_CONST))
+
+    live_bytes = [0]
+    shed = []
+
+    def submit(i, r):
+        vec_bytes = 2 * 8 * (2 * r["N"] - 1)
+        with lock:
+            if i >= 0 and live_bytes[0] + vec_bytes > args.serve_queue_gb * 2 ** 30:
+                shed.append(i)  # the queue's vectors would pass their bound: load shedding
+                return
+            live_bytes[0] += vec_bytes
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(r["seed"])
+        with torch.cuda.stream(gen_stream):
+            b = torch.randn(2 * r["N"] - 1, generator=gen, device="cuda", dtype=torch.float64)
+            x = torch.zeros_like(b)
+        gen_stream.synchronize()  # the server reads b and x on its own stream
+        with lock:
+            rid = B.amg_server_submit(sv, kern(r), r["delta"], r["N"], b, x, r["tol"], opts)
+            live[rid] = (i, b, x)
+
+    def drain(deadline):
+        while time.perf_counter() < deadline:
+            with lock:
+                if not live:
+                    return True
+            inflight, _ = B.amg_server_step(sv, args.serve_rounds)
+            now = time.perf_counter()
+            with lock:
+                for res in B.amg_server_poll(sv):
+                    i, bb, _ = live.pop(res[0])
+                    live_bytes[0] -= 2 * bb.numel() * 8
+                    done[i] = (now, res)
+            if inflight == 0:
+                time.sleep(2e-4)
+        return False
+
+    try:
+        warm = [dict(N=2 ** K, K=K, delta=0.1, weighted=bool(K % 2), tol=1e-8, seed=K)
+                for K in range(12, 23)]
+        for i, r in enumerate(warm):
+            submit(-1 - i, r)
+        drain(time.perf_counter() + 120)
+        done.clear()
+        s0 = B.amg_server_stats(sv)
+        t0 = time.perf_counter()
+
+        def arrivals():
+            for i, r in enumerate(reqs):
+                wait = t0 + r["t"] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+                submit(i, r)
+
+        th = threading.Thread(target=arrivals)
+        th.start()
+        t_note = t0
+        while th.is_alive():
+            drain(time.perf_counter() + 0.05)
+            if time.perf_counter() - t_note > 10:
+                t_note = time.perf_counter()
+                with lock:
+                    print(f"# serve t={t_note - t0:.0f}s completed={len(done)} in flight={len(live)}",
+                          file=sys.stderr, flush=True)
+        th.join()
+        finished = drain(t0 + args.serve_seconds + args.serve_drain_s)
+        t_end = max((d[0] for d in done.values()), default=t0)
+        s1 = B.amg_server_stats(sv)
+    finally:
+        B.amg_server_destroy(sv)
+    lat = np.array([done[i][0] - t0 - reqs[i]["t"] for i in sorted(done)])
+    ok = [i for i in done if done[i][1][1] == B.AMG_OK]
+    unknowns = sum(2 * reqs[i]["N"] - 1 for i in done)
+    wall = t_end - t0
+    by_K = {}
+    for K in range(12, 23):
+        lk = [done[i][0] - t0 - reqs[i]["t"] for i in done if reqs[i]["K"] == K]
+        if lk:
+            by_K[f"2^{K}"] = {"n": len(lk), "p50_ms": round(1e3 * float(np.percentile(lk, 50)), 2),
+                              "p99_ms": round(1e3 * float(np.percentile(lk, 99)), 2)}
+    hits = s1["cache_hits"] - s0["cache_hits"]
+    miss = s1["cache_misses"] - s0["cache_misses"]
+    offered = sum(2 * r["N"] - 1 for r in reqs) / args.serve_seconds
+    return {
+        "workload": (f"Poisson arrivals {args.serve_rate}/s for {args.serve_seconds} s, seed 1; "
+                     "N=2^K, K~U{12..22}; delta~U[0.02,0.3]; const or weighted (1.2/0.8) 50/50; "
+                     "tol 1e-8 or 1e-10 50/50; b~N(0,1) on device; mixed, stationary V-cycle"),
+        "requests": len(reqs), "completed": len(done), "shed": len(shed), "drained": finished,
+        "ok": len(ok), "not_ok": len(done) - len(ok),
+        "max_relres_over_tol": float(max((done[i][1][3] / reqs[i]["tol"] for i in ok), default=0.0)),
+        "wall_s": round(wall, 3), "solves_per_s": round(len(done) / wall, 2),
+        "unknowns_per_s": round(unknowns / wall, 1), "offered_unknowns_per_s": round(offered, 1),
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+        "max_ms": round(1e3 * float(lat.max()), 2), "latency_by_size": by_K,
+        "iters_median": int(np.median([done[i][1][2] for i in done])),
+        "rounds": s1["rounds"] - s0["rounds"],
+        "cache_hits": hits, "cache_misses": miss,
+        "cache_hit_rate": round(hits / max(hits + miss, 1), 4),
+        "evictions": s1["evictions"] - s0["evictions"],
+        "peak_reserved_gb": round(s1["peak_reserved_bytes"] / 2 ** 30, 2),
+        "server_time_s": {k: round((s1[k + "_us"] - s0[k + "_us"]) / 1e6, 3)
+                          for k in ("start", "rebuild", "rounds", "setup")},
+        "plan_rebuilds": s1["rebuilds"] - s0["rebuilds"],
+        "budget_gb": args.serve_budget_gb, "setup_workers": args.serve_workers,
+    }
 
 
 def cpu_baseline(args, b, x_fp64, x_mixed):
@@ -657,6 +838,10 @@ def main():
     if not args.no_c3:
         c3 = run_c3(B, torch, args)
         print(f"# c3 done: {c3}", file=sys.stderr, flush=True)
+    serve = None
+    if args.serve_seconds > 0:
+        serve = run_serve(B, torch, args)
+        print(f"# serve done: {serve}", file=sys.stderr, flush=True)
     batch = None
     if args.batch > 0:
         batch = run_batch(B, torch, args)
@@ -698,6 +883,7 @@ def main():
         "speedup_mixed_vs_fp64": round(smx["solves_per_s"] / s64["solves_per_s"], 3),
         "pcg": krylov,
         "batch": batch,
+        "serving": serve,
         "plain_configs": c2,
         "extensions": ext,
         "precision_config": c3,

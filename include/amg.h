@@ -400,7 +400,8 @@ int amg_destroy(amg_t h);
  * tol), each the same iteration as amg_solve, while requests keep arriving.
  *  - Admission: a submitted request waits until its device footprint
  *    (amg_footprint_bytes) fits in the server's memory budget, counting the
- *    requests in flight and the cached hierarchies (evicted oldest first).
+ *    requests in flight and the cached hierarchies (evicted oldest first;
+ *    a set-up thread frees them, and their bytes count until it has).
  *  - Setup: worker threads build hierarchies on their own streams; a cached
  *    hierarchy of a finished request with the same problem key (kernel
  *    parameters, delta, N, options: its generator spectra for every level)
@@ -413,8 +414,11 @@ int amg_destroy(amg_t h);
  * Supported: constant, weighted and fractional kernels; V-cycle or CG inner
  * iteration; V-cycles (cycle = 1); one (m1, m2) per server (AMG_ENOTSUP
  * otherwise).  b and x are device arrays of 2N-1 doubles owned by the caller,
- * valid until the request is reported by amg_server_poll.  Calls on one
- * server from several threads must be serialised by the caller. */
+ * valid until the request is reported by amg_server_poll.  Threads:
+ * amg_server_submit, amg_server_poll and amg_server_stats may run on any
+ * thread, also while amg_server_step runs on another; calls of
+ * amg_server_step must not overlap each other, and amg_server_destroy must
+ * not overlap any call on the server. */
 typedef struct amg_server* amg_server_t;
 typedef struct {
   int64_t id;        /* the id amg_server_submit returned                    */
@@ -427,11 +431,18 @@ typedef struct {
   int64_t submitted, finished, rounds;
   int64_t cache_hits, cache_misses, evictions;
   int64_t reserved_bytes, peak_reserved_bytes, cached_hierarchies;
+  /* host wall time in microseconds: amg_server_step starting requests, in
+   * rebuilding the batched launch tables, and in enqueueing and waiting for
+   * rounds; the set-up threads' time in amg_setup (summed over threads) */
+  int64_t start_us, rebuild_us, rounds_us, setup_us, rebuilds;
 } amg_server_stats_t;
 
 /* Create a server on the current device: `workers` setup threads (1..64),
- * device memory budget in bytes, rounds enqueued on `stream`.  Errors:
- * AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
+ * device memory budget in bytes, rounds enqueued on `stream` (NULL: a
+ * non-blocking stream of the server's own).  A request's b and initial x
+ * are read on that stream from the next amg_server_step on: work producing
+ * them on another stream must have completed by then (synchronise it before
+ * amg_server_submit).  Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
 int amg_server_create(int64_t mem_budget_bytes, int workers, void* stream, amg_server_t* out);
 /* Queue a request; *id (host, may be NULL) receives its id.  opts may be
  * NULL (defaults).  Errors: AMG_EINVAL (bad arguments), AMG_ENOTSUP (see
@@ -442,8 +453,8 @@ int amg_server_submit(amg_server_t sv, const amg_kernel_t* kernel, double delta,
 /* Start ready requests, run `rounds` rounds over the requests in flight,
  * retire the finished ones; returns when the rounds are done (the calling
  * thread polls the stream).  With rounds > 0 and no request in the rounds,
- * it first waits until a set-up in progress ends (returns at once if there
- * is none).  *in_flight / *waiting (host, may be NULL): the requests started
+ * it first waits until a set-up (or the release of an evicted hierarchy) in
+ * progress ends; it returns at once if there is none.  *in_flight / *waiting (host, may be NULL): the requests started
  * or being set up / waiting for memory. */
 int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting);
 /* Copy up to `cap` results of requests finished since the last poll (host

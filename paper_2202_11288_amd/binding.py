@@ -57,7 +57,8 @@ class amg_server_result_t(ctypes.Structure):
 class amg_server_stats_t(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("submitted", "finished", "rounds", "cache_hits", "cache_misses", "evictions",
-                 "reserved_bytes", "peak_reserved_bytes", "cached_hierarchies")]
+                 "reserved_bytes", "peak_reserved_bytes", "cached_hierarchies",
+                 "start_us", "rebuild_us", "rounds_us", "setup_us", "rebuilds")]
 
 
 class amg_stat_t(ctypes.Structure):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -243,8 +244,18 @@ struct amg_ctx {
   double* rout = nullptr;  // FP64 outer residual (mixed precision)
   std::vector<double> hist;
   int last_iters = 0;
-  std::vector<void*> dev_allocs;
-  std::vector<void*> setup_temps;
+  // Device memory: a handle's buffers are carved from a few large chunks
+  // (the first sized by the footprint estimate), so that a setup makes a
+  // handful of hipMalloc calls and amg_destroy a handful of hipFree calls
+  // rather than hundreds; setup temporaries come from chunks of a per-device
+  // pool that later setups reuse.
+  std::vector<std::pair<void*, size_t>> dev_allocs;  // chunks (address, usable bytes)
+  std::vector<std::pair<void*, size_t>> spare;       // a retired handle's chunks, for reuse
+  char* bump = nullptr;
+  size_t bump_used = 0, bump_cap = 0, arena_hint = 0;
+  std::vector<std::pair<void*, size_t>> setup_temps;  // pool chunks
+  char* tbump = nullptr;
+  size_t tbump_used = 0, tbump_cap = 0;
   // V-cycle replay (see AMG_FLAG_EAGER): captured on an internal stream at
   // the handle's second V-cycle; every argument of its kernels is a
   // handle-owned buffer, so the graph stays valid for the handle's lifetime.
@@ -307,13 +318,42 @@ int hip_fail(hipError_t e, const char* expr, int line) {
     if (_e != hipSuccess) return hip_fail(_e, #expr, __LINE__);   \
   } while (0)
 
+constexpr size_t kAllocAlign = 256;     // every buffer starts on 256 bytes
+constexpr size_t kAllocPad = 256;       // and is followed by this much slack
+constexpr size_t kChunkGuard = 65536;   // unused tail of every chunk
+constexpr size_t kChunkMin = size_t(1) << 20;
+
+inline size_t alloc_bytes(size_t bytes) {
+  return ((bytes + kAllocPad + kAllocAlign - 1) / kAllocAlign) * kAllocAlign;
+}
+
 template <typename T>
 int dalloc(amg_ctx* c, T** p, size_t count) {
-  void* ptr = nullptr;
   if (count == 0) count = 1;
-  if (hipMalloc(&ptr, count * sizeof(T)) != hipSuccess) return AMG_ENOMEM;
-  c->dev_allocs.push_back(ptr);
-  *p = static_cast<T*>(ptr);
+  const size_t need = alloc_bytes(count * sizeof(T));
+  if (!c->bump || c->bump_used + need > c->bump_cap) {
+    size_t cap = std::max(need, std::max(c->arena_hint, kChunkMin));
+    c->arena_hint = 0;  // later chunks are sized by the request
+    void* ptr = nullptr;
+    // a spare chunk that holds the request (the largest first: the spares of
+    // a handle of the same shape match its chunks in order)
+    auto best = c->spare.end();
+    for (auto it = c->spare.begin(); it != c->spare.end(); ++it)
+      if (it->second >= need && (best == c->spare.end() || it->second > best->second)) best = it;
+    if (best != c->spare.end()) {
+      ptr = best->first;
+      cap = best->second;
+      c->spare.erase(best);
+    } else if (hipMalloc(&ptr, cap + kChunkGuard) != hipSuccess) {
+      return AMG_ENOMEM;
+    }
+    c->dev_allocs.push_back({ptr, cap});
+    c->bump = static_cast<char*>(ptr);
+    c->bump_used = 0;
+    c->bump_cap = cap;
+  }
+  *p = reinterpret_cast<T*>(c->bump + c->bump_used);
+  c->bump_used += need;
   return AMG_OK;
 }
 
@@ -330,15 +370,54 @@ int upload(amg_ctx* c, T** dst, const std::vector<T>& src, hipStream_t s) {
   return AMG_OK;
 }
 
+// Per-device pool of setup scratch chunks (power-of-two sizes), kept for
+// later setups up to kTempPoolMax bytes per device, freed beyond that.
+constexpr size_t kTempChunkMin = size_t(64) << 20;
+constexpr size_t kTempPoolMax = size_t(4) << 30;
+struct TempPool {
+  std::multimap<size_t, void*> free;
+  size_t bytes = 0;
+};
+std::mutex g_tmp_mu;
+std::unordered_map<int, TempPool> g_tmp;
+
+int temp_chunk_get(int dev, size_t need, void** out, size_t* size) {
+  size_t sz = kTempChunkMin;
+  while (sz < need) sz <<= 1;
+  {
+    std::lock_guard<std::mutex> g(g_tmp_mu);
+    TempPool& P = g_tmp[dev];
+    auto it = P.free.lower_bound(sz);
+    if (it != P.free.end() && it->first <= 4 * sz) {
+      *out = it->second;
+      *size = it->first;
+      P.bytes -= it->first;
+      P.free.erase(it);
+      return AMG_OK;
+    }
+  }
+  if (hipMalloc(out, sz + kChunkGuard) != hipSuccess) return AMG_ENOMEM;
+  *size = sz;
+  return AMG_OK;
+}
+
 // Setup temporaries that stay allocated until setup has synchronised its
 // stream once at the end (the generators behind the spectra).
 template <typename T>
 int dalloc_temp(amg_ctx* c, T** p, size_t count) {
-  void* ptr = nullptr;
   if (count == 0) count = 1;
-  if (hipMalloc(&ptr, count * sizeof(T)) != hipSuccess) return AMG_ENOMEM;
-  c->setup_temps.push_back(ptr);
-  *p = static_cast<T*>(ptr);
+  const size_t need = alloc_bytes(count * sizeof(T));
+  if (!c->tbump || c->tbump_used + need > c->tbump_cap) {
+    void* ptr = nullptr;
+    size_t sz = 0;
+    AMG_TRY(temp_chunk_get(c->device, need, &ptr, &sz));
+    c->setup_temps.push_back({ptr, sz});
+    c->tbump = static_cast<char*>(ptr);
+    c->tbump_used = 0;
+    c->tbump_cap = sz;
+  }
+  *p = reinterpret_cast<T*>(c->tbump + c->tbump_used);
+  c->tbump_used += need;
   return AMG_OK;
 }
 template <typename T>
@@ -347,18 +426,26 @@ int upload_temp(amg_ctx* c, T** dst, const std::vector<T>& src, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return AMG_OK;
 }
+// The caller has synchronised the setup stream: the chunks go back to the
+// pool (or are freed once the pool is full).
 void free_setup_temps(amg_ctx* c) {
-  for (void* p : c->setup_temps) (void)hipFree(p);
-  c->setup_temps.clear();
-}
-
-// Frees every allocation made after `mark` (setup temporaries); the caller
-// has synchronised the stream.
-void free_since(amg_ctx* c, size_t mark) {
-  while (c->dev_allocs.size() > mark) {
-    (void)hipFree(c->dev_allocs.back());
-    c->dev_allocs.pop_back();
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(g_tmp_mu);
+    TempPool& P = g_tmp[c->device];
+    for (const auto& t : c->setup_temps) {
+      if (P.bytes + t.second <= kTempPoolMax) {
+        P.free.insert({t.second, t.first});
+        P.bytes += t.second;
+      } else {
+        drop.push_back(t.first);
+      }
+    }
   }
+  for (void* q : drop) (void)hipFree(q);
+  c->setup_temps.clear();
+  c->tbump = nullptr;
+  c->tbump_used = c->tbump_cap = 0;
 }
 
 std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
@@ -794,9 +881,8 @@ int form_sub_vcycle(amg_ctx* c, hipStream_t s) {
     col += 3 * (2 * c->lv[l].n + 1) + 4;
   }
   col = (col + 31) & ~int64_t(31);
-  const size_t mark = c->dev_allocs.size();  // setup temporaries
-  double* scr = nullptr;
-  AMG_TRY(dalloc(c, &scr, (size_t)(col * m)));
+  double* scr = nullptr;  // setup temporary
+  AMG_TRY(dalloc_temp(c, &scr, (size_t)(col * m)));
   std::vector<LevelDev<double>> tables((size_t)m * nl);
   for (int j = 0; j < m; ++j)
     for (int l = k; l <= last; ++l) {
@@ -810,7 +896,7 @@ int form_sub_vcycle(amg_ctx* c, hipStream_t s) {
       tables[(size_t)j * nl + l] = d;
     }
   LevelDev<double>* tdev = nullptr;
-  AMG_TRY(upload(c, &tdev, tables, s));
+  AMG_TRY(upload_temp(c, &tdev, tables, s));
   std::vector<TailArgs<double>> args((size_t)m);
   for (int j = 0; j < m; ++j) {
     TailArgs<double>& a = args[(size_t)j];
@@ -827,13 +913,11 @@ int form_sub_vcycle(amg_ctx* c, hipStream_t s) {
     a.gate = GATE_ACTIVE;
   }
   TailArgs<double>* adev = nullptr;
-  AMG_TRY(upload(c, &adev, args, s));
+  AMG_TRY(upload_temp(c, &adev, args, s));
   HIP_TRY(hipMemsetAsync(scr, 0, (size_t)(col * m) * sizeof(double), s));
   HIP_TRY(launch_basis_batch(scr + off[k], col, m, s));
   HIP_TRY(launch_tail_vcycle_batch<double>(adev, m, c->tail_variant, c->tw64, s));
   HIP_TRY(launch_gather_columns(M, scr + off[k] + (2 * c->lv[k].n + 1), col, m, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  free_since(c, mark);
   float* M32 = nullptr;  // the FP32 V-cycle reads the operator's FP32 rounding
   if (c->mixed) {
     AMG_TRY(dalloc(c, &M32, (size_t)m * m));
@@ -1273,9 +1357,14 @@ void release(amg_ctx* c) {
   c->vgraph = nullptr;
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   c->cap_stream = nullptr;
-  for (void* p : c->dev_allocs) (void)hipFree(p);
+  for (const auto& p : c->dev_allocs) (void)hipFree(p.first);
   c->dev_allocs.clear();
-  for (void* p : c->setup_temps) (void)hipFree(p);
+  for (const auto& p : c->spare) (void)hipFree(p.first);
+  c->spare.clear();
+  c->bump = nullptr;
+  // a setup that failed part-way: its stream may still use the temporaries
+  // (hipFree waits for the device; the pool would not)
+  for (const auto& t : c->setup_temps) (void)hipFree(t.first);
   c->setup_temps.clear();
   if (c->st_host) (void)hipHostFree(c->st_host);
   c->st_host = nullptr;
@@ -1313,6 +1402,11 @@ int scratch_address(int dev, void** out) {
 
 }  // namespace
 
+namespace {
+int setup_impl(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opts_t* opts,
+               void* stream, amg_ctx* donor, amg_t* out);
+}  // namespace
+
 extern "C" {
 
 void amg_default_opts(amg_opts_t* o) {
@@ -1347,6 +1441,25 @@ const char* amg_strerror(int st) {
 
 int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opts_t* opts,
               void* stream, amg_t* out) {
+  return setup_impl(kernel, delta, N, opts, stream, nullptr, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// amg_setup; donor (may be NULL): a handle that is no longer used, on the
+// current device, whose device chunks the new hierarchy reuses where they are
+// large enough (no hipMalloc / hipFree for a hierarchy of the same shape);
+// the donor is destroyed in every case.
+int setup_impl(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opts_t* opts,
+               void* stream, amg_ctx* donor, amg_t* out) {
+  struct DonorGuard {
+    amg_ctx* d;
+    ~DonorGuard() {
+      if (d) (void)amg_destroy(d);
+    }
+  } dg{donor};
   if (!kernel || !out) return AMG_EINVAL;
   *out = nullptr;
   amg_opts_t o;
@@ -1428,6 +1541,18 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
       return hip_fail(e, "hipGetDevice", __LINE__);
     }
     void* sp = nullptr;
+    // the first device chunk holds the whole persistent footprint
+    c->arena_hint = (size_t)footprint(N, &o,
+                                      (kernel->kind == AMG_K_CONST ||
+                                       kernel->kind == AMG_K_FRACTIONAL) &&
+                                          ks.scheme == SCHEME_SHIFTED,
+                                      kernel->kind == AMG_K_WEAKLY_SINGULAR);
+    c->arena_hint += c->arena_hint / 32 + (size_t(2) << 20);
+    if (dg.d && dg.d->device == c->device) {
+      c->spare = std::move(dg.d->dev_allocs);
+      dg.d->dev_allocs.clear();
+      dg.d->bump = nullptr;
+    }
     st = scratch_address(c->device, &sp);
     if (st == AMG_OK) st = setup_device(c, (hipStream_t)stream);
     if (st != AMG_OK) {
@@ -1435,10 +1560,16 @@ int amg_setup(const amg_kernel_t* kernel, double delta, int64_t N, const amg_opt
       delete c;
       return st;
     }
+    for (const auto& p : c->spare) (void)hipFree(p.first);  // chunks left over
+    c->spare.clear();
   }
   *out = c;
   return AMG_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int amg_destroy(amg_t h) {
   if (!h) return AMG_OK;
@@ -2290,8 +2421,9 @@ int run_batch_plan(BatchPlan& P, hipStream_t s) {
     if (P.dev) (void)hipFree(P.dev);
     P.dev = nullptr;
     P.dev_bytes = 0;
-    if (hipMalloc(&P.dev, need) != hipSuccess) return AMG_ENOMEM;
-    P.dev_bytes = need;
+    const size_t grow = need + need / 2;  // rebuilt plans of a server vary in size
+    if (hipMalloc(&P.dev, grow) != hipSuccess) return AMG_ENOMEM;
+    P.dev_bytes = grow;
   }
   HIP_TRY(hipMemcpyAsync(P.dev, P.arena.host.data(), need, hipMemcpyHostToDevice, s));
   // the tables must be in place before the round reads them; pageable source
@@ -2626,6 +2758,7 @@ struct ServerReq {
   int64_t bytes = 0;
   ServerKey key{};
   amg_t h = nullptr;
+  amg_t donor = nullptr;  // an evicted hierarchy whose memory the set-up reuses
   int setup_status = AMG_OK;
   bool cached = false;
 };
@@ -2646,6 +2779,8 @@ struct amg_server {
   bool stop = false;
   std::deque<ServerReq*> pending;   // submitted, not admitted
   std::deque<ServerReq*> setup_q;   // admitted (memory reserved), for a worker
+  std::vector<std::pair<amg_t, int64_t>> release_q;  // evicted, for a worker to free
+  int64_t releasing = 0;                              // their bytes, until freed
   std::vector<ServerReq*> ready;    // hierarchy ready, starts at the next step
   std::vector<ServerReq*> active;   // in the rounds (step thread only)
   std::vector<ServerReq*> failed;   // setup failed, reported by the next poll
@@ -2675,7 +2810,10 @@ amg_t cache_take(amg_server* sv, const ServerKey& key, int64_t* bytes) {
   return h;
 }
 
-// Evict the oldest cached hierarchy (caller holds mu); false if none.
+// Evict the oldest cached hierarchy (caller holds mu); false if none.  A
+// set-up thread releases it (hipFree waits for the device, which neither the
+// rounds nor a submitting thread should do); its bytes stay reserved until
+// then, so the reservation never exceeds the budget.
 bool cache_evict_one(amg_server* sv) {
   if (sv->idle_order.empty()) return false;
   const auto victim = sv->idle_order.front();
@@ -2683,12 +2821,13 @@ bool cache_evict_one(amg_server* sv) {
   auto range = sv->idle.equal_range(victim.first);
   for (auto it = range.first; it != range.second; ++it)
     if (it->second.first == victim.second) {
-      sv->reserved -= it->second.second;
+      sv->release_q.push_back(it->second);
+      sv->releasing += it->second.second;
       sv->idle.erase(it);
       break;
     }
-  (void)amg_destroy(victim.second);
   sv->stats.evictions += 1;
+  sv->cv.notify_one();
   return true;
 }
 
@@ -2710,7 +2849,31 @@ void admit(amg_server* sv) {
       sv->ready.push_back(r);
       continue;
     }
-    while (sv->reserved + r->bytes > sv->budget && cache_evict_one(sv)) {
+    if (sv->reserved + r->bytes > sv->budget) {
+      // an idle hierarchy of the same footprint (the same shape: N, options,
+      // kernel symmetry) hands its device memory to this set-up
+      amg_t victim = nullptr;
+      for (auto o = sv->idle_order.begin(); o != sv->idle_order.end() && !victim; ++o) {
+        auto range = sv->idle.equal_range(o->first);
+        for (auto it = range.first; it != range.second; ++it)
+          if (it->second.first == o->second && it->second.second == r->bytes) {
+            victim = o->second;
+            sv->idle.erase(it);
+            sv->idle_order.erase(o);
+            break;
+          }
+      }
+      if (victim) {
+        r->donor = victim;
+        sv->stats.evictions += 1;
+        sv->stats.cache_misses += 1;
+        sv->pending.pop_front();
+        sv->setup_q.push_back(r);
+        sv->cv.notify_one();
+        continue;
+      }
+    }
+    while (sv->reserved - sv->releasing + r->bytes > sv->budget && cache_evict_one(sv)) {
     }
     if (sv->reserved + r->bytes > sv->budget) break;  // waits for memory
     sv->reserved += r->bytes;
@@ -2722,24 +2885,54 @@ void admit(amg_server* sv) {
   }
 }
 
+int64_t usec_since(std::chrono::steady_clock::time_point t0) {
+  return (int64_t)std::chrono::duration_cast<std::chrono::microseconds>(
+             std::chrono::steady_clock::now() - t0)
+      .count();
+}
+
 void server_worker(amg_server* sv) {
   (void)hipSetDevice(sv->device);
   hipStream_t ws = nullptr;
   (void)hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
   for (;;) {
     ServerReq* r = nullptr;
+    std::pair<amg_t, int64_t> victim{nullptr, 0};
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv.wait(lk, [&] { return sv->stop || !sv->setup_q.empty(); });
-      if (sv->stop && sv->setup_q.empty()) break;
-      r = sv->setup_q.front();
-      sv->setup_q.pop_front();
-      sv->setting_up += 1;
+      sv->cv.wait(lk, [&] {
+        return sv->stop || !sv->setup_q.empty() || !sv->release_q.empty();
+      });
+      if (!sv->release_q.empty()) {
+        victim = sv->release_q.back();
+        sv->release_q.pop_back();
+      } else if (sv->stop) {
+        break;  // queued set-ups are dropped by amg_server_destroy
+      } else {
+        r = sv->setup_q.front();
+        sv->setup_q.pop_front();
+        sv->setting_up += 1;
+      }
+    }
+    if (victim.first) {
+      (void)amg_destroy(victim.first);
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->reserved -= victim.second;
+        sv->releasing -= victim.second;
+        admit(sv);
+      }
+      sv->cv_done.notify_all();
+      continue;
     }
     amg_t h = nullptr;
-    const int st = amg_setup(&r->kernel, r->delta, r->N, &r->opts, ws, &h);
+    const auto t0 = std::chrono::steady_clock::now();
+    const int st = setup_impl(&r->kernel, r->delta, r->N, &r->opts, ws, r->donor, &h);
+    r->donor = nullptr;  // destroyed or taken over by the set-up
+    const int64_t us = usec_since(t0);
     {
       std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stats.setup_us += us;
       r->setup_status = st;
       r->h = h;
       if (st == AMG_OK) {
@@ -2754,6 +2947,17 @@ void server_worker(amg_server* sv) {
     sv->cv_done.notify_all();
   }
   if (ws) (void)hipStreamDestroy(ws);
+}
+
+// Wait for the server stream with short sleeps between queries: the set-up
+// threads keep making runtime calls meanwhile, and a query loop without
+// pauses contends with them.
+hipError_t server_wait(hipStream_t s) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) return e;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
 }
 
 void retire(amg_server* sv, ServerReq* r, const SolveState& st) {
@@ -2789,6 +2993,16 @@ int amg_server_create(int64_t mem_budget_bytes, int workers, void* stream, amg_s
   }
   sv->budget = mem_budget_bytes;
   sv->stream = (hipStream_t)stream;
+  if (!sv->stream) {
+    // an own stream: the legacy default stream would also wait for the
+    // set-up threads' work whenever the rounds are waited for
+    const hipError_t es = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (es != hipSuccess) {
+      delete sv;
+      return hip_fail(es, "hipStreamCreateWithFlags", __LINE__);
+    }
+    sv->own_stream = true;
+  }
   try {
     for (int i = 0; i < workers; ++i) sv->workers.emplace_back(server_worker, sv);
   } catch (...) {
@@ -2861,31 +3075,38 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
     if (sv->active.empty() && rounds > 0)
       sv->cv_done.wait(lk, [&] {
         return !sv->ready.empty() || !sv->failed.empty() ||
-               (sv->setup_q.empty() && sv->setting_up == 0);
+               (sv->setup_q.empty() && sv->setting_up == 0 && sv->releasing == 0);
       });
     start.swap(sv->ready);
   }
+  auto t0 = std::chrono::steady_clock::now();
   for (ServerReq* r : start) {
     AMG_TRY(solve_begin(r->h, r->b, r->x, r->tol, s));
     sv->active.push_back(r);
     sv->dirty = true;
   }
-  if (!start.empty()) HIP_TRY(round_wait(s));  // the starting states are on the host
-  // requests solved by their initial guess leave at once
-  for (size_t i = 0; i < sv->active.size();) {
-    ServerReq* r = sv->active[i];
-    if (r->h->st_host->done) {
-      const SolveState st = *r->h->st_host;
-      sv->active.erase(sv->active.begin() + (long)i);
-      retire(sv, r, st);
-      sv->dirty = true;
-    } else {
-      ++i;
+  // the starting states reach the host with the next wait; a request solved
+  // by its initial guess is gated off in the rounds and retired after them
+  if (!start.empty() && rounds == 0) HIP_TRY(server_wait(s));
+  int64_t t_start = usec_since(t0), t_rebuild = 0, t_rounds = 0;
+  if (rounds == 0) {
+    for (size_t i = 0; i < sv->active.size();) {
+      ServerReq* r = sv->active[i];
+      if (r->h->st_host->done) {
+        const SolveState st = *r->h->st_host;
+        sv->active.erase(sv->active.begin() + (long)i);
+        retire(sv, r, st);
+        sv->dirty = true;
+      } else {
+        ++i;
+      }
     }
   }
   if (!sv->active.empty() && rounds > 0) {
     if (sv->dirty) {
-      HIP_TRY(round_wait(s));
+      // the previous rounds have completed (waited below); the new tables
+      // are copied on the stream, behind the starting requests' work
+      t0 = std::chrono::steady_clock::now();
       std::vector<amg_ctx*> cs;
       std::vector<const double*> bs;
       std::vector<double*> xs;
@@ -2899,14 +3120,18 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
       AMG_TRY(build_batch_plan(sv->plan, cs, bs, xs, ts));
       AMG_TRY(run_batch_plan(sv->plan, s));
       sv->dirty = false;
+      t_rebuild = usec_since(t0);
+      sv->stats.rebuilds += 1;
     }
+    t0 = std::chrono::steady_clock::now();
     for (int k = 0; k < rounds; ++k)
       for (const Launch& L : sv->plan.round) {
         const hipError_t e = L(static_cast<unsigned char*>(sv->plan.dev), s);
         if (e != hipSuccess) return hip_fail(e, "server round", __LINE__);
       }
     sv->stats.rounds += rounds;
-    HIP_TRY(round_wait(s));
+    HIP_TRY(server_wait(s));
+    t_rounds = usec_since(t0);
     for (size_t i = 0; i < sv->active.size();) {
       ServerReq* r = sv->active[i];
       if (r->h->st_host->done) {
@@ -2920,6 +3145,9 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
     }
   }
   std::lock_guard<std::mutex> lk(sv->mu);
+  sv->stats.start_us += t_start;
+  sv->stats.rebuild_us += t_rebuild;
+  sv->stats.rounds_us += t_rounds;
   if (in_flight)
     *in_flight = (int)(sv->active.size() + sv->ready.size() + sv->setup_q.size()) + sv->setting_up;
   if (waiting) *waiting = (int)sv->pending.size();
@@ -2972,10 +3200,14 @@ int amg_server_destroy(amg_server_t sv) {
     delete r;
   }
   for (ServerReq* r : sv->pending) delete r;
-  for (ServerReq* r : sv->setup_q) delete r;
+  for (ServerReq* r : sv->setup_q) {
+    if (r->donor) (void)amg_destroy(r->donor);
+    delete r;
+  }
   for (ServerReq* r : sv->failed) delete r;
   for (auto& kv : sv->idle) (void)amg_destroy(kv.second.first);
   if (sv->plan.dev) (void)hipFree(sv->plan.dev);
+  if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
   delete sv;
   return AMG_OK;
 }

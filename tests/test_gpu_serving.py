@@ -75,6 +75,7 @@ def test_serving_alone_vs_mix():
         for r in reqs:
             bs.append(torch.from_numpy(r["b"]).cuda())
             xs.append(torch.zeros_like(bs[-1]))
+        torch.cuda.synchronize()  # the server reads b and x on its own stream
         results = {}
         for wave in range(4):
             for i in range(wave * 5, wave * 5 + 5):
@@ -115,7 +116,9 @@ def test_serving_admission_and_cache():
     """A budget that holds one hierarchy of N = 2^13 at a time: requests wait
     for memory, the peak reservation stays within the budget, and a second
     wave of the same problems (same kernel, delta, N, options) takes the
-    cached hierarchies; results still equal the solo solves."""
+    cached hierarchies; a third wave with another delta evicts the cached
+    hierarchy and sets up in its memory.  Results still equal the solo
+    solves."""
     N, delta = 2 ** 13, 0.1
     k = B.kernel(B.AMG_K_CONST)
     opts = B.amg_default_opts(**OPTS)
@@ -126,10 +129,15 @@ def test_serving_admission_and_cache():
         g = synthetic.rng(5)
         bs = [torch.from_numpy(g.standard_normal(2 * N - 1)).cuda() for _ in range(6)]
         xs = [torch.zeros_like(b) for b in bs]
+        torch.cuda.synchronize()
         done = {}
-        for wave in range(2):
+        deltas = [delta] * 6 + [0.15] * 3
+        bs += [torch.from_numpy(g.standard_normal(2 * N - 1)).cuda() for _ in range(3)]
+        xs += [torch.zeros_like(b) for b in bs[6:]]
+        torch.cuda.synchronize()
+        for wave in range(3):
             for i in range(wave * 3, wave * 3 + 3):
-                B.amg_server_submit(sv, k, delta, N, bs[i], xs[i], 1e-10, opts)
+                B.amg_server_submit(sv, k, deltas[i], N, bs[i], xs[i], 1e-10, opts)
             for _ in range(500):
                 for res in B.amg_server_poll(sv):
                     done[res[0]] = res
@@ -138,17 +146,19 @@ def test_serving_admission_and_cache():
                 B.amg_server_step(sv, 1)
         st = B.amg_server_stats(sv)
         say("stats", st)
-        assert len(done) == 6 and all(r[1] == B.AMG_OK for r in done.values())
+        assert len(done) == 9 and all(r[1] == B.AMG_OK for r in done.values())
         assert st["peak_reserved_bytes"] <= int(fp * 1.5)
         assert st["cache_hits"] >= 3 and sum(r[4] for r in done.values()) >= 3
-        h = B.amg_setup(k, delta, N, opts)
-        try:
-            for i in range(6):
-                x = torch.zeros_like(bs[i])
-                B.amg_solve(h, bs[i], x, 1e-10)
-                assert torch.equal(x, xs[i]), i
-        finally:
-            B.amg_destroy(h)
+        assert st["evictions"] >= 1
+        for d, idx in ((delta, range(6)), (0.15, range(6, 9))):
+            h = B.amg_setup(k, d, N, opts)
+            try:
+                for i in idx:
+                    x = torch.zeros_like(bs[i])
+                    B.amg_solve(h, bs[i], x, 1e-10)
+                    assert torch.equal(x, xs[i]), i
+            finally:
+                B.amg_destroy(h)
     finally:
         B.amg_server_destroy(sv)
 
