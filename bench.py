@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the precision configuration (N = 2^22, fractional alpha = 0.4, "
                          "delta = 0.1, FP32 V-cycle + FP64 residual, CG) beside the headline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default level geometries (no amg_autotune before the runs)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving run (Poisson arrivals, mixed sizes); 0 = skip")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving arrivals per second")
@@ -807,6 +809,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    tuned = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        B.amg_autotune(13, 23)
+        tuned = {"seconds": round(time.perf_counter() - t0, 3),
+                 "note": "geometry (log2 row length, column tile) per level size 2^logL, chosen by "
+                         "amg_autotune: FP32 + FP64 level matvec, median of 7, every candidate "
+                         "checked against the default geometry's product",
+                 "sizes": {f"2^{lg}": B.amg_plan_get(lg) for lg in range(13, 24)}}
+        print(f"# autotune done: {tuned}", file=sys.stderr, flush=True)
     N = 2 ** args.logN
     b = B.amg_manufactured_rhs(kernel_of(B, args), args.delta, N)
     b_dev = torch.from_numpy(b).cuda()
@@ -884,6 +896,7 @@ def main():
         "pcg": krylov,
         "batch": batch,
         "serving": serve,
+        "autotune": tuned,
         "plain_configs": c2,
         "extensions": ext,
         "precision_config": c3,

@@ -395,6 +395,32 @@ int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
 /* Release every device and host resource of the handle (NULL is a no-op). */
 int amg_destroy(amg_t h);
 
+/* ---- Geometry of the level matvecs and its autotuner --------------------
+ * A level of size L = 2^logL (13 <= logL <= 23; smaller levels run in
+ * one-workgroup kernels) evaluates its FFT product (eq. (ccs3.4)) as a
+ * four-step FFT over an L1 x L2 array (rows of L1 = 2^logL1, columns in
+ * tiles of `tcols`).  Every geometry computes the same product up to FP
+ * rounding order; their speed differs.  The geometry in use is
+ * process-wide, per size, and read when a hierarchy is set up (hierarchies
+ * keep theirs).
+ * amg_autotune: for each size in [logL_min, logL_max], times the level
+ * matvec (FP32 + FP64, general blocks, median of 7) in every candidate
+ * geometry on the current device and stream, rejects a candidate whose FP64
+ * product differs from the default geometry's by more than 1e-11 of its
+ * largest entry, and selects the fastest.  Errors: AMG_EINVAL
+ * (logL_min > logL_max), AMG_EHIP, AMG_ENOMEM. */
+int amg_autotune(int logL_min, int logL_max, void* stream);
+/* The geometry in use for size 2^logL and the autotuner's record of it
+ * (host pointers, each may be NULL): log2 row length, tile width, cost of
+ * the default and of the chosen geometry in microseconds (0: not tuned),
+ * number of candidates and of rejected candidates.  AMG_EINVAL for logL
+ * outside 13..23. */
+int amg_plan_get(int logL, int* logL1, int* tcols, double* us_default, double* us_best,
+                 int* candidates, int* rejected);
+/* Select a candidate geometry for size 2^logL (logL1 = 0: the default).
+ * AMG_EINVAL if logL is outside 13..23 or (logL1, tcols) is no candidate. */
+int amg_plan_set(int logL, int logL1, int tcols);
+
 /* ---- Serving: a request loop with continuous batching ------------------
  * A server solves independent requests (kernel, delta, N, options, b, x,
  * tol), each the same iteration as amg_solve, while requests keep arriving.

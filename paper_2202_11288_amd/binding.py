@@ -115,6 +115,10 @@ def _load():
         "amg_server_poll": (I, [P, ctypes.POINTER(amg_server_result_t), I]),
         "amg_server_stats": (I, [P, ctypes.POINTER(amg_server_stats_t)]),
         "amg_server_destroy": (I, [P]),
+        "amg_autotune": (I, [I, I, P]),
+        "amg_plan_get": (I, [I, IP, IP, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), IP, IP]),
+        "amg_plan_set": (I, [I, I, I]),
         "amg_strerror": (ctypes.c_char_p, [I]),
     }
     for name, (res, args) in sig.items():
@@ -454,3 +458,25 @@ def amg_server_stats(sv) -> dict:
 
 def amg_server_destroy(sv):
     return _check(lib.amg_server_destroy(sv), "amg_server_destroy")
+
+
+def amg_autotune(logL_min: int = 13, logL_max: int = 23, stream=None):
+    """Time every candidate geometry of the level matvec for the sizes
+    2^logL_min .. 2^logL_max and select the fastest (process-wide)."""
+    _check(lib.amg_autotune(int(logL_min), int(logL_max), _stream(stream)), "amg_autotune")
+
+
+def amg_plan_get(logL: int):
+    """The geometry in use for size 2^logL and the tuner's record of it."""
+    l1, tc, cand, rej = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
+    ud, ub = ctypes.c_double(), ctypes.c_double()
+    _check(lib.amg_plan_get(int(logL), ctypes.byref(l1), ctypes.byref(tc), ctypes.byref(ud),
+                            ctypes.byref(ub), ctypes.byref(cand), ctypes.byref(rej)),
+           "amg_plan_get")
+    return {"logL": int(logL), "logL1": l1.value, "tcols": tc.value, "us_default": ud.value,
+            "us_best": ub.value, "candidates": cand.value, "rejected": rej.value}
+
+
+def amg_plan_set(logL: int, logL1: int = 0, tcols: int = 0):
+    """Select a candidate geometry for size 2^logL (logL1 = 0: the default)."""
+    _check(lib.amg_plan_set(int(logL), int(logL1), int(tcols)), "amg_plan_set")

@@ -43,10 +43,10 @@ struct Plan {
   bool tail;
 };
 
-Plan plan_level(int64_t n) {
+// The hand-chosen geometry of a four-step level of size 2^logL (and the
+// tail's for logL <= kTailLog).
+Plan default_plan(int logL) {
   Plan p{};
-  int logL = 0;
-  while ((int64_t(1) << logL) < 2 * (n + 1)) ++logL;
   p.logL = logL;
   p.tail = logL <= kTailLog;
   if (p.tail) {
@@ -71,6 +71,59 @@ Plan plan_level(int64_t n) {
   if ((t << p.logL2) == kCap4 && ((1 << p.logL1) / (2 * t)) >= 256) t *= 2;
   p.tcols = t;
   return p;
+}
+
+bool same_geometry(const Plan& a, const Plan& b) {
+  return a.logL == b.logL && a.logL1 == b.logL1 && a.logL2 == b.logL2 && a.tcols == b.tcols;
+}
+
+// Alternative geometries of a size: every (row length, column tile) whose
+// row-pass and column-pass kernel instances are the ones some default plan
+// runs (the same code, other strides and tile counts), default first.
+std::vector<Plan> plan_candidates(int logL) {
+  std::vector<Plan> out;
+  const Plan d = default_plan(logL);
+  out.push_back(d);
+  if (d.tail) return out;
+  struct ColInst { int logL2, tcols; };
+  std::vector<ColInst> cols;
+  std::vector<int> rows;
+  for (int k = kTailLog + 1; k <= 23; ++k) {
+    const Plan q = default_plan(k);
+    bool seen = false;
+    for (const ColInst& c : cols) seen = seen || (c.logL2 == q.logL2 && c.tcols == q.tcols);
+    if (!seen) cols.push_back({q.logL2, q.tcols});
+    if (std::find(rows.begin(), rows.end(), q.logL1) == rows.end()) rows.push_back(q.logL1);
+  }
+  for (int l1 : rows)
+    for (const ColInst& c : cols) {
+      if (l1 + c.logL2 != logL || (1 << l1) / c.tcols < 64) continue;
+      Plan p = d;
+      p.logL1 = l1;
+      p.logL2 = c.logL2;
+      p.tcols = c.tcols;
+      if (!same_geometry(p, d)) out.push_back(p);
+    }
+  return out;
+}
+
+// Geometries in use per size (process-wide): the default, or the one that
+// amg_plan_set or amg_autotune chose; read when a hierarchy is set up.
+struct PlanChoice {
+  bool set = false;
+  Plan p{};
+  double us_default = 0, us_best = 0;
+  int candidates = 0, rejected = 0;
+};
+std::mutex g_plan_mu;
+PlanChoice g_plan[32];
+
+Plan plan_level(int64_t n) {
+  int logL = 0;
+  while ((int64_t(1) << logL) < 2 * (n + 1)) ++logL;
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  if (logL < 32 && g_plan[logL].set) return g_plan[logL].p;
+  return default_plan(logL);
 }
 
 struct LevelRes {
@@ -1644,6 +1697,12 @@ int amg_matvec_noalloc(amg_t h, const double* x, double* y, void* stream) {
                    (long long)h->N, (long long)kScratchMaxN);
     return AMG_EINVAL;
   }
+  {
+    // the block partials of the level's geometry must fit their slot
+    const Plan& q = h->lv[0].plan;
+    const size_t nb = (size_t)std::max(col_blocks(q.logL1, q.tcols), (1 << q.logL2) / 2);
+    if (!q.tail && nb * sizeof(double) > kScratchPartBytes) return AMG_EINVAL;
+  }
   HIP_TRY(hipSetDevice(h->device));
   void* sp = nullptr;
   AMG_TRY(scratch_address(h->device, &sp));
@@ -2041,7 +2100,30 @@ struct SweepItem {
   int gate;
 };
 template <typename T>
+void add_sweep_geom(BatchPlan& P, const std::vector<SweepItem<T>>& items);
+
+// Items of one level size may differ in geometry (hierarchies set up before
+// and after a change of plan): one set of launches per geometry.
+template <typename T>
 void add_sweep(BatchPlan& P, const std::vector<SweepItem<T>>& items) {
+  std::vector<std::pair<int, int>> geoms;
+  for (const auto& it : items) {
+    const Plan& q = it.c->lv[it.l].plan;
+    if (std::find(geoms.begin(), geoms.end(), std::make_pair(q.logL1, q.tcols)) == geoms.end())
+      geoms.push_back({q.logL1, q.tcols});
+  }
+  for (const auto& g : geoms) {
+    std::vector<SweepItem<T>> part;
+    for (const auto& it : items) {
+      const Plan& q = it.c->lv[it.l].plan;
+      if (q.logL1 == g.first && q.tcols == g.second) part.push_back(it);
+    }
+    add_sweep_geom<T>(P, part);
+  }
+}
+
+template <typename T>
+void add_sweep_geom(BatchPlan& P, const std::vector<SweepItem<T>>& items) {
   if (items.empty()) return;
   const Twiddles<T>& tw = tw_of<T>(items[0].c);
   // pass 1 by prologue mode
@@ -2700,6 +2782,198 @@ int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
   return footprint(N, &o, (kernel->kind == AMG_K_CONST || kernel->kind == AMG_K_FRACTIONAL) &&
                               ks.scheme == SCHEME_SHIFTED,
                    kernel->kind == AMG_K_WEAKLY_SINGULAR);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Geometry autotuner: per four-step size, the (row length, column tile) of
+// the level matvec that runs fastest on this GPU among the candidates.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename F>
+int time_median(hipStream_t s, int reps, F&& f, double* us) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return AMG_EHIP;
+  }
+  std::vector<float> t;
+  int st = AMG_OK;
+  for (int r = 0; r < reps && st == AMG_OK; ++r) {
+    float ms = 0;
+    if (hipEventRecord(e0, s) != hipSuccess) st = AMG_EHIP;
+    if (st == AMG_OK) st = f();
+    if (st == AMG_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                         hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = AMG_EHIP;
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != AMG_OK) return st;
+  std::sort(t.begin(), t.end());
+  *us = 1e3 * (double)t[t.size() / 2];
+  return AMG_OK;
+}
+
+// One size: a level of general blocks (random generators and Cross data)
+// with each candidate geometry; the FP64 product of every candidate must
+// agree with the default geometry's to 1e-11 of its largest entry, else the
+// candidate is rejected; cost = median FP32 + median FP64 matvec time.
+int tune_size(int dev, int logL, hipStream_t s, PlanChoice* out) {
+  const std::vector<Plan> cands = plan_candidates(logL);
+  *out = PlanChoice{};
+  out->p = cands[0];
+  out->candidates = (int)cands.size();
+  if (cands[0].tail) return AMG_OK;
+  const int64_t L = int64_t(1) << logL, n = L / 2 - 1, m = 2 * n + 1;
+  amg_ctx t;
+  t.device = dev;
+  t.mixed = true;
+  struct Guard {
+    amg_ctx* c;
+    hipStream_t s;
+    ~Guard() {
+      (void)hipStreamSynchronize(s);
+      free_setup_temps(c);
+      release(c);
+    }
+  } guard{&t, s};
+  AMG_TRY(device_twiddles(dev, s, &t.tw64, &t.tw32));
+  AMG_TRY(dalloc(&t, &t.buf64, (size_t)L));
+  AMG_TRY(dalloc(&t, &t.buf32, (size_t)L));
+  cplx<double>* zs = nullptr;
+  AMG_TRY(dalloc(&t, &zs, (size_t)L));
+  double *ga, *gb, *gc, *gd, *cx, *x, *y;
+  float *cxf, *xf, *yf;
+  for (double** g : {&ga, &gb, &gc, &gd}) AMG_TRY(dalloc(&t, g, (size_t)(2 * n - 1)));
+  AMG_TRY(dalloc(&t, &cx, (size_t)(4 * n)));
+  AMG_TRY(dalloc(&t, &x, (size_t)m));
+  AMG_TRY(dalloc(&t, &y, (size_t)m));
+  AMG_TRY(dalloc(&t, &cxf, (size_t)(4 * n)));
+  AMG_TRY(dalloc(&t, &xf, (size_t)m));
+  AMG_TRY(dalloc(&t, &yf, (size_t)m));
+  unsigned seed = 1;
+  for (double* g : {ga, gb, gc, gd}) HIP_TRY(launch_fill_hash(g, 2 * n - 1, seed++, s));
+  HIP_TRY(launch_fill_hash(cx, 4 * n, seed++, s));
+  HIP_TRY(launch_fill_hash(x, m, seed++, s));
+  HIP_TRY(launch_copy_d2f(cx, cxf, 4 * n, s));
+  HIP_TRY(launch_copy_d2f(x, xf, m, s));
+  int maxb = 1;
+  for (const Plan& q : cands)
+    maxb = std::max({maxb, col_blocks(q.logL1, q.tcols), (1 << q.logL2) / 2});
+  AMG_TRY(dalloc(&t, &t.dpart64, (size_t)maxb));
+  AMG_TRY(dalloc(&t, &t.dpart32, (size_t)maxb));
+  AMG_TRY(dalloc(&t, &t.npart, (size_t)std::max(maxb, vec_blocks(m))));
+  t.lv.resize(1);
+  LevelRes& R = t.lv[0];
+  R.n = n;
+  R.sym = false;
+  R.o = R.dv = R.dw = 1.0;
+  R.pd = cx;
+  R.qd = cx + n;
+  R.xid = cx + 2 * n;
+  R.zetad = cx + 3 * n;
+  R.pf = cxf;
+  R.qf = cxf + n;
+  R.xif = cxf + 2 * n;
+  R.zetaf = cxf + 3 * n;
+  AMG_TRY(dalloc(&t, &R.scald, 4));
+  AMG_TRY(dalloc(&t, &R.scalf, 4));
+  std::vector<double> yref((size_t)m), ycur((size_t)m);
+  double best = 0;
+  for (size_t k = 0; k < cands.size(); ++k) {
+    R.plan = cands[k];
+    AMG_TRY(level_spectra_dev(&t, ga, gb, gc, gd, R, true, zs, s));
+    AMG_TRY(level_matvec<double>(&t, 0, x, y, s));
+    std::vector<double>& h = k == 0 ? yref : ycur;
+    HIP_TRY(hipMemcpyAsync(h.data(), y, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (k > 0) {
+      double dmax = 0, ymax = 0;
+      bool fin = true;
+      for (int64_t i = 0; i < m; ++i) {
+        fin = fin && std::isfinite(ycur[(size_t)i]);
+        dmax = std::max(dmax, std::fabs(ycur[(size_t)i] - yref[(size_t)i]));
+        ymax = std::max(ymax, std::fabs(yref[(size_t)i]));
+      }
+      if (!fin || !(dmax <= 1e-11 * ymax)) {
+        out->rejected += 1;
+        continue;
+      }
+    }
+    double us32 = 0, us64 = 0;
+    AMG_TRY(level_matvec<float>(&t, 0, xf, yf, s));  // warm-up
+    AMG_TRY(time_median(s, 7, [&] { return level_matvec<float>(&t, 0, xf, yf, s); }, &us32));
+    AMG_TRY(time_median(s, 7, [&] { return level_matvec<double>(&t, 0, x, y, s); }, &us64));
+    const double cost = us32 + us64;
+    if (k == 0) out->us_default = cost;
+    if (k == 0 || cost < best) {
+      best = cost;
+      out->p = cands[k];
+    }
+  }
+  out->us_best = best;
+  out->set = true;
+  return AMG_OK;
+}
+
+bool plan_size_ok(int logL) { return logL > kTailLog && logL <= 23; }
+
+}  // namespace
+
+extern "C" {
+
+int amg_autotune(int logL_min, int logL_max, void* stream) {
+  if (logL_min > logL_max) return AMG_EINVAL;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipStream_t s = (hipStream_t)stream;
+  for (int lg = std::max(logL_min, kTailLog + 1); lg <= std::min(logL_max, 23); ++lg) {
+    PlanChoice pc;
+    AMG_TRY(tune_size(dev, lg, s, &pc));
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_plan[lg] = pc;
+  }
+  return AMG_OK;
+}
+
+int amg_plan_get(int logL, int* logL1, int* tcols, double* us_default, double* us_best,
+                 int* candidates, int* rejected) {
+  if (!plan_size_ok(logL)) return AMG_EINVAL;
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  const PlanChoice& c = g_plan[logL];
+  const Plan p = c.set ? c.p : default_plan(logL);
+  if (logL1) *logL1 = p.logL1;
+  if (tcols) *tcols = p.tcols;
+  if (us_default) *us_default = c.us_default;
+  if (us_best) *us_best = c.us_best;
+  if (candidates) *candidates = c.set ? c.candidates : (int)plan_candidates(logL).size();
+  if (rejected) *rejected = c.rejected;
+  return AMG_OK;
+}
+
+int amg_plan_set(int logL, int logL1, int tcols) {
+  if (!plan_size_ok(logL)) return AMG_EINVAL;
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  if (logL1 == 0) {
+    g_plan[logL] = PlanChoice{};
+    return AMG_OK;
+  }
+  const std::vector<Plan> cands = plan_candidates(logL);
+  for (const Plan& p : cands)
+    if (p.logL1 == logL1 && p.tcols == tcols) {
+      g_plan[logL] = PlanChoice{};
+      g_plan[logL].set = true;
+      g_plan[logL].p = p;
+      g_plan[logL].candidates = (int)cands.size();
+      return AMG_OK;
+    }
+  return AMG_EINVAL;
 }
 
 }  // extern "C"

@@ -295,6 +295,7 @@ hipError_t launch_finish(SolveState* st, const double* part, int npart, double t
                          double* hist, hipStream_t s, int verify = 0,
                          SolveState* host = nullptr);
 hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s);
+hipError_t launch_fill_hash(double* p, int64_t n, unsigned seed, hipStream_t s);
 // part[2b] = a.z, part[2b+1] = c.z over chunk b (c may be null); z FP64 or FP32
 template <typename TZ>
 hipError_t launch_vdot(const double* a, const TZ* z, const double* c, int64_t m, double* part,

@@ -166,6 +166,27 @@ __global__ void k_level_scalars(const double* a, const double* d, const double* 
   }
 }
 
+// Deterministic test data in [-1/2, 1/2) (a 32-bit integer hash of the
+// index and the seed; inputs of the geometry tuner, whose results are only
+// compared with each other).
+__global__ __launch_bounds__(kSetupNT) void k_fill_hash(double* p, int64_t n, unsigned seed) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    unsigned h = (unsigned)i * 0x9E3779B1u ^ (unsigned)(i >> 32) ^ (seed * 0x85EBCA77u);
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    p[i] = (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
+  }
+}
+
+hipError_t launch_fill_hash(double* p, int64_t n, unsigned seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_hash, setup_grid(n), kSetupNT, 0, s, p, n, seed);
+  return hipGetLastError();
+}
+
 hipError_t launch_finest_level(const double* Wn, int64_t Sn, const double* Wm, int64_t Sm,
                                int64_t n, double scale, double shift, const DevTpx& f, int* bad,
                                hipStream_t s) {
