@@ -215,3 +215,23 @@ def test_gmres_option():
         f1 = B.amg_footprint_bytes(k, 0.1, 2 ** 16, B.amg_default_opts(inner=B.AMG_INNER_GMRES,
                                                                         restart=R))
         assert f1 - f0 >= (2 * R + 1) * (2 * 2 ** 16 - 1) * 8
+
+
+def test_plan_get_set_host_logic():
+    """The geometry table is host state: defaults per size, candidates only,
+    reset with logL1 = 0; sizes outside 13..23 are rejected."""
+    d = {lg: B.amg_plan_get(lg) for lg in range(13, 24)}
+    assert d[21]["logL1"] == 11 and d[21]["tcols"] == 8 and d[21]["us_best"] == 0.0
+    assert d[13]["candidates"] == 1 and d[19]["candidates"] == 6
+    try:
+        B.amg_plan_set(19, 11, 4)
+        assert (B.amg_plan_get(19)["logL1"], B.amg_plan_get(19)["tcols"]) == (11, 4)
+        with pytest.raises(B.AmgError):
+            B.amg_plan_set(19, 7, 4)  # 2^7 x 2^12: no column pass instance
+        with pytest.raises(B.AmgError):
+            B.amg_plan_get(12)
+        with pytest.raises(B.AmgError):
+            B.amg_plan_set(24, 12, 4)
+    finally:
+        B.amg_plan_set(19)
+    assert (B.amg_plan_get(19)["logL1"], B.amg_plan_get(19)["tcols"]) == (10, 4)
