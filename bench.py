@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the precision configuration (N = 2^22, fractional alpha = 0.4, "
                          "delta = 0.1, FP32 V-cycle + FP64 residual, CG) beside the headline")
+    ap.add_argument("--no-deep-fold", action="store_true",
+                    help="headline forms without AMG_FLAG_DEEP_FOLD (the cycle below the four-step "
+                         "levels in the one-workgroup kernel rather than as one dense product)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default level geometries (no amg_autotune before the runs)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -248,6 +251,8 @@ def run_form(B, torch, args, precision, b_dev, profile=False, inner=0):
     preconditioned CG)."""
     N = 2 ** args.logN
     flags = B.AMG_FLAG_PROFILE if profile else 0
+    if not args.no_deep_fold:
+        flags |= B.AMG_FLAG_DEEP_FOLD
     opts = B.amg_default_opts(precision=precision, flags=flags, max_iter=500, inner=inner)
     steps = args.prof_steps if profile else args.steps
     warmup = 1 if profile else args.warmup
@@ -887,7 +892,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"manufactured u=x^2(1-x)^2, {args.kernel} kernel, delta={args.delta}, "
                                f"N=2^{args.logN} intervals ({2 * N - 1} unknowns), tol={args.tol}, "
-                               "V-cycle to 2^5, omega=2/3, m1=m2=1",
+                               "V-cycle to 2^5, omega=2/3, m1=m2=1"
+                               + ("" if args.no_deep_fold else
+                                  ", levels <= 2^11 as one folded dense product (AMG_FLAG_DEEP_FOLD)"),
                    "N": N, "unknowns": 2 * N - 1, "delta": args.delta, "kernel": args.kernel,
                    "tol": args.tol},
         "unknowns_per_s": smx["unknowns_per_s"],

@@ -217,6 +217,14 @@ typedef struct {
    near-field pass (129 terms per unknown) per outer residual and FP64
    spectra of the far field. */
 #define AMG_FLAG_ACCURATE_RESIDUAL 8
+/* V-cycles only: the cycle below the four-step levels (levels of 2^12 or
+ * fewer intervals, when the problem has more) is formed at setup as its
+ * dense matrix (up to 4095 x 4095, from the unit vectors; about 2 ms more
+ * setup and 201 MB (mixed) or 134 MB (FP64) more memory at its largest) and
+ * applied as one product by many workgroups, in place of the one-workgroup
+ * kernel that runs those levels one after another.  The same linear map up
+ * to rounding; pays off when a hierarchy serves many V-cycles. */
+#define AMG_FLAG_DEEP_FOLD 16
 
 /* Per-kernel timing accumulated while AMG_FLAG_PROFILE is set. */
 typedef struct {

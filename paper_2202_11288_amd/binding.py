@@ -25,6 +25,7 @@ AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2
 AMG_FLAG_EAGER = 4
 AMG_FLAG_ACCURATE_RESIDUAL = 8
+AMG_FLAG_DEEP_FOLD = 16
 AMG_INNER_VCYCLE, AMG_INNER_PCG, AMG_INNER_GMRES = 0, 1, 2
 AMG_SCHEME_SHIFTED, AMG_SCHEME_STANDARD = 0, 1
 

@@ -277,6 +277,11 @@ struct amg_ctx {
   // below and including that level, which is linear in its right-hand side.
   int vc_last = 0;
   CoarseLU lu_vc{};
+  // AMG_FLAG_DEEP_FOLD: the cycle below the four-step levels as one dense
+  // product (row-major m x m, FP64 and its FP32 rounding); m = 0: not formed
+  int deep_m = 0;
+  const double* deep64 = nullptr;
+  const float* deep32 = nullptr;
   // The same for W-cycles: the small-level programs stop at level w_last and
   // apply lu_w there (the coarsest inverse, or the matrix of all the visits a
   // level receives each time the level above descends).
@@ -529,7 +534,7 @@ int check_opts(const amg_opts_t* o) {
   if (o->precision != AMG_FP64 && o->precision != AMG_MIXED) return AMG_EINVAL;
   if (o->max_iter < 0 || o->max_iter > 100000) return AMG_EINVAL;
   if (o->flags & ~(AMG_FLAG_HOST_ONLY | AMG_FLAG_PROFILE | AMG_FLAG_EAGER |
-                   AMG_FLAG_ACCURATE_RESIDUAL))
+                   AMG_FLAG_ACCURATE_RESIDUAL | AMG_FLAG_DEEP_FOLD))
     return AMG_EINVAL;
   if (o->inner != AMG_INNER_VCYCLE && o->inner != AMG_INNER_PCG && o->inner != AMG_INNER_GMRES)
     return AMG_EINVAL;
@@ -537,6 +542,22 @@ int check_opts(const amg_opts_t* o) {
   if (o->cycle != 1 && o->cycle != 2) return AMG_EINVAL;
   if (!(std::isfinite(o->scale) && o->scale > 0.0) || !std::isfinite(o->shift)) return AMG_EINVAL;
   return AMG_OK;
+}
+
+// Unknowns of the deep fold's level (AMG_FLAG_DEEP_FOLD): the first level
+// with L <= 2^kTailLog below the finest, if it has more than kSubDenseMax
+// unknowns; 0 otherwise.
+int64_t deep_fold_size(int64_t N, const amg_opts_t* o) {
+  const int64_t nc = (int64_t(1) << o->coarsest_log2) - 1;
+  int64_t n = N - 1;
+  for (int l = 0;; ++l) {
+    if (2 * (n + 1) <= (int64_t(1) << kTailLog)) {
+      const int64_t m = 2 * n + 1;
+      return (l >= 1 && n > nc && m > kSubDenseMax && m <= kFoldMax) ? m : 0;
+    }
+    if (n <= nc) return 0;
+    n = (n - 1) / 2;
+  }
 }
 
 int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess, bool band) {
@@ -567,12 +588,22 @@ int64_t footprint(int64_t N, const amg_opts_t* o, bool sym_guess, bool band) {
   const int64_t md = o->cycle == 2 ? kSubDenseMaxW : kSubDenseMax;
   if (mc < md) bytes += md * md * (mixed ? 12 : 8);  // the folded sub-cycle's operator
   bytes += (int64_t)(kTwM + kTw4Lo + kTw4Hi) * 24;
+  if ((o->flags & AMG_FLAG_DEEP_FOLD) && o->cycle == 1) {
+    const int64_t md = deep_fold_size(N, o);
+    bytes += md * md * (mixed ? 12 : 8);
+  }
   if (o->flags & AMG_FLAG_ACCURATE_RESIDUAL)  // far-field spectra + Cross, near-field output
     bytes += (sym_guess ? 2 : 4) * L0 * 8 + 4 * (N - 1) * 8 + (2 * N - 1) * 8 +
              (4 * kNearM + 2) * 8;
   return bytes;
 }
 
+template <typename T>
+const T* deep_of(const amg_ctx* c);
+template <>
+const double* deep_of<double>(const amg_ctx* c) { return c->deep64; }
+template <>
+const float* deep_of<float>(const amg_ctx* c) { return c->deep32; }
 template <typename T>
 const Twiddles<T>& tw_of(const amg_ctx* c);
 template <>
@@ -676,8 +707,13 @@ int vcycle_dev(amg_ctx* c, hipStream_t s) {
   {
     const T* rf = (ft > 0) ? c->lv[ft - 1].template dev<T>().r : nullptr;
     const size_t t0 = c->prof.mark(s);
-    HIP_TRY(launch_tail_vcycle<T>(lvdev_of<T>(c), ft, c->vc_last, rf, o.m1, o.m2, wpre, wpost,
-                                  c->lu_vc, tw_of<T>(c), c->maxL_tail, c->tail_variant, s));
+    if (c->deep_m) {
+      T* u = c->lv[ft].template dev<T>().u;
+      const hipError_t e = launch_fold_gemv<T, T>(rf, c->deep_m, deep_of<T>(c), u, s);
+      if (e != hipSuccess) return hip_fail(e, "launch_fold_gemv", __LINE__);
+    } else
+      HIP_TRY(launch_tail_vcycle<T>(lvdev_of<T>(c), ft, c->vc_last, rf, o.m1, o.m2, wpre, wpost,
+                                    c->lu_vc, tw_of<T>(c), c->maxL_tail, c->tail_variant, s));
     c->prof.span(PK_TAIL, t0, c->prof.mark(s));
   }
   for (int l = ft - 1; l >= 0; --l) {
@@ -978,6 +1014,82 @@ int form_sub_vcycle(amg_ctx* c, hipStream_t s) {
   }
   c->vc_last = k;
   c->lu_vc = {m, M, M32};
+  return AMG_OK;
+}
+
+// AMG_FLAG_DEEP_FOLD: the V-cycle below the four-step levels (the small-
+// level kernel's levels first_tail .. vc_last and the operator it applies
+// there) is a linear map of level first_tail's right-hand side; its matrix
+// is formed from the unit vectors (the FP64 small-level kernel, in chunks of
+// columns) and stored row-major for the multi-workgroup product.
+int form_deep_fold(amg_ctx* c, hipStream_t s) {
+  const int nl = (int)c->lv.size();
+  const int k = c->first_tail;
+  const int64_t md = deep_fold_size(c->N, &c->opts);
+  if (md == 0 || k < 1 || k >= nl || 2 * c->lv[k].n + 1 != md || c->vc_last <= k) return AMG_OK;
+  const amg_opts_t& o = c->opts;
+  const int m = (int)md;
+  const int last = c->vc_last;
+  double* M = nullptr;
+  AMG_TRY(dalloc(c, &M, (size_t)m * m));
+  int64_t col = 0;
+  std::vector<int64_t> off(nl, 0);
+  for (int l = k; l <= last; ++l) {
+    off[l] = col;
+    col += 3 * (2 * c->lv[l].n + 1) + 4;
+  }
+  col = (col + 31) & ~int64_t(31);
+  constexpr int kChunk = 1024;
+  double* scr = nullptr;
+  AMG_TRY(dalloc_temp(c, &scr, (size_t)(col * std::min(m, kChunk))));
+  for (int j0 = 0; j0 < m; j0 += kChunk) {
+    const int cnt = std::min(kChunk, m - j0);
+    std::vector<LevelDev<double>> tables((size_t)cnt * nl);
+    for (int j = 0; j < cnt; ++j)
+      for (int l = 0; l < nl; ++l) {
+        LevelDev<double> d = c->lv[l].dev<double>();
+        if (l >= k && l <= last) {
+          const int64_t sz = 2 * c->lv[l].n + 1;
+          double* base = scr + (int64_t)j * col + off[l];
+          d.b = base;
+          d.u = base + sz;
+          d.r = base + 2 * sz;
+          d.scal = base + 3 * sz;
+        }
+        tables[(size_t)j * nl + l] = d;
+      }
+    LevelDev<double>* tdev = nullptr;
+    AMG_TRY(upload_temp(c, &tdev, tables, s));
+    std::vector<TailArgs<double>> args((size_t)cnt);
+    for (int j = 0; j < cnt; ++j) {
+      TailArgs<double>& a = args[(size_t)j];
+      a.levels = tdev + (size_t)j * nl;
+      a.first = k;
+      a.last = last;
+      a.rf = nullptr;
+      a.m1 = o.m1;
+      a.m2 = o.m2;
+      a.wpre = o.omega_pre;
+      a.wpost = o.omega_post;
+      a.lu = c->lu_vc;
+      a.st = nullptr;
+      a.gate = GATE_ACTIVE;
+    }
+    TailArgs<double>* adev = nullptr;
+    AMG_TRY(upload_temp(c, &adev, args, s));
+    HIP_TRY(hipMemsetAsync(scr, 0, (size_t)(col * cnt) * sizeof(double), s));
+    HIP_TRY(launch_basis_batch(scr + off[k], col, m, s, cnt, j0));
+    HIP_TRY(launch_tail_vcycle_batch<double>(adev, cnt, c->tail_variant, c->tw64, s));
+    HIP_TRY(launch_gather_rows(M, scr + off[k] + m, col, m, j0, cnt, s));
+  }
+  float* M32 = nullptr;
+  if (c->mixed) {
+    AMG_TRY(dalloc(c, &M32, (size_t)m * m));
+    HIP_TRY(launch_copy_d2f(M, M32, (int64_t)m * m, s));
+  }
+  c->deep_m = m;
+  c->deep64 = M;
+  c->deep32 = M32;
   return AMG_OK;
 }
 
@@ -1361,6 +1473,7 @@ int setup_device(amg_ctx* c, hipStream_t s) {
   c->vc_last = nl - 1;
   c->lu_vc = c->lu;
   if (c->opts.cycle != 2) AMG_TRY(form_sub_vcycle(c, s));
+  if (c->opts.cycle == 1 && (c->opts.flags & AMG_FLAG_DEEP_FOLD)) AMG_TRY(form_deep_fold(c, s));
   if (c->opts.cycle == 2) {
     const int ft = c->first_tail;
     c->w_last = nl - 1;
@@ -2202,11 +2315,37 @@ void plan_vcycle(BatchPlan& P, const std::vector<amg_ctx*>& cs, const std::vecto
     }
   }
   // the small levels and the coarsest solve, one block per instance
+  {
+    // instances with the deep fold: one product per instance, one launch
+    std::vector<FoldArgs<T>> v;
+    int mmax = 0;
+    for (int i : idx) {
+      amg_ctx* c = cs[i];
+      if (!c->deep_m) continue;
+      FoldArgs<T> a{};
+      a.rf = c->lv[c->first_tail - 1].template dev<T>().r;
+      a.M = deep_of<T>(c);
+      a.u = c->lv[c->first_tail].template dev<T>().u;
+      a.m = c->deep_m;
+      a.st = c->st_dev;
+      a.gate = gates[i];
+      v.push_back(a);
+      mmax = std::max(mmax, a.m);
+    }
+    if (!v.empty()) {
+      const size_t off = P.arena.put(v.data(), v.size() * sizeof(FoldArgs<T>));
+      const int count = (int)v.size();
+      P.round.push_back([=](unsigned char* dev, hipStream_t s) {
+        return launch_fold_gemv_batch<T>(reinterpret_cast<const FoldArgs<T>*>(dev + off), count,
+                                         mmax, s);
+      });
+    }
+  }
   for (int variant = 0; variant < 4; ++variant) {
     std::vector<TailArgs<T>> v;
     for (int i : idx) {
       amg_ctx* c = cs[i];
-      if (c->tail_variant != variant) continue;
+      if (c->deep_m || c->tail_variant != variant) continue;
       TailArgs<T> a{};
       a.levels = lvdev_of<T>(c);
       a.first = c->first_tail;
@@ -2989,7 +3128,7 @@ int amg_plan_set(int logL, int logL1, int tcols) {
 namespace {
 
 struct ServerKey {
-  int kind, scheme, precision, inner, m1, m2, coarsest, max_iter;
+  int kind, scheme, precision, inner, m1, m2, coarsest, max_iter, flags;
   double alpha, wl, wr, delta, omega_pre, omega_post, shift, scale;
   int64_t N;
   bool operator<(const ServerKey& o) const {
@@ -3008,6 +3147,7 @@ ServerKey server_key(const amg_kernel_t& k, double delta, int64_t N, const amg_o
   key.m2 = o.m2;
   key.coarsest = o.coarsest_log2;
   key.max_iter = o.max_iter;
+  key.flags = o.flags;
   key.alpha = k.kind == AMG_K_FRACTIONAL ? k.alpha : 0.0;
   key.wl = k.kind == AMG_K_WEIGHTED ? k.wl : 0.0;
   key.wr = k.kind == AMG_K_WEIGHTED ? k.wr : 0.0;

@@ -180,6 +180,17 @@ struct TailArgs {
   const SolveState* st;
   int gate;
 };
+// The folded V-cycle below the four-step levels as one dense product (see
+// launch_fold_gemv): per instance of a batch.
+template <typename T>
+struct FoldArgs {
+  const T* rf;   // fine residual (2m + 1)
+  const T* M;    // row-major m x m
+  T* u;          // output (m)
+  int m;
+  const SolveState* st;
+  int gate;
+};
 struct VdotArgs {           // part[2b] = a.z, part[2b+1] = c.z over chunk b
   const SolveState* st;
   int gate;
@@ -296,6 +307,18 @@ hipError_t launch_finish(SolveState* st, const double* part, int npart, double t
                          SolveState* host = nullptr);
 hipError_t launch_copy_d2f(const double* a, float* b, int64_t m, hipStream_t s);
 hipError_t launch_fill_hash(double* p, int64_t n, unsigned seed, hipStream_t s);
+// u = M (R rf): R the restriction 1/4 [1 2 1] of the fine residual rf
+// (2m + 1 entries) to m entries, M row-major m x m (m <= kFoldMax); FP64
+// accumulation, one wavefront per row, kFoldRows rows per block.
+constexpr int kFoldMax = 4095;
+template <typename T, typename MT>
+hipError_t launch_fold_gemv(const T* rf, int m, const MT* M, T* u, hipStream_t s);
+template <typename T>
+hipError_t launch_fold_gemv_batch(const FoldArgs<T>* args, int count, int m, hipStream_t s);
+// Columns j0 .. j0+count-1 of a row-major m x m matrix from the vectors at
+// src + k * stride (k = 0 .. count-1, m entries each).
+hipError_t launch_gather_rows(double* M, const double* src, int64_t stride, int m, int j0,
+                              int count, hipStream_t s);
 // part[2b] = a.z, part[2b+1] = c.z over chunk b (c may be null); z FP64 or FP32
 template <typename TZ>
 hipError_t launch_vdot(const double* a, const TZ* z, const double* c, int64_t m, double* part,
@@ -346,7 +369,10 @@ hipError_t launch_copy_f2d(const float* a, double* b, int64_t m, hipStream_t s);
 hipError_t launch_publish(const SolveState* st, SolveState* host, hipStream_t s);
 hipError_t launch_basis(double* b, int m, int j, hipStream_t s);
 // b_j = e_j for j < m, b_j at base + j * stride
-hipError_t launch_basis_batch(double* base, int64_t stride, int m, hipStream_t s);
+// Unit vectors e_{j0 + k} (m entries) at base + k * stride, k < count
+// (count < 0: m vectors from j0 = 0).
+hipError_t launch_basis_batch(double* base, int64_t stride, int m, hipStream_t s, int count = -1,
+                              int j0 = 0);
 // M[:, j] = u_j (column-major m x m), u_j at base + j * stride
 hipError_t launch_gather_columns(double* M, const double* base, int64_t stride, int m,
                                  hipStream_t s);

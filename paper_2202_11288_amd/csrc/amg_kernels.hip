@@ -1173,15 +1173,17 @@ __global__ void k_basis(double* b, int m, int j) {
 }
 // Column j of a batch of unit-vector right-hand sides: b_j = e_j, where b_j
 // starts at base + j * stride (m entries each, m columns).
-__global__ void k_basis_batch(double* base, int64_t stride, int m) {
+__global__ void k_basis_batch(double* base, int64_t stride, int m, int j0) {
   const int j = blockIdx.y;
   double* b = base + (int64_t)j * stride;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
-    b[i] = i == j ? 1.0 : 0.0;
+    b[i] = i == j0 + j ? 1.0 : 0.0;
 }
-hipError_t launch_basis_batch(double* base, int64_t stride, int m, hipStream_t s) {
-  if (m < 1 || m > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_basis_batch, dim3((m + 255) / 256, m), 256, 0, s, base, stride, m);
+hipError_t launch_basis_batch(double* base, int64_t stride, int m, hipStream_t s, int count,
+                              int j0) {
+  if (count < 0) count = m;
+  if (m < 1 || count < 1 || count > 65535 || j0 < 0 || j0 + count > m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_basis_batch, dim3((m + 255) / 256, count), 256, 0, s, base, stride, m, j0);
   return hipGetLastError();
 }
 // M[:, j] = u_j (column-major m x m), u_j at base + j * stride.
@@ -1535,6 +1537,108 @@ hipError_t launch_tail_vcycle_batch(const TailArgs<T>* args, int count, int vari
   }
 }
 
+// ---------------------------------------------------------------------------
+// The folded V-cycle below the four-step levels (its matrix formed at setup
+// from the unit vectors) as one product over many workgroups: every block
+// restricts the fine residual into LDS (FP64), then each wavefront takes
+// rows, lanes striding the row (coalesced), four partial sums per lane in a
+// fixed order and a butterfly over the wavefront.
+// ---------------------------------------------------------------------------
+constexpr int kFoldNT = 512;
+constexpr int kFoldRows = 8;  // one row per wavefront
+
+template <typename T, typename MT>
+__device__ __forceinline__ void fold_gemv_body(const T* __restrict__ rf, int m,
+                                               const MT* __restrict__ M, T* __restrict__ u,
+                                               int block) {
+  extern __shared__ double fb[];  // m values of R rf
+  for (int i = threadIdx.x; i < m; i += kFoldNT) fb[i] = (double)restrict_at(rf, i);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int rr = wave; rr < kFoldRows; rr += kFoldNT / 64) {
+    const int row = block * kFoldRows + rr;
+    if (row >= m) break;  // uniform in the wavefront
+    const MT* a = M + (size_t)row * (size_t)m;
+    // U loads in flight per lane (a row of 4095 in two batches of FP32 or
+    // four of FP64), four partial sums
+    constexpr int U = sizeof(MT) == 4 ? 32 : 16;
+    double acc[4] = {0, 0, 0, 0};
+    int j = lane;
+    for (; j + 64 * (U - 1) < m; j += 64 * U) {
+      MT av[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) av[k] = a[j + 64 * k];
+#pragma unroll
+      for (int k = 0; k < U; ++k) acc[k & 3] += (double)av[k] * fb[j + 64 * k];
+    }
+    {
+      // the rest (fewer than U per lane): clamped loads, masked terms
+      MT av[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) av[k] = a[min(j + 64 * k, m - 1)];
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (j + 64 * k < m) acc[k & 3] += (double)av[k] * fb[j + 64 * k];
+    }
+    double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) u[row] = (T)v;
+  }
+}
+
+template <typename T, typename MT>
+__global__ __launch_bounds__(kFoldNT) void k_fold_gemv(const T* rf, int m, const MT* M, T* u) {
+  fold_gemv_body<T, MT>(rf, m, M, u, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFoldNT) void k_fold_gemv_b(const FoldArgs<T>* __restrict__ args) {
+  const FoldArgs<T>* a = args + blockIdx.y;
+  if (gate_skip(a->st, a->gate)) return;
+  if ((int)blockIdx.x * kFoldRows >= a->m) return;
+  fold_gemv_body<T, T>(a->rf, a->m, a->M, a->u, blockIdx.x);
+}
+
+template <typename T, typename MT>
+hipError_t launch_fold_gemv(const T* rf, int m, const MT* M, T* u, hipStream_t s) {
+  if (m < 1 || m > kFoldMax) return hipErrorInvalidValue;
+  const int grid = (m + kFoldRows - 1) / kFoldRows;
+  return launch_lds(k_fold_gemv<T, MT>, grid, kFoldNT, (size_t)m * sizeof(double), s, rf, m, M, u);
+}
+
+template <typename T>
+hipError_t launch_fold_gemv_batch(const FoldArgs<T>* args, int count, int m, hipStream_t s) {
+  if (count < 1 || m < 1 || m > kFoldMax) return hipErrorInvalidValue;
+  const dim3 grid((m + kFoldRows - 1) / kFoldRows, count);
+  return launch_lds(k_fold_gemv_b<T>, grid, kFoldNT, (size_t)m * sizeof(double), s, args);
+}
+
+// 32 x 32 tiles through LDS: reads along the source vectors, writes along
+// the matrix rows.
+__global__ __launch_bounds__(256) void k_gather_rows(double* M, const double* src, int64_t stride,
+                                                     int m, int j0, int count) {
+  __shared__ double tile[32][33];
+  const int ib = blockIdx.x * 32, kb = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int k = kb + r, i = ib + tx;
+    tile[r][tx] = (k < count && i < m) ? src[(int64_t)k * stride + i] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = ib + r, k = kb + tx;
+    if (i < m && k < count) M[(int64_t)i * m + j0 + k] = tile[tx][r];
+  }
+}
+
+hipError_t launch_gather_rows(double* M, const double* src, int64_t stride, int m, int j0,
+                              int count, hipStream_t s) {
+  if (m < 1 || count < 1 || j0 < 0 || j0 + count > m) return hipErrorInvalidValue;
+  const dim3 grid((m + 31) / 32, (count + 31) / 32);
+  hipLaunchKernelGGL(k_gather_rows, grid, 256, 0, s, M, src, stride, m, j0, count);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_tail_matvec_batch(int colmode, int epimode, const PassArgs<T>* args, int count,
                                     const Twiddles<T>& tw, hipStream_t s) {
@@ -1608,6 +1712,12 @@ template hipError_t launch_cg_dir<float>(const SolveState*, double*, const float
                                              const Twiddles<T>&, int, int, hipStream_t);
 AMG_INSTANTIATE(double)
 AMG_INSTANTIATE(float)
+template hipError_t launch_fold_gemv<double, double>(const double*, int, const double*, double*,
+                                                     hipStream_t);
+template hipError_t launch_fold_gemv<float, float>(const float*, int, const float*, float*,
+                                                   hipStream_t);
+template hipError_t launch_fold_gemv_batch<double>(const FoldArgs<double>*, int, int, hipStream_t);
+template hipError_t launch_fold_gemv_batch<float>(const FoldArgs<float>*, int, int, hipStream_t);
 template hipError_t launch_tail_vcycle_batch<double>(const TailArgs<double>*, int, int,
                                                      const Twiddles<double>&, hipStream_t);
 template hipError_t launch_tail_vcycle_batch<float>(const TailArgs<float>*, int, int,

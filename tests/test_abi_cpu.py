@@ -104,7 +104,7 @@ def _setup_status(kern, delta, N, **opts):
     dict(kind=B.AMG_K_FRACTIONAL, alpha=0.5), dict(kind=B.AMG_K_FRACTIONAL, alpha=0.0),
     dict(kind=B.AMG_K_WEIGHTED, wl=-1.0), dict(kind=7), dict(kind=B.AMG_K_GENERATORS),
     dict(opts=dict(coarsest_log2=1)), dict(opts=dict(coarsest_log2=8)),
-    dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=16)),
+    dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=32)),
     dict(opts=dict(inner=3)), dict(opts=dict(inner=-1)),
     dict(opts=dict(inner=B.AMG_INNER_GMRES, restart=0)), dict(opts=dict(restart=65)),
     dict(opts=dict(cycle=0)), dict(opts=dict(cycle=3)),
@@ -235,3 +235,16 @@ def test_plan_get_set_host_logic():
     finally:
         B.amg_plan_set(19)
     assert (B.amg_plan_get(19)["logL1"], B.amg_plan_get(19)["tcols"]) == (10, 4)
+
+
+def test_deep_fold_footprint():
+    """AMG_FLAG_DEEP_FOLD adds the dense operator of the first small level
+    (2 n + 1 unknowns, FP64 plus FP32 rounding in the mixed form) to the
+    footprint when the problem has levels above it; none at or below 2^11."""
+    k = B.kernel(B.AMG_K_CONST)
+    for N, m in ((2 ** 20, 4095), (2 ** 12, 4095), (2 ** 11, 0), (2 ** 9, 0)):
+        for prec, per in ((B.AMG_FP64, 8), (B.AMG_MIXED, 12)):
+            f0 = B.amg_footprint_bytes(k, 0.1, N, B.amg_default_opts(precision=prec))
+            f1 = B.amg_footprint_bytes(k, 0.1, N, B.amg_default_opts(precision=prec,
+                                                                     flags=B.AMG_FLAG_DEEP_FOLD))
+            assert f1 - f0 == m * m * per, (N, prec)
