@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+LAT_SAMPLES = 100      # solves behind each p50 / p99
 
 
 def parse():
@@ -278,6 +279,14 @@ def run_form(B, torch, args, precision, b_dev, profile=False, inner=0):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
         prof = B.amg_profile_stats(h)
+        # latency percentiles over at least LAT_SAMPLES solves: the timed ones
+        # plus more of the same (these do not enter the throughput)
+        for _ in range(max(0, LAT_SAMPLES - steps) if not profile else 0):
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            B.amg_solve(h, b_dev, x, args.tol)
+            lat.append(time.perf_counter() - t1)
         return dict(handle=None, x=x.clone(), setup_s=setup_s, wall_s=wall, lat=np.array(lat),
                     iters=iters, relres=rel, prof=prof)
     finally:
@@ -307,12 +316,13 @@ def sweep_roofline(prof, n, prefix, p_bytes, sym):
 
 def summary(res, N):
     lat = res["lat"]
-    steps = len(lat)
+    steps = len(res["iters"])
     sps = steps / res["wall_s"]
     return {"solves_per_s": round(sps, 3), "unknowns_per_s": round(sps * (2 * N - 1), 1),
             "ms_per_solve": round(1e3 * res["wall_s"] / steps, 3),
             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+            "latency_samples": int(len(lat)),
             "iters": int(np.median(res["iters"])), "final_relres": res["relres"],
             "setup_s": round(res["setup_s"], 3)}
 
