@@ -228,7 +228,8 @@ typedef struct {
 
 /* Per-kernel timing accumulated while AMG_FLAG_PROFILE is set. */
 typedef struct {
-  char name[48];      /* e.g. "finest_col_fwd", "finest_row", "finest_col_inv" */
+  char name[48];      /* e.g. "fp32_finest_sweep" (the finest level's three
+                         passes, events around the sweep only), "vcycle" */
   int64_t launches;   /* launches timed since the last reset                  */
   double total_ms;    /* summed event-to-event time (ms)                      */
 } amg_stat_t;

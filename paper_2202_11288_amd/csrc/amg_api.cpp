@@ -650,6 +650,8 @@ int fourstep(amg_ctx* c, int l, int cmode, const ColIn<T>& in, int emode, const 
   const Twiddles<T>& tw = tw_of<T>(c);
   Profiler& P = c->prof;
   const bool prof = P.on && l == 0 && !wk.buf;  // caller-provided work memory: no events
+  // events around the whole sweep only: events between its passes would add
+  // their own gaps to it (the passes' durations come from a kernel trace)
   const size_t e0 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_col_fwd<T>(cmode, d, in, buf, tw, dp, s));
   if (d.bmain) {
@@ -658,16 +660,11 @@ int fourstep(amg_ctx* c, int l, int cmode, const ColIn<T>& in, int emode, const 
                 : cmode == COL_OUTER_UPDATE ? reinterpret_cast<const T*>(in.xo) : d.u;
     HIP_TRY(launch_band_mv<T>(d, xb, s));
   }
-  const size_t e1 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_row<T>(1, d, buf, tw, dp, col_blocks(d.logL1, d.tcols), out.xin, s));
-  const size_t e2 = prof ? P.mark(s) : SIZE_MAX;
   HIP_TRY(launch_col_inv<T>(emode, d, out, buf, tw, c->npart, s));
   if (prof) {
     const size_t e3 = P.mark(s);
     const int off = sizeof(T) == 4 ? PK_COL_FWD32 : PK_COL_FWD;
-    P.span(off + 0, e0, e1);
-    P.span(off + 1, e1, e2);
-    P.span(off + 2, e2, e3);
     P.span(off + 3, e0, e3);
   }
   return AMG_OK;
