@@ -79,6 +79,12 @@ def parse():
     ap.add_argument("--pmc-driver", action="store_true",
                     help="the short program the --pmc counter runs profile: a plain copy of "
                          "known size, then two mixed solves of the workload (eager launches)")
+    ap.add_argument("--pmc-batch-driver", action="store_true",
+                    help="the program the batch --pmc runs profile: the uneven batch set up, a "
+                         "plain copy of known size, then two batch solves")
+    ap.add_argument("--batch-traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="from the counter CSVs of two rocprofv3 --pmc runs of --pmc-batch-driver, "
+                         "write one batch solve's HBM bytes to profiles/; no GPU needed")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="from the counter-collection CSVs of two rocprofv3 --pmc runs of "
                          "--pmc-driver (FETCH_SIZE, then WRITE_SIZE), write the finest FP32 "
@@ -151,6 +157,97 @@ def pmc_driver(args):
     finally:
         B.amg_destroy(h)
     print("pmc driver done", flush=True)
+
+
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_c4.json")
+
+
+def pmc_batch_driver(args):
+    """The program the batch --pmc runs profile: the uneven batch's handles
+    are set up, then a plain copy of known size (its counter reading scales
+    the others, and it marks where the solves start), then the batch is
+    solved twice from x_0 = 0 (the bench's untimed and timed calls)."""
+    import torch
+
+    from paper_2202_11288_amd import binding as B
+    inst = batch_instances(args.batch)
+    opts = B.amg_default_opts(precision=B.AMG_MIXED, inner=B.AMG_INNER_PCG, max_iter=500)
+    hs, bs, xs = [], [], []
+    try:
+        for d in inst:
+            k = (B.kernel(B.AMG_K_FRACTIONAL, alpha=d["alpha"]) if d["frac"]
+                 else B.kernel(B.AMG_K_CONST))
+            hs.append(B.amg_setup(k, d["delta"], d["N"], opts))
+            bs.append(torch.from_numpy(d["b"]).cuda())
+            xs.append(torch.zeros_like(bs[-1]))
+        torch.cuda.synchronize()
+        x = torch.ones(COPY_BYTES // 4, device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+        for _ in range(2):
+            for v in xs:
+                v.zero_()
+            B.amg_solve_batch(hs, bs, xs, [args.tol] * len(hs),
+                              allow=(B.AMG_OK, B.AMG_NOT_CONVERGED))
+            torch.cuda.synchronize()
+    finally:
+        for h in hs:
+            B.amg_destroy(h)
+    print("pmc batch driver done", flush=True)
+
+
+def batch_traffic_summary(fetch_csv, write_csv, args):
+    """HBM bytes of one batch solve: FETCH_SIZE / WRITE_SIZE of every
+    dispatch after the marker copy (the two solves), scaled by the copy's
+    factor, halved."""
+    import csv
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        key = "Dispatch_Id" if rows and "Dispatch_Id" in rows[0] else None
+        if key:
+            rows.sort(key=lambda r: int(r[key]))
+        return rows
+
+    out = {}
+    for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = load(path, counter)
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in rows]
+        copies = [i for i, r in enumerate(rows) if "copyBuffer" in r["Kernel_Name"]]
+        mark = max(copies, key=lambda i: vals[i])
+        scale = COPY_BYTES / vals[mark]
+        after = vals[mark + 1:]
+        out[label] = {"scale": round(scale, 4), "dispatches": len(after),
+                      "bytes_per_batch": round(sum(after) * scale / 2)}
+    res = {"kernel": "every dispatch of one amg_solve_batch call of the uneven batch",
+           "workload": {"instances": args.batch, "seed": 0, "tol": args.tol},
+           "source_hash": kernel_source_hash(),
+           "fetch": out["fetch"], "write": out["write"],
+           "bytes_per_batch": out["fetch"]["bytes_per_batch"] + out["write"]["bytes_per_batch"],
+           "commands": [
+               "cd /tmp && timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+               "-d <out>/pmc_bfetch -o run -- python3 <repo>/bench.py --pmc-batch-driver",
+               "cd /tmp && timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv "
+               "-d <out>/pmc_bwrite -o run -- python3 <repo>/bench.py --pmc-batch-driver",
+               "python bench.py --batch-traffic-summary <out>/pmc_bfetch/run_counter_collection.csv "
+               "<out>/pmc_bwrite/run_counter_collection.csv"]}
+    with open(BATCH_TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def measured_batch_traffic(args):
+    try:
+        with open(BATCH_TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash() or \
+            t.get("workload") != {"instances": args.batch, "seed": 0, "tol": args.tol}:
+        return None
+    return t.get("bytes_per_batch")
 
 
 def traffic_workload(args):
@@ -389,6 +486,9 @@ def run_batch(B, torch, args):
             "max_relres": float(max(rels)), "not_converged": int(sum(r >= args.tol for r in rels)),
             "setup_s": round(setup_s, 2),
             "est_alg_bytes": alg, "est_alg_frac_of_hbm_peak": round(alg / wall / 1e9 / HBM_PEAK_GBS, 4),
+            "counted_hbm_bytes": measured_batch_traffic(args),
+            "counted_hbm_frac": (round(measured_batch_traffic(args) / wall / 1e9 / HBM_PEAK_GBS, 4)
+                                 if measured_batch_traffic(args) else None),
             "workload": "N=2^K, K~U{10..16}; delta~U[0.05,0.3]; const or fractional 50/50, "
                         "alpha~U[0.2,0.45] (half the range [0.2,0.8]: the fractional weights are "
                         "finite only for alpha < 1/2); b~N(0,1); seed 0; mixed, inner=PCG, "
@@ -810,6 +910,12 @@ def main():
     if args.pmc_driver:
         pmc_driver(args)
         return
+    if args.pmc_batch_driver:
+        pmc_batch_driver(args)
+        return
+    if args.batch_traffic_summary:
+        batch_traffic_summary(args.batch_traffic_summary[0], args.batch_traffic_summary[1], args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one MI355X; runs on more than one GPU are not "
@@ -887,8 +993,12 @@ def main():
             tb = measured_traffic(args)
             roof32["traffic"] = tb
             if tb:
+                rate = tb / (roof32["avg_us"] * 1e-6) / 1e9
+                roof32["traffic_gbs"] = round(rate, 1)
+                roof32["traffic_frac"] = round(rate / HBM_PEAK_GBS, 4)
                 roof32["traffic_note"] = ("HBM bytes per sweep from rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                          "scaled by a plain copy of known size (profiles/)")
+                                          "scaled by a plain copy of known size (profiles/); "
+                                          "traffic_gbs = those bytes over the sweep's time")
     cpu, errs = (None, None)
     if not args.no_cpu_baseline:
         cpu, errs = cpu_baseline(args, b, r64["x"].cpu().numpy(), rmx["x"].cpu().numpy())
