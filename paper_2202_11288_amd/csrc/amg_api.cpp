@@ -1251,13 +1251,16 @@ int setup_device(amg_ctx* c, hipStream_t s) {
   std::vector<DevTpx> dt;
   if (c->gpu_setup) {
     dt.resize(nl);
-    std::vector<double> Wn, Wm;
+    // per-thread host buffers: a set-up thread's later hierarchies reuse
+    // their pages (the copies are staged when hipMemcpyAsync returns)
+    static thread_local std::vector<double> Wn, Wm;
     int64_t Sn = 0, Sm = 0;
-    row_stencils(c->kspec, c->N, Wn, Sn, Wm, Sm);
+    const bool same = row_stencils_reuse(c->kspec, c->N, Wn, Sn, Wm, Sm);
     double *wn, *wm, *scratch, *dscal;
     int* bad;
     AMG_TRY(upload_temp(c, &wn, Wn, s));
-    AMG_TRY(upload_temp(c, &wm, Wm, s));
+    if (same) wm = wn;
+    else AMG_TRY(upload_temp(c, &wm, Wm, s));
     AMG_TRY(dalloc_temp(c, &scratch, (size_t)(4 * c->host[0].n)));
     AMG_TRY(dalloc_temp(c, &dscal, (size_t)(3 * nl)));
     AMG_TRY(dalloc_temp(c, &bad, 1));

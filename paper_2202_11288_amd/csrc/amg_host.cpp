@@ -206,22 +206,30 @@ namespace {
 // the fractional kernel, 5e7 in size there), which alone moves A x by that
 // much times x; it is set from the identity, summed in long double.
 void own_weight_from_row_sum(std::vector<double>& W, int64_t S) {
-  long double acc = 0.0L;
-  for (int64_t i = 0; i < (int64_t)W.size(); ++i)
-    if (i != S) acc += (long double)W[(size_t)i];
-  W[(size_t)S] = (double)(-acc);
+  // four long double partial sums (independent chains), combined pairwise
+  long double acc[4] = {0.0L, 0.0L, 0.0L, 0.0L};
+  const int64_t m = (int64_t)W.size();
+  auto add_range = [&](int64_t lo, int64_t hi) {
+    int64_t i = lo;
+    for (; i + 3 < hi; i += 4)
+      for (int q = 0; q < 4; ++q) acc[q] += (long double)W[(size_t)(i + q)];
+    for (int q = 0; i < hi; ++i, ++q) acc[q] += (long double)W[(size_t)i];
+  };
+  add_range(0, S);
+  add_range(S + 1, m);
+  W[(size_t)S] = (double)(-((acc[0] + acc[1]) + (acc[2] + acc[3])));
 }
 
 }  // namespace
 
-std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
+void row_stencil_into(const KernelSpec& k, int64_t N, std::vector<double>& W, int64_t* Sout) {
   const double h = 1.0 / (double)N;
   const double R = k.delta * (double)N;  // exact: N is a power of two
   const int64_t r = (int64_t)std::floor(R);
   const double th_last = R - (double)r;
   const int64_t ncell = r + (th_last > 0.0 ? 1 : 0);
   const int64_t S = 2 * ncell;
-  std::vector<double> W(2 * S + 1, 0.0);
+  W.assign((size_t)(2 * S + 1), 0.0);
   const double c = kernel_c(k);
   const bool frac = k.kind == K_FRACTIONAL;
   const double beta = frac ? -1.0 - 2.0 * k.alpha : 0.0;
@@ -257,6 +265,11 @@ std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
   }
   own_weight_from_row_sum(W, S);
   *Sout = S;
+}
+
+std::vector<double> row_stencil(const KernelSpec& k, int64_t N, int64_t* Sout) {
+  std::vector<double> W;
+  row_stencil_into(k, N, W, Sout);
   return W;
 }
 
@@ -323,6 +336,17 @@ void both_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int6
 void row_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
                   std::vector<double>& Wm, int64_t& Sm) {
   both_stencils(k, N, Wn, Sn, Wm, Sm);
+}
+
+bool row_stencils_reuse(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
+                        std::vector<double>& Wm, int64_t& Sm) {
+  if (k.kind != K_WEAKLY_SINGULAR && k.scheme != SCHEME_STANDARD) {
+    row_stencil_into(k, N, Wn, &Sn);
+    Sm = Sn;
+    return true;
+  }
+  both_stencils(k, N, Wn, Sn, Wm, Sm);
+  return false;
 }
 
 namespace {

@@ -70,6 +70,13 @@ void ws_boundary_coupling(double gamma, int64_t N, double* K0, double* K1);
 // (equal under the shifted-symmetric rule); W[s2 + S], s2 in [-S, S].
 void row_stencils(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
                   std::vector<double>& Wm, int64_t& Sm);
+// The same into vectors whose storage is reused (no fresh pages for a
+// caller that keeps them); returns true when the midpoint-row stencil equals
+// the node-row one (shifted-symmetric rule), in which case Wm is untouched.
+bool row_stencils_reuse(const KernelSpec& k, int64_t N, std::vector<double>& Wn, int64_t& Sn,
+                        std::vector<double>& Wm, int64_t& Sm);
+// Row stencil into W (its storage reused).
+void row_stencil_into(const KernelSpec& k, int64_t N, std::vector<double>& W, int64_t* S);
 
 // Reach S (half-grid steps) of the node- and midpoint-row stencils.
 int64_t volume_reach(const KernelSpec& k, int64_t N);
