@@ -69,6 +69,11 @@ def parse():
                     help="set-up threads of the server (each has its own stream; with the "
                          "server's and the arrival side's streams, 2 keep to the 4 hardware queues "
                          "a process gets by default)")
+    ap.add_argument("--serve-small-log2", type=int, default=17,
+                    help="requests with N <= 2^this run in a second lane of the server "
+                         "(0: one lane)")
+    ap.add_argument("--serve-small-rounds", type=int, default=4,
+                    help="rounds of the small lane per round of the other requests")
     ap.add_argument("--serve-rounds", type=int, default=1,
                     help="rounds per amg_server_step of the serving run")
     ap.add_argument("--serve-queue-gb", type=float, default=48.0,
@@ -754,6 +759,8 @@ def run_serve(B, torch, args):
     reqs = serve_requests(args.serve_seconds, args.serve_rate)
     opts = B.amg_default_opts(precision=B.AMG_MIXED, max_iter=100)
     sv = B.amg_server_create(int(args.serve_budget_gb * 2 ** 30), workers=args.serve_workers)
+    if args.serve_small_log2 > 0:
+        B.amg_server_lanes(sv, 2 ** args.serve_small_log2, args.serve_small_rounds)
     lock = threading.Lock()
     live, done = {}, {}
     gen_stream = torch.cuda.Stream()  # the arrival side's stream for b and x
@@ -866,6 +873,9 @@ def run_serve(B, torch, args):
                           for k in ("start", "rebuild", "rounds", "setup")},
         "plan_rebuilds": s1["rebuilds"] - s0["rebuilds"],
         "budget_gb": args.serve_budget_gb, "setup_workers": args.serve_workers,
+        "lanes": ({"small_max_N": 2 ** args.serve_small_log2,
+                   "small_rounds_per_round": args.serve_small_rounds}
+                  if args.serve_small_log2 > 0 else None),
     }
 
 

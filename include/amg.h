@@ -492,6 +492,14 @@ int amg_server_submit(amg_server_t sv, const amg_kernel_t* kernel, double delta,
  * progress ends; it returns at once if there is none.  *in_flight / *waiting (host, may be NULL): the requests started
  * or being set up / waiting for memory. */
 int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting);
+/* Two lanes: requests with N <= small_max_N run their rounds on a second
+ * stream of the server's, small_rounds of them per round of the other
+ * requests (1..16), so that small requests are not paced by the large
+ * ones' iterations and the two lanes' kernels overlap on the device.
+ * small_max_N = 0: one lane (the default).  Only while no request is in the
+ * rounds (AMG_EINVAL otherwise); not concurrently with amg_server_step.
+ * A request's arithmetic is the same in either lane. */
+int amg_server_lanes(amg_server_t sv, int64_t small_max_N, int small_rounds);
 /* Copy up to `cap` results of requests finished since the last poll (host
  * array); returns their number. */
 int amg_server_poll(amg_server_t sv, amg_server_result_t* out, int cap);

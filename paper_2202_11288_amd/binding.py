@@ -116,6 +116,7 @@ def _load():
         "amg_server_poll": (I, [P, ctypes.POINTER(amg_server_result_t), I]),
         "amg_server_stats": (I, [P, ctypes.POINTER(amg_server_stats_t)]),
         "amg_server_destroy": (I, [P]),
+        "amg_server_lanes": (I, [P, ctypes.c_int64, I]),
         "amg_autotune": (I, [I, I, P]),
         "amg_plan_get": (I, [I, IP, IP, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double), IP, IP]),
@@ -481,3 +482,9 @@ def amg_plan_get(logL: int):
 def amg_plan_set(logL: int, logL1: int = 0, tcols: int = 0):
     """Select a candidate geometry for size 2^logL (logL1 = 0: the default)."""
     _check(lib.amg_plan_set(int(logL), int(logL1), int(tcols)), "amg_plan_set")
+
+
+def amg_server_lanes(sv, small_max_N: int, small_rounds: int = 3):
+    """Requests with N <= small_max_N get their own lane (stream) and
+    small_rounds rounds per round of the others; 0 = one lane."""
+    _check(lib.amg_server_lanes(sv, int(small_max_N), int(small_rounds)), "amg_server_lanes")

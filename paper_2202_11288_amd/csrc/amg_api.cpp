@@ -3196,14 +3196,24 @@ struct amg_server {
   std::vector<std::pair<amg_t, int64_t>> release_q;  // evicted, for a worker to free
   int64_t releasing = 0;                              // their bytes, until freed
   std::vector<ServerReq*> ready;    // hierarchy ready, starts at the next step
-  std::vector<ServerReq*> active;   // in the rounds (step thread only)
+  // requests in the rounds (step thread only): lane 0 on the server's
+  // stream, lane 1 (the small requests, when amg_server_lanes set it up) on
+  // a stream of its own, so that the two lanes' rounds overlap on the device
+  struct Lane {
+    std::vector<ServerReq*> active;
+    BatchPlan plan;
+    bool dirty = true;
+    hipStream_t s = nullptr;
+  };
+  Lane lane[2];
+  bool own_small_stream = false;
+  int64_t small_max_N = 0;  // 0: one lane
+  int small_rounds = 1;     // rounds of lane 1 per round of lane 0
   std::vector<ServerReq*> failed;   // setup failed, reported by the next poll
   std::vector<amg_server_result_t> finished;
   std::multimap<ServerKey, std::pair<amg_t, int64_t>> idle;  // cached hierarchies
   std::deque<std::pair<ServerKey, amg_t>> idle_order;       // oldest first
   std::vector<std::thread> workers;
-  BatchPlan plan;
-  bool dirty = true;
   amg_server_stats_t stats{};
 };
 
@@ -3480,13 +3490,13 @@ int amg_server_submit(amg_server_t sv, const amg_kernel_t* kernel, double delta,
 int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
   if (!sv || rounds < 0) return AMG_EINVAL;
   HIP_TRY(hipSetDevice(sv->device));
-  hipStream_t s = sv->stream;
+  sv->lane[0].s = sv->stream;
   std::vector<ServerReq*> start;
   {
     std::unique_lock<std::mutex> lk(sv->mu);
     admit(sv);
     // nothing to run yet: wait for the first set-up to end
-    if (sv->active.empty() && rounds > 0)
+    if (sv->lane[0].active.empty() && sv->lane[1].active.empty() && rounds > 0)
       sv->cv_done.wait(lk, [&] {
         return !sv->ready.empty() || !sv->failed.empty() ||
                (sv->setup_q.empty() && sv->setting_up == 0 && sv->releasing == 0);
@@ -3495,76 +3505,95 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
   }
   auto t0 = std::chrono::steady_clock::now();
   for (ServerReq* r : start) {
-    AMG_TRY(solve_begin(r->h, r->b, r->x, r->tol, s));
-    sv->active.push_back(r);
-    sv->dirty = true;
+    amg_server::Lane& ln = sv->lane[(sv->small_max_N > 0 && r->N <= sv->small_max_N) ? 1 : 0];
+    AMG_TRY(solve_begin(r->h, r->b, r->x, r->tol, ln.s));
+    ln.active.push_back(r);
+    ln.dirty = true;
   }
-  // the starting states reach the host with the next wait; a request solved
-  // by its initial guess is gated off in the rounds and retired after them
-  if (!start.empty() && rounds == 0) HIP_TRY(server_wait(s));
-  int64_t t_start = usec_since(t0), t_rebuild = 0, t_rounds = 0;
-  if (rounds == 0) {
-    for (size_t i = 0; i < sv->active.size();) {
-      ServerReq* r = sv->active[i];
+  auto retire_done = [&](amg_server::Lane& ln) {
+    for (size_t i = 0; i < ln.active.size();) {
+      ServerReq* r = ln.active[i];
       if (r->h->st_host->done) {
         const SolveState st = *r->h->st_host;
-        sv->active.erase(sv->active.begin() + (long)i);
+        ln.active.erase(ln.active.begin() + (long)i);
         retire(sv, r, st);
-        sv->dirty = true;
+        ln.dirty = true;
       } else {
         ++i;
       }
     }
-  }
-  if (!sv->active.empty() && rounds > 0) {
-    if (sv->dirty) {
-      // the previous rounds have completed (waited below); the new tables
-      // are copied on the stream, behind the starting requests' work
-      t0 = std::chrono::steady_clock::now();
+  };
+  // the starting states reach the host with the next wait; a request solved
+  // by its initial guess is gated off in the rounds and retired after them
+  int64_t t_start = 0, t_rebuild = 0, t_rounds = 0;
+  if (rounds == 0) {
+    for (amg_server::Lane& ln : sv->lane)
+      if (!ln.active.empty()) HIP_TRY(server_wait(ln.s));
+    t_start = usec_since(t0);
+    for (amg_server::Lane& ln : sv->lane) retire_done(ln);
+  } else {
+    t_start = usec_since(t0);
+    // rebuild the tables of a lane whose members changed (its previous
+    // rounds have completed: waited below); the copies go on the lane's
+    // stream, behind its starting requests' work
+    t0 = std::chrono::steady_clock::now();
+    for (amg_server::Lane& ln : sv->lane) {
+      if (ln.active.empty() || !ln.dirty) continue;
       std::vector<amg_ctx*> cs;
       std::vector<const double*> bs;
       std::vector<double*> xs;
       std::vector<double> ts;
-      for (ServerReq* r : sv->active) {
+      for (ServerReq* r : ln.active) {
         cs.push_back(r->h);
         bs.push_back(r->b);
         xs.push_back(r->x);
         ts.push_back(r->tol);
       }
-      AMG_TRY(build_batch_plan(sv->plan, cs, bs, xs, ts));
-      AMG_TRY(run_batch_plan(sv->plan, s));
-      sv->dirty = false;
-      t_rebuild = usec_since(t0);
+      AMG_TRY(build_batch_plan(ln.plan, cs, bs, xs, ts));
+      AMG_TRY(run_batch_plan(ln.plan, ln.s));
+      ln.dirty = false;
       sv->stats.rebuilds += 1;
     }
+    t_rebuild = usec_since(t0);
     t0 = std::chrono::steady_clock::now();
-    for (int k = 0; k < rounds; ++k)
-      for (const Launch& L : sv->plan.round) {
-        const hipError_t e = L(static_cast<unsigned char*>(sv->plan.dev), s);
-        if (e != hipSuccess) return hip_fail(e, "server round", __LINE__);
-      }
-    sv->stats.rounds += rounds;
-    HIP_TRY(server_wait(s));
-    t_rounds = usec_since(t0);
-    for (size_t i = 0; i < sv->active.size();) {
-      ServerReq* r = sv->active[i];
-      if (r->h->st_host->done) {
-        const SolveState st = *r->h->st_host;
-        sv->active.erase(sv->active.begin() + (long)i);
-        retire(sv, r, st);
-        sv->dirty = true;
-      } else {
-        ++i;
-      }
+    for (int li = 0; li < 2; ++li) {
+      amg_server::Lane& ln = sv->lane[li];
+      if (ln.active.empty()) continue;
+      const int nr = li == 0 ? rounds : rounds * sv->small_rounds;
+      for (int k = 0; k < nr; ++k)
+        for (const Launch& L : ln.plan.round) {
+          const hipError_t e = L(static_cast<unsigned char*>(ln.plan.dev), ln.s);
+          if (e != hipSuccess) return hip_fail(e, "server round", __LINE__);
+        }
+      sv->stats.rounds += nr;
     }
+    for (amg_server::Lane& ln : sv->lane)
+      if (!ln.active.empty()) HIP_TRY(server_wait(ln.s));
+    t_rounds = usec_since(t0);
+    for (amg_server::Lane& ln : sv->lane) retire_done(ln);
   }
   std::lock_guard<std::mutex> lk(sv->mu);
   sv->stats.start_us += t_start;
   sv->stats.rebuild_us += t_rebuild;
   sv->stats.rounds_us += t_rounds;
   if (in_flight)
-    *in_flight = (int)(sv->active.size() + sv->ready.size() + sv->setup_q.size()) + sv->setting_up;
+    *in_flight = (int)(sv->lane[0].active.size() + sv->lane[1].active.size() + sv->ready.size() +
+                       sv->setup_q.size()) +
+                 sv->setting_up;
   if (waiting) *waiting = (int)sv->pending.size();
+  return AMG_OK;
+}
+
+int amg_server_lanes(amg_server_t sv, int64_t small_max_N, int small_rounds) {
+  if (!sv || small_max_N < 0 || small_rounds < 1 || small_rounds > 16) return AMG_EINVAL;
+  if (!sv->lane[0].active.empty() || !sv->lane[1].active.empty()) return AMG_EINVAL;
+  if (small_max_N > 0 && !sv->lane[1].s) {
+    HIP_TRY(hipSetDevice(sv->device));
+    HIP_TRY(hipStreamCreateWithFlags(&sv->lane[1].s, hipStreamNonBlocking));
+    sv->own_small_stream = true;
+  }
+  sv->small_max_N = small_max_N;
+  sv->small_rounds = small_rounds;
   return AMG_OK;
 }
 
@@ -3605,10 +3634,12 @@ int amg_server_destroy(amg_server_t sv) {
   for (auto& t : sv->workers) t.join();
   (void)hipSetDevice(sv->device);
   if (sv->stream) (void)round_wait(sv->stream);
-  for (ServerReq* r : sv->active) {
-    (void)amg_destroy(r->h);
-    delete r;
-  }
+  if (sv->lane[1].s) (void)round_wait(sv->lane[1].s);
+  for (amg_server::Lane& ln : sv->lane)
+    for (ServerReq* r : ln.active) {
+      (void)amg_destroy(r->h);
+      delete r;
+    }
   for (ServerReq* r : sv->ready) {
     (void)amg_destroy(r->h);
     delete r;
@@ -3620,8 +3651,10 @@ int amg_server_destroy(amg_server_t sv) {
   }
   for (ServerReq* r : sv->failed) delete r;
   for (auto& kv : sv->idle) (void)amg_destroy(kv.second.first);
-  if (sv->plan.dev) (void)hipFree(sv->plan.dev);
+  for (amg_server::Lane& ln : sv->lane)
+    if (ln.plan.dev) (void)hipFree(ln.plan.dev);
   if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
+  if (sv->own_small_stream) (void)hipStreamDestroy(sv->lane[1].s);
   delete sv;
   return AMG_OK;
 }

@@ -61,14 +61,19 @@ def solo(r):
         B.amg_destroy(h)
 
 
-def test_serving_alone_vs_mix():
+@pytest.mark.parametrize("lanes", [0, 2 ** 12])
+def test_serving_alone_vs_mix(lanes):
     """Twenty requests submitted in four waves, two rounds apart, so that
     later ones join rounds already running; every result equals the solo
     solve bit for bit (same kernels and arithmetic per request), with the
-    same status and iteration count, and the oracle confirms the residual."""
+    same status and iteration count, and the oracle confirms the residual.
+    With two lanes (N <= 2^12 on a stream of their own, three rounds per
+    round of the others) the results are the same."""
     reqs = requests(20, seed=11)
-    say("serving mix", [r["N"] for r in reqs])
+    say("serving mix", lanes, [r["N"] for r in reqs])
     sv = B.amg_server_create(8 << 30, workers=3)
+    if lanes:
+        B.amg_server_lanes(sv, lanes, 3)
     try:
         opts = B.amg_default_opts(**OPTS)
         bs, xs, ids = [], [], {}
@@ -175,6 +180,8 @@ def test_serving_rejects_unsupported():
         with pytest.raises(B.AmgError):
             B.amg_server_submit(sv, B.kernel(B.AMG_K_WEAKLY_SINGULAR, gamma=0.5), 0.1, 256, b, x,
                                 1e-10)
+        with pytest.raises(B.AmgError):
+            B.amg_server_lanes(sv, 1024, 0)  # rounds outside 1..16
         with pytest.raises(B.AmgError):  # larger than the whole budget
             big = torch.zeros(2 * 2 ** 20 - 1, device="cuda", dtype=torch.float64)
             B.amg_server_submit(sv, B.kernel(B.AMG_K_CONST), 0.1, 2 ** 20, big, big.clone(), 1e-10)
