@@ -487,15 +487,18 @@ int amg_server_submit(amg_server_t sv, const amg_kernel_t* kernel, double delta,
                       int64_t* id);
 /* Start ready requests, run `rounds` rounds over the requests in flight,
  * retire the finished ones; returns when the rounds are done (the calling
- * thread polls the stream).  With rounds > 0 and no request in the rounds,
+ * thread polls the stream; with two lanes, when one lane's are, see
+ * amg_server_lanes).  With rounds > 0 and no request in the rounds,
  * it first waits until a set-up (or the release of an evicted hierarchy) in
  * progress ends; it returns at once if there is none.  *in_flight / *waiting (host, may be NULL): the requests started
  * or being set up / waiting for memory. */
 int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting);
 /* Two lanes: requests with N <= small_max_N run their rounds on a second
- * stream of the server's, small_rounds of them per round of the other
- * requests (1..16), so that small requests are not paced by the large
- * ones' iterations and the two lanes' kernels overlap on the device.
+ * stream of the server's, small_rounds of them per amg_server_step round
+ * (1..16).  The lanes advance independently: amg_server_step queues the
+ * rounds of every idle lane and returns once one lane has completed (and
+ * been queued again), so small requests are not paced by the large ones'
+ * iterations and the two lanes' kernels overlap on the device.
  * small_max_N = 0: one lane (the default).  Only while no request is in the
  * rounds (AMG_EINVAL otherwise); not concurrently with amg_server_step.
  * A request's arithmetic is the same in either lane. */

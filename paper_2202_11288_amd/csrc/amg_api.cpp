@@ -3203,6 +3203,7 @@ struct amg_server {
     std::vector<ServerReq*> active;
     BatchPlan plan;
     bool dirty = true;
+    bool running = false;  // its last rounds are still on the stream
     hipStream_t s = nullptr;
   };
   Lane lane[2];
@@ -3491,12 +3492,16 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
   if (!sv || rounds < 0) return AMG_EINVAL;
   HIP_TRY(hipSetDevice(sv->device));
   sv->lane[0].s = sv->stream;
+  auto idle = [&]() {
+    return sv->lane[0].active.empty() && sv->lane[1].active.empty() && !sv->lane[0].running &&
+           !sv->lane[1].running;
+  };
   std::vector<ServerReq*> start;
   {
     std::unique_lock<std::mutex> lk(sv->mu);
     admit(sv);
     // nothing to run yet: wait for the first set-up to end
-    if (sv->lane[0].active.empty() && sv->lane[1].active.empty() && rounds > 0)
+    if (idle() && rounds > 0)
       sv->cv_done.wait(lk, [&] {
         return !sv->ready.empty() || !sv->failed.empty() ||
                (sv->setup_q.empty() && sv->setting_up == 0 && sv->releasing == 0);
@@ -3505,6 +3510,7 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
   }
   auto t0 = std::chrono::steady_clock::now();
   for (ServerReq* r : start) {
+    // on a running lane the request's start queues behind its rounds
     amg_server::Lane& ln = sv->lane[(sv->small_max_N > 0 && r->N <= sv->small_max_N) ? 1 : 0];
     AMG_TRY(solve_begin(r->h, r->b, r->x, r->tol, ln.s));
     ln.active.push_back(r);
@@ -3523,54 +3529,65 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
       }
     }
   };
-  // the starting states reach the host with the next wait; a request solved
-  // by its initial guess is gated off in the rounds and retired after them
-  int64_t t_start = 0, t_rebuild = 0, t_rounds = 0;
+  int64_t t_start = usec_since(t0), t_rebuild = 0, t_rounds = 0;
   if (rounds == 0) {
+    // start only: wait for every lane, retire what the starts finished
     for (amg_server::Lane& ln : sv->lane)
-      if (!ln.active.empty()) HIP_TRY(server_wait(ln.s));
-    t_start = usec_since(t0);
-    for (amg_server::Lane& ln : sv->lane) retire_done(ln);
-  } else {
-    t_start = usec_since(t0);
-    // rebuild the tables of a lane whose members changed (its previous
-    // rounds have completed: waited below); the copies go on the lane's
-    // stream, behind its starting requests' work
-    t0 = std::chrono::steady_clock::now();
+      if (!ln.active.empty() || ln.running) HIP_TRY(server_wait(ln.s));
     for (amg_server::Lane& ln : sv->lane) {
-      if (ln.active.empty() || !ln.dirty) continue;
-      std::vector<amg_ctx*> cs;
-      std::vector<const double*> bs;
-      std::vector<double*> xs;
-      std::vector<double> ts;
-      for (ServerReq* r : ln.active) {
-        cs.push_back(r->h);
-        bs.push_back(r->b);
-        xs.push_back(r->x);
-        ts.push_back(r->tol);
-      }
-      AMG_TRY(build_batch_plan(ln.plan, cs, bs, xs, ts));
-      AMG_TRY(run_batch_plan(ln.plan, ln.s));
-      ln.dirty = false;
-      sv->stats.rebuilds += 1;
+      ln.running = false;
+      retire_done(ln);
     }
-    t_rebuild = usec_since(t0);
+  } else {
+    // The lanes advance independently: a lane whose rounds have completed
+    // retires its finished requests and queues its next rounds (rebuilding
+    // its tables if its members changed); the call returns once a lane has
+    // completed and been queued again, so neither lane waits for the other.
     t0 = std::chrono::steady_clock::now();
-    for (int li = 0; li < 2; ++li) {
-      amg_server::Lane& ln = sv->lane[li];
-      if (ln.active.empty()) continue;
-      const int nr = li == 0 ? rounds : rounds * sv->small_rounds;
-      for (int k = 0; k < nr; ++k)
-        for (const Launch& L : ln.plan.round) {
-          const hipError_t e = L(static_cast<unsigned char*>(ln.plan.dev), ln.s);
-          if (e != hipSuccess) return hip_fail(e, "server round", __LINE__);
+    bool progressed = false;
+    for (;;) {
+      for (int li = 0; li < 2; ++li) {
+        amg_server::Lane& ln = sv->lane[li];
+        if (ln.running) {
+          const hipError_t e = hipStreamQuery(ln.s);
+          if (e == hipErrorNotReady) continue;
+          if (e != hipSuccess) return hip_fail(e, "server lane", __LINE__);
+          ln.running = false;
+          retire_done(ln);
+          progressed = true;
         }
-      sv->stats.rounds += nr;
+        if (ln.active.empty()) continue;
+        if (ln.dirty) {
+          const auto tb = std::chrono::steady_clock::now();
+          std::vector<amg_ctx*> cs;
+          std::vector<const double*> bs;
+          std::vector<double*> xs;
+          std::vector<double> ts;
+          for (ServerReq* r : ln.active) {
+            cs.push_back(r->h);
+            bs.push_back(r->b);
+            xs.push_back(r->x);
+            ts.push_back(r->tol);
+          }
+          AMG_TRY(build_batch_plan(ln.plan, cs, bs, xs, ts));
+          AMG_TRY(run_batch_plan(ln.plan, ln.s));
+          ln.dirty = false;
+          sv->stats.rebuilds += 1;
+          t_rebuild += usec_since(tb);
+        }
+        const int nr = li == 0 ? rounds : rounds * sv->small_rounds;
+        for (int k = 0; k < nr; ++k)
+          for (const Launch& L : ln.plan.round) {
+            const hipError_t e = L(static_cast<unsigned char*>(ln.plan.dev), ln.s);
+            if (e != hipSuccess) return hip_fail(e, "server round", __LINE__);
+          }
+        sv->stats.rounds += nr;
+        ln.running = true;
+      }
+      if (progressed || (!sv->lane[0].running && !sv->lane[1].running)) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    for (amg_server::Lane& ln : sv->lane)
-      if (!ln.active.empty()) HIP_TRY(server_wait(ln.s));
-    t_rounds = usec_since(t0);
-    for (amg_server::Lane& ln : sv->lane) retire_done(ln);
+    t_rounds = usec_since(t0) - t_rebuild;
   }
   std::lock_guard<std::mutex> lk(sv->mu);
   sv->stats.start_us += t_start;
@@ -3586,7 +3603,9 @@ int amg_server_step(amg_server_t sv, int rounds, int* in_flight, int* waiting) {
 
 int amg_server_lanes(amg_server_t sv, int64_t small_max_N, int small_rounds) {
   if (!sv || small_max_N < 0 || small_rounds < 1 || small_rounds > 16) return AMG_EINVAL;
-  if (!sv->lane[0].active.empty() || !sv->lane[1].active.empty()) return AMG_EINVAL;
+  if (!sv->lane[0].active.empty() || !sv->lane[1].active.empty() || sv->lane[0].running ||
+      sv->lane[1].running)
+    return AMG_EINVAL;
   if (small_max_N > 0 && !sv->lane[1].s) {
     HIP_TRY(hipSetDevice(sv->device));
     HIP_TRY(hipStreamCreateWithFlags(&sv->lane[1].s, hipStreamNonBlocking));
