@@ -26,6 +26,11 @@ Readings where the paper is silent:
   c = 3/(2 delta^3); "weighted" = c*wl for s < 0 and c*wr for s > 0;
   fractional c |s|^(-1-2 alpha) with c = (1-alpha) delta^(2 alpha - 2),
   0 < alpha < 1/2 (beyond 1/2 the product-integration weights diverge);
+* "fractional_near" (an extension, not in the paper): the same kernel for
+  0 < alpha < 1, with the piecewise quadratic replaced on |t| <= h/2 by the
+  one quadratic through x_c - h/2, x_c, x_c + h/2, so that the linear term
+  cancels between the two sides (principal value) and the rest is
+  integrable; product integration of the cell pieces beyond h/2;
 * when delta/h is not an integer, the last sub-interval I_{r+1} = [r h, delta]
   (Sec. 2.2) is integrated exactly, so the stencil reaches offset r+1;
   when delta < h the same rule integrates over [0, delta];
@@ -48,6 +53,8 @@ import math
 import numpy as np
 
 CONST, WEIGHTED, FRACTIONAL = "const", "weighted", "fractional"
+FRACTIONAL_NEAR = "fractional_near"
+FRACTIONAL_KINDS = (FRACTIONAL, FRACTIONAL_NEAR)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -65,14 +72,14 @@ class Kernel:
     def c(self) -> float:
         if self.kind in (CONST, WEIGHTED):
             return 3.0 / (2.0 * self.delta ** 3)
-        if self.kind == FRACTIONAL:
+        if self.kind in FRACTIONAL_KINDS:
             return (1.0 - self.alpha) * self.delta ** (2.0 * self.alpha - 2.0)
         raise ValueError(self.kind)
 
     @property
     def beta(self) -> float:
         """Exponent of |s| in gamma (0 for the piecewise-constant kernels)."""
-        return -1.0 - 2.0 * self.alpha if self.kind == FRACTIONAL else 0.0
+        return -1.0 - 2.0 * self.alpha if self.kind in FRACTIONAL_KINDS else 0.0
 
     def side_weights(self):
         """(left, right) multipliers: left means s = y - x < 0."""
@@ -84,7 +91,7 @@ class Kernel:
         """gamma(s) itself (used by the quadrature pins only)."""
         s = np.asarray(s, dtype=np.float64)
         a = np.abs(s)
-        base = self.c * (a ** self.beta if self.kind == FRACTIONAL else 1.0)
+        base = self.c * (a ** self.beta if self.kind in FRACTIONAL_KINDS else 1.0)
         side = np.where(s < 0, self.side_weights()[0], self.side_weights()[1])
         return np.where(a <= self.delta, base * side, 0.0)
 
@@ -119,7 +126,9 @@ def _frac_moments(k, theta, beta):
     J = np.full((3, len(k)), np.nan)
     z = k == 0
     for j in (1, 2):
-        J[j, z] = theta[z] ** (beta + j + 1) / (beta + j + 1)
+        e = beta + j + 1
+        if e > 0:  # otherwise the moment diverges (alpha >= 1/2, j = 1)
+            J[j, z] = theta[z] ** e / e
     s = (~z) & (theta <= 0.5 * np.maximum(k, 1.0))
     if s.any():
         ks, ts = k[s], theta[s]
@@ -140,7 +149,8 @@ def _frac_moments(k, theta, beta):
     if o.any():
         assert np.all(k[o] == 1.0)
         to = theta[o]
-        F = lambda e: np.expm1(e * np.log1p(to)) / e  # ((1+theta)^e - 1)/e
+        # ((1+theta)^e - 1)/e, and its limit log(1+theta) at e = 0
+        F = lambda e: np.expm1(e * np.log1p(to)) / e if e != 0 else np.log1p(to)
         f1, f2, f3 = F(beta + 1), F(beta + 2), F(beta + 3)
         J[0, o] = f1
         J[1, o] = f2 - f1
@@ -153,7 +163,7 @@ def cell_moments(kernel: Kernel, N: int):
     unit side weight, tau = t/h - k the local coordinate of cell k."""
     h = 1.0 / N
     k, theta = cells(kernel, N)
-    if kernel.kind == FRACTIONAL:
+    if kernel.kind in FRACTIONAL_KINDS:
         J = _frac_moments(k, theta, kernel.beta)
         scale = kernel.c * h ** (kernel.beta + 1.0)
     else:
@@ -182,6 +192,63 @@ def cell_integrals(kernel: Kernel, N: int):
     return k, Ia, Ib, Ic, Idiag
 
 
+def _power_integral(a, b, e):
+    """int_a^b tau^(e-1) dtau for 0 < a <= b: (b^e - a^e)/e, log(b/a) at e = 0."""
+    if e == 0:
+        return math.log(b / a)
+    return a ** e * math.expm1(e * math.log(b / a)) / e
+
+
+def near_field_rule(kernel: Kernel, N: int):
+    """The fractional_near kernel's rule on cell 0 (one side, unit side
+    weight), in physical units:
+
+    * near part, |t| <= rho h with rho = min(1/2, theta_0): the quadratic
+      through the half-grid neighbours, u_c + t (u_+ - u_-)/h
+      + 2 t^2 (u_+ - 2 u_c + u_-)/h^2; its linear term integrates to zero
+      over the two sides, its quadratic term gives -m (u_+ - 2 u_c + u_-)
+      for the two sides together, m = (4/h^2) int_0^{rho h} gamma t^2 dt;
+    * far part of cell 0, tau in [rho, theta_0]: the cell's own quadratic
+      (basis l_a, l_b, l_c as in `cell_integrals`), moments
+      F_j = int gamma tau^j over that sub-interval.
+
+    Returns (m, F0, F1, F2); F_j = 0 when theta_0 <= 1/2."""
+    h = 1.0 / N
+    _, theta = cells(kernel, N)
+    th0 = float(theta[0])
+    be = kernel.beta
+    scale = kernel.c * h ** (be + 1.0)
+    rho = min(0.5, th0)
+    m = 4.0 * scale * rho ** (be + 3.0) / (be + 3.0)
+    if th0 <= 0.5:
+        return m, 0.0, 0.0, 0.0
+    F = [scale * _power_integral(rho, th0, be + j + 1.0) for j in range(3)]
+    return (m, *F)
+
+
+def stencil_near(kernel: Kernel, N: int):
+    """Row stencil W(s2) of the fractional_near kernel (shifted rule, every
+    row the same), as (W, S): cell 0 by `near_field_rule`, cells k >= 1 by
+    product integration as in `stencil`."""
+    k, Ia, Ib, Ic, Idiag = cell_integrals(kernel, N)
+    m, F0, F1, F2 = near_field_rule(kernel, N)
+    S = 2 * len(k)
+    W = np.zeros(2 * S + 1)
+    W[S] += 2.0 * m
+    W[S - 1] -= m
+    W[S + 1] -= m
+    for sign in (+1, -1):
+        W[S] += 3 * F1 - 2 * F2                     # int gamma (1 - l_a)
+        W[S + sign * 1] -= 4 * F1 - 4 * F2          # l_b
+        W[S + sign * 2] -= -F1 + 2 * F2             # l_c
+        for kk in k[1:]:
+            W[S] += Idiag[kk]
+            W[S + sign * 2 * kk] -= Ia[kk]
+            W[S + sign * (2 * kk + 1)] -= Ib[kk]
+            W[S + sign * (2 * kk + 2)] -= Ic[kk]
+    return W, S
+
+
 def stencil(kernel: Kernel, N: int):
     """Row stencil W(s2) in half-grid offsets s2 = 2 (y - x_c)/h.
 
@@ -190,6 +257,8 @@ def stencil(kernel: Kernel, N: int):
     (W, S) with W[s2 + S] for s2 in [-S, S].  Under the shifted-symmetric rule
     (eq. (system1)) every row -- node or midpoint -- has this stencil.
     """
+    if kernel.kind == FRACTIONAL_NEAR:
+        return stencil_near(kernel, N)
     k, Ia, Ib, Ic, Idiag = cell_integrals(kernel, N)
     S = 2 * len(k)
     W = np.zeros(2 * S + 1)
@@ -226,6 +295,8 @@ def assemble_dense(kernel: Kernel, N: int):
     (eq. (ccs2.6) with zero volume data).  O(N r) Python work: tiny N only.
     """
     M = 2 * N - 1
+    if kernel.kind == FRACTIONAL_NEAR:
+        return _assemble_dense_near(kernel, N)
     k, Ia, Ib, Ic, Idiag = cell_integrals(kernel, N)
     wl, wr = kernel.side_weights()
     Aint = np.zeros((M + 1, M + 1))  # 1-based interleaved positions
@@ -240,6 +311,29 @@ def assemble_dense(kernel: Kernel, N: int):
                     col = p + sign * off
                     if 1 <= col <= M:
                         Aint[p, col] -= ws * I
+    perm = block_permutation(N)
+    return Aint[np.ix_(perm, perm)]
+
+
+def _assemble_dense_near(kernel: Kernel, N: int):
+    """`assemble_dense` for the fractional_near kernel: each row is the near
+    part (second difference on the half grid), the far part of cell 0 and
+    the cells k >= 1 on both sides, with exterior values dropped."""
+    M = 2 * N - 1
+    k, Ia, Ib, Ic, Idiag = cell_integrals(kernel, N)
+    m, F0, F1, F2 = near_field_rule(kernel, N)
+    Aint = np.zeros((M + 1, M + 1))
+    for p in range(1, M + 1):
+        terms = [(0, 2.0 * m), (-1, -m), (1, -m)]
+        for sign in (+1, -1):
+            terms += [(0, 3 * F1 - 2 * F2), (sign, -(4 * F1 - 4 * F2)), (2 * sign, -(-F1 + 2 * F2))]
+            for kk in k[1:]:
+                terms += [(0, Idiag[kk]), (sign * 2 * kk, -Ia[kk]),
+                          (sign * (2 * kk + 1), -Ib[kk]), (sign * (2 * kk + 2), -Ic[kk])]
+        for off, v in terms:
+            col = p + off
+            if 1 <= col <= M:
+                Aint[p, col] += v
     perm = block_permutation(N)
     return Aint[np.ix_(perm, perm)]
 
@@ -302,7 +396,13 @@ def rhs_manufactured(kernel: Kernel, N: int):
               -12 + 24 * x, np.full_like(x, 24.0)]
     f = np.zeros_like(x)
     for p, dp in enumerate(derivs, start=1):
-        Mp = (t2 ** (b + p + 1) + (-1) ** p * t1 ** (b + p + 1)) / (b + p + 1)
+        # int_{-t1}^{t2} t^p |t|^b dt; for b + p + 1 <= 0 (p = 1, alpha >= 1/2)
+        # the principal value, the same expression (log(t2/t1) at 0)
+        e = b + p + 1
+        if e == 0:
+            Mp = np.log(t2 / t1)
+        else:
+            Mp = (t2 ** e + (-1) ** p * t1 ** e) / e
         f -= dp / math.factorial(p) * Mp
     for a in (1.0 - x, x):  # distance to the boundary on each side
         out = a < d

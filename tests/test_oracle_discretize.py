@@ -194,3 +194,114 @@ def test_delta_below_h():
     assert S == 2 and abs(W.sum()) < 1e-12 * np.abs(W).sum()
     m2 = sum(W[s + S] * (-(s / (2 * N)) ** 2) for s in range(-S, S + 1))
     assert abs(m2 - 1.0) < 1e-12
+
+
+# --- the fractional_near kernel (an extension for 0 < alpha < 1, not in the
+# paper): symmetric quadratic on |t| <= h/2, product integration beyond ------
+
+H_NEAR = [
+    D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=0.3),
+    D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=0.5),
+    D.Kernel(D.FRACTIONAL_NEAR, 0.13, alpha=0.7),
+    D.Kernel(D.FRACTIONAL_NEAR, 0.05, alpha=0.9),
+]
+NEAR_IDS = lambda k: f"a{k.alpha}-d{k.delta}"
+
+
+@pytest.mark.parametrize("kern", H_NEAR, ids=NEAR_IDS)
+def test_near_rule_row_sum_and_quadratics(kern):
+    """Both pieces of the rule reproduce quadratics, so on rows whose horizon
+    stays in (0,1): A 1 = 0, A x = 0 (symmetric kernel), A x^2 = -int gamma
+    s^2 = -1; and the stencil's row sum is zero."""
+    for N in (32, 64, 128):
+        W, _ = D.stencil(kern, N)
+        assert abs(W.sum()) <= 1e-12 * np.abs(W).sum()
+    N = 64
+    h = 1.0 / N
+    A = D.assemble_dense(kern, N)
+    x = D.points_block(N)
+    inside = (x - kern.delta > 1.5 * h) & (x + kern.delta < 1 - 1.5 * h)
+    assert inside.sum() > 10
+    scale = np.abs(A).sum(axis=1).max()
+    np.testing.assert_allclose((A @ np.ones_like(x))[inside], 0.0, atol=1e-13 * scale)
+    np.testing.assert_allclose((A @ x)[inside], 0.0, atol=1e-13 * scale)
+    np.testing.assert_allclose((A @ x ** 2)[inside], -1.0, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("kern", H_NEAR, ids=NEAR_IDS)
+def test_near_rule_pieces_vs_quadrature(kern):
+    """The near weight m = (4/h^2) int_0^{h/2} gamma t^2 dt and the far
+    moments of cell 0, int_{h/2}^{h} gamma (t/h)^j dt, against 30-digit
+    quadrature of their definitions (t = (h/2) s^10 smooths the t^(beta+2)
+    endpoint of the first)."""
+    mpmath.mp.dps = 30
+    N = 64
+    h = mpmath.mpf(1) / N
+    c, be = mpmath.mpf(kern.c), mpmath.mpf(kern.beta)
+    m, F0, F1, F2 = D.near_field_rule(kern, N)
+    e = h / 2
+    ref_m = 4 / h ** 2 * mpmath.quad(
+        lambda s: c * (e * s ** 10) ** (be + 2) * e * 10 * s ** 9, [0, 1])
+    assert abs(m - float(ref_m)) <= 1e-14 * abs(float(ref_m))
+    for j, F in enumerate((F0, F1, F2)):
+        ref = mpmath.quad(lambda t: c * t ** be * (t / h) ** j, [h / 2, h])
+        assert abs(F - float(ref)) <= 1e-14 * abs(float(ref)), j
+
+
+@pytest.mark.parametrize("kern", H_NEAR, ids=NEAR_IDS)
+def test_near_rule_symmetric_positive_definite(kern):
+    for N in (32, 128):
+        A = D.assemble_dense(kern, N)
+        np.testing.assert_allclose(A, A.T, rtol=0, atol=1e-14 * np.abs(A).max())
+        assert np.linalg.eigvalsh(A).min() > 0
+
+
+def _f_quadrature_pv(kern, x):
+    """f(x) = p.v. int gamma(t)(u(x) - u~(x+t)) dt by 30-digit quadrature,
+    for a symmetric kernel with |t|^beta, beta <= -2 allowed: on [-a, a]
+    (a = the shorter inside reach) the odd Taylor terms of u(x) - u(x+t)
+    cancel, leaving 2 sum over even p of c_p int_0^a gamma t^p (t = a s^10
+    smooths its endpoint); the rest of the longer side and the outside parts
+    are regular."""
+    mpmath.mp.dps = 30
+    x = mpmath.mpf(float(x))
+    u = lambda y: y * y * (1 - y) ** 2
+    cp = mpmath.taylor(u, x, 4)
+    d, be, c = mpmath.mpf(kern.delta), mpmath.mpf(kern.beta), mpmath.mpf(kern.c)
+    g = lambda t: c * abs(t) ** be
+    poly = lambda t: sum(cp[p] * t ** p for p in range(1, 5))
+    r_in, l_in = min(1 - x, d), min(x, d)
+    a = min(r_in, l_in)
+    even = lambda t: g(t) * (cp[2] * t ** 2 + cp[4] * t ** 4)
+    total = -2 * mpmath.quad(lambda s: even(a * s ** 10) * a * 10 * s ** 9, [0, 1])
+    if r_in > a:
+        total += mpmath.quad(lambda t: -g(t) * poly(t), [a, r_in])
+    if l_in > a:
+        total += mpmath.quad(lambda t: -g(t) * poly(-t), [a, l_in])
+    for edge in (1 - x, x):
+        if edge < d:
+            total += mpmath.quad(lambda t: g(t) * u(x), [edge, d])
+    return float(total)
+
+
+@pytest.mark.parametrize("kern", H_NEAR, ids=NEAR_IDS)
+def test_near_manufactured_rhs_vs_quadrature(kern):
+    N = 32
+    f = D.rhs_manufactured(kern, N)
+    x = D.points_block(N)
+    for i in (0, 3, N - 2, N - 1, N + 5, 2 * N - 2, N // 2):
+        ref = _f_quadrature_pv(kern, float(x[i]))
+        assert abs(f[i] - ref) <= 1e-10 * max(1.0, abs(ref)), (i, f[i], ref)
+
+
+@pytest.mark.parametrize("alpha", [0.7, 0.9])
+def test_near_manufactured_error_falls(alpha):
+    """The collocation error of u = x^2(1-x)^2 falls at least like h^2 (the
+    near quadratic is exact to O(h^3) on |t| <= h/2)."""
+    k = D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=alpha)
+    errs = []
+    for N in (32, 64, 128, 256):
+        U = np.linalg.solve(D.assemble_dense(k, N), D.rhs_manufactured(k, N))
+        errs.append(np.abs(U - D.u_exact(D.points_block(N))).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert all(r > 1.8 for r in rates), (errs, rates)
