@@ -176,13 +176,12 @@ def pmc_batch_driver(args):
 
     from paper_2202_11288_amd import binding as B
     inst = batch_instances(args.batch)
-    opts = B.amg_default_opts(precision=B.AMG_MIXED, inner=B.AMG_INNER_PCG, max_iter=500)
+    opts = B.amg_default_opts(precision=B.AMG_MIXED, inner=B.AMG_INNER_PCG,
+                              max_iter=BATCH_MAX_ITER)
     hs, bs, xs = [], [], []
     try:
         for d in inst:
-            k = (B.kernel(B.AMG_K_FRACTIONAL, alpha=d["alpha"]) if d["frac"]
-                 else B.kernel(B.AMG_K_CONST))
-            hs.append(B.amg_setup(k, d["delta"], d["N"], opts))
+            hs.append(B.amg_setup(batch_kernel(B, d), d["delta"], d["N"], opts))
             bs.append(torch.from_numpy(d["b"]).cuda())
             xs.append(torch.zeros_like(bs[-1]))
         torch.cuda.synchronize()
@@ -227,7 +226,7 @@ def batch_traffic_summary(fetch_csv, write_csv, args):
         out[label] = {"scale": round(scale, 4), "dispatches": len(after),
                       "bytes_per_batch": round(sum(after) * scale / 2)}
     res = {"kernel": "every dispatch of one amg_solve_batch call of the uneven batch",
-           "workload": {"instances": args.batch, "seed": 0, "tol": args.tol},
+           "workload": batch_workload_id(args),
            "source_hash": kernel_source_hash(),
            "fetch": out["fetch"], "write": out["write"],
            "bytes_per_batch": out["fetch"]["bytes_per_batch"] + out["write"]["bytes_per_batch"],
@@ -249,8 +248,7 @@ def measured_batch_traffic(args):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash() or \
-            t.get("workload") != {"instances": args.batch, "seed": 0, "tol": args.tol}:
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != batch_workload_id(args):
         return None
     return t.get("bytes_per_batch")
 
@@ -427,24 +425,42 @@ def summary(res, N):
             "setup_s": round(res["setup_s"], 3)}
 
 
+BATCH_ALPHA = (0.2, 0.8)
+BATCH_MAX_ITER = 4000
+
+
 def batch_instances(count, seed=0):
     """The uneven batch: N = 2^K with K uniform on 10..16, delta uniform on
-    [0.05, 0.3], constant or fractional kernel with even odds, b ~ N(0, 1) per
-    unknown.  alpha is uniform on [0.2, 0.45]: the product-integration weights
-    of the fractional kernel are finite only below 1/2, and the V-cycle-CG
-    iteration count grows without bound as alpha nears 1/2 (about 140 at
-    alpha = 0.45, N = 2^14; as many at alpha = 0.49 already at N = 2^10)."""
+    [0.05, 0.3], constant or fractional kernel with even odds, alpha uniform
+    on [0.2, 0.8], b ~ N(0, 1) per unknown.  The product-integration weights
+    of the fractional kernel are finite only below alpha = 1/2; from 1/2 on
+    the instances use the near-field rule (AMG_K_FRACTIONAL_NEAR, an
+    extension: one symmetric quadratic on |t| <= h/2)."""
     rng = np.random.default_rng(seed)
     K = rng.integers(10, 17, size=count)
     delta = rng.uniform(0.05, 0.3, size=count)
     frac = rng.integers(0, 2, size=count)
-    alpha = rng.uniform(0.2, 0.45, size=count)
+    alpha = rng.uniform(*BATCH_ALPHA, size=count)
     out = []
     for i in range(count):
         N = 2 ** int(K[i])
         out.append(dict(N=N, delta=float(delta[i]), frac=bool(frac[i]), alpha=float(alpha[i]),
                         b=rng.standard_normal(2 * N - 1)))
     return out
+
+
+def batch_kernel(B, d):
+    """The instance's kernel: constant, fractional (alpha < 1/2) or the
+    fractional kernel with the near-field rule (alpha >= 1/2)."""
+    if not d["frac"]:
+        return B.kernel(B.AMG_K_CONST)
+    kind = B.AMG_K_FRACTIONAL if d["alpha"] < 0.5 else B.AMG_K_FRACTIONAL_NEAR
+    return B.kernel(kind, alpha=d["alpha"])
+
+
+def batch_workload_id(args):
+    """What a counted-traffic measurement of the batch belongs to."""
+    return {"instances": args.batch, "seed": 0, "tol": args.tol, "alpha": list(BATCH_ALPHA)}
 
 
 def run_batch(B, torch, args):
@@ -454,14 +470,13 @@ def run_batch(B, torch, args):
     untimed batch first (it captures each handle's V-cycle graph), then the
     timed one from x_0 = 0."""
     inst = batch_instances(args.batch)
-    opts = B.amg_default_opts(precision=B.AMG_MIXED, inner=B.AMG_INNER_PCG, max_iter=500)
+    opts = B.amg_default_opts(precision=B.AMG_MIXED, inner=B.AMG_INNER_PCG,
+                              max_iter=BATCH_MAX_ITER)
     hs, bs, xs = [], [], []
     t0 = time.perf_counter()
     try:
         for d in inst:
-            k = (B.kernel(B.AMG_K_FRACTIONAL, alpha=d["alpha"]) if d["frac"]
-                 else B.kernel(B.AMG_K_CONST))
-            hs.append(B.amg_setup(k, d["delta"], d["N"], opts))
+            hs.append(B.amg_setup(batch_kernel(B, d), d["delta"], d["N"], opts))
             bs.append(torch.from_numpy(d["b"]).cuda())
             xs.append(torch.zeros_like(bs[-1]))
         torch.cuda.synchronize()
@@ -494,10 +509,11 @@ def run_batch(B, torch, args):
             "counted_hbm_bytes": measured_batch_traffic(args),
             "counted_hbm_frac": (round(measured_batch_traffic(args) / wall / 1e9 / HBM_PEAK_GBS, 4)
                                  if measured_batch_traffic(args) else None),
+            "near_field_instances": int(sum(d["frac"] and d["alpha"] >= 0.5 for d in inst)),
             "workload": "N=2^K, K~U{10..16}; delta~U[0.05,0.3]; const or fractional 50/50, "
-                        "alpha~U[0.2,0.45] (half the range [0.2,0.8]: the fractional weights are "
-                        "finite only for alpha < 1/2); b~N(0,1); seed 0; mixed, inner=PCG, "
-                        f"tol={args.tol}"}
+                        "alpha~U[0.2,0.8] (alpha >= 1/2: AMG_K_FRACTIONAL_NEAR, the near-field "
+                        "rule, an extension); b~N(0,1); seed 0; mixed, inner=PCG, "
+                        f"tol={args.tol}, max_iter={BATCH_MAX_ITER}"}
 
 
 def run_c2(B, torch, args):

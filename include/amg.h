@@ -84,12 +84,22 @@ typedef enum {
      divided by its factor eta_{h,gamma}.  delta and scheme are ignored; the
      Dirichlet data enter through amg_volume_rhs (reach 0: g_left[0] = u(0),
      g_right[0] = u(1)).  amg_manufactured_rhs is AMG_ENOTSUP.              */
-  AMG_K_WEAKLY_SINGULAR = 4
+  AMG_K_WEAKLY_SINGULAR = 4,
+  /* The fractional kernel of AMG_K_FRACTIONAL for 0 < alpha < 1, with a
+     near-field rule that is an extension, not in the paper: on |t| <= h/2
+     around each collocation point the piecewise quadratic is replaced by the
+     one quadratic through x_c - h/2, x_c, x_c + h/2, whose linear term
+     cancels between the two sides (a principal value) and whose quadratic
+     term is integrable for alpha < 1; the cell pieces beyond h/2 are
+     integrated as for AMG_K_FRACTIONAL.  Exact on quadratics, symmetric
+     positive definite; shifted rule only.  For alpha < 1/2 it is a
+     different discretization from AMG_K_FRACTIONAL.                         */
+  AMG_K_FRACTIONAL_NEAR = 5
 } amg_kernel_kind;
 
 typedef struct {
   int kind;          /* amg_kernel_kind                                      */
-  double alpha;      /* AMG_K_FRACTIONAL only                                */
+  double alpha;      /* AMG_K_FRACTIONAL, AMG_K_FRACTIONAL_NEAR only         */
   double wl, wr;     /* AMG_K_WEIGHTED only (e.g. 1.2, 0.8)                 */
   const double* gen; /* AMG_K_GENERATORS only (host, copied during setup)    */
   int scheme;        /* AMG_SCHEME_SHIFTED (default) or AMG_SCHEME_STANDARD  */

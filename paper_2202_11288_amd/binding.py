@@ -20,6 +20,7 @@ AMG_OK, AMG_NOT_CONVERGED, AMG_DIVERGED = 0, 1, 2
 AMG_EINVAL, AMG_ENOMEM, AMG_EHIP, AMG_ENOTSUP = -1, -2, -3, -4
 AMG_K_CONST, AMG_K_WEIGHTED, AMG_K_FRACTIONAL, AMG_K_GENERATORS = 0, 1, 2, 3
 AMG_K_WEAKLY_SINGULAR = 4
+AMG_K_FRACTIONAL_NEAR = 5
 AMG_FP64, AMG_MIXED = 0, 1
 AMG_FLAG_HOST_ONLY = 1
 AMG_FLAG_PROFILE = 2

@@ -1647,7 +1647,7 @@ int setup_impl(const amg_kernel_t* kernel, double delta, int64_t N, const amg_op
   c->kspec = ks;
   if (o.flags & AMG_FLAG_ACCURATE_RESIDUAL) {
     if (kernel->kind != AMG_K_CONST && kernel->kind != AMG_K_WEIGHTED &&
-        kernel->kind != AMG_K_FRACTIONAL) {
+        !is_fractional(kernel->kind)) {
       delete c;
       return AMG_ENOTSUP;
     }
@@ -1658,7 +1658,7 @@ int setup_impl(const amg_kernel_t* kernel, double delta, int64_t N, const amg_op
   // (the same arithmetic, amg_setup.hip); the host keeps the level sizes
   c->gpu_setup = !c->host_only && (kernel->kind == AMG_K_CONST ||
                                     kernel->kind == AMG_K_WEIGHTED ||
-                                    kernel->kind == AMG_K_FRACTIONAL);
+                                    is_fractional(kernel->kind));
   // symmetric levels: a symmetric kernel under the shifted rule (the stencil
   // is then exactly symmetric, and Lemma 3.1 keeps it so)
   c->gpu_sym = ks.scheme == SCHEME_SHIFTED &&
@@ -1710,7 +1710,7 @@ int setup_impl(const amg_kernel_t* kernel, double delta, int64_t N, const amg_op
     // the first device chunk holds the whole persistent footprint
     c->arena_hint = (size_t)footprint(N, &o,
                                       (kernel->kind == AMG_K_CONST ||
-                                       kernel->kind == AMG_K_FRACTIONAL) &&
+                                       is_fractional(kernel->kind)) &&
                                           ks.scheme == SCHEME_SHIFTED,
                                       kernel->kind == AMG_K_WEAKLY_SINGULAR);
     c->arena_hint += c->arena_hint / 32 + (size_t(2) << 20);
@@ -2918,7 +2918,7 @@ int64_t amg_footprint_bytes(const amg_kernel_t* kernel, double delta, int64_t N,
   const KernelSpec ks = spec_of(kernel, ignores_delta(kernel) ? 0.25 : delta);
   if (!validate(ks, N, o.coarsest_log2).empty()) return AMG_EINVAL;
   if (!ks.supported()) return AMG_ENOTSUP;
-  return footprint(N, &o, (kernel->kind == AMG_K_CONST || kernel->kind == AMG_K_FRACTIONAL) &&
+  return footprint(N, &o, (kernel->kind == AMG_K_CONST || is_fractional(kernel->kind)) &&
                               ks.scheme == SCHEME_SHIFTED,
                    kernel->kind == AMG_K_WEAKLY_SINGULAR);
 }
@@ -3148,7 +3148,7 @@ ServerKey server_key(const amg_kernel_t& k, double delta, int64_t N, const amg_o
   key.coarsest = o.coarsest_log2;
   key.max_iter = o.max_iter;
   key.flags = o.flags;
-  key.alpha = k.kind == AMG_K_FRACTIONAL ? k.alpha : 0.0;
+  key.alpha = is_fractional(k.kind) ? k.alpha : 0.0;
   key.wl = k.kind == AMG_K_WEIGHTED ? k.wl : 0.0;
   key.wr = k.kind == AMG_K_WEIGHTED ? k.wr : 0.0;
   key.delta = delta;
@@ -3449,7 +3449,7 @@ int amg_server_submit(amg_server_t sv, const amg_kernel_t* kernel, double delta,
                       int64_t* id) {
   if (!sv || !kernel || !b || !x || b == x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_EINVAL;
   if (kernel->kind != AMG_K_CONST && kernel->kind != AMG_K_WEIGHTED &&
-      kernel->kind != AMG_K_FRACTIONAL)
+      !is_fractional(kernel->kind))
     return AMG_ENOTSUP;
   amg_opts_t o;
   if (opts) o = *opts;

@@ -13,7 +13,7 @@ namespace amg {
 namespace {
 
 double kernel_c(const KernelSpec& k) {
-  if (k.kind == K_FRACTIONAL) return (1.0 - k.alpha) * std::pow(k.delta, 2.0 * k.alpha - 2.0);
+  if (is_fractional(k.kind)) return (1.0 - k.alpha) * std::pow(k.delta, 2.0 * k.alpha - 2.0);
   return 3.0 / (2.0 * k.delta * k.delta * k.delta);
 }
 
@@ -70,6 +70,28 @@ void frac_cell(int64_t k, double theta, double beta, double J[3]) {
   J[2] = (double)(s2 * theta);
 }
 
+// int_{t0}^{t1} t^beta t^j dt for j = 0,1,2 and 0 < t0 (zero when t1 <= t0):
+// the integrand's singularity at t = 0 lies a distance t0 >= (t1 - t0)
+// before the interval on the cells this is used for, so 32-point
+// Gauss-Legendre is exact to rounding.
+void frac_cell_from(double t0, double t1, double beta, double J[3]) {
+  J[0] = J[1] = J[2] = 0.0;
+  if (!(t1 > t0)) return;
+  static const GaussLegendre gl32(32);
+  const double len = t1 - t0;
+  long double s0 = 0, s1 = 0, s2 = 0;
+  for (size_t i = 0; i < gl32.x.size(); ++i) {
+    const double t = t0 + len * gl32.x[i];
+    const long double f = (long double)gl32.w[i] * std::pow(t, beta);
+    s0 += f;
+    s1 += f * t;
+    s2 += f * t * t;
+  }
+  J[0] = (double)(s0 * len);
+  J[1] = (double)(s1 * len);
+  J[2] = (double)(s2 * len);
+}
+
 }  // namespace
 
 bool TpxLevel::symmetric() const {
@@ -91,7 +113,7 @@ std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2) {
   if (coarsest_log2 < 2) e << "coarsest_log2 must be >= 2; ";
   if (K <= coarsest_log2) e << "need log2(N) > coarsest_log2; ";
   if (K > 22) e << "log2(N) <= 22 is supported; ";
-  if (k.kind < 0 || k.kind > 4) e << "unknown kernel kind; ";
+  if (k.kind < 0 || k.kind > 5) e << "unknown kernel kind; ";
   if (k.kind == K_WEAKLY_SINGULAR) {
     if (!(k.gamma >= 0.0 && k.gamma < 1.0)) e << "weakly singular kernel needs 0 <= gamma < 1; ";
   } else if (k.kind != K_GENERATORS) {
@@ -101,6 +123,8 @@ std::string validate(const KernelSpec& k, int64_t N, int coarsest_log2) {
   }
   if (k.kind == K_FRACTIONAL && !(k.alpha > 0.0 && k.alpha < 0.5))
     e << "fractional kernel needs 0 < alpha < 1/2; ";
+  if (k.kind == K_FRACTIONAL_NEAR && !(k.alpha > 0.0 && k.alpha < 1.0))
+    e << "fractional kernel with the near-field rule needs 0 < alpha < 1; ";
   if (k.kind == K_WEIGHTED && !(std::isfinite(k.wl) && std::isfinite(k.wr) && k.wl > 0 && k.wr > 0))
     e << "weights must be positive; ";
   if (k.scheme != SCHEME_SHIFTED && k.scheme != SCHEME_STANDARD) e << "unknown scheme; ";
@@ -231,17 +255,34 @@ void row_stencil_into(const KernelSpec& k, int64_t N, std::vector<double>& W, in
   const int64_t S = 2 * ncell;
   W.assign((size_t)(2 * S + 1), 0.0);
   const double c = kernel_c(k);
-  const bool frac = k.kind == K_FRACTIONAL;
+  const bool frac = is_fractional(k.kind);
+  const bool near = k.kind == K_FRACTIONAL_NEAR;
   const double beta = frac ? -1.0 - 2.0 * k.alpha : 0.0;
   const double scale = frac ? c * std::pow(h, beta + 1.0) : c * h;
   const double wr = (k.kind == K_WEIGHTED) ? k.wr : 1.0;
   const double wl = (k.kind == K_WEIGHTED) ? k.wl : 1.0;
+  if (near) {
+    // |t| <= rho h, rho = min(1/2, theta_0): the quadratic through the
+    // half-grid neighbours x_c -+ h/2 and x_c; its linear term cancels
+    // between the sides, its quadratic term 2 t^2 (u_+ - 2 u_c + u_-) / h^2
+    // gives the weight m = (4/h^2) int_0^{rho h} gamma t^2 dt of the second
+    // difference (both sides together)
+    const double th0 = (r > 0) ? 1.0 : th_last;
+    const double rho = std::fmin(0.5, th0);
+    const double m = 4.0 * scale * std::pow(rho, beta + 3.0) / (beta + 3.0);
+    W[S] += 2.0 * m;
+    W[S - 1] -= m;
+    W[S + 1] -= m;
+  }
   // cell k: t in [k h, (k+theta) h]; quadratic through local tau = 0, 1/2, 1:
   //   l_a = 1 - 3 tau + 2 tau^2,  l_b = 4 tau - 4 tau^2,  l_c = 2 tau^2 - tau.
   for (int64_t kc = 0; kc < ncell; ++kc) {
     const double th = (kc < r) ? 1.0 : th_last;
     double J[3];
-    if (frac) {
+    if (near && kc == 0) {
+      // the cell's own quadratic beyond the near part: tau in [1/2, th]
+      frac_cell_from(0.5, th, beta, J);
+    } else if (frac) {
       frac_cell(kc, th, beta, J);
     } else {
       J[0] = th;
@@ -757,7 +798,7 @@ void manufactured_rhs(const KernelSpec& k, int64_t N, double* out) {
                                    : ((double)(idx - (N - 1)) + 0.5) / (double)N;
     const double ux = u(x);
     double f;
-    if (k.kind != K_FRACTIONAL) {
+    if (!is_fractional(k.kind)) {
       const double right = ux * d - (U(std::fmin(x + d, 1.0)) - U(x));
       const double left = ux * d - (U(x) - U(std::fmax(x - d, 0.0)));
       f = c * (wr * right + wl * left);
@@ -769,9 +810,13 @@ void manufactured_rhs(const KernelSpec& k, int64_t N, double* out) {
       const double fact[4] = {1, 2, 6, 24};
       f = 0.0;
       for (int p = 1; p <= 4; ++p) {
+        // int_{-tl}^{tr} t^p |t|^be dt (a principal value for p = 1 when
+        // be + 2 <= 0, the near-field kernel; log(tr/tl) at be + 2 = 0)
         const double e = be + p + 1;
         const double sgn = (p % 2) ? -1.0 : 1.0;
-        f -= du[p - 1] / fact[p - 1] * (std::pow(tr, e) + sgn * std::pow(tl, e)) / e;
+        const double Mp = (e == 0.0) ? std::log(tr / tl)
+                                     : (std::pow(tr, e) + sgn * std::pow(tl, e)) / e;
+        f -= du[p - 1] / fact[p - 1] * Mp;
       }
       for (double a : {1.0 - x, x})
         if (a < d) f += ux * (std::pow(d, be + 1) - std::pow(a, be + 1)) / (be + 1);

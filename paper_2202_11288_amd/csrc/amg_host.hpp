@@ -10,7 +10,11 @@
 namespace amg {
 
 enum KernelKind { K_CONST = 0, K_WEIGHTED = 1, K_FRACTIONAL = 2, K_GENERATORS = 3,
-                  K_WEAKLY_SINGULAR = 4 };
+                  K_WEAKLY_SINGULAR = 4, K_FRACTIONAL_NEAR = 5 };
+
+// c |s|^(-1-2 alpha): product integration throughout (0 < alpha < 1/2), or
+// with the symmetric near-field rule on |t| <= h/2 (0 < alpha < 1)
+inline bool is_fractional(int kind) { return kind == K_FRACTIONAL || kind == K_FRACTIONAL_NEAR; }
 
 enum Scheme { SCHEME_SHIFTED = 0, SCHEME_STANDARD = 1 };
 
@@ -23,7 +27,7 @@ struct KernelSpec {
   int scheme = SCHEME_SHIFTED;
   double gamma = 0.0;  // K_WEAKLY_SINGULAR: |x - y|^-gamma on (0, 1)
   // the standard rule is set up for the constant and weighted kernels
-  bool supported() const { return !(scheme == SCHEME_STANDARD && kind == K_FRACTIONAL); }
+  bool supported() const { return !(scheme == SCHEME_STANDARD && is_fractional(kind)); }
 };
 
 // One level in the Toeplitz-like-plus-Cross form (eq. (split01)):

@@ -18,8 +18,14 @@ KERNELS = [
     (B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8), D.Kernel(D.WEIGHTED, 0.05, wl=1.2, wr=0.8), 0.05),
     (B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4), D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), 0.1),
     (B.kernel(B.AMG_K_FRACTIONAL, alpha=0.2), D.Kernel(D.FRACTIONAL, 0.013, alpha=0.2), 0.013),
+    (B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.7), D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=0.7), 0.1),
+    (B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.5), D.Kernel(D.FRACTIONAL_NEAR, 0.05, alpha=0.5), 0.05),
+    (B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.3), D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=0.3), 0.1),
+    (B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.9), D.Kernel(D.FRACTIONAL_NEAR, 0.013, alpha=0.9),
+     0.013),
 ]
-IDS = ["const-0.25", "const-0.05", "weighted-0.05", "frac-0.4", "frac-0.2-small-delta"]
+IDS = ["const-0.25", "const-0.05", "weighted-0.05", "frac-0.4", "frac-0.2-small-delta",
+       "near-0.7", "near-0.5", "near-0.3", "near-0.9-small-delta"]
 
 
 def test_exports_every_declared_symbol():
@@ -38,7 +44,8 @@ def test_manufactured_rhs_matches_oracle(kp, N):
     # both evaluate f = c * (u(x) delta - (U(x+delta) - U(x))) (or its fractional
     # analogue) in closed form; the difference cancels terms of size
     # c * (delta + int u) with rounding ~eps each, so that is the scale
-    scale = okern.c * (delta ** (okern.beta + 1) if okern.kind == D.FRACTIONAL else delta + 1 / 30)
+    scale = okern.c * (delta ** (okern.beta + 1) if okern.kind in D.FRACTIONAL_KINDS
+                       else delta + 1 / 30)
     assert np.abs(b - ref).max() <= 64 * np.finfo(float).eps * scale
 
 
@@ -102,6 +109,8 @@ def _setup_status(kern, delta, N, **opts):
     dict(N=100), dict(N=0), dict(N=-64), dict(N=32), dict(N=16), dict(N=2 ** 23),
     dict(delta=0.0), dict(delta=-0.1), dict(delta=0.5), dict(delta=float("nan")),
     dict(kind=B.AMG_K_FRACTIONAL, alpha=0.5), dict(kind=B.AMG_K_FRACTIONAL, alpha=0.0),
+    dict(kind=B.AMG_K_FRACTIONAL_NEAR, alpha=1.0), dict(kind=B.AMG_K_FRACTIONAL_NEAR, alpha=0.0),
+    dict(kind=6),
     dict(kind=B.AMG_K_WEIGHTED, wl=-1.0), dict(kind=7), dict(kind=B.AMG_K_GENERATORS),
     dict(opts=dict(coarsest_log2=1)), dict(opts=dict(coarsest_log2=8)),
     dict(opts=dict(omega_pre=0.0)), dict(opts=dict(precision=5)), dict(opts=dict(flags=32)),
@@ -123,7 +132,7 @@ def test_accurate_residual_flag():
     points' order (caller generators, the weakly singular model's band);
     its far-field spectra and near-field output count in the footprint."""
     fl = B.AMG_FLAG_ACCURATE_RESIDUAL
-    for kind in (B.AMG_K_CONST, B.AMG_K_WEIGHTED, B.AMG_K_FRACTIONAL):
+    for kind in (B.AMG_K_CONST, B.AMG_K_WEIGHTED, B.AMG_K_FRACTIONAL, B.AMG_K_FRACTIONAL_NEAR):
         assert _setup_status(B.kernel(kind, alpha=0.3, wl=1.2, wr=0.8), 0.1, 4096, flags=fl) == B.AMG_OK
     gen = np.zeros(8 * 256 - 8)
     gen[255 - 1] = 1.0

@@ -130,10 +130,12 @@ def _status(fn, kern, delta=0.1, N=256, **extra):
 
 @pytest.mark.parametrize("fn", ["setup", "reach", "footprint", "rhs", "volume"])
 def test_scheme_argument_checks(fn):
-    """Standard + fractional is AMG_ENOTSUP; an unknown scheme is AMG_EINVAL;
+    """Standard + fractional (either rule) is AMG_ENOTSUP; an unknown scheme is AMG_EINVAL;
     the standard scheme is accepted for the constant and weighted kernels."""
     frac = B.kernel(B.AMG_K_FRACTIONAL, alpha=0.3, scheme=STD)
     assert _status(fn, frac) == B.AMG_ENOTSUP
+    near = B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.7, scheme=STD)
+    assert _status(fn, near) == B.AMG_ENOTSUP
     assert _status(fn, B.kernel(B.AMG_K_CONST, scheme=2)) == B.AMG_EINVAL
     assert _status(fn, B.kernel(B.AMG_K_CONST, scheme=-1)) == B.AMG_EINVAL
     for k in (B.kernel(B.AMG_K_CONST, scheme=STD), B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8,

@@ -24,6 +24,11 @@ WEIGHT05 = ("weighted-0.05", B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8),
             D.Kernel(D.WEIGHTED, 0.05, wl=1.2, wr=0.8), 0.05)
 FRAC04 = ("frac-0.4", B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4),
           D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), 0.1)
+# the near-field rule (an extension for 0 < alpha < 1, not in the paper)
+NEAR07 = ("near-0.7", B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.7),
+          D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=0.7), 0.1)
+NEAR09 = ("near-0.9", B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.9),
+          D.Kernel(D.FRACTIONAL_NEAR, 0.05, alpha=0.9), 0.05)
 
 
 def say(*a):
@@ -69,6 +74,7 @@ def oracle_level_matvec(H, l, x):
 @pytest.mark.parametrize("case,N", [
     (CONST25, 64), (CONST25, 1024), (CONST25, 8192), (CONST25, 16384), (CONST25, 65536),
     (CONST05, 32768), (WEIGHT05, 256), (WEIGHT05, 16384), (FRAC04, 1024), (FRAC04, 32768),
+    (NEAR07, 16384), (NEAR09, 1024),
 ])
 def test_level_matvec_every_level(case, N):
     """y = A_l x on every level (tail levels: one-workgroup FFT in LDS;
@@ -126,7 +132,7 @@ def test_matvec_general_blocks(N):
 
 
 @pytest.mark.parametrize("case,N", [(CONST25, 1024), (CONST25, 16384), (WEIGHT05, 32768),
-                                    (FRAC04, 16384), (CONST05, 128)])
+                                    (FRAC04, 16384), (CONST05, 128), (NEAR07, 16384)])
 def test_vcycle_matches_oracle(case, N):
     """One V-cycle (Algorithm 2) from zero: same algorithm, so outputs agree
     to rounding amplified by the conditioning (see kappa_tol)."""
@@ -417,7 +423,8 @@ def test_graph_replay_matches_eager(prec):
         B.amg_destroy(hg)
 
 
-@pytest.mark.parametrize("case,N", [(CONST25, 2 ** 14), (CONST05, 4096), (FRAC04, 4096)])
+@pytest.mark.parametrize("case,N", [(CONST25, 2 ** 14), (CONST05, 4096), (FRAC04, 4096),
+                                    (NEAR07, 4096), (NEAR09, 1024)])
 def test_pcg_matches_oracle(case, N):
     """V-cycle-preconditioned CG in FP64 against the oracle's pcg (same steps,
     same Polak-Ribiere update): iteration counts within one, and the
@@ -446,10 +453,12 @@ def test_pcg_matches_oracle(case, N):
 def test_pcg_mixed_and_fractional():
     """PCG with the FP32 V-cycle as preconditioner (FP64 recurrence): the
     fractional kernel (alpha = 0.4) at N = 2^14, where the stationary
-    iteration stalls, converges to 1e-10 (oracle-evaluated residual) within a
-    few iterations of the FP64 PCG; the constant kernel at N = 2^17 needs no
-    more iterations than the stationary mixed iteration."""
-    for case, N, stationary_too in ((FRAC04, 2 ** 14, False), (CONST25, 2 ** 17, True)):
+    iteration stalls, and the near-field rule at alpha = 0.7, converge to
+    1e-10 (oracle-evaluated residual) within a few iterations of the FP64
+    PCG; the constant kernel at N = 2^17 needs no more iterations than the
+    stationary mixed iteration."""
+    for case, N, stationary_too in ((FRAC04, 2 ** 14, False), (NEAR07, 2 ** 12, False),
+                                    (CONST25, 2 ** 17, True)):
         say("pcg mixed", case[0], N)
         H = oracle_hier(case, N)
         b = synthetic.random_vector(2 * N - 1, seed=N + 7)
@@ -483,7 +492,8 @@ def test_pcg_batch_matches_solo():
     gives each solve's solo result bit for bit."""
     say("pcg batch")
     cases = [(CONST25, 8192, B.AMG_INNER_PCG, B.AMG_FP64), (FRAC04, 4096, B.AMG_INNER_PCG, B.AMG_MIXED),
-             (CONST05, 2048, B.AMG_INNER_VCYCLE, B.AMG_FP64), (CONST25, 2 ** 15, B.AMG_INNER_PCG, B.AMG_MIXED)]
+             (CONST05, 2048, B.AMG_INNER_VCYCLE, B.AMG_FP64), (CONST25, 2 ** 15, B.AMG_INNER_PCG, B.AMG_MIXED),
+             (NEAR07, 4096, B.AMG_INNER_PCG, B.AMG_MIXED)]
     hs, bs, xs, solo = [], [], [], []
     try:
         for case, N, inner, prec in cases:
