@@ -374,7 +374,9 @@ int amg_profile_stats(amg_t h, amg_stat_t* out, int cap, int reset);
 /* Right-hand side f(x_c) = -L_delta u(x_c) for the manufactured solution
  * u = x^2 (1-x)^2 (zero outside (0,1)) at the 2N-1 collocation points in
  * block order; host output b_host (2N-1 doubles).  Same kernel/delta/N rules
- * as amg_setup (AMG_K_GENERATORS is AMG_EINVAL). */
+ * as amg_setup (AMG_K_GENERATORS is AMG_EINVAL).  For AMG_K_FRACTIONAL_NEAR
+ * with alpha >= 1/2 the first moment of the kernel over the part of the
+ * horizon inside (0, 1) is a principal value. */
 int amg_manufactured_rhs(const amg_kernel_t* kernel, double delta, int64_t N, double* b_host);
 
 /* One step of the fourth-order backward differentiation formula (Sec. 5,
