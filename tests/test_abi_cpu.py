@@ -68,6 +68,22 @@ def _oracle_levels(T0, coarsest_log2):
     return Ts
 
 
+@pytest.mark.parametrize("delta_h", [0.4, 0.83, 1.6])
+def test_host_near_rule_short_horizons(delta_h):
+    """The near-field rule where the horizon ends inside the first cell
+    (delta < h/2: no far part; h/2 < delta < h: a partial far part) or in
+    the second: host generators equal the oracle's."""
+    N = 64
+    delta = delta_h / N
+    k = B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.7)
+    h = B.amg_setup(k, delta, N, B.amg_default_opts(flags=B.AMG_FLAG_HOST_ONLY, coarsest_log2=4))
+    try:
+        To = tpx.from_stencil(D.Kernel(D.FRACTIONAL_NEAR, delta, alpha=0.7), N)
+        _compare_levels(h, _oracle_levels(To, 4))
+    finally:
+        B.amg_destroy(h)
+
+
 @pytest.mark.parametrize("kp", KERNELS, ids=IDS)
 @pytest.mark.parametrize("N,cl", [(64, 5), (1024, 5), (2048, 6), (128, 6)])
 def test_host_setup_matches_oracle(kp, N, cl):

@@ -305,3 +305,15 @@ def test_near_manufactured_error_falls(alpha):
         errs.append(np.abs(U - D.u_exact(D.points_block(N))).max())
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
     assert all(r > 1.8 for r in rates), (errs, rates)
+
+
+def test_near_rule_delta_below_half_h():
+    """delta < h/2: the near quadratic covers the whole horizon (no far
+    part); the row sum vanishes and the second moment is still 1."""
+    N = 16
+    k = D.Kernel(D.FRACTIONAL_NEAR, 0.4 / N, alpha=0.7)
+    W, S = D.stencil(k, N)
+    assert S == 2 and W[0] == 0.0 and W[-1] == 0.0
+    assert abs(W.sum()) < 1e-12 * np.abs(W).sum()
+    m2 = sum(W[s + S] * (-(s / (2 * N)) ** 2) for s in range(-S, S + 1))
+    assert abs(m2 - 1.0) < 1e-12
