@@ -13,7 +13,9 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libamg.so")
+# AMG_LIBRARY names another build of the same library (the host-sanitizer
+# build of build.py); the default is the in-tree libamg.so
+LIB_PATH = os.environ.get("AMG_LIBRARY") or os.path.join(_HERE, "libamg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "amg.h")
 
 AMG_OK, AMG_NOT_CONVERGED, AMG_DIVERGED = 0, 1, 2
