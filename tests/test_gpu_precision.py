@@ -32,6 +32,8 @@ WEIGHT05 = ("weighted-0.05", B.kernel(B.AMG_K_WEIGHTED, wl=1.2, wr=0.8),
             D.Kernel(D.WEIGHTED, 0.05, wl=1.2, wr=0.8), 0.05)
 FRAC04 = ("frac-0.4", B.kernel(B.AMG_K_FRACTIONAL, alpha=0.4),
           D.Kernel(D.FRACTIONAL, 0.1, alpha=0.4), 0.1)
+NEAR07 = ("near-0.7", B.kernel(B.AMG_K_FRACTIONAL_NEAR, alpha=0.7),
+          D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=0.7), 0.1)
 
 
 def say(*a):
@@ -132,7 +134,8 @@ def test_fp32_level_matvec_rejects_fp64_handle():
 
 @pytest.mark.parametrize("case,N,prec", [(FRAC04, 2 ** 16, B.AMG_FP64), (CONST05, 2 ** 15, B.AMG_MIXED),
                                          (WEIGHT05, 2 ** 14, B.AMG_FP64), (FRAC04, 2 ** 12, B.AMG_MIXED),
-                                         (CONST25, 2 ** 13, B.AMG_FP64)])
+                                         (CONST25, 2 ** 13, B.AMG_FP64), (NEAR07, 2 ** 13, B.AMG_FP64),
+                                         (NEAR07, 2 ** 12, B.AMG_MIXED)])
 def test_split_residual_matches_extended_oracle(case, N, prec):
     """AMG_FLAG_ACCURATE_RESIDUAL: the solve's final relative residual,
     formed on the GPU in split form (near field in difference form, far
@@ -146,9 +149,10 @@ def test_split_residual_matches_extended_oracle(case, N, prec):
     # eps |W(0)| |x|, 2e-10 of |b| at 2^16 for the fractional kernel)
     T = tpx.from_stencil_rowsum(case[2], N)
     xs = {}
+    frac = case[2].kind in D.FRACTIONAL_KINDS
     for flags in (0, B.AMG_FLAG_ACCURATE_RESIDUAL):
         h = B.amg_setup(case[1], case[3], N, B.amg_default_opts(
-            precision=prec, inner=B.AMG_INNER_PCG if case is FRAC04 else B.AMG_INNER_VCYCLE,
+            precision=prec, inner=B.AMG_INNER_PCG if frac else B.AMG_INNER_VCYCLE,
             max_iter=600, flags=flags))
         try:
             x = torch.zeros(2 * N - 1, device="cuda", dtype=torch.float64)
@@ -166,9 +170,9 @@ def test_split_residual_matches_extended_oracle(case, N, prec):
             B.amg_destroy(h)
     # two solutions with relative residuals near 1e-10 differ by at most about
     # kappa 2e-10 (kappa ~ 1e2 for the constant and weighted kernels here,
-    # ~ 1e5 for the fractional one)
+    # ~ 1e5 for the fractional ones)
     d = np.abs(xs[0] - xs[B.AMG_FLAG_ACCURATE_RESIDUAL]).max() / np.abs(xs[0]).max()
-    assert d < (1e-4 if case is FRAC04 else 1e-7), d
+    assert d < (1e-4 if frac else 1e-7), d
 
 
 def test_split_residual_shifted_operator():
