@@ -259,6 +259,9 @@ def stencil(kernel: Kernel, N: int):
     """
     if kernel.kind == FRACTIONAL_NEAR:
         return stencil_near(kernel, N)
+    if kernel.kind == FRACTIONAL and not 0.0 < kernel.alpha < 0.5:
+        raise ValueError("product integration of the fractional kernel needs 0 < alpha < 1/2 "
+                         "(fractional_near covers 0 < alpha < 1)")
     k, Ia, Ib, Ic, Idiag = cell_integrals(kernel, N)
     S = 2 * len(k)
     W = np.zeros(2 * S + 1)
@@ -297,6 +300,8 @@ def assemble_dense(kernel: Kernel, N: int):
     M = 2 * N - 1
     if kernel.kind == FRACTIONAL_NEAR:
         return _assemble_dense_near(kernel, N)
+    if kernel.kind == FRACTIONAL and not 0.0 < kernel.alpha < 0.5:
+        raise ValueError("product integration of the fractional kernel needs 0 < alpha < 1/2")
     k, Ia, Ib, Ic, Idiag = cell_integrals(kernel, N)
     wl, wr = kernel.side_weights()
     Aint = np.zeros((M + 1, M + 1))  # 1-based interleaved positions

@@ -317,3 +317,16 @@ def test_near_rule_delta_below_half_h():
     assert abs(W.sum()) < 1e-12 * np.abs(W).sum()
     m2 = sum(W[s + S] * (-(s / (2 * N)) ** 2) for s in range(-S, S + 1))
     assert abs(m2 - 1.0) < 1e-12
+
+
+def test_product_integration_refuses_alpha_from_one_half():
+    """The plain fractional rule's weights diverge from alpha = 1/2 on; the
+    oracle refuses it (as the library returns AMG_EINVAL) instead of
+    producing non-finite weights."""
+    for a in (0.5, 0.7):
+        with pytest.raises(ValueError):
+            D.stencil(D.Kernel(D.FRACTIONAL, 0.1, alpha=a), 32)
+        with pytest.raises(ValueError):
+            D.assemble_dense(D.Kernel(D.FRACTIONAL, 0.1, alpha=a), 32)
+    W, _ = D.stencil(D.Kernel(D.FRACTIONAL_NEAR, 0.1, alpha=0.7), 32)
+    assert np.all(np.isfinite(W))
